@@ -1,0 +1,184 @@
+/*
+ * hipsso -- differentiable linear-static structural FEA on one MI355X (gfx950).
+ *
+ * C ABI of the hot path: element stiffness of 12-DOF space-frame members and 4-node flat
+ * shells, deterministic assembly into a sparse K, the support-constrained solve K u = f with
+ * block-Jacobi preconditioned conjugate gradients, objectives, and the adjoint sensitivity of an
+ * objective with respect to nodal coordinates, shell thickness and per-element stiffness scale.
+ *
+ * Paper: Wu, "JAX-SSO: Differentiable Finite Element Analysis Solver for Structural
+ * Optimization and Seamless Integration with Neural Networks" (arXiv 2407.20026).
+ *   Sec. 2.2.1  K u = f (Eq. 1); element-to-global index maps; vectorised assembly of all element
+ *               matrices into a sparse K; supports through Lagrange multipliers (Eqs. 2-3);
+ *               the model-building API (nodes, 6-flag supports, 6-component nodal loads,
+ *               beam-columns with E, G, Iy, Iz, J, A; MITC-4 quads with x, y, z of 4 nodes,
+ *               t, E, nu, kx, ky).
+ *   Sec. 2.2.2  solving the constrained system (the paper uses direct solvers; this library
+ *               uses preconditioned conjugate gradients on the masked system).
+ *   Sec. 2.3.1  adjoint equation K^T lambda = dg/du^T (Eq. 5) and adjoint sensitivity
+ *               dg/dp = dg/dp|explicit - lambda^T (dK/dp u - df/dp) (Eq. 6); node parameters
+ *               (coordinate of a node) and objectives ("strain energy" f^T u / 2).
+ *   Sec. 3.3-3.4 thickness as a design variable; SIMP stiffness scaling E = rho^P E0 (Eq. 8).
+ *
+ * Conventions shared by every entry point:
+ *   - Global DOF d = 6 * node + c, c in (ux, uy, uz, rx, ry, rz).  SI units.
+ *   - Every array pointer is a DEVICE pointer (memory the caller allocated on the GPU the
+ *     problem runs on), row-major, densely packed.  Exceptions are marked "host".
+ *   - Input arrays are borrowed for the duration of the call; the library copies what it keeps.
+ *   - Outputs go to caller-allocated device buffers.
+ *   - Work is enqueued on the stream given at creation.  sso_problem_create, sso_solve,
+ *     sso_objective and sso_adjoint synchronise that stream before returning (they report
+ *     convergence, errors and host scalars); sso_problem_update only enqueues.
+ *   - A problem is not thread-safe: use one problem per host thread.
+ *   - Every function returns SSO_OK (0) or a negative status; sso_strerror gives the text.
+ *     On error, outputs are left unspecified and the problem stays usable (except after
+ *     SSO_EHIP, which reports a failed HIP runtime call).
+ */
+#ifndef HIPSSO_H
+#define HIPSSO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SSO_OK = 0,
+  SSO_EINVAL = -1,      /* bad argument, index out of range, degenerate element           */
+  SSO_ENOMEM = -2,      /* device allocation failed                                       */
+  SSO_EHIP = -3,        /* a HIP runtime call failed                                      */
+  SSO_ENOTCONV = -4,    /* PCG reached max_it before the residual target (stats filled)   */
+  SSO_EBREAKDOWN = -5   /* p^T K p <= 0 or not finite: K not positive definite (e.g. an
+                           unsupported rigid-body mode); stats filled                     */
+};
+
+enum {
+  SSO_OBJ_COMPLIANCE = 0,     /* g = f^T u                      (loss of Sec. 3.5)      */
+  SSO_OBJ_STRAIN_ENERGY = 1,  /* g = f^T u / 2                  (Sec. 2.2.3, 2.3.2)     */
+  SSO_OBJ_LINEAR = 2,         /* g = a^T u, a given                                        */
+  SSO_OBJ_USER = 3            /* caller supplies dg/du; dg/dp omits explicit dependence    */
+};
+
+enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
+
+/* Structure description.  Sec. 2.2.1 model-building API. */
+typedef struct {
+  int32_t n_nodes;
+  const double* xyz;          /* [n_nodes][3] nodal coordinates (add_node)                    */
+  const uint8_t* fixed;       /* [n_nodes][6] 1 = DOF fixed, 0 = free (add_support flags)    */
+  const double* f_nodal;      /* [n_nodes][6] nodal forces and moments (add_nodal_load)      */
+  int32_t n_beams;
+  const int32_t* beam_nodes;  /* [n_beams][2] end nodes i, j (add_beamcol)                   */
+  const double* beam_prop;    /* [n_beams][6] E, G, A, Iy, Iz, J                             */
+  int32_t n_quads;
+  const int32_t* quad_nodes;  /* [n_quads][4] corner nodes, counter-clockwise about the
+                                 element normal                                             */
+  const double* quad_prop;    /* [n_quads][5] t, E, nu, kx, ky (kx = ky = 1 required)        */
+  const double* quad_scale;   /* [n_quads] stiffness scale s_e (e.g. rho^3), or NULL = 1     */
+  double unit_weight;         /* self-weight of quads along -Z, N/m^3 (0 = none)             */
+  double surface_load;        /* uniform pressure on quads along -Z, N/m^2 (0 = none)        */
+} sso_mesh;
+
+typedef struct {
+  int32_t precision;          /* SSO_PREC_FP64 or SSO_PREC_MIXED                             */
+  double rtol;                /* stop when ||f - K u||_2 <= rtol ||f||_2 (recursive residual;
+                                 the reported residual is recomputed)                       */
+  int32_t max_it;             /* PCG iteration limit per solve                               */
+  int32_t refine_steps;       /* mixed precision: maximum FP64 refinement steps              */
+  int32_t profile_every;      /* 0 = off; n > 0: time every n-th SpMV launch of the PCG with
+                                 HIP events on the problem's stream (stats.spmv_us)          */
+} sso_options;
+
+typedef struct {
+  int32_t iters;              /* PCG iterations of the last solve (all refinement steps)     */
+  double rel_residual;        /* ||f - K u||_2 / ||f||_2 recomputed in FP64 after the solve  */
+  double t_elem_us;           /* element stiffness + loads                                   */
+  double t_asm_us;            /* assembly + masking + block-Jacobi                           */
+  double t_solve_us;          /* PCG                                                         */
+  double t_adj_us;            /* adjoint solve + element contraction + gather (sso_adjoint)  */
+  double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
+  double spmv_us;             /* mean duration of the sampled SpMV launches (profile_every)  */
+  int32_t spmv_samples;       /* number of sampled SpMV launches                             */
+  double spmv_bytes;          /* algorithmic bytes of one SpMV launch                        */
+} sso_stats;
+
+typedef struct sso_problem sso_problem;
+
+/* Create a problem: copies the mesh into device buffers owned by the problem and builds, once
+ * per topology, the sparse pattern of K, the sort permutation of the element contribution list
+ * and the node-to-element incidence (Sec. 2.2.1, element index maps and sparse storage).
+ * mesh: host struct whose array members are device pointers.  opts: host struct, or NULL for
+ * defaults (FP64, rtol 1e-8, max_it 200000, refine_steps 20).  stream: HIP stream for all work
+ * of this problem (0 = null stream).  *out receives the handle.
+ * Errors: SSO_EINVAL for negative counts, n_nodes == 0, a node index outside [0, n_nodes) or
+ * an element that repeats a node; SSO_ENOMEM; SSO_EHIP. */
+int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
+                       sso_problem** out);
+
+/* Replace design inputs without changing the topology (device pointers, each may be NULL to
+ * keep the current values): xyz [n_nodes][3]; quad_t [n_quads] thickness; quad_scale [n_quads]
+ * stiffness scale.  Enqueued on the problem's stream; invalidates the last solution. */
+int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
+                       const double* quad_scale);
+
+/* Replace solver options (host struct). */
+int sso_set_options(sso_problem* p, const sso_options* opts);
+
+/* Forward analysis: element stiffness (beams: K = s T^T k T; quads: flat shell, K = s T^T W^T k
+ * W T), loads (nodal + self-weight + surface load lumped to corners), deterministic assembly
+ * K[slot] = sum of the slot's element entries in ascending element order, support masking
+ * (constrained d: K[d,:] = K[:,d] = 0, K[d,d] = 1, f[d] = 0 -- for zero prescribed
+ * displacements identical in u to the Lagrange system of Eqs. 2-3), block-Jacobi
+ * preconditioner, PCG.  u_out: [n_nodes][6] device output (may be NULL).  stats: host struct
+ * or NULL.  Errors: SSO_EINVAL (degenerate element: zero-length beam, det J <= 0, zero quad
+ * area, non-positive t/E/A/I/J, nu outside (-1, 0.5), kx or ky != 1; a diagonal 6x6 block that
+ * is not positive definite), SSO_ENOTCONV (u_out then holds the last iterate, and
+ * sso_objective / sso_adjoint may still be called), SSO_EBREAKDOWN, SSO_EHIP. */
+int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
+
+/* Objective value of the last solve into *g_host (host): compliance f^T u, strain energy
+ * f^T u / 2, or a^T u for SSO_OBJ_LINEAR (a: device [n_nodes][6]).  SSO_OBJ_USER: SSO_EINVAL.
+ * Errors: SSO_EINVAL without a previous successful solve. */
+int sso_objective(sso_problem* p, int kind, const double* a, double* g_host);
+
+/* Adjoint sensitivity of the last solve (Eqs. 5-6).  kind selects g:
+ *   COMPLIANCE / STRAIN_ENERGY: lambda = u exactly (K lambda = f), no second solve;
+ *   LINEAR: dg_du = a; USER: dg_du = dg/du supplied by the caller ([n_nodes][6] device), and
+ *   lambda solves the masked K lambda = dg/du with the same K and preconditioner.
+ * Outputs (device, caller-allocated): dg_dxyz [n_nodes][3] (required); dg_dt [n_quads] and
+ * dg_dscale [n_quads] (each may be NULL).  Per element e and parameter p the contribution
+ * c_lam (lambda_e^T df_e/dp - lambda_e^T dK_e/dp u_e) + c_u u_e^T df_e/dp is formed exactly
+ * (forward-mode dual numbers), then summed per node over incident elements in ascending
+ * element order.  stats: host or NULL (t_adj_us; iters of the adjoint solve if one ran).
+ * Errors: SSO_EINVAL (no solve, bad kind, NULL dg_du for LINEAR/USER), SSO_ENOTCONV,
+ * SSO_EBREAKDOWN, SSO_EHIP. */
+int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz,
+                double* dg_dt, double* dg_dscale, sso_stats* stats);
+
+/* The scalar CSR view of the pattern and the scatter permutation (built on first call, owned
+ * by the problem, valid until destroy).  All arrays are device int32:
+ *   row_ptr [n_dof + 1], col [nnz]: scalar CSR of K, columns sorted;
+ *   perm [n_coo]: stable sort of the element contribution list (element-major, beams then
+ *                 quads, each local matrix row-major) by (row, col);
+ *   seg [nnz + 1]: perm[seg[s] .. seg[s+1]) are the contributions of slot s.
+ * *nnz and *n_coo are host outputs.  Errors: SSO_EINVAL if n_coo >= 2^31. */
+int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
+                const int32_t** perm, const int32_t** seg, int64_t* nnz, int64_t* n_coo);
+
+/* Read back the assembled, masked K in scalar CSR order into vals [nnz] (device), the masked
+ * load vector f [n_nodes][6] (device, may be NULL) of the last solve. */
+int sso_matrix(sso_problem* p, double* vals, double* f);
+
+/* Sizes: n_dof, block count (6x6 blocks of K) and nnz = 36 * blocks (host outputs). */
+int sso_sizes(const sso_problem* p, int64_t* n_dof, int64_t* n_blocks, int64_t* nnz);
+
+const char* sso_strerror(int status);
+
+void sso_problem_destroy(sso_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HIPSSO_H */

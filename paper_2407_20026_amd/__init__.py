@@ -1,0 +1,277 @@
+"""Python binding of libhipsso (argument marshalling only).
+
+Every step of the analysis runs in the HIP kernels of ``libhipsso.so``; this module converts
+torch tensors (device memory, streams) into the plain pointers and sizes of the C ABI declared
+in ``include/hipsso.h`` and back.  The names follow the C entry points (``sso_problem_create``,
+``sso_solve`` ...); :class:`Problem` bundles them for convenience.
+
+There is no CPU fallback: importing the binding without the built library, or calling it
+without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhipsso.so")
+
+SSO_OK, SSO_EINVAL, SSO_ENOMEM, SSO_EHIP, SSO_ENOTCONV, SSO_EBREAKDOWN = 0, -1, -2, -3, -4, -5
+OBJ_COMPLIANCE, OBJ_STRAIN_ENERGY, OBJ_LINEAR, OBJ_USER = 0, 1, 2, 3
+PREC_FP64, PREC_MIXED = 0, 1
+
+OBJECTIVES = {"compliance": OBJ_COMPLIANCE, "strain_energy": OBJ_STRAIN_ENERGY,
+              "linear": OBJ_LINEAR, "user": OBJ_USER}
+
+_vp = ctypes.c_void_p
+
+
+class sso_mesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("xyz", _vp), ("fixed", _vp), ("f_nodal", _vp),
+                ("n_beams", ctypes.c_int32), ("beam_nodes", _vp), ("beam_prop", _vp),
+                ("n_quads", ctypes.c_int32), ("quad_nodes", _vp), ("quad_prop", _vp),
+                ("quad_scale", _vp), ("unit_weight", ctypes.c_double),
+                ("surface_load", ctypes.c_double)]
+
+
+class sso_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("max_it", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("profile_every", ctypes.c_int32)]
+
+
+class sso_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("t_elem_us", ctypes.c_double), ("t_asm_us", ctypes.c_double),
+                ("t_solve_us", ctypes.c_double), ("t_adj_us", ctypes.c_double),
+                ("bytes_moved", ctypes.c_double), ("spmv_us", ctypes.c_double),
+                ("spmv_samples", ctypes.c_int32), ("spmv_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ("sso_problem_create", "sso_problem_update", "sso_set_options", "sso_solve",
+           "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix", "sso_sizes",
+           "sso_strerror", "sso_problem_destroy")
+
+_lib = None
+_hip = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhipsso.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2407_20026_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.sso_problem_create.argtypes = [P(sso_mesh), P(sso_options), _vp, P(_vp)]
+    lib.sso_problem_update.argtypes = [_vp, _vp, _vp, _vp]
+    lib.sso_set_options.argtypes = [_vp, P(sso_options)]
+    lib.sso_solve.argtypes = [_vp, _vp, P(sso_stats)]
+    lib.sso_objective.argtypes = [_vp, ctypes.c_int, _vp, P(ctypes.c_double)]
+    lib.sso_adjoint.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, P(sso_stats)]
+    lib.sso_pattern.argtypes = [_vp, P(_vp), P(_vp), P(_vp), P(_vp), P(ctypes.c_int64),
+                                P(ctypes.c_int64)]
+    lib.sso_matrix.argtypes = [_vp, _vp, _vp]
+    lib.sso_sizes.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.sso_strerror.argtypes = [ctypes.c_int]
+    lib.sso_strerror.restype = ctypes.c_char_p
+    lib.sso_problem_destroy.argtypes = [_vp]
+    lib.sso_problem_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("sso_strerror", "sso_problem_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
+
+
+class SSOError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = load_library().sso_strerror(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def _check(status: int, where: str) -> int:
+    if status != SSO_OK:
+        raise SSOError(status, where)
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(a, dtype, device):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+
+
+def _stream_handle(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Options:
+    precision: int = PREC_FP64
+    rtol: float = 1e-8
+    max_it: int = 200000
+    refine_steps: int = 20
+    profile_every: int = 0
+
+    def c(self) -> sso_options:
+        return sso_options(self.precision, self.rtol, self.max_it, self.refine_steps,
+                           self.profile_every)
+
+
+class Problem:
+    """One structure on one GPU: owns the library handle and the device copies of the mesh.
+
+    ``mesh`` is a :class:`meshgen.Mesh`-like object (numpy or torch arrays with the C-ABI
+    layout).  All work runs on ``stream`` (default: torch's current stream)."""
+
+    def __init__(self, mesh, options: Options | None = None, device="cuda", stream=None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("hipsso needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self.stream = stream
+        self.n_nodes = int(mesh.xyz.shape[0])
+        self.n_beams = int(mesh.beam_nodes.shape[0])
+        self.n_quads = int(mesh.quad_nodes.shape[0])
+        d = self.device
+        self._xyz = _dev(mesh.xyz, torch.float64, d)
+        self._fixed = _dev(mesh.fixed, torch.uint8, d)
+        self._f = _dev(mesh.f_nodal, torch.float64, d)
+        self._bn = _dev(mesh.beam_nodes, torch.int32, d)
+        self._bp = _dev(mesh.beam_prop, torch.float64, d)
+        self._qn = _dev(mesh.quad_nodes, torch.int32, d)
+        self._qp = _dev(mesh.quad_prop, torch.float64, d)
+        self._qs = _dev(getattr(mesh, "quad_scale", None), torch.float64, d)
+        cm = sso_mesh(self.n_nodes, _ptr(self._xyz), _ptr(self._fixed), _ptr(self._f),
+                      self.n_beams, _ptr(self._bn), _ptr(self._bp),
+                      self.n_quads, _ptr(self._qn), _ptr(self._qp), _ptr(self._qs),
+                      float(mesh.unit_weight), float(mesh.surface_load))
+        self.options = options or Options()
+        opts = self.options.c()
+        h = ctypes.c_void_p()
+        _check(lib.sso_problem_create(ctypes.byref(cm), ctypes.byref(opts),
+                                      _stream_handle(stream), ctypes.byref(h)),
+               "sso_problem_create")
+        self.handle = h
+        self.n_dof = 6 * self.n_nodes
+        nd, nb, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.sso_sizes(h, ctypes.byref(nd), ctypes.byref(nb), ctypes.byref(nz)),
+               "sso_sizes")
+        self.n_blocks, self.nnz = nb.value, nz.value
+        self.last_stats = None
+
+    # -- lifecycle --------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sso_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- C entry points ---------------------------------------------------------------
+    def update(self, xyz=None, quad_t=None, quad_scale=None):
+        d = self.device
+        self._upd = [_dev(a, torch.float64, d) for a in (xyz, quad_t, quad_scale)]
+        _check(load_library().sso_problem_update(self.handle, *[_ptr(a) for a in self._upd]),
+               "sso_problem_update")
+
+    def set_options(self, options: Options):
+        self.options = options
+        o = options.c()
+        _check(load_library().sso_set_options(self.handle, ctypes.byref(o)), "sso_set_options")
+
+    def solve(self, u_out: torch.Tensor | None = None, check: bool = True):
+        """Forward analysis; returns (u [n_nodes, 6] float64 device tensor, stats dict)."""
+        if u_out is None:
+            u_out = torch.empty((self.n_nodes, 6), dtype=torch.float64, device=self.device)
+        st = sso_stats()
+        status = load_library().sso_solve(self.handle, _ptr(u_out), ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        self.last_status = status
+        if check:
+            _check(status, "sso_solve")
+        return u_out, self.last_stats
+
+    def objective(self, kind="compliance", a=None) -> float:
+        g = ctypes.c_double()
+        at = _dev(a, torch.float64, self.device)
+        _check(load_library().sso_objective(self.handle, OBJECTIVES.get(kind, kind), _ptr(at),
+                                            ctypes.byref(g)), "sso_objective")
+        return g.value
+
+    def adjoint(self, kind="compliance", dg_du=None, want_t=True, want_scale=True):
+        """Gradient of the objective: dict with dg_dxyz [n_nodes, 3], dg_dt [n_quads],
+        dg_dscale [n_quads] (float64 device tensors) and the stats."""
+        d = self.device
+        gx = torch.empty((self.n_nodes, 3), dtype=torch.float64, device=d)
+        gt = torch.empty(self.n_quads, dtype=torch.float64, device=d) if want_t else None
+        gs = torch.empty(self.n_quads, dtype=torch.float64, device=d) if want_scale else None
+        du = _dev(dg_du, torch.float64, d)
+        st = sso_stats()
+        _check(load_library().sso_adjoint(self.handle, OBJECTIVES.get(kind, kind), _ptr(du),
+                                          _ptr(gx), _ptr(gt) if self.n_quads else None,
+                                          _ptr(gs) if self.n_quads else None, ctypes.byref(st)),
+               "sso_adjoint")
+        return dict(dg_dxyz=gx, dg_dt=gt, dg_dscale=gs, stats=st.as_dict())
+
+    def pattern(self):
+        """Copies of the scalar CSR view and the scatter permutation (int32 device tensors)."""
+        rp, col, perm, seg = (ctypes.c_void_p() for _ in range(4))
+        nnz, ncoo = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().sso_pattern(self.handle, ctypes.byref(rp), ctypes.byref(col),
+                                          ctypes.byref(perm), ctypes.byref(seg),
+                                          ctypes.byref(nnz), ctypes.byref(ncoo)), "sso_pattern")
+        out = {}
+        for name, src, n in (("row_ptr", rp, self.n_dof + 1), ("col", col, nnz.value),
+                             ("perm", perm, ncoo.value), ("seg", seg, nnz.value + 1)):
+            t = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)[:n]
+            if n:
+                torch.cuda.synchronize()
+                if _hiprt().hipMemcpy(_ptr(t), src, 4 * n, 3) != 0:
+                    raise RuntimeError("hipMemcpy failed")
+            out[name] = t
+        return out
+
+    def matrix(self):
+        """(K values in scalar CSR order [nnz], masked load vector [n_nodes, 6])."""
+        vals = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        f = torch.empty((self.n_nodes, 6), dtype=torch.float64, device=self.device)
+        _check(load_library().sso_matrix(self.handle, _ptr(vals), _ptr(f)), "sso_matrix")
+        return vals, f

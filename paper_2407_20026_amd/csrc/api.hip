@@ -1,0 +1,385 @@
+// C ABI and host runtime of libhipsso: problem lifecycle, device buffers, launch sequencing on
+// the problem's stream, error mapping and per-stage timing.
+#include <new>
+#include <cstring>
+
+#include "sso_internal.h"
+
+using namespace sso;
+
+struct sso_problem {
+  hipStream_t s = nullptr;
+  Mesh m;
+  Pattern pat;
+  sso_options opt;
+  int64_t n_coo = 0;
+  double* coo = nullptr;
+  double* qarea = nullptr;
+  double* K = nullptr;
+  double* Dinv = nullptr;
+  double* f = nullptr;
+  double* u = nullptr;
+  double* lam = nullptr;
+  double* rhs = nullptr;
+  double* gbeam = nullptr;
+  double* gquad = nullptr;
+  double* d_scal = nullptr;     // small device scalars (dot products, residual norms)
+  double* h_scal = nullptr;     // pinned mirror
+  unsigned* d_err = nullptr;
+  unsigned* h_err = nullptr;    // pinned
+  PcgWork w;
+  int32_t* row_ptr = nullptr;   // scalar CSR view (built on demand)
+  int32_t* col = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* seg = nullptr;
+  bool solved = false;
+  hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+sso_options default_options() {
+  sso_options o;
+  o.precision = SSO_PREC_FP64;
+  o.rtol = 1e-8;
+  o.max_it = 200000;
+  o.refine_steps = 20;
+  o.profile_every = 0;
+  return o;
+}
+
+bool options_ok(const sso_options& o) {
+  return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED) && o.rtol >= 0.0 &&
+         o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0;
+}
+
+__global__ void k_fill(int64_t n, double v, double* out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+template <class T>
+hipError_t dalloc(T** p, int64_t n) {
+  if (n <= 0) n = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
+}
+
+int map_hip(hipError_t e) {
+  if (e == hipSuccess) return SSO_OK;
+  if (e == hipErrorOutOfMemory) return SSO_ENOMEM;
+  return SSO_EHIP;
+}
+
+#define TRY_HIP(x)                     \
+  do {                                 \
+    hipError_t e_ = (x);               \
+    if (e_ != hipSuccess) return map_hip(e_); \
+  } while (0)
+
+float elapsed_us(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return 1000.f * ms;
+}
+
+void free_problem(sso_problem* p) {
+  if (!p) return;
+  if (p->s) hipStreamSynchronize(p->s);
+  Mesh& m = p->m;
+  hipFree(m.xyz); hipFree(m.fixed); hipFree(m.f_nodal); hipFree(m.beam_nodes);
+  hipFree(m.beam_prop); hipFree(m.quad_nodes); hipFree(m.quad_prop); hipFree(m.quad_scale);
+  free_pattern(p->pat);
+  hipFree(p->coo); hipFree(p->qarea); hipFree(p->K); hipFree(p->Dinv); hipFree(p->f);
+  hipFree(p->u); hipFree(p->lam); hipFree(p->rhs); hipFree(p->gbeam); hipFree(p->gquad);
+  hipFree(p->d_scal); hipFree(p->d_err);
+  if (p->h_scal) hipHostFree(p->h_scal);
+  if (p->h_err) hipHostFree(p->h_err);
+  hipFree(p->row_ptr); hipFree(p->col); hipFree(p->perm); hipFree(p->seg);
+  pcg_free(p->w);
+  for (auto& e : p->ev)
+    if (e) hipEventDestroy(e);
+  delete p;
+}
+
+int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
+                sso_problem* p) {
+  p->s = stream;
+  p->opt = opts ? *opts : default_options();
+  Mesh& m = p->m;
+  m.n_nodes = mesh->n_nodes;
+  m.n_beams = mesh->n_beams;
+  m.n_quads = mesh->n_quads;
+  m.unit_weight = mesh->unit_weight;
+  m.surface_load = mesh->surface_load;
+  const int64_t nn = m.n_nodes, nb = m.n_beams, nq = m.n_quads;
+  TRY_HIP(dalloc(&m.xyz, 3 * nn));
+  TRY_HIP(dalloc(&m.fixed, 6 * nn));
+  TRY_HIP(dalloc(&m.f_nodal, 6 * nn));
+  TRY_HIP(dalloc(&m.beam_nodes, 2 * nb));
+  TRY_HIP(dalloc(&m.beam_prop, 6 * nb));
+  TRY_HIP(dalloc(&m.quad_nodes, 4 * nq));
+  TRY_HIP(dalloc(&m.quad_prop, 5 * nq));
+  TRY_HIP(dalloc(&m.quad_scale, nq));
+  hipStream_t s = p->s;
+  TRY_HIP(hipMemcpyAsync(m.xyz, mesh->xyz, sizeof(double) * 3 * nn, hipMemcpyDeviceToDevice, s));
+  TRY_HIP(hipMemcpyAsync(m.fixed, mesh->fixed, 6 * nn, hipMemcpyDeviceToDevice, s));
+  TRY_HIP(hipMemcpyAsync(m.f_nodal, mesh->f_nodal, sizeof(double) * 6 * nn,
+                         hipMemcpyDeviceToDevice, s));
+  if (nb) {
+    TRY_HIP(hipMemcpyAsync(m.beam_nodes, mesh->beam_nodes, sizeof(int32_t) * 2 * nb,
+                           hipMemcpyDeviceToDevice, s));
+    TRY_HIP(hipMemcpyAsync(m.beam_prop, mesh->beam_prop, sizeof(double) * 6 * nb,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  if (nq) {
+    TRY_HIP(hipMemcpyAsync(m.quad_nodes, mesh->quad_nodes, sizeof(int32_t) * 4 * nq,
+                           hipMemcpyDeviceToDevice, s));
+    TRY_HIP(hipMemcpyAsync(m.quad_prop, mesh->quad_prop, sizeof(double) * 5 * nq,
+                           hipMemcpyDeviceToDevice, s));
+    if (mesh->quad_scale) {
+      TRY_HIP(hipMemcpyAsync(m.quad_scale, mesh->quad_scale, sizeof(double) * nq,
+                             hipMemcpyDeviceToDevice, s));
+    } else {
+      hipLaunchKernelGGL(k_fill, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, 1.0,
+                         m.quad_scale);
+      TRY_HIP(hipGetLastError());
+    }
+  }
+  TRY_HIP(dalloc(&p->d_err, 1));
+  TRY_HIP(hipHostMalloc(&p->h_err, sizeof(unsigned), hipHostMallocDefault));
+  TRY_HIP(dalloc(&p->d_scal, 8));
+  TRY_HIP(hipHostMalloc(&p->h_scal, 8 * sizeof(double), hipHostMallocDefault));
+  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
+  *p->h_err = 0;
+  TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
+  if (*p->h_err) return SSO_EINVAL;
+  p->n_coo = 144 * nb + 576 * nq;
+  TRY_HIP(dalloc(&p->coo, p->n_coo));
+  TRY_HIP(dalloc(&p->qarea, nq));
+  TRY_HIP(dalloc(&p->K, 36 * p->pat.n_blocks));
+  TRY_HIP(dalloc(&p->Dinv, 36 * nn));
+  TRY_HIP(dalloc(&p->f, 6 * nn));
+  TRY_HIP(dalloc(&p->u, 6 * nn));
+  TRY_HIP(dalloc(&p->lam, 6 * nn));
+  TRY_HIP(dalloc(&p->rhs, 6 * nn));
+  TRY_HIP(dalloc(&p->gbeam, 6 * nb));
+  TRY_HIP(dalloc(&p->gquad, 14 * nq));
+  TRY_HIP(pcg_alloc(p->w, nn, p->opt.precision == SSO_PREC_MIXED));
+  for (auto& e : p->ev) TRY_HIP(hipEventCreate(&e));
+  TRY_HIP(hipStreamSynchronize(s));
+  return SSO_OK;
+}
+
+int read_errors(sso_problem* p) {
+  TRY_HIP(hipMemcpyAsync(p->h_err, p->d_err, sizeof(unsigned), hipMemcpyDeviceToHost, p->s));
+  TRY_HIP(hipStreamSynchronize(p->s));
+  return *p->h_err ? SSO_EINVAL : SSO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
+                       sso_problem** out) {
+  if (!mesh || !out) return SSO_EINVAL;
+  *out = nullptr;
+  if (mesh->n_nodes <= 0 || mesh->n_beams < 0 || mesh->n_quads < 0) return SSO_EINVAL;
+  if (!mesh->xyz || !mesh->fixed || !mesh->f_nodal) return SSO_EINVAL;
+  if (mesh->n_beams > 0 && (!mesh->beam_nodes || !mesh->beam_prop)) return SSO_EINVAL;
+  if (mesh->n_quads > 0 && (!mesh->quad_nodes || !mesh->quad_prop)) return SSO_EINVAL;
+  if (16 * (int64_t)mesh->n_quads + 4 * (int64_t)mesh->n_beams >= (int64_t)1 << 31)
+    return SSO_EINVAL;
+  if (opts && !options_ok(*opts)) return SSO_EINVAL;
+  sso_problem* p = new (std::nothrow) sso_problem();
+  if (!p) return SSO_ENOMEM;
+  int st = create_impl(mesh, opts, stream, p);
+  if (st != SSO_OK) {
+    free_problem(p);
+    return st;
+  }
+  *out = p;
+  return SSO_OK;
+}
+
+int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
+                       const double* quad_scale) {
+  if (!p) return SSO_EINVAL;
+  Mesh& m = p->m;
+  if (xyz)
+    TRY_HIP(hipMemcpyAsync(m.xyz, xyz, sizeof(double) * 3 * (size_t)m.n_nodes,
+                           hipMemcpyDeviceToDevice, p->s));
+  if (quad_t && m.n_quads)
+    TRY_HIP(hipMemcpy2DAsync(m.quad_prop, 5 * sizeof(double), quad_t, sizeof(double),
+                             sizeof(double), (size_t)m.n_quads, hipMemcpyDeviceToDevice, p->s));
+  if (quad_scale && m.n_quads)
+    TRY_HIP(hipMemcpyAsync(m.quad_scale, quad_scale, sizeof(double) * (size_t)m.n_quads,
+                           hipMemcpyDeviceToDevice, p->s));
+  p->solved = false;
+  return SSO_OK;
+}
+
+int sso_set_options(sso_problem* p, const sso_options* opts) {
+  if (!p || !opts || !options_ok(*opts)) return SSO_EINVAL;
+  p->opt = *opts;
+  return SSO_OK;
+}
+
+int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
+  if (!p) return SSO_EINVAL;
+  if (p->opt.precision != SSO_PREC_FP64) return SSO_EINVAL;
+  hipStream_t s = p->s;
+  p->solved = false;
+  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
+  TRY_HIP(hipEventRecord(p->ev[0], s));
+  TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
+  TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
+  TRY_HIP(hipEventRecord(p->ev[1], s));
+  TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
+  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, nullptr, p->d_err, s));
+  TRY_HIP(hipEventRecord(p->ev[2], s));
+  int st = read_errors(p);
+  if (st != SSO_OK) return st;
+  int iters = 0, status = SSO_OK;
+  TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it, p->w,
+                    s, &iters, &status, p->opt.profile_every));
+  TRY_HIP(hipEventRecord(p->ev[3], s));
+  TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
+  TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (u_out)
+    TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
+                           hipMemcpyDeviceToDevice, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
+    stats->t_elem_us = elapsed_us(p->ev[0], p->ev[1]);
+    stats->t_asm_us = elapsed_us(p->ev[1], p->ev[2]);
+    stats->t_solve_us = elapsed_us(p->ev[2], p->ev[3]);
+    stats->bytes_moved =
+        iters * pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->spmv_samples = p->w.prof_n;
+    stats->spmv_us = p->w.prof_n ? p->w.prof_us / p->w.prof_n : 0.0;
+    stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
+  }
+  // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available
+  p->solved = (status == SSO_OK || status == SSO_ENOTCONV);
+  return status;
+}
+
+int sso_objective(sso_problem* p, int kind, const double* a, double* g_host) {
+  if (!p || !g_host || !p->solved) return SSO_EINVAL;
+  const double* lhs;
+  double scale = 1.0;
+  if (kind == SSO_OBJ_COMPLIANCE) {
+    lhs = p->f;
+  } else if (kind == SSO_OBJ_STRAIN_ENERGY) {
+    lhs = p->f;
+    scale = 0.5;
+  } else if (kind == SSO_OBJ_LINEAR && a) {
+    lhs = a;
+  } else {
+    return SSO_EINVAL;
+  }
+  const int64_t n = 6 * (int64_t)p->m.n_nodes;
+  int nwg = (int)((n + 255) / 256);
+  if (nwg > 1024) nwg = 1024;
+  TRY_HIP(launch_dot(lhs, p->u, n, p->w.partials, nwg, &p->w.st->counter[3], p->d_scal, p->s));
+  TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, sizeof(double), hipMemcpyDeviceToHost, p->s));
+  TRY_HIP(hipStreamSynchronize(p->s));
+  *g_host = scale * p->h_scal[0];
+  return SSO_OK;
+}
+
+int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, double* dg_dt,
+                double* dg_dscale, sso_stats* stats) {
+  if (!p || !p->solved || !dg_dxyz) return SSO_EINVAL;
+  hipStream_t s = p->s;
+  double c_lam = 1.0, c_u = 1.0;
+  const double* lam = p->u;
+  int iters = 0, status = SSO_OK;
+  TRY_HIP(hipEventRecord(p->ev[4], s));
+  if (kind == SSO_OBJ_COMPLIANCE || kind == SSO_OBJ_STRAIN_ENERGY) {
+    if (kind == SSO_OBJ_STRAIN_ENERGY) c_lam = c_u = 0.5;
+  } else if (kind == SSO_OBJ_LINEAR || kind == SSO_OBJ_USER) {
+    if (!dg_du) return SSO_EINVAL;
+    c_u = 0.0;
+    TRY_HIP(launch_mask_vector(p->m, dg_du, p->rhs, s));
+    TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, p->rhs, p->lam, p->opt.rtol, p->opt.max_it,
+                      p->w, s, &iters, &status, p->opt.profile_every));
+    if (status != SSO_OK) return status;
+    lam = p->lam;
+  } else {
+    return SSO_EINVAL;
+  }
+  TRY_HIP(launch_adjoint_terms(p->m, p->pat, p->u, lam, c_lam, c_u, p->gbeam, p->gquad, s));
+  TRY_HIP(launch_gather(p->m, p->pat, p->gbeam, p->gquad, dg_dxyz, dg_dt, dg_dscale, s));
+  TRY_HIP(hipEventRecord(p->ev[5], s));
+  TRY_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
+    stats->bytes_moved =
+        iters * pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false);
+  }
+  return SSO_OK;
+}
+
+int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
+                const int32_t** perm, const int32_t** seg, int64_t* nnz, int64_t* n_coo) {
+  if (!p) return SSO_EINVAL;
+  if (p->n_coo >= ((int64_t)1 << 31) || 36 * p->pat.n_blocks >= ((int64_t)1 << 31))
+    return SSO_EINVAL;
+  const int64_t nz = 36 * p->pat.n_blocks;
+  if (!p->row_ptr) {
+    TRY_HIP(dalloc(&p->row_ptr, 6 * (int64_t)p->m.n_nodes + 1));
+    TRY_HIP(dalloc(&p->col, nz));
+    TRY_HIP(dalloc(&p->perm, p->n_coo));
+    TRY_HIP(dalloc(&p->seg, nz + 1));
+    TRY_HIP(build_scalar_view(p->m, p->pat, p->row_ptr, p->col, p->perm, p->seg, p->s));
+    TRY_HIP(hipStreamSynchronize(p->s));
+  }
+  if (row_ptr) *row_ptr = p->row_ptr;
+  if (col) *col = p->col;
+  if (perm) *perm = p->perm;
+  if (seg) *seg = p->seg;
+  if (nnz) *nnz = nz;
+  if (n_coo) *n_coo = p->n_coo;
+  return SSO_OK;
+}
+
+int sso_matrix(sso_problem* p, double* vals, double* f) {
+  if (!p || !vals) return SSO_EINVAL;
+  TRY_HIP(launch_scalar_values(p->m, p->pat, p->K, vals, p->s));
+  if (f)
+    TRY_HIP(hipMemcpyAsync(f, p->f, sizeof(double) * 6 * (size_t)p->m.n_nodes,
+                           hipMemcpyDeviceToDevice, p->s));
+  TRY_HIP(hipStreamSynchronize(p->s));
+  return SSO_OK;
+}
+
+int sso_sizes(const sso_problem* p, int64_t* n_dof, int64_t* n_blocks, int64_t* nnz) {
+  if (!p) return SSO_EINVAL;
+  if (n_dof) *n_dof = 6 * (int64_t)p->m.n_nodes;
+  if (n_blocks) *n_blocks = p->pat.n_blocks;
+  if (nnz) *nnz = 36 * p->pat.n_blocks;
+  return SSO_OK;
+}
+
+const char* sso_strerror(int status) {
+  switch (status) {
+    case SSO_OK: return "ok";
+    case SSO_EINVAL: return "invalid argument or degenerate element";
+    case SSO_ENOMEM: return "device memory allocation failed";
+    case SSO_EHIP: return "HIP runtime error";
+    case SSO_ENOTCONV: return "PCG did not reach the residual target within max_it";
+    case SSO_EBREAKDOWN: return "PCG breakdown: stiffness not positive definite";
+    default: return "unknown status";
+  }
+}
+
+void sso_problem_destroy(sso_problem* p) { free_problem(p); }
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Assembly, support masking, loads and the block-Jacobi preconditioner.
+//
+// Sec. 2.2.1: K is the sum of all element matrices placed by their index maps; supports enter
+// through Lagrange multipliers with V u = b.  For b = 0 the same displacement follows from
+// masking: a constrained DOF d gets K[d, :] = K[:, d] = 0, K[d, d] = 1 and f[d] = 0, which keeps
+// K symmetric positive definite and its pattern unchanged.
+//
+// Assembly is gather-based and deterministic: one thread per entry (slot, a, b) of a 6x6 block
+// sums the slot's element contributions in ascending contribution id (= ascending element, then
+// ascending scalar index), with no atomics, so K is bitwise reproducible.
+#include "sso_internal.h"
+
+namespace sso {
+namespace {
+
+inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+__device__ inline void node_of(const Mesh& m, const BlockRef& r, int& I) {
+  I = r.quad ? m.quad_nodes[4 * (int64_t)r.e + r.la] : m.beam_nodes[2 * (int64_t)r.e + r.la];
+}
+
+// K block values, row-major inside each 6x6 block, blocks in slot order.
+__global__ void k_assemble(Mesh m, int64_t n_blocks, const int32_t* bsrow, const int32_t* bcol,
+                           const int32_t* bseg, const int32_t* bperm, const double* coo,
+                           double* K) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 36 * n_blocks) return;
+  int64_t s = t / 36;
+  int a = (int)(t % 36) / 6, b = (int)(t % 6);
+  int I = bsrow[s], J = bcol[s];
+  double v;
+  if (m.fixed[6 * (int64_t)I + a] || m.fixed[6 * (int64_t)J + b]) {
+    v = (I == J && a == b) ? 1.0 : 0.0;
+  } else {
+    v = 0.0;
+    for (int p = bseg[s]; p < bseg[s + 1]; ++p) {
+      BlockRef r = decode_block(bperm[p], m.n_beams);
+      v += coo[coo_index(r, a, b, m.n_beams)];
+    }
+  }
+  K[t] = v;
+}
+
+// f = f_nodal + sum over incident quads (ascending element) of -(gamma t + q) A / 4 on uz,
+// masked.  The diagonal block slot of node I lists its incident elements in that order.
+__global__ void k_loads(Mesh m, const int32_t* bdiag, const int32_t* bseg, const int32_t* bperm,
+                        const double* qarea, double* f) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 6 * (int64_t)m.n_nodes) return;
+  int I = (int)(t / 6), c = (int)(t % 6);
+  double v = m.f_nodal[t];
+  if (c == 2 && (m.unit_weight != 0.0 || m.surface_load != 0.0)) {
+    int s = bdiag[I];
+    for (int p = bseg[s]; p < bseg[s + 1]; ++p) {
+      BlockRef r = decode_block(bperm[p], m.n_beams);
+      if (!r.quad) continue;
+      double te = m.quad_prop[5 * (int64_t)r.e];
+      v += -(m.unit_weight * te + m.surface_load) * qarea[r.e] / 4.0;
+    }
+  }
+  f[t] = m.fixed[t] ? 0.0 : v;
+}
+
+__global__ void k_mask_vector(int64_t n, const uint8_t* fixed, const double* in, double* out) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  out[t] = fixed[t] ? 0.0 : in[t];
+}
+
+// Dinv_I = (K_II)^{-1} by Cholesky of the (masked, SPD) diagonal block; full 6x6 row-major.
+__global__ void k_block_jacobi(int n_nodes, const int32_t* bdiag, const double* K, double* Dinv,
+                               float* Dinv32, unsigned* err) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n_nodes) return;
+  const double* A = K + 36 * (int64_t)bdiag[I];
+  double L[6][6];
+  bool ok = true;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) L[i][j] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    double d = A[6 * j + j];
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0)) {
+      ok = false;
+      d = 1.0;
+    }
+    L[j][j] = sqrt(d);
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[6 * i + j];
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  if (!ok) atomicOr(err, ERR_DIAG);
+  // W = L^{-1} (lower triangular), then Dinv = W^T W
+  double W[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) W[i][j] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    W[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < 6; ++i) {
+      double v = 0.0;
+      for (int k = j; k < i; ++k) v -= L[i][k] * W[k][j];
+      W[i][j] = v / L[i][i];
+    }
+  }
+  double* out = Dinv + 36 * (int64_t)I;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double v = 0.0;
+      for (int k = (i > j ? i : j); k < 6; ++k) v += W[k][i] * W[k][j];
+      out[6 * i + j] = v;
+      if (Dinv32) Dinv32[36 * (int64_t)I + 6 * i + j] = (float)v;
+    }
+}
+
+// Scalar CSR order of the block values (for read-back and parity checks).
+__global__ void k_scalar_values(int n_nodes, const int32_t* brow_ptr, const double* K,
+                                double* vals) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 6 * (int64_t)n_nodes) return;
+  int I = (int)(t / 6), a = (int)(t % 6);
+  int rb = brow_ptr[I], nbc = brow_ptr[I + 1] - rb;
+  int64_t rp = 36 * (int64_t)rb + 6 * (int64_t)a * nbc;
+  for (int k = 0; k < nbc; ++k)
+    for (int b = 0; b < 6; ++b) vals[rp + 6 * k + b] = K[36 * (int64_t)(rb + k) + 6 * a + b];
+}
+
+}  // namespace
+
+hipError_t launch_assemble(const Mesh& m, const Pattern& pat, const double* coo, double* K,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble, dim3(nblk(36 * pat.n_blocks, 256)), dim3(256), 0, s, m,
+                     pat.n_blocks, pat.bsrow, pat.bcol, pat.bseg, pat.bperm, coo, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_loads(const Mesh& m, const Pattern& pat, const double* qarea, double* f,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_loads, dim3(nblk(6 * (int64_t)m.n_nodes, 256)), dim3(256), 0, s, m,
+                     pat.bdiag, pat.bseg, pat.bperm, qarea, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_vector(const Mesh& m, const double* in, double* out, hipStream_t s) {
+  int64_t n = 6 * (int64_t)m.n_nodes;
+  hipLaunchKernelGGL(k_mask_vector, dim3(nblk(n, 256)), dim3(256), 0, s, n, m.fixed, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_jacobi(const Mesh& m, const Pattern& pat, const double* K, double* Dinv,
+                               float* Dinv32, unsigned* d_err, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_jacobi, dim3(nblk(m.n_nodes, 128)), dim3(128), 0, s, m.n_nodes,
+                     pat.bdiag, K, Dinv, Dinv32, d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_values(const Mesh& m, const Pattern& pat, const double* K, double* vals,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar_values, dim3(nblk(6 * (int64_t)m.n_nodes, 256)), dim3(256), 0, s,
+                     m.n_nodes, pat.brow_ptr, K, vals);
+  return hipGetLastError();
+}
+
+}  // namespace sso

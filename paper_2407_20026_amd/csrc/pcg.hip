@@ -1,0 +1,421 @@
+// Block-Jacobi preconditioned conjugate gradients on the masked K (BSR, 6x6 blocks).
+//
+// The paper solves K u = f (Eq. 1, with the supports of Eqs. 2-3) with direct solvers
+// (Sec. 2.2.2).  On the GPU the solve is a bandwidth-bound iteration instead: per iteration
+//   k_spmv_dir : p = z + beta p_old (formed on the fly), Ap = K p, partial p^T A p
+//   k_update   : x += alpha p, r -= alpha Ap, z = Dinv r, partials r^T z and r^T r
+// Scalars (alpha, beta, convergence) are finished on the device by the last workgroup to arrive
+// (integer arrival counter; the partials are summed in a fixed order, so every reduction is
+// deterministic), so the host only polls a small state record every few iterations.  Once the
+// state says done, later kernels of the same chunk return at entry.
+//
+// Thread layout of the row kernels: 6 consecutive lanes per node (block row), lane a owning
+// scalar row 6 I + a; it streams the a-th row of every 6x6 block of the block row (48
+// contiguous bytes) so the 6 lanes of a node read each 288-byte block once, in order.
+#include "sso_internal.h"
+
+namespace sso {
+namespace {
+
+constexpr int MAX_TPB = 384;
+constexpr int MAX_WAVES = MAX_TPB / 64;
+
+inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+__device__ inline double atomic_load_f64(const double* p) {
+  unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)b);
+}
+__device__ inline void atomic_store_f64(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order block sum of NV values; the result is valid in thread 0.
+template <int NV>
+__device__ inline void block_sum(double v[NV]) {
+  __shared__ double lds[NV][MAX_WAVES];
+  for (int off = 32; off > 0; off >>= 1)
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = (blockDim.x + 63) >> 6;
+  if (lane == 0)
+    for (int k = 0; k < NV; ++k) lds[k][wave] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NV; ++k) {
+      double s = lds[k][0];
+      for (int w = 1; w < nw; ++w) s += lds[k][w];
+      v[k] = s;
+    }
+  __syncthreads();
+}
+
+// Publish this workgroup's partial sums; returns true in every thread of the last workgroup
+// to arrive, whose v[] then holds the totals (valid in thread 0).
+template <int NV>
+__device__ inline bool publish_and_total(double v[NV], double* partials, unsigned* counter) {
+  __shared__ int last;
+  const int n = gridDim.x;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NV; ++k) atomic_store_f64(&partials[k * n + blockIdx.x], v[k]);
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == (unsigned)n - 1u);
+  }
+  __syncthreads();
+  if (!last) return false;
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += atomic_load_f64(&partials[k * n + i]);
+    v[k] = s;
+  }
+  block_sum<NV>(v);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+struct RowMap {
+  int lr, a, I;
+  bool valid;
+};
+
+__device__ inline RowMap row_map(int rpb, int n_nodes) {
+  RowMap m;
+  m.lr = threadIdx.x / 6;
+  m.a = threadIdx.x - 6 * m.lr;
+  m.I = blockIdx.x * rpb + m.lr;
+  m.valid = (m.lr < rpb) && (m.I < n_nodes);
+  return m;
+}
+
+// z = Dinv r for the node of this lane, r values of the node staged in LDS.
+__device__ inline double apply_dinv(const double* Dinv, const double* rs, const RowMap& m) {
+  const double2* dv = reinterpret_cast<const double2*>(Dinv + 36 * (int64_t)m.I + 6 * m.a);
+  const double* rr = rs + 6 * m.lr;
+  double z = 0.0;
+  for (int h = 0; h < 3; ++h) {
+    double2 d = dv[h];
+    z += d.x * rr[2 * h] + d.y * rr[2 * h + 1];
+  }
+  return z;
+}
+
+__global__ void __launch_bounds__(MAX_TPB)
+k_pcg_init(int n_nodes, int rpb, const double* b, double* x, double* r, double* z, double* p0,
+           const double* Dinv, double rtol, int max_it, double* partials, PcgState* st) {
+  __shared__ double rs[MAX_TPB];
+  RowMap m = row_map(rpb, n_nodes);
+  const int64_t d = 6 * (int64_t)m.I + m.a;
+  double rv = 0.0;
+  if (m.valid) {
+    rv = b[d];
+    x[d] = 0.0;
+    r[d] = rv;
+    p0[d] = 0.0;
+  }
+  rs[threadIdx.x] = rv;
+  __syncthreads();
+  double zz = 0.0;
+  if (m.valid) {
+    zz = apply_dinv(Dinv, rs, m);
+    z[d] = zz;
+  }
+  double v[2] = {rv * zz, rv * rv};
+  block_sum<2>(v);
+  if (publish_and_total<2>(v, partials, &st->counter[0]) && threadIdx.x == 0) {
+    st->rz = v[0];
+    st->rr = v[1];
+    st->ff = v[1];
+    st->tol2 = rtol * rtol * v[1];
+    st->pAp = 0.0;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->it = 0;
+    st->max_it = max_it;
+    st->status = SSO_OK;
+    st->done = (v[1] == 0.0) ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(MAX_TPB)
+k_spmv_dir(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
+           const int32_t* __restrict__ bcol, const double* __restrict__ K,
+           const double* __restrict__ z, const double* __restrict__ pold, double* __restrict__ pnew,
+           double* __restrict__ Ap, double* partials, PcgState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  RowMap m = row_map(rpb, n_nodes);
+  double my = 0.0;
+  if (m.valid) {
+    const int rb = brow_ptr[m.I], re = brow_ptr[m.I + 1];
+    double acc = 0.0;
+    for (int s = rb; s < re; ++s) {
+      const int64_t J = bcol[s];
+      const double2* kr = reinterpret_cast<const double2*>(K + 36 * (int64_t)s + 6 * m.a);
+      const double2* zj = reinterpret_cast<const double2*>(z + 6 * J);
+      const double2* pj = reinterpret_cast<const double2*>(pold + 6 * J);
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const double2 kv = kr[h], zv = zj[h], pv = pj[h];
+        acc += kv.x * (zv.x + beta * pv.x) + kv.y * (zv.y + beta * pv.y);
+      }
+    }
+    const int64_t d = 6 * (int64_t)m.I + m.a;
+    const double pn = z[d] + beta * pold[d];
+    pnew[d] = pn;
+    Ap[d] = acc;
+    my = pn * acc;
+  }
+  double v[1] = {my};
+  block_sum<1>(v);
+  if (publish_and_total<1>(v, partials, &st->counter[1]) && threadIdx.x == 0) {
+    const double pAp = v[0];
+    const double alpha = st->rz / pAp;
+    st->pAp = pAp;
+    st->alpha = alpha;
+    if (!(pAp > 0.0) || !isfinite(alpha)) {
+      st->status = SSO_EBREAKDOWN;
+      st->done = 1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(MAX_TPB)
+k_update(int n_nodes, int rpb, double* __restrict__ x, double* __restrict__ r,
+         double* __restrict__ z, const double* __restrict__ p, const double* __restrict__ Ap,
+         const double* __restrict__ Dinv, double* partials, PcgState* st) {
+  __shared__ double rs[MAX_TPB];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  RowMap m = row_map(rpb, n_nodes);
+  const int64_t d = 6 * (int64_t)m.I + m.a;
+  double rn = 0.0;
+  if (m.valid) {
+    x[d] += alpha * p[d];
+    rn = r[d] - alpha * Ap[d];
+    r[d] = rn;
+  }
+  rs[threadIdx.x] = rn;
+  __syncthreads();
+  double zz = 0.0;
+  if (m.valid) {
+    zz = apply_dinv(Dinv, rs, m);
+    z[d] = zz;
+  }
+  double v[2] = {rn * zz, rn * rn};
+  block_sum<2>(v);
+  if (publish_and_total<2>(v, partials, &st->counter[2]) && threadIdx.x == 0) {
+    const double rz = v[0], rr = v[1];
+    st->beta = rz / st->rz;
+    st->rz = rz;
+    st->rr = rr;
+    st->it += 1;
+    if (!isfinite(rr) || !isfinite(rz)) {
+      st->status = SSO_EBREAKDOWN;
+      st->done = 1;
+    } else if (rr <= st->tol2) {
+      st->done = 1;
+    } else if (st->it >= st->max_it) {
+      st->status = SSO_ENOTCONV;
+      st->done = 1;
+    }
+  }
+}
+
+// r = b - K x; out[0] = ||r||^2, out[1] = ||b||^2.
+__global__ void __launch_bounds__(MAX_TPB)
+k_residual(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
+           const int32_t* __restrict__ bcol, const double* __restrict__ K,
+           const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
+           double* partials, unsigned* counter, double* out) {
+  RowMap m = row_map(rpb, n_nodes);
+  double rr = 0.0, bb = 0.0;
+  if (m.valid) {
+    const int rb = brow_ptr[m.I], re = brow_ptr[m.I + 1];
+    double acc = 0.0;
+    for (int s = rb; s < re; ++s) {
+      const int64_t J = bcol[s];
+      const double* kr = K + 36 * (int64_t)s + 6 * m.a;
+      const double* xj = x + 6 * J;
+      for (int c = 0; c < 6; ++c) acc += kr[c] * xj[c];
+    }
+    const int64_t d = 6 * (int64_t)m.I + m.a;
+    const double rv = b[d] - acc;
+    if (r) r[d] = rv;
+    rr = rv * rv;
+    bb = b[d] * b[d];
+  }
+  double v[2] = {rr, bb};
+  block_sum<2>(v);
+  if (publish_and_total<2>(v, partials, counter) && threadIdx.x == 0) {
+    out[0] = v[0];
+    out[1] = v[1];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* partials,
+      unsigned* counter, double* out) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  double v[1] = {s};
+  block_sum<1>(v);
+  if (publish_and_total<1>(v, partials, counter) && threadIdx.x == 0) out[0] = v[0];
+}
+
+__global__ void k_convert_f32(int64_t n, const double* in, float* out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+}  // namespace
+
+static int choose_rpb(int64_t n_nodes) {
+  if (n_nodes >= 64 * 1024) return 64;    // 384 threads
+  if (n_nodes >= 32 * 512) return 32;     // 192 threads
+  return 10;                              // 64 threads
+}
+
+static int tpb_for(int rpb) { return ((6 * rpb + 63) / 64) * 64; }
+
+hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed) {
+  w.n_dof = 6 * n_nodes;
+  w.rows_per_block = choose_rpb(n_nodes);
+  w.n_wg = (int)((n_nodes + w.rows_per_block - 1) / w.rows_per_block);
+  const size_t vb = sizeof(double) * (size_t)w.n_dof;
+  hipError_t e;
+  if ((e = hipMalloc(&w.r, vb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.z, vb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.p[0], vb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.p[1], vb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.Ap, vb)) != hipSuccess) return e;
+  int np = w.n_wg > 1024 ? w.n_wg : 1024;
+  if ((e = hipMalloc(&w.partials, sizeof(double) * 4 * (size_t)np)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.st, sizeof(PcgState))) != hipSuccess) return e;
+  if ((e = hipMemset(w.st, 0, sizeof(PcgState))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&w.h_st, sizeof(PcgState), hipHostMallocDefault)) != hipSuccess)
+    return e;
+  (void)mixed;
+  return hipSuccess;
+}
+
+void pcg_free(PcgWork& w) {
+  hipFree(w.r); hipFree(w.z); hipFree(w.p[0]); hipFree(w.p[1]); hipFree(w.Ap);
+  hipFree(w.partials); hipFree(w.st);
+  if (w.h_st) hipHostFree(w.h_st);
+  hipFree(w.K32); hipFree(w.Dinv32); hipFree(w.r32); hipFree(w.z32); hipFree(w.p32[0]);
+  hipFree(w.p32[1]); hipFree(w.Ap32); hipFree(w.x32); hipFree(w.xd);
+  if (w.prof_ev) {
+    for (int i = 0; i < 2 * w.prof_cap; ++i) hipEventDestroy(w.prof_ev[i]);
+    delete[] w.prof_ev;
+  }
+  w = PcgWork();
+}
+
+static constexpr int PROF_CAP = 4096;
+
+hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                     hipStream_t s, int* iters, int* status, int profile_every) {
+  const int rpb = w.rows_per_block, tpb = tpb_for(rpb), nwg = w.n_wg, n = m.n_nodes;
+  hipLaunchKernelGGL(k_pcg_init, dim3(nwg), dim3(tpb), 0, s, n, rpb, b, x, w.r, w.z, w.p[0],
+                     Dinv, rtol, max_it, w.partials, w.st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (profile_every > 0 && !w.prof_ev) {
+    w.prof_ev = new hipEvent_t[2 * PROF_CAP];
+    for (int i = 0; i < 2 * PROF_CAP; ++i)
+      if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
+    w.prof_cap = PROF_CAP;
+  }
+  int n_prof = 0;
+  int64_t launched = 0;
+  int chunk = 8;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      const int64_t gk = launched + i;
+      const int k = (int)(gk & 1);
+      const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
+      if (prof) hipEventRecord(w.prof_ev[2 * n_prof], s);
+      hipLaunchKernelGGL(k_spmv_dir, dim3(nwg), dim3(tpb), 0, s, n, rpb, pat.brow_ptr, pat.bcol,
+                         K, w.z, w.p[k], w.p[k ^ 1], w.Ap, w.partials, w.st);
+      if (prof) {
+        hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
+        ++n_prof;
+      }
+      hipLaunchKernelGGL(k_update, dim3(nwg), dim3(tpb), 0, s, n, rpb, x, w.r, w.z, w.p[k ^ 1],
+                         w.Ap, Dinv, w.partials, w.st);
+    }
+    launched += chunk;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (w.h_st->done || launched > (int64_t)max_it + 64) break;
+    chunk = chunk < 64 ? 2 * chunk : 64;
+  }
+  *iters = w.h_st->it;
+  *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
+  // sampled launches with index < iterations did work (later ones returned at entry)
+  w.prof_us = 0.0;
+  w.prof_n = 0;
+  for (int i = 0; i < n_prof; ++i) {
+    if ((int64_t)i * profile_every >= *iters) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) {
+      w.prof_us += 1000.0 * ms;
+      ++w.prof_n;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t pcg_solve_mixed(const Mesh&, const Pattern&, const double*, const double*,
+                           const double*, double*, double, int, int, PcgWork&, hipStream_t, int*,
+                           int*) {
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const double* a, const double* b, int64_t n, double* partials, int n_wg,
+                      unsigned* counter, double* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(n_wg), dim3(256), 0, s, n, a, b, partials, counter, d_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double* K,
+                                const double* x, const double* b, double* r, PcgWork& w,
+                                double* d_out, hipStream_t s) {
+  const int rpb = w.rows_per_block;
+  hipLaunchKernelGGL(k_residual, dim3(w.n_wg), dim3(tpb_for(rpb)), 0, s, m.n_nodes, rpb,
+                     pat.brow_ptr, pat.bcol, K, x, b, r, w.partials, &w.st->counter[3], d_out);
+  return hipGetLastError();
+}
+
+double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed) {
+  const double fb = mixed ? 4.0 : 8.0;
+  return 36.0 * fb * n_blocks + 4.0 * n_blocks + 4.0 * (n_nodes + 1) + 4.0 * fb * 6.0 * n_nodes;
+}
+
+double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) {
+  const double fb = mixed ? 4.0 : 8.0;
+  const double n_dof = 6.0 * (double)n_nodes;
+  // spmv: K values + block columns + row pointers; z, p_old read; p_new, Ap written
+  double spmv = 36.0 * fb * n_blocks + 4.0 * n_blocks + 4.0 * (n_nodes + 1) + 4.0 * fb * n_dof;
+  // update: x, p, Ap, r read, Dinv (6 per DOF); x, r, z written
+  double upd = 4.0 * fb * n_dof + 6.0 * fb * n_dof + 3.0 * fb * n_dof;
+  return spmv + upd;
+}
+
+}  // namespace sso

@@ -1,0 +1,172 @@
+// Internal declarations shared by the translation units of libhipsso.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hipsso.h"
+
+namespace sso {
+
+// Error bits raised by kernels (OR-ed into a device word; read back by the host).
+enum : unsigned {
+  ERR_INDEX = 1u << 0,       // node index out of range
+  ERR_REPEAT = 1u << 1,      // element repeats a node
+  ERR_BEAM = 1u << 2,        // zero-length member or non-positive section property
+  ERR_QUAD = 1u << 3,        // det J <= 0, zero area, bad t/E/nu, kx/ky != 1
+  ERR_DIAG = 1u << 4,        // diagonal 6x6 block not positive definite
+};
+
+// PCG scalar state, one per solve channel, in device memory.
+struct PcgState {
+  double rz;       // r^T z of the current residual
+  double rr;       // r^T r
+  double pAp;
+  double alpha;
+  double beta;
+  double ff;       // ||rhs||^2
+  double tol2;     // rtol^2 ||rhs||^2
+  int it;          // iterations done
+  int done;        // 1: stop (converged, breakdown, or limit)
+  int status;      // SSO_OK, SSO_ENOTCONV, SSO_EBREAKDOWN
+  int max_it;
+  unsigned counter[4];   // arrival counters of the last-block reductions
+};
+
+// Block-level pattern (6x6 blocks, one block row per node).
+struct Pattern {
+  int64_t n_bcoo = 0;       // block contributions: 4 per beam, 16 per quad
+  int64_t n_blocks = 0;     // 6x6 blocks of K
+  int32_t* brow_ptr = nullptr;  // [n_nodes + 1]
+  int32_t* bcol = nullptr;      // [n_blocks]
+  int32_t* bseg = nullptr;      // [n_blocks + 1] segment of each block slot in bperm
+  int32_t* bperm = nullptr;     // [n_bcoo] block contribution ids sorted by (row, col, id)
+  int32_t* bslot = nullptr;     // [n_bcoo] slot of each sorted position
+  int32_t* bdiag = nullptr;     // [n_nodes] slot of the diagonal block of each row
+  int32_t* bsrow = nullptr;     // [n_blocks] block row of each slot
+  int32_t* estart = nullptr;    // [n_nodes + 1] first sorted position of each block row
+};
+
+struct Mesh {
+  int32_t n_nodes = 0, n_beams = 0, n_quads = 0;
+  double* xyz = nullptr;
+  uint8_t* fixed = nullptr;
+  double* f_nodal = nullptr;
+  int32_t* beam_nodes = nullptr;
+  double* beam_prop = nullptr;
+  int32_t* quad_nodes = nullptr;
+  double* quad_prop = nullptr;
+  double* quad_scale = nullptr;   // always allocated when n_quads > 0 (1 when not given)
+  double unit_weight = 0, surface_load = 0;
+};
+
+// Block contribution id j decoding: beams j = 4 e + 2 la + lb; quads j = 4 nb + 16 e + 4 la + lb.
+struct BlockRef {
+  int quad;   // 0 beam, 1 quad
+  int e, la, lb;
+};
+
+__host__ __device__ inline BlockRef decode_block(int64_t j, int n_beams) {
+  BlockRef r;
+  int64_t nb4 = 4 * (int64_t)n_beams;
+  if (j < nb4) {
+    r.quad = 0;
+    r.e = (int)(j >> 2);
+    r.la = (int)((j >> 1) & 1);
+    r.lb = (int)(j & 1);
+  } else {
+    int64_t q = j - nb4;
+    r.quad = 1;
+    r.e = (int)(q >> 4);
+    r.la = (int)((q >> 2) & 3);
+    r.lb = (int)(q & 3);
+  }
+  return r;
+}
+
+// Scalar index (into the element contribution list) of entry (ca, cb) of block contribution r.
+__host__ __device__ inline int64_t coo_index(const BlockRef& r, int ca, int cb, int n_beams) {
+  if (!r.quad) return 144 * (int64_t)r.e + 12 * (6 * r.la + ca) + 6 * r.lb + cb;
+  return 144 * (int64_t)n_beams + 576 * (int64_t)r.e + 24 * (6 * r.la + ca) + 6 * r.lb + cb;
+}
+
+// ---- launch helpers (each defined in its own translation unit) ----------------------------
+
+// pattern.hip
+hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream_t s,
+                         unsigned* h_err);
+hipError_t build_scalar_view(const Mesh& m, const Pattern& pat, int32_t* row_ptr, int32_t* col,
+                             int32_t* perm, int32_t* seg, hipStream_t s);
+void free_pattern(Pattern& pat);
+
+// elements.hip
+hipError_t launch_element_stiffness(const Mesh& m, double* coo, double* qarea, unsigned* d_err,
+                                    hipStream_t s);
+hipError_t launch_adjoint_terms(const Mesh& m, const Pattern& pat, const double* u,
+                                const double* lam, double c_lam, double c_u, double* gbeam,
+                                double* gquad, hipStream_t s);
+hipError_t launch_gather(const Mesh& m, const Pattern& pat, const double* gbeam,
+                         const double* gquad, double* dg_dxyz, double* dg_dt, double* dg_dscale,
+                         hipStream_t s);
+
+// assemble.hip
+hipError_t launch_assemble(const Mesh& m, const Pattern& pat, const double* coo, double* K,
+                           hipStream_t s);
+hipError_t launch_loads(const Mesh& m, const Pattern& pat, const double* qarea, double* f,
+                        hipStream_t s);
+hipError_t launch_block_jacobi(const Mesh& m, const Pattern& pat, const double* K, double* Dinv,
+                               float* Dinv32, unsigned* d_err, hipStream_t s);
+hipError_t launch_mask_vector(const Mesh& m, const double* in, double* out, hipStream_t s);
+hipError_t launch_scalar_values(const Mesh& m, const Pattern& pat, const double* K,
+                                double* vals, hipStream_t s);
+
+// pcg.hip
+struct PcgWork {
+  int64_t n_dof = 0;
+  int rows_per_block = 0;  // block rows (nodes) per workgroup of the vector kernels
+  int n_wg = 0;            // workgroups of the row kernels
+  double* r = nullptr;
+  double* z = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  double* Ap = nullptr;
+  double* partials = nullptr;   // [4 * n_wg]
+  PcgState* st = nullptr;
+  PcgState* h_st = nullptr;     // pinned host mirror
+  // mixed precision
+  float* K32 = nullptr;
+  float* Dinv32 = nullptr;
+  float* r32 = nullptr;
+  float* z32 = nullptr;
+  float* p32[2] = {nullptr, nullptr};
+  float* Ap32 = nullptr;
+  float* x32 = nullptr;
+  double* xd = nullptr;          // FP64 correction accumulator for refinement
+  // sampled SpMV timing (HIP event pairs, created on first use)
+  hipEvent_t* prof_ev = nullptr;
+  int prof_cap = 0;
+  double prof_us = 0.0;          // summed duration of the sampled launches of the last solve
+  int prof_n = 0;
+};
+
+hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed);
+void pcg_free(PcgWork& w);
+// Solve K x = b (b already masked); x overwritten.  Returns SSO status via *status.
+// profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
+hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                     hipStream_t s, int* iters, int* status, int profile_every = 0);
+hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                           const double* b, double* x, double rtol, int max_it, int refine_steps,
+                           PcgWork& w, hipStream_t s, int* iters, int* status);
+hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
+// Deterministic dot product; result written to *d_out (device).
+hipError_t launch_dot(const double* a, const double* b, int64_t n, double* partials, int n_wg,
+                      unsigned* counter, double* d_out, hipStream_t s);
+// r = b - K x (FP64), and rr = ||r||^2, bb = ||b||^2 into d_out[0], d_out[1].
+hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double* K,
+                                const double* x, const double* b, double* r, PcgWork& w,
+                                double* d_out, hipStream_t s);
+double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed);
+double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed);
+
+}  // namespace sso

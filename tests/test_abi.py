@@ -1,0 +1,58 @@
+"""The C-ABI library builds for gfx950, loads without a GPU and exports every entry point that
+include/hipsso.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hipsso.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sso_[a-z_]+)\s*\(", text)))
+
+
+def _lib_path():
+    from paper_2407_20026_amd import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        from paper_2407_20026_amd import build
+        build.build()
+    return LIB_PATH
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("sso_problem_create", "sso_problem_update", "sso_solve", "sso_objective",
+              "sso_adjoint", "sso_pattern", "sso_strerror", "sso_problem_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_binding_names_match_header():
+    import paper_2407_20026_amd as sso
+    assert sorted(sso.EXPORTS) == _declared()
+    lib = sso.load_library()
+    assert lib.sso_strerror(-5).decode().startswith("PCG breakdown")
+    assert lib.sso_strerror(0).decode() == "ok"
+
+
+def test_create_rejects_bad_arguments_without_touching_the_gpu():
+    """Argument checks that happen before any device call."""
+    import paper_2407_20026_amd as sso
+    lib = sso.load_library()
+    h = ctypes.c_void_p()
+    m = sso.sso_mesh()
+    m.n_nodes = 0
+    assert lib.sso_problem_create(ctypes.byref(m), None, None, ctypes.byref(h)) == sso.SSO_EINVAL
+    m.n_nodes = 4
+    m.n_beams = -1
+    assert lib.sso_problem_create(ctypes.byref(m), None, None, ctypes.byref(h)) == sso.SSO_EINVAL
+    assert lib.sso_solve(None, None, None) == sso.SSO_EINVAL
+    assert lib.sso_adjoint(None, 0, None, None, None, None, None) == sso.SSO_EINVAL
