@@ -82,13 +82,17 @@ typedef struct {
 } sso_mesh;
 
 typedef struct {
-  int32_t precision;          /* SSO_PREC_FP64 or SSO_PREC_MIXED                             */
+  int32_t precision;          /* SSO_PREC_FP64, or SSO_PREC_MIXED: FP32 K, vectors, SpMV and
+                                 dot accumulation inside FP64 iterative refinement (element
+                                 stiffness, residual and the update u += d stay FP64)        */
   double rtol;                /* stop when ||f - K u||_2 <= rtol ||f||_2 (recursive residual;
                                  the reported residual is recomputed)                       */
   int32_t max_it;             /* PCG iteration limit per solve                               */
   int32_t refine_steps;       /* mixed precision: maximum FP64 refinement steps              */
   int32_t profile_every;      /* 0 = off; n > 0: time every n-th SpMV launch of the PCG with
                                  HIP events on the problem's stream (stats.spmv_us)          */
+  double inner_rtol;          /* mixed precision: relative tolerance of each FP32 inner PCG
+                                 solve (0 = 1e-5)                                           */
 } sso_options;
 
 typedef struct {
@@ -102,6 +106,7 @@ typedef struct {
   double spmv_us;             /* mean duration of the sampled SpMV launches (profile_every)  */
   int32_t spmv_samples;       /* number of sampled SpMV launches                             */
   double spmv_bytes;          /* algorithmic bytes of one SpMV launch                        */
+  int32_t refine_steps;       /* mixed precision: FP32 inner solves run                      */
 } sso_stats;
 
 typedef struct sso_problem sso_problem;

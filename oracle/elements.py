@@ -107,7 +107,7 @@ def beam_K(X, prop, scale=None):
     E, G, A, Iy, Iz, J = (prop[:, c] for c in range(6))
     k = beam_local_k(E, G, A, Iy, Iz, J, L)
     T = _block_rotation(R, 2)
-    K = np.einsum("nba,nbc,ncd->nad", T, k, T)
+    K = np.swapaxes(T, 1, 2) @ k @ T
     if scale is not None:
         K = K * scale[:, None, None]
     return K
@@ -221,11 +221,11 @@ def shell_local_parts(x, y, t, E, nu):
             bd[:, u] = 0.5 * dNdy[:, i]
         g_xi = 0.5 * (1 + eta) * gA + 0.5 * (1 - eta) * gC
         g_eta = 0.5 * (1 + xi) * gD + 0.5 * (1 - xi) * gB
-        Bs = np.einsum("nij,njk->nik", Jinv, np.stack([g_xi, g_eta], axis=1))
+        Bs = Jinv @ np.stack([g_xi, g_eta], axis=1)
         w = det[:, None, None]
-        Km += w * np.einsum("nsa,nst,ntb->nab", Bm, Dm, Bm)
-        Kb += w * np.einsum("nsa,nst,ntb->nab", Bb, Db, Bb)
-        Ks += (w * ks[:, None, None]) * np.einsum("nsa,nsb->nab", Bs, Bs)
+        Km += w * (np.swapaxes(Bm, 1, 2) @ Dm @ Bm)
+        Kb += w * (np.swapaxes(Bb, 1, 2) @ Db @ Bb)
+        Ks += (w * ks[:, None, None]) * (np.swapaxes(Bs, 1, 2) @ Bs)
         Kd += (w * kd[:, None, None]) * bd[:, :, None] * bd[:, None, :]
     return Km, Kb, Ks, Kd
 
@@ -257,10 +257,10 @@ def shell_K_parts(X, prop, scale=None):
     parts = shell_local_parts(x, y, t, E, nu)
     W = warp_matrix(h)
     T = _block_rotation(R, 4)
-    WT = np.einsum("nab,nbc->nac", W, T)
+    WT = W @ T
     out = []
     for k in parts:
-        K = np.einsum("nba,nbc,ncd->nad", WT, k, WT)
+        K = np.swapaxes(WT, 1, 2) @ k @ WT
         if scale is not None:
             K = K * scale[:, None, None]
         out.append(K)

@@ -41,7 +41,7 @@ class sso_mesh(ctypes.Structure):
 class sso_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("profile_every", ctypes.c_int32)]
+                ("profile_every", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
 
 
 class sso_stats(ctypes.Structure):
@@ -49,7 +49,8 @@ class sso_stats(ctypes.Structure):
                 ("t_elem_us", ctypes.c_double), ("t_asm_us", ctypes.c_double),
                 ("t_solve_us", ctypes.c_double), ("t_adj_us", ctypes.c_double),
                 ("bytes_moved", ctypes.c_double), ("spmv_us", ctypes.c_double),
-                ("spmv_samples", ctypes.c_int32), ("spmv_bytes", ctypes.c_double)]
+                ("spmv_samples", ctypes.c_int32), ("spmv_bytes", ctypes.c_double),
+                ("refine_steps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -139,10 +140,11 @@ class Options:
     max_it: int = 200000
     refine_steps: int = 20
     profile_every: int = 0
+    inner_rtol: float = 0.0
 
     def c(self) -> sso_options:
         return sso_options(self.precision, self.rtol, self.max_it, self.refine_steps,
-                           self.profile_every)
+                           self.profile_every, self.inner_rtol)
 
 
 class Problem:

@@ -17,6 +17,8 @@ struct sso_problem {
   double* qarea = nullptr;
   double* K = nullptr;
   double* Dinv = nullptr;
+  float* K32 = nullptr;         // mixed precision copies (allocated on first mixed solve)
+  float* Dinv32 = nullptr;
   double* f = nullptr;
   double* u = nullptr;
   double* lam = nullptr;
@@ -45,12 +47,14 @@ sso_options default_options() {
   o.max_it = 200000;
   o.refine_steps = 20;
   o.profile_every = 0;
+  o.inner_rtol = 0.0;
   return o;
 }
 
 bool options_ok(const sso_options& o) {
   return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED) && o.rtol >= 0.0 &&
-         o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0;
+         o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0 && o.inner_rtol >= 0.0 &&
+         o.inner_rtol < 1.0;
 }
 
 __global__ void k_fill(int64_t n, double v, double* out) {
@@ -90,6 +94,7 @@ void free_problem(sso_problem* p) {
   hipFree(m.beam_prop); hipFree(m.quad_nodes); hipFree(m.quad_prop); hipFree(m.quad_scale);
   free_pattern(p->pat);
   hipFree(p->coo); hipFree(p->qarea); hipFree(p->K); hipFree(p->Dinv); hipFree(p->f);
+  hipFree(p->K32); hipFree(p->Dinv32);
   hipFree(p->u); hipFree(p->lam); hipFree(p->rhs); hipFree(p->gbeam); hipFree(p->gquad);
   hipFree(p->d_scal); hipFree(p->d_err);
   if (p->h_scal) hipHostFree(p->h_scal);
@@ -225,24 +230,63 @@ int sso_set_options(sso_problem* p, const sso_options* opts) {
   return SSO_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+bool mixed(const sso_problem* p) { return p->opt.precision == SSO_PREC_MIXED; }
+
+// Solve K x = b (b masked) in the problem's precision mode.
+int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* outer) {
+  int status = SSO_OK;
+  *outer = 0;
+  if (!mixed(p)) {
+    TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, b, x, p->opt.rtol, p->opt.max_it, p->w, p->s,
+                      iters, &status, p->opt.profile_every));
+  } else {
+    const double inner = p->opt.inner_rtol > 0.0 ? p->opt.inner_rtol : 1e-5;
+    TRY_HIP(pcg_solve_mixed(p->m, p->pat, p->K, p->K32, p->Dinv32, b, x, p->opt.rtol, inner,
+                            p->opt.max_it, p->opt.refine_steps, p->w, p->s, iters, &status,
+                            outer, p->opt.profile_every));
+  }
+  return status;
+}
+
+double solve_bytes(const sso_problem* p, int iters, int outer) {
+  const int64_t nn = p->m.n_nodes, nb = p->pat.n_blocks;
+  if (!mixed(p)) return iters * pcg_bytes_per_iteration(nn, nb, false);
+  // inner FP32 iterations + one FP64 residual SpMV (K, x, b read; r written) per outer step
+  double resid = 292.0 * nb + 4.0 * (nn + 1) + 3.0 * 8.0 * 6.0 * nn;
+  return iters * pcg_bytes_per_iteration(nn, nb, true) + (outer + 1) * resid;
+}
+
+}  // namespace
+
+extern "C" {
+
 int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   if (!p) return SSO_EINVAL;
-  if (p->opt.precision != SSO_PREC_FP64) return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
+  if (mixed(p) && !p->K32) {
+    TRY_HIP(dalloc(&p->K32, 36 * p->pat.n_blocks));
+    TRY_HIP(dalloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes));
+  }
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(hipEventRecord(p->ev[0], s));
   TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
   TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
   TRY_HIP(hipEventRecord(p->ev[1], s));
   TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
-  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, nullptr, p->d_err, s));
+  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, mixed(p) ? p->Dinv32 : nullptr,
+                              p->d_err, s));
+  if (mixed(p)) TRY_HIP(launch_convert_f32(p->K, p->K32, 36 * p->pat.n_blocks, s));
   TRY_HIP(hipEventRecord(p->ev[2], s));
   int st = read_errors(p);
   if (st != SSO_OK) return st;
-  int iters = 0, status = SSO_OK;
-  TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it, p->w,
-                    s, &iters, &status, p->opt.profile_every));
+  int iters = 0, outer = 0;
+  int status = run_solver(p, p->f, p->u, &iters, &outer);
+  if (status == SSO_EHIP || status == SSO_ENOMEM) return status;
   TRY_HIP(hipEventRecord(p->ev[3], s));
   TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
   TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -253,15 +297,15 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->iters = iters;
+    stats->refine_steps = outer;
     stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
     stats->t_elem_us = elapsed_us(p->ev[0], p->ev[1]);
     stats->t_asm_us = elapsed_us(p->ev[1], p->ev[2]);
     stats->t_solve_us = elapsed_us(p->ev[2], p->ev[3]);
-    stats->bytes_moved =
-        iters * pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->bytes_moved = solve_bytes(p, iters, outer);
     stats->spmv_samples = p->w.prof_n;
     stats->spmv_us = p->w.prof_n ? p->w.prof_us / p->w.prof_n : 0.0;
-    stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, mixed(p));
   }
   // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available
   p->solved = (status == SSO_OK || status == SSO_ENOTCONV);
@@ -306,9 +350,9 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
     if (!dg_du) return SSO_EINVAL;
     c_u = 0.0;
     TRY_HIP(launch_mask_vector(p->m, dg_du, p->rhs, s));
-    TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, p->rhs, p->lam, p->opt.rtol, p->opt.max_it,
-                      p->w, s, &iters, &status, p->opt.profile_every));
-    if (status != SSO_OK) return status;
+    int outer = 0;
+    status = run_solver(p, p->rhs, p->lam, &iters, &outer);
+    if (status != SSO_OK && status != SSO_ENOTCONV) return status;
     lam = p->lam;
   } else {
     return SSO_EINVAL;
@@ -321,10 +365,9 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
     std::memset(stats, 0, sizeof(*stats));
     stats->iters = iters;
     stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
-    stats->bytes_moved =
-        iters * pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->bytes_moved = solve_bytes(p, iters, 0);
   }
-  return SSO_OK;
+  return status;
 }
 
 int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,

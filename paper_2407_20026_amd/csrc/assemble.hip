@@ -15,9 +15,6 @@ namespace {
 
 inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
-__device__ inline void node_of(const Mesh& m, const BlockRef& r, int& I) {
-  I = r.quad ? m.quad_nodes[4 * (int64_t)r.e + r.la] : m.beam_nodes[2 * (int64_t)r.e + r.la];
-}
 
 // K block values, row-major inside each 6x6 block, blocks in slot order.
 __global__ void k_assemble(Mesh m, int64_t n_blocks, const int32_t* bsrow, const int32_t* bcol,

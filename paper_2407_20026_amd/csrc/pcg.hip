@@ -12,6 +12,8 @@
 // Thread layout of the row kernels: 6 consecutive lanes per node (block row), lane a owning
 // scalar row 6 I + a; it streams the a-th row of every 6x6 block of the block row (48
 // contiguous bytes) so the 6 lanes of a node read each 288-byte block once, in order.
+#include <cmath>
+
 #include "sso_internal.h"
 
 namespace sso {
@@ -33,10 +35,14 @@ __device__ inline void atomic_store_f64(double* p, double v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <class T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 // Fixed-order block sum of NV values; the result is valid in thread 0.
-template <int NV>
-__device__ inline void block_sum(double v[NV]) {
-  __shared__ double lds[NV][MAX_WAVES];
+template <int NV, class A>
+__device__ inline void block_sum(A v[NV]) {
+  __shared__ A lds[NV][MAX_WAVES];
   for (int off = 32; off > 0; off >>= 1)
     for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -46,21 +52,22 @@ __device__ inline void block_sum(double v[NV]) {
   __syncthreads();
   if (threadIdx.x == 0)
     for (int k = 0; k < NV; ++k) {
-      double s = lds[k][0];
+      A s = lds[k][0];
       for (int w = 1; w < nw; ++w) s += lds[k][w];
       v[k] = s;
     }
   __syncthreads();
 }
 
-// Publish this workgroup's partial sums; returns true in every thread of the last workgroup
-// to arrive, whose v[] then holds the totals (valid in thread 0).
-template <int NV>
-__device__ inline bool publish_and_total(double v[NV], double* partials, unsigned* counter) {
+// Publish this workgroup's partial sums (converted to FP64); returns true in every thread of
+// the last workgroup to arrive, whose tot[] then holds the FP64 totals (valid in thread 0).
+template <int NV, class A>
+__device__ inline bool publish_and_total(const A v[NV], double tot[NV], double* partials,
+                                         unsigned* counter) {
   __shared__ int last;
   const int n = gridDim.x;
   if (threadIdx.x == 0) {
-    for (int k = 0; k < NV; ++k) atomic_store_f64(&partials[k * n + blockIdx.x], v[k]);
+    for (int k = 0; k < NV; ++k) atomic_store_f64(&partials[k * n + blockIdx.x], (double)v[k]);
     unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
                                            __HIP_MEMORY_SCOPE_AGENT);
     last = (prev == (unsigned)n - 1u);
@@ -70,9 +77,9 @@ __device__ inline bool publish_and_total(double v[NV], double* partials, unsigne
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += atomic_load_f64(&partials[k * n + i]);
-    v[k] = s;
+    tot[k] = s;
   }
-  block_sum<NV>(v);
+  block_sum<NV, double>(tot);
   if (threadIdx.x == 0)
     __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
@@ -93,87 +100,97 @@ __device__ inline RowMap row_map(int rpb, int n_nodes) {
 }
 
 // z = Dinv r for the node of this lane, r values of the node staged in LDS.
-__device__ inline double apply_dinv(const double* Dinv, const double* rs, const RowMap& m) {
-  const double2* dv = reinterpret_cast<const double2*>(Dinv + 36 * (int64_t)m.I + 6 * m.a);
-  const double* rr = rs + 6 * m.lr;
-  double z = 0.0;
+template <class T>
+__device__ inline T apply_dinv(const T* Dinv, const T* rs, const RowMap& m) {
+  using V = typename Vec2<T>::type;
+  const V* dv = reinterpret_cast<const V*>(Dinv + 36 * (int64_t)m.I + 6 * m.a);
+  const T* rr = rs + 6 * m.lr;
+  T z = 0;
   for (int h = 0; h < 3; ++h) {
-    double2 d = dv[h];
+    V d = dv[h];
     z += d.x * rr[2 * h] + d.y * rr[2 * h + 1];
   }
   return z;
 }
 
+// x = 0, r = b, z = Dinv b, p_0 = 0; state: rz, rr = ||b||^2, tolerance, counters.
+template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_pcg_init(int n_nodes, int rpb, const double* b, double* x, double* r, double* z, double* p0,
-           const double* Dinv, double rtol, int max_it, double* partials, PcgState* st) {
-  __shared__ double rs[MAX_TPB];
+k_pcg_init(int n_nodes, int rpb, const T* b, T* x, T* r, T* z, T* p0, const T* Dinv,
+           double rtol, int max_it, double* partials, PcgState* st) {
+  __shared__ T rs[MAX_TPB];
   RowMap m = row_map(rpb, n_nodes);
   const int64_t d = 6 * (int64_t)m.I + m.a;
-  double rv = 0.0;
+  T rv = 0;
   if (m.valid) {
     rv = b[d];
-    x[d] = 0.0;
+    x[d] = 0;
     r[d] = rv;
-    p0[d] = 0.0;
+    p0[d] = 0;
   }
   rs[threadIdx.x] = rv;
   __syncthreads();
-  double zz = 0.0;
+  T zz = 0;
   if (m.valid) {
     zz = apply_dinv(Dinv, rs, m);
     z[d] = zz;
   }
-  double v[2] = {rv * zz, rv * rv};
-  block_sum<2>(v);
-  if (publish_and_total<2>(v, partials, &st->counter[0]) && threadIdx.x == 0) {
-    st->rz = v[0];
-    st->rr = v[1];
-    st->ff = v[1];
-    st->tol2 = rtol * rtol * v[1];
+  T v[2] = {rv * zz, rv * rv};
+  block_sum<2, T>(v);
+  double tot[2];
+  if (publish_and_total<2, T>(v, tot, partials, &st->counter[0]) && threadIdx.x == 0) {
+    st->rz = tot[0];
+    st->rr = tot[1];
+    st->ff = tot[1];
+    st->tol2 = rtol * rtol * tot[1];
     st->pAp = 0.0;
     st->alpha = 0.0;
     st->beta = 0.0;
     st->it = 0;
     st->max_it = max_it;
     st->status = SSO_OK;
-    st->done = (v[1] == 0.0) ? 1 : 0;
+    st->done = (tot[1] == 0.0) ? 1 : 0;
   }
 }
 
+// p = z + beta p_old (own rows written to p_new, neighbours formed on the fly), Ap = K p,
+// partial p^T A p; the last workgroup sets alpha = r^T z / p^T A p.
+template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
-           const int32_t* __restrict__ bcol, const double* __restrict__ K,
-           const double* __restrict__ z, const double* __restrict__ pold, double* __restrict__ pnew,
-           double* __restrict__ Ap, double* partials, PcgState* st) {
+           const int32_t* __restrict__ bcol, const T* __restrict__ K, const T* __restrict__ z,
+           const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ Ap, double* partials,
+           PcgState* st) {
+  using V = typename Vec2<T>::type;
   if (st->done) return;
-  const double beta = st->beta;
+  const T beta = (T)st->beta;
   RowMap m = row_map(rpb, n_nodes);
-  double my = 0.0;
+  T my = 0;
   if (m.valid) {
     const int rb = brow_ptr[m.I], re = brow_ptr[m.I + 1];
-    double acc = 0.0;
+    T acc = 0;
     for (int s = rb; s < re; ++s) {
       const int64_t J = bcol[s];
-      const double2* kr = reinterpret_cast<const double2*>(K + 36 * (int64_t)s + 6 * m.a);
-      const double2* zj = reinterpret_cast<const double2*>(z + 6 * J);
-      const double2* pj = reinterpret_cast<const double2*>(pold + 6 * J);
+      const V* kr = reinterpret_cast<const V*>(K + 36 * (int64_t)s + 6 * m.a);
+      const V* zj = reinterpret_cast<const V*>(z + 6 * J);
+      const V* pj = reinterpret_cast<const V*>(pold + 6 * J);
 #pragma unroll
       for (int h = 0; h < 3; ++h) {
-        const double2 kv = kr[h], zv = zj[h], pv = pj[h];
+        const V kv = kr[h], zv = zj[h], pv = pj[h];
         acc += kv.x * (zv.x + beta * pv.x) + kv.y * (zv.y + beta * pv.y);
       }
     }
     const int64_t d = 6 * (int64_t)m.I + m.a;
-    const double pn = z[d] + beta * pold[d];
+    const T pn = z[d] + beta * pold[d];
     pnew[d] = pn;
     Ap[d] = acc;
     my = pn * acc;
   }
-  double v[1] = {my};
-  block_sum<1>(v);
-  if (publish_and_total<1>(v, partials, &st->counter[1]) && threadIdx.x == 0) {
-    const double pAp = v[0];
+  T v[1] = {my};
+  block_sum<1, T>(v);
+  double tot[1];
+  if (publish_and_total<1, T>(v, tot, partials, &st->counter[1]) && threadIdx.x == 0) {
+    const double pAp = tot[0];
     const double alpha = st->rz / pAp;
     st->pAp = pAp;
     st->alpha = alpha;
@@ -184,16 +201,19 @@ k_spmv_dir(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
   }
 }
 
+// x += alpha p, r -= alpha Ap, z = Dinv r, partials r^T z and r^T r; the last workgroup sets
+// beta and the convergence flags.
+template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_update(int n_nodes, int rpb, double* __restrict__ x, double* __restrict__ r,
-         double* __restrict__ z, const double* __restrict__ p, const double* __restrict__ Ap,
-         const double* __restrict__ Dinv, double* partials, PcgState* st) {
-  __shared__ double rs[MAX_TPB];
+k_update(int n_nodes, int rpb, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+         const T* __restrict__ p, const T* __restrict__ Ap, const T* __restrict__ Dinv,
+         double* partials, PcgState* st) {
+  __shared__ T rs[MAX_TPB];
   if (st->done) return;
-  const double alpha = st->alpha;
+  const T alpha = (T)st->alpha;
   RowMap m = row_map(rpb, n_nodes);
   const int64_t d = 6 * (int64_t)m.I + m.a;
-  double rn = 0.0;
+  T rn = 0;
   if (m.valid) {
     x[d] += alpha * p[d];
     rn = r[d] - alpha * Ap[d];
@@ -201,15 +221,16 @@ k_update(int n_nodes, int rpb, double* __restrict__ x, double* __restrict__ r,
   }
   rs[threadIdx.x] = rn;
   __syncthreads();
-  double zz = 0.0;
+  T zz = 0;
   if (m.valid) {
     zz = apply_dinv(Dinv, rs, m);
     z[d] = zz;
   }
-  double v[2] = {rn * zz, rn * rn};
-  block_sum<2>(v);
-  if (publish_and_total<2>(v, partials, &st->counter[2]) && threadIdx.x == 0) {
-    const double rz = v[0], rr = v[1];
+  T v[2] = {rn * zz, rn * rn};
+  block_sum<2, T>(v);
+  double tot[2];
+  if (publish_and_total<2, T>(v, tot, partials, &st->counter[2]) && threadIdx.x == 0) {
+    const double rz = tot[0], rr = tot[1];
     st->beta = rz / st->rz;
     st->rz = rz;
     st->rr = rr;
@@ -250,10 +271,11 @@ k_residual(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
     bb = b[d] * b[d];
   }
   double v[2] = {rr, bb};
-  block_sum<2>(v);
-  if (publish_and_total<2>(v, partials, counter) && threadIdx.x == 0) {
-    out[0] = v[0];
-    out[1] = v[1];
+  block_sum<2, double>(v);
+  double tot[2];
+  if (publish_and_total<2, double>(v, tot, partials, counter) && threadIdx.x == 0) {
+    out[0] = tot[0];
+    out[1] = tot[1];
   }
 }
 
@@ -265,13 +287,26 @@ k_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b, dou
        i += (int64_t)gridDim.x * blockDim.x)
     s += a[i] * b[i];
   double v[1] = {s};
-  block_sum<1>(v);
-  if (publish_and_total<1>(v, partials, counter) && threadIdx.x == 0) out[0] = v[0];
+  block_sum<1, double>(v);
+  double tot[1];
+  if (publish_and_total<1, double>(v, tot, partials, counter) && threadIdx.x == 0) out[0] = tot[0];
 }
 
 __global__ void k_convert_f32(int64_t n, const double* in, float* out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
+}
+
+// out = (float)(in * scale): the FP64 residual, normalised, as the FP32 inner right-hand side.
+__global__ void k_scale_to_f32(int64_t n, const double* in, double scale, float* out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)(in[i] * scale);
+}
+
+// x += alpha * (double)d: the FP64 refinement update with the FP32 inner correction.
+__global__ void k_refine_update(int64_t n, double alpha, const float* d, double* x) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += alpha * (double)d[i];
 }
 
 }  // namespace
@@ -301,7 +336,21 @@ hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed) {
   if ((e = hipMemset(w.st, 0, sizeof(PcgState))) != hipSuccess) return e;
   if ((e = hipHostMalloc(&w.h_st, sizeof(PcgState), hipHostMallocDefault)) != hipSuccess)
     return e;
-  (void)mixed;
+  if (mixed) return pcg_alloc_mixed(w);
+  return hipSuccess;
+}
+
+hipError_t pcg_alloc_mixed(PcgWork& w) {
+  if (w.r32) return hipSuccess;
+  const size_t fb = sizeof(float) * (size_t)w.n_dof;
+  hipError_t e;
+  if ((e = hipMalloc(&w.r32, fb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.z32, fb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.p32[0], fb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.p32[1], fb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.Ap32, fb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.x32, fb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.b32, fb)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -309,8 +358,8 @@ void pcg_free(PcgWork& w) {
   hipFree(w.r); hipFree(w.z); hipFree(w.p[0]); hipFree(w.p[1]); hipFree(w.Ap);
   hipFree(w.partials); hipFree(w.st);
   if (w.h_st) hipHostFree(w.h_st);
-  hipFree(w.K32); hipFree(w.Dinv32); hipFree(w.r32); hipFree(w.z32); hipFree(w.p32[0]);
-  hipFree(w.p32[1]); hipFree(w.Ap32); hipFree(w.x32); hipFree(w.xd);
+  hipFree(w.r32); hipFree(w.z32); hipFree(w.p32[0]);
+  hipFree(w.p32[1]); hipFree(w.Ap32); hipFree(w.x32); hipFree(w.b32);
   if (w.prof_ev) {
     for (int i = 0; i < 2 * w.prof_cap; ++i) hipEventDestroy(w.prof_ev[i]);
     delete[] w.prof_ev;
@@ -320,12 +369,16 @@ void pcg_free(PcgWork& w) {
 
 static constexpr int PROF_CAP = 4096;
 
-hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
-                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
-                     hipStream_t s, int* iters, int* status, int profile_every) {
+// One PCG solve in precision T on (K, Dinv, b) -> x, polling the state every chunk.  Sampled
+// SpMV launches are bracketed with events and their durations added to w.prof_us / w.prof_n.
+template <class T>
+static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T* Dinv,
+                          const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
+                          int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
+                          int profile_every) {
   const int rpb = w.rows_per_block, tpb = tpb_for(rpb), nwg = w.n_wg, n = m.n_nodes;
-  hipLaunchKernelGGL(k_pcg_init, dim3(nwg), dim3(tpb), 0, s, n, rpb, b, x, w.r, w.z, w.p[0],
-                     Dinv, rtol, max_it, w.partials, w.st);
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, b, x, r, z, p[0], Dinv,
+                     rtol, max_it, w.partials, w.st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (profile_every > 0 && !w.prof_ev) {
@@ -342,15 +395,15 @@ hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const d
       const int64_t gk = launched + i;
       const int k = (int)(gk & 1);
       const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
-      if (prof) hipEventRecord(w.prof_ev[2 * n_prof], s);
-      hipLaunchKernelGGL(k_spmv_dir, dim3(nwg), dim3(tpb), 0, s, n, rpb, pat.brow_ptr, pat.bcol,
-                         K, w.z, w.p[k], w.p[k ^ 1], w.Ap, w.partials, w.st);
+      if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
+      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, pat.brow_ptr,
+                         pat.bcol, K, z, p[k], p[k ^ 1], Ap, w.partials, w.st);
       if (prof) {
-        hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
+        (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
         ++n_prof;
       }
-      hipLaunchKernelGGL(k_update, dim3(nwg), dim3(tpb), 0, s, n, rpb, x, w.r, w.z, w.p[k ^ 1],
-                         w.Ap, Dinv, w.partials, w.st);
+      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, x, r, z, p[k ^ 1], Ap,
+                         Dinv, w.partials, w.st);
     }
     launched += chunk;
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -364,8 +417,6 @@ hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const d
   *iters = w.h_st->it;
   *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
   // sampled launches with index < iterations did work (later ones returned at entry)
-  w.prof_us = 0.0;
-  w.prof_n = 0;
   for (int i = 0; i < n_prof; ++i) {
     if ((int64_t)i * profile_every >= *iters) break;
     float ms = 0.f;
@@ -377,10 +428,76 @@ hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const d
   return hipSuccess;
 }
 
-hipError_t pcg_solve_mixed(const Mesh&, const Pattern&, const double*, const double*,
-                           const double*, double*, double, int, int, PcgWork&, hipStream_t, int*,
-                           int*) {
-  return hipErrorNotSupported;
+hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                     hipStream_t s, int* iters, int* status, int profile_every) {
+  w.prof_us = 0.0;
+  w.prof_n = 0;
+  return pcg_run<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w, s, iters,
+                         status, profile_every);
+}
+
+// FP32 inner PCG (FP32 K, vectors, SpMV and dot accumulation) inside FP64 iterative
+// refinement: r = b - K x recomputed in FP64 with the FP64 K, the inner solve runs on r / |r|,
+// and x += |r| d in FP64, until |r| <= rtol |b| or refinement stalls.
+hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                           const float* Dinv32, const double* b, double* x, double rtol,
+                           double inner_rtol, int max_it, int refine_steps, PcgWork& w,
+                           hipStream_t s, int* iters, int* status, int* outer,
+                           int profile_every) {
+  hipError_t e;
+  if ((e = pcg_alloc_mixed(w)) != hipSuccess) return e;
+  const int64_t n = w.n_dof;
+  w.prof_us = 0.0;
+  w.prof_n = 0;
+  if ((e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s)) != hipSuccess) return e;
+  double* scal = w.partials + 3 * (size_t)(w.n_wg > 1024 ? w.n_wg : 1024);
+  *iters = 0;
+  *status = SSO_ENOTCONV;
+  *outer = 0;
+  double prev = -1.0;
+  for (int step = 0; step <= refine_steps; ++step) {
+    if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, scal, s)) != hipSuccess) return e;
+    double h[2];
+    if ((e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const double rn = sqrt(h[0]), bn = sqrt(h[1]);
+    if (!std::isfinite(rn)) {
+      *status = SSO_EBREAKDOWN;
+      return hipSuccess;
+    }
+    if (rn <= rtol * bn) {
+      *status = SSO_OK;
+      return hipSuccess;
+    }
+    if (step == refine_steps || (prev >= 0.0 && rn > 0.5 * prev)) {
+      *status = SSO_ENOTCONV;   // limit reached or refinement stalled
+      return hipSuccess;
+    }
+    prev = rn;
+    hipLaunchKernelGGL(k_scale_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, w.r, 1.0 / rn,
+                       w.b32);
+    int it = 0, st = SSO_OK;
+    const int left = max_it - *iters;
+    if (left <= 0) {
+      *status = SSO_ENOTCONV;
+      return hipSuccess;
+    }
+    if ((e = pcg_run<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32,
+                            inner_rtol, left, w, s, &it, &st, profile_every)) != hipSuccess)
+      return e;
+    *iters += it;
+    ++*outer;
+    if (st == SSO_EBREAKDOWN && it == 0) {
+      *status = SSO_EBREAKDOWN;
+      return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_refine_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, rn, w.x32, x);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s) {

@@ -132,15 +132,13 @@ struct PcgWork {
   double* partials = nullptr;   // [4 * n_wg]
   PcgState* st = nullptr;
   PcgState* h_st = nullptr;     // pinned host mirror
-  // mixed precision
-  float* K32 = nullptr;
-  float* Dinv32 = nullptr;
+  // mixed precision: FP32 inner PCG vectors (allocated on first use)
   float* r32 = nullptr;
   float* z32 = nullptr;
   float* p32[2] = {nullptr, nullptr};
   float* Ap32 = nullptr;
   float* x32 = nullptr;
-  double* xd = nullptr;          // FP64 correction accumulator for refinement
+  float* b32 = nullptr;
   // sampled SpMV timing (HIP event pairs, created on first use)
   hipEvent_t* prof_ev = nullptr;
   int prof_cap = 0;
@@ -149,15 +147,19 @@ struct PcgWork {
 };
 
 hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed);
+hipError_t pcg_alloc_mixed(PcgWork& w);
 void pcg_free(PcgWork& w);
 // Solve K x = b (b already masked); x overwritten.  Returns SSO status via *status.
 // profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
                      hipStream_t s, int* iters, int* status, int profile_every = 0);
-hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
-                           const double* b, double* x, double rtol, int max_it, int refine_steps,
-                           PcgWork& w, hipStream_t s, int* iters, int* status);
+// FP32 inner PCG inside FP64 iterative refinement (residual recomputed with the FP64 K).
+hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                           const float* Dinv32, const double* b, double* x, double rtol,
+                           double inner_rtol, int max_it, int refine_steps, PcgWork& w,
+                           hipStream_t s, int* iters, int* status, int* outer,
+                           int profile_every);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // Deterministic dot product; result written to *d_out (device).
 hipError_t launch_dot(const double* a, const double* b, int64_t n, double* partials, int n_wg,
