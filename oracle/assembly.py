@@ -154,3 +154,78 @@ def masked_system(mesh, K, f):
     Km = sp.csr_matrix((data, cols.copy(), K.indptr.copy()), shape=K.shape)
     fm = np.where(fixed, 0.0, f)
     return Km, fm
+
+
+# ---- local evaluations (one block row at a time) for spot checks at sizes where the global
+# ---- pattern above would be too slow to build ---------------------------------------------
+
+def incident(mesh, node):
+    """Elements containing node, in element-list order: list of (kind, e, local index)."""
+    out = []
+    for kind, conn in (("beam", mesh.beam_nodes), ("quad", mesh.quad_nodes)):
+        es, ls = np.nonzero(conn == node)
+        for e, la in sorted(zip(es.tolist(), ls.tolist())):
+            out.append((kind, e, la))
+    return out
+
+
+def block_row(mesh, I):
+    """Sorted block columns of block row I (the diagonal block is always present)."""
+    cols = {int(I)}
+    for kind, e, _ in incident(mesh, I):
+        conn = mesh.beam_nodes if kind == "beam" else mesh.quad_nodes
+        cols.update(int(J) for J in conn[e])
+    return sorted(cols)
+
+
+def coo_index(mesh, kind, e, a, b):
+    """Index of local entry (a, b) of element e in the element-major, row-major COO list."""
+    if kind == "beam":
+        return 144 * e + 12 * a + b
+    return 144 * mesh.n_beams + 576 * e + 24 * a + b
+
+
+def slot_contributions(mesh, row, col):
+    """Ascending COO indices of the contributions to entry (row, col) of K."""
+    I, ca = divmod(int(row), 6)
+    J, cb = divmod(int(col), 6)
+    ks = []
+    for kind, e, la in incident(mesh, I):
+        conn = mesh.beam_nodes if kind == "beam" else mesh.quad_nodes
+        for lb, node in enumerate(conn[e]):
+            if node == J:
+                ks.append(coo_index(mesh, kind, e, 6 * la + ca, 6 * lb + cb))
+    return sorted(ks)
+
+
+def K_block_row(mesh, I):
+    """Unconstrained block row I of K: dict J -> 6x6 block, summed in COO order."""
+    out = {J: np.zeros((6, 6)) for J in block_row(mesh, I)}
+    for kind, e, la in incident(mesh, I):
+        if kind == "beam":
+            Ke = elements.beam_K(mesh.xyz[mesh.beam_nodes[e:e + 1]], mesh.beam_prop[e:e + 1])[0]
+            conn = mesh.beam_nodes[e]
+        else:
+            sc = None if mesh.quad_scale is None else mesh.quad_scale[e:e + 1]
+            Ke = elements.shell_K(mesh.xyz[mesh.quad_nodes[e:e + 1]], mesh.quad_prop[e:e + 1],
+                                  sc)[0]
+            conn = mesh.quad_nodes[e]
+        for lb, J in enumerate(conn):
+            out[int(J)] += Ke[6 * la:6 * la + 6, 6 * lb:6 * lb + 6]
+    return out
+
+
+def apply_K_elementwise(mesh, u, chunk=10000):
+    """K u (unconstrained) as the sum of element products, without forming the global K."""
+    y = np.zeros(mesh.n_dof)
+    bd, qd = element_dofs(mesh)
+    for lo in range(0, mesh.n_beams, chunk):
+        hi = min(mesh.n_beams, lo + chunk)
+        Ke = elements.beam_K(mesh.xyz[mesh.beam_nodes[lo:hi]], mesh.beam_prop[lo:hi])
+        np.add.at(y, bd[lo:hi].ravel(), (Ke @ u[bd[lo:hi]][:, :, None])[:, :, 0].ravel())
+    for lo in range(0, mesh.n_quads, chunk):
+        hi = min(mesh.n_quads, lo + chunk)
+        sc = None if mesh.quad_scale is None else mesh.quad_scale[lo:hi]
+        Ke = elements.shell_K(mesh.xyz[mesh.quad_nodes[lo:hi]], mesh.quad_prop[lo:hi], sc)
+        np.add.at(y, qd[lo:hi].ravel(), (Ke @ u[qd[lo:hi]][:, :, None])[:, :, 0].ravel())
+    return y

@@ -327,9 +327,7 @@ int sso_objective(sso_problem* p, int kind, const double* a, double* g_host) {
     return SSO_EINVAL;
   }
   const int64_t n = 6 * (int64_t)p->m.n_nodes;
-  int nwg = (int)((n + 255) / 256);
-  if (nwg > 1024) nwg = 1024;
-  TRY_HIP(launch_dot(lhs, p->u, n, p->w.partials, nwg, &p->w.st->counter[3], p->d_scal, p->s));
+  TRY_HIP(launch_dot(lhs, p->u, n, p->w, p->d_scal, p->s));
   TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, sizeof(double), hipMemcpyDeviceToHost, p->s));
   TRY_HIP(hipStreamSynchronize(p->s));
   *g_host = scale * p->h_scal[0];

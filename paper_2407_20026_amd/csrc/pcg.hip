@@ -1,13 +1,18 @@
 // Block-Jacobi preconditioned conjugate gradients on the masked K (BSR, 6x6 blocks).
 //
 // The paper solves K u = f (Eq. 1, with the supports of Eqs. 2-3) with direct solvers
-// (Sec. 2.2.2).  On the GPU the solve is a bandwidth-bound iteration instead: per iteration
-//   k_spmv_dir : p = z + beta p_old (formed on the fly), Ap = K p, partial p^T A p
-//   k_update   : x += alpha p, r -= alpha Ap, z = Dinv r, partials r^T z and r^T r
-// Scalars (alpha, beta, convergence) are finished on the device by the last workgroup to arrive
-// (integer arrival counter; the partials are summed in a fixed order, so every reduction is
-// deterministic), so the host only polls a small state record every few iterations.  Once the
-// state says done, later kernels of the same chunk return at entry.
+// (Sec. 2.2.2).  On the GPU the solve is a bandwidth-bound iteration instead.  Iteration j:
+//   k_spmv_dir : finish r_j^T z_j and r_j^T r_j from the previous kernel's per-workgroup
+//                partials, test convergence, beta_j = rz_j / rz_{j-1}; p_j = z_j + beta_j p_{j-1}
+//                (own rows stored, neighbour rows formed on the fly), Ap_j = K p_j, partial
+//                p_j^T A p_j
+//   k_update   : finish p_j^T A p_j, alpha_j = rz_j / pAp_j; x += alpha p, r -= alpha Ap,
+//                z = Dinv r, partials r^T z and r^T r
+// Every workgroup sums the previous kernel's partials itself, in the same fixed order, so all
+// workgroups take identical decisions and no atomics or device-scope fences are needed; the
+// kernel boundary makes the partials visible.  Workgroup 0 records the scalars the host polls.
+// Once the state says done, later kernels return at entry, so the host launches iterations in
+// chunks and polls between chunks.  Every reduction is deterministic.
 //
 // Thread layout of the row kernels: 6 consecutive lanes per node (block row), lane a owning
 // scalar row 6 I + a; it streams the a-th row of every 6x6 block of the block row (48
@@ -24,22 +29,11 @@ constexpr int MAX_WAVES = MAX_TPB / 64;
 
 inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
-__device__ inline double atomic_load_f64(const double* p) {
-  unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)b);
-}
-__device__ inline void atomic_store_f64(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <class T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-// Fixed-order block sum of NV values; the result is valid in thread 0.
+// Fixed-order workgroup sum of NV values; the result is returned to every thread.
 template <int NV, class A>
 __device__ inline void block_sum(A v[NV]) {
   __shared__ A lds[NV][MAX_WAVES];
@@ -50,39 +44,29 @@ __device__ inline void block_sum(A v[NV]) {
   if (lane == 0)
     for (int k = 0; k < NV; ++k) lds[k][wave] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0)
-    for (int k = 0; k < NV; ++k) {
-      A s = lds[k][0];
-      for (int w = 1; w < nw; ++w) s += lds[k][w];
-      v[k] = s;
-    }
+  for (int k = 0; k < NV; ++k) {
+    A s = lds[k][0];
+    for (int w = 1; w < nw; ++w) s += lds[k][w];
+    v[k] = s;
+  }
   __syncthreads();
 }
 
-// Publish this workgroup's partial sums (converted to FP64); returns true in every thread of
-// the last workgroup to arrive, whose tot[] then holds the FP64 totals (valid in thread 0).
-template <int NV, class A>
-__device__ inline bool publish_and_total(const A v[NV], double tot[NV], double* partials,
-                                         unsigned* counter) {
-  __shared__ int last;
-  const int n = gridDim.x;
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < NV; ++k) atomic_store_f64(&partials[k * n + blockIdx.x], (double)v[k]);
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == (unsigned)n - 1u);
-  }
-  __syncthreads();
-  if (!last) return false;
+// Sum of NV arrays of n per-workgroup partials (array k at partials + k * n), fixed order.
+template <int NV>
+__device__ inline void finish_partials(const double* partials, int n, double tot[NV]) {
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += atomic_load_f64(&partials[k * n + i]);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[k * n + i];
     tot[k] = s;
   }
   block_sum<NV, double>(tot);
+}
+
+template <int NV, class A>
+__device__ inline void write_partials(const A v[NV], double* partials) {
   if (threadIdx.x == 0)
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
+    for (int k = 0; k < NV; ++k) partials[k * gridDim.x + blockIdx.x] = (double)v[k];
 }
 
 struct RowMap {
@@ -113,11 +97,11 @@ __device__ inline T apply_dinv(const T* Dinv, const T* rs, const RowMap& m) {
   return z;
 }
 
-// x = 0, r = b, z = Dinv b, p_0 = 0; state: rz, rr = ||b||^2, tolerance, counters.
+// x = 0, r = b, z = Dinv b, p_{-1} = 0; partials of r^T z, r^T r; reset the state record.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_pcg_init(int n_nodes, int rpb, const T* b, T* x, T* r, T* z, T* p0, const T* Dinv,
-           double rtol, int max_it, double* partials, PcgState* st) {
+           double rtol, int max_it, double* pb, PcgState* st) {
   __shared__ T rs[MAX_TPB];
   RowMap m = row_map(rpb, n_nodes);
   const int64_t d = 6 * (int64_t)m.I + m.a;
@@ -137,33 +121,52 @@ k_pcg_init(int n_nodes, int rpb, const T* b, T* x, T* r, T* z, T* p0, const T* D
   }
   T v[2] = {rv * zz, rv * rv};
   block_sum<2, T>(v);
-  double tot[2];
-  if (publish_and_total<2, T>(v, tot, partials, &st->counter[0]) && threadIdx.x == 0) {
-    st->rz = tot[0];
-    st->rr = tot[1];
-    st->ff = tot[1];
-    st->tol2 = rtol * rtol * tot[1];
-    st->pAp = 0.0;
-    st->alpha = 0.0;
-    st->beta = 0.0;
-    st->it = 0;
+  write_partials<2, T>(v, pb);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rtol2 = rtol * rtol;
     st->max_it = max_it;
+    st->it = 0;
+    st->done = 0;
     st->status = SSO_OK;
-    st->done = (tot[1] == 0.0) ? 1 : 0;
   }
 }
 
-// p = z + beta p_old (own rows written to p_new, neighbours formed on the fly), Ap = K p,
-// partial p^T A p; the last workgroup sets alpha = r^T z / p^T A p.
+// Iteration j, first half: finish (rz_j, rr_j), decide, form p_j, Ap_j, partial pAp_j.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_spmv_dir(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
+k_spmv_dir(int n_nodes, int rpb, int j, const int32_t* __restrict__ brow_ptr,
            const int32_t* __restrict__ bcol, const T* __restrict__ K, const T* __restrict__ z,
-           const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ Ap, double* partials,
-           PcgState* st) {
+           const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ Ap,
+           const double* __restrict__ pb, double* __restrict__ pa, PcgState* st) {
   using V = typename Vec2<T>::type;
   if (st->done) return;
-  const T beta = (T)st->beta;
+  double tot[2];
+  finish_partials<2>(pb, gridDim.x, tot);
+  const double rz = tot[0], rr = tot[1];
+  const double ff = (j == 0) ? rr : st->ff;
+  const double beta_d = (j == 0) ? 0.0 : rz / st->rzs[(j - 1) & 1];
+  int stop = 0, status = SSO_OK;
+  if (!std::isfinite(rr) || !std::isfinite(rz)) {
+    stop = 1;
+    status = SSO_EBREAKDOWN;
+  } else if (rr <= st->rtol2 * ff) {
+    stop = 1;
+  } else if (j >= st->max_it) {
+    stop = 1;
+    status = SSO_ENOTCONV;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rzs[j & 1] = rz;
+    st->rr = rr;
+    st->it = j;
+    if (j == 0) st->ff = rr;
+    if (stop) {
+      st->status = status;
+      st->done = 1;
+    }
+  }
+  if (stop) return;
+  const T beta = (T)beta_d;
   RowMap m = row_map(rpb, n_nodes);
   T my = 0;
   if (m.valid) {
@@ -188,29 +191,30 @@ k_spmv_dir(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
   }
   T v[1] = {my};
   block_sum<1, T>(v);
+  write_partials<1, T>(v, pa);
+}
+
+// Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
+// partials of (rz_{j+1}, rr_{j+1}).
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_update(int n_nodes, int rpb, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+         const T* __restrict__ p, const T* __restrict__ Ap, const T* __restrict__ Dinv,
+         const double* __restrict__ pa, double* __restrict__ pb, PcgState* st) {
+  __shared__ T rs[MAX_TPB];
+  if (st->done) return;
   double tot[1];
-  if (publish_and_total<1, T>(v, tot, partials, &st->counter[1]) && threadIdx.x == 0) {
-    const double pAp = tot[0];
-    const double alpha = st->rz / pAp;
-    st->pAp = pAp;
-    st->alpha = alpha;
-    if (!(pAp > 0.0) || !isfinite(alpha)) {
+  finish_partials<1>(pa, gridDim.x, tot);
+  const double pAp = tot[0];
+  const double alpha_d = st->rzs[j & 1] / pAp;
+  if (!(pAp > 0.0) || !std::isfinite(alpha_d)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->status = SSO_EBREAKDOWN;
       st->done = 1;
     }
+    return;
   }
-}
-
-// x += alpha p, r -= alpha Ap, z = Dinv r, partials r^T z and r^T r; the last workgroup sets
-// beta and the convergence flags.
-template <class T>
-__global__ void __launch_bounds__(MAX_TPB)
-k_update(int n_nodes, int rpb, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
-         const T* __restrict__ p, const T* __restrict__ Ap, const T* __restrict__ Dinv,
-         double* partials, PcgState* st) {
-  __shared__ T rs[MAX_TPB];
-  if (st->done) return;
-  const T alpha = (T)st->alpha;
+  const T alpha = (T)alpha_d;
   RowMap m = row_map(rpb, n_nodes);
   const int64_t d = 6 * (int64_t)m.I + m.a;
   T rn = 0;
@@ -228,31 +232,15 @@ k_update(int n_nodes, int rpb, T* __restrict__ x, T* __restrict__ r, T* __restri
   }
   T v[2] = {rn * zz, rn * rn};
   block_sum<2, T>(v);
-  double tot[2];
-  if (publish_and_total<2, T>(v, tot, partials, &st->counter[2]) && threadIdx.x == 0) {
-    const double rz = tot[0], rr = tot[1];
-    st->beta = rz / st->rz;
-    st->rz = rz;
-    st->rr = rr;
-    st->it += 1;
-    if (!isfinite(rr) || !isfinite(rz)) {
-      st->status = SSO_EBREAKDOWN;
-      st->done = 1;
-    } else if (rr <= st->tol2) {
-      st->done = 1;
-    } else if (st->it >= st->max_it) {
-      st->status = SSO_ENOTCONV;
-      st->done = 1;
-    }
-  }
+  write_partials<2, T>(v, pb);
 }
 
-// r = b - K x; out[0] = ||r||^2, out[1] = ||b||^2.
+// r = b - K x; partials of ||r||^2 and ||b||^2.
 __global__ void __launch_bounds__(MAX_TPB)
 k_residual(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
            const int32_t* __restrict__ bcol, const double* __restrict__ K,
            const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
-           double* partials, unsigned* counter, double* out) {
+           double* partials) {
   RowMap m = row_map(rpb, n_nodes);
   double rr = 0.0, bb = 0.0;
   if (m.valid) {
@@ -272,24 +260,31 @@ k_residual(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
   }
   double v[2] = {rr, bb};
   block_sum<2, double>(v);
-  double tot[2];
-  if (publish_and_total<2, double>(v, tot, partials, counter) && threadIdx.x == 0) {
-    out[0] = tot[0];
-    out[1] = tot[1];
-  }
+  write_partials<2, double>(v, partials);
 }
 
 __global__ void __launch_bounds__(256)
-k_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* partials,
-      unsigned* counter, double* out) {
+k_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* partials) {
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     s += a[i] * b[i];
   double v[1] = {s};
   block_sum<1, double>(v);
-  double tot[1];
-  if (publish_and_total<1, double>(v, tot, partials, counter) && threadIdx.x == 0) out[0] = tot[0];
+  write_partials<1, double>(v, partials);
+}
+
+// One workgroup: out[k] = sum of partials array k (nv arrays of n), fixed order.
+__global__ void __launch_bounds__(256) k_finish(const double* partials, int n, int nv,
+                                                double* out) {
+  double tot[2] = {0.0, 0.0};
+  if (nv == 1) {
+    finish_partials<1>(partials, n, tot);
+  } else {
+    finish_partials<2>(partials, n, tot);
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nv; ++k) out[k] = tot[k];
 }
 
 __global__ void k_convert_f32(int64_t n, const double* in, float* out) {
@@ -311,13 +306,14 @@ __global__ void k_refine_update(int64_t n, double alpha, const float* d, double*
 
 }  // namespace
 
-static int choose_rpb(int64_t n_nodes) {
-  if (n_nodes >= 64 * 1024) return 64;    // 384 threads
-  if (n_nodes >= 32 * 512) return 32;     // 192 threads
-  return 10;                              // 64 threads
-}
+static int choose_rpb(int64_t n_nodes) { return n_nodes >= 2048 ? 64 : 32; }
 
 static int tpb_for(int rpb) { return ((6 * rpb + 63) / 64) * 64; }
+
+static int partial_stride(const PcgWork& w) { return w.n_wg > 1024 ? w.n_wg : 1024; }
+static double* part_a(PcgWork& w) { return w.partials; }
+static double* part_b(PcgWork& w) { return w.partials + partial_stride(w); }
+static double* part_once(PcgWork& w) { return w.partials + 3 * (size_t)partial_stride(w); }
 
 hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed) {
   w.n_dof = 6 * n_nodes;
@@ -330,8 +326,9 @@ hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed) {
   if ((e = hipMalloc(&w.p[0], vb)) != hipSuccess) return e;
   if ((e = hipMalloc(&w.p[1], vb)) != hipSuccess) return e;
   if ((e = hipMalloc(&w.Ap, vb)) != hipSuccess) return e;
-  int np = w.n_wg > 1024 ? w.n_wg : 1024;
-  if ((e = hipMalloc(&w.partials, sizeof(double) * 4 * (size_t)np)) != hipSuccess) return e;
+  // partials: pA [stride], pB [2 stride], one-off reductions [2 stride] (+ 2 scalars)
+  const size_t np = (size_t)partial_stride(w);
+  if ((e = hipMalloc(&w.partials, sizeof(double) * (5 * np + 8))) != hipSuccess) return e;
   if ((e = hipMalloc(&w.st, sizeof(PcgState))) != hipSuccess) return e;
   if ((e = hipMemset(w.st, 0, sizeof(PcgState))) != hipSuccess) return e;
   if ((e = hipHostMalloc(&w.h_st, sizeof(PcgState), hipHostMallocDefault)) != hipSuccess)
@@ -354,14 +351,18 @@ hipError_t pcg_alloc_mixed(PcgWork& w) {
   return hipSuccess;
 }
 
+static void release(void* p) {
+  if (p) (void)hipFree(p);
+}
+
 void pcg_free(PcgWork& w) {
-  hipFree(w.r); hipFree(w.z); hipFree(w.p[0]); hipFree(w.p[1]); hipFree(w.Ap);
-  hipFree(w.partials); hipFree(w.st);
-  if (w.h_st) hipHostFree(w.h_st);
-  hipFree(w.r32); hipFree(w.z32); hipFree(w.p32[0]);
-  hipFree(w.p32[1]); hipFree(w.Ap32); hipFree(w.x32); hipFree(w.b32);
+  release(w.r); release(w.z); release(w.p[0]); release(w.p[1]); release(w.Ap);
+  release(w.partials); release(w.st);
+  if (w.h_st) (void)hipHostFree(w.h_st);
+  release(w.r32); release(w.z32); release(w.p32[0]); release(w.p32[1]); release(w.Ap32);
+  release(w.x32); release(w.b32);
   if (w.prof_ev) {
-    for (int i = 0; i < 2 * w.prof_cap; ++i) hipEventDestroy(w.prof_ev[i]);
+    for (int i = 0; i < 2 * w.prof_cap; ++i) (void)hipEventDestroy(w.prof_ev[i]);
     delete[] w.prof_ev;
   }
   w = PcgWork();
@@ -377,8 +378,10 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
                           int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
                           int profile_every) {
   const int rpb = w.rows_per_block, tpb = tpb_for(rpb), nwg = w.n_wg, n = m.n_nodes;
+  double* pa = part_a(w);
+  double* pb = part_b(w);
   hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, b, x, r, z, p[0], Dinv,
-                     rtol, max_it, w.partials, w.st);
+                     rtol, max_it, pb, w.st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (profile_every > 0 && !w.prof_ev) {
@@ -393,17 +396,18 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
       const int64_t gk = launched + i;
+      const int j = (int)(gk < 0x7fffffff ? gk : 0x7fffffff);
       const int k = (int)(gk & 1);
       const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
       if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
-      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, pat.brow_ptr,
-                         pat.bcol, K, z, p[k], p[k ^ 1], Ap, w.partials, w.st);
+      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, j, pat.brow_ptr,
+                         pat.bcol, K, z, p[k], p[k ^ 1], Ap, pb, pa, w.st);
       if (prof) {
         (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
         ++n_prof;
       }
-      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, x, r, z, p[k ^ 1], Ap,
-                         Dinv, w.partials, w.st);
+      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, j, x, r, z, p[k ^ 1],
+                         Ap, Dinv, pa, pb, w.st);
     }
     launched += chunk;
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -437,7 +441,7 @@ hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const d
                          status, profile_every);
 }
 
-// FP32 inner PCG (FP32 K, vectors, SpMV and dot accumulation) inside FP64 iterative
+// FP32 inner PCG (FP32 K, vectors, SpMV and workgroup accumulation) inside FP64 iterative
 // refinement: r = b - K x recomputed in FP64 with the FP64 K, the inner solve runs on r / |r|,
 // and x += |r| d in FP64, until |r| <= rtol |b| or refinement stalls.
 hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
@@ -451,7 +455,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
   w.prof_us = 0.0;
   w.prof_n = 0;
   if ((e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s)) != hipSuccess) return e;
-  double* scal = w.partials + 3 * (size_t)(w.n_wg > 1024 ? w.n_wg : 1024);
+  double* scal = part_once(w) + 2 * (size_t)partial_stride(w);
   *iters = 0;
   *status = SSO_ENOTCONV;
   *outer = 0;
@@ -463,7 +467,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
         hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const double rn = sqrt(h[0]), bn = sqrt(h[1]);
+    const double rn = std::sqrt(h[0]), bn = std::sqrt(h[1]);
     if (!std::isfinite(rn)) {
       *status = SSO_EBREAKDOWN;
       return hipSuccess;
@@ -505,9 +509,14 @@ hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_dot(const double* a, const double* b, int64_t n, double* partials, int n_wg,
-                      unsigned* counter, double* d_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(n_wg), dim3(256), 0, s, n, a, b, partials, counter, d_out);
+hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,
+                      hipStream_t s) {
+  int nwg = (int)((n + 255) / 256);
+  if (nwg > 1024) nwg = 1024;
+  if (nwg < 1) nwg = 1;
+  double* part = part_once(w);
+  hipLaunchKernelGGL(k_dot, dim3(nwg), dim3(256), 0, s, n, a, b, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, nwg, 1, d_out);
   return hipGetLastError();
 }
 
@@ -515,8 +524,10 @@ hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double*
                                 const double* x, const double* b, double* r, PcgWork& w,
                                 double* d_out, hipStream_t s) {
   const int rpb = w.rows_per_block;
+  double* part = part_once(w);
   hipLaunchKernelGGL(k_residual, dim3(w.n_wg), dim3(tpb_for(rpb)), 0, s, m.n_nodes, rpb,
-                     pat.brow_ptr, pat.bcol, K, x, b, r, w.partials, &w.st->counter[3], d_out);
+                     pat.brow_ptr, pat.bcol, K, x, b, r, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, w.n_wg, 2, d_out);
   return hipGetLastError();
 }
 
@@ -529,7 +540,7 @@ double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) {
   const double fb = mixed ? 4.0 : 8.0;
   const double n_dof = 6.0 * (double)n_nodes;
   // spmv: K values + block columns + row pointers; z, p_old read; p_new, Ap written
-  double spmv = 36.0 * fb * n_blocks + 4.0 * n_blocks + 4.0 * (n_nodes + 1) + 4.0 * fb * n_dof;
+  double spmv = spmv_bytes_per_launch(n_nodes, n_blocks, mixed);
   // update: x, p, Ap, r read, Dinv (6 per DOF); x, r, z written
   double upd = 4.0 * fb * n_dof + 6.0 * fb * n_dof + 3.0 * fb * n_dof;
   return spmv + upd;

