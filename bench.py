@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import numpy as np  # noqa: E402
+
 import meshgen  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
@@ -48,6 +50,9 @@ def parse():
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the mixed-size served stream (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -77,6 +82,28 @@ def cpu_baseline(mesh, objective, budget_s):
                       f"BLAS threads {cores}, host cpus {os.cpu_count()}"}
 
 
+def serve_bench(n, slots):
+    """Mixed-size served stream: grid-shells (n x n nodes, n ~ U{8..60}) and shells (m x m quads,
+    m ~ U{10..120}) with per-request seeds, mixed precision, rtol 1e-8.  A closed-loop pass
+    measures the capacity; the timed pass uses Poisson arrivals at 0.8 x capacity."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import Request, Server, poisson_arrivals
+    meshes = [meshgen.served_request(i) for i in range(n)]
+    opts = sso.Options(precision=sso.PREC_MIXED, rtol=1e-8)
+    srv = Server(slots=slots, options=opts)
+    n_cl = min(n, 48)
+    cl = srv.run([Request(i, meshes[i], 0.0) for i in range(n_cl)])
+    lam = 0.8 * cl.solves_per_s
+    t = poisson_arrivals(n, lam, seed=3)
+    st = srv.run([Request(i, meshes[i], float(t[i])) for i in range(n)])
+    return {"requests": st.n, "slots": slots, "precision": "mixed", "rtol": 1e-8,
+            "closed_loop_solves_per_s": cl.solves_per_s, "arrival_rate_per_s": lam,
+            "solves_per_s": st.solves_per_s, "dof_per_s": st.dof_per_s,
+            "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_queue_ms": st.mean_queue_ms,
+            "peak_inflight": st.peak_inflight,
+            "mean_dof": float(np.mean([m.n_dof for m in meshes]))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -84,7 +111,6 @@ def main():
               "(independent problems shard whole across GPUs; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_2407_20026_amd as sso
 
@@ -160,6 +186,8 @@ def main():
                      "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},
     }
     prob.close()
+    if args.serve_requests > 0:
+        out["serving"] = serve_bench(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, args.objective, args.cpu_seconds)
     print(json.dumps(out), flush=True)

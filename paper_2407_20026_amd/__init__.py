@@ -158,19 +158,21 @@ class Problem:
         if not torch.cuda.is_available():
             raise RuntimeError("hipsso needs a GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
-        self.stream = stream
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.n_nodes = int(mesh.xyz.shape[0])
         self.n_beams = int(mesh.beam_nodes.shape[0])
         self.n_quads = int(mesh.quad_nodes.shape[0])
         d = self.device
-        self._xyz = _dev(mesh.xyz, torch.float64, d)
-        self._fixed = _dev(mesh.fixed, torch.uint8, d)
-        self._f = _dev(mesh.f_nodal, torch.float64, d)
-        self._bn = _dev(mesh.beam_nodes, torch.int32, d)
-        self._bp = _dev(mesh.beam_prop, torch.float64, d)
-        self._qn = _dev(mesh.quad_nodes, torch.int32, d)
-        self._qp = _dev(mesh.quad_prop, torch.float64, d)
-        self._qs = _dev(getattr(mesh, "quad_scale", None), torch.float64, d)
+        with torch.cuda.stream(self.stream):
+            # uploads run on the problem's stream, so the library's copies are ordered after them
+            self._xyz = _dev(mesh.xyz, torch.float64, d)
+            self._fixed = _dev(mesh.fixed, torch.uint8, d)
+            self._f = _dev(mesh.f_nodal, torch.float64, d)
+            self._bn = _dev(mesh.beam_nodes, torch.int32, d)
+            self._bp = _dev(mesh.beam_prop, torch.float64, d)
+            self._qn = _dev(mesh.quad_nodes, torch.int32, d)
+            self._qp = _dev(mesh.quad_prop, torch.float64, d)
+            self._qs = _dev(getattr(mesh, "quad_scale", None), torch.float64, d)
         cm = sso_mesh(self.n_nodes, _ptr(self._xyz), _ptr(self._fixed), _ptr(self._f),
                       self.n_beams, _ptr(self._bn), _ptr(self._bp),
                       self.n_quads, _ptr(self._qn), _ptr(self._qp), _ptr(self._qs),
@@ -179,7 +181,7 @@ class Problem:
         opts = self.options.c()
         h = ctypes.c_void_p()
         _check(lib.sso_problem_create(ctypes.byref(cm), ctypes.byref(opts),
-                                      _stream_handle(stream), ctypes.byref(h)),
+                                      _stream_handle(self.stream), ctypes.byref(h)),
                "sso_problem_create")
         self.handle = h
         self.n_dof = 6 * self.n_nodes
@@ -188,6 +190,10 @@ class Problem:
                "sso_sizes")
         self.n_blocks, self.nnz = nb.value, nz.value
         self.last_stats = None
+
+    def _new(self, shape, dtype):
+        with torch.cuda.stream(self.stream):
+            return torch.empty(shape, dtype=dtype, device=self.device)
 
     # -- lifecycle --------------------------------------------------------------------
     def close(self):
@@ -210,7 +216,8 @@ class Problem:
     # -- C entry points ---------------------------------------------------------------
     def update(self, xyz=None, quad_t=None, quad_scale=None):
         d = self.device
-        self._upd = [_dev(a, torch.float64, d) for a in (xyz, quad_t, quad_scale)]
+        with torch.cuda.stream(self.stream):
+            self._upd = [_dev(a, torch.float64, d) for a in (xyz, quad_t, quad_scale)]
         _check(load_library().sso_problem_update(self.handle, *[_ptr(a) for a in self._upd]),
                "sso_problem_update")
 
@@ -222,7 +229,7 @@ class Problem:
     def solve(self, u_out: torch.Tensor | None = None, check: bool = True):
         """Forward analysis; returns (u [n_nodes, 6] float64 device tensor, stats dict)."""
         if u_out is None:
-            u_out = torch.empty((self.n_nodes, 6), dtype=torch.float64, device=self.device)
+            u_out = self._new((self.n_nodes, 6), torch.float64)
         st = sso_stats()
         status = load_library().sso_solve(self.handle, _ptr(u_out), ctypes.byref(st))
         self.last_stats = st.as_dict()
@@ -233,7 +240,8 @@ class Problem:
 
     def objective(self, kind="compliance", a=None) -> float:
         g = ctypes.c_double()
-        at = _dev(a, torch.float64, self.device)
+        with torch.cuda.stream(self.stream):
+            at = _dev(a, torch.float64, self.device)
         _check(load_library().sso_objective(self.handle, OBJECTIVES.get(kind, kind), _ptr(at),
                                             ctypes.byref(g)), "sso_objective")
         return g.value
@@ -242,10 +250,11 @@ class Problem:
         """Gradient of the objective: dict with dg_dxyz [n_nodes, 3], dg_dt [n_quads],
         dg_dscale [n_quads] (float64 device tensors) and the stats."""
         d = self.device
-        gx = torch.empty((self.n_nodes, 3), dtype=torch.float64, device=d)
-        gt = torch.empty(self.n_quads, dtype=torch.float64, device=d) if want_t else None
-        gs = torch.empty(self.n_quads, dtype=torch.float64, device=d) if want_scale else None
-        du = _dev(dg_du, torch.float64, d)
+        gx = self._new((self.n_nodes, 3), torch.float64)
+        gt = self._new(self.n_quads, torch.float64) if want_t else None
+        gs = self._new(self.n_quads, torch.float64) if want_scale else None
+        with torch.cuda.stream(self.stream):
+            du = _dev(dg_du, torch.float64, d)
         st = sso_stats()
         _check(load_library().sso_adjoint(self.handle, OBJECTIVES.get(kind, kind), _ptr(du),
                                           _ptr(gx), _ptr(gt) if self.n_quads else None,
@@ -263,9 +272,9 @@ class Problem:
         out = {}
         for name, src, n in (("row_ptr", rp, self.n_dof + 1), ("col", col, nnz.value),
                              ("perm", perm, ncoo.value), ("seg", seg, nnz.value + 1)):
-            t = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)[:n]
+            t = self._new(max(n, 1), torch.int32)[:n]
             if n:
-                torch.cuda.synchronize()
+                self.stream.synchronize()
                 if _hiprt().hipMemcpy(_ptr(t), src, 4 * n, 3) != 0:
                     raise RuntimeError("hipMemcpy failed")
             out[name] = t
@@ -273,7 +282,7 @@ class Problem:
 
     def matrix(self):
         """(K values in scalar CSR order [nnz], masked load vector [n_nodes, 6])."""
-        vals = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
-        f = torch.empty((self.n_nodes, 6), dtype=torch.float64, device=self.device)
+        vals = self._new(self.nnz, torch.float64)
+        f = self._new((self.n_nodes, 6), torch.float64)
         _check(load_library().sso_matrix(self.handle, _ptr(vals), _ptr(f)), "sso_matrix")
         return vals, f

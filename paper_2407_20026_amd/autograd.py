@@ -1,0 +1,81 @@
+"""torch.autograd bindings of the HIP analysis (argument marshalling only).
+
+The paper couples its differentiable solver to neural networks by chaining the adjoint
+sensitivity of the structure into back-propagation (Sec. 2.4, "structural optimization via NN
+reparameterization"; the shape-and-topology example of Sec. 3.5 trains an MLP whose outputs are
+node heights and element densities, with the structure's compliance as the loss).  Here the
+forward pass calls ``sso_problem_update`` + ``sso_solve`` and the backward pass calls
+``sso_adjoint``: every number comes from the HIP kernels.
+
+* :class:`Compliance` -- c = f^T u as a function of nodal coordinates, shell thickness and the
+  per-element stiffness scale s (SIMP: s = rho^P, Sec. 3.4 Eq. 8; chain the power law in torch).
+* :class:`Displacement` -- u as a function of the same inputs; its backward solves the adjoint
+  system K lambda = dL/du (Sec. 2.3.1, Eqs. 5-6) with the same K and preconditioner.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import OBJ_COMPLIANCE, OBJ_USER, Problem
+
+
+def _as_f64(x, dev):
+    return x.detach().to(device=dev, dtype=torch.float64).contiguous()
+
+
+class Compliance(torch.autograd.Function):
+    """c(xyz, t, s) = f^T u for a fixed topology held by ``problem``.
+
+    xyz [n_nodes, 3], t [n_quads], s [n_quads] (float64 tensors on the problem's device).
+    Returns a 0-dim float64 tensor on the same device."""
+
+    @staticmethod
+    def forward(ctx, problem: Problem, xyz, t, s):
+        dev = problem.device
+        problem.update(xyz=_as_f64(xyz, dev), quad_t=_as_f64(t, dev) if t is not None else None,
+                       quad_scale=_as_f64(s, dev) if s is not None else None)
+        problem.solve()
+        c = problem.objective("compliance")
+        ctx.problem = problem
+        ctx.has_t = t is not None
+        ctx.has_s = s is not None
+        return torch.tensor(c, dtype=torch.float64, device=dev)
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        g = ctx.problem.adjoint(OBJ_COMPLIANCE, want_t=ctx.has_t, want_scale=ctx.has_s)
+        w = grad_c.to(torch.float64)
+        gx = g["dg_dxyz"] * w
+        gt = g["dg_dt"] * w if ctx.has_t else None
+        gs = g["dg_dscale"] * w if ctx.has_s else None
+        return None, gx, gt, gs
+
+
+class Displacement(torch.autograd.Function):
+    """u(xyz, t, s) [n_nodes, 6]; backward: dL/dp = lambda^T (df/dp - dK/dp u), K lambda = dL/du."""
+
+    @staticmethod
+    def forward(ctx, problem: Problem, xyz, t, s):
+        dev = problem.device
+        problem.update(xyz=_as_f64(xyz, dev), quad_t=_as_f64(t, dev) if t is not None else None,
+                       quad_scale=_as_f64(s, dev) if s is not None else None)
+        u, _ = problem.solve()
+        ctx.problem = problem
+        ctx.has_t = t is not None
+        ctx.has_s = s is not None
+        return u.clone()
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        g = ctx.problem.adjoint(OBJ_USER, dg_du=grad_u.to(torch.float64).contiguous(),
+                                want_t=ctx.has_t, want_scale=ctx.has_s)
+        return None, g["dg_dxyz"], g["dg_dt"] if ctx.has_t else None, \
+            g["dg_dscale"] if ctx.has_s else None
+
+
+def compliance(problem: Problem, xyz, t=None, s=None):
+    return Compliance.apply(problem, xyz, t, s)
+
+
+def displacement(problem: Problem, xyz, t=None, s=None):
+    return Displacement.apply(problem, xyz, t, s)

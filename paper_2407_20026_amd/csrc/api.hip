@@ -62,11 +62,6 @@ __global__ void k_fill(int64_t n, double v, double* out) {
   if (i < n) out[i] = v;
 }
 
-template <class T>
-hipError_t dalloc(T** p, int64_t n) {
-  if (n <= 0) n = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
-}
 
 int map_hip(hipError_t e) {
   if (e == hipSuccess) return SSO_OK;
@@ -88,21 +83,23 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 
 void free_problem(sso_problem* p) {
   if (!p) return;
-  if (p->s) hipStreamSynchronize(p->s);
+  hipStream_t s = p->s;
   Mesh& m = p->m;
-  hipFree(m.xyz); hipFree(m.fixed); hipFree(m.f_nodal); hipFree(m.beam_nodes);
-  hipFree(m.beam_prop); hipFree(m.quad_nodes); hipFree(m.quad_prop); hipFree(m.quad_scale);
-  free_pattern(p->pat);
-  hipFree(p->coo); hipFree(p->qarea); hipFree(p->K); hipFree(p->Dinv); hipFree(p->f);
-  hipFree(p->K32); hipFree(p->Dinv32);
-  hipFree(p->u); hipFree(p->lam); hipFree(p->rhs); hipFree(p->gbeam); hipFree(p->gquad);
-  hipFree(p->d_scal); hipFree(p->d_err);
-  if (p->h_scal) hipHostFree(p->h_scal);
-  if (p->h_err) hipHostFree(p->h_err);
-  hipFree(p->row_ptr); hipFree(p->col); hipFree(p->perm); hipFree(p->seg);
-  pcg_free(p->w);
+  for (void* q : {(void*)m.xyz, (void*)m.fixed, (void*)m.f_nodal, (void*)m.beam_nodes,
+                  (void*)m.beam_prop, (void*)m.quad_nodes, (void*)m.quad_prop,
+                  (void*)m.quad_scale, (void*)p->coo, (void*)p->qarea, (void*)p->K,
+                  (void*)p->Dinv, (void*)p->f, (void*)p->K32, (void*)p->Dinv32, (void*)p->u,
+                  (void*)p->lam, (void*)p->rhs, (void*)p->gbeam, (void*)p->gquad,
+                  (void*)p->d_scal, (void*)p->d_err, (void*)p->row_ptr, (void*)p->col,
+                  (void*)p->perm, (void*)p->seg})
+    dev_free(q, s);
+  free_pattern(p->pat, s);
+  pcg_free(p->w, s);
+  delete[] p->h_scal;
+  delete p->h_err;
   for (auto& e : p->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
+  (void)hipStreamSynchronize(s);
   delete p;
 }
 
@@ -117,15 +114,15 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
   m.unit_weight = mesh->unit_weight;
   m.surface_load = mesh->surface_load;
   const int64_t nn = m.n_nodes, nb = m.n_beams, nq = m.n_quads;
-  TRY_HIP(dalloc(&m.xyz, 3 * nn));
-  TRY_HIP(dalloc(&m.fixed, 6 * nn));
-  TRY_HIP(dalloc(&m.f_nodal, 6 * nn));
-  TRY_HIP(dalloc(&m.beam_nodes, 2 * nb));
-  TRY_HIP(dalloc(&m.beam_prop, 6 * nb));
-  TRY_HIP(dalloc(&m.quad_nodes, 4 * nq));
-  TRY_HIP(dalloc(&m.quad_prop, 5 * nq));
-  TRY_HIP(dalloc(&m.quad_scale, nq));
   hipStream_t s = p->s;
+  TRY_HIP(dev_alloc(&m.xyz, 3 * nn, s));
+  TRY_HIP(dev_alloc(&m.fixed, 6 * nn, s));
+  TRY_HIP(dev_alloc(&m.f_nodal, 6 * nn, s));
+  TRY_HIP(dev_alloc(&m.beam_nodes, 2 * nb, s));
+  TRY_HIP(dev_alloc(&m.beam_prop, 6 * nb, s));
+  TRY_HIP(dev_alloc(&m.quad_nodes, 4 * nq, s));
+  TRY_HIP(dev_alloc(&m.quad_prop, 5 * nq, s));
+  TRY_HIP(dev_alloc(&m.quad_scale, nq, s));
   TRY_HIP(hipMemcpyAsync(m.xyz, mesh->xyz, sizeof(double) * 3 * nn, hipMemcpyDeviceToDevice, s));
   TRY_HIP(hipMemcpyAsync(m.fixed, mesh->fixed, 6 * nn, hipMemcpyDeviceToDevice, s));
   TRY_HIP(hipMemcpyAsync(m.f_nodal, mesh->f_nodal, sizeof(double) * 6 * nn,
@@ -150,26 +147,26 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
       TRY_HIP(hipGetLastError());
     }
   }
-  TRY_HIP(dalloc(&p->d_err, 1));
-  TRY_HIP(hipHostMalloc(&p->h_err, sizeof(unsigned), hipHostMallocDefault));
-  TRY_HIP(dalloc(&p->d_scal, 8));
-  TRY_HIP(hipHostMalloc(&p->h_scal, 8 * sizeof(double), hipHostMallocDefault));
+  TRY_HIP(dev_alloc(&p->d_err, 1, s));
+  p->h_err = new unsigned(0);
+  TRY_HIP(dev_alloc(&p->d_scal, 8, s));
+  p->h_scal = new double[8]();
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   *p->h_err = 0;
   TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
   if (*p->h_err) return SSO_EINVAL;
   p->n_coo = 144 * nb + 576 * nq;
-  TRY_HIP(dalloc(&p->coo, p->n_coo));
-  TRY_HIP(dalloc(&p->qarea, nq));
-  TRY_HIP(dalloc(&p->K, 36 * p->pat.n_blocks));
-  TRY_HIP(dalloc(&p->Dinv, 36 * nn));
-  TRY_HIP(dalloc(&p->f, 6 * nn));
-  TRY_HIP(dalloc(&p->u, 6 * nn));
-  TRY_HIP(dalloc(&p->lam, 6 * nn));
-  TRY_HIP(dalloc(&p->rhs, 6 * nn));
-  TRY_HIP(dalloc(&p->gbeam, 6 * nb));
-  TRY_HIP(dalloc(&p->gquad, 14 * nq));
-  TRY_HIP(pcg_alloc(p->w, nn, p->opt.precision == SSO_PREC_MIXED));
+  TRY_HIP(dev_alloc(&p->coo, p->n_coo, s));
+  TRY_HIP(dev_alloc(&p->qarea, nq, s));
+  TRY_HIP(dev_alloc(&p->K, 36 * p->pat.n_blocks, s));
+  TRY_HIP(dev_alloc(&p->Dinv, 36 * nn, s));
+  TRY_HIP(dev_alloc(&p->f, 6 * nn, s));
+  TRY_HIP(dev_alloc(&p->u, 6 * nn, s));
+  TRY_HIP(dev_alloc(&p->lam, 6 * nn, s));
+  TRY_HIP(dev_alloc(&p->rhs, 6 * nn, s));
+  TRY_HIP(dev_alloc(&p->gbeam, 6 * nb, s));
+  TRY_HIP(dev_alloc(&p->gquad, 14 * nq, s));
+  TRY_HIP(pcg_alloc(p->w, nn, p->opt.precision == SSO_PREC_MIXED, s));
   for (auto& e : p->ev) TRY_HIP(hipEventCreate(&e));
   TRY_HIP(hipStreamSynchronize(s));
   return SSO_OK;
@@ -269,8 +266,8 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   hipStream_t s = p->s;
   p->solved = false;
   if (mixed(p) && !p->K32) {
-    TRY_HIP(dalloc(&p->K32, 36 * p->pat.n_blocks));
-    TRY_HIP(dalloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes));
+    TRY_HIP(dev_alloc(&p->K32, 36 * p->pat.n_blocks, s));
+    TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
   }
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(hipEventRecord(p->ev[0], s));
@@ -374,11 +371,12 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
   if (p->n_coo >= ((int64_t)1 << 31) || 36 * p->pat.n_blocks >= ((int64_t)1 << 31))
     return SSO_EINVAL;
   const int64_t nz = 36 * p->pat.n_blocks;
+  hipStream_t s = p->s;
   if (!p->row_ptr) {
-    TRY_HIP(dalloc(&p->row_ptr, 6 * (int64_t)p->m.n_nodes + 1));
-    TRY_HIP(dalloc(&p->col, nz));
-    TRY_HIP(dalloc(&p->perm, p->n_coo));
-    TRY_HIP(dalloc(&p->seg, nz + 1));
+    TRY_HIP(dev_alloc(&p->row_ptr, 6 * (int64_t)p->m.n_nodes + 1, s));
+    TRY_HIP(dev_alloc(&p->col, nz, s));
+    TRY_HIP(dev_alloc(&p->perm, p->n_coo, s));
+    TRY_HIP(dev_alloc(&p->seg, nz + 1, s));
     TRY_HIP(build_scalar_view(p->m, p->pat, p->row_ptr, p->col, p->perm, p->seg, p->s));
     TRY_HIP(hipStreamSynchronize(p->s));
   }

@@ -257,16 +257,16 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   uint64_t* keys = nullptr;
   int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE + 2;
   int64_t nk = pat.n_bcoo > 0 ? pat.n_bcoo : 1;
-  SSO_TRY(hipMalloc(&cnt, sizeof(int32_t) * (n + 1)));
-  SSO_TRY(hipMalloc(&fill, sizeof(int32_t) * (n + 1)));
-  SSO_TRY(hipMalloc(&ucnt, sizeof(int32_t) * (n + 1)));
-  SSO_TRY(hipMalloc(&tmp, sizeof(int32_t) * nt));
-  SSO_TRY(hipMalloc(&keys, sizeof(uint64_t) * nk));
-  SSO_TRY(hipMalloc(&pat.estart, sizeof(int32_t) * (n + 1)));
-  SSO_TRY(hipMalloc(&pat.brow_ptr, sizeof(int32_t) * (n + 1)));
-  SSO_TRY(hipMalloc(&pat.bperm, sizeof(int32_t) * nk));
-  SSO_TRY(hipMalloc(&pat.bslot, sizeof(int32_t) * nk));
-  SSO_TRY(hipMalloc(&pat.bdiag, sizeof(int32_t) * n));
+  SSO_TRY(dev_alloc(&cnt, (n + 1), s));
+  SSO_TRY(dev_alloc(&fill, (n + 1), s));
+  SSO_TRY(dev_alloc(&ucnt, (n + 1), s));
+  SSO_TRY(dev_alloc(&tmp, nt, s));
+  SSO_TRY(dev_alloc(&keys, nk, s));
+  SSO_TRY(dev_alloc(&pat.estart, (n + 1), s));
+  SSO_TRY(dev_alloc(&pat.brow_ptr, (n + 1), s));
+  SSO_TRY(dev_alloc(&pat.bperm, nk, s));
+  SSO_TRY(dev_alloc(&pat.bslot, nk, s));
+  SSO_TRY(dev_alloc(&pat.bdiag, n, s));
   SSO_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), s));
   SSO_TRY(hipMemsetAsync(fill, 0, sizeof(int32_t) * (n + 1), s));
   if (pat.n_bcoo)
@@ -276,7 +276,7 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   SSO_TRY(hipMemcpyAsync(h_err, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   SSO_TRY(hipStreamSynchronize(s));
   if (*h_err) {
-    hipFree(cnt); hipFree(fill); hipFree(ucnt); hipFree(tmp); hipFree(keys);
+    dev_free(cnt, s); dev_free(fill, s); dev_free(ucnt, s); dev_free(tmp, s); dev_free(keys, s);
     return hipSuccess;   // caller reports SSO_EINVAL
   }
   SSO_TRY(exclusive_scan(cnt, n, pat.estart, tmp, s));
@@ -291,16 +291,16 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   SSO_TRY(hipMemcpyAsync(&nblk, pat.brow_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   SSO_TRY(hipStreamSynchronize(s));
   pat.n_blocks = nblk;
-  SSO_TRY(hipMalloc(&pat.bcol, sizeof(int32_t) * nblk));
-  SSO_TRY(hipMalloc(&pat.bseg, sizeof(int32_t) * (nblk + 1)));
-  SSO_TRY(hipMalloc(&pat.bsrow, sizeof(int32_t) * nblk));
+  SSO_TRY(dev_alloc(&pat.bcol, nblk, s));
+  SSO_TRY(dev_alloc(&pat.bseg, (nblk + 1), s));
+  SSO_TRY(dev_alloc(&pat.bsrow, nblk, s));
   hipLaunchKernelGGL(k_emit, dim3(blocks_for(n)), dim3(TPB), 0, s, n, pat.estart, keys,
                      pat.brow_ptr, pat.bcol, pat.bseg, pat.bperm, pat.bslot, pat.bdiag, pat.bsrow);
   SSO_TRY(hipGetLastError());
   int32_t last = (int32_t)pat.n_bcoo;
   SSO_TRY(hipMemcpyAsync(pat.bseg + nblk, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
   SSO_TRY(hipStreamSynchronize(s));
-  hipFree(cnt); hipFree(fill); hipFree(ucnt); hipFree(tmp); hipFree(keys);
+  dev_free(cnt, s); dev_free(fill, s); dev_free(ucnt, s); dev_free(tmp, s); dev_free(keys, s);
   return hipSuccess;
 }
 
@@ -316,9 +316,10 @@ hipError_t build_scalar_view(const Mesh& m, const Pattern& pat, int32_t* row_ptr
   return hipGetLastError();
 }
 
-void free_pattern(Pattern& pat) {
-  hipFree(pat.brow_ptr); hipFree(pat.bcol); hipFree(pat.bseg); hipFree(pat.bperm);
-  hipFree(pat.bslot); hipFree(pat.bdiag); hipFree(pat.estart); hipFree(pat.bsrow);
+void free_pattern(Pattern& pat, hipStream_t s) {
+  dev_free(pat.brow_ptr, s); dev_free(pat.bcol, s); dev_free(pat.bseg, s);
+  dev_free(pat.bperm, s); dev_free(pat.bslot, s); dev_free(pat.bdiag, s);
+  dev_free(pat.estart, s); dev_free(pat.bsrow, s);
   pat = Pattern();
 }
 

@@ -14,9 +14,11 @@
 // Once the state says done, later kernels return at entry, so the host launches iterations in
 // chunks and polls between chunks.  Every reduction is deterministic.
 //
-// Thread layout of the row kernels: 6 consecutive lanes per node (block row), lane a owning
-// scalar row 6 I + a; it streams the a-th row of every 6x6 block of the block row (48
-// contiguous bytes) so the 6 lanes of a node read each 288-byte block once, in order.
+// Thread layouts: the SpMV kernels give 18 lanes to a block row, each lane reading one 16-byte
+// piece of every 6x6 block, so one load instruction covers a whole 288-byte block; the vector
+// kernels give 6 lanes to a node.  All kernels stride over the rows with a fixed number of
+// workgroups.  Every 64 iterations the residual is recomputed from x (residual replacement),
+// which keeps the recursively updated residual, and so the stopping test, honest.
 #include <cmath>
 
 #include "sso_internal.h"
@@ -69,26 +71,30 @@ __device__ inline void write_partials(const A v[NV], double* partials) {
     for (int k = 0; k < NV; ++k) partials[k * gridDim.x + blockIdx.x] = (double)v[k];
 }
 
+// ---- vector kernels: 6 consecutive lanes per node, 64 nodes per workgroup pass -----------
+
+constexpr int VEC_NODES = MAX_TPB / 6;   // 64
+
 struct RowMap {
   int lr, a, I;
   bool valid;
 };
 
-__device__ inline RowMap row_map(int rpb, int n_nodes) {
+__device__ inline RowMap row_map_at(int group, int n_nodes) {
   RowMap m;
   m.lr = threadIdx.x / 6;
   m.a = threadIdx.x - 6 * m.lr;
-  m.I = blockIdx.x * rpb + m.lr;
-  m.valid = (m.lr < rpb) && (m.I < n_nodes);
+  m.I = group * VEC_NODES + m.lr;
+  m.valid = (m.lr < VEC_NODES) && (m.I < n_nodes);
   return m;
 }
 
 // z = Dinv r for the node of this lane, r values of the node staged in LDS.
 template <class T>
-__device__ inline T apply_dinv(const T* Dinv, const T* rs, const RowMap& m) {
+__device__ inline T apply_dinv(const T* Dinv, const T* rs, int I, int a, int lr) {
   using V = typename Vec2<T>::type;
-  const V* dv = reinterpret_cast<const V*>(Dinv + 36 * (int64_t)m.I + 6 * m.a);
-  const T* rr = rs + 6 * m.lr;
+  const V* dv = reinterpret_cast<const V*>(Dinv + 36 * (int64_t)I + 6 * a);
+  const T* rr = rs + 6 * lr;
   T z = 0;
   for (int h = 0; h < 3; ++h) {
     V d = dv[h];
@@ -97,29 +103,111 @@ __device__ inline T apply_dinv(const T* Dinv, const T* rs, const RowMap& m) {
   return z;
 }
 
+// ---- SpMV layout: 18 lanes per block row, 3 block rows per wavefront ----------------------
+// Lane l of a row group owns entries (a, b..b+1) of every 6x6 block, a = l / 3, b = 2 (l % 3),
+// so the 18 lanes read each 288-byte block with one contiguous 16-byte load each.
+
+constexpr int ROW_LANES = 18;
+constexpr int ROWS_PER_WAVE = 3;
+constexpr int ROWS_PER_WG = ROWS_PER_WAVE * (MAX_TPB / 64);   // 18
+
+struct SpLane {
+  int lane, g, l, a, b;
+  bool ok;
+};
+
+__device__ inline SpLane sp_lane() {
+  SpLane L;
+  L.lane = threadIdx.x & 63;
+  L.g = L.lane / ROW_LANES;
+  L.l = L.lane - ROW_LANES * L.g;
+  L.a = L.l / 3;
+  L.b = 2 * (L.l - 3 * L.a);
+  L.ok = L.g < ROWS_PER_WAVE;
+  return L;
+}
+
+// sum over the block row of K[s][a][b..b+1] . v[6 J + b..b+1], with v = x (DIR false) or
+// v = x + beta p (DIR true, the search direction formed on the fly).  Unrolled by 3 blocks so
+// the column indices of a step are loaded before the values that depend on them.
+template <class T, bool DIR>
+__device__ inline T row_product(const int32_t* __restrict__ brow_ptr,
+                                const int32_t* __restrict__ bcol, const T* __restrict__ K,
+                                const T* __restrict__ x, const T* __restrict__ p, T beta, int I,
+                                int a, int b) {
+  using V = typename Vec2<T>::type;
+  const int rb = brow_ptr[I], re = brow_ptr[I + 1];
+  const int off = 6 * a + b;
+  T acc = 0;
+  int s = rb;
+  for (; s + 3 <= re; s += 3) {
+    const int64_t J0 = bcol[s], J1 = bcol[s + 1], J2 = bcol[s + 2];
+    const V k0 = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
+    const V k1 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 1) + off);
+    const V k2 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 2) + off);
+    V x0 = *reinterpret_cast<const V*>(x + 6 * J0 + b);
+    V x1 = *reinterpret_cast<const V*>(x + 6 * J1 + b);
+    V x2 = *reinterpret_cast<const V*>(x + 6 * J2 + b);
+    if (DIR) {
+      const V p0 = *reinterpret_cast<const V*>(p + 6 * J0 + b);
+      const V p1 = *reinterpret_cast<const V*>(p + 6 * J1 + b);
+      const V p2 = *reinterpret_cast<const V*>(p + 6 * J2 + b);
+      x0.x = x0.x + beta * p0.x; x0.y = x0.y + beta * p0.y;
+      x1.x = x1.x + beta * p1.x; x1.y = x1.y + beta * p1.y;
+      x2.x = x2.x + beta * p2.x; x2.y = x2.y + beta * p2.y;
+    }
+    acc += k0.x * x0.x + k0.y * x0.y;
+    acc += k1.x * x1.x + k1.y * x1.y;
+    acc += k2.x * x2.x + k2.y * x2.y;
+  }
+  for (; s < re; ++s) {
+    const int64_t J = bcol[s];
+    const V kv = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
+    V xv = *reinterpret_cast<const V*>(x + 6 * J + b);
+    if (DIR) {
+      const V pv = *reinterpret_cast<const V*>(p + 6 * J + b);
+      xv.x = xv.x + beta * pv.x; xv.y = xv.y + beta * pv.y;
+    }
+    acc += kv.x * xv.x + kv.y * xv.y;
+  }
+  return acc;
+}
+
+// Row total in the first lane (l % 3 == 0) of each 3-lane set, fixed order.
+template <class T>
+__device__ inline T sum3(T acc, int lane) {
+  const T t1 = __shfl(acc, lane + 1, 64);
+  const T t2 = __shfl(acc, lane + 2, 64);
+  return acc + t1 + t2;
+}
+
 // x = 0, r = b, z = Dinv b, p_{-1} = 0; partials of r^T z, r^T r; reset the state record.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_pcg_init(int n_nodes, int rpb, const T* b, T* x, T* r, T* z, T* p0, const T* Dinv,
-           double rtol, int max_it, double* pb, PcgState* st) {
+k_pcg_init(int n_nodes, const T* b, T* x, T* r, T* z, T* p0, const T* Dinv, double rtol,
+           int max_it, double* pb, PcgState* st) {
   __shared__ T rs[MAX_TPB];
-  RowMap m = row_map(rpb, n_nodes);
-  const int64_t d = 6 * (int64_t)m.I + m.a;
-  T rv = 0;
-  if (m.valid) {
-    rv = b[d];
-    x[d] = 0;
-    r[d] = rv;
-    p0[d] = 0;
+  T v[2] = {0, 0};
+  for (int gi = blockIdx.x; gi * VEC_NODES < n_nodes; gi += gridDim.x) {
+    RowMap m = row_map_at(gi, n_nodes);
+    const int64_t d = 6 * (int64_t)m.I + m.a;
+    T rv = 0;
+    if (m.valid) {
+      rv = b[d];
+      x[d] = 0;
+      r[d] = rv;
+      p0[d] = 0;
+    }
+    rs[threadIdx.x] = rv;
+    __syncthreads();
+    if (m.valid) {
+      const T zz = apply_dinv(Dinv, rs, m.I, m.a, m.lr);
+      z[d] = zz;
+      v[0] += rv * zz;
+      v[1] += rv * rv;
+    }
+    __syncthreads();
   }
-  rs[threadIdx.x] = rv;
-  __syncthreads();
-  T zz = 0;
-  if (m.valid) {
-    zz = apply_dinv(Dinv, rs, m);
-    z[d] = zz;
-  }
-  T v[2] = {rv * zz, rv * rv};
   block_sum<2, T>(v);
   write_partials<2, T>(v, pb);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -134,11 +222,10 @@ k_pcg_init(int n_nodes, int rpb, const T* b, T* x, T* r, T* z, T* p0, const T* D
 // Iteration j, first half: finish (rz_j, rr_j), decide, form p_j, Ap_j, partial pAp_j.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_spmv_dir(int n_nodes, int rpb, int j, const int32_t* __restrict__ brow_ptr,
+k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
            const int32_t* __restrict__ bcol, const T* __restrict__ K, const T* __restrict__ z,
            const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ Ap,
            const double* __restrict__ pb, double* __restrict__ pa, PcgState* st) {
-  using V = typename Vec2<T>::type;
   if (st->done) return;
   double tot[2];
   finish_partials<2>(pb, gridDim.x, tot);
@@ -167,27 +254,22 @@ k_spmv_dir(int n_nodes, int rpb, int j, const int32_t* __restrict__ brow_ptr,
   }
   if (stop) return;
   const T beta = (T)beta_d;
-  RowMap m = row_map(rpb, n_nodes);
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
   T my = 0;
-  if (m.valid) {
-    const int rb = brow_ptr[m.I], re = brow_ptr[m.I + 1];
+  for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
+    const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
+    const bool ok = L.ok && I < n_nodes;
     T acc = 0;
-    for (int s = rb; s < re; ++s) {
-      const int64_t J = bcol[s];
-      const V* kr = reinterpret_cast<const V*>(K + 36 * (int64_t)s + 6 * m.a);
-      const V* zj = reinterpret_cast<const V*>(z + 6 * J);
-      const V* pj = reinterpret_cast<const V*>(pold + 6 * J);
-#pragma unroll
-      for (int h = 0; h < 3; ++h) {
-        const V kv = kr[h], zv = zj[h], pv = pj[h];
-        acc += kv.x * (zv.x + beta * pv.x) + kv.y * (zv.y + beta * pv.y);
-      }
+    if (ok) acc = row_product<T, true>(brow_ptr, bcol, K, z, pold, beta, I, L.a, L.b);
+    const T sum = sum3(acc, L.lane);
+    if (ok && L.b == 0) {
+      const int64_t d = 6 * (int64_t)I + L.a;
+      const T pn = z[d] + beta * pold[d];
+      pnew[d] = pn;
+      Ap[d] = sum;
+      my += pn * sum;
     }
-    const int64_t d = 6 * (int64_t)m.I + m.a;
-    const T pn = z[d] + beta * pold[d];
-    pnew[d] = pn;
-    Ap[d] = acc;
-    my = pn * acc;
   }
   T v[1] = {my};
   block_sum<1, T>(v);
@@ -198,7 +280,7 @@ k_spmv_dir(int n_nodes, int rpb, int j, const int32_t* __restrict__ brow_ptr,
 // partials of (rz_{j+1}, rr_{j+1}).
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_update(int n_nodes, int rpb, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+k_update(int n_nodes, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
          const T* __restrict__ p, const T* __restrict__ Ap, const T* __restrict__ Dinv,
          const double* __restrict__ pa, double* __restrict__ pb, PcgState* st) {
   __shared__ T rs[MAX_TPB];
@@ -215,50 +297,92 @@ k_update(int n_nodes, int rpb, int j, T* __restrict__ x, T* __restrict__ r, T* _
     return;
   }
   const T alpha = (T)alpha_d;
-  RowMap m = row_map(rpb, n_nodes);
-  const int64_t d = 6 * (int64_t)m.I + m.a;
-  T rn = 0;
-  if (m.valid) {
-    x[d] += alpha * p[d];
-    rn = r[d] - alpha * Ap[d];
-    r[d] = rn;
+  T v[2] = {0, 0};
+  for (int gi = blockIdx.x; gi * VEC_NODES < n_nodes; gi += gridDim.x) {
+    RowMap m = row_map_at(gi, n_nodes);
+    const int64_t d = 6 * (int64_t)m.I + m.a;
+    T rn = 0;
+    if (m.valid) {
+      x[d] += alpha * p[d];
+      rn = r[d] - alpha * Ap[d];
+      r[d] = rn;
+    }
+    rs[threadIdx.x] = rn;
+    __syncthreads();
+    if (m.valid) {
+      const T zz = apply_dinv(Dinv, rs, m.I, m.a, m.lr);
+      z[d] = zz;
+      v[0] += rn * zz;
+      v[1] += rn * rn;
+    }
+    __syncthreads();
   }
-  rs[threadIdx.x] = rn;
-  __syncthreads();
-  T zz = 0;
-  if (m.valid) {
-    zz = apply_dinv(Dinv, rs, m);
-    z[d] = zz;
+  block_sum<2, T>(v);
+  write_partials<2, T>(v, pb);
+}
+
+// Residual replacement: r = b - K x recomputed, z = Dinv r, partials of (r^T z, r^T r)
+// overwrite those of the preceding update, so the recursion keeps tracking the true residual.
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_replace(int n_nodes, const int32_t* __restrict__ brow_ptr, const int32_t* __restrict__ bcol,
+          const T* __restrict__ K, const T* __restrict__ x, const T* __restrict__ b,
+          T* __restrict__ r, T* __restrict__ z, const T* __restrict__ Dinv, double* pb,
+          const PcgState* st) {
+  __shared__ T rs[ROWS_PER_WG * 6];
+  if (st->done) return;
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
+  const int slot = wave * ROWS_PER_WAVE + L.g;   // node slot within the workgroup pass
+  T v[2] = {0, 0};
+  for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
+    const int I = gi * ROWS_PER_WG + slot;
+    const bool ok = L.ok && I < n_nodes;
+    T acc = 0;
+    if (ok) acc = row_product<T, false>(brow_ptr, bcol, K, x, x, (T)0, I, L.a, L.b);
+    const T sum = sum3(acc, L.lane);
+    T rv = 0;
+    if (ok && L.b == 0) {
+      const int64_t d = 6 * (int64_t)I + L.a;
+      rv = b[d] - sum;
+      r[d] = rv;
+      rs[6 * slot + L.a] = rv;
+    }
+    __syncthreads();
+    if (ok && L.b == 0) {
+      const T zz = apply_dinv(Dinv, rs, I, L.a, slot);
+      z[6 * (int64_t)I + L.a] = zz;
+      v[0] += rv * zz;
+      v[1] += rv * rv;
+    }
+    __syncthreads();
   }
-  T v[2] = {rn * zz, rn * rn};
   block_sum<2, T>(v);
   write_partials<2, T>(v, pb);
 }
 
 // r = b - K x; partials of ||r||^2 and ||b||^2.
 __global__ void __launch_bounds__(MAX_TPB)
-k_residual(int n_nodes, int rpb, const int32_t* __restrict__ brow_ptr,
-           const int32_t* __restrict__ bcol, const double* __restrict__ K,
-           const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
-           double* partials) {
-  RowMap m = row_map(rpb, n_nodes);
-  double rr = 0.0, bb = 0.0;
-  if (m.valid) {
-    const int rb = brow_ptr[m.I], re = brow_ptr[m.I + 1];
+k_residual(int n_nodes, const int32_t* __restrict__ brow_ptr, const int32_t* __restrict__ bcol,
+           const double* __restrict__ K, const double* __restrict__ x,
+           const double* __restrict__ b, double* __restrict__ r, double* partials) {
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
+  double v[2] = {0.0, 0.0};
+  for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
+    const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
+    const bool ok = L.ok && I < n_nodes;
     double acc = 0.0;
-    for (int s = rb; s < re; ++s) {
-      const int64_t J = bcol[s];
-      const double* kr = K + 36 * (int64_t)s + 6 * m.a;
-      const double* xj = x + 6 * J;
-      for (int c = 0; c < 6; ++c) acc += kr[c] * xj[c];
+    if (ok) acc = row_product<double, false>(brow_ptr, bcol, K, x, x, 0.0, I, L.a, L.b);
+    const double sum = sum3(acc, L.lane);
+    if (ok && L.b == 0) {
+      const int64_t d = 6 * (int64_t)I + L.a;
+      const double rv = b[d] - sum;
+      if (r) r[d] = rv;
+      v[0] += rv * rv;
+      v[1] += b[d] * b[d];
     }
-    const int64_t d = 6 * (int64_t)m.I + m.a;
-    const double rv = b[d] - acc;
-    if (r) r[d] = rv;
-    rr = rv * rv;
-    bb = b[d] * b[d];
   }
-  double v[2] = {rr, bb};
   block_sum<2, double>(v);
   write_partials<2, double>(v, partials);
 }
@@ -306,61 +430,59 @@ __global__ void k_refine_update(int64_t n, double alpha, const float* d, double*
 
 }  // namespace
 
-static int choose_rpb(int64_t n_nodes) { return n_nodes >= 2048 ? 64 : 32; }
+// Workgroups of the PCG kernels: one pass of 18 block rows each, at most 1024 (every
+// workgroup re-reads all partials, so their number bounds that cost); grid-stride beyond.
+static int choose_wg(int64_t n_nodes) {
+  int64_t g = (n_nodes + ROWS_PER_WG - 1) / ROWS_PER_WG;
+  return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
 
-static int tpb_for(int rpb) { return ((6 * rpb + 63) / 64) * 64; }
+// Residual replacement period (iterations).
+static constexpr int REPLACE_EVERY = 64;
 
 static int partial_stride(const PcgWork& w) { return w.n_wg > 1024 ? w.n_wg : 1024; }
 static double* part_a(PcgWork& w) { return w.partials; }
 static double* part_b(PcgWork& w) { return w.partials + partial_stride(w); }
 static double* part_once(PcgWork& w) { return w.partials + 3 * (size_t)partial_stride(w); }
 
-hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed) {
+hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
   w.n_dof = 6 * n_nodes;
-  w.rows_per_block = choose_rpb(n_nodes);
-  w.n_wg = (int)((n_nodes + w.rows_per_block - 1) / w.rows_per_block);
-  const size_t vb = sizeof(double) * (size_t)w.n_dof;
+  w.n_wg = choose_wg(n_nodes);
   hipError_t e;
-  if ((e = hipMalloc(&w.r, vb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.z, vb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.p[0], vb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.p[1], vb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.Ap, vb)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.r, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.z, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.p[0], w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.p[1], w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.Ap, w.n_dof , s)) != hipSuccess) return e;
   // partials: pA [stride], pB [2 stride], one-off reductions [2 stride] (+ 2 scalars)
   const size_t np = (size_t)partial_stride(w);
-  if ((e = hipMalloc(&w.partials, sizeof(double) * (5 * np + 8))) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.st, sizeof(PcgState))) != hipSuccess) return e;
-  if ((e = hipMemset(w.st, 0, sizeof(PcgState))) != hipSuccess) return e;
-  if ((e = hipHostMalloc(&w.h_st, sizeof(PcgState), hipHostMallocDefault)) != hipSuccess)
-    return e;
-  if (mixed) return pcg_alloc_mixed(w);
+  if ((e = dev_alloc(&w.partials, (int64_t)(5 * np + 8), s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.st, 1, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(w.st, 0, sizeof(PcgState), s)) != hipSuccess) return e;
+  w.h_st = new PcgState();
+  if (mixed) return pcg_alloc_mixed(w, s);
   return hipSuccess;
 }
 
-hipError_t pcg_alloc_mixed(PcgWork& w) {
+hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s) {
   if (w.r32) return hipSuccess;
-  const size_t fb = sizeof(float) * (size_t)w.n_dof;
   hipError_t e;
-  if ((e = hipMalloc(&w.r32, fb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.z32, fb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.p32[0], fb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.p32[1], fb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.Ap32, fb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.x32, fb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.b32, fb)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.r32, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.z32, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.p32[0], w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.p32[1], w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.Ap32, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.x32, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.b32, w.n_dof , s)) != hipSuccess) return e;
   return hipSuccess;
 }
 
-static void release(void* p) {
-  if (p) (void)hipFree(p);
-}
-
-void pcg_free(PcgWork& w) {
-  release(w.r); release(w.z); release(w.p[0]); release(w.p[1]); release(w.Ap);
-  release(w.partials); release(w.st);
-  if (w.h_st) (void)hipHostFree(w.h_st);
-  release(w.r32); release(w.z32); release(w.p32[0]); release(w.p32[1]); release(w.Ap32);
-  release(w.x32); release(w.b32);
+void pcg_free(PcgWork& w, hipStream_t s) {
+  dev_free(w.r, s); dev_free(w.z, s); dev_free(w.p[0], s); dev_free(w.p[1], s);
+  dev_free(w.Ap, s); dev_free(w.partials, s); dev_free(w.st, s);
+  delete w.h_st;
+  dev_free(w.r32, s); dev_free(w.z32, s); dev_free(w.p32[0], s); dev_free(w.p32[1], s);
+  dev_free(w.Ap32, s); dev_free(w.x32, s); dev_free(w.b32, s);
   if (w.prof_ev) {
     for (int i = 0; i < 2 * w.prof_cap; ++i) (void)hipEventDestroy(w.prof_ev[i]);
     delete[] w.prof_ev;
@@ -377,11 +499,11 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
                           const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
                           int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
                           int profile_every) {
-  const int rpb = w.rows_per_block, tpb = tpb_for(rpb), nwg = w.n_wg, n = m.n_nodes;
+  const int tpb = MAX_TPB, nwg = w.n_wg, n = m.n_nodes;
   double* pa = part_a(w);
   double* pb = part_b(w);
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, b, x, r, z, p[0], Dinv,
-                     rtol, max_it, pb, w.st);
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, n, b, x, r, z, p[0], Dinv, rtol,
+                     max_it, pb, w.st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (profile_every > 0 && !w.prof_ev) {
@@ -400,14 +522,17 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
       const int k = (int)(gk & 1);
       const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
       if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
-      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, j, pat.brow_ptr,
-                         pat.bcol, K, z, p[k], p[k ^ 1], Ap, pb, pa, w.st);
+      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, n, j, pat.brow_ptr, pat.bcol,
+                         K, z, p[k], p[k ^ 1], Ap, pb, pa, w.st);
       if (prof) {
         (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
         ++n_prof;
       }
-      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, n, rpb, j, x, r, z, p[k ^ 1],
-                         Ap, Dinv, pa, pb, w.st);
+      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, n, j, x, r, z, p[k ^ 1], Ap,
+                         Dinv, pa, pb, w.st);
+      if ((gk + 1) % REPLACE_EVERY == 0)
+        hipLaunchKernelGGL(k_replace<T>, dim3(nwg), dim3(tpb), 0, s, n, pat.brow_ptr, pat.bcol, K,
+                           x, b, r, z, Dinv, pb, w.st);
     }
     launched += chunk;
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -450,7 +575,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
                            hipStream_t s, int* iters, int* status, int* outer,
                            int profile_every) {
   hipError_t e;
-  if ((e = pcg_alloc_mixed(w)) != hipSuccess) return e;
+  if ((e = pcg_alloc_mixed(w, s)) != hipSuccess) return e;
   const int64_t n = w.n_dof;
   w.prof_us = 0.0;
   w.prof_n = 0;
@@ -523,10 +648,9 @@ hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, d
 hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double* K,
                                 const double* x, const double* b, double* r, PcgWork& w,
                                 double* d_out, hipStream_t s) {
-  const int rpb = w.rows_per_block;
   double* part = part_once(w);
-  hipLaunchKernelGGL(k_residual, dim3(w.n_wg), dim3(tpb_for(rpb)), 0, s, m.n_nodes, rpb,
-                     pat.brow_ptr, pat.bcol, K, x, b, r, part);
+  hipLaunchKernelGGL(k_residual, dim3(w.n_wg), dim3(MAX_TPB), 0, s, m.n_nodes, pat.brow_ptr,
+                     pat.bcol, K, x, b, r, part);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, w.n_wg, 2, d_out);
   return hipGetLastError();
 }

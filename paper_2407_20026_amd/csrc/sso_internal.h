@@ -87,6 +87,17 @@ __host__ __device__ inline int64_t coo_index(const BlockRef& r, int ca, int cb, 
   return 144 * (int64_t)n_beams + 576 * (int64_t)r.e + 24 * (6 * r.la + ca) + 6 * r.lb + cb;
 }
 
+// Stream-ordered device memory: no device-wide synchronisation, so problems that live on
+// different streams keep overlapping while others are created or destroyed.
+template <class T>
+inline hipError_t dev_alloc(T** p, int64_t n, hipStream_t s) {
+  if (n <= 0) n = 1;
+  return hipMallocAsync(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n, s);
+}
+inline void dev_free(void* p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
+}
+
 // ---- launch helpers (each defined in its own translation unit) ----------------------------
 
 // pattern.hip
@@ -94,7 +105,7 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
                          unsigned* h_err);
 hipError_t build_scalar_view(const Mesh& m, const Pattern& pat, int32_t* row_ptr, int32_t* col,
                              int32_t* perm, int32_t* seg, hipStream_t s);
-void free_pattern(Pattern& pat);
+void free_pattern(Pattern& pat, hipStream_t s);
 
 // elements.hip
 hipError_t launch_element_stiffness(const Mesh& m, double* coo, double* qarea, unsigned* d_err,
@@ -120,15 +131,14 @@ hipError_t launch_scalar_values(const Mesh& m, const Pattern& pat, const double*
 // pcg.hip
 struct PcgWork {
   int64_t n_dof = 0;
-  int rows_per_block = 0;  // block rows (nodes) per workgroup of the vector kernels
-  int n_wg = 0;            // workgroups of the row kernels
+  int n_wg = 0;            // workgroups of the PCG kernels (grid-stride over the rows)
   double* r = nullptr;
   double* z = nullptr;
   double* p[2] = {nullptr, nullptr};
   double* Ap = nullptr;
   double* partials = nullptr;   // per-workgroup partial sums (see pcg.hip)
   PcgState* st = nullptr;
-  PcgState* h_st = nullptr;     // pinned host mirror
+  PcgState* h_st = nullptr;     // host mirror
   // mixed precision: FP32 inner PCG vectors (allocated on first use)
   float* r32 = nullptr;
   float* z32 = nullptr;
@@ -143,9 +153,9 @@ struct PcgWork {
   int prof_n = 0;
 };
 
-hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed);
-hipError_t pcg_alloc_mixed(PcgWork& w);
-void pcg_free(PcgWork& w);
+hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s);
+hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s);
+void pcg_free(PcgWork& w, hipStream_t s);
 // Solve K x = b (b already masked); x overwritten.  Returns SSO status via *status.
 // profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,

@@ -1,0 +1,198 @@
+"""Continuous-batching request loop for forward + adjoint analyses of mixed-size structures.
+
+Requests (a structure and an objective) arrive over time.  A request is admitted as soon as a
+slot is free and its device-memory footprint fits in the remaining budget; admitted requests run
+concurrently, each on its own HIP stream, so their kernels overlap on the GPU; a finished request
+frees its slot and its memory at once and the next waiting request is admitted.  Per request the
+loop records arrival, admission and completion times, so p50/p99 latency (arrival to result)
+and throughput (solves/s, DOF/s) are reported side by side.
+
+Every number comes from the HIP library: each slot drives ``sso_problem_create``,
+``sso_solve``, ``sso_objective`` and ``sso_adjoint`` from a host thread (the C calls release the
+interpreter lock), K, the preconditioner and u stay on the device for the request's lifetime.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import Options, Problem
+
+
+def footprint_bytes(mesh, mixed: bool = False) -> int:
+    """Upper bound of the device memory one problem holds (mesh, pattern, element list, K,
+    preconditioner, PCG vectors, gradients)."""
+    nn, nb, nq = mesh.n_nodes, mesh.n_beams, mesh.n_quads
+    blocks = nn + 2 * nb + 12 * nq                  # diagonal + off-diagonal blocks (bound)
+    nbcoo = 4 * nb + 16 * nq
+    ndof = 6 * nn
+    b = 0
+    b += nn * (3 * 8 + 6 + 6 * 8) + nb * (8 + 48) + nq * (16 + 40 + 8)        # mesh copies
+    b += 4 * (3 * nbcoo + 3 * blocks + 4 * nn)                                  # pattern
+    b += 8 * (144 * nb + 576 * nq)                                              # element list
+    b += 288 * blocks + 288 * nn                                                # K, Dinv
+    b += 8 * ndof * 10 + 8 * (6 * nb + 14 * nq)                                 # vectors, grads
+    if mixed:
+        b += 144 * blocks + 144 * nn + 4 * ndof * 7
+    return int(b * 1.1) + (1 << 20)
+
+
+@dataclass
+class Request:
+    rid: int
+    mesh: object
+    arrival: float                      # seconds from the start of the stream
+    objective: str = "compliance"
+
+
+@dataclass
+class Result:
+    rid: int
+    n_dof: int
+    g: float
+    grad_xyz: np.ndarray
+    grad_t: np.ndarray | None
+    iters: int
+    arrival: float
+    admitted: float
+    done: float
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class ServeStats:
+    n: int
+    wall_s: float
+    solves_per_s: float
+    dof_per_s: float
+    p50_ms: float
+    p99_ms: float
+    mean_queue_ms: float
+    peak_inflight: int
+    peak_bytes: int
+    results: list = field(repr=False, default_factory=list)
+
+
+def run_one(req: Request, options: Options, stream=None, device="cuda") -> Result:
+    """Forward + adjoint of one request on ``stream`` (used by the loop and to check results
+    alone)."""
+    t0 = time.perf_counter()
+    with Problem(req.mesh, options, device=device, stream=stream) as p:
+        _, st = p.solve(check=False)
+        if p.last_status not in (0, -4):
+            raise RuntimeError(f"request {req.rid}: solve status {p.last_status}")
+        g = p.objective(req.objective)
+        gr = p.adjoint(req.objective)
+        gx = gr["dg_dxyz"].cpu().numpy()
+        gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
+    t1 = time.perf_counter()
+    return Result(req.rid, req.mesh.n_dof, g, gx, gt, st["iters"], 0.0, t0, t1)
+
+
+class Server:
+    """Admission by slot count and device-memory budget; one host thread and one HIP stream
+    per slot."""
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 64 << 30, options: Options | None = None,
+                 device="cuda"):
+        self.slots = slots
+        self.budget = hbm_budget
+        self.options = options or Options()
+        self.device = torch.device(device)
+        self.mixed = self.options.precision == 1
+
+    def run(self, requests: list[Request]) -> ServeStats:
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for r in reqs:
+            if footprint_bytes(r.mesh, self.mixed) > self.budget:
+                raise ValueError(f"request {r.rid} can never be admitted: footprint above budget")
+        cond = threading.Condition()
+        waiting = collections.deque()
+        results: list[Result] = []
+        state = dict(free=self.budget, inflight=0, peak_inflight=0, peak_bytes=0,
+                     arrived=0, finished=0, error=None)
+        t_start = time.perf_counter()
+
+        def clock():
+            return time.perf_counter() - t_start
+
+        def arrivals():
+            for r in reqs:
+                delay = r.arrival - clock()
+                if delay > 0:
+                    time.sleep(delay)
+                with cond:
+                    waiting.append(r)
+                    state["arrived"] += 1
+                    cond.notify_all()
+
+        def worker(stream):
+            while True:
+                with cond:
+                    while True:
+                        if state["error"] is not None:
+                            return
+                        if waiting and footprint_bytes(waiting[0].mesh, self.mixed) <= \
+                                state["free"]:
+                            req = waiting.popleft()
+                            need = footprint_bytes(req.mesh, self.mixed)
+                            state["free"] -= need
+                            state["inflight"] += 1
+                            state["peak_inflight"] = max(state["peak_inflight"],
+                                                         state["inflight"])
+                            state["peak_bytes"] = max(state["peak_bytes"],
+                                                      self.budget - state["free"])
+                            break
+                        if state["arrived"] == len(reqs) and not waiting:
+                            return
+                        cond.wait()
+                admitted = clock()
+                try:
+                    res = run_one(req, self.options, stream=stream, device=self.device)
+                except Exception as e:  # stop the loop, report the first failure
+                    with cond:
+                        state["error"] = e
+                        cond.notify_all()
+                    return
+                res.arrival, res.admitted, res.done = req.arrival, admitted, clock()
+                with cond:
+                    results.append(res)
+                    state["free"] += need
+                    state["inflight"] -= 1
+                    state["finished"] += 1
+                    cond.notify_all()
+
+        streams = [torch.cuda.Stream(device=self.device) for _ in range(self.slots)]
+        threads = [threading.Thread(target=worker, args=(s,), daemon=True) for s in streams]
+        feeder = threading.Thread(target=arrivals, daemon=True)
+        for t in threads:
+            t.start()
+        feeder.start()
+        feeder.join()
+        for t in threads:
+            t.join()
+        if state["error"] is not None:
+            raise state["error"]
+        wall = clock()
+        lat = np.array([r.latency for r in results])
+        dof = sum(r.n_dof for r in results)
+        return ServeStats(
+            n=len(results), wall_s=wall, solves_per_s=len(results) / wall, dof_per_s=dof / wall,
+            p50_ms=1000 * float(np.percentile(lat, 50)), p99_ms=1000 * float(np.percentile(lat, 99)),
+            mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
+            peak_inflight=state["peak_inflight"], peak_bytes=state["peak_bytes"],
+            results=sorted(results, key=lambda r: r.rid))
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 3) -> np.ndarray:
+    """Arrival times (s) of n requests of a Poisson process with the given rate (1/s)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
