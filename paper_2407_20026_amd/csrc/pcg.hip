@@ -219,7 +219,52 @@ k_pcg_init(int n_nodes, const T* b, T* x, T* r, T* z, T* p0, const T* Dinv, doub
   }
 }
 
-// Iteration j, first half: finish (rz_j, rr_j), decide, form p_j, Ap_j, partial pAp_j.
+// sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
+// not wait for beta): the direction's product is K p_new = Kz + beta Kp.
+template <class T>
+__device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
+                                    const int32_t* __restrict__ bcol, const T* __restrict__ K,
+                                    const T* __restrict__ z, const T* __restrict__ p, int I,
+                                    int a, int b, T& az, T& ap) {
+  using V = typename Vec2<T>::type;
+  const int rb = brow_ptr[I], re = brow_ptr[I + 1];
+  const int off = 6 * a + b;
+  T sz = 0, sp = 0;
+  int s = rb;
+  for (; s + 3 <= re; s += 3) {
+    const int64_t J0 = bcol[s], J1 = bcol[s + 1], J2 = bcol[s + 2];
+    const V k0 = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
+    const V k1 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 1) + off);
+    const V k2 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 2) + off);
+    const V z0 = *reinterpret_cast<const V*>(z + 6 * J0 + b);
+    const V z1 = *reinterpret_cast<const V*>(z + 6 * J1 + b);
+    const V z2 = *reinterpret_cast<const V*>(z + 6 * J2 + b);
+    const V p0 = *reinterpret_cast<const V*>(p + 6 * J0 + b);
+    const V p1 = *reinterpret_cast<const V*>(p + 6 * J1 + b);
+    const V p2 = *reinterpret_cast<const V*>(p + 6 * J2 + b);
+    sz += k0.x * z0.x + k0.y * z0.y;
+    sp += k0.x * p0.x + k0.y * p0.y;
+    sz += k1.x * z1.x + k1.y * z1.y;
+    sp += k1.x * p1.x + k1.y * p1.y;
+    sz += k2.x * z2.x + k2.y * z2.y;
+    sp += k2.x * p2.x + k2.y * p2.y;
+  }
+  for (; s < re; ++s) {
+    const int64_t J = bcol[s];
+    const V kv = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
+    const V zv = *reinterpret_cast<const V*>(z + 6 * J + b);
+    const V pv = *reinterpret_cast<const V*>(p + 6 * J + b);
+    sz += kv.x * zv.x + kv.y * zv.y;
+    sp += kv.x * pv.x + kv.y * pv.y;
+  }
+  az = sz;
+  ap = sp;
+}
+
+// Iteration j, first half: Ap_j = K z_j + beta_j K p_{j-1} and p_j = z_j + beta_j p_{j-1}
+// (own rows stored), partial p_j^T A p_j.  The first pass's products are issued before the
+// previous kernel's partials are finished (rz_j, rr_j -> convergence test, beta_j), so the
+// reduction overlaps the loads.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
@@ -227,48 +272,57 @@ k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
            const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ Ap,
            const double* __restrict__ pb, double* __restrict__ pa, PcgState* st) {
   if (st->done) return;
-  double tot[2];
-  finish_partials<2>(pb, gridDim.x, tot);
-  const double rz = tot[0], rr = tot[1];
-  const double ff = (j == 0) ? rr : st->ff;
-  const double beta_d = (j == 0) ? 0.0 : rz / st->rzs[(j - 1) & 1];
-  int stop = 0, status = SSO_OK;
-  if (!std::isfinite(rr) || !std::isfinite(rz)) {
-    stop = 1;
-    status = SSO_EBREAKDOWN;
-  } else if (rr <= st->rtol2 * ff) {
-    stop = 1;
-  } else if (j >= st->max_it) {
-    stop = 1;
-    status = SSO_ENOTCONV;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->rzs[j & 1] = rz;
-    st->rr = rr;
-    st->it = j;
-    if (j == 0) st->ff = rr;
-    if (stop) {
-      st->status = status;
-      st->done = 1;
-    }
-  }
-  if (stop) return;
-  const T beta = (T)beta_d;
   const SpLane L = sp_lane();
   const int wave = threadIdx.x >> 6;
-  T my = 0;
+  T beta = 0, my = 0;
   for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
     const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
     const bool ok = L.ok && I < n_nodes;
-    T acc = 0;
-    if (ok) acc = row_product<T, true>(brow_ptr, bcol, K, z, pold, beta, I, L.a, L.b);
-    const T sum = sum3(acc, L.lane);
+    T az = 0, ap = 0, zI = 0, pI = 0;
+    if (ok) {
+      row_product2<T>(brow_ptr, bcol, K, z, pold, I, L.a, L.b, az, ap);
+      if (L.b == 0) {
+        zI = z[6 * (int64_t)I + L.a];
+        pI = pold[6 * (int64_t)I + L.a];
+      }
+    }
+    if (gi == (int)blockIdx.x) {
+      double tot[2];
+      finish_partials<2>(pb, gridDim.x, tot);
+      const double rz = tot[0], rr = tot[1];
+      const double ff = (j == 0) ? rr : st->ff;
+      const double beta_d = (j == 0) ? 0.0 : rz / st->rzs[(j - 1) & 1];
+      int stop = 0, status = SSO_OK;
+      if (!std::isfinite(rr) || !std::isfinite(rz)) {
+        stop = 1;
+        status = SSO_EBREAKDOWN;
+      } else if (rr <= st->rtol2 * ff) {
+        stop = 1;
+      } else if (j >= st->max_it) {
+        stop = 1;
+        status = SSO_ENOTCONV;
+      }
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rzs[j & 1] = rz;
+        st->rr = rr;
+        st->it = j;
+        if (j == 0) st->ff = rr;
+        if (stop) {
+          st->status = status;
+          st->done = 1;
+        }
+      }
+      if (stop) return;
+      beta = (T)beta_d;
+    }
+    const T sz = sum3(az, L.lane), sp = sum3(ap, L.lane);
     if (ok && L.b == 0) {
       const int64_t d = 6 * (int64_t)I + L.a;
-      const T pn = z[d] + beta * pold[d];
+      const T pn = zI + beta * pI;
+      const T q = sz + beta * sp;
       pnew[d] = pn;
-      Ap[d] = sum;
-      my += pn * sum;
+      Ap[d] = q;
+      my += pn * q;
     }
   }
   T v[1] = {my};
@@ -277,7 +331,7 @@ k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
 }
 
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
-// partials of (rz_{j+1}, rr_{j+1}).
+// partials of (rz_{j+1}, rr_{j+1}).  The first pass's operands are loaded before the reduction.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_update(int n_nodes, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
@@ -285,26 +339,36 @@ k_update(int n_nodes, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict
          const double* __restrict__ pa, double* __restrict__ pb, PcgState* st) {
   __shared__ T rs[MAX_TPB];
   if (st->done) return;
-  double tot[1];
-  finish_partials<1>(pa, gridDim.x, tot);
-  const double pAp = tot[0];
-  const double alpha_d = st->rzs[j & 1] / pAp;
-  if (!(pAp > 0.0) || !std::isfinite(alpha_d)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->status = SSO_EBREAKDOWN;
-      st->done = 1;
-    }
-    return;
-  }
-  const T alpha = (T)alpha_d;
+  T alpha = 0;
   T v[2] = {0, 0};
   for (int gi = blockIdx.x; gi * VEC_NODES < n_nodes; gi += gridDim.x) {
     RowMap m = row_map_at(gi, n_nodes);
     const int64_t d = 6 * (int64_t)m.I + m.a;
+    T xv = 0, pv = 0, av = 0, rv = 0;
+    if (m.valid) {
+      xv = x[d];
+      pv = p[d];
+      av = Ap[d];
+      rv = r[d];
+    }
+    if (gi == (int)blockIdx.x) {
+      double tot[1];
+      finish_partials<1>(pa, gridDim.x, tot);
+      const double pAp = tot[0];
+      const double alpha_d = st->rzs[j & 1] / pAp;
+      if (!(pAp > 0.0) || !std::isfinite(alpha_d)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          st->status = SSO_EBREAKDOWN;
+          st->done = 1;
+        }
+        return;
+      }
+      alpha = (T)alpha_d;
+    }
     T rn = 0;
     if (m.valid) {
-      x[d] += alpha * p[d];
-      rn = r[d] - alpha * Ap[d];
+      x[d] = xv + alpha * pv;
+      rn = rv - alpha * av;
       r[d] = rn;
     }
     rs[threadIdx.x] = rn;
@@ -614,8 +678,12 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
       *status = SSO_ENOTCONV;
       return hipSuccess;
     }
+    // the inner solve only needs the reduction still missing (with a factor 2 of margin)
+    double tol_k = 0.5 * rtol * bn / rn;
+    if (tol_k < inner_rtol) tol_k = inner_rtol;
+    if (tol_k > 0.5) tol_k = 0.5;
     if ((e = pcg_run<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32,
-                            inner_rtol, left, w, s, &it, &st, profile_every)) != hipSuccess)
+                            tol_k, left, w, s, &it, &st, profile_every)) != hipSuccess)
       return e;
     *iters += it;
     ++*outer;
