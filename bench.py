@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the mixed-size served stream (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=32)
     return ap.parse_args()
 
 
@@ -71,6 +71,7 @@ def cpu_baseline(mesh, objective, budget_s):
         while True:
             oracle.analyze(mesh, objective, a=a)
             n += 1
+            log(f"cpu baseline: oracle analysis {n} done")
             el = time.perf_counter() - t0
             if el >= budget_s or el * (n + 1) / n > 1.5 * budget_s:
                 break
@@ -82,21 +83,28 @@ def cpu_baseline(mesh, objective, budget_s):
                       f"BLAS threads {cores}, host cpus {os.cpu_count()}"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def serve_bench(n, slots):
     """Mixed-size served stream: grid-shells (n x n nodes, n ~ U{8..60}) and shells (m x m quads,
-    m ~ U{10..120}) with per-request seeds, mixed precision, rtol 1e-8.  A closed-loop pass
-    measures the capacity; the timed pass uses Poisson arrivals at 0.8 x capacity."""
+    m ~ U{10..120}) with per-request seeds, FP64, rtol 1e-8, all requests in flight iterating
+    in shared multi-problem launches.  A closed-loop pass measures the capacity; the timed pass
+    uses Poisson arrivals at 0.8 x capacity."""
     import paper_2407_20026_amd as sso
-    from paper_2407_20026_amd.serve import Request, Server, poisson_arrivals
+    from paper_2407_20026_amd.serve import BatchedServer, Request, poisson_arrivals
     meshes = [meshgen.served_request(i) for i in range(n)]
-    opts = sso.Options(precision=sso.PREC_MIXED, rtol=1e-8)
-    srv = Server(slots=slots, options=opts)
-    n_cl = min(n, 48)
+    opts = sso.Options(rtol=1e-8)
+    srv = BatchedServer(slots=slots, options=opts)
+    n_cl = min(n, 64)
     cl = srv.run([Request(i, meshes[i], 0.0) for i in range(n_cl)])
+    log(f"serving closed loop: {cl.solves_per_s:.1f} solves/s")
     lam = 0.8 * cl.solves_per_s
     t = poisson_arrivals(n, lam, seed=3)
     st = srv.run([Request(i, meshes[i], float(t[i])) for i in range(n)])
-    return {"requests": st.n, "slots": slots, "precision": "mixed", "rtol": 1e-8,
+    log(f"serving Poisson stream: {st.solves_per_s:.1f} solves/s p99 {st.p99_ms:.1f} ms")
+    return {"requests": st.n, "slots": slots, "precision": "fp64", "rtol": 1e-8,
             "closed_loop_solves_per_s": cl.solves_per_s, "arrival_rate_per_s": lam,
             "solves_per_s": st.solves_per_s, "dof_per_s": st.dof_per_s,
             "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_queue_ms": st.mean_queue_ms,
@@ -142,8 +150,10 @@ def main():
             spmv_n.append(st["spmv_samples"])
         return st
 
+    log(f"{desc}: problem created")
     for _ in range(args.warmup):
         step()
+    log("warmup done")
     spmv_us.clear(); spmv_n.clear(); iters.clear(); resid.clear(); adj_iters.clear()
     lat = []
     torch.cuda.synchronize()
@@ -154,6 +164,7 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {1000 * el / args.steps:.2f} ms/step")
     ms = 1000.0 * el / args.steps
     rate = args.steps / el
     spmv_bytes = st["spmv_bytes"]

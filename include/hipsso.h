@@ -143,6 +143,25 @@ int sso_set_options(sso_problem* p, const sso_options* opts);
  * sso_objective / sso_adjoint may still be called), SSO_EBREAKDOWN, SSO_EHIP. */
 int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
 
+/* Forward analysis split for multi-problem launches: sso_solve_begin runs everything up to the
+ * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation;
+ * FP64 only, else SSO_EINVAL); sso_batch_iterate then advances many begun problems together;
+ * sso_solve_end finishes one (FP64 refinement of the true residual, u_out as in sso_solve,
+ * stats) once its iteration has stopped.  Results are bitwise the same as sso_solve's. */
+int sso_solve_begin(sso_problem* p);
+int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats);
+
+/* A multi-problem launcher bound to one stream.  Problems iterated together must have been
+ * created on that stream.  Callers: a request loop that keeps many problems in flight. */
+typedef struct sso_batch sso_batch;
+int sso_batch_create(hipStream_t stream, sso_batch** out);
+/* Launch n_iter PCG iterations for every problem of ps[0..n) whose iteration has not stopped,
+ * all problems in one launch per kernel, then read back their states: done[i] (host, may be
+ * NULL) = 1 when problem i's iteration has stopped (converged, limit or breakdown).
+ * Errors: SSO_EINVAL (problem not begun or on another stream), SSO_EHIP. */
+int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done);
+void sso_batch_destroy(sso_batch* b);
+
 /* Objective value of the last solve into *g_host (host): compliance f^T u, strain energy
  * f^T u / 2, or a^T u for SSO_OBJ_LINEAR (a: device [n_nodes][6]).  SSO_OBJ_USER: SSO_EINVAL.
  * Errors: SSO_EINVAL without a previous successful solve. */

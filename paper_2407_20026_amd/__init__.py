@@ -57,8 +57,9 @@ class sso_stats(ctypes.Structure):
 
 
 EXPORTS = ("sso_problem_create", "sso_problem_update", "sso_set_options", "sso_solve",
-           "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix", "sso_sizes",
-           "sso_strerror", "sso_problem_destroy")
+           "sso_solve_begin", "sso_solve_end", "sso_batch_create", "sso_batch_iterate",
+           "sso_batch_destroy", "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix",
+           "sso_sizes", "sso_strerror", "sso_problem_destroy")
 
 _lib = None
 _hip = None
@@ -83,12 +84,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 P(ctypes.c_int64)]
     lib.sso_matrix.argtypes = [_vp, _vp, _vp]
     lib.sso_sizes.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.sso_solve_begin.argtypes = [_vp]
+    lib.sso_solve_end.argtypes = [_vp, _vp, P(sso_stats)]
+    lib.sso_batch_create.argtypes = [_vp, P(_vp)]
+    lib.sso_batch_iterate.argtypes = [_vp, P(_vp), ctypes.c_int, ctypes.c_int,
+                                      P(ctypes.c_int32)]
+    lib.sso_batch_destroy.argtypes = [_vp]
+    lib.sso_batch_destroy.restype = None
     lib.sso_strerror.argtypes = [ctypes.c_int]
     lib.sso_strerror.restype = ctypes.c_char_p
     lib.sso_problem_destroy.argtypes = [_vp]
     lib.sso_problem_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("sso_strerror", "sso_problem_destroy"):
+        if name not in ("sso_strerror", "sso_problem_destroy", "sso_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -238,6 +246,21 @@ class Problem:
             _check(status, "sso_solve")
         return u_out, self.last_stats
 
+    def solve_begin(self):
+        """Everything up to the first PCG iteration; then iterate with :class:`Batch`."""
+        _check(load_library().sso_solve_begin(self.handle), "sso_solve_begin")
+
+    def solve_end(self, u_out: torch.Tensor | None = None, check: bool = True):
+        if u_out is None:
+            u_out = self._new((self.n_nodes, 6), torch.float64)
+        st = sso_stats()
+        status = load_library().sso_solve_end(self.handle, _ptr(u_out), ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        self.last_status = status
+        if check:
+            _check(status, "sso_solve_end")
+        return u_out, self.last_stats
+
     def objective(self, kind="compliance", a=None) -> float:
         g = ctypes.c_double()
         with torch.cuda.stream(self.stream):
@@ -286,3 +309,34 @@ class Problem:
         f = self._new((self.n_nodes, 6), torch.float64)
         _check(load_library().sso_matrix(self.handle, _ptr(vals), _ptr(f)), "sso_matrix")
         return vals, f
+
+
+class Batch:
+    """Multi-problem PCG launcher on one stream (``sso_batch_*``)."""
+
+    def __init__(self, stream=None, device="cuda"):
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _check(load_library().sso_batch_create(_stream_handle(self.stream), ctypes.byref(h)),
+               "sso_batch_create")
+        self.handle = h
+
+    def iterate(self, problems, n_iter: int):
+        """Advance every begun, unfinished problem by n_iter iterations; returns done flags."""
+        n = len(problems)
+        arr = (ctypes.c_void_p * max(n, 1))(*[p.handle for p in problems])
+        done = (ctypes.c_int32 * max(n, 1))()
+        _check(load_library().sso_batch_iterate(self.handle, arr, n, n_iter, done),
+               "sso_batch_iterate")
+        return [bool(done[i]) for i in range(n)]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sso_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -35,7 +35,14 @@ struct sso_problem {
   int32_t* perm = nullptr;
   int32_t* seg = nullptr;
   bool solved = false;
+  bool in_batch = false;        // started with sso_solve_begin, not yet finished
+  PcgDesc<double> desc{};       // its descriptor in multi-problem launches
   hipEvent_t ev[6] = {};
+};
+
+struct sso_batch {
+  hipStream_t s = nullptr;
+  BatchWork bw;
 };
 
 namespace {
@@ -307,6 +314,94 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available
   p->solved = (status == SSO_OK || status == SSO_ENOTCONV);
   return status;
+}
+
+int sso_solve_begin(sso_problem* p) {
+  if (!p) return SSO_EINVAL;
+  if (mixed(p)) return SSO_EINVAL;
+  hipStream_t s = p->s;
+  p->solved = false;
+  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
+  TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
+  TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
+  TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
+  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, nullptr, p->d_err, s));
+  int st = read_errors(p);
+  if (st != SSO_OK) return st;
+  TRY_HIP(pcg_begin(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it, p->w,
+                    s, &p->desc));
+  p->in_batch = true;
+  return SSO_OK;
+}
+
+int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
+  if (!p || !p->in_batch) return SSO_EINVAL;
+  hipStream_t s = p->s;
+  TRY_HIP(hipMemcpyAsync(p->w.h_st, p->w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
+  TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (u_out)
+    TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
+                           hipMemcpyDeviceToDevice, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  int status = p->w.h_st->done ? p->w.h_st->status : SSO_ENOTCONV;
+  int iters = p->w.h_st->it;
+  if (status == SSO_OK) {
+    TRY_HIP(pcg_correct(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it, p->w,
+                        s, &iters, &status));
+    TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
+    TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (u_out)
+      TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
+                             hipMemcpyDeviceToDevice, s));
+    TRY_HIP(hipStreamSynchronize(s));
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
+    stats->bytes_moved = solve_bytes(p, iters, 0);
+    stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
+  }
+  p->in_batch = false;
+  p->solved = (status == SSO_OK || status == SSO_ENOTCONV);
+  return status;
+}
+
+int sso_batch_create(hipStream_t stream, sso_batch** out) {
+  if (!out) return SSO_EINVAL;
+  sso_batch* b = new (std::nothrow) sso_batch();
+  if (!b) return SSO_ENOMEM;
+  b->s = stream;
+  *out = b;
+  return SSO_OK;
+}
+
+int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done) {
+  if (!b || (n > 0 && !ps) || n < 0 || n_iter < 0) return SSO_EINVAL;
+  std::vector<PcgDesc<double>> descs;
+  std::vector<int> idx;
+  descs.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    sso_problem* p = ps[i];
+    if (!p || !p->in_batch || p->s != b->s) return SSO_EINVAL;
+    if (p->w.h_st->done) continue;     // finished at an earlier poll
+    descs.push_back(p->desc);
+    idx.push_back(i);
+  }
+  if (!descs.empty())
+    TRY_HIP(pcg_batch_iterate(descs.data(), (int)descs.size(), n_iter, b->bw, b->s));
+  for (size_t k = 0; k < idx.size(); ++k) *ps[idx[k]]->w.h_st = b->bw.h_states[k];
+  if (done)
+    for (int i = 0; i < n; ++i) done[i] = ps[i]->w.h_st->done ? 1 : 0;
+  return SSO_OK;
+}
+
+void sso_batch_destroy(sso_batch* b) {
+  if (!b) return;
+  batch_free(b->bw, b->s);
+  (void)hipStreamSynchronize(b->s);
+  delete b;
 }
 
 int sso_objective(sso_problem* p, int kind, const double* a, double* g_host) {

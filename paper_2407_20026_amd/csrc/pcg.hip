@@ -17,8 +17,9 @@
 // Thread layouts: the SpMV kernels give 18 lanes to a block row, each lane reading one 16-byte
 // piece of every 6x6 block, so one load instruction covers a whole 288-byte block; the vector
 // kernels give 6 lanes to a node.  All kernels stride over the rows with a fixed number of
-// workgroups.  Every 64 iterations the residual is recomputed from x (residual replacement),
-// which keeps the recursively updated residual, and so the stopping test, honest.
+// workgroups.  The recursively updated residual can drift below the true one (rounding); the
+// FP64 driver therefore recomputes the true residual after convergence and, if it is above the
+// target, solves for a correction (a few steps of FP64 iterative refinement).
 #include <cmath>
 
 #include "sso_internal.h"
@@ -34,6 +35,23 @@ inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb
 template <class T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
+
+// Where a workgroup of a (possibly multi-problem) PCG launch works: its problem's descriptor,
+// its index among that problem's workgroups and their number.
+template <class T>
+struct Wg {
+  const PcgDesc<T>* d;
+  int lb, ng;
+};
+
+template <class T>
+__device__ inline Wg<T> wg_of(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  Wg<T> w;
+  w.d = D + (wg_prob ? wg_prob[blockIdx.x] : 0);
+  w.lb = (int)blockIdx.x - w.d->wg_base;
+  w.ng = w.d->n_wg;
+  return w;
+}
 
 // Fixed-order workgroup sum of NV values; the result is returned to every thread.
 template <int NV, class A>
@@ -66,9 +84,14 @@ __device__ inline void finish_partials(const double* partials, int n, double tot
 }
 
 template <int NV, class A>
-__device__ inline void write_partials(const A v[NV], double* partials) {
+__device__ inline void write_partials(const A v[NV], double* partials, int lb, int ng) {
   if (threadIdx.x == 0)
-    for (int k = 0; k < NV; ++k) partials[k * gridDim.x + blockIdx.x] = (double)v[k];
+    for (int k = 0; k < NV; ++k) partials[k * ng + lb] = (double)v[k];
+}
+
+template <int NV, class A>
+__device__ inline void write_partials(const A v[NV], double* partials) {
+  write_partials<NV, A>(v, partials, blockIdx.x, gridDim.x);
 }
 
 // ---- vector kernels: 6 consecutive lanes per node, 64 nodes per workgroup pass -----------
@@ -181,44 +204,6 @@ __device__ inline T sum3(T acc, int lane) {
   return acc + t1 + t2;
 }
 
-// x = 0, r = b, z = Dinv b, p_{-1} = 0; partials of r^T z, r^T r; reset the state record.
-template <class T>
-__global__ void __launch_bounds__(MAX_TPB)
-k_pcg_init(int n_nodes, const T* b, T* x, T* r, T* z, T* p0, const T* Dinv, double rtol,
-           int max_it, double* pb, PcgState* st) {
-  __shared__ T rs[MAX_TPB];
-  T v[2] = {0, 0};
-  for (int gi = blockIdx.x; gi * VEC_NODES < n_nodes; gi += gridDim.x) {
-    RowMap m = row_map_at(gi, n_nodes);
-    const int64_t d = 6 * (int64_t)m.I + m.a;
-    T rv = 0;
-    if (m.valid) {
-      rv = b[d];
-      x[d] = 0;
-      r[d] = rv;
-      p0[d] = 0;
-    }
-    rs[threadIdx.x] = rv;
-    __syncthreads();
-    if (m.valid) {
-      const T zz = apply_dinv(Dinv, rs, m.I, m.a, m.lr);
-      z[d] = zz;
-      v[0] += rv * zz;
-      v[1] += rv * rv;
-    }
-    __syncthreads();
-  }
-  block_sum<2, T>(v);
-  write_partials<2, T>(v, pb);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->rtol2 = rtol * rtol;
-    st->max_it = max_it;
-    st->it = 0;
-    st->done = 0;
-    st->status = SSO_OK;
-  }
-}
-
 // sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
 // not wait for beta): the direction's product is K p_new = Kz + beta Kp.
 template <class T>
@@ -261,34 +246,85 @@ __device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
   ap = sp;
 }
 
-// Iteration j, first half: Ap_j = K z_j + beta_j K p_{j-1} and p_j = z_j + beta_j p_{j-1}
-// (own rows stored), partial p_j^T A p_j.  The first pass's products are issued before the
-// previous kernel's partials are finished (rz_j, rr_j -> convergence test, beta_j), so the
-// reduction overlaps the loads.
+// x = 0, r = b, z = Dinv b, p_{-1} = 0; partials of r^T z, r^T r; reset the state record.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
-           const int32_t* __restrict__ bcol, const T* __restrict__ K, const T* __restrict__ z,
-           const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ Ap,
-           const double* __restrict__ pb, double* __restrict__ pa, PcgState* st) {
+k_pcg_init(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob, double rtol,
+           int max_it) {
+  __shared__ T rs[MAX_TPB];
+  const Wg<T> W = wg_of(D, wg_prob);
+  const PcgDesc<T>& d = *W.d;
+  const int n_nodes = d.n_nodes;
+  T v[2] = {0, 0};
+  for (int gi = W.lb; gi * VEC_NODES < n_nodes; gi += W.ng) {
+    RowMap m = row_map_at(gi, n_nodes);
+    const int64_t q = 6 * (int64_t)m.I + m.a;
+    T rv = 0;
+    if (m.valid) {
+      rv = d.b[q];
+      d.x[q] = 0;
+      d.r[q] = rv;
+      d.p[0][q] = 0;
+    }
+    rs[threadIdx.x] = rv;
+    __syncthreads();
+    if (m.valid) {
+      const T zz = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
+      d.z[q] = zz;
+      v[0] += rv * zz;
+      v[1] += rv * rv;
+    }
+    __syncthreads();
+  }
+  block_sum<2, T>(v);
+  write_partials<2, T>(v, d.pb, W.lb, W.ng);
+  if (W.lb == 0 && threadIdx.x == 0) {
+    PcgState* st = d.st;
+    st->rtol2 = rtol * rtol;
+    st->max_it = max_it;
+    st->it = 0;
+    st->jn = 0;
+    st->jc = 0;
+    st->done = 0;
+    st->status = SSO_OK;
+  }
+}
+
+// Iteration j (j read from the state), first half: Ap_j = K z_j + beta_j K p_{j-1} and
+// p_j = z_j + beta_j p_{j-1} (own rows stored), partial p_j^T A p_j.  The first pass's products
+// are issued before the previous kernel's partials are finished (rz_j, rr_j -> convergence
+// test, beta_j), so the reduction overlaps the loads.
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  const Wg<T> W = wg_of(D, wg_prob);
+  const PcgDesc<T>& d = *W.d;
+  PcgState* st = d.st;
   if (st->done) return;
+  const int j = st->jn;
+  const int n_nodes = d.n_nodes;
+  const T* __restrict__ K = d.K;
+  const T* __restrict__ z = d.z;
+  const T* __restrict__ pold = d.p[j & 1];
+  T* __restrict__ pnew = d.p[(j + 1) & 1];
+  T* __restrict__ Ap = d.Ap;
   const SpLane L = sp_lane();
   const int wave = threadIdx.x >> 6;
   T beta = 0, my = 0;
-  for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
+  for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
     const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
     const bool ok = L.ok && I < n_nodes;
     T az = 0, ap = 0, zI = 0, pI = 0;
     if (ok) {
-      row_product2<T>(brow_ptr, bcol, K, z, pold, I, L.a, L.b, az, ap);
+      row_product2<T>(d.brow_ptr, d.bcol, K, z, pold, I, L.a, L.b, az, ap);
       if (L.b == 0) {
         zI = z[6 * (int64_t)I + L.a];
         pI = pold[6 * (int64_t)I + L.a];
       }
     }
-    if (gi == (int)blockIdx.x) {
+    if (gi == W.lb) {
       double tot[2];
-      finish_partials<2>(pb, gridDim.x, tot);
+      finish_partials<2>(d.pb, W.ng, tot);
       const double rz = tot[0], rr = tot[1];
       const double ff = (j == 0) ? rr : st->ff;
       const double beta_d = (j == 0) ? 0.0 : rz / st->rzs[(j - 1) & 1];
@@ -302,10 +338,11 @@ k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
         stop = 1;
         status = SSO_ENOTCONV;
       }
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (W.lb == 0 && threadIdx.x == 0) {
         st->rzs[j & 1] = rz;
         st->rr = rr;
         st->it = j;
+        st->jc = j;
         if (j == 0) st->ff = rr;
         if (stop) {
           st->status = status;
@@ -317,47 +354,56 @@ k_spmv_dir(int n_nodes, int j, const int32_t* __restrict__ brow_ptr,
     }
     const T sz = sum3(az, L.lane), sp = sum3(ap, L.lane);
     if (ok && L.b == 0) {
-      const int64_t d = 6 * (int64_t)I + L.a;
+      const int64_t q = 6 * (int64_t)I + L.a;
       const T pn = zI + beta * pI;
-      const T q = sz + beta * sp;
-      pnew[d] = pn;
-      Ap[d] = q;
-      my += pn * q;
+      const T Apq = sz + beta * sp;
+      pnew[q] = pn;
+      Ap[q] = Apq;
+      my += pn * Apq;
     }
   }
   T v[1] = {my};
   block_sum<1, T>(v);
-  write_partials<1, T>(v, pa);
+  write_partials<1, T>(v, d.pa, W.lb, W.ng);
 }
 
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
-// partials of (rz_{j+1}, rr_{j+1}).  The first pass's operands are loaded before the reduction.
+// partials of (rz_{j+1}, rr_{j+1}); the state's next iteration index becomes j + 1.  The first
+// pass's operands are loaded before the reduction.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_update(int n_nodes, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
-         const T* __restrict__ p, const T* __restrict__ Ap, const T* __restrict__ Dinv,
-         const double* __restrict__ pa, double* __restrict__ pb, PcgState* st) {
+k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   __shared__ T rs[MAX_TPB];
+  const Wg<T> W = wg_of(D, wg_prob);
+  const PcgDesc<T>& d = *W.d;
+  PcgState* st = d.st;
   if (st->done) return;
+  const int j = st->jc;
+  const int n_nodes = d.n_nodes;
+  T* __restrict__ x = d.x;
+  T* __restrict__ r = d.r;
+  T* __restrict__ z = d.z;
+  const T* __restrict__ p = d.p[(j + 1) & 1];
+  const T* __restrict__ Ap = d.Ap;
   T alpha = 0;
   T v[2] = {0, 0};
-  for (int gi = blockIdx.x; gi * VEC_NODES < n_nodes; gi += gridDim.x) {
+  for (int gi = W.lb; gi * VEC_NODES < n_nodes; gi += W.ng) {
     RowMap m = row_map_at(gi, n_nodes);
-    const int64_t d = 6 * (int64_t)m.I + m.a;
+    const int64_t q = 6 * (int64_t)m.I + m.a;
     T xv = 0, pv = 0, av = 0, rv = 0;
     if (m.valid) {
-      xv = x[d];
-      pv = p[d];
-      av = Ap[d];
-      rv = r[d];
+      xv = x[q];
+      pv = p[q];
+      av = Ap[q];
+      rv = r[q];
     }
-    if (gi == (int)blockIdx.x) {
+    if (gi == W.lb) {
       double tot[1];
-      finish_partials<1>(pa, gridDim.x, tot);
+      finish_partials<1>(d.pa, W.ng, tot);
       const double pAp = tot[0];
       const double alpha_d = st->rzs[j & 1] / pAp;
       if (!(pAp > 0.0) || !std::isfinite(alpha_d)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (W.lb == 0 && threadIdx.x == 0) {
           st->status = SSO_EBREAKDOWN;
           st->done = 1;
         }
@@ -367,62 +413,23 @@ k_update(int n_nodes, int j, T* __restrict__ x, T* __restrict__ r, T* __restrict
     }
     T rn = 0;
     if (m.valid) {
-      x[d] = xv + alpha * pv;
+      x[q] = xv + alpha * pv;
       rn = rv - alpha * av;
-      r[d] = rn;
+      r[q] = rn;
     }
     rs[threadIdx.x] = rn;
     __syncthreads();
     if (m.valid) {
-      const T zz = apply_dinv(Dinv, rs, m.I, m.a, m.lr);
-      z[d] = zz;
+      const T zz = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
+      z[q] = zz;
       v[0] += rn * zz;
       v[1] += rn * rn;
     }
     __syncthreads();
   }
   block_sum<2, T>(v);
-  write_partials<2, T>(v, pb);
-}
-
-// Residual replacement: r = b - K x recomputed, z = Dinv r, partials of (r^T z, r^T r)
-// overwrite those of the preceding update, so the recursion keeps tracking the true residual.
-template <class T>
-__global__ void __launch_bounds__(MAX_TPB)
-k_replace(int n_nodes, const int32_t* __restrict__ brow_ptr, const int32_t* __restrict__ bcol,
-          const T* __restrict__ K, const T* __restrict__ x, const T* __restrict__ b,
-          T* __restrict__ r, T* __restrict__ z, const T* __restrict__ Dinv, double* pb,
-          const PcgState* st) {
-  __shared__ T rs[ROWS_PER_WG * 6];
-  if (st->done) return;
-  const SpLane L = sp_lane();
-  const int wave = threadIdx.x >> 6;
-  const int slot = wave * ROWS_PER_WAVE + L.g;   // node slot within the workgroup pass
-  T v[2] = {0, 0};
-  for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
-    const int I = gi * ROWS_PER_WG + slot;
-    const bool ok = L.ok && I < n_nodes;
-    T acc = 0;
-    if (ok) acc = row_product<T, false>(brow_ptr, bcol, K, x, x, (T)0, I, L.a, L.b);
-    const T sum = sum3(acc, L.lane);
-    T rv = 0;
-    if (ok && L.b == 0) {
-      const int64_t d = 6 * (int64_t)I + L.a;
-      rv = b[d] - sum;
-      r[d] = rv;
-      rs[6 * slot + L.a] = rv;
-    }
-    __syncthreads();
-    if (ok && L.b == 0) {
-      const T zz = apply_dinv(Dinv, rs, I, L.a, slot);
-      z[6 * (int64_t)I + L.a] = zz;
-      v[0] += rv * zz;
-      v[1] += rv * rv;
-    }
-    __syncthreads();
-  }
-  block_sum<2, T>(v);
-  write_partials<2, T>(v, pb);
+  write_partials<2, T>(v, d.pb, W.lb, W.ng);
+  if (W.lb == 0 && threadIdx.x == 0) st->jn = j + 1;
 }
 
 // r = b - K x; partials of ||r||^2 and ||b||^2.
@@ -475,6 +482,18 @@ __global__ void __launch_bounds__(256) k_finish(const double* partials, int n, i
     for (int k = 0; k < nv; ++k) out[k] = tot[k];
 }
 
+// Copy the state records of a multi-problem launch into one array (one read-back per poll).
+__global__ void k_gather_states(const PcgDesc<double>* D, int n, PcgState* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = *D[i].st;
+}
+
+// y += alpha x
+__global__ void k_axpy(int64_t n, double alpha, const double* x, double* y) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] += alpha * x[i];
+}
+
 __global__ void k_convert_f32(int64_t n, const double* in, float* out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -501,9 +520,6 @@ static int choose_wg(int64_t n_nodes) {
   return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
-// Residual replacement period (iterations).
-static constexpr int REPLACE_EVERY = 64;
-
 static int partial_stride(const PcgWork& w) { return w.n_wg > 1024 ? w.n_wg : 1024; }
 static double* part_a(PcgWork& w) { return w.partials; }
 static double* part_b(PcgWork& w) { return w.partials + partial_stride(w); }
@@ -518,10 +534,16 @@ hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
   if ((e = dev_alloc(&w.p[0], w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.p[1], w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.Ap, w.n_dof , s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.xc, w.n_dof, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.rc, w.n_dof, s)) != hipSuccess) return e;
   // partials: pA [stride], pB [2 stride], one-off reductions [2 stride] (+ 2 scalars)
   const size_t np = (size_t)partial_stride(w);
   if ((e = dev_alloc(&w.partials, (int64_t)(5 * np + 8), s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.st, 1, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(reinterpret_cast<PcgDesc<double>**>(&w.desc64), 1, s)) != hipSuccess)
+    return e;
+  if ((e = dev_alloc(reinterpret_cast<PcgDesc<float>**>(&w.desc32), 1, s)) != hipSuccess)
+    return e;
   if ((e = hipMemsetAsync(w.st, 0, sizeof(PcgState), s)) != hipSuccess) return e;
   w.h_st = new PcgState();
   if (mixed) return pcg_alloc_mixed(w, s);
@@ -544,6 +566,8 @@ hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s) {
 void pcg_free(PcgWork& w, hipStream_t s) {
   dev_free(w.r, s); dev_free(w.z, s); dev_free(w.p[0], s); dev_free(w.p[1], s);
   dev_free(w.Ap, s); dev_free(w.partials, s); dev_free(w.st, s);
+  dev_free(w.xc, s); dev_free(w.rc, s);
+  dev_free(w.desc64, s); dev_free(w.desc32, s);
   delete w.h_st;
   dev_free(w.r32, s); dev_free(w.z32, s); dev_free(w.p32[0], s); dev_free(w.p32[1], s);
   dev_free(w.Ap32, s); dev_free(w.x32, s); dev_free(w.b32, s);
@@ -563,13 +587,30 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
                           const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
                           int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
                           int profile_every) {
-  const int tpb = MAX_TPB, nwg = w.n_wg, n = m.n_nodes;
-  double* pa = part_a(w);
-  double* pb = part_b(w);
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, n, b, x, r, z, p[0], Dinv, rtol,
-                     max_it, pb, w.st);
-  hipError_t e = hipGetLastError();
+  const int tpb = MAX_TPB, nwg = w.n_wg;
+  PcgDesc<T> hd{};
+  hd.brow_ptr = pat.brow_ptr;
+  hd.bcol = pat.bcol;
+  hd.K = K;
+  hd.Dinv = Dinv;
+  hd.b = b;
+  hd.x = x;
+  hd.r = r;
+  hd.z = z;
+  hd.p[0] = p[0];
+  hd.p[1] = p[1];
+  hd.Ap = Ap;
+  hd.pa = part_a(w);
+  hd.pb = part_b(w);
+  hd.st = w.st;
+  hd.n_nodes = m.n_nodes;
+  hd.n_wg = nwg;
+  hd.wg_base = 0;
+  PcgDesc<T>* dd = reinterpret_cast<PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
+  hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr, rtol, max_it);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (profile_every > 0 && !w.prof_ev) {
     w.prof_ev = new hipEvent_t[2 * PROF_CAP];
     for (int i = 0; i < 2 * PROF_CAP; ++i)
@@ -582,21 +623,14 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
       const int64_t gk = launched + i;
-      const int j = (int)(gk < 0x7fffffff ? gk : 0x7fffffff);
-      const int k = (int)(gk & 1);
       const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
       if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
-      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, n, j, pat.brow_ptr, pat.bcol,
-                         K, z, p[k], p[k ^ 1], Ap, pb, pa, w.st);
+      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
       if (prof) {
         (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
         ++n_prof;
       }
-      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, n, j, x, r, z, p[k ^ 1], Ap,
-                         Dinv, pa, pb, w.st);
-      if ((gk + 1) % REPLACE_EVERY == 0)
-        hipLaunchKernelGGL(k_replace<T>, dim3(nwg), dim3(tpb), 0, s, n, pat.brow_ptr, pat.bcol, K,
-                           x, b, r, z, Dinv, pb, w.st);
+      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
     }
     launched += chunk;
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -621,13 +655,143 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   return hipSuccess;
 }
 
+hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                     hipStream_t s, PcgDesc<double>* desc) {
+  PcgDesc<double>& hd = *desc;
+  hd = PcgDesc<double>{};
+  hd.brow_ptr = pat.brow_ptr;
+  hd.bcol = pat.bcol;
+  hd.K = K;
+  hd.Dinv = Dinv;
+  hd.b = b;
+  hd.x = x;
+  hd.r = w.r;
+  hd.z = w.z;
+  hd.p[0] = w.p[0];
+  hd.p[1] = w.p[1];
+  hd.Ap = w.Ap;
+  hd.pa = part_a(w);
+  hd.pb = part_b(w);
+  hd.st = w.st;
+  hd.n_nodes = m.n_nodes;
+  hd.n_wg = w.n_wg;
+  hd.wg_base = 0;
+  PcgDesc<double>* dd = reinterpret_cast<PcgDesc<double>*>(w.desc64);
+  hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pcg_init<double>, dim3(w.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
+                     max_it);
+  w.h_st->done = 0;
+  return hipGetLastError();
+}
+
+hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, int n_iter, BatchWork& bw,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  // lay the problems' workgroups end to end
+  bw.h_desc.assign(descs, descs + n);
+  bw.h_wg.clear();
+  for (int i = 0; i < n; ++i) {
+    bw.h_desc[i].wg_base = (int)bw.h_wg.size();
+    for (int k = 0; k < bw.h_desc[i].n_wg; ++k) bw.h_wg.push_back(i);
+  }
+  const int total = (int)bw.h_wg.size();
+  hipError_t e;
+  if (n > bw.cap_desc) {
+    dev_free(bw.d_desc, s);
+    bw.cap_desc = 2 * n;
+    if ((e = dev_alloc(reinterpret_cast<PcgDesc<double>**>(&bw.d_desc), bw.cap_desc, s)) !=
+        hipSuccess)
+      return e;
+  }
+  if (total > bw.cap_wg) {
+    dev_free(bw.d_wg, s);
+    bw.cap_wg = 2 * total;
+    if ((e = dev_alloc(&bw.d_wg, bw.cap_wg, s)) != hipSuccess) return e;
+  }
+  PcgDesc<double>* dd = reinterpret_cast<PcgDesc<double>*>(bw.d_desc);
+  if ((e = hipMemcpyAsync(dd, bw.h_desc.data(), sizeof(PcgDesc<double>) * n,
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(bw.d_wg, bw.h_wg.data(), sizeof(int32_t) * total,
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  for (int i = 0; i < n_iter; ++i) {
+    hipLaunchKernelGGL(k_spmv_dir<double>, dim3(total), dim3(MAX_TPB), 0, s, dd, bw.d_wg);
+    hipLaunchKernelGGL(k_update<double>, dim3(total), dim3(MAX_TPB), 0, s, dd, bw.d_wg);
+    ++bw.launched;
+  }
+  if (n > bw.cap_states) {
+    dev_free(bw.d_states, s);
+    bw.cap_states = 2 * n;
+    if ((e = dev_alloc(&bw.d_states, bw.cap_states, s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_gather_states, dim3((n + 63) / 64), dim3(64), 0, s, dd, n, bw.d_states);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bw.h_states.resize(n);
+  if ((e = hipMemcpyAsync(bw.h_states.data(), bw.d_states, sizeof(PcgState) * n,
+                          hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(s);
+}
+
+void batch_free(BatchWork& bw, hipStream_t s) {
+  dev_free(bw.d_desc, s);
+  dev_free(bw.d_wg, s);
+  dev_free(bw.d_states, s);
+  bw = BatchWork();
+}
+
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
                      hipStream_t s, int* iters, int* status, int profile_every) {
   w.prof_us = 0.0;
   w.prof_n = 0;
-  return pcg_run<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w, s, iters,
-                         status, profile_every);
+  hipError_t e = pcg_run<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w, s,
+                                 iters, status, profile_every);
+  if (e != hipSuccess || *status != SSO_OK) return e;
+  return pcg_correct(m, pat, K, Dinv, b, x, rtol, max_it, w, s, iters, status);
+}
+
+// FP64 iterative refinement after a converged PCG: while the true residual b - K x is above
+// rtol |b| (the recursive residual drifted below it), solve K d = r for the missing reduction
+// and set x += d.  Stops when the target is met, refinement stalls (status SSO_ENOTCONV) or
+// after 3 steps.
+hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                       const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                       hipStream_t s, int* iters, int* status) {
+  hipError_t e;
+  double* scal = part_once(w) + 2 * (size_t)partial_stride(w);
+  double prev = -1.0;
+  for (int step = 0; step <= 3; ++step) {
+    if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, scal, s)) != hipSuccess) return e;
+    double h[2];
+    if ((e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const double rn = std::sqrt(h[0]), bn = std::sqrt(h[1]);
+    if (!(rn > rtol * bn)) {
+      *status = std::isfinite(rn) ? SSO_OK : SSO_EBREAKDOWN;
+      return hipSuccess;
+    }
+    if (step == 3 || (prev >= 0.0 && rn > 0.5 * prev) || *iters >= max_it) {
+      *status = SSO_ENOTCONV;
+      return hipSuccess;
+    }
+    prev = rn;
+    double tol_k = 0.5 * rtol * bn / rn;
+    if (tol_k > 0.5) tol_k = 0.5;
+    int it = 0, st = SSO_OK;
+    // correction d in w.Ap-free storage: solve into the second direction buffer's partner x2
+    if ((e = pcg_run<double>(m, pat, K, Dinv, w.r, w.xc, w.rc, w.z, w.p, w.Ap, tol_k,
+                             max_it - *iters, w, s, &it, &st, 0)) != hipSuccess)
+      return e;
+    *iters += it;
+    if ((e = launch_axpy(1.0, w.xc, x, w.n_dof, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // FP32 inner PCG (FP32 K, vectors, SpMV and workgroup accumulation) inside FP64 iterative
@@ -695,6 +859,11 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(nblk(n, 256)), dim3(256), 0, s, n, alpha, x, y);
+  return hipGetLastError();
 }
 
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "hipsso.h"
 
 namespace sso {
@@ -28,6 +30,28 @@ struct PcgState {
   int done;        // 1: stop (converged, breakdown, or limit)
   int status;      // SSO_OK, SSO_ENOTCONV, SSO_EBREAKDOWN
   int max_it;
+  int jn;          // index of the next iteration (written by the update kernel)
+  int jc;          // index of the iteration in flight (written by the SpMV kernel)
+};
+
+// One problem of a PCG launch: operands, work vectors, partial sums, state record, and its
+// range of workgroups in the launch.
+template <class T>
+struct PcgDesc {
+  const int32_t* brow_ptr;
+  const int32_t* bcol;
+  const T* K;
+  const T* Dinv;
+  const T* b;
+  T* x;
+  T* r;
+  T* z;
+  T* p[2];
+  T* Ap;
+  double* pa;
+  double* pb;
+  PcgState* st;
+  int n_nodes, n_wg, wg_base, pad;
 };
 
 // Block-level pattern (6x6 blocks, one block row per node).
@@ -136,6 +160,8 @@ struct PcgWork {
   double* z = nullptr;
   double* p[2] = {nullptr, nullptr};
   double* Ap = nullptr;
+  double* xc = nullptr;          // FP64 correction solve: solution and residual
+  double* rc = nullptr;
   double* partials = nullptr;   // per-workgroup partial sums (see pcg.hip)
   PcgState* st = nullptr;
   PcgState* h_st = nullptr;     // host mirror
@@ -146,6 +172,8 @@ struct PcgWork {
   float* Ap32 = nullptr;
   float* x32 = nullptr;
   float* b32 = nullptr;
+  void* desc64 = nullptr;        // device descriptors of single-problem launches
+  void* desc32 = nullptr;
   // sampled SpMV timing (HIP event pairs, created on first use)
   hipEvent_t* prof_ev = nullptr;
   int prof_cap = 0;
@@ -168,6 +196,34 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
                            hipStream_t s, int* iters, int* status, int* outer,
                            int profile_every);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);
+// FP64 refinement of a converged solve until the true residual meets rtol (see pcg.hip).
+hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                       const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                       hipStream_t s, int* iters, int* status);
+
+// Multi-problem iteration: problems started with pcg_begin advance together, one launch per
+// kernel for all of them (FP64).
+struct BatchWork {
+  void* d_desc = nullptr;
+  int cap_desc = 0;
+  int32_t* d_wg = nullptr;
+  int cap_wg = 0;
+  PcgState* d_states = nullptr;
+  int cap_states = 0;
+  std::vector<PcgDesc<double>> h_desc;
+  std::vector<int32_t> h_wg;
+  std::vector<PcgState> h_states;
+  int64_t launched = 0;
+};
+hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                     hipStream_t s, PcgDesc<double>* desc);
+// Launch n_iter iterations for the n problems, then copy their state records into
+// bw.h_states (synchronising the stream).
+hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, int n_iter, BatchWork& bw,
+                             hipStream_t s);
+void batch_free(BatchWork& bw, hipStream_t s);
 // Deterministic dot product a^T b; result written to *d_out (device).
 hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,
                       hipStream_t s);

@@ -1,15 +1,20 @@
-"""Continuous-batching request loop for forward + adjoint analyses of mixed-size structures.
+"""Continuous-batching request loops for forward + adjoint analyses of mixed-size structures.
 
 Requests (a structure and an objective) arrive over time.  A request is admitted as soon as a
-slot is free and its device-memory footprint fits in the remaining budget; admitted requests run
-concurrently, each on its own HIP stream, so their kernels overlap on the GPU; a finished request
-frees its slot and its memory at once and the next waiting request is admitted.  Per request the
-loop records arrival, admission and completion times, so p50/p99 latency (arrival to result)
-and throughput (solves/s, DOF/s) are reported side by side.
+slot is free and its device-memory footprint fits in the remaining budget; a finished request
+frees its slot and its memory at once and the next waiting request is admitted.  Per request
+the loops record arrival, admission and completion times, so p50/p99 latency (arrival to
+result) and throughput (solves/s, DOF/s) are reported side by side.
 
-Every number comes from the HIP library: each slot drives ``sso_problem_create``,
-``sso_solve``, ``sso_objective`` and ``sso_adjoint`` from a host thread (the C calls release the
-interpreter lock), K, the preconditioner and u stay on the device for the request's lifetime.
+* :class:`BatchedServer` -- one host thread and one stream: every admitted request's PCG
+  iterations run in shared launches (``sso_batch_iterate``: one launch per kernel for all
+  requests in flight, each request on its own range of workgroups); requests join and leave at
+  the chunk boundaries.
+* :class:`Server` -- one host thread and one HIP stream per slot, each slot solving its request
+  with ``sso_solve``; supports mixed precision.
+
+Every number comes from the HIP library; K, the preconditioner and u stay on the device for a
+request's lifetime.
 """
 from __future__ import annotations
 
@@ -189,6 +194,98 @@ class Server:
             p50_ms=1000 * float(np.percentile(lat, 50)), p99_ms=1000 * float(np.percentile(lat, 99)),
             mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
             peak_inflight=state["peak_inflight"], peak_bytes=state["peak_bytes"],
+            results=sorted(results, key=lambda r: r.rid))
+
+
+def finish_one(p: Problem, req: Request):
+    """Finish a request whose iteration has stopped: FP64 refinement, objective, adjoint."""
+    _, st = p.solve_end(check=False)
+    if p.last_status not in (0, -4):
+        raise RuntimeError(f"request {req.rid}: solve status {p.last_status}")
+    g = p.objective(req.objective)
+    gr = p.adjoint(req.objective)
+    gx = gr["dg_dxyz"].cpu().numpy()
+    gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
+    return g, gx, gt, st["iters"]
+
+
+class BatchedServer:
+    """Admission by slot count and device-memory budget; the iterations of all requests in
+    flight advance together in multi-problem launches on one stream."""
+
+    def __init__(self, slots: int = 64, hbm_budget: int = 64 << 30,
+                 options: Options | None = None, device="cuda", chunk: int = 32):
+        self.slots = slots
+        self.budget = hbm_budget
+        self.options = options or Options()
+        if self.options.precision != 0:
+            raise ValueError("multi-problem launches run the FP64 iteration")
+        self.device = torch.device(device)
+        self.chunk = chunk
+
+    def run(self, requests: list[Request]) -> ServeStats:
+        from . import Batch
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for r in reqs:
+            if footprint_bytes(r.mesh) > self.budget:
+                raise ValueError(f"request {r.rid} can never be admitted: footprint above budget")
+        stream = torch.cuda.Stream(device=self.device)
+        batch = Batch(stream, self.device)
+        waiting = collections.deque()
+        active = []          # (problem, request, admitted time, footprint)
+        results: list[Result] = []
+        free = self.budget
+        peak_inflight = peak_bytes = 0
+        nxt = 0
+        t_start = time.perf_counter()
+
+        def clock():
+            return time.perf_counter() - t_start
+
+        try:
+            while len(results) < len(reqs):
+                now = clock()
+                while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                    waiting.append(reqs[nxt])
+                    nxt += 1
+                while waiting and len(active) < self.slots and \
+                        footprint_bytes(waiting[0].mesh) <= free:
+                    req = waiting.popleft()
+                    need = footprint_bytes(req.mesh)
+                    free -= need
+                    p = Problem(req.mesh, self.options, device=self.device, stream=stream)
+                    p.solve_begin()
+                    active.append((p, req, clock(), need))
+                peak_inflight = max(peak_inflight, len(active))
+                peak_bytes = max(peak_bytes, self.budget - free)
+                if not active:
+                    if nxt < len(reqs):
+                        time.sleep(max(0.0, reqs[nxt].arrival - clock()))
+                    continue
+                done = batch.iterate([a[0] for a in active], self.chunk)
+                still = []
+                for flag, (p, req, adm, need) in zip(done, active):
+                    if not flag:
+                        still.append((p, req, adm, need))
+                        continue
+                    g, gx, gt, iters = finish_one(p, req)
+                    p.close()
+                    free += need
+                    results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
+                                          req.arrival, adm, clock()))
+                active = still
+        finally:
+            for p, *_ in active:
+                p.close()
+            batch.close()
+        wall = clock()
+        lat = np.array([r.latency for r in results])
+        dof = sum(r.n_dof for r in results)
+        return ServeStats(
+            n=len(results), wall_s=wall, solves_per_s=len(results) / wall, dof_per_s=dof / wall,
+            p50_ms=1000 * float(np.percentile(lat, 50)), p99_ms=1000 * float(np.percentile(lat, 99)),
+            mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
+            peak_inflight=peak_inflight, peak_bytes=peak_bytes,
             results=sorted(results, key=lambda r: r.rid))
 
 

@@ -45,6 +45,25 @@ def test_results_in_the_mix_equal_results_alone(precision):
           f"p99={stats.p99_ms:.2f} ms peak in flight={stats.peak_inflight}")
 
 
+def test_batched_loop_results_equal_results_alone():
+    """Multi-problem launches: each request keeps its own workgroup decomposition, so its
+    arithmetic, and its result, is bitwise that of the request solved alone."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import BatchedServer, run_one
+    print("[gpu] batched serve mix", flush=True)
+    opts = sso.Options(rtol=1e-10)
+    reqs = _requests(16, seed=7, rate=5000.0)
+    stats = BatchedServer(slots=8, options=opts, chunk=16).run(reqs)
+    assert stats.n == len(reqs)
+    assert stats.peak_inflight >= 4
+    for r, req in zip(stats.results, reqs):
+        alone = run_one(req, opts)
+        assert r.g == alone.g
+        assert np.array_equal(r.grad_xyz, alone.grad_xyz)
+    print(f"  solves/s={stats.solves_per_s:.1f} p50={stats.p50_ms:.2f} ms "
+          f"p99={stats.p99_ms:.2f} ms peak in flight={stats.peak_inflight}")
+
+
 def test_memory_budget_limits_admission():
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import Server, footprint_bytes
