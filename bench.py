@@ -6,8 +6,10 @@ coordinate, every shell thickness and every stiffness scale, for the 60 x 60 con
 (22,326 DOF, compliance; the adjoint of compliance is lambda = u, no second solve).  Inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
-The SpMV of the PCG (the dominant kernel) is timed live with HIP events on the problem's stream
-for every n-th launch; its roofline uses the algorithmic bytes of one launch.  The CPU baseline
+The dominant kernel of the PCG -- the fused pipelined iteration k_pipe_iter on problems up to
+40,000 nodes, the direction + SpMV kernel k_spmv_dir above -- is timed live with HIP events on
+the problem's stream for every n-th launch; its roofline uses the algorithmic bytes of one
+launch.  The CPU baseline
 is the FP64 oracle timed on the host on one forward + adjoint of the same workload.
 """
 from __future__ import annotations
@@ -47,6 +49,7 @@ def parse():
                     choices=["compliance", "strain_energy", "linear"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--solver", default="auto", choices=["auto", "standard", "pipelined"])
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -130,8 +133,10 @@ def main():
         a = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
         a[6 * (mesh.n_nodes // 2) + 2] = 1.0
     prec = sso.PREC_MIXED if args.precision == "mixed" else sso.PREC_FP64
+    solver = {"auto": sso.SOLVER_AUTO, "standard": sso.SOLVER_STANDARD,
+              "pipelined": sso.SOLVER_PIPELINED}[args.solver]
     opts = sso.Options(precision=prec, rtol=args.rtol, max_it=400000,
-                       profile_every=args.profile_every)
+                       profile_every=args.profile_every, solver=solver)
     prob = sso.Problem(mesh, opts)
     u_out = torch.empty((mesh.n_nodes, 6), dtype=torch.float64, device="cuda")
 
@@ -170,6 +175,9 @@ def main():
     spmv_bytes = st["spmv_bytes"]
     spmv_avg_us = sum(spmv_us) / max(1, sum(spmv_n))
     achieved = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9 if spmv_avg_us > 0 else 0.0
+    kernel = "k_pipe_iter" if st["solver"] == sso.SOLVER_PIPELINED else "k_spmv_dir"
+    solver_name = "pipelined" if st["solver"] == sso.SOLVER_PIPELINED else "standard"
+
     out = {
         "metric": METRIC,
         "value": rate,
@@ -187,11 +195,11 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32 inner / f64 refinement",
         "data": "synthetic (seeded generator)",
         "config": {"workload": desc, "n_dof": mesh.n_dof, "objective": args.objective,
-                   "rtol": args.rtol, "precision": args.precision,
+                   "rtol": args.rtol, "precision": args.precision, "pcg": solver_name,
                    "pcg_iters": int(np.median(iters)),
                    "adjoint_pcg_iters": int(np.median(adj_iters)),
                    "rel_residual": float(np.max(resid)), "n_blocks": prob.n_blocks},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_dir", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": spmv_bytes,
                      "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},

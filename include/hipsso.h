@@ -63,6 +63,11 @@ enum {
 
 enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
 
+/* PCG recurrences: standard (two kernels and two reductions per iteration) or pipelined
+ * (Ghysels & Vanroose: one kernel and one reduction per iteration, more vector traffic);
+ * AUTO takes the pipelined form for problems of up to 40,000 nodes. */
+enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_PIPELINED = 2 };
+
 /* Structure description.  Sec. 2.2.1 model-building API. */
 typedef struct {
   int32_t n_nodes;
@@ -93,6 +98,7 @@ typedef struct {
                                  HIP events on the problem's stream (stats.spmv_us)          */
   double inner_rtol;          /* mixed precision: relative tolerance of each FP32 inner PCG
                                  solve (0 = 1e-5)                                           */
+  int32_t solver;             /* SSO_SOLVER_*: recurrences of the FP64 solves                */
 } sso_options;
 
 typedef struct {
@@ -103,10 +109,13 @@ typedef struct {
   double t_solve_us;          /* PCG                                                         */
   double t_adj_us;            /* adjoint solve + element contraction + gather (sso_adjoint)  */
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
-  double spmv_us;             /* mean duration of the sampled SpMV launches (profile_every)  */
+  double spmv_us;             /* mean duration of the sampled SpMV launches (profile_every):
+                                 k_spmv_dir for the standard recurrences, the whole fused
+                                 iteration k_pipe_iter for the pipelined ones               */
   int32_t spmv_samples;       /* number of sampled SpMV launches                             */
-  double spmv_bytes;          /* algorithmic bytes of one SpMV launch                        */
+  double spmv_bytes;          /* algorithmic bytes of one such launch                        */
   int32_t refine_steps;       /* mixed precision: FP32 inner solves run                      */
+  int32_t solver;             /* SSO_SOLVER_STANDARD or _PIPELINED: recurrences that ran     */
 } sso_stats;
 
 typedef struct sso_problem sso_problem;

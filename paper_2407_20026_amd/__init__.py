@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libhipsso.so")
 SSO_OK, SSO_EINVAL, SSO_ENOMEM, SSO_EHIP, SSO_ENOTCONV, SSO_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 OBJ_COMPLIANCE, OBJ_STRAIN_ENERGY, OBJ_LINEAR, OBJ_USER = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
+SOLVER_AUTO, SOLVER_STANDARD, SOLVER_PIPELINED = 0, 1, 2
 
 OBJECTIVES = {"compliance": OBJ_COMPLIANCE, "strain_energy": OBJ_STRAIN_ENERGY,
               "linear": OBJ_LINEAR, "user": OBJ_USER}
@@ -41,7 +42,8 @@ class sso_mesh(ctypes.Structure):
 class sso_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("profile_every", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("profile_every", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("solver", ctypes.c_int32)]
 
 
 class sso_stats(ctypes.Structure):
@@ -50,7 +52,7 @@ class sso_stats(ctypes.Structure):
                 ("t_solve_us", ctypes.c_double), ("t_adj_us", ctypes.c_double),
                 ("bytes_moved", ctypes.c_double), ("spmv_us", ctypes.c_double),
                 ("spmv_samples", ctypes.c_int32), ("spmv_bytes", ctypes.c_double),
-                ("refine_steps", ctypes.c_int32)]
+                ("refine_steps", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -149,10 +151,11 @@ class Options:
     refine_steps: int = 20
     profile_every: int = 0
     inner_rtol: float = 0.0
+    solver: int = SOLVER_AUTO
 
     def c(self) -> sso_options:
         return sso_options(self.precision, self.rtol, self.max_it, self.refine_steps,
-                           self.profile_every, self.inner_rtol)
+                           self.profile_every, self.inner_rtol, self.solver)
 
 
 class Problem:

@@ -36,6 +36,7 @@ struct sso_problem {
   int32_t* seg = nullptr;
   bool solved = false;
   bool in_batch = false;        // started with sso_solve_begin, not yet finished
+  int solver_used = SSO_SOLVER_STANDARD;   // recurrences of the last solve
   PcgDesc<double> desc{};       // its descriptor in multi-problem launches
   hipEvent_t ev[6] = {};
 };
@@ -55,13 +56,14 @@ sso_options default_options() {
   o.refine_steps = 20;
   o.profile_every = 0;
   o.inner_rtol = 0.0;
+  o.solver = SSO_SOLVER_AUTO;
   return o;
 }
 
 bool options_ok(const sso_options& o) {
   return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED) && o.rtol >= 0.0 &&
          o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0 && o.inner_rtol >= 0.0 &&
-         o.inner_rtol < 1.0;
+         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_PIPELINED;
 }
 
 __global__ void k_fill(int64_t n, double v, double* out) {
@@ -244,9 +246,10 @@ bool mixed(const sso_problem* p) { return p->opt.precision == SSO_PREC_MIXED; }
 int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* outer) {
   int status = SSO_OK;
   *outer = 0;
+  p->solver_used = mixed(p) ? SSO_SOLVER_STANDARD : pcg_pick_solver(p->opt.solver, p->m.n_nodes);
   if (!mixed(p)) {
     TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, b, x, p->opt.rtol, p->opt.max_it, p->w, p->s,
-                      iters, &status, p->opt.profile_every));
+                      iters, &status, p->opt.profile_every, p->opt.solver));
   } else {
     const double inner = p->opt.inner_rtol > 0.0 ? p->opt.inner_rtol : 1e-5;
     TRY_HIP(pcg_solve_mixed(p->m, p->pat, p->K, p->K32, p->Dinv32, b, x, p->opt.rtol, inner,
@@ -256,8 +259,11 @@ int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* oute
   return status;
 }
 
+bool pipelined(const sso_problem* p) { return p->solver_used == SSO_SOLVER_PIPELINED; }
+
 double solve_bytes(const sso_problem* p, int iters, int outer) {
   const int64_t nn = p->m.n_nodes, nb = p->pat.n_blocks;
+  if (pipelined(p)) return iters * pipe_bytes_per_iteration(nn, nb);
   if (!mixed(p)) return iters * pcg_bytes_per_iteration(nn, nb, false);
   // inner FP32 iterations + one FP64 residual SpMV (K, x, b read; r written) per outer step
   double resid = 292.0 * nb + 4.0 * (nn + 1) + 3.0 * 8.0 * 6.0 * nn;
@@ -309,7 +315,10 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->bytes_moved = solve_bytes(p, iters, outer);
     stats->spmv_samples = p->w.prof_n;
     stats->spmv_us = p->w.prof_n ? p->w.prof_us / p->w.prof_n : 0.0;
-    stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, mixed(p));
+    stats->spmv_bytes = pipelined(p) ? pipe_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks)
+                                     : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks,
+                                                             mixed(p));
+    stats->solver = p->solver_used;
   }
   // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available
   p->solved = (status == SSO_OK || status == SSO_ENOTCONV);
@@ -321,6 +330,7 @@ int sso_solve_begin(sso_problem* p) {
   if (mixed(p)) return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
+  p->solver_used = SSO_SOLVER_STANDARD;
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
   TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
@@ -362,6 +372,7 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
     stats->bytes_moved = solve_bytes(p, iters, 0);
     stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->solver = p->solver_used;
   }
   p->in_batch = false;
   p->solved = (status == SSO_OK || status == SSO_ENOTCONV);

@@ -38,20 +38,24 @@ template <> struct Vec2<float> { using type = float2; };
 
 // Where a workgroup of a (possibly multi-problem) PCG launch works: its problem's descriptor,
 // its index among that problem's workgroups and their number.
-template <class T>
-struct Wg {
-  const PcgDesc<T>* d;
+template <class Desc>
+struct WgOf {
+  const Desc* d;
   int lb, ng;
 };
 
-template <class T>
-__device__ inline Wg<T> wg_of(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  Wg<T> w;
+template <class Desc>
+__device__ inline WgOf<Desc> wg_of(const Desc* __restrict__ D,
+                                   const int32_t* __restrict__ wg_prob) {
+  WgOf<Desc> w;
   w.d = D + (wg_prob ? wg_prob[blockIdx.x] : 0);
   w.lb = (int)blockIdx.x - w.d->wg_base;
   w.ng = w.d->n_wg;
   return w;
 }
+
+template <class T>
+using Wg = WgOf<PcgDesc<T>>;
 
 // Fixed-order workgroup sum of NV values; the result is returned to every thread.
 template <int NV, class A>
@@ -432,6 +436,187 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   if (W.lb == 0 && threadIdx.x == 0) st->jn = j + 1;
 }
 
+// ---- pipelined PCG (Ghysels & Vanroose): one kernel and one reduction per iteration --------
+//
+// With m_i = Dinv w_i available from the previous kernel, iteration i needs no other global
+// synchronisation: n_i = K m_i; z = n + beta z; q = m + beta q; s = w + beta s; p = u + beta p;
+// x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z; m_{i+1} = Dinv w_{i+1}; partials of
+// gamma = r.u, delta = w.u and r.r for the next iteration.  m and the partials are
+// double-buffered by iteration parity; every workgroup keeps its own iteration counter.
+
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_pipe_init1(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob, double rtol,
+             int max_it) {
+  __shared__ T rs[MAX_TPB];
+  const WgOf<PipeDesc<T>> W = wg_of(D, wg_prob);
+  const PipeDesc<T>& d = *W.d;
+  const int n_nodes = d.n_nodes;
+  for (int gi = W.lb; gi * VEC_NODES < n_nodes; gi += W.ng) {
+    RowMap m = row_map_at(gi, n_nodes);
+    const int64_t q = 6 * (int64_t)m.I + m.a;
+    T rv = 0;
+    if (m.valid) {
+      rv = d.b[q];
+      d.x[q] = 0;
+      d.r[q] = rv;
+      d.z[q] = 0;
+      d.q[q] = 0;
+      d.s[q] = 0;
+      d.p[q] = 0;
+    }
+    rs[threadIdx.x] = rv;
+    __syncthreads();
+    if (m.valid) d.u[q] = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.jw[W.lb] = 0;
+  if (W.lb == 0 && threadIdx.x == 0) {
+    PcgState* st = d.st;
+    st->rtol2 = rtol * rtol;
+    st->max_it = max_it;
+    st->it = 0;
+    st->done = 0;
+    st->status = SSO_OK;
+  }
+}
+
+// w_0 = K u_0, m_0 = Dinv w_0, partials of (r.u, w.u, r.r).
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_pipe_init2(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  __shared__ T ws[ROWS_PER_WG * 6];
+  const WgOf<PipeDesc<T>> W = wg_of(D, wg_prob);
+  const PipeDesc<T>& d = *W.d;
+  const int n_nodes = d.n_nodes;
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
+  const int slot = wave * ROWS_PER_WAVE + L.g;
+  T v[3] = {0, 0, 0};
+  for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
+    const int I = gi * ROWS_PER_WG + slot;
+    const bool ok = L.ok && I < n_nodes;
+    T acc = 0;
+    if (ok) acc = row_product<T, false>(d.brow_ptr, d.bcol, d.K, d.u, d.u, (T)0, I, L.a, L.b);
+    const T wv = sum3(acc, L.lane);
+    if (ok && L.b == 0) {
+      const int64_t q = 6 * (int64_t)I + L.a;
+      d.w[q] = wv;
+      ws[6 * slot + L.a] = wv;
+    }
+    __syncthreads();
+    if (ok && L.b == 0) {
+      const int64_t q = 6 * (int64_t)I + L.a;
+      d.m[0][q] = apply_dinv(d.Dinv, ws, I, L.a, slot);
+      const T rv = d.r[q], uv = d.u[q];
+      v[0] += rv * uv;
+      v[1] += wv * uv;
+      v[2] += rv * rv;
+    }
+    __syncthreads();
+  }
+  block_sum<3, T>(v);
+  write_partials<3, T>(v, d.pp[0], W.lb, W.ng);
+}
+
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_pipe_iter(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  __shared__ T ws[ROWS_PER_WG * 6];
+  const WgOf<PipeDesc<T>> W = wg_of(D, wg_prob);
+  const PipeDesc<T>& d = *W.d;
+  PcgState* st = d.st;
+  if (st->done) return;
+  const int i = d.jw[W.lb];
+  const int n_nodes = d.n_nodes;
+  const T* __restrict__ mi = d.m[i & 1];
+  T* __restrict__ mn = d.m[(i + 1) & 1];
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
+  const int slot = wave * ROWS_PER_WAVE + L.g;
+  T alpha = 0, beta = 0;
+  T v[3] = {0, 0, 0};
+  for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
+    const int I = gi * ROWS_PER_WG + slot;
+    const bool ok = L.ok && I < n_nodes;
+    T acc = 0;
+    if (ok) acc = row_product<T, false>(d.brow_ptr, d.bcol, d.K, mi, mi, (T)0, I, L.a, L.b);
+    if (gi == W.lb) {
+      double tot[3];
+      finish_partials<3>(d.pp[i & 1], W.ng, tot);
+      const double gam = tot[0], del = tot[1], rr = tot[2];
+      const double ff = (i == 0) ? rr : st->ff;
+      double beta_d = 0.0, alpha_d;
+      if (i == 0) {
+        alpha_d = gam / del;
+      } else {
+        beta_d = gam / st->rzs[(i - 1) & 1];
+        alpha_d = gam / (del - beta_d * gam / st->alphas[(i - 1) & 1]);
+      }
+      int stop = 0, status = SSO_OK;
+      if (!std::isfinite(rr) || !std::isfinite(gam)) {
+        stop = 1;
+        status = SSO_EBREAKDOWN;
+      } else if (rr <= st->rtol2 * ff) {
+        stop = 1;
+      } else if (i >= st->max_it) {
+        stop = 1;
+        status = SSO_ENOTCONV;
+      } else if (!(alpha_d > 0.0) || !std::isfinite(alpha_d)) {
+        stop = 1;
+        status = SSO_EBREAKDOWN;
+      }
+      if (W.lb == 0 && threadIdx.x == 0) {
+        st->rzs[i & 1] = gam;
+        st->alphas[i & 1] = alpha_d;
+        st->rr = rr;
+        st->it = i;
+        if (i == 0) st->ff = rr;
+        if (stop) {
+          st->status = status;
+          st->done = 1;
+        }
+      }
+      if (stop) return;
+      alpha = (T)alpha_d;
+      beta = (T)beta_d;
+    }
+    const T nv = sum3(acc, L.lane);
+    T wn = 0, rn = 0, un = 0;
+    if (ok && L.b == 0) {
+      const int64_t q = 6 * (int64_t)I + L.a;
+      const T zq = nv + beta * d.z[q];
+      const T qq = mi[q] + beta * d.q[q];
+      const T wv = d.w[q], uv = d.u[q];
+      const T sq = wv + beta * d.s[q];
+      const T pq = uv + beta * d.p[q];
+      d.z[q] = zq;
+      d.q[q] = qq;
+      d.s[q] = sq;
+      d.p[q] = pq;
+      d.x[q] += alpha * pq;
+      rn = d.r[q] - alpha * sq;
+      un = uv - alpha * qq;
+      wn = wv - alpha * zq;
+      d.r[q] = rn;
+      d.u[q] = un;
+      d.w[q] = wn;
+      ws[6 * slot + L.a] = wn;
+    }
+    __syncthreads();
+    if (ok && L.b == 0) {
+      mn[6 * (int64_t)I + L.a] = apply_dinv(d.Dinv, ws, I, L.a, slot);
+      v[0] += rn * un;
+      v[1] += wn * un;
+      v[2] += rn * rn;
+    }
+    __syncthreads();
+  }
+  block_sum<3, T>(v);
+  write_partials<3, T>(v, d.pp[(i + 1) & 1], W.lb, W.ng);
+  if (threadIdx.x == 0) d.jw[W.lb] = i + 1;
+}
+
 // r = b - K x; partials of ||r||^2 and ||b||^2.
 __global__ void __launch_bounds__(MAX_TPB)
 k_residual(int n_nodes, const int32_t* __restrict__ brow_ptr, const int32_t* __restrict__ bcol,
@@ -520,10 +705,17 @@ static int choose_wg(int64_t n_nodes) {
   return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
+// Partial-sum buffers (units of the stride S = max(n_wg, 1024) doubles):
+//   [0, S) pA | [S, 3S) pB | [3S, 5S) one-off reductions, then 8 scalars |
+//   [5S + 8, 8S + 8) pipelined even | [8S + 8, 11S + 8) pipelined odd
 static int partial_stride(const PcgWork& w) { return w.n_wg > 1024 ? w.n_wg : 1024; }
+static size_t partial_total(const PcgWork& w) { return 11 * (size_t)partial_stride(w) + 16; }
 static double* part_a(PcgWork& w) { return w.partials; }
 static double* part_b(PcgWork& w) { return w.partials + partial_stride(w); }
 static double* part_once(PcgWork& w) { return w.partials + 3 * (size_t)partial_stride(w); }
+static double* part_pipe(PcgWork& w, int k) {
+  return w.partials + (5 + 3 * k) * (size_t)partial_stride(w) + 8;
+}
 
 hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
   w.n_dof = 6 * n_nodes;
@@ -536,9 +728,7 @@ hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
   if ((e = dev_alloc(&w.Ap, w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.xc, w.n_dof, s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.rc, w.n_dof, s)) != hipSuccess) return e;
-  // partials: pA [stride], pB [2 stride], one-off reductions [2 stride] (+ 2 scalars)
-  const size_t np = (size_t)partial_stride(w);
-  if ((e = dev_alloc(&w.partials, (int64_t)(5 * np + 8), s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.partials, (int64_t)partial_total(w), s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.st, 1, s)) != hipSuccess) return e;
   if ((e = dev_alloc(reinterpret_cast<PcgDesc<double>**>(&w.desc64), 1, s)) != hipSuccess)
     return e;
@@ -567,6 +757,8 @@ void pcg_free(PcgWork& w, hipStream_t s) {
   dev_free(w.r, s); dev_free(w.z, s); dev_free(w.p[0], s); dev_free(w.p[1], s);
   dev_free(w.Ap, s); dev_free(w.partials, s); dev_free(w.st, s);
   dev_free(w.xc, s); dev_free(w.rc, s);
+  dev_free(w.pu, s); dev_free(w.pw, s); dev_free(w.pm[0], s); dev_free(w.pm[1], s);
+  dev_free(w.jw, s); dev_free(w.pdesc64, s);
   dev_free(w.desc64, s); dev_free(w.desc32, s);
   delete w.h_st;
   dev_free(w.r32, s); dev_free(w.z32, s); dev_free(w.p32[0], s); dev_free(w.p32[1], s);
@@ -743,13 +935,117 @@ void batch_free(BatchWork& bw, hipStream_t s) {
   bw = BatchWork();
 }
 
+// Problems up to this many nodes are latency-bound: the pipelined variant's single kernel per
+// iteration beats the two kernels of the standard recurrences there.
+static constexpr int64_t PIPE_MAX_NODES = 40000;
+
+int pcg_pick_solver(int solver, int64_t n_nodes) {
+  if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_PIPELINED) return solver;
+  return n_nodes <= PIPE_MAX_NODES ? SSO_SOLVER_PIPELINED : SSO_SOLVER_STANDARD;
+}
+
+static hipError_t pipe_alloc(PcgWork& w, hipStream_t s) {
+  if (w.pu) return hipSuccess;
+  hipError_t e;
+  if ((e = dev_alloc(&w.pu, w.n_dof, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.pw, w.n_dof, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.pm[0], w.n_dof, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.pm[1], w.n_dof, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.jw, w.n_wg, s)) != hipSuccess) return e;
+  return dev_alloc(reinterpret_cast<PipeDesc<double>**>(&w.pdesc64), 1, s);
+}
+
+// Pipelined PCG on (K, Dinv, b) -> x (FP64), polling the state every chunk; sampled launches of
+// the iteration kernel are timed into w.prof_us / w.prof_n.
+static hipError_t pipe_run(const Mesh& m, const Pattern& pat, const double* K,
+                           const double* Dinv, const double* b, double* x, double rtol,
+                           int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
+                           int profile_every) {
+  hipError_t e;
+  if ((e = pipe_alloc(w, s)) != hipSuccess) return e;
+  PipeDesc<double> hd{};
+  hd.brow_ptr = pat.brow_ptr;
+  hd.bcol = pat.bcol;
+  hd.K = K;
+  hd.Dinv = Dinv;
+  hd.b = b;
+  hd.x = x;
+  hd.r = w.r;
+  hd.u = w.pu;
+  hd.w = w.pw;
+  hd.z = w.z;
+  hd.q = w.p[1];
+  hd.s = w.Ap;
+  hd.p = w.p[0];
+  hd.m[0] = w.pm[0];
+  hd.m[1] = w.pm[1];
+  hd.pp[0] = part_pipe(w, 0);
+  hd.pp[1] = part_pipe(w, 1);
+  hd.jw = w.jw;
+  hd.st = w.st;
+  hd.n_nodes = m.n_nodes;
+  hd.n_wg = w.n_wg;
+  hd.wg_base = 0;
+  PipeDesc<double>* dd = reinterpret_cast<PipeDesc<double>*>(w.pdesc64);
+  if ((e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  const int nwg = w.n_wg;
+  hipLaunchKernelGGL(k_pipe_init1<double>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
+                     max_it);
+  hipLaunchKernelGGL(k_pipe_init2<double>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (profile_every > 0 && !w.prof_ev) {
+    w.prof_ev = new hipEvent_t[2 * PROF_CAP];
+    for (int i = 0; i < 2 * PROF_CAP; ++i)
+      if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
+    w.prof_cap = PROF_CAP;
+  }
+  int n_prof = 0;
+  int64_t launched = 0;
+  int chunk = 8;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      const int64_t gk = launched + i;
+      const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
+      if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
+      hipLaunchKernelGGL(k_pipe_iter<double>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+      if (prof) {
+        (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
+        ++n_prof;
+      }
+    }
+    launched += chunk;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (w.h_st->done || launched > (int64_t)max_it + 64) break;
+    chunk = chunk < 64 ? 2 * chunk : 64;
+  }
+  *iters = w.h_st->it;
+  *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
+  for (int i = 0; i < n_prof; ++i) {
+    if ((int64_t)i * profile_every >= *iters) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) {
+      w.prof_us += 1000.0 * ms;
+      ++w.prof_n;
+    }
+  }
+  return hipSuccess;
+}
+
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
-                     hipStream_t s, int* iters, int* status, int profile_every) {
+                     hipStream_t s, int* iters, int* status, int profile_every, int solver) {
   w.prof_us = 0.0;
   w.prof_n = 0;
-  hipError_t e = pcg_run<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w, s,
-                                 iters, status, profile_every);
+  hipError_t e;
+  if (pcg_pick_solver(solver, m.n_nodes) == SSO_SOLVER_PIPELINED)
+    e = pipe_run(m, pat, K, Dinv, b, x, rtol, max_it, w, s, iters, status, profile_every);
+  else
+    e = pcg_run<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w, s, iters,
+                        status, profile_every);
   if (e != hipSuccess || *status != SSO_OK) return e;
   return pcg_correct(m, pat, K, Dinv, b, x, rtol, max_it, w, s, iters, status);
 }
@@ -890,6 +1186,13 @@ hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double*
                      pat.bcol, K, x, b, r, part);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, w.n_wg, 2, d_out);
   return hipGetLastError();
+}
+
+double pipe_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks) {
+  const double n_dof = 6.0 * (double)n_nodes;
+  // K values + block columns + row pointers; m gathered; z, q, s, p, x, r, u, w read; Dinv;
+  // z, q, s, p, x, r, u, w and the new m written
+  return 292.0 * n_blocks + 4.0 * (n_nodes + 1) + (8.0 + 64.0 + 48.0 + 72.0) * n_dof;
 }
 
 double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed) {

@@ -23,6 +23,7 @@ enum : unsigned {
 // by the host between chunks of iterations).
 struct PcgState {
   double rzs[2];   // r_j^T z_j by iteration parity
+  double alphas[2];  // alpha_j by iteration parity (pipelined variant)
   double rr;       // r^T r of the last finished iteration
   double ff;       // ||rhs||^2
   double rtol2;    // rtol^2
@@ -50,6 +51,29 @@ struct PcgDesc {
   T* Ap;
   double* pa;
   double* pb;
+  PcgState* st;
+  int n_nodes, n_wg, wg_base, pad;
+};
+
+// One problem of a pipelined-PCG launch (one kernel and one reduction per iteration).
+template <class T>
+struct PipeDesc {
+  const int32_t* brow_ptr;
+  const int32_t* bcol;
+  const T* K;
+  const T* Dinv;
+  const T* b;
+  T* x;
+  T* r;
+  T* u;
+  T* w;
+  T* z;
+  T* q;
+  T* s;
+  T* p;
+  T* m[2];
+  double* pp[2];
+  int32_t* jw;      // per-workgroup iteration counters
   PcgState* st;
   int n_nodes, n_wg, wg_base, pad;
 };
@@ -162,6 +186,11 @@ struct PcgWork {
   double* Ap = nullptr;
   double* xc = nullptr;          // FP64 correction solve: solution and residual
   double* rc = nullptr;
+  double* pu = nullptr;          // pipelined variant: u, w, m[2] (allocated on first use)
+  double* pw = nullptr;
+  double* pm[2] = {nullptr, nullptr};
+  int32_t* jw = nullptr;
+  void* pdesc64 = nullptr;
   double* partials = nullptr;   // per-workgroup partial sums (see pcg.hip)
   PcgState* st = nullptr;
   PcgState* h_st = nullptr;     // host mirror
@@ -186,9 +215,12 @@ hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s);
 void pcg_free(PcgWork& w, hipStream_t s);
 // Solve K x = b (b already masked); x overwritten.  Returns SSO status via *status.
 // profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
+// solver: SSO_SOLVER_STANDARD or SSO_SOLVER_PIPELINED (SSO_SOLVER_AUTO picks by size).
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
-                     hipStream_t s, int* iters, int* status, int profile_every = 0);
+                     hipStream_t s, int* iters, int* status, int profile_every = 0,
+                     int solver = 0);
+int pcg_pick_solver(int solver, int64_t n_nodes);
 // FP32 inner PCG inside FP64 iterative refinement (residual recomputed with the FP64 K).
 hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
                            const float* Dinv32, const double* b, double* x, double rtol,
@@ -233,5 +265,6 @@ hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double*
                                 double* d_out, hipStream_t s);
 double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed);
 double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed);
+double pipe_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks);
 
 }  // namespace sso

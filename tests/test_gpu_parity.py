@@ -214,6 +214,29 @@ def test_bitwise_determinism(refs, name):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("solver", ["standard", "pipelined"])
+@pytest.mark.parametrize("name", ["grid11", "mixed", "shell60"])
+def test_both_recurrences(refs, name, solver):
+    """Standard and pipelined PCG recurrences, each chosen explicitly: u and the gradients at
+    the parity bars, the recurrence reported back, and two runs bitwise equal."""
+    sso = _sso()
+    mesh, _, r = refs(name)
+    code = {"standard": sso.SOLVER_STANDARD, "pipelined": sso.SOLVER_PIPELINED}[solver]
+    print(f"[gpu] recurrences {name} {solver}", flush=True)
+    outs = []
+    for _ in range(2):
+        with _problem(mesh, solver=code) as p:
+            u, st = _solve_tight(p)
+            g = p.adjoint("compliance")
+            outs.append((u.cpu().numpy().ravel(), g["dg_dxyz"].cpu().numpy()))
+        assert st["solver"] == code
+    u, gx = outs[0]
+    assert np.linalg.norm(u - r["u"]) / np.linalg.norm(r["u"]) <= 1e-10
+    assert _grad_err(gx, r["grad_xyz"]) <= 1e-8
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_update_changes_design_and_matches_fresh_problem():
     mesh = small_shell(6, seed=4)
     print("[gpu] update", flush=True)
