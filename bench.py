@@ -6,10 +6,10 @@ coordinate, every shell thickness and every stiffness scale, for the 60 x 60 con
 (22,326 DOF, compliance; the adjoint of compliance is lambda = u, no second solve).  Inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
-The dominant kernel of the PCG -- the fused pipelined iteration k_pipe_iter on problems up to
-40,000 nodes, the direction + SpMV kernel k_spmv_dir above -- is timed live with HIP events on
-the problem's stream for every n-th launch; its roofline uses the algorithmic bytes of one
-launch.  The CPU baseline
+The dominant kernel of the PCG -- k_cg1_iter, one whole single-reduction iteration (the
+default), or k_spmv_dir, the direction + SpMV kernel of the standard recurrences -- is timed live
+with HIP events on the problem's stream for every n-th launch; its roofline uses the algorithmic
+bytes of one launch.  The CPU baseline
 is the FP64 oracle timed on the host on one forward + adjoint of the same workload.
 """
 from __future__ import annotations
@@ -49,7 +49,7 @@ def parse():
                     choices=["compliance", "strain_energy", "linear"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--solver", default="auto", choices=["auto", "standard", "pipelined"])
+    ap.add_argument("--solver", default="auto", choices=["auto", "standard", "fused"])
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -134,7 +134,7 @@ def main():
         a[6 * (mesh.n_nodes // 2) + 2] = 1.0
     prec = sso.PREC_MIXED if args.precision == "mixed" else sso.PREC_FP64
     solver = {"auto": sso.SOLVER_AUTO, "standard": sso.SOLVER_STANDARD,
-              "pipelined": sso.SOLVER_PIPELINED}[args.solver]
+              "fused": sso.SOLVER_FUSED}[args.solver]
     opts = sso.Options(precision=prec, rtol=args.rtol, max_it=400000,
                        profile_every=args.profile_every, solver=solver)
     prob = sso.Problem(mesh, opts)
@@ -175,8 +175,8 @@ def main():
     spmv_bytes = st["spmv_bytes"]
     spmv_avg_us = sum(spmv_us) / max(1, sum(spmv_n))
     achieved = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9 if spmv_avg_us > 0 else 0.0
-    kernel = "k_pipe_iter" if st["solver"] == sso.SOLVER_PIPELINED else "k_spmv_dir"
-    solver_name = "pipelined" if st["solver"] == sso.SOLVER_PIPELINED else "standard"
+    kernel = "k_cg1_iter" if st["solver"] == sso.SOLVER_FUSED else "k_spmv_dir"
+    solver_name = "fused single-reduction" if st["solver"] == sso.SOLVER_FUSED else "standard"
 
     out = {
         "metric": METRIC,

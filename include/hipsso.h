@@ -63,10 +63,11 @@ enum {
 
 enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
 
-/* PCG recurrences: standard (two kernels and two reductions per iteration) or pipelined
- * (Ghysels & Vanroose: one kernel and one reduction per iteration, more vector traffic);
- * AUTO takes the pipelined form for problems of up to 40,000 nodes. */
-enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_PIPELINED = 2 };
+/* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
+ * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one
+ * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
+ * of K's size).  AUTO = FUSED. */
+enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */
 typedef struct {
@@ -98,7 +99,7 @@ typedef struct {
                                  HIP events on the problem's stream (stats.spmv_us)          */
   double inner_rtol;          /* mixed precision: relative tolerance of each FP32 inner PCG
                                  solve (0 = 1e-5)                                           */
-  int32_t solver;             /* SSO_SOLVER_*: recurrences of the FP64 solves                */
+  int32_t solver;             /* SSO_SOLVER_*: PCG recurrences (also of the FP32 inner solves) */
 } sso_options;
 
 typedef struct {
@@ -111,11 +112,11 @@ typedef struct {
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
   double spmv_us;             /* mean duration of the sampled SpMV launches (profile_every):
                                  k_spmv_dir for the standard recurrences, the whole fused
-                                 iteration k_pipe_iter for the pipelined ones               */
+                                 iteration k_cg1_iter for the single-reduction ones         */
   int32_t spmv_samples;       /* number of sampled SpMV launches                             */
   double spmv_bytes;          /* algorithmic bytes of one such launch                        */
   int32_t refine_steps;       /* mixed precision: FP32 inner solves run                      */
-  int32_t solver;             /* SSO_SOLVER_STANDARD or _PIPELINED: recurrences that ran     */
+  int32_t solver;             /* SSO_SOLVER_STANDARD or _FUSED: recurrences that ran         */
 } sso_stats;
 
 typedef struct sso_problem sso_problem;
@@ -137,7 +138,9 @@ int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_
 int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
                        const double* quad_scale);
 
-/* Replace solver options (host struct). */
+/* Replace solver options (host struct).  A change of precision or solver invalidates the last
+ * solution (sso_objective / sso_adjoint need a new sso_solve).  Errors: SSO_EINVAL for values
+ * outside their ranges. */
 int sso_set_options(sso_problem* p, const sso_options* opts);
 
 /* Forward analysis: element stiffness (beams: K = s T^T k T; quads: flat shell, K = s T^T W^T k

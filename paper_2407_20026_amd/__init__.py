@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libhipsso.so")
 SSO_OK, SSO_EINVAL, SSO_ENOMEM, SSO_EHIP, SSO_ENOTCONV, SSO_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 OBJ_COMPLIANCE, OBJ_STRAIN_ENERGY, OBJ_LINEAR, OBJ_USER = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
-SOLVER_AUTO, SOLVER_STANDARD, SOLVER_PIPELINED = 0, 1, 2
+SOLVER_AUTO, SOLVER_STANDARD, SOLVER_FUSED = 0, 1, 2
 
 OBJECTIVES = {"compliance": OBJ_COMPLIANCE, "strain_energy": OBJ_STRAIN_ENERGY,
               "linear": OBJ_LINEAR, "user": OBJ_USER}

@@ -17,6 +17,8 @@ struct sso_problem {
   double* qarea = nullptr;
   double* K = nullptr;
   double* Dinv = nullptr;
+  double* B = nullptr;          // K times the block-Jacobi inverse (single-reduction PCG)
+  float* B32 = nullptr;
   float* K32 = nullptr;         // mixed precision copies (allocated on first mixed solve)
   float* Dinv32 = nullptr;
   double* f = nullptr;
@@ -63,7 +65,7 @@ sso_options default_options() {
 bool options_ok(const sso_options& o) {
   return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED) && o.rtol >= 0.0 &&
          o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0 && o.inner_rtol >= 0.0 &&
-         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_PIPELINED;
+         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_FUSED;
 }
 
 __global__ void k_fill(int64_t n, double v, double* out) {
@@ -97,7 +99,7 @@ void free_problem(sso_problem* p) {
   for (void* q : {(void*)m.xyz, (void*)m.fixed, (void*)m.f_nodal, (void*)m.beam_nodes,
                   (void*)m.beam_prop, (void*)m.quad_nodes, (void*)m.quad_prop,
                   (void*)m.quad_scale, (void*)p->coo, (void*)p->qarea, (void*)p->K,
-                  (void*)p->Dinv, (void*)p->f, (void*)p->K32, (void*)p->Dinv32, (void*)p->u,
+                  (void*)p->Dinv, (void*)p->f, (void*)p->K32, (void*)p->Dinv32, (void*)p->B, (void*)p->B32, (void*)p->u,
                   (void*)p->lam, (void*)p->rhs, (void*)p->gbeam, (void*)p->gquad,
                   (void*)p->d_scal, (void*)p->d_err, (void*)p->row_ptr, (void*)p->col,
                   (void*)p->perm, (void*)p->seg})
@@ -232,6 +234,8 @@ int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
 
 int sso_set_options(sso_problem* p, const sso_options* opts) {
   if (!p || !opts || !options_ok(*opts)) return SSO_EINVAL;
+  // K32 / B / B32 are built by sso_solve for the precision and recurrences it runs with
+  if (opts->precision != p->opt.precision || opts->solver != p->opt.solver) p->solved = false;
   p->opt = *opts;
   return SSO_OK;
 }
@@ -241,29 +245,30 @@ int sso_set_options(sso_problem* p, const sso_options* opts) {
 namespace {
 
 bool mixed(const sso_problem* p) { return p->opt.precision == SSO_PREC_MIXED; }
+bool fused(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
 
 // Solve K x = b (b masked) in the problem's precision mode.
 int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* outer) {
   int status = SSO_OK;
   *outer = 0;
-  p->solver_used = mixed(p) ? SSO_SOLVER_STANDARD : pcg_pick_solver(p->opt.solver, p->m.n_nodes);
   if (!mixed(p)) {
-    TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, b, x, p->opt.rtol, p->opt.max_it, p->w, p->s,
-                      iters, &status, p->opt.profile_every, p->opt.solver));
+    TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, fused(p) ? p->B : nullptr, b, x, p->opt.rtol,
+                      p->opt.max_it, p->w, p->s, iters, &status, p->opt.profile_every));
   } else {
     const double inner = p->opt.inner_rtol > 0.0 ? p->opt.inner_rtol : 1e-5;
-    TRY_HIP(pcg_solve_mixed(p->m, p->pat, p->K, p->K32, p->Dinv32, b, x, p->opt.rtol, inner,
+    TRY_HIP(pcg_solve_mixed(p->m, p->pat, p->K, p->K32, p->Dinv32, fused(p) ? p->B32 : nullptr,
+                            b, x, p->opt.rtol, inner,
                             p->opt.max_it, p->opt.refine_steps, p->w, p->s, iters, &status,
                             outer, p->opt.profile_every));
   }
   return status;
 }
 
-bool pipelined(const sso_problem* p) { return p->solver_used == SSO_SOLVER_PIPELINED; }
+bool fused_used(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
 
 double solve_bytes(const sso_problem* p, int iters, int outer) {
   const int64_t nn = p->m.n_nodes, nb = p->pat.n_blocks;
-  if (pipelined(p)) return iters * pipe_bytes_per_iteration(nn, nb);
+  if (fused_used(p) && !mixed(p)) return iters * fused_bytes_per_iteration(nn, nb, false);
   if (!mixed(p)) return iters * pcg_bytes_per_iteration(nn, nb, false);
   // inner FP32 iterations + one FP64 residual SpMV (K, x, b read; r written) per outer step
   double resid = 292.0 * nb + 4.0 * (nn + 1) + 3.0 * 8.0 * 6.0 * nn;
@@ -282,6 +287,9 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
     TRY_HIP(dev_alloc(&p->K32, 36 * p->pat.n_blocks, s));
     TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
   }
+  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
+  if (fused(p) && !mixed(p) && !p->B) TRY_HIP(dev_alloc(&p->B, 36 * p->pat.n_blocks, s));
+  if (fused(p) && mixed(p) && !p->B32) TRY_HIP(dev_alloc(&p->B32, 36 * p->pat.n_blocks, s));
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(hipEventRecord(p->ev[0], s));
   TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
@@ -291,6 +299,9 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, mixed(p) ? p->Dinv32 : nullptr,
                               p->d_err, s));
   if (mixed(p)) TRY_HIP(launch_convert_f32(p->K, p->K32, 36 * p->pat.n_blocks, s));
+  if (fused(p))
+    TRY_HIP(launch_right_precondition(p->pat, p->K, p->Dinv, mixed(p) ? nullptr : p->B,
+                                      mixed(p) ? p->B32 : nullptr, s));
   TRY_HIP(hipEventRecord(p->ev[2], s));
   int st = read_errors(p);
   if (st != SSO_OK) return st;
@@ -315,9 +326,9 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->bytes_moved = solve_bytes(p, iters, outer);
     stats->spmv_samples = p->w.prof_n;
     stats->spmv_us = p->w.prof_n ? p->w.prof_us / p->w.prof_n : 0.0;
-    stats->spmv_bytes = pipelined(p) ? pipe_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks)
-                                     : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks,
-                                                             mixed(p));
+    stats->spmv_bytes = fused_used(p)
+                            ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
+                            : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, mixed(p));
     stats->solver = p->solver_used;
   }
   // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available

@@ -436,39 +436,98 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   if (W.lb == 0 && threadIdx.x == 0) st->jn = j + 1;
 }
 
-// ---- pipelined PCG (Ghysels & Vanroose): one kernel and one reduction per iteration --------
+// ---- single-reduction PCG (Chronopoulos & Gear): one kernel and one reduction per iteration --
 //
-// With m_i = Dinv w_i available from the previous kernel, iteration i needs no other global
-// synchronisation: n_i = K m_i; z = n + beta z; q = m + beta q; s = w + beta s; p = u + beta p;
-// x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z; m_{i+1} = Dinv w_{i+1}; partials of
-// gamma = r.u, delta = w.u and r.r for the next iteration.  m and the partials are
-// double-buffered by iteration parity; every workgroup keeps its own iteration counter.
+// The recurrences carry s = K p beside p, and w = K M r (M the block-Jacobi inverse) comes from
+// an SpMV with B = K M, which has the block pattern of K because M is block diagonal.  With
+// r_i, w_i, s_{i-1} stored and the partial sums of gamma_i = r_i.M r_i, delta_i = w_i.M r_i and
+// rho_i = r_i.r_i left by the previous launch, iteration i is
+//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta_i - beta gamma_i / alpha_{i-1})
+//   p_i = M r_i + beta p_{i-1};  s_i = w_i + beta s_{i-1};  x += alpha p_i;  r_{i+1} = r_i - alpha s_i
+//   w_{i+1} = B r_{i+1} = B r_i - alpha B w_i - alpha beta B s_{i-1}
+// and partials of gamma_{i+1}, delta_{i+1}, rho_{i+1}.  The three products of the last line use
+// stored vectors only, so no workgroup waits for another inside a launch; their loads are issued
+// before the previous partials are finished.  r, w, s and the partials are double-buffered by
+// iteration parity and every workgroup keeps its own iteration counter.
+
+// sum over the block row of B[s][a][b..b+1] . (r, w, t) (three accumulators).
+template <class T>
+__device__ inline void row_product3(const int32_t* __restrict__ brow_ptr,
+                                    const int32_t* __restrict__ bcol, const T* __restrict__ B,
+                                    const T* __restrict__ r, const T* __restrict__ w,
+                                    const T* __restrict__ t, int I, int a, int b, T& ar, T& aw,
+                                    T& at) {
+  using V = typename Vec2<T>::type;
+  const int rb = brow_ptr[I], re = brow_ptr[I + 1];
+  const int off = 6 * a + b;
+  T sr = 0, sw = 0, st = 0;
+  int s = rb;
+  for (; s + 2 <= re; s += 2) {
+    const int64_t J0 = bcol[s], J1 = bcol[s + 1];
+    const V k0 = *reinterpret_cast<const V*>(B + 36 * (int64_t)s + off);
+    const V k1 = *reinterpret_cast<const V*>(B + 36 * (int64_t)(s + 1) + off);
+    const V r0 = *reinterpret_cast<const V*>(r + 6 * J0 + b);
+    const V r1 = *reinterpret_cast<const V*>(r + 6 * J1 + b);
+    const V w0 = *reinterpret_cast<const V*>(w + 6 * J0 + b);
+    const V w1 = *reinterpret_cast<const V*>(w + 6 * J1 + b);
+    const V t0 = *reinterpret_cast<const V*>(t + 6 * J0 + b);
+    const V t1 = *reinterpret_cast<const V*>(t + 6 * J1 + b);
+    sr += k0.x * r0.x + k0.y * r0.y;
+    sw += k0.x * w0.x + k0.y * w0.y;
+    st += k0.x * t0.x + k0.y * t0.y;
+    sr += k1.x * r1.x + k1.y * r1.y;
+    sw += k1.x * w1.x + k1.y * w1.y;
+    st += k1.x * t1.x + k1.y * t1.y;
+  }
+  if (s < re) {
+    const int64_t J = bcol[s];
+    const V kv = *reinterpret_cast<const V*>(B + 36 * (int64_t)s + off);
+    const V rv = *reinterpret_cast<const V*>(r + 6 * J + b);
+    const V wv = *reinterpret_cast<const V*>(w + 6 * J + b);
+    const V tv = *reinterpret_cast<const V*>(t + 6 * J + b);
+    sr += kv.x * rv.x + kv.y * rv.y;
+    sw += kv.x * wv.x + kv.y * wv.y;
+    st += kv.x * tv.x + kv.y * tv.y;
+  }
+  ar = sr;
+  aw = sw;
+  at = st;
+}
+
+// Row a of the node's 6x6 block-Jacobi inverse applied to the 6 values at v.
+template <class T>
+struct DinvRow {
+  typename Vec2<T>::type d[3];
+  __device__ inline T apply(const T* v) const {
+    T z = 0;
+    for (int h = 0; h < 3; ++h) z += d[h].x * v[2 * h] + d[h].y * v[2 * h + 1];
+    return z;
+  }
+};
 
 template <class T>
+__device__ inline DinvRow<T> dinv_row(const T* Dinv, int I, int a) {
+  using V = typename Vec2<T>::type;
+  const V* dv = reinterpret_cast<const V*>(Dinv + 36 * (int64_t)I + 6 * a);
+  DinvRow<T> R;
+  for (int h = 0; h < 3; ++h) R.d[h] = dv[h];
+  return R;
+}
+
+// x = 0, p = 0, r_0 = b, s_{-1} = 0; iteration counters and the state record reset.
+template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_pipe_init1(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob, double rtol,
-             int max_it) {
-  __shared__ T rs[MAX_TPB];
-  const WgOf<PipeDesc<T>> W = wg_of(D, wg_prob);
-  const PipeDesc<T>& d = *W.d;
-  const int n_nodes = d.n_nodes;
-  for (int gi = W.lb; gi * VEC_NODES < n_nodes; gi += W.ng) {
-    RowMap m = row_map_at(gi, n_nodes);
-    const int64_t q = 6 * (int64_t)m.I + m.a;
-    T rv = 0;
-    if (m.valid) {
-      rv = d.b[q];
-      d.x[q] = 0;
-      d.r[q] = rv;
-      d.z[q] = 0;
-      d.q[q] = 0;
-      d.s[q] = 0;
-      d.p[q] = 0;
-    }
-    rs[threadIdx.x] = rv;
-    __syncthreads();
-    if (m.valid) d.u[q] = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
-    __syncthreads();
+k_cg1_init1(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob, double rtol,
+            int max_it) {
+  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
+  const FusedDesc<T>& d = *W.d;
+  const int64_t n_dof = 6 * (int64_t)d.n_nodes;
+  for (int64_t q = (int64_t)W.lb * MAX_TPB + threadIdx.x; q < n_dof;
+       q += (int64_t)W.ng * MAX_TPB) {
+    d.x[q] = 0;
+    d.p[q] = 0;
+    d.r[0][q] = d.b[q];
+    d.s[0][q] = 0;
   }
   if (threadIdx.x == 0) d.jw[W.lb] = 0;
   if (W.lb == 0 && threadIdx.x == 0) {
@@ -481,37 +540,37 @@ k_pipe_init1(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
   }
 }
 
-// w_0 = K u_0, m_0 = Dinv w_0, partials of (r.u, w.u, r.r).
+// w_0 = B r_0; partials of gamma_0 = r_0.M r_0, delta_0 = w_0.M r_0, rho_0 = r_0.r_0.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_pipe_init2(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  __shared__ T ws[ROWS_PER_WG * 6];
-  const WgOf<PipeDesc<T>> W = wg_of(D, wg_prob);
-  const PipeDesc<T>& d = *W.d;
+k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  __shared__ T rs[ROWS_PER_WG * 6];
+  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
+  const FusedDesc<T>& d = *W.d;
   const int n_nodes = d.n_nodes;
+  const T* __restrict__ r0 = d.r[0];
   const SpLane L = sp_lane();
-  const int wave = threadIdx.x >> 6;
-  const int slot = wave * ROWS_PER_WAVE + L.g;
+  const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
   T v[3] = {0, 0, 0};
   for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
     const int I = gi * ROWS_PER_WG + slot;
     const bool ok = L.ok && I < n_nodes;
-    T acc = 0;
-    if (ok) acc = row_product<T, false>(d.brow_ptr, d.bcol, d.K, d.u, d.u, (T)0, I, L.a, L.b);
+    const bool own = ok && L.b == 0;
+    const int64_t q = 6 * (int64_t)I + L.a;
+    T acc = 0, rq = 0;
+    if (ok) acc = row_product<T, false>(d.brow_ptr, d.bcol, d.B, r0, r0, (T)0, I, L.a, L.b);
     const T wv = sum3(acc, L.lane);
-    if (ok && L.b == 0) {
-      const int64_t q = 6 * (int64_t)I + L.a;
-      d.w[q] = wv;
-      ws[6 * slot + L.a] = wv;
+    if (own) {
+      rq = r0[q];
+      d.w[0][q] = wv;
+      rs[6 * slot + L.a] = rq;
     }
     __syncthreads();
-    if (ok && L.b == 0) {
-      const int64_t q = 6 * (int64_t)I + L.a;
-      d.m[0][q] = apply_dinv(d.Dinv, ws, I, L.a, slot);
-      const T rv = d.r[q], uv = d.u[q];
-      v[0] += rv * uv;
-      v[1] += wv * uv;
-      v[2] += rv * rv;
+    if (own) {
+      const T uq = dinv_row(d.Dinv, I, L.a).apply(rs + 6 * slot);
+      v[0] += rq * uq;
+      v[1] += wv * uq;
+      v[2] += rq * rq;
     }
     __syncthreads();
   }
@@ -521,31 +580,46 @@ k_pipe_init2(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
 
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
-k_pipe_iter(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  __shared__ T ws[ROWS_PER_WG * 6];
-  const WgOf<PipeDesc<T>> W = wg_of(D, wg_prob);
-  const PipeDesc<T>& d = *W.d;
+k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  __shared__ T rs[2][ROWS_PER_WG * 6];
+  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
+  const FusedDesc<T>& d = *W.d;
   PcgState* st = d.st;
   if (st->done) return;
   const int i = d.jw[W.lb];
   const int n_nodes = d.n_nodes;
-  const T* __restrict__ mi = d.m[i & 1];
-  T* __restrict__ mn = d.m[(i + 1) & 1];
+  const T* __restrict__ ri = d.r[i & 1];
+  const T* __restrict__ wi = d.w[i & 1];
+  const T* __restrict__ so = d.s[i & 1];
+  T* __restrict__ rn = d.r[(i + 1) & 1];
+  T* __restrict__ wn = d.w[(i + 1) & 1];
+  T* __restrict__ sn = d.s[(i + 1) & 1];
+  T* __restrict__ p = d.p;
+  T* __restrict__ x = d.x;
   const SpLane L = sp_lane();
-  const int wave = threadIdx.x >> 6;
-  const int slot = wave * ROWS_PER_WAVE + L.g;
-  T alpha = 0, beta = 0;
+  const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
+  T alpha = 0, beta = 0, ab = 0;
   T v[3] = {0, 0, 0};
   for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
     const int I = gi * ROWS_PER_WG + slot;
     const bool ok = L.ok && I < n_nodes;
-    T acc = 0;
-    if (ok) acc = row_product<T, false>(d.brow_ptr, d.bcol, d.K, mi, mi, (T)0, I, L.a, L.b);
+    const bool own = ok && L.b == 0;
+    const int64_t q = 6 * (int64_t)I + L.a;
+    T br = 0, bw = 0, bs = 0;
+    if (ok) row_product3<T>(d.brow_ptr, d.bcol, d.B, ri, wi, so, I, L.a, L.b, br, bw, bs);
+    T rq = 0, wq = 0, sq = 0, pq = 0, xq = 0;
+    if (own) {
+      rq = ri[q];
+      wq = wi[q];
+      sq = so[q];
+      pq = p[q];
+      xq = x[q];
+    }
     if (gi == W.lb) {
       double tot[3];
       finish_partials<3>(d.pp[i & 1], W.ng, tot);
-      const double gam = tot[0], del = tot[1], rr = tot[2];
-      const double ff = (i == 0) ? rr : st->ff;
+      const double gam = tot[0], del = tot[1], rho = tot[2];
+      const double ff = (i == 0) ? rho : st->ff;
       double beta_d = 0.0, alpha_d;
       if (i == 0) {
         alpha_d = gam / del;
@@ -554,10 +628,10 @@ k_pipe_iter(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
         alpha_d = gam / (del - beta_d * gam / st->alphas[(i - 1) & 1]);
       }
       int stop = 0, status = SSO_OK;
-      if (!std::isfinite(rr) || !std::isfinite(gam)) {
+      if (!std::isfinite(rho) || !std::isfinite(gam)) {
         stop = 1;
         status = SSO_EBREAKDOWN;
-      } else if (rr <= st->rtol2 * ff) {
+      } else if (rho <= st->rtol2 * ff) {
         stop = 1;
       } else if (i >= st->max_it) {
         stop = 1;
@@ -569,9 +643,9 @@ k_pipe_iter(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
       if (W.lb == 0 && threadIdx.x == 0) {
         st->rzs[i & 1] = gam;
         st->alphas[i & 1] = alpha_d;
-        st->rr = rr;
+        st->rr = rho;
         st->it = i;
-        if (i == 0) st->ff = rr;
+        if (i == 0) st->ff = rho;
         if (stop) {
           st->status = status;
           st->done = 1;
@@ -580,41 +654,53 @@ k_pipe_iter(const PipeDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
       if (stop) return;
       alpha = (T)alpha_d;
       beta = (T)beta_d;
+      ab = alpha * beta;
     }
-    const T nv = sum3(acc, L.lane);
-    T wn = 0, rn = 0, un = 0;
-    if (ok && L.b == 0) {
-      const int64_t q = 6 * (int64_t)I + L.a;
-      const T zq = nv + beta * d.z[q];
-      const T qq = mi[q] + beta * d.q[q];
-      const T wv = d.w[q], uv = d.u[q];
-      const T sq = wv + beta * d.s[q];
-      const T pq = uv + beta * d.p[q];
-      d.z[q] = zq;
-      d.q[q] = qq;
-      d.s[q] = sq;
-      d.p[q] = pq;
-      d.x[q] += alpha * pq;
-      rn = d.r[q] - alpha * sq;
-      un = uv - alpha * qq;
-      wn = wv - alpha * zq;
-      d.r[q] = rn;
-      d.u[q] = un;
-      d.w[q] = wn;
-      ws[6 * slot + L.a] = wn;
+    const T wv = sum3(br - alpha * bw - ab * bs, L.lane);
+    if (own) rs[0][6 * slot + L.a] = rq;
+    __syncthreads();
+    DinvRow<T> M{};
+    T rv = 0;
+    if (own) {
+      M = dinv_row(d.Dinv, I, L.a);
+      const T pv = M.apply(rs[0] + 6 * slot) + beta * pq;
+      const T sv = wq + beta * sq;
+      p[q] = pv;
+      sn[q] = sv;
+      x[q] = xq + alpha * pv;
+      rv = rq - alpha * sv;
+      rn[q] = rv;
+      wn[q] = wv;
+      rs[1][6 * slot + L.a] = rv;
     }
     __syncthreads();
-    if (ok && L.b == 0) {
-      mn[6 * (int64_t)I + L.a] = apply_dinv(d.Dinv, ws, I, L.a, slot);
-      v[0] += rn * un;
-      v[1] += wn * un;
-      v[2] += rn * rn;
+    if (own) {
+      const T uv = M.apply(rs[1] + 6 * slot);
+      v[0] += rv * uv;
+      v[1] += wv * uv;
+      v[2] += rv * rv;
     }
-    __syncthreads();
   }
   block_sum<3, T>(v);
   write_partials<3, T>(v, d.pp[(i + 1) & 1], W.lb, W.ng);
   if (threadIdx.x == 0) d.jw[W.lb] = i + 1;
+}
+
+// B = K M: block (I, J) of K times the block-Jacobi inverse of node J, one entry per thread.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_right_precondition(int64_t n_blocks, const int32_t* __restrict__ bcol,
+                     const double* __restrict__ K, const double* __restrict__ Dinv,
+                     T* __restrict__ B) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= 36 * n_blocks) return;
+  const int64_t s = e / 36;
+  const int ab = (int)(e - 36 * s), a = ab / 6, b = ab - 6 * a;
+  const double* k = K + 36 * s + 6 * a;
+  const double* m = Dinv + 36 * (int64_t)bcol[s] + b;
+  double acc = 0.0;
+  for (int c = 0; c < 6; ++c) acc += k[c] * m[6 * c];
+  B[e] = (T)acc;
 }
 
 // r = b - K x; partials of ||r||^2 and ||b||^2.
@@ -707,13 +793,13 @@ static int choose_wg(int64_t n_nodes) {
 
 // Partial-sum buffers (units of the stride S = max(n_wg, 1024) doubles):
 //   [0, S) pA | [S, 3S) pB | [3S, 5S) one-off reductions, then 8 scalars |
-//   [5S + 8, 8S + 8) pipelined even | [8S + 8, 11S + 8) pipelined odd
+//   [5S + 8, 8S + 8) single-reduction even | [8S + 8, 11S + 8) single-reduction odd
 static int partial_stride(const PcgWork& w) { return w.n_wg > 1024 ? w.n_wg : 1024; }
 static size_t partial_total(const PcgWork& w) { return 11 * (size_t)partial_stride(w) + 16; }
 static double* part_a(PcgWork& w) { return w.partials; }
 static double* part_b(PcgWork& w) { return w.partials + partial_stride(w); }
 static double* part_once(PcgWork& w) { return w.partials + 3 * (size_t)partial_stride(w); }
-static double* part_pipe(PcgWork& w, int k) {
+static double* part_fused(PcgWork& w, int k) {
   return w.partials + (5 + 3 * k) * (size_t)partial_stride(w) + 8;
 }
 
@@ -734,6 +820,11 @@ hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
     return e;
   if ((e = dev_alloc(reinterpret_cast<PcgDesc<float>**>(&w.desc32), 1, s)) != hipSuccess)
     return e;
+  if ((e = dev_alloc(reinterpret_cast<FusedDesc<double>**>(&w.fdesc64), 1, s)) != hipSuccess)
+    return e;
+  if ((e = dev_alloc(reinterpret_cast<FusedDesc<float>**>(&w.fdesc32), 1, s)) != hipSuccess)
+    return e;
+  if ((e = dev_alloc(&w.jw, w.n_wg, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(w.st, 0, sizeof(PcgState), s)) != hipSuccess) return e;
   w.h_st = new PcgState();
   if (mixed) return pcg_alloc_mixed(w, s);
@@ -757,8 +848,8 @@ void pcg_free(PcgWork& w, hipStream_t s) {
   dev_free(w.r, s); dev_free(w.z, s); dev_free(w.p[0], s); dev_free(w.p[1], s);
   dev_free(w.Ap, s); dev_free(w.partials, s); dev_free(w.st, s);
   dev_free(w.xc, s); dev_free(w.rc, s);
-  dev_free(w.pu, s); dev_free(w.pw, s); dev_free(w.pm[0], s); dev_free(w.pm[1], s);
-  dev_free(w.jw, s); dev_free(w.pdesc64, s);
+  dev_free(w.fw[0], s); dev_free(w.fw[1], s); dev_free(w.fw32[0], s); dev_free(w.fw32[1], s);
+  dev_free(w.jw, s); dev_free(w.fdesc64, s); dev_free(w.fdesc32, s);
   dev_free(w.desc64, s); dev_free(w.desc32, s);
   delete w.h_st;
   dev_free(w.r32, s); dev_free(w.z32, s); dev_free(w.p32[0], s); dev_free(w.p32[1], s);
@@ -772,8 +863,57 @@ void pcg_free(PcgWork& w, hipStream_t s) {
 
 static constexpr int PROF_CAP = 4096;
 
-// One PCG solve in precision T on (K, Dinv, b) -> x, polling the state every chunk.  Sampled
-// SpMV launches are bracketed with events and their durations added to w.prof_us / w.prof_n.
+// Launch iterations in chunks of growing size (8 .. 64), reading the state record back after
+// each chunk; launch(e0, e1) enqueues one iteration and, when e0 is not null, records e0 and e1
+// around the kernel that is profiled.  Launches past convergence return at entry.  The
+// sampled durations (launch index below the iteration count) go to w.prof_us / w.prof_n.
+template <class F>
+static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_every,
+                             const F& launch, int* iters, int* status) {
+  hipError_t e;
+  if (profile_every > 0 && !w.prof_ev) {
+    w.prof_ev = new hipEvent_t[2 * PROF_CAP];
+    for (int i = 0; i < 2 * PROF_CAP; ++i)
+      if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
+    w.prof_cap = PROF_CAP;
+  }
+  int n_prof = 0;
+  int64_t launched = 0;
+  int chunk = 8;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      const int64_t gk = launched + i;
+      const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
+      if (prof) {
+        launch(&w.prof_ev[2 * n_prof], &w.prof_ev[2 * n_prof + 1]);
+        ++n_prof;
+      } else {
+        launch(nullptr, nullptr);
+      }
+    }
+    launched += chunk;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (w.h_st->done || launched > (int64_t)max_it + 64) break;
+    chunk = chunk < 64 ? 2 * chunk : 64;
+  }
+  *iters = w.h_st->it;
+  *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
+  for (int i = 0; i < n_prof; ++i) {
+    if ((int64_t)i * profile_every >= *iters) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) {
+      w.prof_us += 1000.0 * ms;
+      ++w.prof_n;
+    }
+  }
+  return hipSuccess;
+}
+
+// One standard PCG solve in precision T on (K, Dinv, b) -> x; the SpMV kernel is profiled.
 template <class T>
 static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T* Dinv,
                           const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
@@ -803,46 +943,71 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr, rtol, max_it);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (profile_every > 0 && !w.prof_ev) {
-    w.prof_ev = new hipEvent_t[2 * PROF_CAP];
-    for (int i = 0; i < 2 * PROF_CAP; ++i)
-      if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
-    w.prof_cap = PROF_CAP;
+  auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
+    if (e0) (void)hipEventRecord(*e0, s);
+    hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
+    if (e1) (void)hipEventRecord(*e1, s);
+    hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
+  };
+  return run_polled(w, s, max_it, profile_every, launch, iters, status);
+}
+
+// Vectors of one single-reduction solve.
+template <class T>
+struct FusedBuffers {
+  T* x;
+  T* p;
+  T* r[2];
+  T* s[2];
+  T* w[2];
+};
+
+// One single-reduction PCG solve in precision T with B = K Dinv; the iteration kernel (the
+// whole iteration) is profiled.
+template <class T>
+static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const T* Dinv,
+                            const T* b, const FusedBuffers<T>& v, double rtol, int max_it,
+                            PcgWork& w, hipStream_t s, int* iters, int* status,
+                            int profile_every) {
+  const int nwg = w.n_wg;
+  FusedDesc<T> hd{};
+  hd.brow_ptr = pat.brow_ptr;
+  hd.bcol = pat.bcol;
+  hd.B = B;
+  hd.Dinv = Dinv;
+  hd.b = b;
+  hd.x = v.x;
+  hd.p = v.p;
+  for (int k = 0; k < 2; ++k) {
+    hd.r[k] = v.r[k];
+    hd.s[k] = v.s[k];
+    hd.w[k] = v.w[k];
+    hd.pp[k] = part_fused(w, k);
   }
-  int n_prof = 0;
-  int64_t launched = 0;
-  int chunk = 8;
-  for (;;) {
-    for (int i = 0; i < chunk; ++i) {
-      const int64_t gk = launched + i;
-      const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
-      if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
-      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
-      if (prof) {
-        (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
-        ++n_prof;
-      }
-      hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
-    }
-    launched += chunk;
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (w.h_st->done || launched > (int64_t)max_it + 64) break;
-    chunk = chunk < 64 ? 2 * chunk : 64;
-  }
-  *iters = w.h_st->it;
-  *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
-  // sampled launches with index < iterations did work (later ones returned at entry)
-  for (int i = 0; i < n_prof; ++i) {
-    if ((int64_t)i * profile_every >= *iters) break;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) {
-      w.prof_us += 1000.0 * ms;
-      ++w.prof_n;
-    }
+  hd.jw = w.jw;
+  hd.st = w.st;
+  hd.n_nodes = m.n_nodes;
+  hd.n_wg = nwg;
+  hd.wg_base = 0;
+  FusedDesc<T>* dd = reinterpret_cast<FusedDesc<T>*>(sizeof(T) == 8 ? w.fdesc64 : w.fdesc32);
+  hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cg1_init1<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol, max_it);
+  hipLaunchKernelGGL(k_cg1_init2<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
+    if (e0) (void)hipEventRecord(*e0, s);
+    hipLaunchKernelGGL(k_cg1_iter<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    if (e1) (void)hipEventRecord(*e1, s);
+  };
+  return run_polled(w, s, max_it, profile_every, launch, iters, status);
+}
+
+static hipError_t fused_alloc(PcgWork& w, bool f32, hipStream_t s) {
+  hipError_t e;
+  for (int k = 0; k < 2; ++k) {
+    if (!f32 && !w.fw[k] && (e = dev_alloc(&w.fw[k], w.n_dof, s)) != hipSuccess) return e;
+    if (f32 && !w.fw32[k] && (e = dev_alloc(&w.fw32[k], w.n_dof, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -935,117 +1100,39 @@ void batch_free(BatchWork& bw, hipStream_t s) {
   bw = BatchWork();
 }
 
-// Problems up to this many nodes are latency-bound: the pipelined variant's single kernel per
-// iteration beats the two kernels of the standard recurrences there.
-static constexpr int64_t PIPE_MAX_NODES = 40000;
-
 int pcg_pick_solver(int solver, int64_t n_nodes) {
-  if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_PIPELINED) return solver;
-  return n_nodes <= PIPE_MAX_NODES ? SSO_SOLVER_PIPELINED : SSO_SOLVER_STANDARD;
+  (void)n_nodes;
+  if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED) return solver;
+  return SSO_SOLVER_FUSED;
 }
 
-static hipError_t pipe_alloc(PcgWork& w, hipStream_t s) {
-  if (w.pu) return hipSuccess;
-  hipError_t e;
-  if ((e = dev_alloc(&w.pu, w.n_dof, s)) != hipSuccess) return e;
-  if ((e = dev_alloc(&w.pw, w.n_dof, s)) != hipSuccess) return e;
-  if ((e = dev_alloc(&w.pm[0], w.n_dof, s)) != hipSuccess) return e;
-  if ((e = dev_alloc(&w.pm[1], w.n_dof, s)) != hipSuccess) return e;
-  if ((e = dev_alloc(&w.jw, w.n_wg, s)) != hipSuccess) return e;
-  return dev_alloc(reinterpret_cast<PipeDesc<double>**>(&w.pdesc64), 1, s);
-}
-
-// Pipelined PCG on (K, Dinv, b) -> x (FP64), polling the state every chunk; sampled launches of
-// the iteration kernel are timed into w.prof_us / w.prof_n.
-static hipError_t pipe_run(const Mesh& m, const Pattern& pat, const double* K,
-                           const double* Dinv, const double* b, double* x, double rtol,
-                           int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
-                           int profile_every) {
-  hipError_t e;
-  if ((e = pipe_alloc(w, s)) != hipSuccess) return e;
-  PipeDesc<double> hd{};
-  hd.brow_ptr = pat.brow_ptr;
-  hd.bcol = pat.bcol;
-  hd.K = K;
-  hd.Dinv = Dinv;
-  hd.b = b;
-  hd.x = x;
-  hd.r = w.r;
-  hd.u = w.pu;
-  hd.w = w.pw;
-  hd.z = w.z;
-  hd.q = w.p[1];
-  hd.s = w.Ap;
-  hd.p = w.p[0];
-  hd.m[0] = w.pm[0];
-  hd.m[1] = w.pm[1];
-  hd.pp[0] = part_pipe(w, 0);
-  hd.pp[1] = part_pipe(w, 1);
-  hd.jw = w.jw;
-  hd.st = w.st;
-  hd.n_nodes = m.n_nodes;
-  hd.n_wg = w.n_wg;
-  hd.wg_base = 0;
-  PipeDesc<double>* dd = reinterpret_cast<PipeDesc<double>*>(w.pdesc64);
-  if ((e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
-  const int nwg = w.n_wg;
-  hipLaunchKernelGGL(k_pipe_init1<double>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
-                     max_it);
-  hipLaunchKernelGGL(k_pipe_init2<double>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (profile_every > 0 && !w.prof_ev) {
-    w.prof_ev = new hipEvent_t[2 * PROF_CAP];
-    for (int i = 0; i < 2 * PROF_CAP; ++i)
-      if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
-    w.prof_cap = PROF_CAP;
-  }
-  int n_prof = 0;
-  int64_t launched = 0;
-  int chunk = 8;
-  for (;;) {
-    for (int i = 0; i < chunk; ++i) {
-      const int64_t gk = launched + i;
-      const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
-      if (prof) (void)hipEventRecord(w.prof_ev[2 * n_prof], s);
-      hipLaunchKernelGGL(k_pipe_iter<double>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-      if (prof) {
-        (void)hipEventRecord(w.prof_ev[2 * n_prof + 1], s);
-        ++n_prof;
-      }
-    }
-    launched += chunk;
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (w.h_st->done || launched > (int64_t)max_it + 64) break;
-    chunk = chunk < 64 ? 2 * chunk : 64;
-  }
-  *iters = w.h_st->it;
-  *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
-  for (int i = 0; i < n_prof; ++i) {
-    if ((int64_t)i * profile_every >= *iters) break;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) {
-      w.prof_us += 1000.0 * ms;
-      ++w.prof_n;
-    }
-  }
-  return hipSuccess;
+hipError_t launch_right_precondition(const Pattern& pat, const double* K, const double* Dinv,
+                                     double* B, float* B32, hipStream_t s) {
+  const int64_t n = 36 * pat.n_blocks;
+  if (B)
+    hipLaunchKernelGGL(k_right_precondition<double>, dim3(nblk(n, 256)), dim3(256), 0, s,
+                       pat.n_blocks, pat.bcol, K, Dinv, B);
+  if (B32)
+    hipLaunchKernelGGL(k_right_precondition<float>, dim3(nblk(n, 256)), dim3(256), 0, s,
+                       pat.n_blocks, pat.bcol, K, Dinv, B32);
+  return hipGetLastError();
 }
 
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
-                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
-                     hipStream_t s, int* iters, int* status, int profile_every, int solver) {
+                     const double* B, const double* b, double* x, double rtol, int max_it,
+                     PcgWork& w, hipStream_t s, int* iters, int* status, int profile_every) {
   w.prof_us = 0.0;
   w.prof_n = 0;
   hipError_t e;
-  if (pcg_pick_solver(solver, m.n_nodes) == SSO_SOLVER_PIPELINED)
-    e = pipe_run(m, pat, K, Dinv, b, x, rtol, max_it, w, s, iters, status, profile_every);
-  else
+  if (B) {
+    if ((e = fused_alloc(w, false, s)) != hipSuccess) return e;
+    const FusedBuffers<double> v{x, w.p[0], {w.r, w.z}, {w.p[1], w.Ap}, {w.fw[0], w.fw[1]}};
+    e = fused_run<double>(m, pat, B, Dinv, b, v, rtol, max_it, w, s, iters, status,
+                          profile_every);
+  } else {
     e = pcg_run<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w, s, iters,
                         status, profile_every);
+  }
   if (e != hipSuccess || *status != SSO_OK) return e;
   return pcg_correct(m, pat, K, Dinv, b, x, rtol, max_it, w, s, iters, status);
 }
@@ -1094,12 +1181,14 @@ hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const
 // refinement: r = b - K x recomputed in FP64 with the FP64 K, the inner solve runs on r / |r|,
 // and x += |r| d in FP64, until |r| <= rtol |b| or refinement stalls.
 hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
-                           const float* Dinv32, const double* b, double* x, double rtol,
+                           const float* Dinv32, const float* B32, const double* b, double* x,
+                           double rtol,
                            double inner_rtol, int max_it, int refine_steps, PcgWork& w,
                            hipStream_t s, int* iters, int* status, int* outer,
                            int profile_every) {
   hipError_t e;
   if ((e = pcg_alloc_mixed(w, s)) != hipSuccess) return e;
+  if (B32 && (e = fused_alloc(w, true, s)) != hipSuccess) return e;
   const int64_t n = w.n_dof;
   w.prof_us = 0.0;
   w.prof_n = 0;
@@ -1142,9 +1231,16 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
     double tol_k = 0.5 * rtol * bn / rn;
     if (tol_k < inner_rtol) tol_k = inner_rtol;
     if (tol_k > 0.5) tol_k = 0.5;
-    if ((e = pcg_run<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32,
-                            tol_k, left, w, s, &it, &st, profile_every)) != hipSuccess)
-      return e;
+    if (B32) {
+      const FusedBuffers<float> v{w.x32, w.p32[0], {w.r32, w.z32}, {w.p32[1], w.Ap32},
+                                  {w.fw32[0], w.fw32[1]}};
+      e = fused_run<float>(m, pat, B32, Dinv32, w.b32, v, tol_k, left, w, s, &it, &st,
+                           profile_every);
+    } else {
+      e = pcg_run<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32, tol_k,
+                         left, w, s, &it, &st, profile_every);
+    }
+    if (e != hipSuccess) return e;
     *iters += it;
     ++*outer;
     if (st == SSO_EBREAKDOWN && it == 0) {
@@ -1188,11 +1284,11 @@ hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double*
   return hipGetLastError();
 }
 
-double pipe_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks) {
-  const double n_dof = 6.0 * (double)n_nodes;
-  // K values + block columns + row pointers; m gathered; z, q, s, p, x, r, u, w read; Dinv;
-  // z, q, s, p, x, r, u, w and the new m written
-  return 292.0 * n_blocks + 4.0 * (n_nodes + 1) + (8.0 + 64.0 + 48.0 + 72.0) * n_dof;
+double fused_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) {
+  const double n_dof = 6.0 * (double)n_nodes, v = mixed ? 4.0 : 8.0;
+  // B values + block columns + row pointers; r, w, s gathered; p, x read; Dinv (36 per node);
+  // p, x, s, r, w written
+  return (36.0 * v + 4.0) * n_blocks + 4.0 * (n_nodes + 1) + (3 + 2 + 6 + 5) * v * n_dof;
 }
 
 double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed) {

@@ -23,7 +23,7 @@ enum : unsigned {
 // by the host between chunks of iterations).
 struct PcgState {
   double rzs[2];   // r_j^T z_j by iteration parity
-  double alphas[2];  // alpha_j by iteration parity (pipelined variant)
+  double alphas[2];  // alpha_j by iteration parity (single-reduction variant)
   double rr;       // r^T r of the last finished iteration
   double ff;       // ||rhs||^2
   double rtol2;    // rtol^2
@@ -55,23 +55,19 @@ struct PcgDesc {
   int n_nodes, n_wg, wg_base, pad;
 };
 
-// One problem of a pipelined-PCG launch (one kernel and one reduction per iteration).
+// One problem of a single-reduction PCG launch (one kernel and one reduction per iteration).
 template <class T>
-struct PipeDesc {
+struct FusedDesc {
   const int32_t* brow_ptr;
   const int32_t* bcol;
-  const T* K;
+  const T* B;       // K times the block-Jacobi inverse, block layout of K
   const T* Dinv;
   const T* b;
   T* x;
-  T* r;
-  T* u;
-  T* w;
-  T* z;
-  T* q;
-  T* s;
   T* p;
-  T* m[2];
+  T* r[2];
+  T* w[2];
+  T* s[2];
   double* pp[2];
   int32_t* jw;      // per-workgroup iteration counters
   PcgState* st;
@@ -186,11 +182,11 @@ struct PcgWork {
   double* Ap = nullptr;
   double* xc = nullptr;          // FP64 correction solve: solution and residual
   double* rc = nullptr;
-  double* pu = nullptr;          // pipelined variant: u, w, m[2] (allocated on first use)
-  double* pw = nullptr;
-  double* pm[2] = {nullptr, nullptr};
-  int32_t* jw = nullptr;
-  void* pdesc64 = nullptr;
+  double* fw[2] = {nullptr, nullptr};    // single-reduction variant: w = B r (on first use)
+  float* fw32[2] = {nullptr, nullptr};
+  int32_t* jw = nullptr;                  // per-workgroup iteration counters
+  void* fdesc64 = nullptr;
+  void* fdesc32 = nullptr;
   double* partials = nullptr;   // per-workgroup partial sums (see pcg.hip)
   PcgState* st = nullptr;
   PcgState* h_st = nullptr;     // host mirror
@@ -215,15 +211,21 @@ hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s);
 void pcg_free(PcgWork& w, hipStream_t s);
 // Solve K x = b (b already masked); x overwritten.  Returns SSO status via *status.
 // profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
-// solver: SSO_SOLVER_STANDARD or SSO_SOLVER_PIPELINED (SSO_SOLVER_AUTO picks by size).
+// B = K Dinv (launch_right_precondition) selects the single-reduction recurrences, B = nullptr
+// the standard ones.
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
-                     const double* b, double* x, double rtol, int max_it, PcgWork& w,
-                     hipStream_t s, int* iters, int* status, int profile_every = 0,
-                     int solver = 0);
+                     const double* B, const double* b, double* x, double rtol, int max_it,
+                     PcgWork& w, hipStream_t s, int* iters, int* status, int profile_every = 0);
+// SSO_SOLVER_STANDARD or SSO_SOLVER_FUSED for an sso_options.solver value.
 int pcg_pick_solver(int solver, int64_t n_nodes);
-// FP32 inner PCG inside FP64 iterative refinement (residual recomputed with the FP64 K).
+// B = K Dinv block by block (B32: the same rounded to FP32); either may be null.
+hipError_t launch_right_precondition(const Pattern& pat, const double* K, const double* Dinv,
+                                     double* B, float* B32, hipStream_t s);
+// FP32 inner PCG inside FP64 iterative refinement (residual recomputed with the FP64 K); the
+// inner solves use the single-reduction recurrences when B32 is given.
 hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
-                           const float* Dinv32, const double* b, double* x, double rtol,
+                           const float* Dinv32, const float* B32, const double* b, double* x,
+                           double rtol,
                            double inner_rtol, int max_it, int refine_steps, PcgWork& w,
                            hipStream_t s, int* iters, int* status, int* outer,
                            int profile_every);
@@ -265,6 +267,6 @@ hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double*
                                 double* d_out, hipStream_t s);
 double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed);
 double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed);
-double pipe_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks);
+double fused_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed);
 
 }  // namespace sso

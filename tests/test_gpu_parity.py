@@ -214,14 +214,14 @@ def test_bitwise_determinism(refs, name):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("solver", ["standard", "pipelined"])
+@pytest.mark.parametrize("solver", ["standard", "fused"])
 @pytest.mark.parametrize("name", ["grid11", "mixed", "shell60"])
 def test_both_recurrences(refs, name, solver):
-    """Standard and pipelined PCG recurrences, each chosen explicitly: u and the gradients at
-    the parity bars, the recurrence reported back, and two runs bitwise equal."""
+    """Standard and single-reduction (fused) PCG recurrences, each chosen explicitly: u and the
+    gradients at the parity bars, the recurrence reported back, and two runs bitwise equal."""
     sso = _sso()
     mesh, _, r = refs(name)
-    code = {"standard": sso.SOLVER_STANDARD, "pipelined": sso.SOLVER_PIPELINED}[solver]
+    code = {"standard": sso.SOLVER_STANDARD, "fused": sso.SOLVER_FUSED}[solver]
     print(f"[gpu] recurrences {name} {solver}", flush=True)
     outs = []
     for _ in range(2):
