@@ -168,9 +168,10 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats);
 typedef struct sso_batch sso_batch;
 int sso_batch_create(hipStream_t stream, sso_batch** out);
 /* Launch n_iter PCG iterations for every problem of ps[0..n) whose iteration has not stopped,
- * all problems in one launch per kernel, then read back their states: done[i] (host, may be
- * NULL) = 1 when problem i's iteration has stopped (converged, limit or breakdown).
- * Errors: SSO_EINVAL (problem not begun or on another stream), SSO_EHIP. */
+ * all problems of one recurrence kind (sso_options.solver at sso_solve_begin) in one launch per
+ * kernel, then read back their states: done[i] (host, may be NULL) = 1 when problem i's
+ * iteration has stopped (converged, limit or breakdown).  Errors: SSO_EINVAL (problem not
+ * begun, on another stream, or listed twice), SSO_EHIP. */
 int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done);
 void sso_batch_destroy(sso_batch* b);
 

@@ -39,7 +39,8 @@ struct sso_problem {
   bool solved = false;
   bool in_batch = false;        // started with sso_solve_begin, not yet finished
   int solver_used = SSO_SOLVER_STANDARD;   // recurrences of the last solve
-  PcgDesc<double> desc{};       // its descriptor in multi-problem launches
+  PcgDesc<double> desc{};       // its descriptor in multi-problem launches (standard / fused)
+  FusedDesc<double> fdesc{};
   hipEvent_t ev[6] = {};
 };
 
@@ -341,16 +342,22 @@ int sso_solve_begin(sso_problem* p) {
   if (mixed(p)) return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
-  p->solver_used = SSO_SOLVER_STANDARD;
+  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
+  if (fused(p) && !p->B) TRY_HIP(dev_alloc(&p->B, 36 * p->pat.n_blocks, s));
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
   TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
   TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
   TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, nullptr, p->d_err, s));
+  if (fused(p)) TRY_HIP(launch_right_precondition(p->pat, p->K, p->Dinv, p->B, nullptr, s));
   int st = read_errors(p);
   if (st != SSO_OK) return st;
-  TRY_HIP(pcg_begin(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it, p->w,
-                    s, &p->desc));
+  if (fused(p))
+    TRY_HIP(fused_begin(p->m, p->pat, p->B, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it,
+                        p->w, s, &p->fdesc));
+  else
+    TRY_HIP(pcg_begin(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it,
+                      p->w, s, &p->desc));
   p->in_batch = true;
   return SSO_OK;
 }
@@ -382,7 +389,8 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->iters = iters;
     stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
     stats->bytes_moved = solve_bytes(p, iters, 0);
-    stats->spmv_bytes = spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->spmv_bytes = fused(p) ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false)
+                                 : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
     stats->solver = p->solver_used;
   }
   p->in_batch = false;
@@ -402,18 +410,31 @@ int sso_batch_create(hipStream_t stream, sso_batch** out) {
 int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done) {
   if (!b || (n > 0 && !ps) || n < 0 || n_iter < 0) return SSO_EINVAL;
   std::vector<PcgDesc<double>> descs;
-  std::vector<int> idx;
-  descs.reserve(n);
+  std::vector<FusedDesc<double>> fdescs;
+  std::vector<int> idx, fidx;
   for (int i = 0; i < n; ++i) {
     sso_problem* p = ps[i];
     if (!p || !p->in_batch || p->s != b->s) return SSO_EINVAL;
-    if (p->w.h_st->done) continue;     // finished at an earlier poll
-    descs.push_back(p->desc);
-    idx.push_back(i);
+    for (int k = 0; k < i; ++k)
+      if (ps[k] == p) return SSO_EINVAL;   // a problem listed twice would advance twice
   }
-  if (!descs.empty())
-    TRY_HIP(pcg_batch_iterate(descs.data(), (int)descs.size(), n_iter, b->bw, b->s));
+  for (int i = 0; i < n; ++i) {
+    sso_problem* p = ps[i];
+    if (p->w.h_st->done) continue;     // finished at an earlier poll
+    if (fused(p)) {
+      fdescs.push_back(p->fdesc);
+      fidx.push_back(i);
+    } else {
+      descs.push_back(p->desc);
+      idx.push_back(i);
+    }
+  }
+  if (!descs.empty() || !fdescs.empty())
+    TRY_HIP(pcg_batch_iterate(descs.data(), (int)descs.size(), fdescs.data(), (int)fdescs.size(),
+                              n_iter, b->bw, b->s));
   for (size_t k = 0; k < idx.size(); ++k) *ps[idx[k]]->w.h_st = b->bw.h_states[k];
+  for (size_t k = 0; k < fidx.size(); ++k)
+    *ps[fidx[k]]->w.h_st = b->bw.h_states[idx.size() + k];
   if (done)
     for (int i = 0; i < n; ++i) done[i] = ps[i]->w.h_st->done ? 1 : 0;
   return SSO_OK;

@@ -754,9 +754,9 @@ __global__ void __launch_bounds__(256) k_finish(const double* partials, int n, i
 }
 
 // Copy the state records of a multi-problem launch into one array (one read-back per poll).
-__global__ void k_gather_states(const PcgDesc<double>* D, int n, PcgState* out) {
+__global__ void k_gather_states(PcgState* const* st, int n, PcgState* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = *D[i].st;
+  if (i < n) out[i] = *st[i];
 }
 
 // y += alpha x
@@ -962,14 +962,9 @@ struct FusedBuffers {
   T* w[2];
 };
 
-// One single-reduction PCG solve in precision T with B = K Dinv; the iteration kernel (the
-// whole iteration) is profiled.
 template <class T>
-static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const T* Dinv,
-                            const T* b, const FusedBuffers<T>& v, double rtol, int max_it,
-                            PcgWork& w, hipStream_t s, int* iters, int* status,
-                            int profile_every) {
-  const int nwg = w.n_wg;
+static FusedDesc<T> fused_desc(const Mesh& m, const Pattern& pat, const T* B, const T* Dinv,
+                               const T* b, const FusedBuffers<T>& v, PcgWork& w) {
   FusedDesc<T> hd{};
   hd.brow_ptr = pat.brow_ptr;
   hd.bcol = pat.bcol;
@@ -987,14 +982,37 @@ static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const
   hd.jw = w.jw;
   hd.st = w.st;
   hd.n_nodes = m.n_nodes;
-  hd.n_wg = nwg;
+  hd.n_wg = w.n_wg;
   hd.wg_base = 0;
+  return hd;
+}
+
+// Upload the descriptor and start a single-reduction solve (initial residual and partials).
+template <class T>
+static hipError_t fused_start(const FusedDesc<T>& hd, double rtol, int max_it, PcgWork& w,
+                              hipStream_t s, FusedDesc<T>** out) {
   FusedDesc<T>* dd = reinterpret_cast<FusedDesc<T>*>(sizeof(T) == 8 ? w.fdesc64 : w.fdesc32);
   hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cg1_init1<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol, max_it);
-  hipLaunchKernelGGL(k_cg1_init2<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cg1_init1<T>, dim3(hd.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
+                     max_it);
+  hipLaunchKernelGGL(k_cg1_init2<T>, dim3(hd.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr);
+  *out = dd;
+  return hipGetLastError();
+}
+
+// One single-reduction PCG solve in precision T with B = K Dinv; the iteration kernel (the
+// whole iteration) is profiled.
+template <class T>
+static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const T* Dinv,
+                            const T* b, const FusedBuffers<T>& v, double rtol, int max_it,
+                            PcgWork& w, hipStream_t s, int* iters, int* status,
+                            int profile_every) {
+  const FusedDesc<T> hd = fused_desc(m, pat, B, Dinv, b, v, w);
+  FusedDesc<T>* dd = nullptr;
+  hipError_t e = fused_start(hd, rtol, max_it, w, s, &dd);
+  if (e != hipSuccess) return e;
+  const int nwg = hd.n_wg;
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
     hipLaunchKernelGGL(k_cg1_iter<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
@@ -1043,59 +1061,106 @@ hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const d
   return hipGetLastError();
 }
 
-hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, int n_iter, BatchWork& bw,
-                             hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  // lay the problems' workgroups end to end
-  bw.h_desc.assign(descs, descs + n);
-  bw.h_wg.clear();
-  for (int i = 0; i < n; ++i) {
-    bw.h_desc[i].wg_base = (int)bw.h_wg.size();
-    for (int k = 0; k < bw.h_desc[i].n_wg; ++k) bw.h_wg.push_back(i);
-  }
-  const int total = (int)bw.h_wg.size();
+hipError_t fused_begin(const Mesh& m, const Pattern& pat, const double* B, const double* Dinv,
+                       const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                       hipStream_t s, FusedDesc<double>* desc) {
   hipError_t e;
-  if (n > bw.cap_desc) {
-    dev_free(bw.d_desc, s);
-    bw.cap_desc = 2 * n;
-    if ((e = dev_alloc(reinterpret_cast<PcgDesc<double>**>(&bw.d_desc), bw.cap_desc, s)) !=
-        hipSuccess)
+  if ((e = fused_alloc(w, false, s)) != hipSuccess) return e;
+  const FusedBuffers<double> v{x, w.p[0], {w.r, w.z}, {w.p[1], w.Ap}, {w.fw[0], w.fw[1]}};
+  *desc = fused_desc(m, pat, B, Dinv, b, v, w);
+  FusedDesc<double>* dd = nullptr;
+  if ((e = fused_start(*desc, rtol, max_it, w, s, &dd)) != hipSuccess) return e;
+  w.h_st->done = 0;
+  return hipSuccess;
+}
+
+template <class Desc>
+static hipError_t table_upload(LaunchTable<Desc>& t, const Desc* descs, int n, hipStream_t s) {
+  t.h_desc.assign(descs, descs + n);
+  t.h_wg.clear();
+  for (int i = 0; i < n; ++i) {
+    t.h_desc[i].wg_base = (int)t.h_wg.size();
+    for (int k = 0; k < t.h_desc[i].n_wg; ++k) t.h_wg.push_back(i);
+  }
+  t.total = (int)t.h_wg.size();
+  if (n == 0) return hipSuccess;
+  hipError_t e;
+  if (n > t.cap_desc) {
+    dev_free(t.d_desc, s);
+    t.d_desc = nullptr;
+    t.cap_desc = 2 * n;
+    if ((e = dev_alloc(reinterpret_cast<Desc**>(&t.d_desc), t.cap_desc, s)) != hipSuccess)
       return e;
   }
-  if (total > bw.cap_wg) {
-    dev_free(bw.d_wg, s);
-    bw.cap_wg = 2 * total;
-    if ((e = dev_alloc(&bw.d_wg, bw.cap_wg, s)) != hipSuccess) return e;
+  if (t.total > t.cap_wg) {
+    dev_free(t.d_wg, s);
+    t.d_wg = nullptr;
+    t.cap_wg = 2 * t.total;
+    if ((e = dev_alloc(&t.d_wg, t.cap_wg, s)) != hipSuccess) return e;
   }
-  PcgDesc<double>* dd = reinterpret_cast<PcgDesc<double>*>(bw.d_desc);
-  if ((e = hipMemcpyAsync(dd, bw.h_desc.data(), sizeof(PcgDesc<double>) * n,
-                          hipMemcpyHostToDevice, s)) != hipSuccess)
+  if ((e = hipMemcpyAsync(t.d_desc, t.h_desc.data(), sizeof(Desc) * n, hipMemcpyHostToDevice,
+                          s)) != hipSuccess)
     return e;
-  if ((e = hipMemcpyAsync(bw.d_wg, bw.h_wg.data(), sizeof(int32_t) * total,
-                          hipMemcpyHostToDevice, s)) != hipSuccess)
-    return e;
+  return hipMemcpyAsync(t.d_wg, t.h_wg.data(), sizeof(int32_t) * t.total,
+                        hipMemcpyHostToDevice, s);
+}
+
+template <class Desc>
+static void table_free(LaunchTable<Desc>& t, hipStream_t s) {
+  dev_free(t.d_desc, s);
+  dev_free(t.d_wg, s);
+}
+
+hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDesc<double>* fdescs,
+                             int nf, int n_iter, BatchWork& bw, hipStream_t s) {
+  if (n + nf <= 0) return hipSuccess;
+  hipError_t e;
+  if ((e = table_upload(bw.standard, descs, n, s)) != hipSuccess) return e;
+  if ((e = table_upload(bw.fused, fdescs, nf, s)) != hipSuccess) return e;
+  const PcgDesc<double>* ds = reinterpret_cast<const PcgDesc<double>*>(bw.standard.d_desc);
+  const FusedDesc<double>* df = reinterpret_cast<const FusedDesc<double>*>(bw.fused.d_desc);
   for (int i = 0; i < n_iter; ++i) {
-    hipLaunchKernelGGL(k_spmv_dir<double>, dim3(total), dim3(MAX_TPB), 0, s, dd, bw.d_wg);
-    hipLaunchKernelGGL(k_update<double>, dim3(total), dim3(MAX_TPB), 0, s, dd, bw.d_wg);
+    if (n > 0) {
+      hipLaunchKernelGGL(k_spmv_dir<double>, dim3(bw.standard.total), dim3(MAX_TPB), 0, s, ds,
+                         bw.standard.d_wg);
+      hipLaunchKernelGGL(k_update<double>, dim3(bw.standard.total), dim3(MAX_TPB), 0, s, ds,
+                         bw.standard.d_wg);
+    }
+    if (nf > 0)
+      hipLaunchKernelGGL(k_cg1_iter<double>, dim3(bw.fused.total), dim3(MAX_TPB), 0, s, df,
+                         bw.fused.d_wg);
     ++bw.launched;
   }
-  if (n > bw.cap_states) {
+  const int nt = n + nf;
+  bw.h_stp.clear();
+  for (int i = 0; i < n; ++i) bw.h_stp.push_back(descs[i].st);
+  for (int i = 0; i < nf; ++i) bw.h_stp.push_back(fdescs[i].st);
+  if (nt > bw.cap_states) {
     dev_free(bw.d_states, s);
-    bw.cap_states = 2 * n;
+    dev_free(bw.d_stp, s);
+    bw.d_states = nullptr;
+    bw.d_stp = nullptr;
+    bw.cap_states = bw.cap_stp = 2 * nt;
     if ((e = dev_alloc(&bw.d_states, bw.cap_states, s)) != hipSuccess) return e;
+    if ((e = dev_alloc(&bw.d_stp, bw.cap_stp, s)) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_gather_states, dim3((n + 63) / 64), dim3(64), 0, s, dd, n, bw.d_states);
+  if ((e = hipMemcpyAsync(bw.d_stp, bw.h_stp.data(), sizeof(PcgState*) * nt,
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_gather_states, dim3((nt + 63) / 64), dim3(64), 0, s, bw.d_stp, nt,
+                     bw.d_states);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bw.h_states.resize(n);
-  if ((e = hipMemcpyAsync(bw.h_states.data(), bw.d_states, sizeof(PcgState) * n,
+  bw.h_states.resize(nt);
+  if ((e = hipMemcpyAsync(bw.h_states.data(), bw.d_states, sizeof(PcgState) * nt,
                           hipMemcpyDeviceToHost, s)) != hipSuccess)
     return e;
   return hipStreamSynchronize(s);
 }
 
 void batch_free(BatchWork& bw, hipStream_t s) {
-  dev_free(bw.d_desc, s);
-  dev_free(bw.d_wg, s);
+  table_free(bw.standard, s);
+  table_free(bw.fused, s);
+  dev_free(bw.d_stp, s);
   dev_free(bw.d_states, s);
   bw = BatchWork();
 }

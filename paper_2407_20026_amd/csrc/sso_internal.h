@@ -236,27 +236,40 @@ hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const
                        const double* b, double* x, double rtol, int max_it, PcgWork& w,
                        hipStream_t s, int* iters, int* status);
 
-// Multi-problem iteration: problems started with pcg_begin advance together, one launch per
-// kernel for all of them (FP64).
-struct BatchWork {
+// Multi-problem iteration: problems started with pcg_begin (standard recurrences) or
+// fused_begin (single-reduction) advance together, one launch per kernel for all problems of a
+// kind (FP64).  A table lays the problems' workgroups end to end.
+template <class Desc>
+struct LaunchTable {
   void* d_desc = nullptr;
   int cap_desc = 0;
   int32_t* d_wg = nullptr;
   int cap_wg = 0;
+  std::vector<Desc> h_desc;
+  std::vector<int32_t> h_wg;
+  int total = 0;          // workgroups of one launch
+};
+struct BatchWork {
+  LaunchTable<PcgDesc<double>> standard;
+  LaunchTable<FusedDesc<double>> fused;
+  PcgState** d_stp = nullptr;
+  int cap_stp = 0;
   PcgState* d_states = nullptr;
   int cap_states = 0;
-  std::vector<PcgDesc<double>> h_desc;
-  std::vector<int32_t> h_wg;
+  std::vector<PcgState*> h_stp;
   std::vector<PcgState> h_states;
   int64_t launched = 0;
 };
 hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
                      hipStream_t s, PcgDesc<double>* desc);
-// Launch n_iter iterations for the n problems, then copy their state records into
-// bw.h_states (synchronising the stream).
-hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, int n_iter, BatchWork& bw,
-                             hipStream_t s);
+hipError_t fused_begin(const Mesh& m, const Pattern& pat, const double* B, const double* Dinv,
+                       const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                       hipStream_t s, FusedDesc<double>* desc);
+// Launch n_iter iterations for the n standard and nf single-reduction problems, then copy their
+// state records into bw.h_states (standard ones first; synchronises the stream).
+hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDesc<double>* fdescs,
+                             int nf, int n_iter, BatchWork& bw, hipStream_t s);
 void batch_free(BatchWork& bw, hipStream_t s);
 // Deterministic dot product a^T b; result written to *d_out (device).
 hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,

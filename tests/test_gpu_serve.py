@@ -75,3 +75,42 @@ def test_memory_budget_limits_admission():
     assert stats.n == 8
     assert stats.peak_bytes <= budget
     assert stats.peak_inflight <= 6
+
+
+def test_batch_mixing_both_recurrences_matches_solves_alone():
+    """One multi-problem launcher with problems on the standard and on the single-reduction
+    recurrences: each result is bitwise the same as its own sso_solve; a problem listed twice
+    is rejected."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] batch with both recurrences", flush=True)
+    meshes = [meshgen.gridshell(9, seed=11), meshgen.shell(10, seed=12),
+              meshgen.shell(12, seed=13), meshgen.gridshell(12, seed=14)]
+    solvers = [sso.SOLVER_STANDARD, sso.SOLVER_FUSED, sso.SOLVER_STANDARD, sso.SOLVER_FUSED]
+    stream = torch.cuda.Stream()
+    batch = sso.Batch(stream)
+    probs = [sso.Problem(m, sso.Options(rtol=1e-10, solver=k), stream=stream)
+             for m, k in zip(meshes, solvers)]
+    try:
+        for p in probs:
+            p.solve_begin()
+        with pytest.raises(sso.SSOError):
+            batch.iterate([probs[0], probs[0]], 1)
+        done = [False] * len(probs)
+        for _ in range(10000):
+            done = batch.iterate(probs, 16)
+            if all(done):
+                break
+        assert all(done)
+        got = []
+        for p in probs:
+            u, st = p.solve_end()
+            got.append((u.cpu().numpy(), st["solver"]))
+    finally:
+        for p in probs:
+            p.close()
+        batch.close()
+    for m, k, (u, used) in zip(meshes, solvers, got):
+        assert used == k
+        with sso.Problem(m, sso.Options(rtol=1e-10, solver=k)) as q:
+            ua, _ = q.solve()
+        assert np.array_equal(u, ua.cpu().numpy())
