@@ -39,6 +39,13 @@ WORKLOADS = {
 }
 
 
+# the workload's generator at another seed (for the batched measurement)
+SEEDED = {
+    "shell60": lambda seed: meshgen.shell(60, seed=seed),
+    "grid11": lambda seed: meshgen.gridshell(11, seed=seed),
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +63,12 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the mixed-size served stream (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--batch", type=int, default=16,
+                    help="also time this many problems of the workload (seeds 1..n) advancing "
+                         "together in multi-problem launches (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before the workload, copy a float64 tensor of this many MiB 3 times "
+                         "(a plain copy kernel of known size for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -115,6 +128,56 @@ def serve_bench(n, slots):
             "mean_dof": float(np.mean([m.n_dof for m in meshes]))}
 
 
+def batch_bench(gen_seed, n_problems, rtol, objective):
+    """n problems of the workload with seeds 1..n, all iterating together in multi-problem
+    launches (one launch per kernel for all of them), forward + adjoint each."""
+    import torch
+    import paper_2407_20026_amd as sso
+    meshes = [gen_seed(k + 1) for k in range(n_problems)]
+    stream = torch.cuda.Stream()
+    batch = sso.Batch(stream)
+    probs = [sso.Problem(m, sso.Options(rtol=rtol, max_it=400000), stream=stream)
+             for m in meshes]
+
+    def one_pass():
+        for p in probs:
+            p.solve_begin()
+        done = [False] * len(probs)
+        while not all(done):
+            done = batch.iterate(probs, 32)
+        for p in probs:
+            p.solve_end()
+            p.objective(objective)
+            p.adjoint(objective)
+
+    try:
+        one_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one_pass()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        for p in probs:
+            p.close()
+        batch.close()
+    log(f"batched: {n_problems} problems in {1000 * el:.1f} ms")
+    return {"problems": n_problems, "solves_per_s": n_problems / el,
+            "dof_per_s": sum(m.n_dof for m in meshes) / el, "wall_ms": 1000 * el,
+            "note": "same generator, seeds 1..n; all problems in flight together"}
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x {mib} MiB")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -128,6 +191,8 @@ def main():
     desc, gen = WORKLOADS[args.workload]
     mesh = gen()
     torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib)
     a = None
     if args.objective == "linear":
         a = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
@@ -205,6 +270,9 @@ def main():
                      "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},
     }
     prob.close()
+    if args.batch > 0 and args.workload in SEEDED and args.objective != "linear":
+        out["batched"] = batch_bench(SEEDED[args.workload], args.batch, args.rtol,
+                                     args.objective)
     if args.serve_requests > 0:
         out["serving"] = serve_bench(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:

@@ -140,7 +140,7 @@ int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
 
 /* Replace solver options (host struct).  A change of precision or solver invalidates the last
  * solution (sso_objective / sso_adjoint need a new sso_solve).  Errors: SSO_EINVAL for values
- * outside their ranges. */
+ * outside their ranges or while a begun solve (sso_solve_begin) is not yet ended. */
 int sso_set_options(sso_problem* p, const sso_options* opts);
 
 /* Forward analysis: element stiffness (beams: K = s T^T k T; quads: flat shell, K = s T^T W^T k
@@ -157,9 +157,11 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
 
 /* Forward analysis split for multi-problem launches: sso_solve_begin runs everything up to the
  * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation;
- * FP64 only, else SSO_EINVAL); sso_batch_iterate then advances many begun problems together;
- * sso_solve_end finishes one (FP64 refinement of the true residual, u_out as in sso_solve,
- * stats) once its iteration has stopped.  Results are bitwise the same as sso_solve's. */
+ * FP64 with either recurrence, or mixed precision with the single-reduction one, else
+ * SSO_EINVAL); sso_batch_iterate then advances many begun problems together (mixed precision:
+ * including the FP64 refinement between FP32 inner solves); sso_solve_end finishes one (FP64
+ * correction of the true residual, u_out as in sso_solve, stats) once its iteration has
+ * stopped.  Results are bitwise the same as sso_solve's. */
 int sso_solve_begin(sso_problem* p);
 int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats);
 

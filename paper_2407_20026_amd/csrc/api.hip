@@ -41,6 +41,7 @@ struct sso_problem {
   int solver_used = SSO_SOLVER_STANDARD;   // recurrences of the last solve
   PcgDesc<double> desc{};       // its descriptor in multi-problem launches (standard / fused)
   FusedDesc<double> fdesc{};
+  MixedState ms;                // mixed precision begun with sso_solve_begin
   hipEvent_t ev[6] = {};
 };
 
@@ -234,7 +235,7 @@ int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
 }
 
 int sso_set_options(sso_problem* p, const sso_options* opts) {
-  if (!p || !opts || !options_ok(*opts)) return SSO_EINVAL;
+  if (!p || !opts || !options_ok(*opts) || p->in_batch) return SSO_EINVAL;
   // K32 / B / B32 are built by sso_solve for the precision and recurrences it runs with
   if (opts->precision != p->opt.precision || opts->solver != p->opt.solver) p->solved = false;
   p->opt = *opts;
@@ -247,6 +248,17 @@ namespace {
 
 bool mixed(const sso_problem* p) { return p->opt.precision == SSO_PREC_MIXED; }
 bool fused(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
+// iteration of a begun problem has stopped (mixed precision: the refinement loop has)
+bool stopped(const sso_problem* p) { return mixed(p) ? p->ms.done : p->w.h_st->done != 0; }
+
+MixedParams mixed_params(const sso_problem* p) {
+  MixedParams mp;
+  mp.rtol = p->opt.rtol;
+  mp.inner_rtol = p->opt.inner_rtol > 0.0 ? p->opt.inner_rtol : 1e-5;
+  mp.max_it = p->opt.max_it;
+  mp.refine_steps = p->opt.refine_steps;
+  return mp;
+}
 
 // Solve K x = b (b masked) in the problem's precision mode.
 int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* outer) {
@@ -256,13 +268,39 @@ int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* oute
     TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, fused(p) ? p->B : nullptr, b, x, p->opt.rtol,
                       p->opt.max_it, p->w, p->s, iters, &status, p->opt.profile_every));
   } else {
-    const double inner = p->opt.inner_rtol > 0.0 ? p->opt.inner_rtol : 1e-5;
     TRY_HIP(pcg_solve_mixed(p->m, p->pat, p->K, p->K32, p->Dinv32, fused(p) ? p->B32 : nullptr,
-                            b, x, p->opt.rtol, inner,
-                            p->opt.max_it, p->opt.refine_steps, p->w, p->s, iters, &status,
-                            outer, p->opt.profile_every));
+                            b, x, mixed_params(p), p->w, p->s, iters, &status, outer,
+                            p->opt.profile_every));
   }
   return status;
+}
+
+// Elements, loads, assembly, masking, block-Jacobi and the operators the chosen PCG needs
+// (B = K M for the single-reduction recurrences; FP32 copies for mixed precision).  Events 0-2
+// bracket the stages.
+int prepare(sso_problem* p) {
+  hipStream_t s = p->s;
+  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
+  const bool mx = mixed(p), fu = fused(p);
+  const int64_t nk = 36 * p->pat.n_blocks;
+  if (mx && !p->Dinv32) TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
+  if (mx && !fu && !p->K32) TRY_HIP(dev_alloc(&p->K32, nk, s));
+  if (fu && !mx && !p->B) TRY_HIP(dev_alloc(&p->B, nk, s));
+  if (fu && mx && !p->B32) TRY_HIP(dev_alloc(&p->B32, nk, s));
+  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
+  TRY_HIP(hipEventRecord(p->ev[0], s));
+  TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
+  TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
+  TRY_HIP(hipEventRecord(p->ev[1], s));
+  TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
+  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, mx ? p->Dinv32 : nullptr, p->d_err,
+                              s));
+  if (mx && !fu) TRY_HIP(launch_convert_f32(p->K, p->K32, nk, s));
+  if (fu)
+    TRY_HIP(launch_right_precondition(p->pat, p->K, p->Dinv, mx ? nullptr : p->B,
+                                      mx ? p->B32 : nullptr, s));
+  TRY_HIP(hipEventRecord(p->ev[2], s));
+  return read_errors(p);
 }
 
 bool fused_used(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
@@ -284,27 +322,8 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   if (!p) return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
-  if (mixed(p) && !p->K32) {
-    TRY_HIP(dev_alloc(&p->K32, 36 * p->pat.n_blocks, s));
-    TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
-  }
-  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
-  if (fused(p) && !mixed(p) && !p->B) TRY_HIP(dev_alloc(&p->B, 36 * p->pat.n_blocks, s));
-  if (fused(p) && mixed(p) && !p->B32) TRY_HIP(dev_alloc(&p->B32, 36 * p->pat.n_blocks, s));
-  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
-  TRY_HIP(hipEventRecord(p->ev[0], s));
-  TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
-  TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
-  TRY_HIP(hipEventRecord(p->ev[1], s));
-  TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
-  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, mixed(p) ? p->Dinv32 : nullptr,
-                              p->d_err, s));
-  if (mixed(p)) TRY_HIP(launch_convert_f32(p->K, p->K32, 36 * p->pat.n_blocks, s));
-  if (fused(p))
-    TRY_HIP(launch_right_precondition(p->pat, p->K, p->Dinv, mixed(p) ? nullptr : p->B,
-                                      mixed(p) ? p->B32 : nullptr, s));
-  TRY_HIP(hipEventRecord(p->ev[2], s));
-  int st = read_errors(p);
+  p->in_batch = false;
+  int st = prepare(p);
   if (st != SSO_OK) return st;
   int iters = 0, outer = 0;
   int status = run_solver(p, p->f, p->u, &iters, &outer);
@@ -339,20 +358,18 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
 
 int sso_solve_begin(sso_problem* p) {
   if (!p) return SSO_EINVAL;
-  if (mixed(p)) return SSO_EINVAL;
+  // multi-problem launches run FP64 iterations of either kind and FP32 single-reduction ones
+  if (mixed(p) && pcg_pick_solver(p->opt.solver, p->m.n_nodes) != SSO_SOLVER_FUSED)
+    return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
-  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
-  if (fused(p) && !p->B) TRY_HIP(dev_alloc(&p->B, 36 * p->pat.n_blocks, s));
-  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
-  TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
-  TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
-  TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
-  TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, nullptr, p->d_err, s));
-  if (fused(p)) TRY_HIP(launch_right_precondition(p->pat, p->K, p->Dinv, p->B, nullptr, s));
-  int st = read_errors(p);
+  p->in_batch = false;
+  int st = prepare(p);
   if (st != SSO_OK) return st;
-  if (fused(p))
+  if (mixed(p))
+    TRY_HIP(mixed_begin(p->m, p->pat, p->K, p->K32, p->Dinv32, p->B32, p->f, p->u,
+                        mixed_params(p), p->w, s, p->ms));
+  else if (fused(p))
     TRY_HIP(fused_begin(p->m, p->pat, p->B, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it,
                         p->w, s, &p->fdesc));
   else
@@ -373,8 +390,12 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
                            hipMemcpyDeviceToDevice, s));
   TRY_HIP(hipStreamSynchronize(s));
   int status = p->w.h_st->done ? p->w.h_st->status : SSO_ENOTCONV;
-  int iters = p->w.h_st->it;
-  if (status == SSO_OK) {
+  int iters = p->w.h_st->it, outer = 0;
+  if (mixed(p)) {   // the refinement loop already ended on the FP64 true residual
+    status = p->ms.done ? p->ms.status : SSO_ENOTCONV;
+    iters = p->ms.iters;
+    outer = p->ms.outer;
+  } else if (status == SSO_OK) {
     TRY_HIP(pcg_correct(p->m, p->pat, p->K, p->Dinv, p->f, p->u, p->opt.rtol, p->opt.max_it, p->w,
                         s, &iters, &status));
     TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
@@ -388,9 +409,11 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->iters = iters;
     stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
-    stats->bytes_moved = solve_bytes(p, iters, 0);
-    stats->spmv_bytes = fused(p) ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false)
-                                 : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, false);
+    stats->refine_steps = outer;
+    stats->bytes_moved = solve_bytes(p, iters, outer);
+    stats->spmv_bytes =
+        fused(p) ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
+                 : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, mixed(p));
     stats->solver = p->solver_used;
   }
   p->in_batch = false;
@@ -411,7 +434,8 @@ int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, i
   if (!b || (n > 0 && !ps) || n < 0 || n_iter < 0) return SSO_EINVAL;
   std::vector<PcgDesc<double>> descs;
   std::vector<FusedDesc<double>> fdescs;
-  std::vector<int> idx, fidx;
+  std::vector<FusedDesc<float>> mdescs;
+  std::vector<int> idx, fidx, midx;
   for (int i = 0; i < n; ++i) {
     sso_problem* p = ps[i];
     if (!p || !p->in_batch || p->s != b->s) return SSO_EINVAL;
@@ -420,8 +444,11 @@ int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, i
   }
   for (int i = 0; i < n; ++i) {
     sso_problem* p = ps[i];
-    if (p->w.h_st->done) continue;     // finished at an earlier poll
-    if (fused(p)) {
+    if (stopped(p)) continue;          // finished at an earlier poll
+    if (mixed(p)) {
+      mdescs.push_back(p->ms.fdesc);
+      midx.push_back(i);
+    } else if (fused(p)) {
       fdescs.push_back(p->fdesc);
       fidx.push_back(i);
     } else {
@@ -429,14 +456,20 @@ int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, i
       idx.push_back(i);
     }
   }
-  if (!descs.empty() || !fdescs.empty())
+  if (!descs.empty() || !fdescs.empty() || !mdescs.empty())
     TRY_HIP(pcg_batch_iterate(descs.data(), (int)descs.size(), fdescs.data(), (int)fdescs.size(),
-                              n_iter, b->bw, b->s));
-  for (size_t k = 0; k < idx.size(); ++k) *ps[idx[k]]->w.h_st = b->bw.h_states[k];
-  for (size_t k = 0; k < fidx.size(); ++k)
-    *ps[fidx[k]]->w.h_st = b->bw.h_states[idx.size() + k];
+                              mdescs.data(), (int)mdescs.size(), n_iter, b->bw, b->s));
+  size_t k0 = 0;
+  for (const std::vector<int>* v : {&idx, &fidx, &midx})
+    for (int i : *v) *ps[i]->w.h_st = b->bw.h_states[k0++];
+  // mixed precision: a stopped inner solve is refined in FP64 and the next one started
+  for (int i : midx) {
+    sso_problem* p = ps[i];
+    TRY_HIP(mixed_step(p->m, p->pat, p->K, p->K32, p->Dinv32, p->B32, p->f, p->u,
+                       mixed_params(p), p->w, p->s, p->ms));
+  }
   if (done)
-    for (int i = 0; i < n; ++i) done[i] = ps[i]->w.h_st->done ? 1 : 0;
+    for (int i = 0; i < n; ++i) done[i] = stopped(ps[i]) ? 1 : 0;
   return SSO_OK;
 }
 

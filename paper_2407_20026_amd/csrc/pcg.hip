@@ -913,13 +913,11 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
   return hipSuccess;
 }
 
-// One standard PCG solve in precision T on (K, Dinv, b) -> x; the SpMV kernel is profiled.
+// Upload the descriptor of a standard solve and run its initialisation kernel.
 template <class T>
-static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T* Dinv,
-                          const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
-                          int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
-                          int profile_every) {
-  const int tpb = MAX_TPB, nwg = w.n_wg;
+static hipError_t pcg_start(const Mesh& m, const Pattern& pat, const T* K, const T* Dinv,
+                            const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
+                            int max_it, PcgWork& w, hipStream_t s, PcgDesc<T>* out) {
   PcgDesc<T> hd{};
   hd.brow_ptr = pat.brow_ptr;
   hd.bcol = pat.bcol;
@@ -936,18 +934,33 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   hd.pb = part_b(w);
   hd.st = w.st;
   hd.n_nodes = m.n_nodes;
-  hd.n_wg = nwg;
+  hd.n_wg = w.n_wg;
   hd.wg_base = 0;
+  if (out) *out = hd;
   PcgDesc<T>* dd = reinterpret_cast<PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
   hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr, rtol, max_it);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(w.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
+                     max_it);
+  return hipGetLastError();
+}
+
+// One standard PCG solve in precision T on (K, Dinv, b) -> x; the SpMV kernel is profiled.
+template <class T>
+static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T* Dinv,
+                          const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
+                          int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
+                          int profile_every) {
+  hipError_t e = pcg_start<T>(m, pat, K, Dinv, b, x, r, z, p, Ap, rtol, max_it, w, s, nullptr);
+  if (e != hipSuccess) return e;
+  const int nwg = w.n_wg;
+  const PcgDesc<T>* dd =
+      reinterpret_cast<const PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
-    hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
+    hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
     if (e1) (void)hipEventRecord(*e1, s);
-    hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(tpb), 0, s, dd, nullptr);
+    hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
   };
   return run_polled(w, s, max_it, profile_every, launch, iters, status);
 }
@@ -1033,32 +1046,10 @@ static hipError_t fused_alloc(PcgWork& w, bool f32, hipStream_t s) {
 hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
                      hipStream_t s, PcgDesc<double>* desc) {
-  PcgDesc<double>& hd = *desc;
-  hd = PcgDesc<double>{};
-  hd.brow_ptr = pat.brow_ptr;
-  hd.bcol = pat.bcol;
-  hd.K = K;
-  hd.Dinv = Dinv;
-  hd.b = b;
-  hd.x = x;
-  hd.r = w.r;
-  hd.z = w.z;
-  hd.p[0] = w.p[0];
-  hd.p[1] = w.p[1];
-  hd.Ap = w.Ap;
-  hd.pa = part_a(w);
-  hd.pb = part_b(w);
-  hd.st = w.st;
-  hd.n_nodes = m.n_nodes;
-  hd.n_wg = w.n_wg;
-  hd.wg_base = 0;
-  PcgDesc<double>* dd = reinterpret_cast<PcgDesc<double>*>(w.desc64);
-  hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pcg_init<double>, dim3(w.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
-                     max_it);
+  hipError_t e = pcg_start<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w,
+                                   s, desc);
   w.h_st->done = 0;
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t fused_begin(const Mesh& m, const Pattern& pat, const double* B, const double* Dinv,
@@ -1112,13 +1103,16 @@ static void table_free(LaunchTable<Desc>& t, hipStream_t s) {
 }
 
 hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDesc<double>* fdescs,
-                             int nf, int n_iter, BatchWork& bw, hipStream_t s) {
-  if (n + nf <= 0) return hipSuccess;
+                             int nf, const FusedDesc<float>* mdescs, int nm, int n_iter,
+                             BatchWork& bw, hipStream_t s) {
+  if (n + nf + nm <= 0) return hipSuccess;
   hipError_t e;
   if ((e = table_upload(bw.standard, descs, n, s)) != hipSuccess) return e;
   if ((e = table_upload(bw.fused, fdescs, nf, s)) != hipSuccess) return e;
+  if ((e = table_upload(bw.fused32, mdescs, nm, s)) != hipSuccess) return e;
   const PcgDesc<double>* ds = reinterpret_cast<const PcgDesc<double>*>(bw.standard.d_desc);
   const FusedDesc<double>* df = reinterpret_cast<const FusedDesc<double>*>(bw.fused.d_desc);
+  const FusedDesc<float>* dm = reinterpret_cast<const FusedDesc<float>*>(bw.fused32.d_desc);
   for (int i = 0; i < n_iter; ++i) {
     if (n > 0) {
       hipLaunchKernelGGL(k_spmv_dir<double>, dim3(bw.standard.total), dim3(MAX_TPB), 0, s, ds,
@@ -1129,12 +1123,16 @@ hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDes
     if (nf > 0)
       hipLaunchKernelGGL(k_cg1_iter<double>, dim3(bw.fused.total), dim3(MAX_TPB), 0, s, df,
                          bw.fused.d_wg);
+    if (nm > 0)
+      hipLaunchKernelGGL(k_cg1_iter<float>, dim3(bw.fused32.total), dim3(MAX_TPB), 0, s, dm,
+                         bw.fused32.d_wg);
     ++bw.launched;
   }
-  const int nt = n + nf;
+  const int nt = n + nf + nm;
   bw.h_stp.clear();
   for (int i = 0; i < n; ++i) bw.h_stp.push_back(descs[i].st);
   for (int i = 0; i < nf; ++i) bw.h_stp.push_back(fdescs[i].st);
+  for (int i = 0; i < nm; ++i) bw.h_stp.push_back(mdescs[i].st);
   if (nt > bw.cap_states) {
     dev_free(bw.d_states, s);
     dev_free(bw.d_stp, s);
@@ -1160,6 +1158,7 @@ hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDes
 void batch_free(BatchWork& bw, hipStream_t s) {
   table_free(bw.standard, s);
   table_free(bw.fused, s);
+  table_free(bw.fused32, s);
   dev_free(bw.d_stp, s);
   dev_free(bw.d_states, s);
   bw = BatchWork();
@@ -1245,77 +1244,135 @@ hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const
 // FP32 inner PCG (FP32 K, vectors, SpMV and workgroup accumulation) inside FP64 iterative
 // refinement: r = b - K x recomputed in FP64 with the FP64 K, the inner solve runs on r / |r|,
 // and x += |r| d in FP64, until |r| <= rtol |b| or refinement stalls.
-hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
-                           const float* Dinv32, const float* B32, const double* b, double* x,
-                           double rtol,
-                           double inner_rtol, int max_it, int refine_steps, PcgWork& w,
-                           hipStream_t s, int* iters, int* status, int* outer,
-                           int profile_every) {
+// Mixed precision as a step machine, so that single solves and multi-problem launches share
+// it.  mixed_next: with the FP64 iterate x, recompute the true residual r = b - K x in FP64 and
+// either stop (converged, refinement limit, stalled, iteration budget, breakdown) or start the
+// next FP32 inner solve K d = r / |r| (tolerance: the reduction still missing, with a factor 2
+// of margin, clamped to [inner_rtol, 0.5]).  mixed_inner_done: after the inner solve stopped,
+// x += |r| d, then mixed_next.
+static hipError_t mixed_next(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                             const float* Dinv32, const float* B32, const double* b, double* x,
+                             const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms) {
+  hipError_t e;
+  const int64_t n = w.n_dof;
+  double* scal = part_once(w) + 2 * (size_t)partial_stride(w);
+  if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, scal, s)) != hipSuccess) return e;
+  double h[2];
+  if ((e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  const double rn = std::sqrt(h[0]), bn = std::sqrt(h[1]);
+  const int left = mp.max_it - ms.iters;
+  ms.done = true;
+  if (!std::isfinite(rn)) {
+    ms.status = SSO_EBREAKDOWN;
+    return hipSuccess;
+  }
+  if (rn <= mp.rtol * bn) {
+    ms.status = SSO_OK;
+    return hipSuccess;
+  }
+  if (ms.outer == mp.refine_steps || (ms.prev >= 0.0 && rn > 0.5 * ms.prev) || left <= 0) {
+    ms.status = SSO_ENOTCONV;   // limit reached, refinement stalled or iterations used up
+    return hipSuccess;
+  }
+  ms.done = false;
+  ms.prev = rn;
+  ms.rn = rn;
+  hipLaunchKernelGGL(k_scale_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, w.r, 1.0 / rn,
+                     w.b32);
+  double tol_k = 0.5 * mp.rtol * bn / rn;
+  if (tol_k < mp.inner_rtol) tol_k = mp.inner_rtol;
+  if (tol_k > 0.5) tol_k = 0.5;
+  if (B32) {
+    const FusedBuffers<float> v{w.x32, w.p32[0], {w.r32, w.z32}, {w.p32[1], w.Ap32},
+                                {w.fw32[0], w.fw32[1]}};
+    ms.fdesc = fused_desc(m, pat, B32, Dinv32, (const float*)w.b32, v, w);
+    FusedDesc<float>* dd = nullptr;
+    if ((e = fused_start(ms.fdesc, tol_k, left, w, s, &dd)) != hipSuccess) return e;
+  } else {
+    if ((e = pcg_start<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32,
+                              tol_k, left, w, s, nullptr)) != hipSuccess)
+      return e;
+  }
+  w.h_st->done = 0;
+  return hipSuccess;
+}
+
+static hipError_t mixed_inner_done(const Mesh& m, const Pattern& pat, const double* K,
+                                   const float* K32, const float* Dinv32, const float* B32,
+                                   const double* b, double* x, const MixedParams& mp, PcgWork& w,
+                                   hipStream_t s, MixedState& ms) {
+  const int it = w.h_st->it;
+  const int st = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
+  ms.iters += it;
+  ++ms.outer;
+  if (st == SSO_EBREAKDOWN && it == 0) {
+    ms.done = true;
+    ms.status = SSO_EBREAKDOWN;
+    return hipSuccess;
+  }
+  const int64_t n = w.n_dof;
+  hipLaunchKernelGGL(k_refine_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, ms.rn, w.x32, x);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
+}
+
+hipError_t mixed_begin(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                       const float* Dinv32, const float* B32, const double* b, double* x,
+                       const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms) {
   hipError_t e;
   if ((e = pcg_alloc_mixed(w, s)) != hipSuccess) return e;
   if (B32 && (e = fused_alloc(w, true, s)) != hipSuccess) return e;
-  const int64_t n = w.n_dof;
+  if ((e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)w.n_dof, s)) != hipSuccess) return e;
+  ms = MixedState();
+  return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
+}
+
+hipError_t mixed_step(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                      const float* Dinv32, const float* B32, const double* b, double* x,
+                      const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms) {
+  if (ms.done || !w.h_st->done) return hipSuccess;
+  return mixed_inner_done(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
+}
+
+hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                           const float* Dinv32, const float* B32, const double* b, double* x,
+                           const MixedParams& mp, PcgWork& w, hipStream_t s, int* iters,
+                           int* status, int* outer, int profile_every) {
   w.prof_us = 0.0;
   w.prof_n = 0;
-  if ((e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s)) != hipSuccess) return e;
-  double* scal = part_once(w) + 2 * (size_t)partial_stride(w);
-  *iters = 0;
-  *status = SSO_ENOTCONV;
-  *outer = 0;
-  double prev = -1.0;
-  for (int step = 0; step <= refine_steps; ++step) {
-    if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, scal, s)) != hipSuccess) return e;
-    double h[2];
-    if ((e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const double rn = std::sqrt(h[0]), bn = std::sqrt(h[1]);
-    if (!std::isfinite(rn)) {
-      *status = SSO_EBREAKDOWN;
-      return hipSuccess;
-    }
-    if (rn <= rtol * bn) {
-      *status = SSO_OK;
-      return hipSuccess;
-    }
-    if (step == refine_steps || (prev >= 0.0 && rn > 0.5 * prev)) {
-      *status = SSO_ENOTCONV;   // limit reached or refinement stalled
-      return hipSuccess;
-    }
-    prev = rn;
-    hipLaunchKernelGGL(k_scale_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, w.r, 1.0 / rn,
-                       w.b32);
+  MixedState ms;
+  hipError_t e = mixed_begin(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
+  while (e == hipSuccess && !ms.done) {
     int it = 0, st = SSO_OK;
-    const int left = max_it - *iters;
-    if (left <= 0) {
-      *status = SSO_ENOTCONV;
-      return hipSuccess;
-    }
-    // the inner solve only needs the reduction still missing (with a factor 2 of margin)
-    double tol_k = 0.5 * rtol * bn / rn;
-    if (tol_k < inner_rtol) tol_k = inner_rtol;
-    if (tol_k > 0.5) tol_k = 0.5;
+    const int nwg = w.n_wg;
+    const int left = mp.max_it - ms.iters;
     if (B32) {
-      const FusedBuffers<float> v{w.x32, w.p32[0], {w.r32, w.z32}, {w.p32[1], w.Ap32},
-                                  {w.fw32[0], w.fw32[1]}};
-      e = fused_run<float>(m, pat, B32, Dinv32, w.b32, v, tol_k, left, w, s, &it, &st,
-                           profile_every);
+      const FusedDesc<float>* dd = reinterpret_cast<const FusedDesc<float>*>(w.fdesc32);
+      auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
+        if (e0) (void)hipEventRecord(*e0, s);
+        hipLaunchKernelGGL(k_cg1_iter<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+        if (e1) (void)hipEventRecord(*e1, s);
+      };
+      e = run_polled(w, s, left, profile_every, launch, &it, &st);
     } else {
-      e = pcg_run<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32, tol_k,
-                         left, w, s, &it, &st, profile_every);
+      const PcgDesc<float>* dd = reinterpret_cast<const PcgDesc<float>*>(w.desc32);
+      auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
+        if (e0) (void)hipEventRecord(*e0, s);
+        hipLaunchKernelGGL(k_spmv_dir<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+        if (e1) (void)hipEventRecord(*e1, s);
+        hipLaunchKernelGGL(k_update<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+      };
+      e = run_polled(w, s, left, profile_every, launch, &it, &st);
     }
-    if (e != hipSuccess) return e;
-    *iters += it;
-    ++*outer;
-    if (st == SSO_EBREAKDOWN && it == 0) {
-      *status = SSO_EBREAKDOWN;
-      return hipSuccess;
-    }
-    hipLaunchKernelGGL(k_refine_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, rn, w.x32, x);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e == hipSuccess) e = mixed_inner_done(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
   }
-  return hipSuccess;
+  *iters = ms.iters;
+  *status = ms.status;
+  *outer = ms.outer;
+  return e;
 }
 
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s) {

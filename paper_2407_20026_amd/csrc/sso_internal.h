@@ -222,13 +222,30 @@ int pcg_pick_solver(int solver, int64_t n_nodes);
 hipError_t launch_right_precondition(const Pattern& pat, const double* K, const double* Dinv,
                                      double* B, float* B32, hipStream_t s);
 // FP32 inner PCG inside FP64 iterative refinement (residual recomputed with the FP64 K); the
-// inner solves use the single-reduction recurrences when B32 is given.
+// inner solves use the single-reduction recurrences when B32 is given, else K32.
+struct MixedParams {
+  double rtol, inner_rtol;
+  int max_it, refine_steps;
+};
+struct MixedState {
+  int outer = 0, iters = 0, status = SSO_OK;
+  double prev = -1.0, rn = 0.0;
+  bool done = false;
+  FusedDesc<float> fdesc{};   // descriptor of the running inner solve (B32 given)
+};
 hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
                            const float* Dinv32, const float* B32, const double* b, double* x,
-                           double rtol,
-                           double inner_rtol, int max_it, int refine_steps, PcgWork& w,
-                           hipStream_t s, int* iters, int* status, int* outer,
-                           int profile_every);
+                           const MixedParams& mp, PcgWork& w, hipStream_t s, int* iters,
+                           int* status, int* outer, int profile_every);
+// The same one step at a time: mixed_begin sets x = 0 and starts the first inner solve (or
+// stops at once); after the inner solve's state says done, mixed_step refines x and starts the
+// next one or stops (ms.done, ms.status).  Both synchronise the stream.
+hipError_t mixed_begin(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                       const float* Dinv32, const float* B32, const double* b, double* x,
+                       const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms);
+hipError_t mixed_step(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
+                      const float* Dinv32, const float* B32, const double* b, double* x,
+                      const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);
 // FP64 refinement of a converged solve until the true residual meets rtol (see pcg.hip).
@@ -252,6 +269,7 @@ struct LaunchTable {
 struct BatchWork {
   LaunchTable<PcgDesc<double>> standard;
   LaunchTable<FusedDesc<double>> fused;
+  LaunchTable<FusedDesc<float>> fused32;    // FP32 inner solves of mixed-precision problems
   PcgState** d_stp = nullptr;
   int cap_stp = 0;
   PcgState* d_states = nullptr;
@@ -266,10 +284,12 @@ hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const d
 hipError_t fused_begin(const Mesh& m, const Pattern& pat, const double* B, const double* Dinv,
                        const double* b, double* x, double rtol, int max_it, PcgWork& w,
                        hipStream_t s, FusedDesc<double>* desc);
-// Launch n_iter iterations for the n standard and nf single-reduction problems, then copy their
-// state records into bw.h_states (standard ones first; synchronises the stream).
+// Launch n_iter iterations for the n standard, nf single-reduction and nm FP32 single-reduction
+// (inner solves of mixed precision) problems, then copy their state records into bw.h_states
+// in that order (synchronises the stream).
 hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDesc<double>* fdescs,
-                             int nf, int n_iter, BatchWork& bw, hipStream_t s);
+                             int nf, const FusedDesc<float>* mdescs, int nm, int n_iter,
+                             BatchWork& bw, hipStream_t s);
 void batch_free(BatchWork& bw, hipStream_t s);
 // Deterministic dot product a^T b; result written to *d_out (device).
 hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,

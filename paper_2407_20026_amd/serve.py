@@ -9,9 +9,9 @@ result) and throughput (solves/s, DOF/s) are reported side by side.
 * :class:`BatchedServer` -- one host thread and one stream: every admitted request's PCG
   iterations run in shared launches (``sso_batch_iterate``: one launch per kernel for all
   requests in flight, each request on its own range of workgroups); requests join and leave at
-  the chunk boundaries.
+  the chunk boundaries.  FP64 or mixed precision (FP32 inner iterations, FP64 refinement).
 * :class:`Server` -- one host thread and one HIP stream per slot, each slot solving its request
-  with ``sso_solve``; supports mixed precision.
+  with ``sso_solve``.
 
 Every number comes from the HIP library; K, the preconditioner and u stay on the device for a
 request's lifetime.
@@ -31,7 +31,7 @@ from . import Options, Problem
 
 def footprint_bytes(mesh, mixed: bool = False) -> int:
     """Upper bound of the device memory one problem holds (mesh, pattern, element list, K,
-    preconditioner, PCG vectors, gradients)."""
+    preconditioner, B = K M of the single-reduction PCG, PCG vectors, gradients)."""
     nn, nb, nq = mesh.n_nodes, mesh.n_beams, mesh.n_quads
     blocks = nn + 2 * nb + 12 * nq                  # diagonal + off-diagonal blocks (bound)
     nbcoo = 4 * nb + 16 * nq
@@ -41,9 +41,11 @@ def footprint_bytes(mesh, mixed: bool = False) -> int:
     b += 4 * (3 * nbcoo + 3 * blocks + 4 * nn)                                  # pattern
     b += 8 * (144 * nb + 576 * nq)                                              # element list
     b += 288 * blocks + 288 * nn                                                # K, Dinv
-    b += 8 * ndof * 10 + 8 * (6 * nb + 14 * nq)                                 # vectors, grads
+    b += 8 * ndof * 12 + 8 * (6 * nb + 14 * nq)                                 # vectors, grads
     if mixed:
-        b += 144 * blocks + 144 * nn + 4 * ndof * 7
+        b += 144 * blocks + 144 * nn + 4 * ndof * 9       # B (or K) and Dinv in FP32, vectors
+    else:
+        b += 288 * blocks                                 # B in FP64
     return int(b * 1.1) + (1 << 20)
 
 
@@ -218,8 +220,7 @@ class BatchedServer:
         self.slots = slots
         self.budget = hbm_budget
         self.options = options or Options()
-        if self.options.precision != 0:
-            raise ValueError("multi-problem launches run the FP64 iteration")
+        self.mixed = self.options.precision == 1
         self.device = torch.device(device)
         self.chunk = chunk
 
@@ -227,7 +228,7 @@ class BatchedServer:
         from . import Batch
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
-            if footprint_bytes(r.mesh) > self.budget:
+            if footprint_bytes(r.mesh, self.mixed) > self.budget:
                 raise ValueError(f"request {r.rid} can never be admitted: footprint above budget")
         stream = torch.cuda.Stream(device=self.device)
         batch = Batch(stream, self.device)
@@ -249,9 +250,9 @@ class BatchedServer:
                     waiting.append(reqs[nxt])
                     nxt += 1
                 while waiting and len(active) < self.slots and \
-                        footprint_bytes(waiting[0].mesh) <= free:
+                        footprint_bytes(waiting[0].mesh, self.mixed) <= free:
                     req = waiting.popleft()
-                    need = footprint_bytes(req.mesh)
+                    need = footprint_bytes(req.mesh, self.mixed)
                     free -= need
                     p = Problem(req.mesh, self.options, device=self.device, stream=stream)
                     p.solve_begin()

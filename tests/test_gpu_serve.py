@@ -114,3 +114,21 @@ def test_batch_mixing_both_recurrences_matches_solves_alone():
         with sso.Problem(m, sso.Options(rtol=1e-10, solver=k)) as q:
             ua, _ = q.solve()
         assert np.array_equal(u, ua.cpu().numpy())
+
+
+def test_batched_mixed_precision_matches_solves_alone():
+    """Mixed precision in multi-problem launches (FP32 single-reduction inner iterations, FP64
+    refinement between them): every request bitwise equal to the same request solved alone
+    with sso_solve, and within the requested residual."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import BatchedServer, run_one
+    print("[gpu] batched serve mixed precision", flush=True)
+    opts = sso.Options(precision=sso.PREC_MIXED, rtol=1e-8)
+    reqs = _requests(12, seed=21, rate=5000.0)
+    stats = BatchedServer(slots=6, options=opts, chunk=16).run(reqs)
+    assert stats.n == len(reqs)
+    assert stats.peak_inflight >= 3
+    for r, req in zip(stats.results, reqs):
+        alone = run_one(req, opts)
+        assert r.g == alone.g
+        assert np.array_equal(r.grad_xyz, alone.grad_xyz)

@@ -10,10 +10,12 @@ def test_footprint_grows_with_size_and_bounds_the_matrix():
     from paper_2407_20026_amd.serve import footprint_bytes
     small, large = meshgen.shell(10), meshgen.shell(40)
     assert footprint_bytes(large) > footprint_bytes(small)
-    # K values alone: (3m+1)^2 blocks of 288 bytes; element list 4608 bytes per quad
+    # (3m+1)^2 blocks: K and B = K M in FP64 (288 bytes each), or K in FP64 and B in FP32 for
+    # mixed precision; element list 4608 bytes per quad
     m = 40
-    assert footprint_bytes(large) > 288 * (3 * m + 1) ** 2 + 4608 * m * m
-    assert footprint_bytes(large, mixed=True) > footprint_bytes(large)
+    nb = (3 * m + 1) ** 2
+    assert footprint_bytes(large) > 2 * 288 * nb + 4608 * m * m
+    assert footprint_bytes(large, mixed=True) > (288 + 144) * nb + 4608 * m * m
     g = meshgen.gridshell(20)
     assert footprint_bytes(g) > 288 * (20 * 20 + 4 * 20 * 19)
 
