@@ -103,24 +103,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serve_bench(n, slots):
+def serve_bench(n, slots, precision):
     """Mixed-size served stream: grid-shells (n x n nodes, n ~ U{8..60}) and shells (m x m quads,
-    m ~ U{10..120}) with per-request seeds, FP64, rtol 1e-8, all requests in flight iterating
-    in shared multi-problem launches.  A closed-loop pass measures the capacity; the timed pass
-    uses Poisson arrivals at 0.8 x capacity."""
+    m ~ U{10..120}) with per-request seeds, rtol 1e-8 on the FP64 true residual, all requests in
+    flight iterating in shared multi-problem launches; FP64 or mixed precision (FP32 inner
+    iterations).  A closed-loop pass measures the capacity; the timed pass uses Poisson arrivals
+    at 0.8 x capacity."""
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import BatchedServer, Request, poisson_arrivals
     meshes = [meshgen.served_request(i) for i in range(n)]
-    opts = sso.Options(rtol=1e-8)
+    opts = sso.Options(rtol=1e-8, precision=sso.PREC_MIXED if precision == "mixed" else
+                       sso.PREC_FP64)
     srv = BatchedServer(slots=slots, options=opts)
     n_cl = min(n, 64)
     cl = srv.run([Request(i, meshes[i], 0.0) for i in range(n_cl)])
-    log(f"serving closed loop: {cl.solves_per_s:.1f} solves/s")
+    log(f"serving {precision} closed loop: {cl.solves_per_s:.1f} solves/s")
     lam = 0.8 * cl.solves_per_s
     t = poisson_arrivals(n, lam, seed=3)
     st = srv.run([Request(i, meshes[i], float(t[i])) for i in range(n)])
-    log(f"serving Poisson stream: {st.solves_per_s:.1f} solves/s p99 {st.p99_ms:.1f} ms")
-    return {"requests": st.n, "slots": slots, "precision": "fp64", "rtol": 1e-8,
+    log(f"serving {precision} Poisson stream: {st.solves_per_s:.1f} solves/s "
+        f"p99 {st.p99_ms:.1f} ms")
+    return {"requests": st.n, "slots": slots, "precision": precision, "rtol": 1e-8,
             "closed_loop_solves_per_s": cl.solves_per_s, "arrival_rate_per_s": lam,
             "solves_per_s": st.solves_per_s, "dof_per_s": st.dof_per_s,
             "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_queue_ms": st.mean_queue_ms,
@@ -274,7 +277,8 @@ def main():
         out["batched"] = batch_bench(SEEDED[args.workload], args.batch, args.rtol,
                                      args.objective)
     if args.serve_requests > 0:
-        out["serving"] = serve_bench(args.serve_requests, args.serve_slots)
+        out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec)
+                          for prec in ("fp64", "mixed")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, args.objective, args.cpu_seconds)
     print(json.dumps(out), flush=True)
