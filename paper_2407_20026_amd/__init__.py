@@ -227,6 +227,8 @@ class Problem:
     # -- C entry points ---------------------------------------------------------------
     def update(self, xyz=None, quad_t=None, quad_scale=None):
         d = self.device
+        # inputs may come from work queued on the caller's stream
+        self.stream.wait_stream(torch.cuda.current_stream(d))
         with torch.cuda.stream(self.stream):
             self._upd = [_dev(a, torch.float64, d) for a in (xyz, quad_t, quad_scale)]
         _check(load_library().sso_problem_update(self.handle, *[_ptr(a) for a in self._upd]),
@@ -279,6 +281,8 @@ class Problem:
         gx = self._new((self.n_nodes, 3), torch.float64)
         gt = self._new(self.n_quads, torch.float64) if want_t else None
         gs = self._new(self.n_quads, torch.float64) if want_scale else None
+        if dg_du is not None:
+            self.stream.wait_stream(torch.cuda.current_stream(d))
         with torch.cuda.stream(self.stream):
             du = _dev(dg_du, torch.float64, d)
         st = sso_stats()

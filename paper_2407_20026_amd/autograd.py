@@ -11,6 +11,9 @@ forward pass calls ``sso_problem_update`` + ``sso_solve`` and the backward pass 
   per-element stiffness scale s (SIMP: s = rho^P, Sec. 3.4 Eq. 8; chain the power law in torch).
 * :class:`Displacement` -- u as a function of the same inputs; its backward solves the adjoint
   system K lambda = dL/du (Sec. 2.3.1, Eqs. 5-6) with the same K and preconditioner.
+* :class:`BatchCompliance` -- the compliances of V problems of one topology that share the
+  nodal coordinates and thickness and differ in the stiffness scales, their PCG iterations
+  advancing together in multi-problem launches (``sso_batch_iterate``).
 """
 from __future__ import annotations
 
@@ -71,6 +74,54 @@ class Displacement(torch.autograd.Function):
                                 want_t=ctx.has_t, want_scale=ctx.has_s)
         return None, g["dg_dxyz"], g["dg_dt"] if ctx.has_t else None, \
             g["dg_dscale"] if ctx.has_s else None
+
+
+class BatchCompliance(torch.autograd.Function):
+    """c_v = f_v^T u_v (v < V) for problems created on ``batch``'s stream; xyz [n_nodes, 3] and
+    t [n_quads] shared, s [V, n_quads] per problem.  Returns c [V] (float64, problems' device).
+    Backward: dL/dxyz = sum_v dL/dc_v dc_v/dxyz (likewise t), dL/ds_v = dL/dc_v dc_v/ds_v."""
+
+    @staticmethod
+    def forward(ctx, batch, problems, chunk, xyz, t, s):
+        dev = problems[0].device
+        x, tt, ss = _as_f64(xyz, dev), _as_f64(t, dev), _as_f64(s, dev)
+        for v, p in enumerate(problems):
+            p.update(xyz=x, quad_t=tt, quad_scale=ss[v])
+            p.solve_begin()
+        done = [False] * len(problems)
+        while not all(done):
+            done = batch.iterate(problems, chunk)
+        c = []
+        for p in problems:
+            p.solve_end(check=False)
+            if p.last_status not in (0, -4):
+                raise RuntimeError(f"batched solve failed with status {p.last_status}")
+            c.append(p.objective("compliance"))
+        ctx.problems = problems
+        return torch.tensor(c, dtype=torch.float64, device=dev)
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        w = grad_c.to(torch.float64).cpu().tolist()
+        gx = gt = None
+        gs = []
+        for wv, p in zip(w, ctx.problems):
+            g = p.adjoint(OBJ_COMPLIANCE, want_t=True, want_scale=True)
+            with torch.cuda.stream(p.stream):
+                gx = g["dg_dxyz"] * wv if gx is None else gx + g["dg_dxyz"] * wv
+                gt = g["dg_dt"] * wv if gt is None else gt + g["dg_dt"] * wv
+                gs.append(g["dg_dscale"] * wv)
+            stream = p.stream
+        with torch.cuda.stream(stream):
+            gsv = torch.stack(gs)
+        torch.cuda.current_stream(gx.device).wait_stream(stream)
+        for a in (gx, gt, gsv):
+            a.record_stream(torch.cuda.current_stream(gx.device))
+        return None, None, None, gx, gt, gsv
+
+
+def batch_compliance(batch, problems, xyz, t, s, chunk: int = 32):
+    return BatchCompliance.apply(batch, problems, chunk, xyz, t, s)
 
 
 def compliance(problem: Problem, xyz, t=None, s=None):

@@ -18,8 +18,8 @@ import torch
 
 import meshgen
 
-from . import Options, Problem
-from .autograd import compliance
+from . import Batch, Options, Problem
+from .autograd import batch_compliance, compliance
 
 
 class DesignMLP(torch.nn.Module):
@@ -46,10 +46,13 @@ def geometry(net: DesignMLP, xy: torch.Tensor, L: float, quad_nodes: torch.Tenso
 
 
 class ShellBatch:
-    """n_variants problems on one m x m plan; ``loss(net)`` is differentiable in the weights."""
+    """n_variants problems on one m x m plan; ``loss(net)`` is differentiable in the weights.
+    batched=True: the variants' PCG iterations advance together in multi-problem launches on
+    one stream (results bitwise equal to solving them one by one)."""
 
     def __init__(self, m: int = 80, n_variants: int = 256, L: float = 20.0,
-                 options: Options | None = None, device="cuda", density_seed: int = 4000):
+                 options: Options | None = None, device="cuda", density_seed: int = 4000,
+                 batched: bool = False):
         self.base = meshgen.shell(m, L=L, seed=density_seed, flat=True)
         self.L = L
         self.device = torch.device(device)
@@ -59,14 +62,20 @@ class ShellBatch:
                                     dtype=torch.float64, device=self.device)
                     for v in range(n_variants)]
         opts = options or Options(rtol=1e-8)
+        self.batched = batched
+        self.stream = torch.cuda.Stream(device=self.device) if batched else None
+        self.batch = Batch(self.stream, self.device) if batched else None
         self.problems = []
         for v in range(n_variants):
             mv = self.base.copy()
             mv.quad_scale = self.rho[v].cpu().numpy() ** 3
-            self.problems.append(Problem(mv, opts, device=self.device))
+            self.problems.append(Problem(mv, opts, device=self.device, stream=self.stream))
 
     def loss(self, net: DesignMLP):
         xyz, t = geometry(net, self.xy, self.L, self.quads)
+        if self.batched:
+            s = torch.stack(self.rho) ** 3
+            return batch_compliance(self.batch, self.problems, xyz, t, s).mean()
         total = 0.0
         for prob, rho in zip(self.problems, self.rho):
             total = total + compliance(prob, xyz, t, rho ** 3)
@@ -76,3 +85,6 @@ class ShellBatch:
         for p in self.problems:
             p.close()
         self.problems = []
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None

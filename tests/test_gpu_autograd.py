@@ -91,3 +91,26 @@ def test_displacement_backward_matches_oracle_adjoint():
         1e-8 * np.abs(ref["grad_t"]).max()
     assert np.abs(s.grad.cpu().numpy() - ref["grad_scale"]).max() <= \
         1e-8 * np.abs(ref["grad_scale"]).max()
+
+
+def test_batched_network_batch_matches_one_by_one():
+    """The variants' solves advancing together in multi-problem launches give the loss and the
+    network gradient of the one-by-one form (each solve is bitwise the same; only the order in
+    which the per-variant gradients are summed differs)."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch
+    print("[gpu] shellnet batched vs one by one", flush=True)
+    out = []
+    for batched in (False, True):
+        b = ShellBatch(m=8, n_variants=4, L=20.0, options=sso.Options(rtol=1e-10),
+                       batched=batched)
+        net = DesignMLP().to("cuda")
+        loss = b.loss(net)
+        loss.backward()
+        out.append((loss.item(), [p.grad.detach().cpu().numpy().copy()
+                                  for p in net.parameters()]))
+        b.close()
+    (l0, g0), (l1, g1) = out
+    assert l1 == pytest.approx(l0, rel=1e-14)
+    for a, c in zip(g0, g1):
+        np.testing.assert_allclose(c, a, rtol=1e-12, atol=1e-12 * np.abs(a).max())
