@@ -66,7 +66,7 @@ enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
 /* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
  * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one
  * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
- * of K's size).  AUTO = FUSED. */
+ * of K's size).  AUTO: FUSED up to 20,000 nodes (latency-bound sizes), STANDARD above. */
 enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */

@@ -1164,10 +1164,14 @@ void batch_free(BatchWork& bw, hipStream_t s) {
   bw = BatchWork();
 }
 
+// Up to this many nodes the single launch per iteration of the single-reduction recurrences wins
+// (the 60 x 60 shell: 19.1 vs 21.0 ms per solve); on large problems the standard pair streams
+// closer to the bandwidth peak (the 300 x 300 shell: 80 vs 125 us per iteration).
+static constexpr int64_t FUSED_MAX_NODES = 20000;
+
 int pcg_pick_solver(int solver, int64_t n_nodes) {
-  (void)n_nodes;
   if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED) return solver;
-  return SSO_SOLVER_FUSED;
+  return n_nodes <= FUSED_MAX_NODES ? SSO_SOLVER_FUSED : SSO_SOLVER_STANDARD;
 }
 
 hipError_t launch_right_precondition(const Pattern& pat, const double* K, const double* Dinv,

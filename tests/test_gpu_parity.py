@@ -162,7 +162,9 @@ def test_gradient_general_objective(refs, name, objective):
     else:
         a = rng.normal(size=mesh.n_dof)
     r = oracle.analyze(mesh, objective, a=a, dg_du=a, pat=pat)
-    with _problem(mesh) as p:
+    # the adjoint solve runs to the problem's rtol on the true residual, so it must be above
+    # the FP64 floor (~3e-11 on the grid-shell) for the call to report success
+    with _problem(mesh, rtol=1e-10) as p:
         _solve_tight(p)
         if objective == "linear":
             assert p.objective("linear", a) == pytest.approx(r["g"], rel=1e-9)
