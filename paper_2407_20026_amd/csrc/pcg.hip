@@ -784,17 +784,52 @@ __global__ void k_refine_update(int64_t n, double alpha, const float* d, double*
 
 }  // namespace
 
-// Workgroups of the PCG kernels: one pass of 18 block rows each, at most 1024 (every
-// workgroup re-reads all partials, so their number bounds that cost); grid-stride beyond.
-static int choose_wg(int64_t n_nodes) {
-  int64_t g = (n_nodes + ROWS_PER_WG - 1) / ROWS_PER_WG;
-  return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+// Workgroups of the given iteration kernels that are resident on the current device at once
+// (occupancy x compute units), at most 1024 (every workgroup re-reads all partials, so their
+// number bounds that cost).  A grid-stride launch of exactly this many workgroups runs in one
+// round: a larger grid would leave a partial second round of workgroups behind.
+static int resident_wg(const void* const* kernels, int n_kernels) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 1024;
+  int per_cu = 1 << 30;
+  for (int k = 0; k < n_kernels; ++k) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernels[k], MAX_TPB, 0) != hipSuccess)
+      return 1024;
+    if (b < per_cu) per_cu = b;
+  }
+  const int64_t r = (int64_t)(per_cu < 1 ? 1 : per_cu) * cus;
+  return (int)(r > 1024 ? 1024 : r);
 }
 
-// Partial-sum buffers (units of the stride S = max(n_wg, 1024) doubles):
+static int resident_standard() {
+  static const void* const ks[] = {
+      reinterpret_cast<const void*>(&k_spmv_dir<double>),
+      reinterpret_cast<const void*>(&k_update<double>),
+      reinterpret_cast<const void*>(&k_spmv_dir<float>),
+      reinterpret_cast<const void*>(&k_update<float>)};
+  return resident_wg(ks, 4);
+}
+
+static int resident_fused() {
+  static const void* const ks[] = {reinterpret_cast<const void*>(&k_cg1_iter<double>),
+                                   reinterpret_cast<const void*>(&k_cg1_iter<float>)};
+  return resident_wg(ks, 2);
+}
+
+// Workgroups of a PCG launch: one pass of 18 block rows each, at most `cap`; grid-stride beyond.
+static int choose_wg(int64_t n_nodes, int cap) {
+  int64_t g = (n_nodes + ROWS_PER_WG - 1) / ROWS_PER_WG;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+// Partial-sum buffers (units of the stride S = 1024 >= n_wg, n_wg_f doubles):
 //   [0, S) pA | [S, 3S) pB | [3S, 5S) one-off reductions, then 8 scalars |
 //   [5S + 8, 8S + 8) single-reduction even | [8S + 8, 11S + 8) single-reduction odd
-static int partial_stride(const PcgWork& w) { return w.n_wg > 1024 ? w.n_wg : 1024; }
+static int partial_stride(const PcgWork&) { return 1024; }
 static size_t partial_total(const PcgWork& w) { return 11 * (size_t)partial_stride(w) + 16; }
 static double* part_a(PcgWork& w) { return w.partials; }
 static double* part_b(PcgWork& w) { return w.partials + partial_stride(w); }
@@ -805,7 +840,8 @@ static double* part_fused(PcgWork& w, int k) {
 
 hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
   w.n_dof = 6 * n_nodes;
-  w.n_wg = choose_wg(n_nodes);
+  w.n_wg = choose_wg(n_nodes, resident_standard());
+  w.n_wg_f = choose_wg(n_nodes, resident_fused());
   hipError_t e;
   if ((e = dev_alloc(&w.r, w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.z, w.n_dof , s)) != hipSuccess) return e;
@@ -824,7 +860,7 @@ hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
     return e;
   if ((e = dev_alloc(reinterpret_cast<FusedDesc<float>**>(&w.fdesc32), 1, s)) != hipSuccess)
     return e;
-  if ((e = dev_alloc(&w.jw, w.n_wg, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.jw, w.n_wg_f, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(w.st, 0, sizeof(PcgState), s)) != hipSuccess) return e;
   w.h_st = new PcgState();
   if (mixed) return pcg_alloc_mixed(w, s);
@@ -995,7 +1031,7 @@ static FusedDesc<T> fused_desc(const Mesh& m, const Pattern& pat, const T* B, co
   hd.jw = w.jw;
   hd.st = w.st;
   hd.n_nodes = m.n_nodes;
-  hd.n_wg = w.n_wg;
+  hd.n_wg = w.n_wg_f;
   hd.wg_base = 0;
   return hd;
 }
@@ -1351,7 +1387,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
   hipError_t e = mixed_begin(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
   while (e == hipSuccess && !ms.done) {
     int it = 0, st = SSO_OK;
-    const int nwg = w.n_wg;
+    const int nwg = B32 ? w.n_wg_f : w.n_wg;
     const int left = mp.max_it - ms.iters;
     if (B32) {
       const FusedDesc<float>* dd = reinterpret_cast<const FusedDesc<float>*>(w.fdesc32);

@@ -175,7 +175,8 @@ hipError_t launch_scalar_values(const Mesh& m, const Pattern& pat, const double*
 // pcg.hip
 struct PcgWork {
   int64_t n_dof = 0;
-  int n_wg = 0;            // workgroups of the PCG kernels (grid-stride over the rows)
+  int n_wg = 0;            // workgroups of the standard PCG kernels (grid-stride over the rows)
+  int n_wg_f = 0;          // workgroups of the single-reduction kernels
   double* r = nullptr;
   double* z = nullptr;
   double* p[2] = {nullptr, nullptr};
