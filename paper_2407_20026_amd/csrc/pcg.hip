@@ -1286,7 +1286,8 @@ hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const
 // and x += |r| d in FP64, until |r| <= rtol |b| or refinement stalls.
 // Mixed precision as a step machine, so that single solves and multi-problem launches share
 // it.  mixed_next: with the FP64 iterate x, recompute the true residual r = b - K x in FP64 and
-// either stop (converged, refinement limit, stalled, iteration budget, breakdown) or start the
+// either stop (converged, refinement limit, stalled, iteration budget, breakdown; a correction
+// that raised the residual is undone) or start the
 // next FP32 inner solve K d = r / |r| (tolerance: the reduction still missing, with a factor 2
 // of margin, clamped to [inner_rtol, 0.5]).  mixed_inner_done: after the inner solve stopped,
 // x += |r| d, then mixed_next.
@@ -1304,6 +1305,15 @@ static hipError_t mixed_next(const Mesh& m, const Pattern& pat, const double* K,
   const double rn = std::sqrt(h[0]), bn = std::sqrt(h[1]);
   const int left = mp.max_it - ms.iters;
   ms.done = true;
+  if (ms.prev >= 0.0 && !(rn < ms.prev)) {
+    // the last correction made the residual worse (the FP32 operator is too far from K for
+    // this conditioning): return the previous iterate
+    if ((e = hipMemcpyAsync(x, w.xc, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s)) !=
+        hipSuccess)
+      return e;
+    ms.status = SSO_ENOTCONV;
+    return hipSuccess;
+  }
   if (!std::isfinite(rn)) {
     ms.status = SSO_EBREAKDOWN;
     return hipSuccess;
@@ -1353,9 +1363,10 @@ static hipError_t mixed_inner_done(const Mesh& m, const Pattern& pat, const doub
     return hipSuccess;
   }
   const int64_t n = w.n_dof;
-  hipLaunchKernelGGL(k_refine_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, ms.rn, w.x32, x);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipMemcpyAsync(w.xc, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_refine_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, ms.rn, w.x32, x);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
 }
 

@@ -41,7 +41,7 @@ def test_network_batch_gradient_vs_oracle_fd():
     from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch
     print("[gpu] shellnet batch 8x8 x 3 variants", flush=True)
     L = 20.0
-    batch = ShellBatch(m=8, n_variants=3, L=L, options=sso.Options(rtol=1e-10, max_it=50000))
+    batch = ShellBatch(m=8, n_variants=3, L=L, options=sso.Options(rtol=1e-12, max_it=50000))
     net = DesignMLP().to("cuda")
     loss = batch.loss(net)
     loss.backward()
