@@ -585,8 +585,9 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
   const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
   const FusedDesc<T>& d = *W.d;
   PcgState* st = d.st;
-  if (st->done) return;
+  const int done = st->done;
   const int i = d.jw[W.lb];
+  if (done) return;
   const int n_nodes = d.n_nodes;
   const T* __restrict__ ri = d.r[i & 1];
   const T* __restrict__ wi = d.w[i & 1];
@@ -598,6 +599,21 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
   T* __restrict__ x = d.x;
   const SpLane L = sp_lane();
   const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
+  // scalars of the previous iterations and this thread's share of the previous launch's
+  // partial sums (same order as finish_partials): their loads are in flight during the first
+  // pass's row products
+  const double ff_prev = st->ff, rtol2 = st->rtol2;
+  const double gam_prev = st->rzs[(i - 1) & 1], alpha_prev = st->alphas[(i - 1) & 1];
+  const int max_it = st->max_it;
+  double tot[3] = {0.0, 0.0, 0.0};
+  {
+    const double* pp = d.pp[i & 1];
+    for (int k = threadIdx.x; k < W.ng; k += blockDim.x) {
+      tot[0] += pp[k];
+      tot[1] += pp[W.ng + k];
+      tot[2] += pp[2 * W.ng + k];
+    }
+  }
   T alpha = 0, beta = 0, ab = 0;
   T v[3] = {0, 0, 0};
   for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
@@ -605,35 +621,36 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
     const bool ok = L.ok && I < n_nodes;
     const bool own = ok && L.b == 0;
     const int64_t q = 6 * (int64_t)I + L.a;
-    T br = 0, bw = 0, bs = 0;
-    if (ok) row_product3<T>(d.brow_ptr, d.bcol, d.B, ri, wi, so, I, L.a, L.b, br, bw, bs);
     T rq = 0, wq = 0, sq = 0, pq = 0, xq = 0;
-    if (own) {
+    DinvRow<T> M{};
+    if (own) {   // own-row operands, independent of the row products
       rq = ri[q];
       wq = wi[q];
       sq = so[q];
       pq = p[q];
       xq = x[q];
+      M = dinv_row(d.Dinv, I, L.a);
     }
+    T br = 0, bw = 0, bs = 0;
+    if (ok) row_product3<T>(d.brow_ptr, d.bcol, d.B, ri, wi, so, I, L.a, L.b, br, bw, bs);
     if (gi == W.lb) {
-      double tot[3];
-      finish_partials<3>(d.pp[i & 1], W.ng, tot);
+      block_sum<3, double>(tot);
       const double gam = tot[0], del = tot[1], rho = tot[2];
-      const double ff = (i == 0) ? rho : st->ff;
+      const double ff = (i == 0) ? rho : ff_prev;
       double beta_d = 0.0, alpha_d;
       if (i == 0) {
         alpha_d = gam / del;
       } else {
-        beta_d = gam / st->rzs[(i - 1) & 1];
-        alpha_d = gam / (del - beta_d * gam / st->alphas[(i - 1) & 1]);
+        beta_d = gam / gam_prev;
+        alpha_d = gam / (del - beta_d * gam / alpha_prev);
       }
       int stop = 0, status = SSO_OK;
       if (!std::isfinite(rho) || !std::isfinite(gam)) {
         stop = 1;
         status = SSO_EBREAKDOWN;
-      } else if (rho <= st->rtol2 * ff) {
+      } else if (rho <= rtol2 * ff) {
         stop = 1;
-      } else if (i >= st->max_it) {
+      } else if (i >= max_it) {
         stop = 1;
         status = SSO_ENOTCONV;
       } else if (!(alpha_d > 0.0) || !std::isfinite(alpha_d)) {
@@ -659,10 +676,8 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
     const T wv = sum3(br - alpha * bw - ab * bs, L.lane);
     if (own) rs[0][6 * slot + L.a] = rq;
     __syncthreads();
-    DinvRow<T> M{};
     T rv = 0;
     if (own) {
-      M = dinv_row(d.Dinv, I, L.a);
       const T pv = M.apply(rs[0] + 6 * slot) + beta * pq;
       const T sv = wq + beta * sq;
       p[q] = pv;
