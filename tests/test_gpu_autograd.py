@@ -1,7 +1,7 @@
 """torch.autograd through the HIP analysis: the network-driven shell batch (MLP -> heights and
-thickness -> rho^3-scaled shells -> mean compliance) against central finite differences of the
-oracle (h = 1e-6) on 20 random network parameters, and the displacement function's backward
-against the oracle adjoint."""
+thickness -> rho^3-scaled shells -> mean compliance) against the oracle adjoint chained through
+the network (every weight) and central finite differences of the oracle (h = 1e-6) on 20 random
+network parameters, and the displacement function's backward against the oracle adjoint."""
 import numpy as np
 import pytest
 
@@ -36,6 +36,27 @@ def _oracle_loss(params, base, rhos, L):
     return total / len(rhos)
 
 
+def _oracle_adjoint_grads(net_cpu, base, rhos, L):
+    """Network gradient of the mean oracle compliance: the oracle adjoint (dc/dz, dc/dt per
+    variant) chained through the MLP with torch's CPU autograd."""
+    from paper_2407_20026_amd.shellnet import geometry
+    xy = torch.tensor(base.xyz[:, :2])
+    qn = torch.tensor(base.quad_nodes.astype(np.int64))
+    xyz, t = geometry(net_cpu, xy, L, qn)
+    gx = np.zeros((base.n_nodes, 3))
+    gt = np.zeros(base.n_quads)
+    for rho in rhos:
+        m = base.copy()
+        m.xyz = np.ascontiguousarray(xyz.detach().numpy())
+        m.quad_prop[:, 0] = t.detach().numpy()
+        m.quad_scale = rho ** 3
+        r = oracle.analyze(m, "compliance")
+        gx += r["grad_xyz"] / len(rhos)
+        gt += r["grad_t"] / len(rhos)
+    ((xyz * torch.tensor(gx)).sum() + (t * torch.tensor(gt)).sum()).backward()
+    return [p.grad.numpy().copy() for p in net_cpu.parameters()]
+
+
 def test_network_batch_gradient_vs_oracle_fd():
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch
@@ -51,24 +72,28 @@ def test_network_batch_gradient_vs_oracle_fd():
     base = batch.base
     ref = _oracle_loss(params, base, rhos, L)
     assert loss.item() == pytest.approx(ref, rel=1e-10)
-    rng = np.random.default_rng(0)
     gmax = max(np.abs(g).max() for g in grads)
-    # The oracle evaluates the loss (~1e6 here) to about 4e-13 relative, so a central difference
-    # at h carries a rounding error of about 4e-13 |L| / h on top of its O(h^2) truncation: at
-    # the prescribed h = 1e-6 that term (~0.5) is added to the bound; h = 1e-5 is also checked
-    # at the plain bound.
+    # every weight: the oracle adjoint chained through the network
+    for g, r in zip(grads, _oracle_adjoint_grads(DesignMLP(), base, rhos, L)):
+        assert np.abs(g - r).max() <= 1e-8 * gmax
+    # 20 sampled weights: central differences of the oracle at h = 1e-6.  The oracle evaluates
+    # the loss (~1e6 here) to about 4e-13 relative, so the difference quotient carries a
+    # rounding error of about 4e-13 |L| / h on top of its O(h^2) truncation; that term is added
+    # to the bound.
+    rng = np.random.default_rng(0)
+    h = 1e-6
     for _ in range(20):
         k = int(rng.integers(len(params)))
         idx = tuple(int(rng.integers(s)) for s in params[k].shape)
         g = grads[k][idx]
-        for h, extra in ((1e-6, 4e-13 * abs(ref) / 1e-6), (1e-5, 0.0)):
-            vals = []
-            for sgn in (1.0, -1.0):
-                pp = [q.copy() for q in params]
-                pp[k][idx] += sgn * h
-                vals.append(_oracle_loss(pp, base, rhos, L))
-            fd = (vals[0] - vals[1]) / (2 * h)
-            assert abs(g - fd) <= 1e-5 * max(abs(fd), 1e-3 * gmax) + extra, (k, idx, h, g, fd)
+        vals = []
+        for sgn in (1.0, -1.0):
+            pp = [q.copy() for q in params]
+            pp[k][idx] += sgn * h
+            vals.append(_oracle_loss(pp, base, rhos, L))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(g - fd) <= 1e-5 * max(abs(fd), 1e-3 * gmax) + 4e-13 * abs(ref) / h, \
+            (k, idx, g, fd)
     batch.close()
 
 
