@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=16,
                     help="also time this many problems of the workload (seeds 1..n) advancing "
                          "together in multi-problem launches (0: skip)")
+    ap.add_argument("--general-steps", type=int, default=5,
+                    help="also time this many steps with a linear objective (second PCG "
+                         "for the adjoint; 0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the workload, copy a float64 tensor of this many MiB 3 times "
                          "(a plain copy kernel of known size for scaling HBM counters)")
@@ -168,6 +171,33 @@ def batch_bench(gen_seed, n_problems, rtol, objective):
     return {"problems": n_problems, "solves_per_s": n_problems / el,
             "dof_per_s": sum(m.n_dof for m in meshes) / el, "wall_ms": 1000 * el,
             "note": "same generator, seeds 1..n; all problems in flight together"}
+
+
+def general_objective_bench(mesh, opts, steps):
+    """The same workload with a linear objective g = u_z at the centre node: its adjoint is a
+    second PCG solve (K lambda = a), unlike compliance where lambda = u."""
+    import torch
+    import paper_2407_20026_amd as sso
+    a = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+    a[6 * (mesh.n_nodes // 2) + 2] = 1.0
+    adj = []
+    with sso.Problem(mesh, opts) as prob:
+        def step():
+            prob.solve(check=False)
+            if prob.last_status not in (sso.SSO_OK, sso.SSO_ENOTCONV):
+                raise sso.SSOError(prob.last_status, "sso_solve")
+            prob.objective("linear", a)
+            adj.append(prob.adjoint("linear", dg_du=a)["stats"]["iters"])
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    log(f"general objective: {1000 * el / steps:.2f} ms/step")
+    return {"objective": "linear (u_z at the centre node)", "solves_per_s": steps / el,
+            "ms_per_step": 1000 * el / steps, "adjoint_pcg_iters": int(np.median(adj))}
 
 
 def copy_calibration(mib):
@@ -281,6 +311,8 @@ def main():
                      "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},
     }
     prob.close()
+    if args.objective != "linear" and args.general_steps > 0:
+        out["general_objective"] = general_objective_bench(mesh, opts, args.general_steps)
     if args.batch > 0 and args.workload in SEEDED and args.objective != "linear":
         out["batched"] = batch_bench(SEEDED[args.workload], args.batch, args.rtol,
                                      args.objective)

@@ -209,9 +209,8 @@ __device__ inline T sum3(T acc, int lane) {
 }
 
 // sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
-// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Six blocks per step
-// (a shell row has 4 to 9) keep 18 loads per lane in flight; measured 15 % faster than three on
-// the 300 x 300 shell.
+// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Three blocks per step
+// (measured on the 300 x 300 shell: 67 us per launch, against 77 us with six blocks per step).
 template <class T>
 __device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
                                     const int32_t* __restrict__ bcol, const T* __restrict__ K,
@@ -222,19 +221,6 @@ __device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
   const int off = 6 * a + b;
   T sz = 0, sp = 0;
   int s = rb;
-  for (; s + 6 <= re; s += 6) {   // six blocks per step: 12 loads in flight per lane
-    int64_t J[6];
-    V kk[6], zz[6], pp[6];
-    for (int u = 0; u < 6; ++u) J[u] = bcol[s + u];
-    for (int u = 0; u < 6; ++u)
-      kk[u] = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + u) + off);
-    for (int u = 0; u < 6; ++u) zz[u] = *reinterpret_cast<const V*>(z + 6 * J[u] + b);
-    for (int u = 0; u < 6; ++u) pp[u] = *reinterpret_cast<const V*>(p + 6 * J[u] + b);
-    for (int u = 0; u < 6; ++u) {
-      sz += kk[u].x * zz[u].x + kk[u].y * zz[u].y;
-      sp += kk[u].x * pp[u].x + kk[u].y * pp[u].y;
-    }
-  }
   for (; s + 3 <= re; s += 3) {
     const int64_t J0 = bcol[s], J1 = bcol[s + 1], J2 = bcol[s + 2];
     const V k0 = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
@@ -594,7 +580,7 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
 }
 
 template <class T>
-__global__ void __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(MAX_TPB)
 k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   __shared__ T rs[2][ROWS_PER_WG * 6];
   const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
@@ -614,21 +600,12 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
   T* __restrict__ x = d.x;
   const SpLane L = sp_lane();
   const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
-  // scalars of the previous iterations and this thread's share of the previous launch's
-  // partial sums (same order as finish_partials): their loads are in flight during the first
-  // pass's row products
+  // scalars of the previous iterations: their loads are in flight during the first pass's row
+  // products (loading the partials early as well cost registers, and an occupancy step, that
+  // multi-problem launches pay for)
   const double ff_prev = st->ff, rtol2 = st->rtol2;
   const double gam_prev = st->rzs[(i - 1) & 1], alpha_prev = st->alphas[(i - 1) & 1];
   const int max_it = st->max_it;
-  double tot[3] = {0.0, 0.0, 0.0};
-  {
-    const double* pp = d.pp[i & 1];
-    for (int k = threadIdx.x; k < W.ng; k += blockDim.x) {
-      tot[0] += pp[k];
-      tot[1] += pp[W.ng + k];
-      tot[2] += pp[2 * W.ng + k];
-    }
-  }
   T alpha = 0, beta = 0, ab = 0;
   T v[3] = {0, 0, 0};
   for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
@@ -649,7 +626,8 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
       M = dinv_row(d.Dinv, I, L.a);
     }
     if (gi == W.lb) {
-      block_sum<3, double>(tot);
+      double tot[3];
+      finish_partials<3>(d.pp[i & 1], W.ng, tot);
       const double gam = tot[0], del = tot[1], rho = tot[2];
       const double ff = (i == 0) ? rho : ff_prev;
       double beta_d = 0.0, alpha_d;
