@@ -29,6 +29,15 @@ import numpy as np  # noqa: E402
 import meshgen  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters
+# (KiB per dispatch, mean over working launches) scaled by what they read for a plain 256 MiB
+# copy (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel code they were taken on: an
+# entry is removed when that kernel changes.
+MEASURED_TRAFFIC = {
+    ("shell60", "fp64", "k_cg1_iter"): (6470.2 * 2.000 + 898.1 * 1.000) * 1024,
+    ("shell300", "fp64", "k_spmv_dir"): (128304.8 * 2.000 + 8528.7 * 1.000) * 1024,
+}
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
 WORKLOADS = {
@@ -69,6 +78,9 @@ def parse():
     ap.add_argument("--general-steps", type=int, default=5,
                     help="also time this many steps with a linear objective (second PCG "
                          "for the adjoint; 0: skip)")
+    ap.add_argument("--shellnet", type=int, default=0,
+                    help="also time one loss + backward of the network-driven batch of this "
+                         "many 80 x 80 shells (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the workload, copy a float64 tensor of this many MiB 3 times "
                          "(a plain copy kernel of known size for scaling HBM counters)")
@@ -200,6 +212,39 @@ def general_objective_bench(mesh, opts, steps):
             "ms_per_step": 1000 * el / steps, "adjoint_pcg_iters": int(np.median(adj))}
 
 
+def shellnet_bench(n_variants, m=80):
+    """The network-driven batch: n_variants shells on an m x m plan, heights and thickness from
+    the MLP, element stiffness scaled by rho^3; one loss (mean compliance) + backward into the
+    network weights, the variants' PCG iterations advancing together in multi-problem launches.
+    Timed: the second of two passes."""
+    import torch
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch
+    t0 = time.perf_counter()
+    b = ShellBatch(m=m, n_variants=n_variants, options=sso.Options(rtol=1e-8), batched=True)
+    log(f"shellnet: {n_variants} problems created in {time.perf_counter() - t0:.1f} s")
+    net = DesignMLP().to("cuda")
+    try:
+        times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            net.zero_grad()
+            loss = b.loss(net)
+            loss.backward()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            log(f"shellnet: loss + backward {times[-1]:.2f} s")
+        iters = [p.last_stats["iters"] for p in b.problems]
+        n_dof = b.problems[0].n_dof
+    finally:
+        b.close()
+    return {"variants": n_variants, "mesh": f"{m}x{m} quads", "n_dof_per_variant": n_dof,
+            "loss_and_backward_s": times[-1], "solves_per_s": n_variants / times[-1],
+            "dof_per_s": n_variants * n_dof / times[-1], "loss": float(loss.item()),
+            "pcg_iters_median": int(np.median(iters)), "pcg_iters_max": int(max(iters))}
+
+
 def copy_calibration(mib):
     import torch
     n = mib * (1 << 20) // 8
@@ -307,7 +352,8 @@ def main():
                    "stopped above rtol (FP64 residual floor)"},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": spmv_bytes,
+                     "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision, kernel)),
+                     "bytes_per_launch": spmv_bytes,
                      "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},
     }
     prob.close()
@@ -316,6 +362,8 @@ def main():
     if args.batch > 0 and args.workload in SEEDED and args.objective != "linear":
         out["batched"] = batch_bench(SEEDED[args.workload], args.batch, args.rtol,
                                      args.objective)
+    if args.shellnet > 0:
+        out["shellnet"] = shellnet_bench(args.shellnet)
     if args.serve_requests > 0:
         out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec)
                           for prec in ("fp64", "mixed")}

@@ -110,9 +110,10 @@ typedef struct {
   double t_solve_us;          /* PCG                                                         */
   double t_adj_us;            /* adjoint solve + element contraction + gather (sso_adjoint)  */
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
-  double spmv_us;             /* mean duration of the sampled SpMV launches (profile_every):
-                                 k_spmv_dir for the standard recurrences, the whole fused
-                                 iteration k_cg1_iter for the single-reduction ones         */
+  double spmv_us;             /* mean duration per launch of the sampled iteration kernel
+                                 (profile_every): k_spmv_dir of the standard recurrences,
+                                 timed alone; k_cg1_iter of the single-reduction ones, timed
+                                 over 8 back-to-back launches (dispatch gaps included)      */
   int32_t spmv_samples;       /* number of sampled SpMV launches                             */
   double spmv_bytes;          /* algorithmic bytes of one such launch                        */
   int32_t refine_steps;       /* mixed precision: FP32 inner solves run                      */

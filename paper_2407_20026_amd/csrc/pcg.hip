@@ -878,13 +878,17 @@ void pcg_free(PcgWork& w, hipStream_t s) {
 }
 
 static constexpr int PROF_CAP = 4096;
+static constexpr int FUSED_SPAN = 8;   // launches per timing sample of the fused iteration
 
 // Launch iterations in chunks of growing size (8 .. 64), reading the state record back after
-// each chunk; launch(e0, e1) enqueues one iteration and, when e0 is not null, records e0 and e1
-// around the kernel that is profiled.  Launches past convergence return at entry.  The
-// sampled durations (launch index below the iteration count) go to w.prof_us / w.prof_n.
+// each chunk; launch(e0, e1) enqueues one iteration, recording e0 (when not null) before the
+// kernel that is profiled and e1 (when not null) after it.  A sample starts at every
+// profile_every-th launch and spans `span` consecutive launches (span divides 8, so a sample
+// never crosses a chunk); launches past convergence return at entry, so only samples that end
+// below the iteration count are kept: their mean duration per launch goes to w.prof_us /
+// w.prof_n.
 template <class F>
-static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_every,
+static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_every, int span,
                              const F& launch, int* iters, int* status) {
   hipError_t e;
   if (profile_every > 0 && !w.prof_ev) {
@@ -893,19 +897,19 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
       if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
     w.prof_cap = PROF_CAP;
   }
+  if (profile_every > 0 && profile_every < span) profile_every = span;
   int n_prof = 0;
   int64_t launched = 0;
   int chunk = 8;
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
       const int64_t gk = launched + i;
-      const bool prof = profile_every > 0 && gk % profile_every == 0 && n_prof < w.prof_cap;
-      if (prof) {
-        launch(&w.prof_ev[2 * n_prof], &w.prof_ev[2 * n_prof + 1]);
-        ++n_prof;
-      } else {
-        launch(nullptr, nullptr);
-      }
+      const int64_t ph = profile_every > 0 ? gk % profile_every : -1;
+      const bool first = ph == 0 && n_prof < w.prof_cap;
+      const bool last = ph == span - 1 && n_prof < w.prof_cap;
+      launch(first ? &w.prof_ev[2 * n_prof] : nullptr,
+             last ? &w.prof_ev[2 * n_prof + 1] : nullptr);
+      if (last) ++n_prof;
     }
     launched += chunk;
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -919,10 +923,10 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
   *iters = w.h_st->it;
   *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
   for (int i = 0; i < n_prof; ++i) {
-    if ((int64_t)i * profile_every >= *iters) break;
+    if ((int64_t)i * profile_every + span > *iters) break;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) {
-      w.prof_us += 1000.0 * ms;
+      w.prof_us += 1000.0 * ms / span;
       ++w.prof_n;
     }
   }
@@ -978,7 +982,7 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
     if (e1) (void)hipEventRecord(*e1, s);
     hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
   };
-  return run_polled(w, s, max_it, profile_every, launch, iters, status);
+  return run_polled(w, s, max_it, profile_every, 1, launch, iters, status);
 }
 
 // Vectors of one single-reduction solve.
@@ -1047,7 +1051,8 @@ static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const
     hipLaunchKernelGGL(k_cg1_iter<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
     if (e1) (void)hipEventRecord(*e1, s);
   };
-  return run_polled(w, s, max_it, profile_every, launch, iters, status);
+  // the only kernel of an iteration: samples of 8 back-to-back launches
+  return run_polled(w, s, max_it, profile_every, FUSED_SPAN, launch, iters, status);
 }
 
 static hipError_t fused_alloc(PcgWork& w, bool f32, hipStream_t s) {
@@ -1387,7 +1392,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
         hipLaunchKernelGGL(k_cg1_iter<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
         if (e1) (void)hipEventRecord(*e1, s);
       };
-      e = run_polled(w, s, left, profile_every, launch, &it, &st);
+      e = run_polled(w, s, left, profile_every, FUSED_SPAN, launch, &it, &st);
     } else {
       const PcgDesc<float>* dd = reinterpret_cast<const PcgDesc<float>*>(w.desc32);
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
@@ -1396,7 +1401,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
         if (e1) (void)hipEventRecord(*e1, s);
         hipLaunchKernelGGL(k_update<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
       };
-      e = run_polled(w, s, left, profile_every, launch, &it, &st);
+      e = run_polled(w, s, left, profile_every, 1, launch, &it, &st);
     }
     if (e == hipSuccess) e = mixed_inner_done(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
   }
