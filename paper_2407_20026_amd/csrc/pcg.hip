@@ -29,6 +29,8 @@ namespace {
 
 constexpr int MAX_TPB = 384;
 constexpr int MAX_WAVES = MAX_TPB / 64;
+// Workgroups of a PCG launch at most (grid-stride beyond); see choose_wg.
+constexpr int PCG_MAX_WG = 1024;
 
 inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
@@ -451,15 +453,14 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
 // before the previous partials are finished.  r, w, s and the partials are double-buffered by
 // iteration parity and every workgroup keeps its own iteration counter.
 
-// sum over the block row of B[s][a][b..b+1] . (r, w, t) (three accumulators).
+// sum over the block slots [rb, re) of one block row of B[s][a][b..b+1] . (r, w, t) (three
+// accumulators).
 template <class T>
-__device__ inline void row_product3(const int32_t* __restrict__ brow_ptr,
-                                    const int32_t* __restrict__ bcol, const T* __restrict__ B,
-                                    const T* __restrict__ r, const T* __restrict__ w,
-                                    const T* __restrict__ t, int I, int a, int b, T& ar, T& aw,
-                                    T& at) {
+__device__ inline void row_product3(int rb, int re, const int32_t* __restrict__ bcol,
+                                    const T* __restrict__ B, const T* __restrict__ r,
+                                    const T* __restrict__ w, const T* __restrict__ t, int a,
+                                    int b, T& ar, T& aw, T& at) {
   using V = typename Vec2<T>::type;
-  const int rb = brow_ptr[I], re = brow_ptr[I + 1];
   const int off = 6 * a + b;
   T sr = 0, sw = 0, st = 0;
   int s = rb;
@@ -579,16 +580,22 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
   write_partials<3, T>(v, d.pp[0], W.lb, W.ng);
 }
 
-template <class T>
-__global__ void __launch_bounds__(MAX_TPB)
-k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+// One single-reduction iteration for workgroup lb of ng.  SINGLE (one problem, launched by its
+// own host loop): the iteration index comes from the host (launch k is iteration k until the
+// state says done) and every load that does not depend on another -- done flag, state scalars,
+// the previous partials, row pointers, own-row operands -- is issued before the done test, so
+// an iteration costs three dependent memory round trips (row pointers, column indices and
+// values, gathered vectors).  Otherwise (multi-problem launches) the index is the workgroup's
+// own counter and the partials are loaded where they are summed, which keeps the register
+// count, and the occupancy that many problems in flight need, lower.
+template <class T, bool SINGLE>
+__device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int ng,
+                                              int i_host) {
   __shared__ T rs[2][ROWS_PER_WG * 6];
-  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
-  const FusedDesc<T>& d = *W.d;
   PcgState* st = d.st;
   const int done = st->done;
-  const int i = d.jw[W.lb];
-  if (done) return;
+  const int i = SINGLE ? i_host : d.jw[lb];
+  if (!SINGLE && done) return;
   const int n_nodes = d.n_nodes;
   const T* __restrict__ ri = d.r[i & 1];
   const T* __restrict__ wi = d.w[i & 1];
@@ -600,34 +607,69 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
   T* __restrict__ x = d.x;
   const SpLane L = sp_lane();
   const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
-  // scalars of the previous iterations: their loads are in flight during the first pass's row
-  // products (loading the partials early as well cost registers, and an occupancy step, that
-  // multi-problem launches pay for)
   const double ff_prev = st->ff, rtol2 = st->rtol2;
   const double gam_prev = st->rzs[(i - 1) & 1], alpha_prev = st->alphas[(i - 1) & 1];
   const int max_it = st->max_it;
+  static_assert(3 * MAX_TPB >= PCG_MAX_WG, "three partials per thread");
+  double pv[3][3] = {};
   T alpha = 0, beta = 0, ab = 0;
   T v[3] = {0, 0, 0};
-  for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
+  for (int gi = lb; gi * ROWS_PER_WG < n_nodes; gi += ng) {
     const int I = gi * ROWS_PER_WG + slot;
     const bool ok = L.ok && I < n_nodes;
     const bool own = ok && L.b == 0;
     const int64_t q = 6 * (int64_t)I + L.a;
-    T br = 0, bw = 0, bs = 0;
-    if (ok) row_product3<T>(d.brow_ptr, d.bcol, d.B, ri, wi, so, I, L.a, L.b, br, bw, bs);
+    // loads without branches (lanes past the last row read row 0 and discard it), so that no
+    // merge of a loaded register with a constant forces an early wait on the load
+    const int Ic = ok ? I : 0;
+    const int64_t qc = 6 * (int64_t)Ic + L.a;
+    int rb = d.brow_ptr[Ic], re = d.brow_ptr[Ic + 1];
     T rq = 0, wq = 0, sq = 0, pq = 0, xq = 0;
     DinvRow<T> M{};
-    if (own) {
-      rq = ri[q];
-      wq = wi[q];
-      sq = so[q];
-      pq = p[q];
-      xq = x[q];
-      M = dinv_row(d.Dinv, I, L.a);
+    if (SINGLE) {
+      rq = ri[qc];
+      wq = wi[qc];
+      sq = so[qc];
+      pq = p[qc];
+      xq = x[qc];
+      M = dinv_row(d.Dinv, Ic, L.a);
+      // this thread's (at most 3) previous partials per sum, issued after the loads above so
+      // that waiting for them waits for one round trip; added later in the order
+      // finish_partials uses (ng <= PCG_MAX_WG <= 3 MAX_TPB); unconditional loads from a
+      // clamped index, the out-of-range ones dropped where they are added
+      if (gi == lb) {
+        const double* pp = d.pp[i & 1];
+        for (int u = 0; u < 3; ++u) {
+          const int k = (int)threadIdx.x + u * MAX_TPB;
+          const int kc = k < ng ? k : 0;
+          for (int c = 0; c < 3; ++c) pv[c][u] = pp[c * ng + kc];
+        }
+      }
     }
-    if (gi == W.lb) {
+    if (SINGLE && gi == lb && done) return;   // every load above is in bounds either way
+    if (!ok) re = rb;
+    T br = 0, bw = 0, bs = 0;
+    row_product3<T>(rb, re, d.bcol, d.B, ri, wi, so, L.a, L.b, br, bw, bs);
+    if (!SINGLE) {
+      rq = ri[qc];
+      wq = wi[qc];
+      sq = so[qc];
+      pq = p[qc];
+      xq = x[qc];
+      M = dinv_row(d.Dinv, Ic, L.a);
+    }
+    if (gi == lb) {
       double tot[3];
-      finish_partials<3>(d.pp[i & 1], W.ng, tot);
+      if (SINGLE) {
+        const int k0 = (int)threadIdx.x;
+        for (int c = 0; c < 3; ++c)
+          tot[c] = ((0.0 + (k0 < ng ? pv[c][0] : 0.0)) +
+                    (k0 + MAX_TPB < ng ? pv[c][1] : 0.0)) +
+                   (k0 + 2 * MAX_TPB < ng ? pv[c][2] : 0.0);
+        block_sum<3, double>(tot);
+      } else {
+        finish_partials<3>(d.pp[i & 1], ng, tot);
+      }
       const double gam = tot[0], del = tot[1], rho = tot[2];
       const double ff = (i == 0) ? rho : ff_prev;
       double beta_d = 0.0, alpha_d;
@@ -650,7 +692,7 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
         stop = 1;
         status = SSO_EBREAKDOWN;
       }
-      if (W.lb == 0 && threadIdx.x == 0) {
+      if (lb == 0 && threadIdx.x == 0) {
         st->rzs[i & 1] = gam;
         st->alphas[i & 1] = alpha_d;
         st->rr = rho;
@@ -690,8 +732,23 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
     }
   }
   block_sum<3, T>(v);
-  write_partials<3, T>(v, d.pp[(i + 1) & 1], W.lb, W.ng);
-  if (threadIdx.x == 0) d.jw[W.lb] = i + 1;
+  write_partials<3, T>(v, d.pp[(i + 1) & 1], lb, ng);
+  if (!SINGLE && threadIdx.x == 0) d.jw[lb] = i + 1;
+}
+
+// Multi-problem form: descriptor table + workgroup map, iteration index per workgroup.
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
+  cg1_iteration<T, false>(*W.d, W.lb, W.ng, 0);
+}
+
+// One problem: the descriptor by value, launch k performs iteration k (unless done).
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_cg1_iter1(const FusedDesc<T> d, int i) {
+  cg1_iteration<T, true>(d, blockIdx.x, gridDim.x, i);
 }
 
 // B = K M: block (I, J) of K times the block-Jacobi inverse of node J, one entry per thread.
@@ -796,8 +853,6 @@ __global__ void k_refine_update(int64_t n, double alpha, const float* d, double*
 // workgroup re-reads all partials of the previous launch, so their number bounds that cost);
 // grid-stride beyond.  Measured on the 300 x 300 shell: 1024 workgroups beat a grid sized to
 // one resident round of workgroups (occupancy x compute units) by 18 %.
-constexpr int PCG_MAX_WG = 1024;
-
 static int choose_wg(int64_t n_nodes, int cap) {
   int64_t g = (n_nodes + ROWS_PER_WG - 1) / ROWS_PER_WG;
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
@@ -1046,10 +1101,12 @@ static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const
   hipError_t e = fused_start(hd, rtol, max_it, w, s, &dd);
   if (e != hipSuccess) return e;
   const int nwg = hd.n_wg;
+  int k = 0;   // launch index = iteration index until the state says done
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
-    hipLaunchKernelGGL(k_cg1_iter<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    hipLaunchKernelGGL(k_cg1_iter1<T>, dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
     if (e1) (void)hipEventRecord(*e1, s);
+    ++k;
   };
   // the only kernel of an iteration: samples of 8 back-to-back launches
   return run_polled(w, s, max_it, profile_every, FUSED_SPAN, launch, iters, status);
@@ -1386,11 +1443,13 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
     const int nwg = B32 ? w.n_wg_f : w.n_wg;
     const int left = mp.max_it - ms.iters;
     if (B32) {
-      const FusedDesc<float>* dd = reinterpret_cast<const FusedDesc<float>*>(w.fdesc32);
+      const FusedDesc<float> hd = ms.fdesc;
+      int k = 0;
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
         if (e0) (void)hipEventRecord(*e0, s);
-        hipLaunchKernelGGL(k_cg1_iter<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+        hipLaunchKernelGGL(k_cg1_iter1<float>, dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
         if (e1) (void)hipEventRecord(*e1, s);
+        ++k;
       };
       e = run_polled(w, s, left, profile_every, FUSED_SPAN, launch, &it, &st);
     } else {
