@@ -118,7 +118,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serve_bench(n, slots, precision):
+def serve_bench(n, slots, precision, solver):
     """Mixed-size served stream: grid-shells (n x n nodes, n ~ U{8..60}) and shells (m x m quads,
     m ~ U{10..120}) with per-request seeds, rtol 1e-8 on the FP64 true residual, all requests in
     flight iterating in shared multi-problem launches; FP64 or mixed precision (FP32 inner
@@ -127,8 +127,10 @@ def serve_bench(n, slots, precision):
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import BatchedServer, Request, poisson_arrivals
     meshes = [meshgen.served_request(i) for i in range(n)]
+    # multi-problem launches run mixed precision with the single-reduction recurrences only
     opts = sso.Options(rtol=1e-8, precision=sso.PREC_MIXED if precision == "mixed" else
-                       sso.PREC_FP64)
+                       sso.PREC_FP64,
+                       solver=solver if precision == "fp64" else sso.SOLVER_AUTO)
     srv = BatchedServer(slots=slots, options=opts)
     n_cl = min(n, 64)
     cl = srv.run([Request(i, meshes[i], 0.0) for i in range(n_cl)])
@@ -143,10 +145,12 @@ def serve_bench(n, slots, precision):
             "solves_per_s": st.solves_per_s, "dof_per_s": st.dof_per_s,
             "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_queue_ms": st.mean_queue_ms,
             "peak_inflight": st.peak_inflight,
-            "mean_dof": float(np.mean([m.n_dof for m in meshes]))}
+            "mean_dof": float(np.mean([m.n_dof for m in meshes])),
+            "closed_loop_phase_s": {k: round(v, 4) for k, v in cl.host_s.items()},
+            "phase_s": {k: round(v, 4) for k, v in st.host_s.items()}}
 
 
-def batch_bench(gen_seed, n_problems, rtol, objective):
+def batch_bench(gen_seed, n_problems, rtol, objective, solver):
     """n problems of the workload with seeds 1..n, all iterating together in multi-problem
     launches (one launch per kernel for all of them), forward + adjoint each."""
     import torch
@@ -154,7 +158,7 @@ def batch_bench(gen_seed, n_problems, rtol, objective):
     meshes = [gen_seed(k + 1) for k in range(n_problems)]
     stream = torch.cuda.Stream()
     batch = sso.Batch(stream)
-    probs = [sso.Problem(m, sso.Options(rtol=rtol, max_it=400000), stream=stream)
+    probs = [sso.Problem(m, sso.Options(rtol=rtol, max_it=400000, solver=solver), stream=stream)
              for m in meshes]
 
     def one_pass():
@@ -212,7 +216,7 @@ def general_objective_bench(mesh, opts, steps):
             "ms_per_step": 1000 * el / steps, "adjoint_pcg_iters": int(np.median(adj))}
 
 
-def shellnet_bench(n_variants, m=80):
+def shellnet_bench(n_variants, solver, m=80):
     """The network-driven batch: n_variants shells on an m x m plan, heights and thickness from
     the MLP, element stiffness scaled by rho^3; one loss (mean compliance) + backward into the
     network weights, the variants' PCG iterations advancing together in multi-problem launches.
@@ -221,7 +225,8 @@ def shellnet_bench(n_variants, m=80):
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch
     t0 = time.perf_counter()
-    b = ShellBatch(m=m, n_variants=n_variants, options=sso.Options(rtol=1e-8), batched=True)
+    b = ShellBatch(m=m, n_variants=n_variants, options=sso.Options(rtol=1e-8, solver=solver),
+                   batched=True)
     log(f"shellnet: {n_variants} problems created in {time.perf_counter() - t0:.1f} s")
     net = DesignMLP().to("cuda")
     try:
@@ -361,11 +366,11 @@ def main():
         out["general_objective"] = general_objective_bench(mesh, opts, args.general_steps)
     if args.batch > 0 and args.workload in SEEDED and args.objective != "linear":
         out["batched"] = batch_bench(SEEDED[args.workload], args.batch, args.rtol,
-                                     args.objective)
+                                     args.objective, solver)
     if args.shellnet > 0:
-        out["shellnet"] = shellnet_bench(args.shellnet)
+        out["shellnet"] = shellnet_bench(args.shellnet, solver)
     if args.serve_requests > 0:
-        out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec)
+        out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec, solver)
                           for prec in ("fp64", "mixed")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, args.objective, args.cpu_seconds)

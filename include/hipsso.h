@@ -158,8 +158,8 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
 
 /* Forward analysis split for multi-problem launches: sso_solve_begin runs everything up to the
  * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation;
- * FP64 with either recurrence, or mixed precision with the single-reduction one, else
- * SSO_EINVAL); sso_batch_iterate then advances many begun problems together (mixed precision:
+ * FP64 with either recurrence, or mixed precision with the single-reduction one -- which
+ * SSO_SOLVER_AUTO then picks at any size -- and SSO_EINVAL for mixed with STANDARD); sso_batch_iterate then advances many begun problems together (mixed precision:
  * including the FP64 refinement between FP32 inner solves); sso_solve_end finishes one (FP64
  * correction of the true residual, u_out as in sso_solve, stats) once its iteration has
  * stopped.  Results are bitwise the same as sso_solve's. */

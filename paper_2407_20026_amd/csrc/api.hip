@@ -278,9 +278,11 @@ int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* oute
 // Elements, loads, assembly, masking, block-Jacobi and the operators the chosen PCG needs
 // (B = K M for the single-reduction recurrences; FP32 copies for mixed precision).  Events 0-2
 // bracket the stages.
-int prepare(sso_problem* p) {
+int prepare(sso_problem* p, bool batch) {
   hipStream_t s = p->s;
   p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
+  // multi-problem launches run FP32 iterations in the single-reduction form only
+  if (batch && mixed(p) && p->opt.solver == SSO_SOLVER_AUTO) p->solver_used = SSO_SOLVER_FUSED;
   const bool mx = mixed(p), fu = fused(p);
   const int64_t nk = 36 * p->pat.n_blocks;
   if (mx && !p->Dinv32) TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
@@ -323,7 +325,7 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   hipStream_t s = p->s;
   p->solved = false;
   p->in_batch = false;
-  int st = prepare(p);
+  int st = prepare(p, false);
   if (st != SSO_OK) return st;
   int iters = 0, outer = 0;
   int status = run_solver(p, p->f, p->u, &iters, &outer);
@@ -359,12 +361,11 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
 int sso_solve_begin(sso_problem* p) {
   if (!p) return SSO_EINVAL;
   // multi-problem launches run FP64 iterations of either kind and FP32 single-reduction ones
-  if (mixed(p) && pcg_pick_solver(p->opt.solver, p->m.n_nodes) != SSO_SOLVER_FUSED)
-    return SSO_EINVAL;
+  if (mixed(p) && p->opt.solver == SSO_SOLVER_STANDARD) return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
   p->in_batch = false;
-  int st = prepare(p);
+  int st = prepare(p, true);
   if (st != SSO_OK) return st;
   if (mixed(p))
     TRY_HIP(mixed_begin(p->m, p->pat, p->K, p->K32, p->Dinv32, p->B32, p->f, p->u,

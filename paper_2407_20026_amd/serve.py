@@ -86,6 +86,7 @@ class ServeStats:
     peak_inflight: int
     peak_bytes: int
     results: list = field(repr=False, default_factory=list)
+    host_s: dict = field(default_factory=dict)   # BatchedServer: wall time per phase
 
 
 def run_one(req: Request, options: Options, stream=None, device="cuda") -> Result:
@@ -239,6 +240,7 @@ class BatchedServer:
         peak_inflight = peak_bytes = 0
         nxt = 0
         t_start = time.perf_counter()
+        phase = dict(admit=0.0, iterate=0.0, finish=0.0, idle=0.0)
 
         def clock():
             return time.perf_counter() - t_start
@@ -249,6 +251,7 @@ class BatchedServer:
                 while nxt < len(reqs) and reqs[nxt].arrival <= now:
                     waiting.append(reqs[nxt])
                     nxt += 1
+                t0 = time.perf_counter()
                 while waiting and len(active) < self.slots and \
                         footprint_bytes(waiting[0].mesh, self.mixed) <= free:
                     req = waiting.popleft()
@@ -257,13 +260,18 @@ class BatchedServer:
                     p = Problem(req.mesh, self.options, device=self.device, stream=stream)
                     p.solve_begin()
                     active.append((p, req, clock(), need))
+                t1 = time.perf_counter()
+                phase["admit"] += t1 - t0
                 peak_inflight = max(peak_inflight, len(active))
                 peak_bytes = max(peak_bytes, self.budget - free)
                 if not active:
                     if nxt < len(reqs):
                         time.sleep(max(0.0, reqs[nxt].arrival - clock()))
+                    phase["idle"] += time.perf_counter() - t1
                     continue
                 done = batch.iterate([a[0] for a in active], self.chunk)
+                t2 = time.perf_counter()
+                phase["iterate"] += t2 - t1
                 still = []
                 for flag, (p, req, adm, need) in zip(done, active):
                     if not flag:
@@ -275,6 +283,7 @@ class BatchedServer:
                     results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
                                           req.arrival, adm, clock()))
                 active = still
+                phase["finish"] += time.perf_counter() - t2
         finally:
             for p, *_ in active:
                 p.close()
@@ -287,7 +296,8 @@ class BatchedServer:
             p50_ms=1000 * float(np.percentile(lat, 50)), p99_ms=1000 * float(np.percentile(lat, 99)),
             mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
             peak_inflight=peak_inflight, peak_bytes=peak_bytes,
-            results=sorted(results, key=lambda r: r.rid))
+            results=sorted(results, key=lambda r: r.rid),
+            host_s=phase)
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = 3) -> np.ndarray:
