@@ -66,7 +66,8 @@ enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
 /* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
  * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one
  * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
- * of K's size).  AUTO: FUSED up to 20,000 nodes (latency-bound sizes), STANDARD above. */
+ * of K's size).  AUTO: sso_solve takes FUSED up to 20,000 nodes (latency-bound sizes) and
+ * STANDARD above; sso_solve_begin (multi-problem launches) takes STANDARD. */
 enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */
@@ -158,8 +159,8 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
 
 /* Forward analysis split for multi-problem launches: sso_solve_begin runs everything up to the
  * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation;
- * FP64 with either recurrence, or mixed precision with the single-reduction one -- which
- * SSO_SOLVER_AUTO then picks at any size -- and SSO_EINVAL for mixed with STANDARD); sso_batch_iterate then advances many begun problems together (mixed precision:
+ * FP64 or mixed precision, either recurrence; SSO_SOLVER_AUTO picks STANDARD here, the faster
+ * form when many problems share the launches); sso_batch_iterate then advances many begun problems together (mixed precision:
  * including the FP64 refinement between FP32 inner solves); sso_solve_end finishes one (FP64
  * correction of the true residual, u_out as in sso_solve, stats) once its iteration has
  * stopped.  Results are bitwise the same as sso_solve's. */

@@ -281,8 +281,10 @@ int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* oute
 int prepare(sso_problem* p, bool batch) {
   hipStream_t s = p->s;
   p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
-  // multi-problem launches run FP32 iterations in the single-reduction form only
-  if (batch && mixed(p) && p->opt.solver == SSO_SOLVER_AUTO) p->solver_used = SSO_SOLVER_FUSED;
+  // multi-problem launches: many problems in flight make the iteration bandwidth-bound, where
+  // the standard pair streams faster than the fused kernel (16 60 x 60 shells: 123 vs 93
+  // solves/s; 256 80 x 80 shells: 13.2 vs 19.2 s)
+  if (batch && p->opt.solver == SSO_SOLVER_AUTO) p->solver_used = SSO_SOLVER_STANDARD;
   const bool mx = mixed(p), fu = fused(p);
   const int64_t nk = 36 * p->pat.n_blocks;
   if (mx && !p->Dinv32) TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
@@ -361,7 +363,6 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
 int sso_solve_begin(sso_problem* p) {
   if (!p) return SSO_EINVAL;
   // multi-problem launches run FP64 iterations of either kind and FP32 single-reduction ones
-  if (mixed(p) && p->opt.solver == SSO_SOLVER_STANDARD) return SSO_EINVAL;
   hipStream_t s = p->s;
   p->solved = false;
   p->in_batch = false;
@@ -433,10 +434,8 @@ int sso_batch_create(hipStream_t stream, sso_batch** out) {
 
 int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done) {
   if (!b || (n > 0 && !ps) || n < 0 || n_iter < 0) return SSO_EINVAL;
-  std::vector<PcgDesc<double>> descs;
-  std::vector<FusedDesc<double>> fdescs;
-  std::vector<FusedDesc<float>> mdescs;
-  std::vector<int> idx, fidx, midx;
+  BatchLists lists;
+  std::vector<int> idx[4];
   for (int i = 0; i < n; ++i) {
     sso_problem* p = ps[i];
     if (!p || !p->in_batch || p->s != b->s) return SSO_EINVAL;
@@ -446,29 +445,31 @@ int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, i
   for (int i = 0; i < n; ++i) {
     sso_problem* p = ps[i];
     if (stopped(p)) continue;          // finished at an earlier poll
-    if (mixed(p)) {
-      mdescs.push_back(p->ms.fdesc);
-      midx.push_back(i);
+    if (mixed(p) && fused(p)) {
+      lists.fused32.push_back(p->ms.fdesc);
+      idx[3].push_back(i);
+    } else if (mixed(p)) {
+      lists.standard32.push_back(p->ms.sdesc);
+      idx[2].push_back(i);
     } else if (fused(p)) {
-      fdescs.push_back(p->fdesc);
-      fidx.push_back(i);
+      lists.fused.push_back(p->fdesc);
+      idx[1].push_back(i);
     } else {
-      descs.push_back(p->desc);
-      idx.push_back(i);
+      lists.standard.push_back(p->desc);
+      idx[0].push_back(i);
     }
   }
-  if (!descs.empty() || !fdescs.empty() || !mdescs.empty())
-    TRY_HIP(pcg_batch_iterate(descs.data(), (int)descs.size(), fdescs.data(), (int)fdescs.size(),
-                              mdescs.data(), (int)mdescs.size(), n_iter, b->bw, b->s));
+  TRY_HIP(pcg_batch_iterate(lists, n_iter, b->bw, b->s));
   size_t k0 = 0;
-  for (const std::vector<int>* v : {&idx, &fidx, &midx})
-    for (int i : *v) *ps[i]->w.h_st = b->bw.h_states[k0++];
+  for (const auto& v : idx)
+    for (int i : v) *ps[i]->w.h_st = b->bw.h_states[k0++];
   // mixed precision: a stopped inner solve is refined in FP64 and the next one started
-  for (int i : midx) {
-    sso_problem* p = ps[i];
-    TRY_HIP(mixed_step(p->m, p->pat, p->K, p->K32, p->Dinv32, p->B32, p->f, p->u,
-                       mixed_params(p), p->w, p->s, p->ms));
-  }
+  for (const std::vector<int>* v : {&idx[2], &idx[3]})
+    for (int i : *v) {
+      sso_problem* p = ps[i];
+      TRY_HIP(mixed_step(p->m, p->pat, p->K, p->K32, p->Dinv32, p->B32, p->f, p->u,
+                         mixed_params(p), p->w, p->s, p->ms));
+    }
   if (done)
     for (int i = 0; i < n; ++i) done[i] = stopped(ps[i]) ? 1 : 0;
   return SSO_OK;

@@ -1180,37 +1180,47 @@ static void table_free(LaunchTable<Desc>& t, hipStream_t s) {
   dev_free(t.d_wg, s);
 }
 
-hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDesc<double>* fdescs,
-                             int nf, const FusedDesc<float>* mdescs, int nm, int n_iter,
-                             BatchWork& bw, hipStream_t s) {
-  if (n + nf + nm <= 0) return hipSuccess;
+template <class T>
+static void launch_standard(const LaunchTable<PcgDesc<T>>& t, hipStream_t s) {
+  if (t.total == 0) return;
+  const PcgDesc<T>* d = reinterpret_cast<const PcgDesc<T>*>(t.d_desc);
+  hipLaunchKernelGGL(k_spmv_dir<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+  hipLaunchKernelGGL(k_update<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+}
+
+template <class T>
+static void launch_fused(const LaunchTable<FusedDesc<T>>& t, hipStream_t s) {
+  if (t.total == 0) return;
+  const FusedDesc<T>* d = reinterpret_cast<const FusedDesc<T>*>(t.d_desc);
+  hipLaunchKernelGGL(k_cg1_iter<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+}
+
+hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hipStream_t s) {
+  const int nt = (int)(L.standard.size() + L.fused.size() + L.standard32.size() +
+                       L.fused32.size());
+  if (nt <= 0) return hipSuccess;
   hipError_t e;
-  if ((e = table_upload(bw.standard, descs, n, s)) != hipSuccess) return e;
-  if ((e = table_upload(bw.fused, fdescs, nf, s)) != hipSuccess) return e;
-  if ((e = table_upload(bw.fused32, mdescs, nm, s)) != hipSuccess) return e;
-  const PcgDesc<double>* ds = reinterpret_cast<const PcgDesc<double>*>(bw.standard.d_desc);
-  const FusedDesc<double>* df = reinterpret_cast<const FusedDesc<double>*>(bw.fused.d_desc);
-  const FusedDesc<float>* dm = reinterpret_cast<const FusedDesc<float>*>(bw.fused32.d_desc);
+  if ((e = table_upload(bw.standard, L.standard.data(), (int)L.standard.size(), s)) !=
+      hipSuccess)
+    return e;
+  if ((e = table_upload(bw.fused, L.fused.data(), (int)L.fused.size(), s)) != hipSuccess) return e;
+  if ((e = table_upload(bw.standard32, L.standard32.data(), (int)L.standard32.size(), s)) !=
+      hipSuccess)
+    return e;
+  if ((e = table_upload(bw.fused32, L.fused32.data(), (int)L.fused32.size(), s)) != hipSuccess)
+    return e;
   for (int i = 0; i < n_iter; ++i) {
-    if (n > 0) {
-      hipLaunchKernelGGL(k_spmv_dir<double>, dim3(bw.standard.total), dim3(MAX_TPB), 0, s, ds,
-                         bw.standard.d_wg);
-      hipLaunchKernelGGL(k_update<double>, dim3(bw.standard.total), dim3(MAX_TPB), 0, s, ds,
-                         bw.standard.d_wg);
-    }
-    if (nf > 0)
-      hipLaunchKernelGGL(k_cg1_iter<double>, dim3(bw.fused.total), dim3(MAX_TPB), 0, s, df,
-                         bw.fused.d_wg);
-    if (nm > 0)
-      hipLaunchKernelGGL(k_cg1_iter<float>, dim3(bw.fused32.total), dim3(MAX_TPB), 0, s, dm,
-                         bw.fused32.d_wg);
+    launch_standard(bw.standard, s);
+    launch_fused(bw.fused, s);
+    launch_standard(bw.standard32, s);
+    launch_fused(bw.fused32, s);
     ++bw.launched;
   }
-  const int nt = n + nf + nm;
   bw.h_stp.clear();
-  for (int i = 0; i < n; ++i) bw.h_stp.push_back(descs[i].st);
-  for (int i = 0; i < nf; ++i) bw.h_stp.push_back(fdescs[i].st);
-  for (int i = 0; i < nm; ++i) bw.h_stp.push_back(mdescs[i].st);
+  for (const auto& d : L.standard) bw.h_stp.push_back(d.st);
+  for (const auto& d : L.fused) bw.h_stp.push_back(d.st);
+  for (const auto& d : L.standard32) bw.h_stp.push_back(d.st);
+  for (const auto& d : L.fused32) bw.h_stp.push_back(d.st);
   if (nt > bw.cap_states) {
     dev_free(bw.d_states, s);
     dev_free(bw.d_stp, s);
@@ -1236,6 +1246,7 @@ hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDes
 void batch_free(BatchWork& bw, hipStream_t s) {
   table_free(bw.standard, s);
   table_free(bw.fused, s);
+  table_free(bw.standard32, s);
   table_free(bw.fused32, s);
   dev_free(bw.d_stp, s);
   dev_free(bw.d_states, s);
@@ -1384,7 +1395,7 @@ static hipError_t mixed_next(const Mesh& m, const Pattern& pat, const double* K,
     if ((e = fused_start(ms.fdesc, tol_k, left, w, s, &dd)) != hipSuccess) return e;
   } else {
     if ((e = pcg_start<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32,
-                              tol_k, left, w, s, nullptr)) != hipSuccess)
+                              tol_k, left, w, s, &ms.sdesc)) != hipSuccess)
       return e;
   }
   w.h_st->done = 0;

@@ -232,7 +232,8 @@ struct MixedState {
   int outer = 0, iters = 0, status = SSO_OK;
   double prev = -1.0, rn = 0.0;
   bool done = false;
-  FusedDesc<float> fdesc{};   // descriptor of the running inner solve (B32 given)
+  FusedDesc<float> fdesc{};   // descriptor of the running inner solve: B32 given
+  PcgDesc<float> sdesc{};     //   or the standard recurrences on K32
 };
 hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
                            const float* Dinv32, const float* B32, const double* b, double* x,
@@ -270,7 +271,8 @@ struct LaunchTable {
 struct BatchWork {
   LaunchTable<PcgDesc<double>> standard;
   LaunchTable<FusedDesc<double>> fused;
-  LaunchTable<FusedDesc<float>> fused32;    // FP32 inner solves of mixed-precision problems
+  LaunchTable<PcgDesc<float>> standard32;   // FP32 inner solves of mixed-precision problems
+  LaunchTable<FusedDesc<float>> fused32;
   PcgState** d_stp = nullptr;
   int cap_stp = 0;
   PcgState* d_states = nullptr;
@@ -285,12 +287,17 @@ hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const d
 hipError_t fused_begin(const Mesh& m, const Pattern& pat, const double* B, const double* Dinv,
                        const double* b, double* x, double rtol, int max_it, PcgWork& w,
                        hipStream_t s, FusedDesc<double>* desc);
-// Launch n_iter iterations for the n standard, nf single-reduction and nm FP32 single-reduction
-// (inner solves of mixed precision) problems, then copy their state records into bw.h_states
-// in that order (synchronises the stream).
-hipError_t pcg_batch_iterate(const PcgDesc<double>* descs, int n, const FusedDesc<double>* fdescs,
-                             int nf, const FusedDesc<float>* mdescs, int nm, int n_iter,
-                             BatchWork& bw, hipStream_t s);
+// Descriptors of the problems of one multi-problem launch, by kind.
+struct BatchLists {
+  std::vector<PcgDesc<double>> standard;
+  std::vector<FusedDesc<double>> fused;
+  std::vector<PcgDesc<float>> standard32;   // FP32 inner solves of mixed precision
+  std::vector<FusedDesc<float>> fused32;
+};
+// Launch n_iter iterations for every listed problem, one launch per kernel and kind, then copy
+// their state records into bw.h_states in list order (standard, fused, standard32, fused32;
+// synchronises the stream).
+hipError_t pcg_batch_iterate(const BatchLists& lists, int n_iter, BatchWork& bw, hipStream_t s);
 void batch_free(BatchWork& bw, hipStream_t s);
 // Deterministic dot product a^T b; result written to *d_out (device).
 hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,

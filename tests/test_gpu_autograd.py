@@ -129,14 +129,15 @@ def test_displacement_backward_matches_oracle_adjoint():
 
 def test_batched_network_batch_matches_one_by_one():
     """The variants' solves advancing together in multi-problem launches give the loss and the
-    network gradient of the one-by-one form (each solve is bitwise the same; only the order in
-    which the per-variant gradients are summed differs)."""
+    network gradient of the one-by-one form (same recurrences: each solve is bitwise the same;
+    only the order in which the per-variant gradients are summed differs)."""
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch
     print("[gpu] shellnet batched vs one by one", flush=True)
     out = []
     for batched in (False, True):
-        b = ShellBatch(m=8, n_variants=4, L=20.0, options=sso.Options(rtol=1e-10),
+        b = ShellBatch(m=8, n_variants=4, L=20.0,
+                       options=sso.Options(rtol=1e-10, solver=sso.SOLVER_STANDARD),
                        batched=batched)
         net = DesignMLP().to("cuda")
         loss = b.loss(net)

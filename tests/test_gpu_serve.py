@@ -45,13 +45,16 @@ def test_results_in_the_mix_equal_results_alone(precision):
           f"p99={stats.p99_ms:.2f} ms peak in flight={stats.peak_inflight}")
 
 
-def test_batched_loop_results_equal_results_alone():
+@pytest.mark.parametrize("solver", ["standard", "fused"])
+def test_batched_loop_results_equal_results_alone(solver):
     """Multi-problem launches: each request keeps its own workgroup decomposition, so its
-    arithmetic, and its result, is bitwise that of the request solved alone."""
+    arithmetic, and its result, is bitwise that of the request solved alone with the same
+    recurrences."""
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import BatchedServer, run_one
-    print("[gpu] batched serve mix", flush=True)
-    opts = sso.Options(rtol=1e-10)
+    print(f"[gpu] batched serve mix {solver}", flush=True)
+    code = {"standard": sso.SOLVER_STANDARD, "fused": sso.SOLVER_FUSED}[solver]
+    opts = sso.Options(rtol=1e-10, solver=code)
     reqs = _requests(16, seed=7, rate=5000.0)
     stats = BatchedServer(slots=8, options=opts, chunk=16).run(reqs)
     assert stats.n == len(reqs)
@@ -62,6 +65,22 @@ def test_batched_loop_results_equal_results_alone():
         assert np.array_equal(r.grad_xyz, alone.grad_xyz)
     print(f"  solves/s={stats.solves_per_s:.1f} p50={stats.p50_ms:.2f} ms "
           f"p99={stats.p99_ms:.2f} ms peak in flight={stats.peak_inflight}")
+
+
+def test_batched_auto_matches_single_auto_within_tolerance():
+    """Under SSO_SOLVER_AUTO a request in the mix runs the standard recurrences and alone the
+    single-reduction ones (below 20,000 nodes): equal within the solve tolerance."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import BatchedServer, run_one
+    print("[gpu] batched serve auto", flush=True)
+    opts = sso.Options(rtol=1e-10)
+    reqs = _requests(8, seed=9, rate=5000.0)
+    stats = BatchedServer(slots=8, options=opts, chunk=16).run(reqs)
+    for r, req in zip(stats.results, reqs):
+        alone = run_one(req, opts)
+        assert r.g == pytest.approx(alone.g, rel=1e-9)
+        np.testing.assert_allclose(r.grad_xyz, alone.grad_xyz, rtol=0,
+                                   atol=1e-7 * np.abs(alone.grad_xyz).max())
 
 
 def test_memory_budget_limits_admission():
@@ -116,14 +135,16 @@ def test_batch_mixing_both_recurrences_matches_solves_alone():
         assert np.array_equal(u, ua.cpu().numpy())
 
 
-def test_batched_mixed_precision_matches_solves_alone():
-    """Mixed precision in multi-problem launches (FP32 single-reduction inner iterations, FP64
-    refinement between them): every request bitwise equal to the same request solved alone
-    with sso_solve, and within the requested residual."""
+@pytest.mark.parametrize("solver", ["standard", "fused"])
+def test_batched_mixed_precision_matches_solves_alone(solver):
+    """Mixed precision in multi-problem launches (FP32 inner iterations, FP64 refinement between
+    them): every request bitwise equal to the same request solved alone with sso_solve and the
+    same recurrences."""
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import BatchedServer, run_one
-    print("[gpu] batched serve mixed precision", flush=True)
-    opts = sso.Options(precision=sso.PREC_MIXED, rtol=1e-8)
+    print(f"[gpu] batched serve mixed precision {solver}", flush=True)
+    code = {"standard": sso.SOLVER_STANDARD, "fused": sso.SOLVER_FUSED}[solver]
+    opts = sso.Options(precision=sso.PREC_MIXED, rtol=1e-8, solver=code)
     reqs = _requests(12, seed=21, rate=5000.0)
     stats = BatchedServer(slots=6, options=opts, chunk=16).run(reqs)
     assert stats.n == len(reqs)
