@@ -287,10 +287,11 @@ int prepare(sso_problem* p, bool batch) {
   if (batch && p->opt.solver == SSO_SOLVER_AUTO) p->solver_used = SSO_SOLVER_STANDARD;
   const bool mx = mixed(p), fu = fused(p);
   const int64_t nk = 36 * p->pat.n_blocks;
+  const int64_t nb = 36 * right_precondition_blocks(p->pat, p->m.n_nodes);
   if (mx && !p->Dinv32) TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
   if (mx && !fu && !p->K32) TRY_HIP(dev_alloc(&p->K32, nk, s));
-  if (fu && !mx && !p->B) TRY_HIP(dev_alloc(&p->B, nk, s));
-  if (fu && mx && !p->B32) TRY_HIP(dev_alloc(&p->B32, nk, s));
+  if (fu && !mx && !p->B) TRY_HIP(dev_alloc(&p->B, nb, s));
+  if (fu && mx && !p->B32) TRY_HIP(dev_alloc(&p->B32, nb, s));
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(hipEventRecord(p->ev[0], s));
   TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
@@ -301,7 +302,7 @@ int prepare(sso_problem* p, bool batch) {
                               s));
   if (mx && !fu) TRY_HIP(launch_convert_f32(p->K, p->K32, nk, s));
   if (fu)
-    TRY_HIP(launch_right_precondition(p->pat, p->K, p->Dinv, mx ? nullptr : p->B,
+    TRY_HIP(launch_right_precondition(p->m, p->pat, p->K, p->Dinv, mx ? nullptr : p->B,
                                       mx ? p->B32 : nullptr, s));
   TRY_HIP(hipEventRecord(p->ev[2], s));
   return read_errors(p);

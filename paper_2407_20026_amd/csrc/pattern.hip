@@ -249,6 +249,35 @@ __global__ void k_scalar_perm(Mesh m, int64_t n_bcoo, const int32_t* bperm, cons
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
+// Largest block count of a row (one workgroup, fixed order).
+__global__ void __launch_bounds__(256) k_max_row(int n_nodes, const int32_t* brow_ptr,
+                                                 int32_t* out) {
+  __shared__ int32_t sm[256];
+  int32_t mx = 0;
+  for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) {
+    const int32_t c = brow_ptr[i + 1] - brow_ptr[i];
+    mx = c > mx ? c : mx;
+  }
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h && sm[threadIdx.x + h] > sm[threadIdx.x])
+      sm[threadIdx.x] = sm[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+// Padded block columns: slot u of row I is the row's u-th block column, or I past its count.
+__global__ void k_ell_cols(int n_nodes, int w, const int32_t* brow_ptr, const int32_t* bcol,
+                           int32_t* bcol_ell) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_nodes * w) return;
+  const int I = (int)(e / w), u = (int)(e - (int64_t)I * w);
+  const int rb = brow_ptr[I], cnt = brow_ptr[I + 1] - rb;
+  bcol_ell[e] = u < cnt ? bcol[rb + u] : I;
+}
+
 hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream_t s,
                          unsigned* h_err) {
   const int n = m.n_nodes;
@@ -299,7 +328,19 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   SSO_TRY(hipGetLastError());
   int32_t last = (int32_t)pat.n_bcoo;
   SSO_TRY(hipMemcpyAsync(pat.bseg + nblk, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_max_row, dim3(1), dim3(256), 0, s, n, pat.brow_ptr, tmp);
+  SSO_TRY(hipGetLastError());
+  int32_t max_row = 0;
+  SSO_TRY(hipMemcpyAsync(&max_row, tmp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   SSO_TRY(hipStreamSynchronize(s));
+  pat.ell_w = ell_width(max_row);
+  if (pat.ell_w) {
+    const int64_t ne = (int64_t)n * pat.ell_w;
+    SSO_TRY(dev_alloc(&pat.bcol_ell, ne, s));
+    hipLaunchKernelGGL(k_ell_cols, dim3(blocks_for(ne)), dim3(TPB), 0, s, n, pat.ell_w,
+                       pat.brow_ptr, pat.bcol, pat.bcol_ell);
+    SSO_TRY(hipGetLastError());
+  }
   dev_free(cnt, s); dev_free(fill, s); dev_free(ucnt, s); dev_free(tmp, s); dev_free(keys, s);
   return hipSuccess;
 }
@@ -319,7 +360,7 @@ hipError_t build_scalar_view(const Mesh& m, const Pattern& pat, int32_t* row_ptr
 void free_pattern(Pattern& pat, hipStream_t s) {
   dev_free(pat.brow_ptr, s); dev_free(pat.bcol, s); dev_free(pat.bseg, s);
   dev_free(pat.bperm, s); dev_free(pat.bslot, s); dev_free(pat.bdiag, s);
-  dev_free(pat.estart, s); dev_free(pat.bsrow, s);
+  dev_free(pat.estart, s); dev_free(pat.bsrow, s); dev_free(pat.bcol_ell, s);
   pat = Pattern();
 }
 

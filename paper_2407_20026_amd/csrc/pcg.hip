@@ -496,6 +496,55 @@ __device__ inline void row_product3(int rb, int re, const int32_t* __restrict__ 
   at = st;
 }
 
+// The same over the W padded slots of row I (B in the padded layout, bcol_ell): every load
+// address is known without the row pointers, the padding adds exact zeros.
+template <class T, int W>
+__device__ inline void row_product3_ell(int I, const int32_t* __restrict__ bcol_ell,
+                                        const T* __restrict__ B, const T* __restrict__ r,
+                                        const T* __restrict__ w, const T* __restrict__ t, int a,
+                                        int b, T& ar, T& aw, T& at) {
+  using V = typename Vec2<T>::type;
+  const int64_t base = (int64_t)I * W;
+  const int off = 6 * a + b;
+  int64_t J[W];
+  V k[W];
+  for (int u = 0; u < W; ++u) J[u] = bcol_ell[base + u];
+  for (int u = 0; u < W; ++u) k[u] = *reinterpret_cast<const V*>(B + 36 * (base + u) + off);
+  T sr = 0, sw = 0, st = 0;
+  for (int u = 0; u < W; ++u) {
+    const V rv = *reinterpret_cast<const V*>(r + 6 * J[u] + b);
+    const V wv = *reinterpret_cast<const V*>(w + 6 * J[u] + b);
+    const V tv = *reinterpret_cast<const V*>(t + 6 * J[u] + b);
+    sr += k[u].x * rv.x + k[u].y * rv.y;
+    sw += k[u].x * wv.x + k[u].y * wv.y;
+    st += k[u].x * tv.x + k[u].y * tv.y;
+  }
+  ar = sr;
+  aw = sw;
+  at = st;
+}
+
+// Single-vector product B x over the row (W = 0: block order of K via the row pointers).
+template <class T, int W>
+__device__ inline T row_product_b(const FusedDesc<T>& d, int I, const T* __restrict__ x, int a,
+                                  int b) {
+  if constexpr (W == 0) {
+    return row_product<T, false>(d.brow_ptr, d.bcol, d.B, x, x, (T)0, I, a, b);
+  } else {
+    using V = typename Vec2<T>::type;
+    const int64_t base = (int64_t)I * W;
+    const int off = 6 * a + b;
+    T acc = 0;
+    for (int u = 0; u < W; ++u) {
+      const int64_t J = d.bcol_ell[base + u];
+      const V kv = *reinterpret_cast<const V*>(d.B + 36 * (base + u) + off);
+      const V xv = *reinterpret_cast<const V*>(x + 6 * J + b);
+      acc += kv.x * xv.x + kv.y * xv.y;
+    }
+    return acc;
+  }
+}
+
 // Row a of the node's 6x6 block-Jacobi inverse applied to the 6 values at v.
 template <class T>
 struct DinvRow {
@@ -543,24 +592,24 @@ k_cg1_init1(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
 }
 
 // w_0 = B r_0; partials of gamma_0 = r_0.M r_0, delta_0 = w_0.M r_0, rho_0 = r_0.r_0.
-template <class T>
+template <class T, int W>
 __global__ void __launch_bounds__(MAX_TPB)
 k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   __shared__ T rs[ROWS_PER_WG * 6];
-  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
-  const FusedDesc<T>& d = *W.d;
+  const WgOf<FusedDesc<T>> G = wg_of(D, wg_prob);
+  const FusedDesc<T>& d = *G.d;
   const int n_nodes = d.n_nodes;
   const T* __restrict__ r0 = d.r[0];
   const SpLane L = sp_lane();
   const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
   T v[3] = {0, 0, 0};
-  for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
+  for (int gi = G.lb; gi * ROWS_PER_WG < n_nodes; gi += G.ng) {
     const int I = gi * ROWS_PER_WG + slot;
     const bool ok = L.ok && I < n_nodes;
     const bool own = ok && L.b == 0;
     const int64_t q = 6 * (int64_t)I + L.a;
     T acc = 0, rq = 0;
-    if (ok) acc = row_product<T, false>(d.brow_ptr, d.bcol, d.B, r0, r0, (T)0, I, L.a, L.b);
+    if (ok) acc = row_product_b<T, W>(d, I, r0, L.a, L.b);
     const T wv = sum3(acc, L.lane);
     if (own) {
       rq = r0[q];
@@ -577,7 +626,7 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
     __syncthreads();
   }
   block_sum<3, T>(v);
-  write_partials<3, T>(v, d.pp[0], W.lb, W.ng);
+  write_partials<3, T>(v, d.pp[0], G.lb, G.ng);
 }
 
 // One single-reduction iteration for workgroup lb of ng.  SINGLE (one problem, launched by its
@@ -588,7 +637,7 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
 // values, gathered vectors).  Otherwise (multi-problem launches) the index is the workgroup's
 // own counter and the partials are loaded where they are summed, which keeps the register
 // count, and the occupancy that many problems in flight need, lower.
-template <class T, bool SINGLE>
+template <class T, bool SINGLE, int W>
 __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int ng,
                                               int i_host) {
   __shared__ T rs[2][ROWS_PER_WG * 6];
@@ -623,7 +672,11 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
     // merge of a loaded register with a constant forces an early wait on the load
     const int Ic = ok ? I : 0;
     const int64_t qc = 6 * (int64_t)Ic + L.a;
-    int rb = d.brow_ptr[Ic], re = d.brow_ptr[Ic + 1];
+    int rb = 0, re = 0;
+    if constexpr (W == 0) {
+      rb = d.brow_ptr[Ic];
+      re = d.brow_ptr[Ic + 1];
+    }
     T rq = 0, wq = 0, sq = 0, pq = 0, xq = 0;
     DinvRow<T> M{};
     if (SINGLE) {
@@ -647,9 +700,13 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
       }
     }
     if (SINGLE && gi == lb && done) return;   // every load above is in bounds either way
-    if (!ok) re = rb;
     T br = 0, bw = 0, bs = 0;
-    row_product3<T>(rb, re, d.bcol, d.B, ri, wi, so, L.a, L.b, br, bw, bs);
+    if constexpr (W == 0) {
+      if (!ok) re = rb;
+      row_product3<T>(rb, re, d.bcol, d.B, ri, wi, so, L.a, L.b, br, bw, bs);
+    } else {
+      row_product3_ell<T, W>(Ic, d.bcol_ell, d.B, ri, wi, so, L.a, L.b, br, bw, bs);
+    }
     if (!SINGLE) {
       rq = ri[qc];
       wq = wi[qc];
@@ -737,30 +794,55 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
 }
 
 // Multi-problem form: descriptor table + workgroup map, iteration index per workgroup.
-template <class T>
+template <class T, int W>
 __global__ void __launch_bounds__(MAX_TPB)
 k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  const WgOf<FusedDesc<T>> W = wg_of(D, wg_prob);
-  cg1_iteration<T, false>(*W.d, W.lb, W.ng, 0);
+  const WgOf<FusedDesc<T>> G = wg_of(D, wg_prob);
+  cg1_iteration<T, false, W>(*G.d, G.lb, G.ng, 0);
 }
 
 // One problem: the descriptor by value, launch k performs iteration k (unless done).
-template <class T>
+template <class T, int W>
 __global__ void __launch_bounds__(MAX_TPB)
 k_cg1_iter1(const FusedDesc<T> d, int i) {
-  cg1_iteration<T, true>(d, blockIdx.x, gridDim.x, i);
+  cg1_iteration<T, true, W>(d, blockIdx.x, gridDim.x, i);
 }
 
-// B = K M: block (I, J) of K times the block-Jacobi inverse of node J, one entry per thread.
+// Kernel of a padded width (0: block order of K); a width the pattern builder does not make is
+// an error.
+#define SSO_ELL_DISPATCH(W, CALL) \
+  switch (W) {                    \
+    case 0: CALL(0); break;       \
+    case 6: CALL(6); break;       \
+    case 9: CALL(9); break;       \
+    case 12: CALL(12); break;     \
+    case 16: CALL(16); break;     \
+    default: return hipErrorInvalidValue; \
+  }
+
+// B = K M: block (I, J) of K times the block-Jacobi inverse of node J, one entry per thread, in
+// the padded block-row layout (row I, slot u at (I w + u) 36; zero blocks past the row's count)
+// or, with w = 0, in the block order of K.
 template <class T>
 __global__ void __launch_bounds__(256)
-k_right_precondition(int64_t n_blocks, const int32_t* __restrict__ bcol,
-                     const double* __restrict__ K, const double* __restrict__ Dinv,
-                     T* __restrict__ B) {
+k_right_precondition(int n_nodes, int64_t n_blocks, int w, const int32_t* __restrict__ brow_ptr,
+                     const int32_t* __restrict__ bcol, const double* __restrict__ K,
+                     const double* __restrict__ Dinv, T* __restrict__ B) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= 36 * n_blocks) return;
-  const int64_t s = e / 36;
-  const int ab = (int)(e - 36 * s), a = ab / 6, b = ab - 6 * a;
+  const int64_t n_out = w ? 36 * (int64_t)n_nodes * w : 36 * n_blocks;
+  if (e >= n_out) return;
+  const int64_t g = e / 36;   // output block
+  const int ab = (int)(e - 36 * g), a = ab / 6, b = ab - 6 * a;
+  int64_t s = g;              // block slot of K
+  if (w) {
+    const int I = (int)(g / w), u = (int)(g - (int64_t)I * w);
+    const int rb = brow_ptr[I];
+    if (u >= brow_ptr[I + 1] - rb) {
+      B[e] = (T)0;
+      return;
+    }
+    s = rb + u;
+  }
   const double* k = K + 36 * s + 6 * a;
   const double* m = Dinv + 36 * (int64_t)bcol[s] + b;
   double acc = 0.0;
@@ -1050,12 +1132,31 @@ struct FusedBuffers {
   T* w[2];
 };
 
+// One single-problem iteration launch for the descriptor's padded width (the width was checked
+// when the solve started: fused_start).
+template <class T>
+static void launch_iter1(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s) {
+  switch (hd.ell_w) {
+    case 6: hipLaunchKernelGGL((k_cg1_iter1<T, 6>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k); break;
+    case 9: hipLaunchKernelGGL((k_cg1_iter1<T, 9>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k); break;
+    case 12:
+      hipLaunchKernelGGL((k_cg1_iter1<T, 12>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_cg1_iter1<T, 16>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+      break;
+    default: hipLaunchKernelGGL((k_cg1_iter1<T, 0>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+  }
+}
+
 template <class T>
 static FusedDesc<T> fused_desc(const Mesh& m, const Pattern& pat, const T* B, const T* Dinv,
                                const T* b, const FusedBuffers<T>& v, PcgWork& w) {
   FusedDesc<T> hd{};
   hd.brow_ptr = pat.brow_ptr;
   hd.bcol = pat.bcol;
+  hd.bcol_ell = pat.bcol_ell;
+  hd.ell_w = pat.ell_w;
   hd.B = B;
   hd.Dinv = Dinv;
   hd.b = b;
@@ -1084,7 +1185,10 @@ static hipError_t fused_start(const FusedDesc<T>& hd, double rtol, int max_it, P
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cg1_init1<T>, dim3(hd.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr, rtol,
                      max_it);
-  hipLaunchKernelGGL(k_cg1_init2<T>, dim3(hd.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr);
+#define SSO_INIT2(W) \
+  hipLaunchKernelGGL((k_cg1_init2<T, W>), dim3(hd.n_wg), dim3(MAX_TPB), 0, s, dd, nullptr)
+  SSO_ELL_DISPATCH(hd.ell_w, SSO_INIT2)
+#undef SSO_INIT2
   *out = dd;
   return hipGetLastError();
 }
@@ -1104,7 +1208,7 @@ static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const
   int k = 0;   // launch index = iteration index until the state says done
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
-    hipLaunchKernelGGL(k_cg1_iter1<T>, dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+    launch_iter1(hd, nwg, k, s);
     if (e1) (void)hipEventRecord(*e1, s);
     ++k;
   };
@@ -1188,11 +1292,40 @@ static void launch_standard(const LaunchTable<PcgDesc<T>>& t, hipStream_t s) {
   hipLaunchKernelGGL(k_update<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
 }
 
-template <class T>
-static void launch_fused(const LaunchTable<FusedDesc<T>>& t, hipStream_t s) {
-  if (t.total == 0) return;
+template <class T, int W>
+static void launch_fused_w(const LaunchTable<FusedDesc<T>>& t, hipStream_t s) {
   const FusedDesc<T>* d = reinterpret_cast<const FusedDesc<T>*>(t.d_desc);
-  hipLaunchKernelGGL(k_cg1_iter<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+  hipLaunchKernelGGL((k_cg1_iter<T, W>), dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+}
+
+template <class T>
+static void launch_fused(const std::map<int, LaunchTable<FusedDesc<T>>>& tables, hipStream_t s) {
+  for (const auto& kv : tables) {
+    if (kv.second.total == 0) continue;
+    switch (kv.first) {
+      case 6: launch_fused_w<T, 6>(kv.second, s); break;
+      case 9: launch_fused_w<T, 9>(kv.second, s); break;
+      case 12: launch_fused_w<T, 12>(kv.second, s); break;
+      case 16: launch_fused_w<T, 16>(kv.second, s); break;
+      default: launch_fused_w<T, 0>(kv.second, s);
+    }
+  }
+}
+
+// Per padded width, the problems of one fused list laid into that width's table.
+template <class T>
+static hipError_t fused_upload(std::map<int, LaunchTable<FusedDesc<T>>>& tables,
+                               const std::vector<FusedDesc<T>>& list, hipStream_t s) {
+  std::map<int, std::vector<FusedDesc<T>>> by_w;
+  for (const auto& d : list) by_w[d.ell_w].push_back(d);
+  for (auto& kv : tables) kv.second.total = 0;
+  for (const auto& kv : by_w) {
+    if (kv.first != 0 && kv.first != 6 && kv.first != 9 && kv.first != 12 && kv.first != 16)
+      return hipErrorInvalidValue;
+    hipError_t e = table_upload(tables[kv.first], kv.second.data(), (int)kv.second.size(), s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hipStream_t s) {
@@ -1203,12 +1336,11 @@ hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hip
   if ((e = table_upload(bw.standard, L.standard.data(), (int)L.standard.size(), s)) !=
       hipSuccess)
     return e;
-  if ((e = table_upload(bw.fused, L.fused.data(), (int)L.fused.size(), s)) != hipSuccess) return e;
+  if ((e = fused_upload(bw.fused, L.fused, s)) != hipSuccess) return e;
   if ((e = table_upload(bw.standard32, L.standard32.data(), (int)L.standard32.size(), s)) !=
       hipSuccess)
     return e;
-  if ((e = table_upload(bw.fused32, L.fused32.data(), (int)L.fused32.size(), s)) != hipSuccess)
-    return e;
+  if ((e = fused_upload(bw.fused32, L.fused32, s)) != hipSuccess) return e;
   for (int i = 0; i < n_iter; ++i) {
     launch_standard(bw.standard, s);
     launch_fused(bw.fused, s);
@@ -1245,9 +1377,9 @@ hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hip
 
 void batch_free(BatchWork& bw, hipStream_t s) {
   table_free(bw.standard, s);
-  table_free(bw.fused, s);
+  for (auto& kv : bw.fused) table_free(kv.second, s);
   table_free(bw.standard32, s);
-  table_free(bw.fused32, s);
+  for (auto& kv : bw.fused32) table_free(kv.second, s);
   dev_free(bw.d_stp, s);
   dev_free(bw.d_states, s);
   bw = BatchWork();
@@ -1263,15 +1395,20 @@ int pcg_pick_solver(int solver, int64_t n_nodes) {
   return n_nodes <= FUSED_MAX_NODES ? SSO_SOLVER_FUSED : SSO_SOLVER_STANDARD;
 }
 
-hipError_t launch_right_precondition(const Pattern& pat, const double* K, const double* Dinv,
-                                     double* B, float* B32, hipStream_t s) {
-  const int64_t n = 36 * pat.n_blocks;
+int64_t right_precondition_blocks(const Pattern& pat, int64_t n_nodes) {
+  return pat.ell_w ? n_nodes * pat.ell_w : pat.n_blocks;
+}
+
+hipError_t launch_right_precondition(const Mesh& m, const Pattern& pat, const double* K,
+                                     const double* Dinv, double* B, float* B32, hipStream_t s) {
+  const int64_t n = 36 * right_precondition_blocks(pat, m.n_nodes);
   if (B)
     hipLaunchKernelGGL(k_right_precondition<double>, dim3(nblk(n, 256)), dim3(256), 0, s,
-                       pat.n_blocks, pat.bcol, K, Dinv, B);
+                       m.n_nodes, pat.n_blocks, pat.ell_w, pat.brow_ptr, pat.bcol, K, Dinv, B);
   if (B32)
     hipLaunchKernelGGL(k_right_precondition<float>, dim3(nblk(n, 256)), dim3(256), 0, s,
-                       pat.n_blocks, pat.bcol, K, Dinv, B32);
+                       m.n_nodes, pat.n_blocks, pat.ell_w, pat.brow_ptr, pat.bcol, K, Dinv,
+                       B32);
   return hipGetLastError();
 }
 
@@ -1458,7 +1595,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
       int k = 0;
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
         if (e0) (void)hipEventRecord(*e0, s);
-        hipLaunchKernelGGL(k_cg1_iter1<float>, dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+        launch_iter1(hd, nwg, k, s);
         if (e1) (void)hipEventRecord(*e1, s);
         ++k;
       };

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <vector>
 
 #include "hipsso.h"
@@ -60,7 +61,8 @@ template <class T>
 struct FusedDesc {
   const int32_t* brow_ptr;
   const int32_t* bcol;
-  const T* B;       // K times the block-Jacobi inverse, block layout of K
+  const int32_t* bcol_ell;   // padded block-row columns (ell_w > 0)
+  const T* B;       // K times the block-Jacobi inverse: padded layout (ell_w > 0) or K's
   const T* Dinv;
   const T* b;
   T* x;
@@ -71,7 +73,7 @@ struct FusedDesc {
   double* pp[2];
   int32_t* jw;      // per-workgroup iteration counters
   PcgState* st;
-  int n_nodes, n_wg, wg_base, pad;
+  int n_nodes, n_wg, wg_base, ell_w;
 };
 
 // Block-level pattern (6x6 blocks, one block row per node).
@@ -86,7 +88,17 @@ struct Pattern {
   int32_t* bdiag = nullptr;     // [n_nodes] slot of the diagonal block of each row
   int32_t* bsrow = nullptr;     // [n_blocks] block row of each slot
   int32_t* estart = nullptr;    // [n_nodes + 1] first sorted position of each block row
+  // Padded layout of the block rows (every row ell_w slots; 0 = not built: a row has more
+  // than 16 blocks): bcol_ell[I * ell_w + u] = column of block u of row I for u below the
+  // row's block count, I itself (with a zero block) beyond.
+  int ell_w = 0;
+  int32_t* bcol_ell = nullptr;  // [n_nodes * ell_w]
 };
+
+// Slots per row of the padded block-row layout for a largest row of `max_blocks` blocks.
+inline int ell_width(int max_blocks) {
+  return max_blocks <= 6 ? 6 : max_blocks <= 9 ? 9 : max_blocks <= 12 ? 12 : max_blocks <= 16 ? 16 : 0;
+}
 
 struct Mesh {
   int32_t n_nodes = 0, n_beams = 0, n_quads = 0;
@@ -219,9 +231,11 @@ hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const d
                      PcgWork& w, hipStream_t s, int* iters, int* status, int profile_every = 0);
 // SSO_SOLVER_STANDARD or SSO_SOLVER_FUSED for an sso_options.solver value.
 int pcg_pick_solver(int solver, int64_t n_nodes);
-// B = K Dinv block by block (B32: the same rounded to FP32); either may be null.
-hipError_t launch_right_precondition(const Pattern& pat, const double* K, const double* Dinv,
-                                     double* B, float* B32, hipStream_t s);
+// B = K Dinv block by block (B32: the same rounded to FP32; either may be null), in the padded
+// block-row layout when the pattern has one; B holds right_precondition_blocks() 6x6 blocks.
+int64_t right_precondition_blocks(const Pattern& pat, int64_t n_nodes);
+hipError_t launch_right_precondition(const Mesh& m, const Pattern& pat, const double* K,
+                                     const double* Dinv, double* B, float* B32, hipStream_t s);
 // FP32 inner PCG inside FP64 iterative refinement (residual recomputed with the FP64 K); the
 // inner solves use the single-reduction recurrences when B32 is given, else K32.
 struct MixedParams {
@@ -270,9 +284,9 @@ struct LaunchTable {
 };
 struct BatchWork {
   LaunchTable<PcgDesc<double>> standard;
-  LaunchTable<FusedDesc<double>> fused;
+  std::map<int, LaunchTable<FusedDesc<double>>> fused;   // by padded width
   LaunchTable<PcgDesc<float>> standard32;   // FP32 inner solves of mixed-precision problems
-  LaunchTable<FusedDesc<float>> fused32;
+  std::map<int, LaunchTable<FusedDesc<float>>> fused32;
   PcgState** d_stp = nullptr;
   int cap_stp = 0;
   PcgState* d_states = nullptr;
