@@ -6,8 +6,9 @@ coordinate, every shell thickness and every stiffness scale, for the 60 x 60 con
 (22,326 DOF, compliance; the adjoint of compliance is lambda = u, no second solve).  Inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
-The dominant kernel of the PCG -- k_cg1_iter, one whole single-reduction iteration (the
-default), or k_spmv_dir, the direction + SpMV kernel of the standard recurrences -- is timed live
+The dominant kernel of the PCG -- k_cg1_iter1, one whole single-reduction iteration (the
+default up to 20,000 nodes), or k_spmv_dir, the direction + SpMV kernel of the standard
+recurrences -- is timed live
 with HIP events on the problem's stream for every n-th launch; its roofline uses the algorithmic
 bytes of one launch.  The CPU baseline
 is the FP64 oracle timed on the host on one forward + adjoint of the same workload.
@@ -35,7 +36,6 @@ HBM_PEAK_GBS = 8000.0
 # copy (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel code they were taken on: an
 # entry is removed when that kernel changes.
 MEASURED_TRAFFIC = {
-    ("shell60", "fp64", "k_cg1_iter"): (6470.2 * 2.000 + 898.1 * 1.000) * 1024,
     ("shell300", "fp64", "k_spmv_dir"): (128304.8 * 2.000 + 8528.7 * 1.000) * 1024,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
@@ -329,7 +329,7 @@ def main():
     spmv_bytes = st["spmv_bytes"]
     spmv_avg_us = sum(spmv_us) / max(1, sum(spmv_n))
     achieved = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9 if spmv_avg_us > 0 else 0.0
-    kernel = "k_cg1_iter" if st["solver"] == sso.SOLVER_FUSED else "k_spmv_dir"
+    kernel = "k_cg1_iter1" if st["solver"] == sso.SOLVER_FUSED else "k_spmv_dir"
     solver_name = "fused single-reduction" if st["solver"] == sso.SOLVER_FUSED else "standard"
 
     out = {

@@ -37,8 +37,30 @@ def mixed_mesh():
     return s
 
 
+def hub_mesh(n_spokes=20):
+    """A hub node joined to a ring of n_spokes nodes (spokes + ring members): the hub's block row
+    has n_spokes + 1 blocks, more than the padded layout takes (the block order of K is used)."""
+    ang = np.linspace(0.0, 2 * np.pi, n_spokes, endpoint=False)
+    ring = np.column_stack([5 * np.cos(ang), 5 * np.sin(ang), 0.3 * np.sin(3 * ang)])
+    xyz = np.vstack([[0.0, 0.0, 1.5], ring])
+    n = len(xyz)
+    spokes = [[0, 1 + k] for k in range(n_spokes)]
+    hoop = [[1 + k, 1 + (k + 1) % n_spokes] for k in range(n_spokes)]
+    fixed = np.zeros((n, 6), np.uint8)
+    fixed[1::4, :3] = 1
+    f = np.zeros((n, 6))
+    f[:, 2] = -1e4
+    f[0, 0] = 3e3
+    beams = np.array(spokes + hoop, np.int32)
+    prop = np.tile([2.1e11, 8.1e10, 1e-3, 1e-6, 1.5e-6, 2e-6], (len(beams), 1))
+    return meshgen.Mesh(xyz=xyz, fixed=fixed, f_nodal=f, beam_nodes=beams, beam_prop=prop,
+                        quad_nodes=np.zeros((0, 4), np.int32), quad_prop=np.zeros((0, 5)),
+                        name="hub")
+
+
 CASES = {
     "grid11": meshgen.grid_shell_11,
+    "hub": hub_mesh,
     "grid_ragged": lambda: meshgen.gridshell(13, seed=5),
     "shell8": small_shell,
     "mixed": mixed_mesh,
