@@ -113,7 +113,7 @@ typedef struct {
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
   double spmv_us;             /* mean duration per launch of the sampled iteration kernel
                                  (profile_every): k_spmv_dir of the standard recurrences,
-                                 timed alone; k_cg1_iter of the single-reduction ones, timed
+                                 timed alone; k_cg1_iter1 of the single-reduction ones, timed
                                  over 8 back-to-back launches (dispatch gaps included)      */
   int32_t spmv_samples;       /* number of sampled SpMV launches                             */
   double spmv_bytes;          /* algorithmic bytes of one such launch                        */
