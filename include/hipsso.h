@@ -158,12 +158,13 @@ int sso_set_options(sso_problem* p, const sso_options* opts);
 int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
 
 /* Forward analysis split for multi-problem launches: sso_solve_begin runs everything up to the
- * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation;
- * FP64 or mixed precision, either recurrence; SSO_SOLVER_AUTO picks STANDARD here, the faster
- * form when many problems share the launches); sso_batch_iterate then advances many begun problems together (mixed precision:
- * including the FP64 refinement between FP32 inner solves); sso_solve_end finishes one (FP64
- * correction of the true residual, u_out as in sso_solve, stats) once its iteration has
- * stopped.  Results are bitwise the same as sso_solve's. */
+ * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation),
+ * FP64 or mixed precision, either recurrence (SSO_SOLVER_AUTO picks STANDARD here: the faster
+ * form when many problems share the launches); sso_batch_iterate then advances many begun
+ * problems together (mixed precision: including the FP64 refinement between FP32 inner
+ * solves); sso_solve_end finishes one (FP64 correction of the true residual, u_out as in
+ * sso_solve, stats) once its iteration has stopped.  With the same precision and recurrence,
+ * results are bitwise the same as sso_solve's. */
 int sso_solve_begin(sso_problem* p);
 int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats);
 

@@ -1,7 +1,10 @@
 // Block-Jacobi preconditioned conjugate gradients on the masked K (BSR, 6x6 blocks).
 //
 // The paper solves K u = f (Eq. 1, with the supports of Eqs. 2-3) with direct solvers
-// (Sec. 2.2.2).  On the GPU the solve is a bandwidth-bound iteration instead.  Iteration j:
+// (Sec. 2.2.2).  On the GPU the solve is a bandwidth-bound iteration instead, in one of two
+// forms: the standard recurrences (two kernels per iteration, below) or the single-reduction
+// recurrences of Chronopoulos and Gear (one kernel per iteration, k_cg1_*, further down).
+// Standard iteration j:
 //   k_spmv_dir : finish r_j^T z_j and r_j^T r_j from the previous kernel's per-workgroup
 //                partials, test convergence, beta_j = rz_j / rz_{j-1}; p_j = z_j + beta_j p_{j-1}
 //                (own rows stored, neighbour rows formed on the fly), Ap_j = K p_j, partial
