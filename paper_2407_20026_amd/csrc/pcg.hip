@@ -214,8 +214,9 @@ __device__ inline T sum3(T acc, int lane) {
 }
 
 // sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
-// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Three blocks per step
-// (measured on the 300 x 300 shell: 67 us per launch, against 77 us with six blocks per step).
+// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Two blocks per step:
+// 72 VGPRs and 7 waves per SIMD; measured on the 300 x 300 shell 58.7 us per launch against
+// 67.8 (three per step, 88 VGPRs, 5 waves) and 77 (six per step).
 template <class T>
 __device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
                                     const int32_t* __restrict__ bcol, const T* __restrict__ K,
@@ -226,23 +227,18 @@ __device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
   const int off = 6 * a + b;
   T sz = 0, sp = 0;
   int s = rb;
-  for (; s + 3 <= re; s += 3) {
-    const int64_t J0 = bcol[s], J1 = bcol[s + 1], J2 = bcol[s + 2];
+  for (; s + 2 <= re; s += 2) {
+    const int64_t J0 = bcol[s], J1 = bcol[s + 1];
     const V k0 = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
     const V k1 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 1) + off);
-    const V k2 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 2) + off);
     const V z0 = *reinterpret_cast<const V*>(z + 6 * J0 + b);
     const V z1 = *reinterpret_cast<const V*>(z + 6 * J1 + b);
-    const V z2 = *reinterpret_cast<const V*>(z + 6 * J2 + b);
     const V p0 = *reinterpret_cast<const V*>(p + 6 * J0 + b);
     const V p1 = *reinterpret_cast<const V*>(p + 6 * J1 + b);
-    const V p2 = *reinterpret_cast<const V*>(p + 6 * J2 + b);
     sz += k0.x * z0.x + k0.y * z0.y;
     sp += k0.x * p0.x + k0.y * p0.y;
     sz += k1.x * z1.x + k1.y * z1.y;
     sp += k1.x * p1.x + k1.y * p1.y;
-    sz += k2.x * z2.x + k2.y * z2.y;
-    sp += k2.x * p2.x + k2.y * p2.y;
   }
   for (; s < re; ++s) {
     const int64_t J = bcol[s];
