@@ -105,3 +105,26 @@ def test_gradient_invariants(big):
     # loads do not depend on the stiffness scale (all 1 here): sum_e dc/ds_e = -c
     assert gs.sum() == pytest.approx(-c, rel=1e-6)
     assert np.all(np.isfinite(big["gt"]))
+
+
+def test_fused_recurrences_at_full_size(big):
+    """The single-reduction kernel forced on the 300x300 shell: grid-stride passes (5 row groups
+    per workgroup) over the padded 9-slot rows.  Same residual bar under the oracle's operator,
+    and u within the solve tolerance of the standard recurrences' u."""
+    import paper_2407_20026_amd as sso
+    mesh = big["mesh"]
+    print("[gpu] large shell 300x300: fused recurrences", flush=True)
+    with sso.Problem(mesh, sso.Options(rtol=1e-10, max_it=400000,
+                                       solver=sso.SOLVER_FUSED)) as p:
+        u, st = p.solve(check=False)
+        status = p.last_status
+        assert st["solver"] == sso.SOLVER_FUSED
+    u = u.cpu().numpy().ravel()
+    assert status in (0, -4)
+    f = assembly.load_vector(mesh)
+    free = mesh.fixed.reshape(-1) == 0
+    r = (f - assembly.apply_K_elementwise(mesh, u))[free]
+    assert np.linalg.norm(r) / np.linalg.norm(f[free]) <= 1e-9
+    d = np.linalg.norm(u - big["u"]) / np.linalg.norm(big["u"])
+    print(f"  |u_fused - u_standard| / |u| = {d:.2e}, iters {st['iters']}")
+    assert d <= 1e-6
