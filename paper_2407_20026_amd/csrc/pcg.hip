@@ -1004,6 +1004,12 @@ void pcg_free(PcgWork& w, hipStream_t s) {
   dev_free(w.jw, s); dev_free(w.fdesc64, s); dev_free(w.fdesc32, s);
   dev_free(w.desc64, s); dev_free(w.desc32, s);
   delete w.h_st;
+  if (w.h_ring) {
+    (void)hipStreamSynchronize(s);   // the last polled chunk's read-back may still be queued
+    (void)hipHostFree(w.h_ring);
+  }
+  for (auto& ev : w.poll_ev)
+    if (ev) (void)hipEventDestroy(ev);
   dev_free(w.r32, s); dev_free(w.z32, s); dev_free(w.p32[0], s); dev_free(w.p32[1], s);
   dev_free(w.Ap32, s); dev_free(w.x32, s); dev_free(w.b32, s);
   if (w.prof_ev) {
@@ -1034,10 +1040,20 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
     w.prof_cap = PROF_CAP;
   }
   if (profile_every > 0 && profile_every < span) profile_every = span;
+  if (!w.h_ring) {
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&w.h_ring), 2 * sizeof(PcgState),
+                           hipHostMallocDefault)) != hipSuccess)
+      return e;
+    for (auto& ev : w.poll_ev)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  // Two state read-backs in flight: chunk c + 1 is enqueued before the host waits for chunk c's
+  // state, so the GPU does not idle at a poll; the launches of the chunk enqueued after
+  // convergence return at entry.
   int n_prof = 0;
-  int64_t launched = 0;
+  int64_t launched = 0, launched_prev = 0;
   int chunk = 8;
-  for (;;) {
+  for (int c = 0;; ++c) {
     for (int i = 0; i < chunk; ++i) {
       const int64_t gk = launched + i;
       const int64_t ph = profile_every > 0 ? gk % profile_every : -1;
@@ -1049,11 +1065,19 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
     }
     launched += chunk;
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
+    if ((e = hipMemcpyAsync(&w.h_ring[c & 1], w.st, sizeof(PcgState), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
       return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (w.h_st->done || launched > (int64_t)max_it + 64) break;
+    if ((e = hipEventRecord(w.poll_ev[c & 1], s)) != hipSuccess) return e;
+    if (c > 0) {
+      if ((e = hipEventSynchronize(w.poll_ev[(c - 1) & 1])) != hipSuccess) return e;
+      const PcgState& prev = w.h_ring[(c - 1) & 1];
+      if (prev.done || launched_prev > (int64_t)max_it + 64) {
+        *w.h_st = prev;
+        break;
+      }
+    }
+    launched_prev = launched;
     chunk = chunk < 64 ? 2 * chunk : 64;
   }
   *iters = w.h_st->it;

@@ -203,6 +203,8 @@ struct PcgWork {
   double* partials = nullptr;   // per-workgroup partial sums (see pcg.hip)
   PcgState* st = nullptr;
   PcgState* h_st = nullptr;     // host mirror
+  PcgState* h_ring = nullptr;   // pinned [2]: state read-backs of consecutive polled chunks
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   // mixed precision: FP32 inner PCG vectors (allocated on first use)
   float* r32 = nullptr;
   float* z32 = nullptr;
