@@ -149,3 +149,49 @@ def test_batched_network_batch_matches_one_by_one():
     assert l1 == pytest.approx(l0, rel=1e-14)
     for a, c in zip(g0, g1):
         np.testing.assert_allclose(c, a, rtol=1e-12, atol=1e-12 * np.abs(a).max())
+
+
+def test_nonlinear_displacement_objective_through_autograd():
+    """A nonlinear objective of u written in torch (a p-norm of the vertical displacement, a
+    smooth stand-in for the displacement penalty among the paper's objectives): the gradient
+    through Displacement's backward (the USER adjoint with dg/du from torch) against the oracle
+    adjoint with the same dg/du, and against the oracle's central differences of g."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.autograd import displacement
+    from oracle import sensitivity
+    print("[gpu] p-norm displacement objective", flush=True)
+    mesh = meshgen.shell(6, L=6.0, seed=11)
+    pexp = 4.0
+
+    def g_of(u):
+        return float(np.sum(np.abs(u.reshape(-1, 6)[:, 2]) ** pexp) ** (1.0 / pexp))
+
+    fw = sensitivity.forward(mesh)
+    uz = fw["u"].reshape(-1, 6)[:, 2]
+    norm = np.sum(np.abs(uz) ** pexp) ** (1.0 / pexp)
+    dg = np.zeros((mesh.n_nodes, 6))
+    dg[:, 2] = np.sign(uz) * np.abs(uz) ** (pexp - 1) * norm ** (1 - pexp)
+    ref = oracle.analyze(mesh, "user", dg_du=dg.ravel())
+    with sso.Problem(mesh, sso.Options(rtol=1e-10, max_it=50000)) as p:
+        xyz = torch.tensor(mesh.xyz, device="cuda", requires_grad=True)
+        t = torch.tensor(mesh.quad_prop[:, 0], device="cuda", requires_grad=True)
+        u = displacement(p, xyz, t)
+        g = (u[:, 2].abs() ** pexp).sum() ** (1.0 / pexp)
+        g.backward()
+    assert g.item() == pytest.approx(g_of(fw["u"]), rel=1e-9)
+    gx, gt = xyz.grad.cpu().numpy(), t.grad.cpu().numpy()
+    assert np.abs(gx - ref["grad_xyz"]).max() <= 1e-8 * np.abs(ref["grad_xyz"]).max()
+    assert np.abs(gt - ref["grad_t"]).max() <= 1e-8 * np.abs(ref["grad_t"]).max()
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    gmax = np.abs(gx).max()
+    for _ in range(6):
+        i, c = int(rng.integers(mesh.n_nodes)), int(rng.integers(3))
+        vals = []
+        for sgn in (1.0, -1.0):
+            m = mesh.copy()
+            m.xyz = mesh.xyz.copy()
+            m.xyz[i, c] += sgn * h
+            vals.append(g_of(sensitivity.forward(m)["u"]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(gx[i, c] - fd) <= 1e-5 * max(abs(fd), 1e-3 * gmax), (i, c, gx[i, c], fd)
