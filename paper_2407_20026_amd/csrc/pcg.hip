@@ -1019,7 +1019,7 @@ void pcg_free(PcgWork& w, hipStream_t s) {
   w = PcgWork();
 }
 
-static constexpr int PROF_CAP = 4096;
+static constexpr int PROF_CAP = 1024;
 static constexpr int FUSED_SPAN = 8;   // launches per timing sample of the fused iteration
 
 // Launch iterations in chunks of growing size (8 .. 64), reading the state record back after
