@@ -505,15 +505,16 @@ __device__ inline void row_product3_ell(int I, const int32_t* __restrict__ bcol_
   using V = typename Vec2<T>::type;
   const int64_t base = (int64_t)I * W;
   const int off = 6 * a + b;
-  int64_t J[W];
+  int32_t J[W];
   V k[W];
   for (int u = 0; u < W; ++u) J[u] = bcol_ell[base + u];
   for (int u = 0; u < W; ++u) k[u] = *reinterpret_cast<const V*>(B + 36 * (base + u) + off);
   T sr = 0, sw = 0, st = 0;
   for (int u = 0; u < W; ++u) {
-    const V rv = *reinterpret_cast<const V*>(r + 6 * J[u] + b);
-    const V wv = *reinterpret_cast<const V*>(w + 6 * J[u] + b);
-    const V tv = *reinterpret_cast<const V*>(t + 6 * J[u] + b);
+    const int64_t j = 6 * (int64_t)J[u] + b;
+    const V rv = *reinterpret_cast<const V*>(r + j);
+    const V wv = *reinterpret_cast<const V*>(w + j);
+    const V tv = *reinterpret_cast<const V*>(t + j);
     sr += k[u].x * rv.x + k[u].y * rv.y;
     sw += k[u].x * wv.x + k[u].y * wv.y;
     st += k[u].x * tv.x + k[u].y * tv.y;
@@ -562,6 +563,14 @@ __device__ inline DinvRow<T> dinv_row(const T* Dinv, int I, int a) {
   DinvRow<T> R;
   for (int h = 0; h < 3; ++h) R.d[h] = dv[h];
   return R;
+}
+
+// The 6 values v of this lane's node (SpMV layout: lane 18 g + 3 c of row group g holds
+// component c), gathered by wave shuffles.
+template <class T>
+__device__ inline void node_values(T v, const SpLane& L, T out[6]) {
+  const int base = ROW_LANES * L.g;
+  for (int c = 0; c < 6; ++c) out[c] = __shfl(v, base + 3 * c, 64);
 }
 
 // x = 0, p = 0, r_0 = b, s_{-1} = 0; iteration counters and the state record reset.
@@ -639,7 +648,6 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
 template <class T, bool SINGLE, int W>
 __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int ng,
                                               int i_host) {
-  __shared__ T rs[2][ROWS_PER_WG * 6];
   PcgState* st = d.st;
   const int done = st->done;
   const int i = SINGLE ? i_host : d.jw[lb];
@@ -765,23 +773,23 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
       ab = alpha * beta;
     }
     const T wv = sum3(br - alpha * bw - ab * bs, L.lane);
-    if (own) rs[0][6 * slot + L.a] = rq;
-    __syncthreads();
-    T rv = 0;
+    // every lane of a row holds its component a's operands; the node's 6 values of r_i and
+    // r_{i+1} for M r come from the row's own lanes by wave shuffles (no LDS, no barrier)
+    T r6[6];
+    node_values(rq, L, r6);
+    const T pv = M.apply(r6) + beta * pq;
+    const T sv = wq + beta * sq;
+    const T rv = rq - alpha * sv;
     if (own) {
-      const T pv = M.apply(rs[0] + 6 * slot) + beta * pq;
-      const T sv = wq + beta * sq;
       p[q] = pv;
       sn[q] = sv;
       x[q] = xq + alpha * pv;
-      rv = rq - alpha * sv;
       rn[q] = rv;
       wn[q] = wv;
-      rs[1][6 * slot + L.a] = rv;
     }
-    __syncthreads();
+    node_values(rv, L, r6);
     if (own) {
-      const T uv = M.apply(rs[1] + 6 * slot);
+      const T uv = M.apply(r6);
       v[0] += rv * uv;
       v[1] += wv * uv;
       v[2] += rv * rv;
