@@ -66,6 +66,10 @@ def parse():
                     choices=["compliance", "strain_energy", "linear"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--inner-max-it", type=int, default=0,
+                    help="mixed precision: iteration cap of each FP32 inner solve (0 = none)")
+    ap.add_argument("--refine-steps", type=int, default=20,
+                    help="mixed precision: outer (FP64 flexible CG) step limit")
     ap.add_argument("--solver", default="auto", choices=["auto", "standard", "fused"])
     ap.add_argument("--profile-every", type=int, default=64,
                     help="time every n-th iteration kernel with HIP events "
@@ -287,11 +291,12 @@ def main():
     solver = {"auto": sso.SOLVER_AUTO, "standard": sso.SOLVER_STANDARD,
               "fused": sso.SOLVER_FUSED}[args.solver]
     opts = sso.Options(precision=prec, rtol=args.rtol, max_it=400000,
-                       profile_every=args.profile_every, solver=solver)
+                       profile_every=args.profile_every, solver=solver,
+                       refine_steps=args.refine_steps, inner_max_it=args.inner_max_it)
     prob = sso.Problem(mesh, opts)
     u_out = torch.empty((mesh.n_nodes, 6), dtype=torch.float64, device="cuda")
 
-    spmv_us, spmv_n, iters, resid, adj_iters = [], [], [], [], []
+    spmv_us, spmv_n, iters, resid, adj_iters, outer = [], [], [], [], [], []
 
     statuses = []
 
@@ -304,6 +309,7 @@ def main():
             prob.objective(args.objective)
         g = prob.adjoint(args.objective, dg_du=a)
         iters.append(st["iters"])
+        outer.append(st["refine_steps"])
         resid.append(st["rel_residual"])
         adj_iters.append(g["stats"]["iters"])
         if st["spmv_samples"]:
@@ -349,10 +355,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 inner / f64 refinement",
+        "dtype": "f64" if args.precision == "fp64" else "f32 inner / f64 flexible CG",
         "data": "synthetic (seeded generator)",
         "config": {"workload": desc, "n_dof": mesh.n_dof, "objective": args.objective,
                    "rtol": args.rtol, "precision": args.precision, "pcg": solver_name,
+                   **({"inner_max_it": args.inner_max_it, "outer_steps": int(np.median(outer))}
+                      if args.precision == "mixed" else {}),
                    "pcg_iters": int(np.median(iters)),
                    "adjoint_pcg_iters": int(np.median(adj_iters)),
                    "rel_residual": float(np.max(resid)), "n_blocks": prob.n_blocks,

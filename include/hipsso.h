@@ -89,22 +89,26 @@ typedef struct {
 } sso_mesh;
 
 typedef struct {
-  int32_t precision;          /* SSO_PREC_FP64, or SSO_PREC_MIXED: FP32 K, vectors, SpMV and
-                                 dot accumulation inside FP64 iterative refinement (element
-                                 stiffness, residual and the update u += d stay FP64)        */
+  int32_t precision;          /* SSO_PREC_FP64, or SSO_PREC_MIXED: FP64 flexible CG (one
+                                 stored direction) whose preconditioner is an FP32 PCG solve
+                                 (FP32 K, vectors, SpMV and dot accumulation); element
+                                 stiffness, the outer products with K, the step lengths and
+                                 the updates of u stay FP64                                  */
   double rtol;                /* stop when ||f - K u||_2 <= rtol ||f||_2 (recursive residual;
                                  the reported residual is recomputed)                       */
   int32_t max_it;             /* PCG iteration limit per solve                               */
-  int32_t refine_steps;       /* mixed precision: maximum FP64 refinement steps              */
+  int32_t refine_steps;       /* mixed precision: maximum outer (FP64) steps                 */
   int32_t profile_every;      /* 0 = off; n > 0: time every n-th SpMV launch of the PCG with
                                  HIP events on the problem's stream (stats.spmv_us)          */
   double inner_rtol;          /* mixed precision: relative tolerance of each FP32 inner PCG
                                  solve (0 = 1e-5)                                           */
   int32_t solver;             /* SSO_SOLVER_*: PCG recurrences (also of the FP32 inner solves) */
+  int32_t inner_max_it;       /* mixed precision: iteration cap of each FP32 inner solve
+                                 (0 = none: each inner solve runs to its tolerance)          */
 } sso_options;
 
 typedef struct {
-  int32_t iters;              /* PCG iterations of the last solve (all refinement steps)     */
+  int32_t iters;              /* PCG iterations of the last solve (all inner solves)         */
   double rel_residual;        /* ||f - K u||_2 / ||f||_2 recomputed in FP64 after the solve  */
   double t_elem_us;           /* element stiffness + loads                                   */
   double t_asm_us;            /* assembly + masking + block-Jacobi                           */
@@ -117,7 +121,7 @@ typedef struct {
                                  over 8 back-to-back launches (dispatch gaps included)      */
   int32_t spmv_samples;       /* number of sampled SpMV launches                             */
   double spmv_bytes;          /* algorithmic bytes of one such launch                        */
-  int32_t refine_steps;       /* mixed precision: FP32 inner solves run                      */
+  int32_t refine_steps;       /* mixed precision: outer steps (FP32 inner solves) run        */
   int32_t solver;             /* SSO_SOLVER_STANDARD or _FUSED: recurrences that ran         */
 } sso_stats;
 
@@ -161,7 +165,7 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats);
  * first PCG iteration (elements, loads, assembly, masking, block-Jacobi, PCG initialisation),
  * FP64 or mixed precision, either recurrence (SSO_SOLVER_AUTO picks STANDARD here: the faster
  * form when many problems share the launches); sso_batch_iterate then advances many begun
- * problems together (mixed precision: including the FP64 refinement between FP32 inner
+ * problems together (mixed precision: including the FP64 outer steps between FP32 inner
  * solves); sso_solve_end finishes one (FP64 correction of the true residual, u_out as in
  * sso_solve, stats) once its iteration has stopped.  With the same precision and recurrence,
  * results are bitwise the same as sso_solve's. */

@@ -43,7 +43,7 @@ class sso_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("profile_every", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("solver", ctypes.c_int32)]
+                ("solver", ctypes.c_int32), ("inner_max_it", ctypes.c_int32)]
 
 
 class sso_stats(ctypes.Structure):
@@ -152,10 +152,11 @@ class Options:
     profile_every: int = 0
     inner_rtol: float = 0.0
     solver: int = SOLVER_AUTO
+    inner_max_it: int = 0
 
     def c(self) -> sso_options:
         return sso_options(self.precision, self.rtol, self.max_it, self.refine_steps,
-                           self.profile_every, self.inner_rtol, self.solver)
+                           self.profile_every, self.inner_rtol, self.solver, self.inner_max_it)
 
 
 class Problem:

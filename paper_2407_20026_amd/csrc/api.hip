@@ -61,13 +61,15 @@ sso_options default_options() {
   o.profile_every = 0;
   o.inner_rtol = 0.0;
   o.solver = SSO_SOLVER_AUTO;
+  o.inner_max_it = 0;
   return o;
 }
 
 bool options_ok(const sso_options& o) {
   return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED) && o.rtol >= 0.0 &&
          o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0 && o.inner_rtol >= 0.0 &&
-         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_FUSED;
+         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_FUSED &&
+         o.inner_max_it >= 0;
 }
 
 __global__ void k_fill(int64_t n, double v, double* out) {
@@ -257,6 +259,7 @@ MixedParams mixed_params(const sso_problem* p) {
   mp.inner_rtol = p->opt.inner_rtol > 0.0 ? p->opt.inner_rtol : 1e-5;
   mp.max_it = p->opt.max_it;
   mp.refine_steps = p->opt.refine_steps;
+  mp.inner_max_it = p->opt.inner_max_it;
   return mp;
 }
 

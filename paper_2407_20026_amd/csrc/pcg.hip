@@ -930,10 +930,74 @@ __global__ void k_scale_to_f32(int64_t n, const double* in, double scale, float*
   if (i < n) out[i] = (float)(in[i] * scale);
 }
 
-// x += alpha * (double)d: the FP64 refinement update with the FP32 inner correction.
-__global__ void k_refine_update(int64_t n, double alpha, const float* d, double* x) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) x[i] += alpha * (double)d[i];
+// ---- FP64 flexible CG around the FP32 inner solves ----------------------------------------
+// Scalars (device, written by k_finish): sc[0] = r^T r, sc[2] = z^T q_prev, sc[3] = p^T q
+// (the last direction's), sc[4] = p^T r.
+
+// z = s * (double)d: the inner FP32 solution of K d = r / |r|, scaled back; partials of z^T q
+// (the previous direction's product) when dot is set.
+__global__ void __launch_bounds__(256)
+k_fcg_z(int64_t n, double s, const float* __restrict__ d, const double* __restrict__ q,
+        double* __restrict__ z, int dot, double* partials) {
+  double v[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double zi = s * (double)d[i];
+    z[i] = zi;
+    if (dot) v[0] += zi * q[i];
+  }
+  block_sum<1, double>(v);
+  write_partials<1, double>(v, partials);
+}
+
+// p = z - beta p_prev with beta = z^T q_prev / p_prev^T q_prev (0 on a restart), q = K p with
+// the direction formed on the fly from z and p_prev at the neighbour columns (p_prev and p are
+// different buffers); partials of p^T q and p^T r.
+__global__ void __launch_bounds__(MAX_TPB)
+k_fcg_direction(int n_nodes, const int32_t* __restrict__ brow_ptr,
+                const int32_t* __restrict__ bcol, const double* __restrict__ K,
+                const double* __restrict__ z, const double* __restrict__ p_prev,
+                const double* __restrict__ r, const double* __restrict__ sc, int restart,
+                double* __restrict__ p, double* __restrict__ q, double* partials) {
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
+  const double nb = restart ? 0.0 : -(sc[2] / sc[3]);
+  double v[2] = {0.0, 0.0};
+  for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
+    const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
+    const bool ok = L.ok && I < n_nodes;
+    double acc = 0.0;
+    if (ok) acc = row_product<double, true>(brow_ptr, bcol, K, z, p_prev, nb, I, L.a, L.b);
+    const double sum = sum3(acc, L.lane);
+    if (ok && L.b == 0) {
+      const int64_t d = 6 * (int64_t)I + L.a;
+      const double pv = z[d] + nb * p_prev[d];
+      p[d] = pv;
+      q[d] = sum;
+      v[0] += pv * sum;
+      v[1] += pv * r[d];
+    }
+  }
+  block_sum<2, double>(v);
+  write_partials<2, double>(v, partials);
+}
+
+// alpha = p^T r / p^T q (0 unless p^T q > 0); x += alpha p, r -= alpha q; partials of r^T r.
+__global__ void __launch_bounds__(256)
+k_fcg_update(int64_t n, const double* __restrict__ sc, const double* __restrict__ p,
+             const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
+             double* partials) {
+  const double alpha = sc[3] > 0.0 ? sc[4] / sc[3] : 0.0;
+  double v[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+  }
+  block_sum<1, double>(v);
+  write_partials<1, double>(v, partials);
 }
 
 }  // namespace
@@ -1502,74 +1566,97 @@ hipError_t pcg_correct(const Mesh& m, const Pattern& pat, const double* K, const
   return hipSuccess;
 }
 
-// FP32 inner PCG (FP32 K, vectors, SpMV and workgroup accumulation) inside FP64 iterative
-// refinement: r = b - K x recomputed in FP64 with the FP64 K, the inner solve runs on r / |r|,
-// and x += |r| d in FP64, until |r| <= rtol |b| or refinement stalls.
-// Mixed precision as a step machine, so that single solves and multi-problem launches share
-// it.  mixed_next: with the FP64 iterate x, recompute the true residual r = b - K x in FP64 and
-// either stop (converged, refinement limit, stalled, iteration budget, breakdown; a correction
-// that raised the residual is undone) or start the
-// next FP32 inner solve K d = r / |r| (tolerance: the reduction still missing, with a factor 2
-// of margin, clamped to [inner_rtol, 0.5]).  mixed_inner_done: after the inner solve stopped,
-// x += |r| d, then mixed_next.
+// Mixed precision: FP64 flexible conjugate gradients (Notay's FCG with one stored direction)
+// whose preconditioner is an FP32 PCG solve (FP32 K, vectors, SpMV and workgroup
+// accumulation).  Each outer step: inner solve K d = r / |r| in FP32 to the tolerance still
+// missing (factor 2 of margin, clamped to [inner_rtol, 0.5]) or inner_max_it iterations;
+// z = |r| d; p = z - beta p_prev, q = K p in FP64; x += alpha p, r -= alpha q.  Because alpha
+// and beta come from FP64 products with the FP64 K, a crude inner solve (a few iterations, or
+// an FP32 operator too far from K for plain refinement) still makes progress.  When the
+// recursive residual meets the target, the true residual is recomputed; if it misses, the
+// iteration restarts from it (at most twice).
+// Kept as a step machine, so that single solves and multi-problem launches share it:
+// mixed_begin starts the first inner solve, mixed_inner_done takes the stopped inner solve
+// through the outer step and starts the next one (or stops: ms.done, ms.status).
+static constexpr int FCG_RESTARTS = 2;
+
+static int64_t fcg_grid(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return g > 1024 ? 1024 : (g < 1 ? 1 : g);
+}
+
+static double* fcg_scalars(PcgWork& w) { return part_once(w) + 2 * (size_t)partial_stride(w); }
+
+// Read sc[0..4] back (synchronises the stream).
+static hipError_t fcg_read(PcgWork& w, hipStream_t s, double h[5]) {
+  hipError_t e = hipMemcpyAsync(h, fcg_scalars(w), 5 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+// With the residual norm rn of r (w.r), stop or start the next inner solve.
 static hipError_t mixed_next(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
                              const float* Dinv32, const float* B32, const double* b, double* x,
-                             const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms) {
+                             const MixedParams& mp, PcgWork& w, hipStream_t s, MixedState& ms,
+                             double rn) {
   hipError_t e;
   const int64_t n = w.n_dof;
-  double* scal = part_once(w) + 2 * (size_t)partial_stride(w);
-  if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, scal, s)) != hipSuccess) return e;
-  double h[2];
-  if ((e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
-    return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  const double rn = std::sqrt(h[0]), bn = std::sqrt(h[1]);
-  const int left = mp.max_it - ms.iters;
   ms.done = true;
-  if (ms.prev >= 0.0 && !(rn < ms.prev)) {
-    // the last correction made the residual worse (the FP32 operator is too far from K for
-    // this conditioning): return the previous iterate
-    if ((e = hipMemcpyAsync(x, w.xc, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s)) !=
-        hipSuccess)
-      return e;
-    ms.status = SSO_ENOTCONV;
-    return hipSuccess;
-  }
   if (!std::isfinite(rn)) {
     ms.status = SSO_EBREAKDOWN;
     return hipSuccess;
   }
-  if (rn <= mp.rtol * bn) {
-    ms.status = SSO_OK;
-    return hipSuccess;
+  if (rn <= mp.rtol * ms.bn) {
+    if (ms.outer == 0) {
+      ms.status = SSO_OK;
+      return hipSuccess;
+    }
+    double* sc = fcg_scalars(w);
+    if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, sc, s)) != hipSuccess) return e;
+    double h[5];
+    if ((e = fcg_read(w, s, h)) != hipSuccess) return e;
+    const double rt = std::sqrt(h[0]);
+    if (rt <= mp.rtol * ms.bn) {
+      ms.status = SSO_OK;
+      return hipSuccess;
+    }
+    if (ms.restarts == FCG_RESTARTS || !std::isfinite(rt)) {
+      ms.status = SSO_ENOTCONV;   // the recursive residual drifted from the true one
+      return hipSuccess;
+    }
+    ++ms.restarts;
+    ms.k = 0;
+    rn = rt;
   }
-  if (ms.outer == mp.refine_steps || (ms.prev >= 0.0 && rn > 0.5 * ms.prev) || left <= 0) {
-    ms.status = SSO_ENOTCONV;   // limit reached, refinement stalled or iterations used up
+  const int left = mp.max_it - ms.iters;
+  if (ms.outer == mp.refine_steps || left <= 0) {
+    ms.status = SSO_ENOTCONV;   // outer limit reached or iterations used up
     return hipSuccess;
   }
   ms.done = false;
-  ms.prev = rn;
   ms.rn = rn;
   hipLaunchKernelGGL(k_scale_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, w.r, 1.0 / rn,
                      w.b32);
-  double tol_k = 0.5 * mp.rtol * bn / rn;
+  double tol_k = 0.5 * mp.rtol * ms.bn / rn;
   if (tol_k < mp.inner_rtol) tol_k = mp.inner_rtol;
   if (tol_k > 0.5) tol_k = 0.5;
+  const int cap = (mp.inner_max_it > 0 && mp.inner_max_it < left) ? mp.inner_max_it : left;
   if (B32) {
     const FusedBuffers<float> v{w.x32, w.p32[0], {w.r32, w.z32}, {w.p32[1], w.Ap32},
                                 {w.fw32[0], w.fw32[1]}};
     ms.fdesc = fused_desc(m, pat, B32, Dinv32, (const float*)w.b32, v, w);
     FusedDesc<float>* dd = nullptr;
-    if ((e = fused_start(ms.fdesc, tol_k, left, w, s, &dd)) != hipSuccess) return e;
+    if ((e = fused_start(ms.fdesc, tol_k, cap, w, s, &dd)) != hipSuccess) return e;
   } else {
     if ((e = pcg_start<float>(m, pat, K32, Dinv32, w.b32, w.x32, w.r32, w.z32, w.p32, w.Ap32,
-                              tol_k, left, w, s, &ms.sdesc)) != hipSuccess)
+                              tol_k, cap, w, s, &ms.sdesc)) != hipSuccess)
       return e;
   }
   w.h_st->done = 0;
   return hipSuccess;
 }
 
+// The outer step after an inner solve stopped.
 static hipError_t mixed_inner_done(const Mesh& m, const Pattern& pat, const double* K,
                                    const float* K32, const float* Dinv32, const float* B32,
                                    const double* b, double* x, const MixedParams& mp, PcgWork& w,
@@ -1584,11 +1671,32 @@ static hipError_t mixed_inner_done(const Mesh& m, const Pattern& pat, const doub
     return hipSuccess;
   }
   const int64_t n = w.n_dof;
-  hipError_t e = hipMemcpyAsync(w.xc, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
+  const int g = (int)fcg_grid(n);
+  double* sc = fcg_scalars(w);
+  double* part = part_once(w);
+  double* p_prev = w.p[ms.k & 1];
+  double* p_new = w.p[(ms.k + 1) & 1];
+  hipLaunchKernelGGL(k_fcg_z, dim3(g), dim3(256), 0, s, n, ms.rn, w.x32, w.Ap, w.z,
+                     ms.k > 0 ? 1 : 0, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, g, 1, sc + 2);
+  hipLaunchKernelGGL(k_fcg_direction, dim3(w.n_wg), dim3(MAX_TPB), 0, s, m.n_nodes,
+                     pat.brow_ptr, pat.bcol, K, w.z, p_prev, w.r, sc, ms.k == 0 ? 1 : 0, p_new,
+                     w.Ap, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, w.n_wg, 2, sc + 3);
+  hipLaunchKernelGGL(k_fcg_update, dim3(g), dim3(256), 0, s, n, sc, p_new, w.Ap, x, w.r, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, g, 1, sc);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_refine_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, ms.rn, w.x32, x);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
+  double h[5];
+  if ((e = fcg_read(w, s, h)) != hipSuccess) return e;
+  if (!(h[3] > 0.0)) {
+    // p^T K p <= 0: zero direction (the inner solve returned nothing) or not finite
+    ms.done = true;
+    ms.status = std::isfinite(h[3]) ? SSO_ENOTCONV : SSO_EBREAKDOWN;
+    return hipSuccess;
+  }
+  ++ms.k;
+  return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms, std::sqrt(h[0]));
 }
 
 hipError_t mixed_begin(const Mesh& m, const Pattern& pat, const double* K, const float* K32,
@@ -1599,7 +1707,13 @@ hipError_t mixed_begin(const Mesh& m, const Pattern& pat, const double* K, const
   if (B32 && (e = fused_alloc(w, true, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)w.n_dof, s)) != hipSuccess) return e;
   ms = MixedState();
-  return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
+  // r = b - K 0 = b, and |b|
+  if ((e = launch_true_residual(m, pat, K, x, b, w.r, w, fcg_scalars(w), s)) != hipSuccess)
+    return e;
+  double h[5];
+  if ((e = fcg_read(w, s, h)) != hipSuccess) return e;
+  ms.bn = std::sqrt(h[1]);
+  return mixed_next(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms, std::sqrt(h[0]));
 }
 
 hipError_t mixed_step(const Mesh& m, const Pattern& pat, const double* K, const float* K32,

@@ -242,11 +242,12 @@ hipError_t launch_right_precondition(const Mesh& m, const Pattern& pat, const do
 // inner solves use the single-reduction recurrences when B32 is given, else K32.
 struct MixedParams {
   double rtol, inner_rtol;
-  int max_it, refine_steps;
+  int max_it, refine_steps, inner_max_it;
 };
 struct MixedState {
   int outer = 0, iters = 0, status = SSO_OK;
-  double prev = -1.0, rn = 0.0;
+  int k = 0, restarts = 0;    // outer steps since the last (re)start; restarts so far
+  double rn = 0.0, bn = 0.0;  // |r| of the running inner solve's right-hand side; |b|
   bool done = false;
   FusedDesc<float> fdesc{};   // descriptor of the running inner solve: B32 given
   PcgDesc<float> sdesc{};     //   or the standard recurrences on K32

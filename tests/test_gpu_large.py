@@ -128,3 +128,30 @@ def test_fused_recurrences_at_full_size(big):
     d = np.linalg.norm(u - big["u"]) / np.linalg.norm(big["u"])
     print(f"  |u_fused - u_standard| / |u| = {d:.2e}, iters {st['iters']}")
     assert d <= 1e-6
+
+
+def test_mixed_precision_flexible_cg_at_full_size(big):
+    """Mixed precision on the 300x300 shell, where an FP32 inner solve is too far from K for
+    plain iterative refinement: the FP64 flexible CG with inner solves capped at 20 FP32
+    iterations reaches the residual target under the oracle's operator, and u and the compliance
+    agree with the FP64 solve."""
+    import paper_2407_20026_amd as sso
+    mesh = big["mesh"]
+    print("[gpu] large shell 300x300: mixed precision, flexible CG, inner cap 20", flush=True)
+    with sso.Problem(mesh, sso.Options(precision=sso.PREC_MIXED, rtol=1e-8, max_it=400000,
+                                       refine_steps=20000, inner_max_it=20)) as p:
+        u, st = p.solve(check=False)
+        status = p.last_status
+        c = p.objective("compliance")
+    u = u.cpu().numpy().ravel()
+    f = assembly.load_vector(mesh)
+    free = mesh.fixed.reshape(-1) == 0
+    r = (f - assembly.apply_K_elementwise(mesh, u))[free]
+    rel = np.linalg.norm(r) / np.linalg.norm(f[free])
+    d = np.linalg.norm(u - big["u"]) / np.linalg.norm(big["u"])
+    print(f"  status={status} outer={st['refine_steps']} inner iters={st['iters']} "
+          f"oracle-operator residual {rel:.2e} |u_mixed - u_fp64| / |u| = {d:.2e}")
+    assert status == 0
+    assert rel <= 1.01e-8
+    assert d <= 1e-4
+    assert c == pytest.approx(big["c"], rel=1e-7)
