@@ -42,6 +42,7 @@ class Mesh:
     unit_weight: float = 0.0
     surface_load: float = 0.0
     name: str = ""
+    u_prescribed: np.ndarray | None = None   # [n_nodes, 6], used at fixed DOFs; None = zero
 
     @property
     def n_nodes(self) -> int:

@@ -32,12 +32,14 @@ def forward(mesh, pat=None, xyz=None, quad_t=None, quad_scale=None, refine=2):
     K = assembly.assemble(mesh, pat, xyz, quad_t, quad_scale)
     f = assembly.load_vector(mesh, xyz, quad_t)
     Km, fm = assembly.masked_system(mesh, K, f)
-    u, solver = solve.solve_eliminated(mesh, K, f, refine)
-    return dict(K=K, Km=Km, f=f, fm=fm, u=u, solver=solver)
+    b = solve.prescribed(mesh)
+    u, solver = solve.solve_eliminated(mesh, K, f, refine, b=b)
+    return dict(K=K, Km=Km, f=f, fm=fm, u=u, solver=solver, b=b)
 
 
 def objective_value(kind, f, u, a=None):
-    """g(u): compliance f^T u, strain energy f^T u / 2, or linear a^T u (f masked)."""
+    """g(u): compliance f^T u, strain energy f^T u / 2 (f masked: the applied load on the free
+    DOFs), or linear a^T u."""
     if kind == "compliance":
         return float(f @ u)
     if kind == "strain_energy":
@@ -57,7 +59,8 @@ def _quad_inputs(mesh, xyz, quad_t, quad_scale):
 
 def element_terms(mesh, u, lam, c_lam, c_u, xyz=None, quad_t=None, quad_scale=None):
     """Per-element adjoint terms g_e,p = c_lam (lam_e^T df_e/dp - lam_e^T dK_e/dp u_e)
-    + c_u u_e^T df_e/dp.
+    + c_u u_e^T df_e/dp, the last with u_e zero at constrained DOFs (the objectives use the
+    load on the free DOFs only; this matters with prescribed displacements).
 
     Returns beam terms [nb, 6] (3 coordinates of each end node) and quad terms [nq, 14]
     (12 coordinates of the 4 corners, then t, then the stiffness scale)."""
@@ -79,6 +82,7 @@ def element_terms(mesh, u, lam, c_lam, c_u, xyz=None, quad_t=None, quad_scale=No
     if mesh.n_quads:
         X, prop, scale = _quad_inputs(mesh, xyz, quad_t, quad_scale)
         ue, le = u[qd], lam[qd]
+        ux = np.where(mesh.fixed.reshape(-1)[qd] != 0, 0.0, ue)
         for d in range(14):
             Xp, pp, sp_ = X.copy(), prop.copy(), scale.copy()
             if d < 12:
@@ -92,7 +96,7 @@ def element_terms(mesh, u, lam, c_lam, c_u, xyz=None, quad_t=None, quad_scale=No
                                               mesh.surface_load)) / h
             gq[:, d] = (c_lam * (np.einsum("na,na->n", le, dfe)
                                  - np.einsum("na,nab,nb->n", le, dK, ue))
-                        + c_u * np.einsum("na,na->n", ue, dfe))
+                        + c_u * np.einsum("na,na->n", ux, dfe))
     return gb, gq
 
 
@@ -120,7 +124,11 @@ def analyze(mesh, objective="compliance", a=None, dg_du=None, refine=2, pat=None
     if objective in ("compliance", "strain_energy"):
         c = 1.0 if objective == "compliance" else 0.5
         g = objective_value(objective, fm, u)
-        lam = u.copy()            # K lam = f has the solution lam = u
+        if fw["b"] is None:
+            lam = u.copy()        # K lam = f has the solution lam = u
+        else:
+            # with prescribed displacements u solves the lifted system, so lam != u
+            lam, _ = solve.solve_eliminated(mesh, fw["K"], fm, refine, solver=fw["solver"])
         c_lam, c_u = c, c
     else:
         rhs = np.asarray(a if objective == "linear" else dg_du, dtype=float)

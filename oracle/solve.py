@@ -3,9 +3,9 @@ Lagrange-multiplier system, and extended-precision iterative refinement.
 
 Paper: Sec. 2.2.1-2.2.2 -- K u = f (Eq. (1)); supports enter through Lagrange multipliers,
 [[K, V^T], [V, 0]] [u; mu] = [f; b] (Eq. (2)) with V u = b (Eq. (3)); the paper solves it with a
-dense LU or with sparse direct solvers.  The oracle eliminates the constrained DOFs instead
-(b = 0), which gives the identical u, and solves the symmetric positive definite K_ff with a
-banded Cholesky in natural node order.
+dense LU or with sparse direct solvers.  The oracle eliminates the constrained DOFs instead,
+u_c = b_c and K_ff u_f = f_f - K_fc b_c, which gives the identical u, and solves the symmetric
+positive definite K_ff with a banded Cholesky in natural node order.
 """
 from __future__ import annotations
 
@@ -64,15 +64,32 @@ class SPDSolver:
         return x
 
 
-def solve_eliminated(mesh, K, f, refine=2, solver=None):
-    """u with u_c = 0 on constrained DOFs and K_ff u_f = f_f on the free ones.
+def prescribed(mesh):
+    """The prescribed displacement vector b [n_dof] (Eq. (3)): mesh.u_prescribed at the
+    constrained DOFs, 0 at the free ones; None when the mesh prescribes none."""
+    up = getattr(mesh, "u_prescribed", None)
+    if up is None:
+        return None
+    fixed = mesh.fixed.reshape(-1) != 0
+    return np.where(fixed, np.asarray(up, dtype=float).reshape(-1), 0.0)
+
+
+def solve_eliminated(mesh, K, f, refine=2, solver=None, b=None):
+    """u with u_c = b_c on constrained DOFs (0 when b is None) and
+    K_ff u_f = f_f - K_fc b_c on the free ones.
 
     Returns (u, solver) so that the adjoint can reuse the factorisation."""
     F = free_dofs(mesh)
+    K = K.tocsr()
     if solver is None:
-        solver = SPDSolver(K.tocsr()[F][:, F])
+        solver = SPDSolver(K[F][:, F])
+    rhs = np.asarray(f, dtype=float)[F]
     u = np.zeros(mesh.n_dof)
-    u[F] = solver.solve(np.asarray(f)[F], refine)
+    if b is not None:
+        C = np.flatnonzero(mesh.fixed.reshape(-1) != 0)
+        u[C] = b[C]
+        rhs = rhs - K[F][:, C] @ b[C]
+    u[F] = solver.solve(rhs, refine)
     return u, solver
 
 
