@@ -86,6 +86,8 @@ typedef struct {
   const double* quad_scale;   /* [n_quads] stiffness scale s_e (e.g. rho^3), or NULL = 1     */
   double unit_weight;         /* self-weight of quads along -Z, N/m^3 (0 = none)             */
   double surface_load;        /* uniform pressure on quads along -Z, N/m^2 (0 = none)        */
+  const double* u_prescribed; /* [n_nodes][6] prescribed displacements b of Eq. 3, read at the
+                                 fixed DOFs (the rest is ignored), or NULL = all zero        */
 } sso_mesh;
 
 typedef struct {
@@ -152,9 +154,10 @@ int sso_set_options(sso_problem* p, const sso_options* opts);
 /* Forward analysis: element stiffness (beams: K = s T^T k T; quads: flat shell, K = s T^T W^T k
  * W T), loads (nodal + self-weight + surface load lumped to corners), deterministic assembly
  * K[slot] = sum of the slot's element entries in ascending element order, support masking
- * (constrained d: K[d,:] = K[:,d] = 0, K[d,d] = 1, f[d] = 0 -- for zero prescribed
- * displacements identical in u to the Lagrange system of Eqs. 2-3), block-Jacobi
- * preconditioner, PCG.  u_out: [n_nodes][6] device output (may be NULL).  stats: host struct
+ * (constrained d: K[d,:] = K[:,d] = 0, K[d,d] = 1, f[d] = 0; with prescribed values b a
+ * free row's load loses K(row, d) b[d] and u[d] = b[d] is set after the solve -- identical in
+ * u to the Lagrange system of Eqs. 2-3 with V u = b), block-Jacobi preconditioner, PCG; the
+ * relative residual is that of the free equations.  u_out: [n_nodes][6] device output (may be NULL).  stats: host struct
  * or NULL.  Errors: SSO_EINVAL (degenerate element: zero-length beam, det J <= 0, zero quad
  * area, non-positive t/E/A/I/J, nu outside (-1, 0.5), kx or ky != 1; a diagonal 6x6 block that
  * is not positive definite), SSO_ENOTCONV (u_out then holds the last iterate, and
@@ -185,17 +188,20 @@ int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, i
 void sso_batch_destroy(sso_batch* b);
 
 /* Objective value of the last solve into *g_host (host): compliance f^T u, strain energy
- * f^T u / 2, or a^T u for SSO_OBJ_LINEAR (a: device [n_nodes][6]).  SSO_OBJ_USER: SSO_EINVAL.
+ * f^T u / 2 (f: the applied load on the free DOFs), or a^T u for SSO_OBJ_LINEAR (a: device
+ * [n_nodes][6]).  SSO_OBJ_USER: SSO_EINVAL.
  * Errors: SSO_EINVAL without a previous successful solve. */
 int sso_objective(sso_problem* p, int kind, const double* a, double* g_host);
 
 /* Adjoint sensitivity of the last solve (Eqs. 5-6).  kind selects g:
- *   COMPLIANCE / STRAIN_ENERGY: lambda = u exactly (K lambda = f), no second solve;
+ *   COMPLIANCE / STRAIN_ENERGY: lambda = u exactly (K lambda = f), no second solve -- unless
+ *   displacements are prescribed (then lambda solves the masked K lambda = f);
  *   LINEAR: dg_du = a; USER: dg_du = dg/du supplied by the caller ([n_nodes][6] device), and
  *   lambda solves the masked K lambda = dg/du with the same K and preconditioner.
  * Outputs (device, caller-allocated): dg_dxyz [n_nodes][3] (required); dg_dt [n_quads] and
  * dg_dscale [n_quads] (each may be NULL).  Per element e and parameter p the contribution
- * c_lam (lambda_e^T df_e/dp - lambda_e^T dK_e/dp u_e) + c_u u_e^T df_e/dp is formed exactly
+ * c_lam (lambda_e^T df_e/dp - lambda_e^T dK_e/dp u_e) + c_u u_e^T df_e/dp (u_e taken as 0 at
+ * constrained DOFs in the last term) is formed exactly
  * (forward-mode dual numbers), then summed per node over incident elements in ascending
  * element order.  stats: host or NULL (t_adj_us; iters of the adjoint solve if one ran).
  * Errors: SSO_EINVAL (no solve, bad kind, NULL dg_du for LINEAR/USER), SSO_ENOTCONV,
@@ -214,7 +220,8 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
                 const int32_t** perm, const int32_t** seg, int64_t* nnz, int64_t* n_coo);
 
 /* Read back the assembled, masked K in scalar CSR order into vals [nnz] (device), the masked
- * load vector f [n_nodes][6] (device, may be NULL) of the last solve. */
+ * system's right-hand side f [n_nodes][6] (device, may be NULL) of the last solve (0 on the
+ * fixed DOFs; with prescribed displacements the lifted load on the free ones). */
 int sso_matrix(sso_problem* p, double* vals, double* f);
 
 /* Sizes: n_dof, block count (6x6 blocks of K) and nnz = 36 * blocks (host outputs). */

@@ -36,7 +36,7 @@ class sso_mesh(ctypes.Structure):
                 ("n_beams", ctypes.c_int32), ("beam_nodes", _vp), ("beam_prop", _vp),
                 ("n_quads", ctypes.c_int32), ("quad_nodes", _vp), ("quad_prop", _vp),
                 ("quad_scale", _vp), ("unit_weight", ctypes.c_double),
-                ("surface_load", ctypes.c_double)]
+                ("surface_load", ctypes.c_double), ("u_prescribed", _vp)]
 
 
 class sso_options(ctypes.Structure):
@@ -185,10 +185,11 @@ class Problem:
             self._qn = _dev(mesh.quad_nodes, torch.int32, d)
             self._qp = _dev(mesh.quad_prop, torch.float64, d)
             self._qs = _dev(getattr(mesh, "quad_scale", None), torch.float64, d)
+            self._up = _dev(getattr(mesh, "u_prescribed", None), torch.float64, d)
         cm = sso_mesh(self.n_nodes, _ptr(self._xyz), _ptr(self._fixed), _ptr(self._f),
                       self.n_beams, _ptr(self._bn), _ptr(self._bp),
                       self.n_quads, _ptr(self._qn), _ptr(self._qp), _ptr(self._qs),
-                      float(mesh.unit_weight), float(mesh.surface_load))
+                      float(mesh.unit_weight), float(mesh.surface_load), _ptr(self._up))
         self.options = options or Options()
         opts = self.options.c()
         h = ctypes.c_void_p()

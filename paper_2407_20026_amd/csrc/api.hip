@@ -21,7 +21,8 @@ struct sso_problem {
   float* B32 = nullptr;
   float* K32 = nullptr;         // mixed precision copies (allocated on first mixed solve)
   float* Dinv32 = nullptr;
-  double* f = nullptr;
+  double* f = nullptr;          // right-hand side of the masked system (lifted when prescribed)
+  double* fm = nullptr;         // applied load on the free DOFs, when displacements are prescribed
   double* u = nullptr;
   double* lam = nullptr;
   double* rhs = nullptr;
@@ -106,7 +107,7 @@ void free_problem(sso_problem* p) {
                   (void*)p->Dinv, (void*)p->f, (void*)p->K32, (void*)p->Dinv32, (void*)p->B, (void*)p->B32, (void*)p->u,
                   (void*)p->lam, (void*)p->rhs, (void*)p->gbeam, (void*)p->gquad,
                   (void*)p->d_scal, (void*)p->d_err, (void*)p->row_ptr, (void*)p->col,
-                  (void*)p->perm, (void*)p->seg})
+                  (void*)p->perm, (void*)p->seg, (void*)m.u_presc, (void*)p->fm})
     dev_free(q, s);
   free_pattern(p->pat, s);
   pcg_free(p->w, s);
@@ -138,6 +139,12 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
   TRY_HIP(dev_alloc(&m.quad_nodes, 4 * nq, s));
   TRY_HIP(dev_alloc(&m.quad_prop, 5 * nq, s));
   TRY_HIP(dev_alloc(&m.quad_scale, nq, s));
+  if (mesh->u_prescribed) {
+    TRY_HIP(dev_alloc(&m.u_presc, 6 * nn, s));
+    TRY_HIP(hipMemcpyAsync(m.u_presc, mesh->u_prescribed, sizeof(double) * 6 * nn,
+                           hipMemcpyDeviceToDevice, s));
+    TRY_HIP(dev_alloc(&p->fm, 6 * nn, s));
+  }
   TRY_HIP(hipMemcpyAsync(m.xyz, mesh->xyz, sizeof(double) * 3 * nn, hipMemcpyDeviceToDevice, s));
   TRY_HIP(hipMemcpyAsync(m.fixed, mesh->fixed, 6 * nn, hipMemcpyDeviceToDevice, s));
   TRY_HIP(hipMemcpyAsync(m.f_nodal, mesh->f_nodal, sizeof(double) * 6 * nn,
@@ -298,7 +305,12 @@ int prepare(sso_problem* p, bool batch) {
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   TRY_HIP(hipEventRecord(p->ev[0], s));
   TRY_HIP(launch_element_stiffness(p->m, p->coo, p->qarea, p->d_err, s));
-  TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
+  if (p->fm) {
+    TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->fm, s));
+    TRY_HIP(launch_lift(p->m, p->pat, p->coo, p->fm, p->f, s));
+  } else {
+    TRY_HIP(launch_loads(p->m, p->pat, p->qarea, p->f, s));
+  }
   TRY_HIP(hipEventRecord(p->ev[1], s));
   TRY_HIP(launch_assemble(p->m, p->pat, p->coo, p->K, s));
   TRY_HIP(launch_block_jacobi(p->m, p->pat, p->K, p->Dinv, mx ? p->Dinv32 : nullptr, p->d_err,
@@ -339,6 +351,7 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   TRY_HIP(hipEventRecord(p->ev[3], s));
   TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
   TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (p->m.u_presc) TRY_HIP(launch_apply_prescribed(p->m, p->u, s));
   if (u_out)
     TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
                            hipMemcpyDeviceToDevice, s));
@@ -391,9 +404,6 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
   TRY_HIP(hipMemcpyAsync(p->w.h_st, p->w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
   TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
   TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (u_out)
-    TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
-                           hipMemcpyDeviceToDevice, s));
   TRY_HIP(hipStreamSynchronize(s));
   int status = p->w.h_st->done ? p->w.h_st->status : SSO_ENOTCONV;
   int iters = p->w.h_st->it, outer = 0;
@@ -406,11 +416,12 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
                         s, &iters, &status));
     TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
     TRY_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (u_out)
-      TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
-                             hipMemcpyDeviceToDevice, s));
-    TRY_HIP(hipStreamSynchronize(s));
   }
+  if (p->m.u_presc) TRY_HIP(launch_apply_prescribed(p->m, p->u, s));
+  if (u_out)
+    TRY_HIP(hipMemcpyAsync(u_out, p->u, sizeof(double) * 6 * (size_t)p->m.n_nodes,
+                           hipMemcpyDeviceToDevice, s));
+  TRY_HIP(hipStreamSynchronize(s));
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->iters = iters;
@@ -490,10 +501,11 @@ int sso_objective(sso_problem* p, int kind, const double* a, double* g_host) {
   if (!p || !g_host || !p->solved) return SSO_EINVAL;
   const double* lhs;
   double scale = 1.0;
+  const double* load = p->fm ? p->fm : p->f;
   if (kind == SSO_OBJ_COMPLIANCE) {
-    lhs = p->f;
+    lhs = load;
   } else if (kind == SSO_OBJ_STRAIN_ENERGY) {
-    lhs = p->f;
+    lhs = load;
     scale = 0.5;
   } else if (kind == SSO_OBJ_LINEAR && a) {
     lhs = a;
@@ -518,6 +530,13 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
   TRY_HIP(hipEventRecord(p->ev[4], s));
   if (kind == SSO_OBJ_COMPLIANCE || kind == SSO_OBJ_STRAIN_ENERGY) {
     if (kind == SSO_OBJ_STRAIN_ENERGY) c_lam = c_u = 0.5;
+    if (p->fm) {
+      // prescribed displacements: u solves the lifted system, so K lambda = f needs a solve
+      int outer = 0;
+      status = run_solver(p, p->fm, p->lam, &iters, &outer);
+      if (status != SSO_OK && status != SSO_ENOTCONV) return status;
+      lam = p->lam;
+    }
   } else if (kind == SSO_OBJ_LINEAR || kind == SSO_OBJ_USER) {
     if (!dg_du) return SSO_EINVAL;
     c_u = 0.0;

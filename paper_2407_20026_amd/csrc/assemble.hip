@@ -1,9 +1,10 @@
 // Assembly, support masking, loads and the block-Jacobi preconditioner.
 //
 // Sec. 2.2.1: K is the sum of all element matrices placed by their index maps; supports enter
-// through Lagrange multipliers with V u = b.  For b = 0 the same displacement follows from
-// masking: a constrained DOF d gets K[d, :] = K[:, d] = 0, K[d, d] = 1 and f[d] = 0, which keeps
-// K symmetric positive definite and its pattern unchanged.
+// through Lagrange multipliers with V u = b.  The same displacement follows from masking: a
+// constrained DOF d gets K[d, :] = K[:, d] = 0, K[d, d] = 1 and f[d] = 0, and with prescribed
+// values b a free row's load loses K(row, d) b[d] (lifting; u = b is written on d after the
+// solve), which keeps K symmetric positive definite and its pattern unchanged.
 //
 // Assembly is gather-based and deterministic: one thread per entry (slot, a, b) of a 6x6 block
 // sums the slot's element contributions in ascending contribution id (= ascending element, then
@@ -56,6 +57,44 @@ __global__ void k_loads(Mesh m, const int32_t* bdiag, const int32_t* bseg, const
     }
   }
   f[t] = m.fixed[t] ? 0.0 : v;
+}
+
+// Prescribed support displacements b (Eq. 3 with b != 0) by lifting: the solve runs on
+// u - b (b extended by 0 to the free DOFs), so f[t] = 0 on a constrained DOF (the masked row
+// is the identity) and, on a free DOF t = 6 I + a, f[t] = fm[t] - sum over the slots of block
+// row I (ascending) and components c of a constrained (J, c) of K(t, 6 J + c) b[6 J + c], with
+// the unmasked entry summed from the element contributions in the assembly's order.  The
+// solve keeps the constrained components at exactly 0 and solves K_ff u_f = f_f - K_fc b_c;
+// k_apply_prescribed then writes u_c = b_c.
+__global__ void k_lift(Mesh m, const int32_t* brow_ptr, const int32_t* bcol, const int32_t* bseg,
+                       const int32_t* bperm, const double* coo, const double* fm, double* f) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 6 * (int64_t)m.n_nodes) return;
+  if (m.fixed[t]) {
+    f[t] = 0.0;
+    return;
+  }
+  const int I = (int)(t / 6), a = (int)(t % 6);
+  double acc = 0.0;
+  for (int s = brow_ptr[I]; s < brow_ptr[I + 1]; ++s) {
+    const int64_t J = bcol[s];
+    for (int c = 0; c < 6; ++c) {
+      const int64_t d = 6 * J + c;
+      if (!m.fixed[d] || m.u_presc[d] == 0.0) continue;
+      double kv = 0.0;
+      for (int p = bseg[s]; p < bseg[s + 1]; ++p) {
+        const BlockRef r = decode_block(bperm[p], m.n_beams);
+        kv += coo[coo_index(r, a, c, m.n_beams)];
+      }
+      acc += kv * m.u_presc[d];
+    }
+  }
+  f[t] = fm[t] - acc;
+}
+
+__global__ void k_apply_prescribed(int64_t n, const uint8_t* fixed, const double* b, double* u) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n && fixed[t]) u[t] = b[t];
 }
 
 __global__ void k_mask_vector(int64_t n, const uint8_t* fixed, const double* in, double* out) {
@@ -136,6 +175,20 @@ hipError_t launch_loads(const Mesh& m, const Pattern& pat, const double* qarea, 
                         hipStream_t s) {
   hipLaunchKernelGGL(k_loads, dim3(nblk(6 * (int64_t)m.n_nodes, 256)), dim3(256), 0, s, m,
                      pat.bdiag, pat.bseg, pat.bperm, qarea, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift(const Mesh& m, const Pattern& pat, const double* coo, const double* fm,
+                       double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_lift, dim3(nblk(6 * (int64_t)m.n_nodes, 256)), dim3(256), 0, s, m,
+                     pat.brow_ptr, pat.bcol, pat.bseg, pat.bperm, coo, fm, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_prescribed(const Mesh& m, double* u, hipStream_t s) {
+  const int64_t n = 6 * (int64_t)m.n_nodes;
+  hipLaunchKernelGGL(k_apply_prescribed, dim3(nblk(n, 256)), dim3(256), 0, s, n, m.fixed,
+                     m.u_presc, u);
   return hipGetLastError();
 }
 

@@ -465,7 +465,9 @@ __global__ void __launch_bounds__(128) k_beam_adjoint(Mesh m, const double* u, c
 }
 
 // Quads: thread (e, d), d in 0..13 = 12 corner coordinates, thickness, stiffness scale.
-// gquad[14 e + d] = c_lam (lam^T df/dp - lam^T dK/dp u) + c_u u^T df/dp.
+// gquad[14 e + d] = c_lam (lam^T df/dp - lam^T dK/dp u) + c_u u^T df/dp, the last with u taken
+// as 0 on constrained DOFs (the objectives weigh the load on the free DOFs; u there is the
+// prescribed displacement, not a response to the load).
 __global__ void __launch_bounds__(128) k_quad_adjoint(Mesh m, const double* u, const double* lam, double c_lam,
                                double c_u, double* gquad) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -519,8 +521,10 @@ __global__ void __launch_bounds__(128) k_quad_adjoint(Mesh m, const double* u, c
   // loads: -(gamma t + q) A / 4 on uz of each corner
   Dual fz = -((m.unit_weight * tt + m.surface_load) * g.area) / 4.0;
   double wz = 0.0;
-  for (int i = 0; i < 4; ++i)
-    wz += c_lam * lam[6 * (int64_t)nd[i] + 2] + c_u * u[6 * (int64_t)nd[i] + 2];
+  for (int i = 0; i < 4; ++i) {
+    const int64_t z = 6 * (int64_t)nd[i] + 2;
+    wz += c_lam * lam[z] + c_u * (m.fixed[z] ? 0.0 : u[z]);
+  }
   gquad[t] = wz * fz.d - c_lam * phi.d;
 }
 

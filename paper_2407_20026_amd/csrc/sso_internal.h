@@ -111,6 +111,7 @@ struct Mesh {
   double* quad_prop = nullptr;
   double* quad_scale = nullptr;   // always allocated when n_quads > 0 (1 when not given)
   double unit_weight = 0, surface_load = 0;
+  double* u_presc = nullptr;      // [n_nodes][6] prescribed displacements, or null (all zero)
 };
 
 // Block contribution id j decoding: beams j = 4 e + 2 la + lb; quads j = 4 nb + 16 e + 4 la + lb.
@@ -180,6 +181,11 @@ hipError_t launch_loads(const Mesh& m, const Pattern& pat, const double* qarea, 
                         hipStream_t s);
 hipError_t launch_block_jacobi(const Mesh& m, const Pattern& pat, const double* K, double* Dinv,
                                float* Dinv32, unsigned* d_err, hipStream_t s);
+// Lifting of prescribed displacements: f = 0 on constrained DOFs, fm - K_fc b on free ones;
+// after the solve u = b on constrained DOFs.
+hipError_t launch_lift(const Mesh& m, const Pattern& pat, const double* coo, const double* fm,
+                       double* f, hipStream_t s);
+hipError_t launch_apply_prescribed(const Mesh& m, double* u, hipStream_t s);
 hipError_t launch_mask_vector(const Mesh& m, const double* in, double* out, hipStream_t s);
 hipError_t launch_scalar_values(const Mesh& m, const Pattern& pat, const double* K,
                                 double* vals, hipStream_t s);

@@ -56,3 +56,35 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.sso_problem_create(ctypes.byref(m), None, None, ctypes.byref(h)) == sso.SSO_EINVAL
     assert lib.sso_solve(None, None, None) == sso.SSO_EINVAL
     assert lib.sso_adjoint(None, 0, None, None, None, None, None) == sso.SSO_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every member offset of sso_mesh, sso_options and sso_stats as the C compiler
+    lays them out from include/hipsso.h, against the ctypes structures of the binding."""
+    import shutil
+    import subprocess
+    import pytest
+    import paper_2407_20026_amd as sso
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hipsso.h"',
+             "int main(void) {"]
+    structs = (sso.sso_mesh, sso.sso_options, sso.sso_stats)
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    "-I" + os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, (name, f)
