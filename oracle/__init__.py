@@ -16,12 +16,14 @@ constraint V u = b; Sec. 2.3.1, Eqs. (5)-(6), the adjoint equation and the adjoi
   iterative refinement, and the paper's Lagrange-multiplier form for tiny cross-checks
   (:mod:`oracle.solve`),
 * objectives, the adjoint solve, complex-step element derivatives and the gathered gradient
-  dg/dp, plus central finite differences of the whole pipeline (:mod:`oracle.sensitivity`).
+  dg/dp, plus central finite differences of the whole pipeline (:mod:`oracle.sensitivity`),
+* the penalised-volume objective of the size optimisation example and the sensitivity hat
+  filter (:mod:`oracle.extras`).
 
 Every function names the passage of the paper (or the published method the paper cites) that it
 follows.  Parity unpinned: the drilling penalty factor, the frame choice of warped quads and the
 input-definition choices (self-weight density, bump recipe) are fixed by specification and have
 no closed form to pin them; every other part is pinned by the not-gpu tests.
 """
-from . import elements, assembly, solve, sensitivity  # noqa: F401
+from . import elements, assembly, solve, sensitivity, extras  # noqa: F401
 from .sensitivity import analyze, objective_and_grad_fd  # noqa: F401
