@@ -209,6 +209,28 @@ int sso_objective(sso_problem* p, int kind, const double* a, double* g_host);
 int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz,
                 double* dg_dt, double* dg_dscale, sso_stats* stats);
 
+/* Penalised material volume of the size optimisation example (Sec. 3.3) on the last solve:
+ *   g = (1 + eps1 c) W,  c = sum over nodes j of max(0, |u_jz| / u_max - 1),
+ *   W = sum over quads e of A_e t_e + max(0, (t_min - t_e) / t_min),
+ * A_e = |d13 x d24| / 2 (the area the loads use).  out_host[3] (host) = {g, c, W}.
+ * dg_dxyz [n_nodes][3] (required) and dg_dt [n_quads] (may be NULL), device outputs:
+ * eps1 W dc/dp + (1 + eps1 c) dW/dp, with dc/dp from the adjoint (Eqs. 5-6) for
+ * dg/du = sign(u_jz) / u_max on the active nodes (0 elsewhere, also at the kink).  The
+ * self-adaptive update of eps1 between optimisation steps is the caller's.  stats: host or
+ * NULL (iters of the adjoint solve, t_adj_us).  Errors: SSO_EINVAL (no solve, eps1 < 0,
+ * u_max or t_min not positive, NULL outputs), SSO_ENOTCONV, SSO_EBREAKDOWN, SSO_EHIP. */
+int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
+                       double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats);
+
+/* Hat filter of nodal sensitivities (Sec. 3.1-3.2): for n design nodes (nodes [n] device int32
+ * indices into the problem's nodes, or NULL for nodes 0..n-1) with sensitivities g [n]
+ * (device), out[i] = sum_j w_ij g_j / sum_j w_ij, w_ij = max(0, radius - |X_i - X_j|), X the
+ * problem's current coordinates (3-D distance), j ascending.  out [n] device.  Errors:
+ * SSO_EINVAL (n < 0, radius not positive, NULL arrays, a node index outside [0, n_nodes)),
+ * SSO_EHIP.  Synchronises the stream. */
+int sso_hat_filter(sso_problem* p, int32_t n, const int32_t* nodes, const double* g,
+                   double radius, double* out);
+
 /* The scalar CSR view of the pattern and the scatter permutation (built on first call, owned
  * by the problem, valid until destroy).  All arrays are device int32:
  *   row_ptr [n_dof + 1], col [nnz]: scalar CSR of K, columns sorted;

@@ -61,7 +61,8 @@ class sso_stats(ctypes.Structure):
 EXPORTS = ("sso_problem_create", "sso_problem_update", "sso_set_options", "sso_solve",
            "sso_solve_begin", "sso_solve_end", "sso_batch_create", "sso_batch_iterate",
            "sso_batch_destroy", "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix",
-           "sso_sizes", "sso_strerror", "sso_problem_destroy")
+           "sso_sizes", "sso_strerror", "sso_problem_destroy", "sso_size_objective",
+           "sso_hat_filter")
 
 _lib = None
 _hip = None
@@ -91,6 +92,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sso_batch_create.argtypes = [_vp, P(_vp)]
     lib.sso_batch_iterate.argtypes = [_vp, P(_vp), ctypes.c_int, ctypes.c_int,
                                       P(ctypes.c_int32)]
+    lib.sso_size_objective.argtypes = [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       P(ctypes.c_double), _vp, _vp, P(sso_stats)]
+    lib.sso_hat_filter.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_double, _vp]
     lib.sso_batch_destroy.argtypes = [_vp]
     lib.sso_batch_destroy.restype = None
     lib.sso_strerror.argtypes = [ctypes.c_int]
@@ -293,6 +297,38 @@ class Problem:
                                           _ptr(gs) if self.n_quads else None, ctypes.byref(st)),
                "sso_adjoint")
         return dict(dg_dxyz=gx, dg_dt=gt, dg_dscale=gs, stats=st.as_dict())
+
+    def size_objective(self, eps1, u_max, t_min, want_t=True):
+        """Penalised material volume g = (1 + eps1 c) W of the last solve (sso_size_objective):
+        dict with g, c, W, dg_dxyz [n_nodes, 3], dg_dt [n_quads] and the stats."""
+        gx = self._new((self.n_nodes, 3), torch.float64)
+        gt = self._new(self.n_quads, torch.float64) if want_t and self.n_quads else None
+        out = (ctypes.c_double * 3)()
+        st = sso_stats()
+        _check(load_library().sso_size_objective(self.handle, float(eps1), float(u_max),
+                                                 float(t_min), out, _ptr(gx), _ptr(gt),
+                                                 ctypes.byref(st)), "sso_size_objective")
+        return dict(g=out[0], c=out[1], W=out[2], dg_dxyz=gx, dg_dt=gt, stats=st.as_dict())
+
+    def hat_filter(self, g, radius, nodes=None):
+        """Hat-filtered nodal sensitivities (sso_hat_filter): g [n] for the design nodes
+        (int indices, or None for nodes 0..n-1), weights max(0, radius - distance)."""
+        d = self.device
+        self.stream.wait_stream(torch.cuda.current_stream(d))
+        with torch.cuda.stream(self.stream):
+            gd = _dev(g, torch.float64, d)
+            nd = _dev(nodes, torch.int32, d)
+        n = int(gd.numel())
+        out = self._new(n, torch.float64)
+        _check(load_library().sso_hat_filter(self.handle, n, _ptr(nd), _ptr(gd), float(radius),
+                                             _ptr(out)), "sso_hat_filter")
+        return out
+
+    @staticmethod
+    def update_eps1(eps1, violated, kappa=1.015):
+        """Self-adaptive penalty coefficient of the size optimisation (Sec. 3.3): times kappa
+        after a step that violates the displacement limit, divided by it otherwise."""
+        return eps1 * kappa if violated else eps1 / kappa
 
     def pattern(self):
         """Copies of the scalar CSR view and the scatter permutation (int32 device tensors)."""

@@ -1,6 +1,7 @@
 // C ABI and host runtime of libhipsso: problem lifecycle, device buffers, launch sequencing on
 // the problem's stream, error mapping and per-stage timing.
 #include <new>
+#include <cmath>
 #include <cstring>
 
 #include "sso_internal.h"
@@ -28,6 +29,9 @@ struct sso_problem {
   double* rhs = nullptr;
   double* gbeam = nullptr;
   double* gquad = nullptr;
+  double* gw = nullptr;         // size objective: volume terms [14 n_quads], shares [n_quads],
+  double* wv = nullptr;         //   partials (allocated on first use)
+  double* xpart = nullptr;
   double* d_scal = nullptr;     // small device scalars (dot products, residual norms)
   double* h_scal = nullptr;     // pinned mirror
   unsigned* d_err = nullptr;
@@ -107,7 +111,8 @@ void free_problem(sso_problem* p) {
                   (void*)p->Dinv, (void*)p->f, (void*)p->K32, (void*)p->Dinv32, (void*)p->B, (void*)p->B32, (void*)p->u,
                   (void*)p->lam, (void*)p->rhs, (void*)p->gbeam, (void*)p->gquad,
                   (void*)p->d_scal, (void*)p->d_err, (void*)p->row_ptr, (void*)p->col,
-                  (void*)p->perm, (void*)p->seg, (void*)m.u_presc, (void*)p->fm})
+                  (void*)p->perm, (void*)p->seg, (void*)m.u_presc, (void*)p->fm,
+                  (void*)p->gw, (void*)p->wv, (void*)p->xpart})
     dev_free(q, s);
   free_pattern(p->pat, s);
   pcg_free(p->w, s);
@@ -559,6 +564,57 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
     stats->bytes_moved = solve_bytes(p, iters, 0);
   }
   return status;
+}
+
+int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
+                       double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats) {
+  if (!p || !p->solved || !out_host || !dg_dxyz) return SSO_EINVAL;
+  if (!(eps1 >= 0.0) || !std::isfinite(eps1) || !(u_max > 0.0) || !std::isfinite(u_max) ||
+      !(t_min > 0.0) || !std::isfinite(t_min))
+    return SSO_EINVAL;
+  hipStream_t s = p->s;
+  const Mesh& m = p->m;
+  constexpr int XWG = 1024;
+  if (!p->xpart) {
+    TRY_HIP(dev_alloc(&p->xpart, 2 * XWG, s));
+    TRY_HIP(dev_alloc(&p->gw, 14 * (int64_t)m.n_quads, s));
+    TRY_HIP(dev_alloc(&p->wv, m.n_quads, s));
+  }
+  TRY_HIP(hipEventRecord(p->ev[4], s));
+  // volume terms, then dc/du (masked) with the sums c and W in d_scal[2..3]
+  TRY_HIP(launch_volume_terms(m, t_min, p->gw, p->wv, s));
+  TRY_HIP(launch_size_terms(m, p->u, u_max, p->wv, p->rhs, p->xpart, XWG, p->d_scal + 2, s));
+  int iters = 0, outer = 0;
+  const int status = run_solver(p, p->rhs, p->lam, &iters, &outer);
+  if (status != SSO_OK && status != SSO_ENOTCONV) return status;
+  TRY_HIP(launch_adjoint_terms(m, p->pat, p->u, p->lam, 1.0, 0.0, p->gbeam, p->gquad, s));
+  TRY_HIP(launch_size_combine(m, eps1, p->d_scal + 2, p->gw, p->gbeam, p->gquad, s));
+  TRY_HIP(launch_gather(m, p->pat, p->gbeam, p->gquad, dg_dxyz, dg_dt, nullptr, s));
+  TRY_HIP(hipEventRecord(p->ev[5], s));
+  TRY_HIP(hipMemcpyAsync(p->h_scal + 2, p->d_scal + 2, 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  const double c = p->h_scal[2], W = p->h_scal[3];
+  out_host[0] = (1.0 + eps1 * c) * W;
+  out_host[1] = c;
+  out_host[2] = W;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
+  }
+  return status;
+}
+
+int sso_hat_filter(sso_problem* p, int32_t n, const int32_t* nodes, const double* g,
+                   double radius, double* out) {
+  if (!p || n < 0 || (n > 0 && (!g || !out)) || !(radius > 0.0) || !std::isfinite(radius))
+    return SSO_EINVAL;
+  if (!nodes && n > p->m.n_nodes) return SSO_EINVAL;
+  hipStream_t s = p->s;
+  TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
+  TRY_HIP(launch_hat_filter(n, nodes, p->m, g, radius, out, p->d_err, s));
+  return read_errors(p);
 }
 
 int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,

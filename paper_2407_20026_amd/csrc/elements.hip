@@ -528,6 +528,37 @@ __global__ void __launch_bounds__(128) k_quad_adjoint(Mesh m, const double* u, c
   gquad[t] = wz * fz.d - c_lam * phi.d;
 }
 
+// ---- penalised material volume of the size optimisation (Sec. 3.3) ------------------------
+// Thread (e, d), d in 0..13 (the layout of the adjoint element terms): gw[14 e + d] =
+// t_e dA_e/dX_d for the 12 corner coordinates, dW/dt_e = A_e - [t_e < t_min] / t_min for
+// d = 12, 0 for d = 13; the d = 12 thread also writes the element's share of W,
+// w[e] = A_e t_e + max(0, (t_min - t_e) / t_min), with A_e = |d13 x d24| / 2 (the load area).
+__global__ void __launch_bounds__(128) k_volume_terms(Mesh m, double t_min, double* gw,
+                                                      double* w) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 14 * (int64_t)m.n_quads) return;
+  const int64_t e = t / 14;
+  const int d = (int)(t % 14);
+  Dual X[4][3];
+  for (int i = 0; i < 4; ++i) {
+    const int nd = m.quad_nodes[4 * e + i];
+    for (int k = 0; k < 3; ++k)
+      X[i][k] = Dual(m.xyz[3 * (int64_t)nd + k], (3 * i + k == d) ? 1.0 : 0.0);
+  }
+  QGeom<Dual> g;
+  quad_geom(X, g);
+  const double te = m.quad_prop[5 * e];
+  const bool below = te < t_min;
+  double v = 0.0;
+  if (d < 12) {
+    v = te * g.area.d;
+  } else if (d == 12) {
+    v = g.area.v - (below ? 1.0 / t_min : 0.0);
+    w[e] = g.area.v * te + (below ? (t_min - te) / t_min : 0.0);
+  }
+  gw[t] = v;
+}
+
 // dg/dxyz of node I: sum over incident elements in ascending element order (the diagonal
 // block slot of row I lists exactly the incident elements, sorted by contribution id).
 __global__ void k_gather(Mesh m, const int32_t* bdiag, const int32_t* bseg, const int32_t* bperm,
@@ -577,6 +608,14 @@ hipError_t launch_adjoint_terms(const Mesh& m, const Pattern& pat, const double*
   if (m.n_quads)
     hipLaunchKernelGGL(k_quad_adjoint, dim3(nblk(14 * (int64_t)m.n_quads, 128)), dim3(128), 0, s,
                        m, u, lam, c_lam, c_u, gquad);
+  return hipGetLastError();
+}
+
+hipError_t launch_volume_terms(const Mesh& m, double t_min, double* gw, double* w,
+                               hipStream_t s) {
+  if (m.n_quads)
+    hipLaunchKernelGGL(k_volume_terms, dim3(nblk(14 * (int64_t)m.n_quads, 128)), dim3(128), 0,
+                       s, m, t_min, gw, w);
   return hipGetLastError();
 }
 

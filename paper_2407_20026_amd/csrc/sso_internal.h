@@ -170,6 +170,16 @@ hipError_t launch_element_stiffness(const Mesh& m, double* coo, double* qarea, u
 hipError_t launch_adjoint_terms(const Mesh& m, const Pattern& pat, const double* u,
                                 const double* lam, double c_lam, double c_u, double* gbeam,
                                 double* gquad, hipStream_t s);
+// Size optimisation objective pieces and the sensitivity hat filter (extras.hip, elements.hip).
+hipError_t launch_volume_terms(const Mesh& m, double t_min, double* gw, double* w,
+                               hipStream_t s);
+hipError_t launch_size_terms(const Mesh& m, const double* u, double u_max, const double* w,
+                             double* dcdu, double* partials, int max_wg, double* d_out,
+                             hipStream_t s);
+hipError_t launch_size_combine(const Mesh& m, double eps1, const double* sc, const double* gw,
+                               double* gbeam, double* gquad, hipStream_t s);
+hipError_t launch_hat_filter(int n, const int32_t* nodes, const Mesh& m, const double* g,
+                             double r, double* out, unsigned* err, hipStream_t s);
 hipError_t launch_gather(const Mesh& m, const Pattern& pat, const double* gbeam,
                          const double* gquad, double* dg_dxyz, double* dg_dt, double* dg_dscale,
                          hipStream_t s);
