@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--shellnet", type=int, default=0,
                     help="also time one loss + backward of the network-driven batch of this "
                          "many 80 x 80 shells (0: skip)")
+    ap.add_argument("--arch", default="2,6,10,20,30,80",
+                    help="elements per span of the arch-bridge rows to time ('' = none)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the workload, copy a float64 tensor of this many MiB 3 times "
                          "(a plain copy kernel of known size for scaling HBM counters)")
@@ -221,6 +223,51 @@ def general_objective_bench(mesh, opts, steps):
     log(f"general objective: {1000 * el / steps:.2f} ms/step")
     return {"objective": "linear (u_z at the centre node)", "solves_per_s": steps / el,
             "ms_per_step": 1000 * el / steps, "adjoint_pcg_iters": int(np.median(adj))}
+
+
+# FEA time of the paper's performance table (seconds, best column: SciPy sparse with GPU
+# assembly, A100 + Xeon 6342) for the 100-span arch bridge, by DOF; context only.
+PAPER_ARCH_FEA_S = {1206: 0.006, 3606: 0.006, 6006: 0.007, 12006: 0.038, 18006: 0.044,
+                    48006: 0.072}
+
+
+def arch_bench(rows, reps=3):
+    """The paper's performance-study structure (100 parabolic arch spans, beam elements only):
+    FEA (elements, assembly, block-Jacobi PCG to 1e-8) and sensitivity (FEA + adjoint of the
+    strain energy) wall time per row, beside the paper's best FEA time for the same DOF."""
+    import torch
+    import meshgen
+    import paper_2407_20026_amd as sso
+    out = []
+    for n_el in rows:
+        mesh = meshgen.arch_bridge(n_el)
+        with sso.Problem(mesh, sso.Options(rtol=1e-8, max_it=400000)) as prob:
+            def fea():
+                _, st = prob.solve(check=False)
+                if prob.last_status not in (sso.SSO_OK, sso.SSO_ENOTCONV):
+                    raise sso.SSOError(prob.last_status, "sso_solve")
+                return st
+
+            def sens():
+                st = fea()
+                prob.adjoint("strain_energy")
+                return st
+            st = sens()
+            times = {}
+            for name, fn in (("fea", fea), ("sensitivity", sens)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                torch.cuda.synchronize()
+                times[name] = (time.perf_counter() - t0) / reps
+        out.append({"elements_per_span": n_el, "dof": mesh.n_dof, "pcg_iters": st["iters"],
+                    "rel_residual": st["rel_residual"], "fea_ms": 1000 * times["fea"],
+                    "sensitivity_ms": 1000 * times["sensitivity"],
+                    "paper_best_fea_s": PAPER_ARCH_FEA_S.get(mesh.n_dof)})
+        log(f"arch {n_el} elements/span ({mesh.n_dof} DOF): {st['iters']} iterations, "
+            f"FEA {1000 * times['fea']:.2f} ms, sensitivity {1000 * times['sensitivity']:.2f} ms")
+    return out
 
 
 def shellnet_bench(n_variants, solver, m=80):
@@ -383,6 +430,8 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec, solver)
                           for prec in ("fp64", "mixed")}
+    if args.arch:
+        out["arch_replay"] = arch_bench([int(v) for v in args.arch.split(",")])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, args.objective, args.cpu_seconds)
     print(json.dumps(out), flush=True)

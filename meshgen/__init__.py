@@ -132,6 +132,37 @@ def gridshell(n: int = 11, span: float = 10.0, rise: float = 2.0, noise: float =
                 name=f"gridshell{n}x{n}")
 
 
+def arch_bridge(n_el: int, n_spans: int = 100, span: float = 30.0, rise: float = 10.0,
+                E: float = 200e9, nu: float = 0.3, A: float = 0.05, Iy: float = 0.01,
+                Iz: float = 0.01, J: float = 0.02, w: float = -100e3) -> Mesh:
+    """The multi-span arch bridge of the paper's performance study: n_spans parabolic arches
+    (span 30 m, rise 10 m) in the XZ plane, each cut into n_el equal-x beam elements, sharing
+    their pier nodes; DOF = 6 (n_spans n_el + 1).  Piers pinned (translations) with the twist
+    about the bridge axis also held, so the chain has no out-of-plane rigid rotation.
+    Self-weight as downward nodal loads: w (N/m) times each node's tributary arc length.
+    Section and load are not given by the paper: a steel box section is assumed."""
+    n = n_spans * n_el + 1
+    x = np.linspace(0.0, n_spans * span, n)
+    s = (x % span) / span
+    s[-1] = 1.0 if n_el else 0.0
+    z = 4.0 * rise * s * (1.0 - s)
+    z[::n_el] = 0.0
+    xyz = _c(np.stack([x, np.zeros(n), z], 1), np.float64)
+    fixed = np.zeros((n, 6), np.uint8)
+    fixed[::n_el, :4] = 1
+    seg = np.sqrt(np.diff(x) ** 2 + np.diff(z) ** 2)
+    trib = np.zeros(n)
+    trib[:-1] += 0.5 * seg
+    trib[1:] += 0.5 * seg
+    f = np.zeros((n, 6))
+    f[:, 2] = w * trib
+    beams = _c(np.stack([np.arange(n - 1), np.arange(1, n)], 1), np.int32)
+    G = E / (2.0 * (1.0 + nu))
+    prop = np.tile(np.array([E, G, A, Iy, Iz, J]), (n - 1, 1))
+    return Mesh(xyz=xyz, fixed=fixed, f_nodal=f, beam_nodes=beams, beam_prop=_c(prop, np.float64),
+                name=f"arch{n_spans}x{n_el}")
+
+
 def bump_heights(x: np.ndarray, y: np.ndarray, L: float, rng: np.random.Generator,
                  n_bumps: int = 5, amp_max: float = 3.0) -> np.ndarray:
     """Sum of Gaussian bumps: amplitude ~ U[0, amp_max], centre ~ U[0, L]^2,

@@ -65,6 +65,7 @@ CASES = {
     "shell8": small_shell,
     "mixed": mixed_mesh,
     "shell60": meshgen.shell_60,
+    "arch6": lambda: meshgen.arch_bridge(6),
 }
 
 TIGHT = dict(rtol=1e-13, max_it=50000)
