@@ -344,6 +344,7 @@ def main():
     u_out = torch.empty((mesh.n_nodes, 6), dtype=torch.float64, device="cuda")
 
     spmv_us, spmv_n, iters, resid, adj_iters, outer = [], [], [], [], [], []
+    last_g = []
 
     statuses = []
 
@@ -355,6 +356,7 @@ def main():
         prob.objective(args.objective, a) if args.objective == "linear" else \
             prob.objective(args.objective)
         g = prob.adjoint(args.objective, dg_du=a)
+        last_g[:] = [g]
         iters.append(st["iters"])
         outer.append(st["refine_steps"])
         resid.append(st["rel_residual"])
@@ -380,6 +382,22 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     log(f"timed {args.steps} steps: {1000 * el / args.steps:.2f} ms/step")
+    vs_fp64 = None
+    if args.precision == "mixed":
+        # the error of u and of the gradients against the FP64 path, same mesh and rtol
+        u_mx, g_mx = u_out.clone(), last_g[0]
+        with sso.Problem(mesh, sso.Options(rtol=args.rtol, max_it=400000,
+                                           solver=solver)) as ref:
+            u_ref, _ = ref.solve(check=False)
+            g_ref = ref.adjoint(args.objective, dg_du=a)
+
+        def rel_inf(x, y):
+            return float((x - y).abs().max() / y.abs().max())
+        vs_fp64 = {"u_rel_2norm": float((u_mx - u_ref).norm() / u_ref.norm()),
+                   "dg_dxyz_rel_inf": rel_inf(g_mx["dg_dxyz"], g_ref["dg_dxyz"]),
+                   "dg_dt_rel_inf": rel_inf(g_mx["dg_dt"], g_ref["dg_dt"])
+                   if g_ref["dg_dt"] is not None and g_ref["dg_dt"].numel() else None}
+        log(f"mixed vs FP64: {vs_fp64}")
     ms = 1000.0 * el / args.steps
     rate = args.steps / el
     spmv_bytes = st["spmv_bytes"]
@@ -406,8 +424,8 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": desc, "n_dof": mesh.n_dof, "objective": args.objective,
                    "rtol": args.rtol, "precision": args.precision, "pcg": solver_name,
-                   **({"inner_max_it": args.inner_max_it, "outer_steps": int(np.median(outer))}
-                      if args.precision == "mixed" else {}),
+                   **({"inner_max_it": args.inner_max_it, "outer_steps": int(np.median(outer)),
+                       "vs_fp64": vs_fp64} if args.precision == "mixed" else {}),
                    "pcg_iters": int(np.median(iters)),
                    "adjoint_pcg_iters": int(np.median(adj_iters)),
                    "rel_residual": float(np.max(resid)), "n_blocks": prob.n_blocks,
