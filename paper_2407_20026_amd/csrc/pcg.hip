@@ -497,18 +497,32 @@ __device__ inline void row_product3(int rb, int re, const int32_t* __restrict__ 
 
 // The same over the W padded slots of row I (B in the padded layout, bcol_ell): every load
 // address is known without the row pointers, the padding adds exact zeros.
+// The row's column indices and this lane's entries of its W blocks (addresses from the row
+// index alone).
 template <class T, int W>
-__device__ inline void row_product3_ell(int I, const int32_t* __restrict__ bcol_ell,
-                                        const T* __restrict__ B, const T* __restrict__ r,
-                                        const T* __restrict__ w, const T* __restrict__ t, int a,
-                                        int b, T& ar, T& aw, T& at) {
+struct EllRow {
+  int32_t J[W];
+  typename Vec2<T>::type k[W];
+};
+
+template <class T, int W>
+__device__ inline void ell_load(int I, const int32_t* __restrict__ bcol_ell,
+                                const T* __restrict__ B, int a, int b, EllRow<T, W>& e) {
   using V = typename Vec2<T>::type;
   const int64_t base = (int64_t)I * W;
   const int off = 6 * a + b;
-  int32_t J[W];
-  V k[W];
-  for (int u = 0; u < W; ++u) J[u] = bcol_ell[base + u];
-  for (int u = 0; u < W; ++u) k[u] = *reinterpret_cast<const V*>(B + 36 * (base + u) + off);
+  for (int u = 0; u < W; ++u) e.J[u] = bcol_ell[base + u];
+  for (int u = 0; u < W; ++u) e.k[u] = *reinterpret_cast<const V*>(B + 36 * (base + u) + off);
+}
+
+// The three products over a loaded row: gathers of r, w, t at the row's columns.
+template <class T, int W>
+__device__ inline void ell_gather3(const EllRow<T, W>& e, const T* __restrict__ r,
+                                   const T* __restrict__ w, const T* __restrict__ t, int b,
+                                   T& ar, T& aw, T& at) {
+  using V = typename Vec2<T>::type;
+  const int32_t* J = e.J;
+  const V* k = e.k;
   T sr = 0, sw = 0, st = 0;
   for (int u = 0; u < W; ++u) {
     const int64_t j = 6 * (int64_t)J[u] + b;
@@ -522,6 +536,26 @@ __device__ inline void row_product3_ell(int I, const int32_t* __restrict__ bcol_
   ar = sr;
   aw = sw;
   at = st;
+}
+
+template <class T, int W>
+__device__ inline void row_product3_ell(int I, const int32_t* __restrict__ bcol_ell,
+                                        const T* __restrict__ B, const T* __restrict__ r,
+                                        const T* __restrict__ w, const T* __restrict__ t, int a,
+                                        int b, T& ar, T& aw, T& at) {
+  EllRow<T, W> e;
+  ell_load<T, W>(I, bcol_ell, B, a, b, e);
+  ell_gather3<T, W>(e, r, w, t, b, ar, aw, at);
+}
+
+// The state record seen through an address the compiler must treat as per-lane (offset by a
+// zero it cannot see through), so its fields are fetched by vector loads issued with the other
+// first-group loads and waited for where they are used, instead of by scalar loads that the
+// kernel waits for before issuing anything else.
+__device__ inline const PcgState* lane_view(const PcgState* st) {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return reinterpret_cast<const PcgState*>(reinterpret_cast<const char*>(st) + z);
 }
 
 // Single-vector product B x over the row (W = 0: block order of K via the row pointers).
@@ -637,6 +671,60 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
   write_partials<3, T>(v, d.pp[0], G.lb, G.ng);
 }
 
+// The operands of iteration i with the parity-dependent buffers resolved.  The host builds it
+// for the single-problem kernel and passes it by value, so no kernel argument's address depends
+// on another argument (the kernel issues its argument loads at once); multi-problem launches
+// build it from the table entry and the workgroup's iteration counter.
+template <class T>
+struct Cg1Args {
+  const T* r_in;
+  const T* w_in;
+  const T* s_in;
+  T* r_out;
+  T* w_out;
+  T* s_out;
+  T* p;
+  T* x;
+  const int32_t* brow_ptr;
+  const int32_t* bcol;
+  const int32_t* bcol_ell;
+  const T* B;
+  const T* Dinv;
+  const double* pp_in;
+  double* pp_out;
+  PcgState* st;
+  int32_t* jw;
+  double rtol2;
+  int n_nodes, i, max_it;
+};
+
+template <class T>
+__host__ __device__ inline Cg1Args<T> cg1_args(const FusedDesc<T>& d, int i) {
+  Cg1Args<T> a;
+  a.r_in = d.r[i & 1];
+  a.w_in = d.w[i & 1];
+  a.s_in = d.s[i & 1];
+  a.r_out = d.r[(i + 1) & 1];
+  a.w_out = d.w[(i + 1) & 1];
+  a.s_out = d.s[(i + 1) & 1];
+  a.p = d.p;
+  a.x = d.x;
+  a.brow_ptr = d.brow_ptr;
+  a.bcol = d.bcol;
+  a.bcol_ell = d.bcol_ell;
+  a.B = d.B;
+  a.Dinv = d.Dinv;
+  a.pp_in = d.pp[i & 1];
+  a.pp_out = d.pp[(i + 1) & 1];
+  a.st = d.st;
+  a.jw = d.jw;
+  a.rtol2 = d.rtol2;
+  a.n_nodes = d.n_nodes;
+  a.i = i;
+  a.max_it = d.max_it;
+  return a;
+}
+
 // One single-reduction iteration for workgroup lb of ng.  SINGLE (one problem, launched by its
 // own host loop): the iteration index comes from the host (launch k is iteration k until the
 // state says done) and every load that does not depend on another -- done flag, state scalars,
@@ -645,32 +733,35 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
 // values, gathered vectors).  Otherwise (multi-problem launches) the index is the workgroup's
 // own counter and the partials are loaded where they are summed, which keeps the register
 // count, and the occupancy that many problems in flight need, lower.
-template <class T, bool SINGLE, int W>
-__device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int ng,
-                                              int i_host) {
+template <class T, bool SINGLE, int W, bool ONE_PASS = false>
+__device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int ng) {
   PcgState* st = d.st;
-  const int done = st->done;
-  const int i = SINGLE ? i_host : d.jw[lb];
-  if (!SINGLE && done) return;
+  const PcgState* stv = SINGLE ? lane_view(st) : st;
+  const int done = stv->done;
+  const int i = d.i;
   const int n_nodes = d.n_nodes;
-  const T* __restrict__ ri = d.r[i & 1];
-  const T* __restrict__ wi = d.w[i & 1];
-  const T* __restrict__ so = d.s[i & 1];
-  T* __restrict__ rn = d.r[(i + 1) & 1];
-  T* __restrict__ wn = d.w[(i + 1) & 1];
-  T* __restrict__ sn = d.s[(i + 1) & 1];
+  const T* __restrict__ ri = d.r_in;
+  const T* __restrict__ wi = d.w_in;
+  const T* __restrict__ so = d.s_in;
+  T* __restrict__ rn = d.r_out;
+  T* __restrict__ wn = d.w_out;
+  T* __restrict__ sn = d.s_out;
   T* __restrict__ p = d.p;
   T* __restrict__ x = d.x;
   const SpLane L = sp_lane();
   const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
-  const double ff_prev = st->ff, rtol2 = st->rtol2;
-  const double gam_prev = st->rzs[(i - 1) & 1], alpha_prev = st->alphas[(i - 1) & 1];
-  const int max_it = st->max_it;
+  // SINGLE: the state record through vector loads issued first, waited for with the rest of
+  // the first group (the done test comes after the row's indices and values are issued)
+  const double ff_prev = stv->ff, rtol2 = d.rtol2;
+  const double gam_prev = stv->rzs[(i - 1) & 1], alpha_prev = stv->alphas[(i - 1) & 1];
+  const int max_it = d.max_it;
   static_assert(3 * MAX_TPB >= PCG_MAX_WG, "three partials per thread");
   double pv[3][3] = {};
   T alpha = 0, beta = 0, ab = 0;
   T v[3] = {0, 0, 0};
-  for (int gi = lb; gi * ROWS_PER_WG < n_nodes; gi += ng) {
+  // ONE_PASS: the launch gives every workgroup rows (n_wg = ceil(n_nodes / 18)), so the body
+  // runs once without an entry test and every kernel argument is loaded at once
+  for (int gi = lb; ONE_PASS || gi * ROWS_PER_WG < n_nodes; gi += ng) {
     const int I = gi * ROWS_PER_WG + slot;
     const bool ok = L.ok && I < n_nodes;
     const bool own = ok && L.b == 0;
@@ -698,7 +789,7 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
       // finish_partials uses (ng <= PCG_MAX_WG <= 3 MAX_TPB); unconditional loads from a
       // clamped index, the out-of-range ones dropped where they are added
       if (gi == lb) {
-        const double* pp = d.pp[i & 1];
+        const double* pp = d.pp_in;
         for (int u = 0; u < 3; ++u) {
           const int k = (int)threadIdx.x + u * MAX_TPB;
           const int kc = k < ng ? k : 0;
@@ -706,13 +797,18 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
         }
       }
     }
-    if (SINGLE && gi == lb && done) return;   // every load above is in bounds either way
     T br = 0, bw = 0, bs = 0;
     if constexpr (W == 0) {
       if (!ok) re = rb;
       row_product3<T>(rb, re, d.bcol, d.B, ri, wi, so, L.a, L.b, br, bw, bs);
     } else {
-      row_product3_ell<T, W>(Ic, d.bcol_ell, d.B, ri, wi, so, L.a, L.b, br, bw, bs);
+      EllRow<T, W> e;
+      ell_load<T, W>(Ic, d.bcol_ell, d.B, L.a, L.b, e);
+      // keep the scheduler from sinking the loads above below the first wait: the first
+      // group (state, own-row operands, partials, column indices and block values) goes out
+      // at once
+      if (SINGLE) __builtin_amdgcn_sched_barrier(0);
+      ell_gather3<T, W>(e, ri, wi, so, L.b, br, bw, bs);
     }
     if (!SINGLE) {
       rq = ri[qc];
@@ -731,8 +827,11 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
                     (k0 + MAX_TPB < ng ? pv[c][1] : 0.0)) +
                    (k0 + 2 * MAX_TPB < ng ? pv[c][2] : 0.0);
         block_sum<3, double>(tot);
+        // after the barriers of the sum, so that no load above is moved past the test: a
+        // launch after convergence has read (in bounds) but writes nothing
+        if (__builtin_amdgcn_readfirstlane(done)) return;
       } else {
-        finish_partials<3>(d.pp[i & 1], ng, tot);
+        finish_partials<3>(d.pp_in, ng, tot);
       }
       const double gam = tot[0], del = tot[1], rho = tot[2];
       const double ff = (i == 0) ? rho : ff_prev;
@@ -794,9 +893,12 @@ __device__ __forceinline__ void cg1_iteration(const FusedDesc<T>& d, int lb, int
       v[1] += wv * uv;
       v[2] += rv * rv;
     }
+    // one pass (the grid covers every row): no back edge, so the waits for the first group's
+    // loads are placed where their values are used
+    if constexpr (ONE_PASS) break;
   }
   block_sum<3, T>(v);
-  write_partials<3, T>(v, d.pp[(i + 1) & 1], lb, ng);
+  write_partials<3, T>(v, d.pp_out, lb, ng);
   if (!SINGLE && threadIdx.x == 0) d.jw[lb] = i + 1;
 }
 
@@ -805,14 +907,15 @@ template <class T, int W>
 __global__ void __launch_bounds__(MAX_TPB)
 k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   const WgOf<FusedDesc<T>> G = wg_of(D, wg_prob);
-  cg1_iteration<T, false, W>(*G.d, G.lb, G.ng, 0);
+  if (G.d->st->done) return;
+  cg1_iteration<T, false, W>(cg1_args(*G.d, G.d->jw[G.lb]), G.lb, G.ng);
 }
 
 // One problem: the descriptor by value, launch k performs iteration k (unless done).
-template <class T, int W>
+template <class T, int W, bool ONE_PASS>
 __global__ void __launch_bounds__(MAX_TPB)
-k_cg1_iter1(const FusedDesc<T> d, int i) {
-  cg1_iteration<T, true, W>(d, blockIdx.x, gridDim.x, i);
+k_cg1_iter1(const Cg1Args<T> a) {
+  cg1_iteration<T, true, W, ONE_PASS>(a, blockIdx.x, gridDim.x);
 }
 
 // Kernel of a padded width (0: block order of K); a width the pattern builder does not make is
@@ -1229,19 +1332,33 @@ struct FusedBuffers {
 
 // One single-problem iteration launch for the descriptor's padded width (the width was checked
 // when the solve started: fused_start).
-template <class T>
-static void launch_iter1(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s) {
+template <class T, bool P1>
+static void launch_iter1_w(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s) {
+  const Cg1Args<T> a = cg1_args(hd, k);
   switch (hd.ell_w) {
-    case 6: hipLaunchKernelGGL((k_cg1_iter1<T, 6>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k); break;
-    case 9: hipLaunchKernelGGL((k_cg1_iter1<T, 9>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k); break;
+    case 6:
+      hipLaunchKernelGGL((k_cg1_iter1<T, 6, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
+      break;
+    case 9:
+      hipLaunchKernelGGL((k_cg1_iter1<T, 9, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
+      break;
     case 12:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 12>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+      hipLaunchKernelGGL((k_cg1_iter1<T, 12, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
       break;
     case 16:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 16>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+      hipLaunchKernelGGL((k_cg1_iter1<T, 16, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
       break;
-    default: hipLaunchKernelGGL((k_cg1_iter1<T, 0>), dim3(nwg), dim3(MAX_TPB), 0, s, hd, k);
+    default:
+      hipLaunchKernelGGL((k_cg1_iter1<T, 0, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
   }
+}
+
+template <class T>
+static void launch_iter1(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s) {
+  if ((int64_t)nwg * ROWS_PER_WG >= hd.n_nodes)
+    launch_iter1_w<T, true>(hd, nwg, k, s);
+  else
+    launch_iter1_w<T, false>(hd, nwg, k, s);
 }
 
 template <class T>
@@ -1273,8 +1390,10 @@ static FusedDesc<T> fused_desc(const Mesh& m, const Pattern& pat, const T* B, co
 
 // Upload the descriptor and start a single-reduction solve (initial residual and partials).
 template <class T>
-static hipError_t fused_start(const FusedDesc<T>& hd, double rtol, int max_it, PcgWork& w,
+static hipError_t fused_start(FusedDesc<T>& hd, double rtol, int max_it, PcgWork& w,
                               hipStream_t s, FusedDesc<T>** out) {
+  hd.rtol2 = rtol * rtol;
+  hd.max_it = max_it;
   FusedDesc<T>* dd = reinterpret_cast<FusedDesc<T>*>(sizeof(T) == 8 ? w.fdesc64 : w.fdesc32);
   hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
@@ -1295,7 +1414,7 @@ static hipError_t fused_run(const Mesh& m, const Pattern& pat, const T* B, const
                             const T* b, const FusedBuffers<T>& v, double rtol, int max_it,
                             PcgWork& w, hipStream_t s, int* iters, int* status,
                             int profile_every) {
-  const FusedDesc<T> hd = fused_desc(m, pat, B, Dinv, b, v, w);
+  FusedDesc<T> hd = fused_desc(m, pat, B, Dinv, b, v, w);
   FusedDesc<T>* dd = nullptr;
   hipError_t e = fused_start(hd, rtol, max_it, w, s, &dd);
   if (e != hipSuccess) return e;

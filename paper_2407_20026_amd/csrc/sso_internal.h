@@ -74,6 +74,8 @@ struct FusedDesc {
   int32_t* jw;      // per-workgroup iteration counters
   PcgState* st;
   int n_nodes, n_wg, wg_base, ell_w;
+  double rtol2;     // squared relative tolerance and iteration limit of the running solve
+  int max_it;       //   (set when it starts; read by the single-problem iteration)
 };
 
 // Block-level pattern (6x6 blocks, one block row per node).
