@@ -62,8 +62,10 @@ __device__ inline WgOf<Desc> wg_of(const Desc* __restrict__ D,
 template <class T>
 using Wg = WgOf<PcgDesc<T>>;
 
-// Fixed-order workgroup sum of NV values; the result is returned to every thread.
-template <int NV, class A>
+// Fixed-order workgroup sum of NV values; the result is returned to every thread.  TAG gives
+// a call site its own LDS array; LAST (the array is not written again before the kernel ends
+// or before a barrier) drops the trailing barrier that protects the array's reuse.
+template <int NV, class A, int TAG = 0, bool LAST = false>
 __device__ inline void block_sum(A v[NV]) {
   __shared__ A lds[NV][MAX_WAVES];
   for (int off = 32; off > 0; off >>= 1)
@@ -78,7 +80,7 @@ __device__ inline void block_sum(A v[NV]) {
     for (int w = 1; w < nw; ++w) s += lds[k][w];
     v[k] = s;
   }
-  __syncthreads();
+  if (!LAST) __syncthreads();
 }
 
 // Sum of NV arrays of n per-workgroup partials (array k at partials + k * n), fixed order.
@@ -826,8 +828,8 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
           tot[c] = ((0.0 + (k0 < ng ? pv[c][0] : 0.0)) +
                     (k0 + MAX_TPB < ng ? pv[c][1] : 0.0)) +
                    (k0 + 2 * MAX_TPB < ng ? pv[c][2] : 0.0);
-        block_sum<3, double>(tot);
-        // after the barriers of the sum, so that no load above is moved past the test: a
+        block_sum<3, double, 1, true>(tot);
+        // after the barrier of the sum, so that no load above is moved past the test: a
         // launch after convergence has read (in bounds) but writes nothing
         if (__builtin_amdgcn_readfirstlane(done)) return;
       } else {
@@ -897,7 +899,7 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
     // loads are placed where their values are used
     if constexpr (ONE_PASS) break;
   }
-  block_sum<3, T>(v);
+  block_sum<3, T, 2, true>(v);   // the kernel ends after it
   write_partials<3, T>(v, d.pp_out, lb, ng);
   if (!SINGLE && threadIdx.x == 0) d.jw[lb] = i + 1;
 }
