@@ -697,7 +697,7 @@ struct Cg1Args {
   PcgState* st;
   int32_t* jw;
   double rtol2;
-  int n_nodes, i, max_it;
+  int n_nodes, i, max_it, n_wg;
 };
 
 template <class T>
@@ -724,6 +724,7 @@ __host__ __device__ inline Cg1Args<T> cg1_args(const FusedDesc<T>& d, int i) {
   a.n_nodes = d.n_nodes;
   a.i = i;
   a.max_it = d.max_it;
+  a.n_wg = d.n_wg;
   return a;
 }
 
@@ -806,10 +807,13 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
     } else {
       EllRow<T, W> e;
       ell_load<T, W>(Ic, d.bcol_ell, d.B, L.a, L.b, e);
-      // keep the scheduler from sinking the loads above below the first wait: the first
-      // group (state, own-row operands, partials, column indices and block values) goes out
-      // at once
-      if (SINGLE) __builtin_amdgcn_sched_barrier(0);
+      if (SINGLE && gi == lb) {
+        // the column indices are in registers before the done test (their wait is the done
+        // flag's, one round trip): a launch after convergence stops there, and the gathers
+        // that depend on them go out right after it with the rest of the row's loads
+        for (int u = 0; u < W; ++u) asm volatile("" ::"v"(e.J[u]));
+        if (__builtin_amdgcn_readfirstlane(done)) return;
+      }
       ell_gather3<T, W>(e, ri, wi, so, L.b, br, bw, bs);
     }
     if (!SINGLE) {
@@ -829,9 +833,9 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
                     (k0 + MAX_TPB < ng ? pv[c][1] : 0.0)) +
                    (k0 + 2 * MAX_TPB < ng ? pv[c][2] : 0.0);
         block_sum<3, double, 1, true>(tot);
-        // after the barrier of the sum, so that no load above is moved past the test: a
-        // launch after convergence has read (in bounds) but writes nothing
-        if (__builtin_amdgcn_readfirstlane(done)) return;
+        // block order of K: after the barrier of the sum, so that no load above is moved past
+        // the test (a launch after convergence has read, in bounds, but writes nothing)
+        if (W == 0 && __builtin_amdgcn_readfirstlane(done)) return;
       } else {
         finish_partials<3>(d.pp_in, ng, tot);
       }
@@ -917,7 +921,9 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
 template <class T, int W, bool ONE_PASS>
 __global__ void __launch_bounds__(MAX_TPB)
 k_cg1_iter1(const Cg1Args<T> a) {
-  cg1_iteration<T, true, W, ONE_PASS>(a, blockIdx.x, gridDim.x);
+  // the grid is a.n_wg workgroups; taking the count from the arguments keeps it in the one
+  // batch of argument loads
+  cg1_iteration<T, true, W, ONE_PASS>(a, blockIdx.x, a.n_wg);
 }
 
 // Kernel of a padded width (0: block order of K); a width the pattern builder does not make is
@@ -1336,7 +1342,8 @@ struct FusedBuffers {
 // when the solve started: fused_start).
 template <class T, bool P1>
 static void launch_iter1_w(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s) {
-  const Cg1Args<T> a = cg1_args(hd, k);
+  Cg1Args<T> a = cg1_args(hd, k);
+  a.n_wg = nwg;   // the grid launched below
   switch (hd.ell_w) {
     case 6:
       hipLaunchKernelGGL((k_cg1_iter1<T, 6, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
