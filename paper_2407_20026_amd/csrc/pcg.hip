@@ -1236,7 +1236,13 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
   int n_prof = 0;
   int64_t launched = 0, launched_prev = 0;
   int chunk = 8;
+  // (iteration, log(r.r / b.b)) of the last polls, for the chunk size near convergence
+  constexpr int HIST = 4;
+  int hist_it[HIST] = {};
+  double hist_lr[HIST] = {};
+  int n_hist = 0;
   for (int c = 0;; ++c) {
+    int next = chunk < 64 ? 2 * chunk : 64;   // size of the chunk after this one
     for (int i = 0; i < chunk; ++i) {
       const int64_t gk = launched + i;
       const int64_t ph = profile_every > 0 ? gk % profile_every : -1;
@@ -1259,9 +1265,30 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
         *w.h_st = prev;
         break;
       }
+      // Near convergence, size the next chunk from the residual's rate of decrease over the
+      // last polls, so that few launches are enqueued past the converging iteration (they
+      // cost a round trip each).  Only the chunking changes: the iteration that stops is
+      // decided on the device.
+      if (prev.rr > 0.0 && prev.ff > 0.0 && prev.rtol2 > 0.0) {
+        const double lr = std::log(prev.rr / prev.ff);
+        const int old = n_hist < HIST ? 0 : n_hist % HIST;
+        if (n_hist > 0 && prev.it > hist_it[old]) {
+          const double rate = (lr - hist_lr[old]) / (double)(prev.it - hist_it[old]);
+          if (rate < 0.0) {
+            // iterations still needed beyond those already enqueued, plus a margin; chunks
+            // stay multiples of 8 (a timing sample never straddles two chunks)
+            const double need = (std::log(prev.rtol2) - lr) / rate;
+            const double left = need - (double)(launched - prev.it) + 8.0;
+            if (left < (double)next) next = left <= 8.0 ? 8 : 8 * (int)((left + 7.0) / 8.0);
+          }
+        }
+        hist_it[n_hist % HIST] = prev.it;
+        hist_lr[n_hist % HIST] = lr;
+        ++n_hist;
+      }
     }
     launched_prev = launched;
-    chunk = chunk < 64 ? 2 * chunk : 64;
+    chunk = next;
   }
   *iters = w.h_st->it;
   *status = w.h_st->done ? w.h_st->status : SSO_ENOTCONV;
