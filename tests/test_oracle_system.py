@@ -271,3 +271,16 @@ def test_paper_arch_centre_sensitivity_soft():
     g = r["grad_xyz"][n // 2 - 1, 2]
     assert r["grad_xyz"][n // 2, 2] == pytest.approx(g, rel=1e-8)
     assert g == pytest.approx(gv["dSE_dz_centre_adjoint"], rel=0.02)
+
+
+@pytest.mark.parametrize("which", ["grid11", "shell8"])
+def test_displacement_parity_bar_is_attainable(which):
+    """kappa_eff = ||K||_2 ||u||_2 / ||f||_2 of the masked system: the 1e-10 relative bar on u is
+    within reach of a backward-stable FP64 solve only where kappa_eff * eps64 is below it."""
+    import scipy.sparse.linalg as sla
+    m = meshgen.grid_shell_11() if which == "grid11" else meshgen.shell(8, L=8.0, seed=3)
+    r = oracle.analyze(m, "compliance")
+    lmax = sla.eigsh(r["Km"].tocsr(), k=1, which="LA", return_eigenvectors=False)[0]
+    k_eff = lmax * np.linalg.norm(r["u"]) / np.linalg.norm(r["fm"])
+    print(f"{which}: kappa_eff = {k_eff:.3e}, kappa_eff * eps = {k_eff * np.finfo(float).eps:.2e}")
+    assert k_eff * np.finfo(float).eps < 1e-10
