@@ -96,31 +96,55 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(mesh, objective, budget_s):
-    """The oracle as it stands, one forward + adjoint at a time, for about budget_s seconds."""
+def _oracle_rate(mesh, objective, budget_s, threads):
     import numpy as np
     import oracle
     from threadpoolctl import threadpool_limits
-    cores = 1   # BLAS limited to one thread: the oracle is vectorised NumPy, not threaded code
     a = None
     if objective == "linear":
         a = np.zeros(mesh.n_dof)
         a[6 * (mesh.n_nodes // 2) + 2] = 1.0
     n, t0 = 0, time.perf_counter()
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         while True:
             oracle.analyze(mesh, objective, a=a)
             n += 1
-            log(f"cpu baseline: oracle analysis {n} done")
+            log(f"cpu baseline ({threads} BLAS threads): oracle analysis {n} done")
             el = time.perf_counter() - t0
             if el >= budget_s or el * (n + 1) / n > 1.5 * budget_s:
                 break
+    return n, el
+
+
+def cpu_baseline(mesh, objective, budget_s):
+    """The oracle as it stands, one forward + adjoint at a time, for about budget_s seconds with
+    one BLAS thread (the reported value), then for about budget_s / 2 seconds with every host
+    core given to BLAS (the banded Cholesky is the threaded part), and one SciPy sparse direct
+    solve of the same system (SuperLU) for context."""
+    import numpy as np
+    import scipy.sparse.linalg as sla
+    from oracle import assembly, solve
+    n, el = _oracle_rate(mesh, objective, budget_s, 1)
     rate = n / el
-    return {"value": rate, "unit": "solves/s", "dof_per_s": rate * mesh.n_dof, "cores": cores,
+    # the host cores this process may use (the thread limit of the environment when it sets one)
+    all_cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
+    n2, el2 = _oracle_rate(mesh, objective, budget_s / 2, all_cores)
+    K = assembly.assemble(mesh)
+    f = assembly.load_vector(mesh)
+    F = solve.free_dofs(mesh)
+    Kff = K.tocsc()[F][:, F]
+    t0 = time.perf_counter()
+    sla.spsolve(Kff, np.asarray(f)[F])
+    t_sp = time.perf_counter() - t0
+    log(f"cpu baseline: SciPy spsolve {t_sp:.2f} s")
+    return {"value": rate, "unit": "solves/s", "dof_per_s": rate * mesh.n_dof, "cores": 1,
             "kind": "oracle",
             "sample": f"{n} forward+adjoint analyses (pattern, assembly, banded Cholesky, "
                       f"complex-step adjoint) of the benchmark workload in {el:.1f} s, "
-                      f"BLAS threads {cores}, host cpus {os.cpu_count()}"}
+                      f"BLAS threads 1, host cpus {all_cores}",
+            "all_cores": {"value": n2 / el2, "unit": "solves/s", "cores": all_cores,
+                          "sample": f"{n2} analyses in {el2:.1f} s"},
+            "scipy_spsolve_s": t_sp}
 
 
 def log(msg):
@@ -315,6 +339,27 @@ def copy_calibration(mib):
     log(f"copy calibration: 3 x {mib} MiB")
 
 
+def measured_copy_bandwidth(mib=1024, reps=10):
+    """HBM bandwidth a plain device copy reaches on this GPU (bytes read + written per second,
+    GB/s), the measured ceiling beside the datasheet peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"measured copy bandwidth: {gbs:.0f} GB/s")
+    return gbs
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -438,6 +483,9 @@ def main():
                      "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},
     }
     prob.close()
+    copy_gbs = measured_copy_bandwidth()
+    out["roofline"]["measured_copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_measured"] = achieved / copy_gbs
     if args.objective != "linear" and args.general_steps > 0:
         out["general_objective"] = general_objective_bench(mesh, opts, args.general_steps)
     if args.batch > 0 and args.workload in SEEDED and args.objective != "linear":
