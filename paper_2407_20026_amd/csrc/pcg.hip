@@ -1078,11 +1078,14 @@ k_fcg_direction(int n_nodes, const int32_t* __restrict__ brow_ptr,
     const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
     const bool ok = L.ok && I < n_nodes;
     double acc = 0.0;
-    if (ok) acc = row_product<double, true>(brow_ptr, bcol, K, z, p_prev, nb, I, L.a, L.b);
+    // on a (re)start p_prev is not read at all (it may hold anything)
+    if (ok)
+      acc = restart ? row_product<double, false>(brow_ptr, bcol, K, z, z, 0.0, I, L.a, L.b)
+                    : row_product<double, true>(brow_ptr, bcol, K, z, p_prev, nb, I, L.a, L.b);
     const double sum = sum3(acc, L.lane);
     if (ok && L.b == 0) {
       const int64_t d = 6 * (int64_t)I + L.a;
-      const double pv = z[d] + nb * p_prev[d];
+      const double pv = restart ? z[d] : z[d] + nb * p_prev[d];
       p[d] = pv;
       q[d] = sum;
       v[0] += pv * sum;
