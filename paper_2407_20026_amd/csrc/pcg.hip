@@ -220,12 +220,10 @@ __device__ inline T sum3(T acc, int lane) {
 // 72 VGPRs and 7 waves per SIMD; measured on the 300 x 300 shell 58.7 us per launch against
 // 67.8 (three per step, 88 VGPRs, 5 waves) and 77 (six per step).
 template <class T>
-__device__ inline void row_product2(const int32_t* __restrict__ brow_ptr,
-                                    const int32_t* __restrict__ bcol, const T* __restrict__ K,
-                                    const T* __restrict__ z, const T* __restrict__ p, int I,
-                                    int a, int b, T& az, T& ap) {
+__device__ inline void row_product2(int rb, int re, const int32_t* __restrict__ bcol,
+                                    const T* __restrict__ K, const T* __restrict__ z,
+                                    const T* __restrict__ p, int a, int b, T& az, T& ap) {
   using V = typename Vec2<T>::type;
-  const int rb = brow_ptr[I], re = brow_ptr[I + 1];
   const int off = 6 * a + b;
   T sz = 0, sp = 0;
   int s = rb;
@@ -298,55 +296,100 @@ k_pcg_init(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   }
 }
 
+// The state scalars of a standard iteration, read at entry in one group: a kernel's later
+// loads of the state would each be a round trip of their own after the done test.
+struct StdState {
+  double rz0, rz1, ff, rtol2;
+  int done, jn, jc, max_it;
+};
+
+// A value every lane holds the same of, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)b);
+  const long long hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The state is read through vector loads (other workgroups of the kernel write it, so scalar
+// cache loads are not allowed); its fields are the same for every lane, so they are kept in
+// scalar registers, where they cost no vector registers across the row products.
+__device__ __forceinline__ StdState std_state(const PcgState* __restrict__ st) {
+  StdState s;
+  s.rz0 = uniform(st->rzs[0]);
+  s.rz1 = uniform(st->rzs[1]);
+  s.ff = uniform(st->ff);
+  s.rtol2 = uniform(st->rtol2);
+  s.max_it = __builtin_amdgcn_readfirstlane(st->max_it);
+  s.done = __builtin_amdgcn_readfirstlane(st->done);
+  s.jn = __builtin_amdgcn_readfirstlane(st->jn);
+  s.jc = __builtin_amdgcn_readfirstlane(st->jc);
+  return s;
+}
+
 // Iteration j (j read from the state), first half: Ap_j = K z_j + beta_j K p_{j-1} and
 // p_j = z_j + beta_j p_{j-1} (own rows stored), partial p_j^T A p_j.  The first pass's products
 // are issued before the previous kernel's partials are finished (rz_j, rr_j -> convergence
-// test, beta_j), so the reduction overlaps the loads.
+// test, beta_j), so the reduction overlaps the loads.  The descriptor is copied whole and the
+// first pass's row pointers are loaded with the state (neither needs the other), so a
+// workgroup's first products start two round trips after its descriptor.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  const Wg<T> W = wg_of(D, wg_prob);
-  const PcgDesc<T>& d = *W.d;
+  const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
+  const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
   PcgState* st = d.st;
-  if (st->done) return;
-  const int j = st->jn;
   const int n_nodes = d.n_nodes;
-  const T* __restrict__ K = d.K;
-  const T* __restrict__ z = d.z;
-  const T* __restrict__ pold = d.p[j & 1];
-  T* __restrict__ pnew = d.p[(j + 1) & 1];
-  T* __restrict__ Ap = d.Ap;
   const SpLane L = sp_lane();
   const int wave = threadIdx.x >> 6;
+  const int I0 = lb * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
+  const int I0c = (L.ok && I0 < n_nodes) ? I0 : 0;
+  const int rb0 = d.brow_ptr[I0c], re0 = d.brow_ptr[I0c + 1];
+  const StdState S = std_state(st);
+  // the first group in registers before the done test (an empty asm that takes them), so that
+  // the compiler cannot sink these loads below it, one round trip after another
+  asm volatile("" ::"v"(rb0), "v"(re0), "s"(S.rz0), "s"(S.rz1), "s"(S.ff), "s"(S.rtol2),
+               "s"(S.jn), "s"(S.max_it));
+  if (S.done) return;
+  const int j = S.jn;
+  const T* __restrict__ K = d.K;
+  const T* __restrict__ z = d.z;
+  const T* __restrict__ pold = (j & 1) ? d.p[1] : d.p[0];
+  T* __restrict__ pnew = (j & 1) ? d.p[0] : d.p[1];
+  T* __restrict__ Ap = d.Ap;
   T beta = 0, my = 0;
-  for (int gi = W.lb; gi * ROWS_PER_WG < n_nodes; gi += W.ng) {
+  for (int gi = lb; gi * ROWS_PER_WG < n_nodes; gi += ng) {
     const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
     const bool ok = L.ok && I < n_nodes;
     T az = 0, ap = 0, zI = 0, pI = 0;
-    if (ok) {
-      row_product2<T>(d.brow_ptr, d.bcol, K, z, pold, I, L.a, L.b, az, ap);
-      if (L.b == 0) {
-        zI = z[6 * (int64_t)I + L.a];
-        pI = pold[6 * (int64_t)I + L.a];
-      }
+    int rb = rb0, re = re0;
+    if (gi != lb && ok) {
+      rb = d.brow_ptr[I];
+      re = d.brow_ptr[I + 1];
     }
-    if (gi == W.lb) {
+    if (!ok) re = rb;
+    row_product2<T>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
+    if (ok && L.b == 0) {
+      zI = z[6 * (int64_t)I + L.a];
+      pI = pold[6 * (int64_t)I + L.a];
+    }
+    if (gi == lb) {
       double tot[2];
-      finish_partials<2>(d.pb, W.ng, tot);
+      finish_partials<2>(d.pb, ng, tot);
       const double rz = tot[0], rr = tot[1];
-      const double ff = (j == 0) ? rr : st->ff;
-      const double beta_d = (j == 0) ? 0.0 : rz / st->rzs[(j - 1) & 1];
+      const double ff = (j == 0) ? rr : S.ff;
+      const double beta_d = (j == 0) ? 0.0 : rz / ((j & 1) ? S.rz0 : S.rz1);
       int stop = 0, status = SSO_OK;
       if (!std::isfinite(rr) || !std::isfinite(rz)) {
         stop = 1;
         status = SSO_EBREAKDOWN;
-      } else if (rr <= st->rtol2 * ff) {
+      } else if (rr <= S.rtol2 * ff) {
         stop = 1;
-      } else if (j >= st->max_it) {
+      } else if (j >= S.max_it) {
         stop = 1;
         status = SSO_ENOTCONV;
       }
-      if (W.lb == 0 && threadIdx.x == 0) {
+      if (lb == 0 && threadIdx.x == 0) {
         st->rzs[j & 1] = rz;
         st->rr = rr;
         st->it = j;
@@ -372,46 +415,58 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   }
   T v[1] = {my};
   block_sum<1, T>(v);
-  write_partials<1, T>(v, d.pa, W.lb, W.ng);
+  write_partials<1, T>(v, d.pa, lb, ng);
 }
 
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
 // partials of (rz_{j+1}, rr_{j+1}); the state's next iteration index becomes j + 1.  The first
-// pass's operands are loaded before the reduction.
+// pass's operands are loaded before the reduction, those that need no state (x, Ap, r) with the
+// state itself.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   __shared__ T rs[MAX_TPB];
-  const Wg<T> W = wg_of(D, wg_prob);
-  const PcgDesc<T>& d = *W.d;
+  const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
+  // every field the kernel uses in one batch of scalar loads
+  asm volatile("" ::"s"(d.x), "s"(d.r), "s"(d.z), "s"(d.p[0]), "s"(d.p[1]), "s"(d.Ap),
+               "s"(d.Dinv), "s"(d.pa), "s"(d.pb), "s"(d.st), "s"(d.n_nodes), "s"(d.n_wg),
+               "s"(d.wg_base));
+  const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
   PcgState* st = d.st;
-  if (st->done) return;
-  const int j = st->jc;
   const int n_nodes = d.n_nodes;
   T* __restrict__ x = d.x;
   T* __restrict__ r = d.r;
   T* __restrict__ z = d.z;
-  const T* __restrict__ p = d.p[(j + 1) & 1];
   const T* __restrict__ Ap = d.Ap;
+  const RowMap m0 = row_map_at(lb, n_nodes);
+  const int64_t q0 = 6 * (int64_t)(m0.valid ? m0.I : 0) + m0.a;
+  const T x0 = x[q0], a0 = Ap[q0], r0 = r[q0];
+  const StdState S = std_state(st);
+  asm volatile("" ::"v"(x0), "v"(a0), "v"(r0), "s"(S.rz0), "s"(S.rz1), "s"(S.jc));
+  if (S.done) return;
+  const int j = S.jc;
+  const T* __restrict__ p = (j & 1) ? d.p[0] : d.p[1];
   T alpha = 0;
   T v[2] = {0, 0};
-  for (int gi = W.lb; gi * VEC_NODES < n_nodes; gi += W.ng) {
+  for (int gi = lb; gi * VEC_NODES < n_nodes; gi += ng) {
     RowMap m = row_map_at(gi, n_nodes);
     const int64_t q = 6 * (int64_t)m.I + m.a;
-    T xv = 0, pv = 0, av = 0, rv = 0;
+    T xv = x0, pv = 0, av = a0, rv = r0;
     if (m.valid) {
-      xv = x[q];
+      if (gi != lb) {
+        xv = x[q];
+        av = Ap[q];
+        rv = r[q];
+      }
       pv = p[q];
-      av = Ap[q];
-      rv = r[q];
     }
-    if (gi == W.lb) {
+    if (gi == lb) {
       double tot[1];
-      finish_partials<1>(d.pa, W.ng, tot);
+      finish_partials<1>(d.pa, ng, tot);
       const double pAp = tot[0];
-      const double alpha_d = st->rzs[j & 1] / pAp;
+      const double alpha_d = ((j & 1) ? S.rz1 : S.rz0) / pAp;
       if (!(pAp > 0.0) || !std::isfinite(alpha_d)) {
-        if (W.lb == 0 && threadIdx.x == 0) {
+        if (lb == 0 && threadIdx.x == 0) {
           st->status = SSO_EBREAKDOWN;
           st->done = 1;
         }
@@ -436,8 +491,8 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
     __syncthreads();
   }
   block_sum<2, T>(v);
-  write_partials<2, T>(v, d.pb, W.lb, W.ng);
-  if (W.lb == 0 && threadIdx.x == 0) st->jn = j + 1;
+  write_partials<2, T>(v, d.pb, lb, ng);
+  if (lb == 0 && threadIdx.x == 0) st->jn = j + 1;
 }
 
 // ---- single-reduction PCG (Chronopoulos & Gear): one kernel and one reduction per iteration --
