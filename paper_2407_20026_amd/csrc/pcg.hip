@@ -62,14 +62,53 @@ __device__ inline WgOf<Desc> wg_of(const Desc* __restrict__ D,
 template <class T>
 using Wg = WgOf<PcgDesc<T>>;
 
+// Cross-lane moves through DPP, register to register in a few cycles, where a shuffle would be
+// a round trip through the LDS crossbar.  CTRL is the DPP control word: quad_perm 0x00-0xff,
+// row_ror:n 0x120 + n.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)b, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane: each quad by two quad_perm
+// exchanges, each 16-lane row by rotations of 4 and 8 (lane 16r then holds its row's sum), and
+// the four row sums in a fixed order.
+template <class A>
+__device__ __forceinline__ A wave_sum(A v) {
+  v += dpp_move<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x124>(v);   // row_ror:4
+  v += dpp_move<0x128>(v);   // row_ror:8
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 // Fixed-order workgroup sum of NV values; the result is returned to every thread.  TAG gives
 // a call site its own LDS array; LAST (the array is not written again before the kernel ends
-// or before a barrier) drops the trailing barrier that protects the array's reuse.
+// or before a barrier) drops the trailing barrier that protects the array's reuse.  Called by
+// every thread of the workgroup (full waves).
 template <int NV, class A, int TAG = 0, bool LAST = false>
 __device__ inline void block_sum(A v[NV]) {
   __shared__ A lds[NV][MAX_WAVES];
-  for (int off = 32; off > 0; off >>= 1)
-    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = (blockDim.x + 63) >> 6;
   if (lane == 0)
