@@ -246,11 +246,13 @@ __device__ inline T row_product(const int32_t* __restrict__ brow_ptr,
   return acc;
 }
 
-// Row total in the first lane (l % 3 == 0) of each 3-lane set, fixed order.
+// Row total in the first lane (l % 3 == 0) of each 3-lane set, fixed order; the next two
+// lanes' values come by one and two wave_shl:1 moves (lane i reads lane i + 1).  Every lane of
+// the wave must be active.
 template <class T>
-__device__ inline T sum3(T acc, int lane) {
-  const T t1 = __shfl(acc, lane + 1, 64);
-  const T t2 = __shfl(acc, lane + 2, 64);
+__device__ inline T sum3(T acc) {
+  const T t1 = dpp_move<0x130>(acc);
+  const T t2 = dpp_move<0x130>(t1);
   return acc + t1 + t2;
 }
 
@@ -442,7 +444,7 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
       if (stop) return;
       beta = (T)beta_d;
     }
-    const T sz = sum3(az, L.lane), sp = sum3(ap, L.lane);
+    const T sz = sum3(az), sp = sum3(ap);
     if (ok && L.b == 0) {
       const int64_t q = 6 * (int64_t)I + L.a;
       const T pn = zI + beta * pI;
@@ -748,7 +750,7 @@ k_cg1_init2(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_p
     const int64_t q = 6 * (int64_t)I + L.a;
     T acc = 0, rq = 0;
     if (ok) acc = row_product_b<T, W>(d, I, r0, L.a, L.b);
-    const T wv = sum3(acc, L.lane);
+    const T wv = sum3(acc);
     if (own) {
       rq = r0[q];
       d.w[0][q] = wv;
@@ -971,7 +973,7 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
       beta = (T)beta_d;
       ab = alpha * beta;
     }
-    const T wv = sum3(br - alpha * bw - ab * bs, L.lane);
+    const T wv = sum3(br - alpha * bw - ab * bs);
     // every lane of a row holds its component a's operands; the node's 6 values of r_i and
     // r_{i+1} for M r come from the row's own lanes by wave shuffles (no LDS, no barrier)
     T r6[6];
@@ -1075,7 +1077,7 @@ k_residual(int n_nodes, const int32_t* __restrict__ brow_ptr, const int32_t* __r
     const bool ok = L.ok && I < n_nodes;
     double acc = 0.0;
     if (ok) acc = row_product<double, false>(brow_ptr, bcol, K, x, x, 0.0, I, L.a, L.b);
-    const double sum = sum3(acc, L.lane);
+    const double sum = sum3(acc);
     if (ok && L.b == 0) {
       const int64_t d = 6 * (int64_t)I + L.a;
       const double rv = b[d] - sum;
@@ -1176,7 +1178,7 @@ k_fcg_direction(int n_nodes, const int32_t* __restrict__ brow_ptr,
     if (ok)
       acc = restart ? row_product<double, false>(brow_ptr, bcol, K, z, z, 0.0, I, L.a, L.b)
                     : row_product<double, true>(brow_ptr, bcol, K, z, p_prev, nb, I, L.a, L.b);
-    const double sum = sum3(acc, L.lane);
+    const double sum = sum3(acc);
     if (ok && L.b == 0) {
       const int64_t d = 6 * (int64_t)I + L.a;
       const double pv = restart ? z[d] : z[d] + nb * p_prev[d];
