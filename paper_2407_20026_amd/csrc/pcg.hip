@@ -293,6 +293,44 @@ __device__ inline void row_product2(int rb, int re, const int32_t* __restrict__ 
   ap = sp;
 }
 
+// FP32 standard recurrences keep z and p interleaved: buffer k holds (z, p) pairs, (z_j,
+// p_{j-1}) in buffer j & 1, so that one 16-byte gather per lane brings both vectors' entries of
+// a block (two entries each), where separate arrays need two 8-byte gathers.
+template <class T>
+constexpr bool zp_pairs() {
+  return sizeof(T) == 4;
+}
+
+// row_product2 on interleaved (z, p) pairs: the same products in the same order.
+__device__ inline void row_product2_zp(int rb, int re, const int32_t* __restrict__ bcol,
+                                       const float* __restrict__ K,
+                                       const float* __restrict__ zp, int a, int b, float& az,
+                                       float& ap) {
+  const int off = 6 * a + b;
+  float sz = 0, sp = 0;
+  int s = rb;
+  for (; s + 2 <= re; s += 2) {
+    const int64_t J0 = bcol[s], J1 = bcol[s + 1];
+    const float2 k0 = *reinterpret_cast<const float2*>(K + 36 * (int64_t)s + off);
+    const float2 k1 = *reinterpret_cast<const float2*>(K + 36 * (int64_t)(s + 1) + off);
+    const float4 v0 = *reinterpret_cast<const float4*>(zp + 2 * (6 * J0 + b));
+    const float4 v1 = *reinterpret_cast<const float4*>(zp + 2 * (6 * J1 + b));
+    sz += k0.x * v0.x + k0.y * v0.z;
+    sp += k0.x * v0.y + k0.y * v0.w;
+    sz += k1.x * v1.x + k1.y * v1.z;
+    sp += k1.x * v1.y + k1.y * v1.w;
+  }
+  for (; s < re; ++s) {
+    const int64_t J = bcol[s];
+    const float2 kv = *reinterpret_cast<const float2*>(K + 36 * (int64_t)s + off);
+    const float4 v = *reinterpret_cast<const float4*>(zp + 2 * (6 * J + b));
+    sz += kv.x * v.x + kv.y * v.z;
+    sp += kv.x * v.y + kv.y * v.w;
+  }
+  az = sz;
+  ap = sp;
+}
+
 // x = 0, r = b, z = Dinv b, p_{-1} = 0; partials of r^T z, r^T r; reset the state record.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
@@ -311,13 +349,18 @@ k_pcg_init(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
       rv = d.b[q];
       d.x[q] = 0;
       d.r[q] = rv;
-      d.p[0][q] = 0;
+      if constexpr (!zp_pairs<T>()) d.p[0][q] = 0;
     }
     rs[threadIdx.x] = rv;
     __syncthreads();
     if (m.valid) {
       const T zz = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
-      d.z[q] = zz;
+      if constexpr (zp_pairs<T>()) {
+        d.p[0][2 * q] = zz;
+        d.p[0][2 * q + 1] = 0;
+      } else {
+        d.z[q] = zz;
+      }
       v[0] += rv * zz;
       v[1] += rv * rv;
     }
@@ -409,10 +452,18 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
       re = d.brow_ptr[I + 1];
     }
     if (!ok) re = rb;
-    row_product2<T>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
-    if (ok && L.b == 0) {
-      zI = z[6 * (int64_t)I + L.a];
-      pI = pold[6 * (int64_t)I + L.a];
+    if constexpr (zp_pairs<T>()) {
+      row_product2_zp(rb, re, d.bcol, K, pold, L.a, L.b, az, ap);
+      if (ok && L.b == 0) {
+        zI = pold[2 * (6 * (int64_t)I + L.a)];
+        pI = pold[2 * (6 * (int64_t)I + L.a) + 1];
+      }
+    } else {
+      row_product2<T>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
+      if (ok && L.b == 0) {
+        zI = z[6 * (int64_t)I + L.a];
+        pI = pold[6 * (int64_t)I + L.a];
+      }
     }
     if (gi == lb) {
       double tot[2];
@@ -449,7 +500,10 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
       const int64_t q = 6 * (int64_t)I + L.a;
       const T pn = zI + beta * pI;
       const T Apq = sz + beta * sp;
-      pnew[q] = pn;
+      if constexpr (zp_pairs<T>())
+        pnew[2 * q + 1] = pn;
+      else
+        pnew[q] = pn;
       Ap[q] = Apq;
       my += pn * Apq;
     }
@@ -486,7 +540,7 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   asm volatile("" ::"v"(x0), "v"(a0), "v"(r0), "s"(S.rz0), "s"(S.rz1), "s"(S.jc));
   if (S.done) return;
   const int j = S.jc;
-  const T* __restrict__ p = (j & 1) ? d.p[0] : d.p[1];
+  T* __restrict__ p = (j & 1) ? d.p[0] : d.p[1];   // p_j (FP32: beside z_{j+1}, written here)
   T alpha = 0;
   T v[2] = {0, 0};
   for (int gi = lb; gi * VEC_NODES < n_nodes; gi += ng) {
@@ -499,7 +553,7 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
         av = Ap[q];
         rv = r[q];
       }
-      pv = p[q];
+      pv = zp_pairs<T>() ? p[2 * q + 1] : p[q];
     }
     if (gi == lb) {
       double tot[1];
@@ -525,7 +579,10 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
     __syncthreads();
     if (m.valid) {
       const T zz = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
-      z[q] = zz;
+      if constexpr (zp_pairs<T>())
+        p[2 * q] = zz;   // z_{j+1} beside p_j
+      else
+        z[q] = zz;
       v[0] += rn * zz;
       v[1] += rn * rn;
     }
@@ -1270,8 +1327,9 @@ hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s) {
   hipError_t e;
   if ((e = dev_alloc(&w.r32, w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.z32, w.n_dof , s)) != hipSuccess) return e;
-  if ((e = dev_alloc(&w.p32[0], w.n_dof , s)) != hipSuccess) return e;
-  if ((e = dev_alloc(&w.p32[1], w.n_dof , s)) != hipSuccess) return e;
+  // (z, p) pairs of the standard recurrences: two floats per DOF
+  if ((e = dev_alloc(&w.p32[0], 2 * w.n_dof, s)) != hipSuccess) return e;
+  if ((e = dev_alloc(&w.p32[1], 2 * w.n_dof, s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.Ap32, w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.x32, w.n_dof , s)) != hipSuccess) return e;
   if ((e = dev_alloc(&w.b32, w.n_dof , s)) != hipSuccess) return e;
