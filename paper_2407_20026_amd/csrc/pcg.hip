@@ -1038,12 +1038,14 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
     const T pv = M.apply(r6) + beta * pq;
     const T sv = wq + beta * sq;
     const T rv = rq - alpha * sv;
+    // streaming stores: the next launch reads these from memory anyway (other XCDs), and
+    // lines left dirty in this XCD's L2 would be written back at the kernel's end
     if (own) {
-      p[q] = pv;
-      sn[q] = sv;
-      x[q] = xq + alpha * pv;
-      rn[q] = rv;
-      wn[q] = wv;
+      __builtin_nontemporal_store(pv, &p[q]);
+      __builtin_nontemporal_store(sv, &sn[q]);
+      __builtin_nontemporal_store(xq + alpha * pv, &x[q]);
+      __builtin_nontemporal_store(rv, &rn[q]);
+      __builtin_nontemporal_store(wv, &wn[q]);
     }
     node_values(rv, L, r6);
     if (own) {
