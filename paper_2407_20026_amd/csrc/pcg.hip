@@ -1089,7 +1089,6 @@ k_cg1_iter1(const Cg1Args<T> a) {
     case 6: CALL(6); break;       \
     case 9: CALL(9); break;       \
     case 12: CALL(12); break;     \
-    case 16: CALL(16); break;     \
     default: return hipErrorInvalidValue; \
   }
 
@@ -1540,9 +1539,6 @@ static void launch_iter1_w(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s
     case 12:
       hipLaunchKernelGGL((k_cg1_iter1<T, 12, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
       break;
-    case 16:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 16, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
-      break;
     default:
       hipLaunchKernelGGL((k_cg1_iter1<T, 0, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
   }
@@ -1715,7 +1711,6 @@ static void launch_fused(const std::map<int, LaunchTable<FusedDesc<T>>>& tables,
       case 6: launch_fused_w<T, 6>(kv.second, s); break;
       case 9: launch_fused_w<T, 9>(kv.second, s); break;
       case 12: launch_fused_w<T, 12>(kv.second, s); break;
-      case 16: launch_fused_w<T, 16>(kv.second, s); break;
       default: launch_fused_w<T, 0>(kv.second, s);
     }
   }
@@ -1796,8 +1791,10 @@ void batch_free(BatchWork& bw, hipStream_t s) {
 
 // Up to this many nodes the single launch per iteration of the single-reduction recurrences wins
 // (the 60 x 60 shell: 19.1 vs 21.0 ms per solve); on large problems the standard pair streams
-// closer to the bandwidth peak (the 300 x 300 shell: 80 vs 125 us per iteration).
-static constexpr int64_t FUSED_MAX_NODES = 20000;
+// closer to the bandwidth peak (the 300 x 300 shell: 80 vs 125 us per iteration).  The limit is
+// the one-pass grid (PCG_MAX_WG workgroups of 18 block rows): the multi-pass instance of the
+// 12-slot padded rows keeps more values live than the registers hold.
+static constexpr int64_t FUSED_MAX_NODES = (int64_t)PCG_MAX_WG * ROWS_PER_WG;
 
 int pcg_pick_solver(int solver, int64_t n_nodes) {
   if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED) return solver;

@@ -91,15 +91,17 @@ struct Pattern {
   int32_t* bsrow = nullptr;     // [n_blocks] block row of each slot
   int32_t* estart = nullptr;    // [n_nodes + 1] first sorted position of each block row
   // Padded layout of the block rows (every row ell_w slots; 0 = not built: a row has more
-  // than 16 blocks): bcol_ell[I * ell_w + u] = column of block u of row I for u below the
+  // than 12 blocks): bcol_ell[I * ell_w + u] = column of block u of row I for u below the
   // row's block count, I itself (with a zero block) beyond.
   int ell_w = 0;
   int32_t* bcol_ell = nullptr;  // [n_nodes * ell_w]
 };
 
-// Slots per row of the padded block-row layout for a largest row of `max_blocks` blocks.
+// Slots per row of the padded block-row layout for a largest row of `max_blocks` blocks; wider
+// rows keep the row pointers (a padded FP64 row of 16 slots does not fit the registers of the
+// fused iteration, whose spills would cost more memory traffic than the kernel's own).
 inline int ell_width(int max_blocks) {
-  return max_blocks <= 6 ? 6 : max_blocks <= 9 ? 9 : max_blocks <= 12 ? 12 : max_blocks <= 16 ? 16 : 0;
+  return max_blocks <= 6 ? 6 : max_blocks <= 9 ? 9 : max_blocks <= 12 ? 12 : 0;
 }
 
 struct Mesh {

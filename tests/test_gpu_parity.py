@@ -276,7 +276,7 @@ def test_bitwise_determinism(refs, name):
 
 
 @pytest.mark.parametrize("solver", ["standard", "fused"])
-@pytest.mark.parametrize("name", ["grid11", "mixed", "shell60"])
+@pytest.mark.parametrize("name", ["grid11", "hub", "mixed", "shell60"])
 def test_both_recurrences(refs, name, solver):
     """Standard and single-reduction (fused) PCG recurrences, each chosen explicitly: u and the
     gradients at the parity bars, the recurrence reported back, and two runs bitwise equal."""
