@@ -58,7 +58,38 @@ def hub_mesh(n_spokes=20):
                         name="hub")
 
 
+def cantilever_beam():
+    """One member, one workgroup with a single active row pair: node 0 clamped, a skew tip load."""
+    xyz = np.array([[0.0, 0.0, 0.0], [3.0, 0.4, 0.7]])
+    fixed = np.zeros((2, 6), np.uint8)
+    fixed[0] = 1
+    f = np.zeros((2, 6))
+    f[1, :3] = [2e3, -1e3, -5e3]
+    f[1, 5] = 4e2
+    return meshgen.Mesh(xyz=xyz, fixed=fixed, f_nodal=f,
+                        beam_nodes=np.array([[0, 1]], np.int32),
+                        beam_prop=np.array([[2.1e11, 8.1e10, 1e-3, 1e-6, 2e-6, 1.5e-6]]),
+                        name="cantilever")
+
+
+def one_quad():
+    """One warped shell element clamped along one edge, loaded at the free corners."""
+    xyz = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.1], [2.1, 1.8, -0.05], [0.0, 2.0, 0.0]])
+    fixed = np.zeros((4, 6), np.uint8)
+    fixed[[0, 3]] = 1
+    f = np.zeros((4, 6))
+    f[1, 2] = -3e3
+    f[2, 2] = -2e3
+    f[2, 0] = 1e3
+    return meshgen.Mesh(xyz=xyz, fixed=fixed, f_nodal=f,
+                        quad_nodes=np.array([[0, 1, 2, 3]], np.int32),
+                        quad_prop=np.array([[0.12, 30e9, 0.2, 1.0, 1.0]]),
+                        quad_scale=np.array([0.7]), name="one_quad")
+
+
 CASES = {
+    "cantilever": cantilever_beam,
+    "one_quad": one_quad,
     "grid11": meshgen.grid_shell_11,
     "hub": hub_mesh,
     "grid_ragged": lambda: meshgen.gridshell(13, seed=5),
@@ -359,6 +390,23 @@ def test_invalid_inputs_are_rejected():
         with pytest.raises(sso.SSOError) as e:
             p.solve()
         assert e.value.status == sso.SSO_EINVAL
+
+
+def test_every_dof_fixed_gives_zero_solution():
+    """Degenerate supports (no free DOF): the masked system is the identity with a zero
+    right-hand side, so u, the compliance and its gradients are exactly zero."""
+    sso = _sso()
+    g = meshgen.gridshell(4)
+    g.fixed = np.ones_like(g.fixed)
+    print("[gpu] every DOF fixed", flush=True)
+    with _problem(g) as p:
+        u, st = p.solve()
+        assert p.last_status == sso.SSO_OK
+        assert st["iters"] == 0
+        assert not torch.any(u != 0)
+        assert p.objective("compliance") == 0.0
+        grads = p.adjoint("compliance")
+        assert not torch.any(grads["dg_dxyz"] != 0)
 
 
 def test_unsupported_structure_reports_failure():
