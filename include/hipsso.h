@@ -66,8 +66,9 @@ enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
 /* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
  * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one
  * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
- * of K's size).  AUTO: sso_solve takes FUSED up to 20,000 nodes (latency-bound sizes) and
- * STANDARD above; sso_solve_begin (multi-problem launches) takes STANDARD. */
+ * of K's size).  AUTO: sso_solve takes FUSED up to 18,432 nodes (latency-bound sizes; one
+ * pass of 1,024 workgroups of 18 block rows) and STANDARD above; sso_solve_begin
+ * (multi-problem launches) takes STANDARD. */
 enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */
