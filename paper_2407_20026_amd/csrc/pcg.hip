@@ -1401,6 +1401,12 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
   int n_hist = 0;
   for (int c = 0;; ++c) {
     int next = chunk < 64 ? 2 * chunk : 64;   // size of the chunk after this one
+    // launch k performs iteration k and the one with index max_it stops on the limit: no launch
+    // past it is ever needed (an inner solve of a few iterations would otherwise enqueue the
+    // rest of the first chunks for nothing); polling ends when the state says done or once
+    // the launch at the limit has run
+    if (launched + chunk > (int64_t)max_it + 1)
+      chunk = launched > (int64_t)max_it ? 0 : (int)((int64_t)max_it + 1 - launched);
     for (int i = 0; i < chunk; ++i) {
       const int64_t gk = launched + i;
       const int64_t ph = profile_every > 0 ? gk % profile_every : -1;
@@ -1419,7 +1425,8 @@ static hipError_t run_polled(PcgWork& w, hipStream_t s, int max_it, int profile_
     if (c > 0) {
       if ((e = hipEventSynchronize(w.poll_ev[(c - 1) & 1])) != hipSuccess) return e;
       const PcgState& prev = w.h_ring[(c - 1) & 1];
-      if (prev.done || launched_prev > (int64_t)max_it + 64) {
+      // done, or every launch up to the limit has run (the state read after them is final)
+      if (prev.done || launched_prev > (int64_t)max_it) {
         *w.h_st = prev;
         break;
       }
@@ -2046,6 +2053,8 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
     int it = 0, st = SSO_OK;
     const int nwg = B32 ? w.n_wg_f : w.n_wg;
     const int left = mp.max_it - ms.iters;
+    // the inner solve's own limit (set on the device by mixed_next)
+    const int cap = (mp.inner_max_it > 0 && mp.inner_max_it < left) ? mp.inner_max_it : left;
     if (B32) {
       const FusedDesc<float> hd = ms.fdesc;
       int k = 0;
@@ -2055,7 +2064,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
         if (e1) (void)hipEventRecord(*e1, s);
         ++k;
       };
-      e = run_polled(w, s, left, profile_every, FUSED_SPAN, launch, &it, &st);
+      e = run_polled(w, s, cap, profile_every, FUSED_SPAN, launch, &it, &st);
     } else {
       const PcgDesc<float>* dd = reinterpret_cast<const PcgDesc<float>*>(w.desc32);
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
@@ -2064,7 +2073,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
         if (e1) (void)hipEventRecord(*e1, s);
         hipLaunchKernelGGL(k_update<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
       };
-      e = run_polled(w, s, left, profile_every, 1, launch, &it, &st);
+      e = run_polled(w, s, cap, profile_every, 1, launch, &it, &st);
     }
     if (e == hipSuccess) e = mixed_inner_done(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
   }
