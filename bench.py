@@ -151,7 +151,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serve_bench(n, slots, precision, solver):
+def serve_bench(n, slots, precision, solver, inner_max_it=0, refine_steps=20):
     """Mixed-size served stream: grid-shells (n x n nodes, n ~ U{8..60}) and shells (m x m quads,
     m ~ U{10..120}) with per-request seeds, rtol 1e-8 on the FP64 true residual, all requests in
     flight iterating in shared multi-problem launches; FP64 or mixed precision (FP32 inner
@@ -160,10 +160,13 @@ def serve_bench(n, slots, precision, solver):
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import BatchedServer, Request, poisson_arrivals
     meshes = [meshgen.served_request(i) for i in range(n)]
-    # multi-problem launches run mixed precision with the single-reduction recurrences only
+    # multi-problem launches take the standard recurrences under AUTO; mixed precision may cap
+    # each FP32 inner solve
     opts = sso.Options(rtol=1e-8, precision=sso.PREC_MIXED if precision == "mixed" else
                        sso.PREC_FP64,
-                       solver=solver if precision == "fp64" else sso.SOLVER_AUTO)
+                       solver=solver if precision == "fp64" else sso.SOLVER_AUTO,
+                       inner_max_it=inner_max_it if precision == "mixed" else 0,
+                       refine_steps=refine_steps)
     srv = BatchedServer(slots=slots, options=opts)
     n_cl = min(n, 64)
     cl = srv.run([Request(i, meshes[i], 0.0) for i in range(n_cl)])
@@ -178,6 +181,8 @@ def serve_bench(n, slots, precision, solver):
             "solves_per_s": st.solves_per_s, "dof_per_s": st.dof_per_s,
             "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_queue_ms": st.mean_queue_ms,
             "peak_inflight": st.peak_inflight,
+            "not_converged": st.not_converged + cl.not_converged,
+            "max_rel_residual": max(st.max_rel_residual, cl.max_rel_residual),
             "mean_dof": float(np.mean([m.n_dof for m in meshes])),
             "closed_loop_phase_s": {k: round(v, 4) for k, v in cl.host_s.items()},
             "phase_s": {k: round(v, 4) for k, v in st.host_s.items()}}
@@ -494,7 +499,8 @@ def main():
     if args.shellnet > 0:
         out["shellnet"] = shellnet_bench(args.shellnet, solver)
     if args.serve_requests > 0:
-        out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec, solver)
+        out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec, solver,
+                                            args.inner_max_it, args.refine_steps)
                           for prec in ("fp64", "mixed")}
     if args.arch:
         out["arch_replay"] = arch_bench([int(v) for v in args.arch.split(",")])

@@ -68,6 +68,8 @@ class Result:
     arrival: float
     admitted: float
     done: float
+    status: int = 0              # SSO_OK, or SSO_ENOTCONV (stopped above rtol)
+    rel_residual: float = 0.0    # true relative residual of the solve
 
     @property
     def latency(self) -> float:
@@ -87,6 +89,14 @@ class ServeStats:
     peak_bytes: int
     results: list = field(repr=False, default_factory=list)
     host_s: dict = field(default_factory=dict)   # BatchedServer: wall time per phase
+    not_converged: int = 0         # requests that stopped above rtol (status SSO_ENOTCONV)
+    max_rel_residual: float = 0.0  # largest true relative residual over the requests
+
+
+def _convergence(results) -> dict:
+    """How many requests stopped above rtol, and the largest true residual."""
+    return {"not_converged": sum(1 for r in results if r.status != 0),
+            "max_rel_residual": max((r.rel_residual for r in results), default=0.0)}
 
 
 def run_one(req: Request, options: Options, stream=None, device="cuda") -> Result:
@@ -102,7 +112,8 @@ def run_one(req: Request, options: Options, stream=None, device="cuda") -> Resul
         gx = gr["dg_dxyz"].cpu().numpy()
         gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
     t1 = time.perf_counter()
-    return Result(req.rid, req.mesh.n_dof, g, gx, gt, st["iters"], 0.0, t0, t1)
+    return Result(req.rid, req.mesh.n_dof, g, gx, gt, st["iters"], 0.0, t0, t1,
+                  p.last_status, st["rel_residual"])
 
 
 class Server:
@@ -197,7 +208,7 @@ class Server:
             p50_ms=1000 * float(np.percentile(lat, 50)), p99_ms=1000 * float(np.percentile(lat, 99)),
             mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
             peak_inflight=state["peak_inflight"], peak_bytes=state["peak_bytes"],
-            results=sorted(results, key=lambda r: r.rid))
+            results=sorted(results, key=lambda r: r.rid), **_convergence(results))
 
 
 def finish_one(p: Problem, req: Request):
@@ -209,7 +220,7 @@ def finish_one(p: Problem, req: Request):
     gr = p.adjoint(req.objective)
     gx = gr["dg_dxyz"].cpu().numpy()
     gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
-    return g, gx, gt, st["iters"]
+    return g, gx, gt, st["iters"], p.last_status, st["rel_residual"]
 
 
 class BatchedServer:
@@ -277,11 +288,11 @@ class BatchedServer:
                     if not flag:
                         still.append((p, req, adm, need))
                         continue
-                    g, gx, gt, iters = finish_one(p, req)
+                    g, gx, gt, iters, status, rres = finish_one(p, req)
                     p.close()
                     free += need
                     results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
-                                          req.arrival, adm, clock()))
+                                          req.arrival, adm, clock(), status, rres))
                 active = still
                 phase["finish"] += time.perf_counter() - t2
         finally:
@@ -297,7 +308,7 @@ class BatchedServer:
             mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
             peak_inflight=peak_inflight, peak_bytes=peak_bytes,
             results=sorted(results, key=lambda r: r.rid),
-            host_s=phase)
+            host_s=phase, **_convergence(results))
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = 3) -> np.ndarray:
