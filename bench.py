@@ -324,13 +324,16 @@ def shellnet_bench(n_variants, solver, m=80):
             times.append(time.perf_counter() - t0)
             log(f"shellnet: loss + backward {times[-1]:.2f} s")
         iters = [p.last_stats["iters"] for p in b.problems]
+        rres = [p.last_stats["rel_residual"] for p in b.problems]
+        not_conv = sum(1 for p in b.problems if p.last_status != 0)
         n_dof = b.problems[0].n_dof
     finally:
         b.close()
     return {"variants": n_variants, "mesh": f"{m}x{m} quads", "n_dof_per_variant": n_dof,
             "loss_and_backward_s": times[-1], "solves_per_s": n_variants / times[-1],
             "dof_per_s": n_variants * n_dof / times[-1], "loss": float(loss.item()),
-            "pcg_iters_median": int(np.median(iters)), "pcg_iters_max": int(max(iters))}
+            "pcg_iters_median": int(np.median(iters)), "pcg_iters_max": int(max(iters)),
+            "not_converged": not_conv, "max_rel_residual": float(max(rres))}
 
 
 def copy_calibration(mib):
