@@ -125,6 +125,22 @@ def assemble(mesh, pat=None, xyz=None, quad_t=None, quad_scale=None):
     return sp.csr_matrix((data, pat["col"], pat["row_ptr"]), shape=(n, n))
 
 
+def assemble_coo(mesh, xyz=None, quad_t=None, quad_scale=None):
+    """Unconstrained global K as the plain sum K = sum_e P_e^T K_e P_e, formed by SciPy's
+    duplicate summation of the (row, col, value) list (a library primitive, no dictionary).
+
+    Same K as :func:`assemble` up to the order in which a slot's (at most four) contributions
+    are added; used at sizes where the dictionary route of :func:`scatter_map` is too slow
+    (hundreds of thousands of DOF)."""
+    rows, cols = coo_rows_cols(mesh)
+    vals = coo_values(mesh, xyz, quad_t, quad_scale)
+    n = mesh.n_dof
+    K = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    return K
+
+
 def load_vector(mesh, xyz=None, quad_t=None):
     """f = prescribed nodal loads - sum_e (gamma t_e + q) A_e / 4 on uz of each quad corner."""
     xyz = mesh.xyz if xyz is None else xyz

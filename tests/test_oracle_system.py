@@ -284,3 +284,38 @@ def test_displacement_parity_bar_is_attainable(which):
     k_eff = lmax * np.linalg.norm(r["u"]) / np.linalg.norm(r["fm"])
     print(f"{which}: kappa_eff = {k_eff:.3e}, kappa_eff * eps = {k_eff * np.finfo(float).eps:.2e}")
     assert k_eff * np.finfo(float).eps < 1e-10
+
+
+def test_assemble_coo_equals_dictionary_assembly():
+    """The duplicate-summing COO route (used for the 300 x 300 reference) gives the K of the
+    dictionary-scatter route, up to the order of a slot's at most four additions."""
+    import scipy.sparse as sp
+    for mesh in (meshgen.gridshell(7, seed=3), meshgen.shell(6, L=6.0, seed=4)):
+        K1 = assembly.assemble(mesh).tocsr()
+        K2 = assembly.assemble_coo(mesh)
+        d = abs(K1 - K2)
+        assert d.max() <= 1e-14 * abs(K1).max()
+        assert K2.nnz == K1.nnz
+
+
+@pytest.mark.slow
+def test_shell300_reference_solution_properties():
+    """The stored reference of the 300 x 300 shell against what fixes it at any size: its
+    residual under the element-by-element operator, c = f^T u, translation invariance of the
+    coordinate gradient and homogeneity of c in the stiffness scale."""
+    import os
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "shell300_oracle.npz"))
+    mesh = meshgen.shell_300()
+    u = z["u"]
+    f = assembly.load_vector(mesh)
+    free = mesh.fixed.reshape(-1) == 0
+    r = (f - assembly.apply_K_elementwise(mesh, u))[free]
+    assert np.linalg.norm(r) / np.linalg.norm(f[free]) <= 2e-10
+    assert np.all(u[~free] == 0.0)
+    c = float(z["c"])
+    assert c == pytest.approx(float(f[free] @ u[free]), rel=1e-13)
+    gx = z["grad_xyz"]
+    for k in range(3):
+        assert abs(gx[:, k].sum()) <= 1e-9 * np.abs(gx[:, k]).sum()
+    assert z["grad_scale"].sum() == pytest.approx(-c, rel=1e-10)
+    assert float(z["kappa_eff"]) * np.finfo(float).eps > 1e-10
