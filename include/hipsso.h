@@ -112,7 +112,8 @@ typedef struct {
 
 typedef struct {
   int32_t iters;              /* PCG iterations of the last solve (all inner solves)         */
-  double rel_residual;        /* ||f - K u||_2 / ||f||_2 recomputed in FP64 after the solve  */
+  double rel_residual;        /* ||f - K u||_2 / ||f||_2 recomputed after the solve, the row
+                                 sums of K u in double-double (compensated) arithmetic       */
   double t_elem_us;           /* element stiffness + loads                                   */
   double t_asm_us;            /* assembly + masking + block-Jacobi                           */
   double t_solve_us;          /* PCG                                                         */

@@ -21,8 +21,9 @@
 // piece of every 6x6 block, so one load instruction covers a whole 288-byte block; the vector
 // kernels give 6 lanes to a node.  All kernels stride over the rows with a fixed number of
 // workgroups.  The recursively updated residual can drift below the true one (rounding); the
-// FP64 driver therefore recomputes the true residual after convergence and, if it is above the
-// target, solves for a correction (a few steps of FP64 iterative refinement).
+// FP64 driver therefore recomputes the true residual after convergence (row sums in
+// double-double, k_residual) and, if it is above the target, solves for a correction (a few
+// steps of iterative refinement).
 #include <cmath>
 
 #include "sso_internal.h"
@@ -1122,23 +1123,87 @@ k_right_precondition(int n_nodes, int64_t n_blocks, int w, const int32_t* __rest
   B[e] = (T)acc;
 }
 
-// r = b - K x; partials of ||r||^2 and ||b||^2.
+// ---- compensated residual ------------------------------------------------------------------
+// The true residual b - K x is a difference of nearly equal quantities: on a system whose
+// products K_ij x_j are kappa times larger than the load, an FP64 evaluation carries a rounding
+// error near kappa * eps relative to |b| (about 1.3e-10 on the 300 x 300 shell), so a residual
+// target below that cannot be confirmed.  Here every product is split exactly with an FMA
+// (two-product) and the sums are carried as unevaluated pairs hi + lo (two-sum), i.e. the row
+// sum is formed in double-double arithmetic and rounded to FP64 once, after the subtraction
+// from b.  Contraction is switched off so that the error terms are computed as written.
+
+// s + e = a + b exactly (Knuth's two-sum).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) += k * x, the product's rounding error recovered by an FMA.
+__device__ __forceinline__ void dd_add_product(double k, double x, double& hi, double& lo) {
+#pragma clang fp contract(off)
+  const double p = k * x;
+  const double pe = __builtin_fma(k, x, -p);
+  double s, e;
+  two_sum(hi, p, s, e);
+  hi = s;
+  lo += e + pe;
+}
+
+// (hi, lo) += (h2, l2).
+__device__ __forceinline__ void dd_add(double h2, double l2, double& hi, double& lo) {
+#pragma clang fp contract(off)
+  double s, e;
+  two_sum(hi, h2, s, e);
+  hi = s;
+  lo += e + l2;
+}
+
+// The row product of row_product<double, false> in double-double: this lane's entries (a,
+// b..b+1) of every block of block row I against x.
+__device__ inline void row_product_dd(const int32_t* __restrict__ brow_ptr,
+                                      const int32_t* __restrict__ bcol,
+                                      const double* __restrict__ K, const double* __restrict__ x,
+                                      int I, int a, int b, double& hi, double& lo) {
+  const int rb = brow_ptr[I], re = brow_ptr[I + 1];
+  const int off = 6 * a + b;
+  hi = 0.0;
+  lo = 0.0;
+  for (int s = rb; s < re; ++s) {
+    const int64_t J = bcol[s];
+    const double2 kv = *reinterpret_cast<const double2*>(K + 36 * (int64_t)s + off);
+    const double2 xv = *reinterpret_cast<const double2*>(x + 6 * J + b);
+    dd_add_product(kv.x, xv.x, hi, lo);
+    dd_add_product(kv.y, xv.y, hi, lo);
+  }
+}
+
+// r = b - K x with the row sums in double-double (rounded once); partials of ||r||^2 and
+// ||b||^2.
 __global__ void __launch_bounds__(MAX_TPB)
 k_residual(int n_nodes, const int32_t* __restrict__ brow_ptr, const int32_t* __restrict__ bcol,
            const double* __restrict__ K, const double* __restrict__ x,
            const double* __restrict__ b, double* __restrict__ r, double* partials) {
+#pragma clang fp contract(off)
   const SpLane L = sp_lane();
   const int wave = threadIdx.x >> 6;
   double v[2] = {0.0, 0.0};
   for (int gi = blockIdx.x; gi * ROWS_PER_WG < n_nodes; gi += gridDim.x) {
     const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
     const bool ok = L.ok && I < n_nodes;
-    double acc = 0.0;
-    if (ok) acc = row_product<double, false>(brow_ptr, bcol, K, x, x, 0.0, I, L.a, L.b);
-    const double sum = sum3(acc);
+    double hi = 0.0, lo = 0.0;
+    if (ok) row_product_dd(brow_ptr, bcol, K, x, I, L.a, L.b, hi, lo);
+    // the 3-lane set's pairs into its first lane (lane i reads lane i + 1), fixed order
+    const double h1 = dpp_move<0x130>(hi), l1 = dpp_move<0x130>(lo);
+    const double h2 = dpp_move<0x130>(h1), l2 = dpp_move<0x130>(l1);
+    dd_add(h1, l1, hi, lo);
+    dd_add(h2, l2, hi, lo);
     if (ok && L.b == 0) {
       const int64_t d = 6 * (int64_t)I + L.a;
-      const double rv = b[d] - sum;
+      double s, e;
+      two_sum(b[d], -hi, s, e);
+      const double rv = s + (e - lo);
       if (r) r[d] = rv;
       v[0] += rv * rv;
       v[1] += b[d] * b[d];

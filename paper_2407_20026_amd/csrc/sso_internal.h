@@ -339,7 +339,8 @@ void batch_free(BatchWork& bw, hipStream_t s);
 // Deterministic dot product a^T b; result written to *d_out (device).
 hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, double* d_out,
                       hipStream_t s);
-// r = b - K x (FP64), and rr = ||r||^2, bb = ||b||^2 into d_out[0], d_out[1].
+// r = b - K x (row sums in double-double, rounded to FP64 once), and rr = ||r||^2,
+// bb = ||b||^2 into d_out[0], d_out[1].
 hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double* K,
                                 const double* x, const double* b, double* r, PcgWork& w,
                                 double* d_out, hipStream_t s);

@@ -1,14 +1,23 @@
 """The 300 x 300 shell (90,601 nodes, 543,606 DOF) at full size, in the launch configuration the
-benchmark uses.  The oracle cannot build the global pattern or factorise K at this size in a
-test, so it checks sampled outputs it computes one by one (pattern rows, permutation segments,
-K rows) and properties that hold at any size (the residual of u under the oracle's own K and f,
-the compliance identity, translation invariance of the coordinate gradient, and homogeneity of
-the compliance in the stiffness scale)."""
+benchmark uses.
+
+u and every gradient entry are compared element by element with the oracle's reference solution
+committed in ``tests/golden/shell300_oracle.npz`` (written by ``tests/golden/make_shell300.py``
+from the oracle alone: banded Cholesky with long-double refinement, complex-step element terms).
+The oracle's global pattern is too slow to build in a test at this size, so the pattern and K are
+checked on sampled rows that the oracle computes one by one.  Residuals are evaluated under the
+oracle's own K with long-double products and sums (an FP64 evaluation has a floor near 1.3e-10
+on this system, above the 1e-10 target)."""
+import os
+
 import numpy as np
 import pytest
 
 import meshgen
-from oracle import assembly
+from oracle import assembly, solve
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "shell300_oracle.npz")
+EPS = np.finfo(float).eps
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +44,54 @@ def big():
                 gx=g["dg_dxyz"].cpu().numpy(), gt=g["dg_dt"].cpu().numpy(),
                 gs=g["dg_dscale"].cpu().numpy(), vals=vals.cpu().numpy(),
                 f=f.cpu().numpy().ravel(), pat=pat)
+
+
+@pytest.fixture(scope="module")
+def ref(big):
+    """The oracle's reference solution, its K_ff and f_f (free equations), the GPU's own
+    assembled K_ff read back, and the part of a residual that the two K's rounding differences
+    explain, |(K_gpu - K_oracle) u| / |f| (long double)."""
+    import scipy.sparse as sp
+    mesh = big["mesh"]
+    d = dict(np.load(GOLDEN))
+    K = assembly.assemble_coo(mesh).tocsr()
+    f = assembly.load_vector(mesh)
+    F = solve.free_dofs(mesh)
+    pat = big["pat"]
+    Kg = sp.csr_matrix((big["vals"], pat["col"], pat["row_ptr"]), shape=K.shape)
+    d.update(F=F, Kff=K[F][:, F], ff=f[F], f=f, Kg_ff=Kg[F][:, F])
+    dK = (d["Kg_ff"] - d["Kff"]).tocsr()
+    # entry by entry the two FP64 K agree to rounding: relative to each row's largest entry
+    row_max = np.maximum.reduceat(np.abs(d["Kff"].data), d["Kff"].indptr[:-1])
+    d["dK_rel"] = float(np.max(np.abs(dK).max(axis=1).toarray().ravel() / row_max))
+    d["dK_u"] = lambda u: float(
+        np.sqrt(np.sum(solve.residual_ld(dK, u[F], np.zeros(len(F))) ** 2)) /
+        np.linalg.norm(d["ff"]))
+    return d
+
+
+def _rel_res_ld(ref, u, K="Kff"):
+    """Relative residual of the free equations, products and sums in long double, under the
+    oracle's K (K="Kff") or the GPU's own (K="Kg_ff")."""
+    r = solve.residual_ld(ref[K], u[ref["F"]], ref["ff"])
+    return float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(ref["ff"].astype(np.longdouble) ** 2)))
+
+
+def _check_against_reference(ref, u, rtol, label):
+    """u of a solve to rtol against the oracle: the residual under the GPU's own K at rtol; under
+    the oracle's K at rtol plus the share of the two K's rounding differences; u within 1e-10
+    (relative 2-norm) of the oracle's u once rtol is 1e-10."""
+    res_own = _rel_res_ld(ref, u, "Kg_ff")
+    res_or = _rel_res_ld(ref, u)
+    dku = ref["dK_u"](u)
+    du = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
+    print(f"  {label}: residual (long double) under the GPU's K {res_own:.3e}, under the "
+          f"oracle's K {res_or:.3e} (K rounding share {dku:.3e}, max entry difference "
+          f"{ref['dK_rel']:.2e} of the row); |u - u_ref| / |u_ref| = {du:.3e} "
+          f"(kappa_eff {float(ref['kappa_eff']):.3e})")
+    assert res_own <= rtol
+    assert res_or <= rtol + 1.01 * dku
+    return du
 
 
 def _sample_nodes(mesh):
@@ -81,21 +138,29 @@ def test_sampled_stiffness_rows(big):
                 assert abs(vals[q] - ref) <= 1e-13 * scale
 
 
-def test_residual_under_oracle_operator(big):
+def test_u_against_oracle_reference(big, ref):
     mesh, u = big["mesh"], big["u"]
-    f = assembly.load_vector(mesh)
     free = mesh.fixed.reshape(-1) == 0
-    np.testing.assert_allclose(big["f"], np.where(free, f, 0.0), rtol=0,
-                               atol=1e-13 * np.abs(f).max())
-    r = (f - assembly.apply_K_elementwise(mesh, u))[free]
-    rel = np.linalg.norm(r) / np.linalg.norm(f[free])
-    print(f"  oracle-operator residual {rel:.2e}, GPU-reported {big['st']['rel_residual']:.2e}")
-    # 1e-10 is requested; the correction steps stop early only where the FP64 residual floor
-    # of this system is reached
-    assert big["status"] in (0, -4)
-    assert rel <= 1e-9
+    np.testing.assert_allclose(big["f"], np.where(free, ref["f"], 0.0), rtol=0,
+                               atol=1e-13 * np.abs(ref["f"]).max())
+    # the two assembled K agree entry by entry to rounding
+    assert ref["dK_rel"] <= 64 * EPS
+    assert big["status"] == 0
+    assert big["st"]["rel_residual"] <= 1e-10
+    du = _check_against_reference(ref, u, 1e-10, "FP64")
+    assert du <= 1e-10
     assert np.all(u[~free] == 0.0)
-    assert big["c"] == pytest.approx(float(f[free] @ u[free]), rel=1e-12)
+    assert big["c"] == pytest.approx(float(ref["c"]), rel=1e-10)
+
+
+def test_gradients_against_oracle_reference(big, ref):
+    """Every entry of dc/dxyz, dc/dt and dc/ds against the oracle's adjoint, inf-norm relative."""
+    for name, key in (("dc/dxyz", "gx"), ("dc/dt", "gt"), ("dc/ds", "gs")):
+        g = big[key]
+        g_ref = ref[{"gx": "grad_xyz", "gt": "grad_t", "gs": "grad_scale"}[key]]
+        err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+        print(f"  {name}: max |g - g_ref| / max |g_ref| = {err:.3e}")
+        assert err <= 1e-8, name
 
 
 def test_gradient_invariants(big):
@@ -107,10 +172,9 @@ def test_gradient_invariants(big):
     assert np.all(np.isfinite(big["gt"]))
 
 
-def test_fused_recurrences_at_full_size(big):
+def test_fused_recurrences_at_full_size(big, ref):
     """The single-reduction kernel forced on the 300x300 shell: grid-stride passes (5 row groups
-    per workgroup) over the padded 9-slot rows.  Same residual bar under the oracle's operator,
-    and u within the solve tolerance of the standard recurrences' u."""
+    per workgroup) over the padded 9-slot rows, to the same bars as the standard recurrences."""
     import paper_2407_20026_amd as sso
     mesh = big["mesh"]
     print("[gpu] large shell 300x300: fused recurrences", flush=True)
@@ -120,38 +184,41 @@ def test_fused_recurrences_at_full_size(big):
         status = p.last_status
         assert st["solver"] == sso.SOLVER_FUSED
     u = u.cpu().numpy().ravel()
-    assert status in (0, -4)
-    f = assembly.load_vector(mesh)
-    free = mesh.fixed.reshape(-1) == 0
-    r = (f - assembly.apply_K_elementwise(mesh, u))[free]
-    assert np.linalg.norm(r) / np.linalg.norm(f[free]) <= 1e-9
-    d = np.linalg.norm(u - big["u"]) / np.linalg.norm(big["u"])
-    print(f"  |u_fused - u_standard| / |u| = {d:.2e}, iters {st['iters']}")
-    assert d <= 1e-6
+    print(f"  status {status}, iters {st['iters']}, GPU-reported residual "
+          f"{st['rel_residual']:.3e}")
+    assert status == 0
+    du = _check_against_reference(ref, u, 1e-10, "fused")
+    assert du <= 1e-10
 
 
-def test_mixed_precision_flexible_cg_at_full_size(big):
-    """Mixed precision on the 300x300 shell, where an FP32 inner solve is too far from K for
-    plain iterative refinement: the FP64 flexible CG with inner solves capped at 20 FP32
-    iterations reaches the residual target under the oracle's operator, and u and the compliance
-    agree with the FP64 solve."""
+def test_mixed_precision_flexible_cg_at_full_size(big, ref):
+    """Mixed precision on the 300x300 shell at the configured 1e-10: the FP64 flexible CG with
+    inner solves capped at 20 FP32 iterations.  u and every gradient entry are compared with
+    the FP64 path and with the oracle."""
     import paper_2407_20026_amd as sso
     mesh = big["mesh"]
     print("[gpu] large shell 300x300: mixed precision, flexible CG, inner cap 20", flush=True)
-    with sso.Problem(mesh, sso.Options(precision=sso.PREC_MIXED, rtol=1e-8, max_it=400000,
+    with sso.Problem(mesh, sso.Options(precision=sso.PREC_MIXED, rtol=1e-10, max_it=400000,
                                        refine_steps=20000, inner_max_it=20)) as p:
         u, st = p.solve(check=False)
         status = p.last_status
         c = p.objective("compliance")
+        g = p.adjoint("compliance")
     u = u.cpu().numpy().ravel()
-    f = assembly.load_vector(mesh)
-    free = mesh.fixed.reshape(-1) == 0
-    r = (f - assembly.apply_K_elementwise(mesh, u))[free]
-    rel = np.linalg.norm(r) / np.linalg.norm(f[free])
-    d = np.linalg.norm(u - big["u"]) / np.linalg.norm(big["u"])
     print(f"  status={status} outer={st['refine_steps']} inner iters={st['iters']} "
-          f"oracle-operator residual {rel:.2e} |u_mixed - u_fp64| / |u| = {d:.2e}")
+          f"GPU-reported residual {st['rel_residual']:.3e}")
     assert status == 0
-    assert rel <= 1.01e-8
-    assert d <= 1e-4
-    assert c == pytest.approx(big["c"], rel=1e-7)
+    du = _check_against_reference(ref, u, 1e-10, "mixed")
+    assert du <= 1e-10
+    d64 = np.linalg.norm(u - big["u"]) / np.linalg.norm(big["u"])
+    print(f"  |u_mixed - u_fp64| / |u_fp64| = {d64:.3e}")
+    assert d64 <= 1e-10
+    assert c == pytest.approx(big["c"], rel=1e-10)
+    for name, key, gk in (("dc/dxyz", "gx", "dg_dxyz"), ("dc/dt", "gt", "dg_dt"),
+                          ("dc/ds", "gs", "dg_dscale")):
+        gm = g[gk].cpu().numpy()
+        e64 = np.abs(gm - big[key]).max() / np.abs(big[key]).max()
+        g_ref = ref[{"gx": "grad_xyz", "gt": "grad_t", "gs": "grad_scale"}[key]]
+        eor = np.abs(gm - g_ref).max() / np.abs(g_ref).max()
+        print(f"  {name}: against the FP64 path {e64:.3e}, against the oracle {eor:.3e}")
+        assert e64 <= 1e-8 and eor <= 1e-8, name
