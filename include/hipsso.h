@@ -18,7 +18,7 @@
  *   Sec. 2.3.1  adjoint equation K^T lambda = dg/du^T (Eq. 5) and adjoint sensitivity
  *               dg/dp = dg/dp|explicit - lambda^T (dK/dp u - df/dp) (Eq. 6); node parameters
  *               (coordinate of a node) and objectives ("strain energy" f^T u / 2).
- *   Sec. 3.3-3.4 thickness as a design variable; SIMP stiffness scaling E = rho^P E0 (Eq. 8).
+ *   Sec. 3.3-3.4 thickness as a design variable; SIMP stiffness scaling E = rho^P E0 (Eq. 13).
  *
  * Conventions shared by every entry point:
  *   - Global DOF d = 6 * node + c, c in (ux, uy, uz, rx, ry, rz).  SI units.
@@ -55,7 +55,7 @@ enum {
 };
 
 enum {
-  SSO_OBJ_COMPLIANCE = 0,     /* g = f^T u                      (loss of Sec. 3.5)      */
+  SSO_OBJ_COMPLIANCE = 0,     /* g = f^T u                      (loss of Sec. 3.6)      */
   SSO_OBJ_STRAIN_ENERGY = 1,  /* g = f^T u / 2                  (Sec. 2.2.3, 2.3.2)     */
   SSO_OBJ_LINEAR = 2,         /* g = a^T u, a given                                        */
   SSO_OBJ_USER = 3            /* caller supplies dg/du; dg/dp omits explicit dependence    */
@@ -142,9 +142,12 @@ typedef struct sso_problem sso_problem;
 int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
                        sso_problem** out);
 
-/* Replace design inputs without changing the topology (device pointers, each may be NULL to
- * keep the current values): xyz [n_nodes][3]; quad_t [n_quads] thickness; quad_scale [n_quads]
- * stiffness scale.  Enqueued on the problem's stream; invalidates the last solution. */
+/* Replace design inputs without changing the topology: the design parameters p of the
+ * optimisation problem (Sec. 2.3.1, Eq. (4); updated between steps as in Eq. (7)) -- nodal
+ * coordinates (node parameters, Sec. 2.3.1), shell thickness (Sec. 3.3) and the per-element
+ * stiffness scale (SIMP, Sec. 3.4 Eq. (13)).  Device pointers, each may be NULL to keep the
+ * current values: xyz [n_nodes][3]; quad_t [n_quads] thickness; quad_scale [n_quads] stiffness
+ * scale.  Enqueued on the problem's stream; invalidates the last solution. */
 int sso_problem_update(sso_problem* p, const double* xyz, const double* quad_t,
                        const double* quad_scale);
 
@@ -189,9 +192,10 @@ int sso_batch_create(hipStream_t stream, sso_batch** out);
 int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done);
 void sso_batch_destroy(sso_batch* b);
 
-/* Objective value of the last solve into *g_host (host): compliance f^T u, strain energy
- * f^T u / 2 (f: the applied load on the free DOFs), or a^T u for SSO_OBJ_LINEAR (a: device
- * [n_nodes][6]).  SSO_OBJ_USER: SSO_EINVAL.
+/* Objective value g(u) of the last solve (the objective of Sec. 2.3.1, Eq. (4)) into *g_host
+ * (host): compliance f^T u (the loss of the network example, Sec. 3.6), strain energy f^T u / 2
+ * (Sec. 2.2.3, 2.3.2; f: the applied load on the free DOFs), or a^T u for SSO_OBJ_LINEAR (a:
+ * device [n_nodes][6]).  SSO_OBJ_USER: SSO_EINVAL.
  * Errors: SSO_EINVAL without a previous successful solve. */
 int sso_objective(sso_problem* p, int kind, const double* a, double* g_host);
 
@@ -224,6 +228,13 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz,
 int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
                        double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats);
 
+/* The self-adaptive penalty coefficient of the size optimisation for the next step (Sec. 3.3,
+ * Eq. (10)): *eps1_next (host) = kappa * eps1 after a design that violated the displacement limit
+ * (c > 0 in sso_size_objective's output), eps1 / kappa otherwise (the paper's example uses
+ * kappa = 1.015).  Host arithmetic only; no problem and no GPU involved.  Errors: SSO_EINVAL for
+ * eps1 < 0, kappa <= 0, a value that is not finite, or eps1_next NULL. */
+int sso_size_penalty_update(double eps1, int violated, double kappa, double* eps1_next);
+
 /* Hat filter of nodal sensitivities (Sec. 3.1-3.2): for n design nodes (nodes [n] device int32
  * indices into the problem's nodes, or NULL for nodes 0..n-1) with sensitivities g [n]
  * (device), out[i] = sum_j w_ij g_j / sum_j w_ij, w_ij = max(0, radius - |X_i - X_j|), X the
@@ -233,8 +244,9 @@ int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
 int sso_hat_filter(sso_problem* p, int32_t n, const int32_t* nodes, const double* g,
                    double radius, double* out);
 
-/* The scalar CSR view of the pattern and the scatter permutation (built on first call, owned
- * by the problem, valid until destroy).  All arrays are device int32:
+/* The scalar CSR view of the pattern and the scatter permutation: the element-to-global index
+ * maps and the sparse storage of the assembled K (Sec. 2.2.1, Eq. (1)), built on first call,
+ * owned by the problem, valid until destroy.  All arrays are device int32:
  *   row_ptr [n_dof + 1], col [nnz]: scalar CSR of K, columns sorted;
  *   perm [n_coo]: stable sort of the element contribution list (element-major, beams then
  *                 quads, each local matrix row-major) by (row, col);

@@ -5,10 +5,10 @@ Paper: Sec. 2.3.1 -- minimise g(u, p) subject to K(p) u = f(p); the adjoint equa
 K^T lambda = (dg/du)^T (Eq. (5)) and the adjoint sensitivity
 dg/dp = dg/dp|_explicit - lambda^T (dK/dp u - df/dp) (Eq. (6)).  Objectives: the paper's
 "strain energy" g = f^T u / 2 (Sec. 2.2.3 and 2.3.2), compliance f^T u (the loss of the neural
-network example, Sec. 3.5), a linear functional a^T u, or any g whose dg/du the caller provides.
+network example, Sec. 3.6), a linear functional a^T u, or any g whose dg/du the caller provides.
 Design parameters: nodal Z (and X, Y) coordinates (Sec. 2.3.1 listing, NodeParameter(node, 2))
 and shell thickness (Sec. 3.3), plus the per-element stiffness scale that carries the SIMP
-density (Sec. 3.4, Eq. (8)).
+density (Sec. 3.4, Eq. (13)).
 
 Element derivatives dK_e/dp and df_e/dp are taken by the complex step,
 dK_e/dp = Im K_e(p + i h) / h with h = 1e-30 (exact to rounding, independent of any dual or

@@ -62,7 +62,7 @@ EXPORTS = ("sso_problem_create", "sso_problem_update", "sso_set_options", "sso_s
            "sso_solve_begin", "sso_solve_end", "sso_batch_create", "sso_batch_iterate",
            "sso_batch_destroy", "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix",
            "sso_sizes", "sso_strerror", "sso_problem_destroy", "sso_size_objective",
-           "sso_hat_filter")
+           "sso_size_penalty_update", "sso_hat_filter")
 
 _lib = None
 _hip = None
@@ -94,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                       P(ctypes.c_int32)]
     lib.sso_size_objective.argtypes = [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        P(ctypes.c_double), _vp, _vp, P(sso_stats)]
+    lib.sso_size_penalty_update.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                            P(ctypes.c_double)]
     lib.sso_hat_filter.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_double, _vp]
     lib.sso_batch_destroy.argtypes = [_vp]
     lib.sso_batch_destroy.restype = None
@@ -207,6 +209,8 @@ class Problem:
                "sso_sizes")
         self.n_blocks, self.nnz = nb.value, nz.value
         self.last_stats = None
+        # bumped by every call that changes the design or the solution (update, options, solves)
+        self.generation = 0
 
     def _new(self, shape, dtype):
         with torch.cuda.stream(self.stream):
@@ -237,11 +241,13 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream(d))
         with torch.cuda.stream(self.stream):
             self._upd = [_dev(a, torch.float64, d) for a in (xyz, quad_t, quad_scale)]
+        self.generation += 1
         _check(load_library().sso_problem_update(self.handle, *[_ptr(a) for a in self._upd]),
                "sso_problem_update")
 
     def set_options(self, options: Options):
         self.options = options
+        self.generation += 1
         o = options.c()
         _check(load_library().sso_set_options(self.handle, ctypes.byref(o)), "sso_set_options")
 
@@ -250,6 +256,7 @@ class Problem:
         if u_out is None:
             u_out = self._new((self.n_nodes, 6), torch.float64)
         st = sso_stats()
+        self.generation += 1
         status = load_library().sso_solve(self.handle, _ptr(u_out), ctypes.byref(st))
         self.last_stats = st.as_dict()
         self.last_status = status
@@ -259,6 +266,7 @@ class Problem:
 
     def solve_begin(self):
         """Everything up to the first PCG iteration; then iterate with :class:`Batch`."""
+        self.generation += 1
         _check(load_library().sso_solve_begin(self.handle), "sso_solve_begin")
 
     def solve_end(self, u_out: torch.Tensor | None = None, check: bool = True):
@@ -326,9 +334,13 @@ class Problem:
 
     @staticmethod
     def update_eps1(eps1, violated, kappa=1.015):
-        """Self-adaptive penalty coefficient of the size optimisation (Sec. 3.3): times kappa
-        after a step that violates the displacement limit, divided by it otherwise."""
-        return eps1 * kappa if violated else eps1 / kappa
+        """Self-adaptive penalty coefficient for the next size-optimisation step
+        (sso_size_penalty_update)."""
+        out = ctypes.c_double()
+        _check(load_library().sso_size_penalty_update(float(eps1), int(bool(violated)),
+                                                      float(kappa), ctypes.byref(out)),
+               "sso_size_penalty_update")
+        return out.value
 
     def pattern(self):
         """Copies of the scalar CSR view and the scatter permutation (int32 device tensors)."""

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhipsso.so")
-SOURCES = ["api.hip", "pattern.hip", "elements.hip", "assemble.hip", "pcg.hip", "extras.hip"]
+SOURCES = ["api.hip", "pattern.hip", "elements.hip", "assemble.hip", "pcg.hip", "extras.hip",
+           "ceiling.hip"]
 ARCH = os.environ.get("HIPSSO_ARCH", "gfx950")
 
 CFLAGS = [

@@ -33,9 +33,9 @@ struct sso_problem {
   double* wv = nullptr;         //   partials (allocated on first use)
   double* xpart = nullptr;
   double* d_scal = nullptr;     // small device scalars (dot products, residual norms)
-  double* h_scal = nullptr;     // pinned mirror
+  double* h_scal = nullptr;     // host mirror of d_scal (pageable)
   unsigned* d_err = nullptr;
-  unsigned* h_err = nullptr;    // pinned
+  unsigned* h_err = nullptr;    // host mirror of d_err (pageable)
   PcgWork w;
   int32_t* row_ptr = nullptr;   // scalar CSR view (built on demand)
   int32_t* col = nullptr;
@@ -604,6 +604,14 @@ int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
     stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
   }
   return status;
+}
+
+int sso_size_penalty_update(double eps1, int violated, double kappa, double* eps1_next) {
+  if (!eps1_next || !(eps1 >= 0.0) || !std::isfinite(eps1) || !(kappa > 0.0) ||
+      !std::isfinite(kappa))
+    return SSO_EINVAL;
+  *eps1_next = violated ? eps1 * kappa : eps1 / kappa;
+  return SSO_OK;
 }
 
 int sso_hat_filter(sso_problem* p, int32_t n, const int32_t* nodes, const double* g,

@@ -99,6 +99,27 @@ def _convergence(results) -> dict:
             "max_rel_residual": max((r.rel_residual for r in results), default=0.0)}
 
 
+def errors_against(results, reference) -> list[dict]:
+    """Per request, the error of each result against the same request's result in a reference
+    run (e.g. the plain FP64 path): relative error of g, and max-norm relative errors of dg/dxyz
+    and dg/dt.  Requests are matched by id; ids missing from the reference are skipped."""
+    ref = {r.rid: r for r in reference}
+    out = []
+    for r in results:
+        q = ref.get(r.rid)
+        if q is None:
+            continue
+        e = {"rid": r.rid, "n_dof": r.n_dof,
+             "g_rel": abs(r.g - q.g) / max(abs(q.g), 1e-300),
+             "dg_dxyz_rel_inf": float(np.abs(r.grad_xyz - q.grad_xyz).max() /
+                                      max(np.abs(q.grad_xyz).max(), 1e-300))}
+        if r.grad_t is not None and q.grad_t is not None and q.grad_t.size:
+            e["dg_dt_rel_inf"] = float(np.abs(r.grad_t - q.grad_t).max() /
+                                       max(np.abs(q.grad_t).max(), 1e-300))
+        out.append(e)
+    return out
+
+
 def run_one(req: Request, options: Options, stream=None, device="cuda") -> Result:
     """Forward + adjoint of one request on ``stream`` (used by the loop and to check results
     alone)."""

@@ -1,11 +1,11 @@
 """Differentiable batch of shell variants driven by a neural network.
 
-The paper's physics-in-the-loop workflow (Sec. 2.4; example of Sec. 3.5): an MLP maps the plan
+The paper's physics-in-the-loop workflow (Sec. 2.4; example of Sec. 3.6): an MLP maps the plan
 coordinates of every node to the node height and to a shell thickness, the structure is
 analysed, and the loss (compliance) is back-propagated through the solver's adjoint into the
 network weights.  Here a batch of variants shares the network and the plan; each variant has
 its own seeded element density rho, which scales the element stiffness by rho^3 (SIMP with
-P = 3, Sec. 3.4 Eq. 8; the loads do not depend on rho).  Network: Linear(2, 64) -> tanh ->
+P = 3, Sec. 3.4 Eq. (13); the loads do not depend on rho).  Network: Linear(2, 64) -> tanh ->
 Linear(64, 2); z = 3 sigmoid(o_0) m, nodal t = 0.1 + 0.2 sigmoid(o_1) m, element t = mean of its
 4 corners; loss = mean compliance over the variants.
 

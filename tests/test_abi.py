@@ -88,3 +88,30 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(st), name
         for f, _ in st._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, (name, f)
+
+
+def test_library_exports_the_ceiling_probes():
+    text = open(os.path.join(ROOT, "include", "hipsso_ceiling.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(hipsso_ceiling_[a-z_]+)\s*\(", text)))
+    from paper_2407_20026_amd import ceiling
+    assert names == sorted(ceiling.EXPORTS)
+    lib = ctypes.CDLL(_lib_path())
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_size_penalty_update_matches_the_oracle_rule():
+    """The host-only penalty rule of the C ABI against the oracle's (no GPU call)."""
+    import paper_2407_20026_amd as sso
+    from oracle import extras
+    for eps1, violated, kappa in ((2.0, True, 1.015), (2.03, False, 1.015), (1.0, True, 1.1),
+                                  (0.0, True, 1.015), (5.0, False, 2.0)):
+        assert sso.Problem.update_eps1(eps1, violated, kappa) == \
+            extras.update_eps1(eps1, violated, kappa)
+    lib = sso.load_library()
+    out = ctypes.c_double()
+    for bad in ((-1.0, 1, 1.015), (1.0, 1, 0.0), (float("nan"), 0, 1.015),
+                (1.0, 0, float("inf"))):
+        assert lib.sso_size_penalty_update(*bad, ctypes.byref(out)) == sso.SSO_EINVAL
+    assert lib.sso_size_penalty_update(1.0, 1, 1.015, None) == sso.SSO_EINVAL

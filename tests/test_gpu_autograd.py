@@ -195,3 +195,73 @@ def test_nonlinear_displacement_objective_through_autograd():
             vals.append(g_of(sensitivity.forward(m)["u"]))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(gx[i, c] - fd) <= 1e-5 * max(abs(fd), 1e-3 * gmax), (i, c, gx[i, c], fd)
+
+
+def test_network_batch_at_configured_size_vs_oracle_adjoint():
+    """The configured plan, 80 x 80 quads (39,366 DOF per variant), variants 0 and 1 in
+    multi-problem launches: the loss and every network weight's gradient against the oracle's
+    adjoint of the same design (tests/golden/make_shellnet80.py) chained through the same MLP
+    with torch's CPU autograd, at 1e-8 of the largest weight gradient."""
+    import os
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.shellnet import DesignMLP, ShellBatch, geometry
+    print("[gpu] shellnet batch 80x80 x 2 variants vs oracle adjoint", flush=True)
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "shellnet80_oracle.npz"))
+    L = 20.0
+    batch = ShellBatch(m=80, n_variants=2, L=L, options=sso.Options(rtol=1e-11, max_it=400000),
+                       batched=True)
+    try:
+        net = DesignMLP().to("cuda")
+        for p, k in zip(net.parameters(), ("W1", "b1", "W2", "b2")):
+            assert np.array_equal(p.detach().cpu().numpy(), ref[k]), k   # the same network
+        loss = batch.loss(net)
+        loss.backward()
+        grads = [p.grad.detach().cpu().numpy().copy() for p in net.parameters()]
+        statuses = [p.last_status for p in batch.problems]
+        base = batch.base
+    finally:
+        batch.close()
+    assert statuses == [0, 0]
+    c_ref = np.mean([float(ref[f"c_{v}"]) for v in (0, 1)])
+    assert loss.item() == pytest.approx(c_ref, rel=1e-9)
+    gx = np.mean([ref[f"grad_xyz_{v}"] for v in (0, 1)], axis=0)
+    gt = np.mean([ref[f"grad_t_{v}"] for v in (0, 1)], axis=0)
+    net_cpu = DesignMLP()
+    xyz, t = geometry(net_cpu, torch.tensor(base.xyz[:, :2]), L,
+                      torch.tensor(base.quad_nodes.astype(np.int64)))
+    ((xyz * torch.tensor(gx)).sum() + (t * torch.tensor(gt)).sum()).backward()
+    gmax = max(np.abs(g).max() for g in grads)
+    for g, p in zip(grads, net_cpu.parameters()):
+        err = np.abs(g - p.grad.numpy()).max() / gmax
+        print(f"  weight block {tuple(g.shape)}: max error {err:.2e} of the largest gradient")
+        assert err <= 1e-8
+
+
+def test_two_forwards_on_one_problem_then_one_backward():
+    """Two compliance evaluations of different designs on one problem, summed, then one
+    backward: each node differentiates its own design (the later forward changed K and u in
+    between), so the gradients equal those of two separate problems."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.autograd import compliance
+    print("[gpu] two forwards, one backward", flush=True)
+    mesh = meshgen.shell(8, L=8.0, seed=31)
+    x0 = torch.tensor(mesh.xyz, device="cuda")
+    t0 = torch.tensor(mesh.quad_prop[:, 0], device="cuda")
+    designs = [(x0, t0), (x0 + torch.tensor([0.0, 0.0, 0.3], dtype=torch.float64,
+                                            device="cuda") * x0[:, :1] / 8.0, 1.3 * t0)]
+    opts = sso.Options(rtol=1e-11, solver=sso.SOLVER_STANDARD)
+
+    def leaves():
+        return [(x.clone().requires_grad_(True), t.clone().requires_grad_(True))
+                for x, t in designs]
+
+    shared = leaves()
+    with sso.Problem(mesh, opts) as p:
+        (compliance(p, *shared[0]) + compliance(p, *shared[1])).backward()
+    apart = leaves()
+    for (x, t) in apart:
+        with sso.Problem(mesh, opts) as q:
+            compliance(q, x, t).backward()
+    for (xs, ts), (xa, ta) in zip(shared, apart):
+        assert torch.equal(xs.grad, xa.grad) and torch.equal(ts.grad, ta.grad)
+    assert not torch.equal(shared[0][0].grad, shared[1][0].grad)

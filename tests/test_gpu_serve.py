@@ -1,9 +1,14 @@
 """Continuous batching: requests of mixed sizes admitted by slots and device-memory budget run
-concurrently on separate streams; every result equals the same request solved alone."""
+concurrently on separate streams; every result equals the same request solved alone, and a
+sample of the served stream, its largest sizes included, matches the oracle."""
+import os
+
 import numpy as np
 import pytest
 
 import meshgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "served_sample_oracle.npz")
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +40,7 @@ def test_results_in_the_mix_equal_results_alone(precision):
     assert stats.n == len(reqs)
     assert stats.peak_inflight >= 2          # work did overlap
     for r, req in zip(stats.results, reqs):
+        assert r.status == sso.SSO_OK and r.rel_residual <= opts.rtol
         alone = run_one(req, opts)
         assert r.g == pytest.approx(alone.g, rel=1e-12)
         np.testing.assert_allclose(r.grad_xyz, alone.grad_xyz, rtol=0,
@@ -60,6 +66,7 @@ def test_batched_loop_results_equal_results_alone(solver):
     assert stats.n == len(reqs)
     assert stats.peak_inflight >= 4
     for r, req in zip(stats.results, reqs):
+        assert r.status == sso.SSO_OK and r.rel_residual <= opts.rtol
         alone = run_one(req, opts)
         assert r.g == alone.g
         assert np.array_equal(r.grad_xyz, alone.grad_xyz)
@@ -150,6 +157,7 @@ def test_batched_mixed_precision_matches_solves_alone(solver):
     assert stats.n == len(reqs)
     assert stats.peak_inflight >= 3
     for r, req in zip(stats.results, reqs):
+        assert r.status == sso.SSO_OK and r.rel_residual <= opts.rtol
         alone = run_one(req, opts)
         assert r.g == alone.g
         assert np.array_equal(r.grad_xyz, alone.grad_xyz)
@@ -189,3 +197,58 @@ def test_batch_with_prescribed_displacements_matches_solves_alone():
         with sso.Problem(m, sso.Options(rtol=1e-10, solver=k)) as q:
             ua, _ = q.solve()
         assert np.array_equal(u, ua.cpu().numpy())
+
+
+@pytest.fixture(scope="module")
+def served_sample():
+    """Requests 0, 1, 2, 3, 4, 6, 10, 11 and 51 of the served stream (shells 55, 54, 25, 16 and
+    120 -- the stream's largest -- and grid-shells 26, 41, 13 and 60, the largest) and the
+    oracle's c and gradients of each (tests/golden/make_served_sample.py)."""
+    from paper_2407_20026_amd import Options, PREC_FP64, PREC_MIXED
+    from paper_2407_20026_amd.serve import BatchedServer, Request
+    ref = np.load(GOLDEN)
+    rids = [int(i) for i in ref["rids"]]
+    reqs = [Request(i, meshgen.served_request(i), 0.002 * k) for k, i in enumerate(rids)]
+    for q in reqs:
+        assert q.mesh.name == str(ref[f"name_{q.rid}"])
+    out = {}
+    for name, prec in (("fp64", PREC_FP64), ("mixed", PREC_MIXED)):
+        print(f"[gpu] served sample vs oracle: {name}, {len(reqs)} requests", flush=True)
+        opts = Options(precision=prec, rtol=1e-10, max_it=400000)
+        out[name] = BatchedServer(slots=16, options=opts, chunk=32).run(reqs)
+    return ref, reqs, out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_served_results_match_the_oracle(served_sample, precision):
+    """Each served result (in the mix, multi-problem launches, rtol 1e-10) against the oracle:
+    c within 1e-10 relative, every entry of dc/dxyz and dc/dt within 1e-8 of the largest."""
+    ref, reqs, out = served_sample
+    stats = out[precision]
+    assert stats.n == len(reqs)
+    assert stats.peak_inflight >= 4
+    for r in stats.results:
+        assert r.status == 0 and r.rel_residual <= 1e-10, (r.rid, r.status, r.rel_residual)
+        g_ref = float(ref[f"g_{r.rid}"])
+        gx_ref, gt_ref = ref[f"grad_xyz_{r.rid}"], ref[f"grad_t_{r.rid}"]
+        eg = abs(r.g - g_ref) / abs(g_ref)
+        ex = np.abs(r.grad_xyz - gx_ref).max() / np.abs(gx_ref).max()
+        et = (np.abs(r.grad_t - gt_ref).max() / np.abs(gt_ref).max()
+              if gt_ref.size else 0.0)
+        print(f"  {precision} request {r.rid} ({str(ref[f'name_{r.rid}'])}, {r.n_dof} DOF): "
+              f"c {eg:.2e}, dc/dxyz {ex:.2e}, dc/dt {et:.2e}, residual {r.rel_residual:.2e}")
+        assert eg <= 1e-10 and ex <= 1e-8 and et <= 1e-8, r.rid
+
+
+def test_mixed_served_results_report_their_error_against_fp64(served_sample):
+    """The served mixed-precision form reports, per result, its error against the FP64 path
+    (the same requests served in FP64); here every one is within the parity bars."""
+    from paper_2407_20026_amd.serve import errors_against
+    _, reqs, out = served_sample
+    errs = errors_against(out["mixed"].results, out["fp64"].results)
+    assert [e["rid"] for e in errs] == sorted(q.rid for q in reqs)
+    for e in errs:
+        assert e["g_rel"] <= 1e-10 and e["dg_dxyz_rel_inf"] <= 1e-8
+        assert e.get("dg_dt_rel_inf", 0.0) <= 1e-8
+    print("  mixed vs FP64: max g", max(e["g_rel"] for e in errs), "max dc/dxyz",
+          max(e["dg_dxyz_rel_inf"] for e in errs))
