@@ -50,8 +50,10 @@ enum {
   SSO_ENOMEM = -2,      /* device allocation failed                                       */
   SSO_EHIP = -3,        /* a HIP runtime call failed                                      */
   SSO_ENOTCONV = -4,    /* PCG reached max_it before the residual target (stats filled)   */
-  SSO_EBREAKDOWN = -5   /* p^T K p <= 0 or not finite: K not positive definite (e.g. an
+  SSO_EBREAKDOWN = -5,  /* p^T K p <= 0 or not finite: K not positive definite (e.g. an
                            unsupported rigid-body mode); stats filled                     */
+  SSO_ESIZE = -6        /* problem larger than the static scratch of
+                           sso_size_objective_noalloc (SSO_NOALLOC_MAX_QUADS)              */
 };
 
 enum {
@@ -234,6 +236,23 @@ int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
  * kappa = 1.015).  Host arithmetic only; no problem and no GPU involved.  Errors: SSO_EINVAL for
  * eps1 < 0, kappa <= 0, a value that is not finite, or eps1_next NULL. */
 int sso_size_penalty_update(double eps1, int violated, double kappa, double* eps1_next);
+
+/* The same as sso_size_objective, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or optimisation loops, harnesses that forbid hipMalloc): its
+ * scratch -- the reduction partials and the per-quad volume terms -- lives in a static device
+ * array of SSO_NOALLOC_SCRATCH_BYTES (16 MiB) that the library holds on each GPU it runs on
+ * until the process ends, instead of buffers the problem allocates on first use.  No hipMalloc,
+ * hipFree or allocating library routine is called: the problem must have been solved with its
+ * current options (sso_solve, which allocated the solver's own work vectors); the adjoint solve
+ * runs in those.  Results are bitwise those of sso_size_objective.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other host threads, other streams) race and
+ * must be serialised by the caller.  Errors: as sso_size_objective, and SSO_ESIZE when the
+ * problem has more than SSO_NOALLOC_MAX_QUADS quads. */
+#define SSO_NOALLOC_SCRATCH_BYTES (16u << 20)
+#define SSO_NOALLOC_MAX_QUADS 139673
+int sso_size_objective_noalloc(sso_problem* p, double eps1, double u_max, double t_min,
+                               double* out_host, double* dg_dxyz, double* dg_dt,
+                               sso_stats* stats);
 
 /* Hat filter of nodal sensitivities (Sec. 3.1-3.2): for n design nodes (nodes [n] device int32
  * indices into the problem's nodes, or NULL for nodes 0..n-1) with sensitivities g [n]

@@ -21,6 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhipsso.so")
 
 SSO_OK, SSO_EINVAL, SSO_ENOMEM, SSO_EHIP, SSO_ENOTCONV, SSO_EBREAKDOWN = 0, -1, -2, -3, -4, -5
+SSO_ESIZE = -6
+NOALLOC_MAX_QUADS = 139673   # SSO_NOALLOC_MAX_QUADS
 OBJ_COMPLIANCE, OBJ_STRAIN_ENERGY, OBJ_LINEAR, OBJ_USER = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 SOLVER_AUTO, SOLVER_STANDARD, SOLVER_FUSED = 0, 1, 2
@@ -62,7 +64,7 @@ EXPORTS = ("sso_problem_create", "sso_problem_update", "sso_set_options", "sso_s
            "sso_solve_begin", "sso_solve_end", "sso_batch_create", "sso_batch_iterate",
            "sso_batch_destroy", "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix",
            "sso_sizes", "sso_strerror", "sso_problem_destroy", "sso_size_objective",
-           "sso_size_penalty_update", "sso_hat_filter")
+           "sso_size_objective_noalloc", "sso_size_penalty_update", "sso_hat_filter")
 
 _lib = None
 _hip = None
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                       P(ctypes.c_int32)]
     lib.sso_size_objective.argtypes = [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        P(ctypes.c_double), _vp, _vp, P(sso_stats)]
+    lib.sso_size_objective_noalloc.argtypes = lib.sso_size_objective.argtypes
     lib.sso_size_penalty_update.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             P(ctypes.c_double)]
     lib.sso_hat_filter.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_double, _vp]
@@ -306,17 +309,24 @@ class Problem:
                "sso_adjoint")
         return dict(dg_dxyz=gx, dg_dt=gt, dg_dscale=gs, stats=st.as_dict())
 
-    def size_objective(self, eps1, u_max, t_min, want_t=True):
-        """Penalised material volume g = (1 + eps1 c) W of the last solve (sso_size_objective):
-        dict with g, c, W, dg_dxyz [n_nodes, 3], dg_dt [n_quads] and the stats."""
-        gx = self._new((self.n_nodes, 3), torch.float64)
-        gt = self._new(self.n_quads, torch.float64) if want_t and self.n_quads else None
-        out = (ctypes.c_double * 3)()
+    def size_objective(self, eps1, u_max, t_min, want_t=True, noalloc=False, out=None):
+        """Penalised material volume g = (1 + eps1 c) W of the last solve (sso_size_objective,
+        or sso_size_objective_noalloc with noalloc=True): dict with g, c, W, dg_dxyz
+        [n_nodes, 3], dg_dt [n_quads] and the stats.  ``out`` = (dg_dxyz, dg_dt) preallocated
+        device tensors (dg_dt may be None), else allocated here."""
+        if out is None:
+            gx = self._new((self.n_nodes, 3), torch.float64)
+            gt = self._new(self.n_quads, torch.float64) if want_t and self.n_quads else None
+        else:
+            gx, gt = out
+        res = (ctypes.c_double * 3)()
         st = sso_stats()
-        _check(load_library().sso_size_objective(self.handle, float(eps1), float(u_max),
-                                                 float(t_min), out, _ptr(gx), _ptr(gt),
-                                                 ctypes.byref(st)), "sso_size_objective")
-        return dict(g=out[0], c=out[1], W=out[2], dg_dxyz=gx, dg_dt=gt, stats=st.as_dict())
+        lib = load_library()
+        fn = lib.sso_size_objective_noalloc if noalloc else lib.sso_size_objective
+        _check(fn(self.handle, float(eps1), float(u_max), float(t_min), res, _ptr(gx), _ptr(gt),
+                  ctypes.byref(st)),
+               "sso_size_objective_noalloc" if noalloc else "sso_size_objective")
+        return dict(g=res[0], c=res[1], W=res[2], dg_dxyz=gx, dg_dt=gt, stats=st.as_dict())
 
     def hat_filter(self, g, radius, nodes=None):
         """Hat-filtered nodal sensitivities (sso_hat_filter): g [n] for the design nodes

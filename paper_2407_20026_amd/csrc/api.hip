@@ -3,10 +3,20 @@
 #include <new>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "sso_internal.h"
 
 using namespace sso;
+
+// The static scratch of sso_size_objective_noalloc: one copy per device, for the life of the
+// process.  In host code `scratch` names a host-side stand-in, not device memory; its device
+// address on each GPU comes from hipGetSymbolAddress (taken once per device, with that device
+// current) and only that address is ever handed to kernels.
+static __device__ __align__(256) double scratch[SSO_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+static_assert(SSO_NOALLOC_MAX_QUADS * 15 + 2 * 1024 <=
+                  (int64_t)(SSO_NOALLOC_SCRATCH_BYTES / sizeof(double)),
+              "the no-allocation scratch holds the partials and 15 values per quad");
 
 struct sso_problem {
   hipStream_t s = nullptr;
@@ -48,6 +58,7 @@ struct sso_problem {
   FusedDesc<double> fdesc{};
   MixedState ms;                // mixed precision begun with sso_solve_begin
   hipEvent_t ev[6] = {};
+  int device = 0;               // the device current at creation (holds the problem's memory)
 };
 
 struct sso_batch {
@@ -127,6 +138,7 @@ void free_problem(sso_problem* p) {
 int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
                 sso_problem* p) {
   p->s = stream;
+  TRY_HIP(hipGetDevice(&p->device));
   p->opt = opts ? *opts : default_options();
   Mesh& m = p->m;
   m.n_nodes = mesh->n_nodes;
@@ -337,6 +349,71 @@ double solve_bytes(const sso_problem* p, int iters, int outer) {
   // inner FP32 iterations + one FP64 residual SpMV (K, x, b read; r written) per outer step
   double resid = 292.0 * nb + 4.0 * (nn + 1) + 3.0 * 8.0 * 6.0 * nn;
   return iters * pcg_bytes_per_iteration(nn, nb, true) + (outer + 1) * resid;
+}
+
+// ---- penalised volume objective (Sec. 3.3): shared by the allocating and static-scratch forms
+
+constexpr int SIZE_XWG = 1024;   // workgroups (partials) of the size-objective reduction
+
+bool size_args_ok(const sso_problem* p, double eps1, double u_max, double t_min,
+                  const double* out_host, const double* dg_dxyz) {
+  return p && p->solved && out_host && dg_dxyz && eps1 >= 0.0 && std::isfinite(eps1) &&
+         u_max > 0.0 && std::isfinite(u_max) && t_min > 0.0 && std::isfinite(t_min);
+}
+
+// g = (1 + eps1 c) W and its gradient with the scratch arrays xpart [2 SIZE_XWG], gw
+// [14 n_quads] and wv [n_quads] given.
+int size_objective_impl(sso_problem* p, double eps1, double u_max, double t_min,
+                        double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats,
+                        double* xpart, double* gw, double* wv) {
+  hipStream_t s = p->s;
+  const Mesh& m = p->m;
+  TRY_HIP(hipEventRecord(p->ev[4], s));
+  // volume terms, then dc/du (masked) with the sums c and W in d_scal[2..3]
+  TRY_HIP(launch_volume_terms(m, t_min, gw, wv, s));
+  TRY_HIP(launch_size_terms(m, p->u, u_max, wv, p->rhs, xpart, SIZE_XWG, p->d_scal + 2, s));
+  int iters = 0, outer = 0;
+  const int status = run_solver(p, p->rhs, p->lam, &iters, &outer);
+  if (status != SSO_OK && status != SSO_ENOTCONV) return status;
+  TRY_HIP(launch_adjoint_terms(m, p->pat, p->u, p->lam, 1.0, 0.0, p->gbeam, p->gquad, s));
+  TRY_HIP(launch_size_combine(m, eps1, p->d_scal + 2, gw, p->gbeam, p->gquad, s));
+  TRY_HIP(launch_gather(m, p->pat, p->gbeam, p->gquad, dg_dxyz, dg_dt, nullptr, s));
+  TRY_HIP(hipEventRecord(p->ev[5], s));
+  TRY_HIP(hipMemcpyAsync(p->h_scal + 2, p->d_scal + 2, 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  const double c = p->h_scal[2], W = p->h_scal[3];
+  out_host[0] = (1.0 + eps1 * c) * W;
+  out_host[1] = c;
+  out_host[2] = W;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
+  }
+  return status;
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double* scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_address(int device, double** out) {
+  if (device < 0 || device >= MAX_DEVICES) return SSO_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[device]) {
+    int cur = 0;
+    TRY_HIP(hipGetDevice(&cur));
+    if (cur != device) TRY_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return map_hip(e);
+    if (!ptr) return SSO_EHIP;
+    scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = scratch_ptr[device];
+  return SSO_OK;
 }
 
 }  // namespace
@@ -568,42 +645,14 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
 
 int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
                        double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats) {
-  if (!p || !p->solved || !out_host || !dg_dxyz) return SSO_EINVAL;
-  if (!(eps1 >= 0.0) || !std::isfinite(eps1) || !(u_max > 0.0) || !std::isfinite(u_max) ||
-      !(t_min > 0.0) || !std::isfinite(t_min))
-    return SSO_EINVAL;
-  hipStream_t s = p->s;
-  const Mesh& m = p->m;
-  constexpr int XWG = 1024;
+  if (!size_args_ok(p, eps1, u_max, t_min, out_host, dg_dxyz)) return SSO_EINVAL;
   if (!p->xpart) {
-    TRY_HIP(dev_alloc(&p->xpart, 2 * XWG, s));
-    TRY_HIP(dev_alloc(&p->gw, 14 * (int64_t)m.n_quads, s));
-    TRY_HIP(dev_alloc(&p->wv, m.n_quads, s));
+    TRY_HIP(dev_alloc(&p->xpart, 2 * SIZE_XWG, p->s));
+    TRY_HIP(dev_alloc(&p->gw, 14 * (int64_t)p->m.n_quads, p->s));
+    TRY_HIP(dev_alloc(&p->wv, p->m.n_quads, p->s));
   }
-  TRY_HIP(hipEventRecord(p->ev[4], s));
-  // volume terms, then dc/du (masked) with the sums c and W in d_scal[2..3]
-  TRY_HIP(launch_volume_terms(m, t_min, p->gw, p->wv, s));
-  TRY_HIP(launch_size_terms(m, p->u, u_max, p->wv, p->rhs, p->xpart, XWG, p->d_scal + 2, s));
-  int iters = 0, outer = 0;
-  const int status = run_solver(p, p->rhs, p->lam, &iters, &outer);
-  if (status != SSO_OK && status != SSO_ENOTCONV) return status;
-  TRY_HIP(launch_adjoint_terms(m, p->pat, p->u, p->lam, 1.0, 0.0, p->gbeam, p->gquad, s));
-  TRY_HIP(launch_size_combine(m, eps1, p->d_scal + 2, p->gw, p->gbeam, p->gquad, s));
-  TRY_HIP(launch_gather(m, p->pat, p->gbeam, p->gquad, dg_dxyz, dg_dt, nullptr, s));
-  TRY_HIP(hipEventRecord(p->ev[5], s));
-  TRY_HIP(hipMemcpyAsync(p->h_scal + 2, p->d_scal + 2, 2 * sizeof(double),
-                         hipMemcpyDeviceToHost, s));
-  TRY_HIP(hipStreamSynchronize(s));
-  const double c = p->h_scal[2], W = p->h_scal[3];
-  out_host[0] = (1.0 + eps1 * c) * W;
-  out_host[1] = c;
-  out_host[2] = W;
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->iters = iters;
-    stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
-  }
-  return status;
+  return size_objective_impl(p, eps1, u_max, t_min, out_host, dg_dxyz, dg_dt, stats,
+                             p->xpart, p->gw, p->wv);
 }
 
 int sso_size_penalty_update(double eps1, int violated, double kappa, double* eps1_next) {
@@ -612,6 +661,23 @@ int sso_size_penalty_update(double eps1, int violated, double kappa, double* eps
     return SSO_EINVAL;
   *eps1_next = violated ? eps1 * kappa : eps1 / kappa;
   return SSO_OK;
+}
+
+int sso_size_objective_noalloc(sso_problem* p, double eps1, double u_max, double t_min,
+                               double* out_host, double* dg_dxyz, double* dg_dt,
+                               sso_stats* stats) {
+  if (p && p->m.n_quads > SSO_NOALLOC_MAX_QUADS) return SSO_ESIZE;
+  if (!size_args_ok(p, eps1, u_max, t_min, out_host, dg_dxyz)) return SSO_EINVAL;
+  double* base = nullptr;
+  const int st = scratch_address(p->device, &base);
+  if (st != SSO_OK) return st;
+  // partials, then the per-quad volume terms and shares; every entry is written before it is
+  // read, so nothing needs clearing between calls
+  double* xpart = base;
+  double* gw = xpart + 2 * SIZE_XWG;
+  double* wv = gw + 14 * (int64_t)p->m.n_quads;
+  return size_objective_impl(p, eps1, u_max, t_min, out_host, dg_dxyz, dg_dt, stats, xpart, gw,
+                             wv);
 }
 
 int sso_hat_filter(sso_problem* p, int32_t n, const int32_t* nodes, const double* g,
@@ -675,6 +741,7 @@ const char* sso_strerror(int status) {
     case SSO_EHIP: return "HIP runtime error";
     case SSO_ENOTCONV: return "PCG did not reach the residual target within max_it";
     case SSO_EBREAKDOWN: return "PCG breakdown: stiffness not positive definite";
+    case SSO_ESIZE: return "problem larger than the static scratch of the no-allocation entry point";
     default: return "unknown status";
   }
 }
