@@ -1,17 +1,27 @@
 """Benchmark: forward + adjoint structural analyses per second on one MI355X.
 
-One step = one forward analysis (element stiffness, loads, assembly, masking, block-Jacobi, PCG
-to 1e-8 relative residual) + the objective + its adjoint gradient with respect to every nodal
-coordinate, every shell thickness and every stiffness scale, for the 60 x 60 continuous shell
-(22,326 DOF, compliance; the adjoint of compliance is lambda = u, no second solve).  Inputs are
-resident in HBM before the timed region.  Prints one JSON line.
+Headline (the default): the mixed-size served stream.  2,000 forward + adjoint requests, each a
+grid-shell (n x n nodes, n ~ U{8..60}) or a quad shell (m x m elements, m ~ U{10..120}) with its
+own seed (``meshgen.served_request``), compliance, rtol 1e-8, served by continuous batching
+(``serve.BatchedServer``: admission by slots and device-memory footprint, all requests in flight
+iterating in shared multi-problem launches).  A "step" is one request.  The headline runs in
+mixed precision (FP32 inner PCG solves inside an FP64 flexible CG) with plain FP64 beside it:
 
-The dominant kernel of the PCG -- k_cg1_iter1, one whole single-reduction iteration (the
-default up to 20,000 nodes), or k_spmv_dir, the direction + SpMV kernel of the standard
-recurrences -- is timed live
-with HIP events on the problem's stream for every n-th launch; its roofline uses the algorithmic
-bytes of one launch.  The CPU baseline
-is the FP64 oracle timed on the host on one forward + adjoint of the same workload.
+* value (solves/s) and DOF/s: all requests queued at once (closed loop), wall time of the whole
+  stream -- the throughput the server sustains on this mix of sizes;
+* p50/p99 latency (arrival to result): the same 2,000 requests arriving as a Poisson process at
+  0.8 times the smaller of the two precisions' closed-loop capacities;
+* per request, the error of the mixed result against the FP64 result (g, dg/dxyz, dg/dt).
+
+Inputs are resident in HBM before each request's timed work starts: a request's mesh is uploaded
+when it is admitted, which is part of serving it.
+
+Legs: the 300 x 300 shell (543,606 DOF) at rtol 1e-10 in FP64 and mixed precision, whose PCG
+iteration (k_spmv_dir + k_update, timed live with HIP events on the problem's stream) gives the
+roofline; the 60 x 60 shell; a linear objective (second PCG for the adjoint); the network batch
+(256 variants of the 80 x 80 shell through the MLP); the paper's arch-bridge rows; the measured
+HBM and FP64 ceilings; the oracle timed on the host on a sample of the stream's requests.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -31,13 +41,12 @@ import meshgen  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters
-# (KiB per dispatch, mean over working launches) scaled by what they read for a plain 256 MiB
-# copy (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel code they were taken on: an
-# entry is removed when that kernel changes.
+# HBM bytes per PCG iteration, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters (KiB per
+# dispatch, mean over working launches, summed over the iteration's kernels) scaled by what they
+# read for a plain copy of known size (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel
+# code they were taken on: an entry is removed when one of its kernels changes.
 MEASURED_TRAFFIC = {
     ("shell60", "fp64", "k_cg1_iter1"): (6570.6 * 2.000 + 954.4 * 1.000) * 1024,
-    ("shell300", "fp64", "k_spmv_dir"): (131735.3 * 2.000 + 8554.7 * 1.000) * 1024,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
@@ -59,133 +68,360 @@ SEEDED = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="shell60", choices=list(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps: requests of the stream (default 2000), or solves of a "
+                         "single-problem workload (default 20)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 32 requests of other seeds, or 3 solves)")
+    ap.add_argument("--workload", default="stream", choices=["stream", *WORKLOADS])
     ap.add_argument("--objective", default="compliance",
                     choices=["compliance", "strain_energy", "linear"])
-    ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--rtol", type=float, default=None,
+                    help="relative residual target (default 1e-8; 1e-10 for shell300)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="headline precision (default: mixed for the stream, fp64 otherwise)")
     ap.add_argument("--inner-max-it", type=int, default=0,
                     help="mixed precision: iteration cap of each FP32 inner solve (0 = none)")
     ap.add_argument("--refine-steps", type=int, default=20,
                     help="mixed precision: outer (FP64 flexible CG) step limit")
     ap.add_argument("--solver", default="auto", choices=["auto", "standard", "fused"])
+    ap.add_argument("--slots", type=int, default=32, help="stream: requests in flight at most")
+    ap.add_argument("--chunk", type=int, default=32,
+                    help="stream: iterations per multi-problem launch sequence between polls")
     ap.add_argument("--profile-every", type=int, default=64,
-                    help="time every n-th iteration kernel with HIP events "
+                    help="time every n-th PCG iteration with HIP events "
                          "(16: ~5 %% overhead, 64: ~1.5 %%, 0: off)")
+    ap.add_argument("--legs", default="large,shell60,general,network,arch,ceilings",
+                    help="comma-separated extra measurements ('' = none): large (300x300 shell, "
+                         "FP64 + mixed, rtol 1e-10, the roofline), shell60, general (linear "
+                         "objective), batch (16 60x60 shells in one launch), network (the MLP "
+                         "batch), arch (the paper's arch-bridge rows), ceilings")
+    ap.add_argument("--network-variants", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="requests of the mixed-size served stream (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=32)
-    ap.add_argument("--batch", type=int, default=16,
-                    help="also time this many problems of the workload (seeds 1..n) advancing "
-                         "together in multi-problem launches (0: skip)")
-    ap.add_argument("--general-steps", type=int, default=5,
-                    help="also time this many steps with a linear objective (second PCG "
-                         "for the adjoint; 0: skip)")
-    ap.add_argument("--shellnet", type=int, default=0,
-                    help="also time one loss + backward of the network-driven batch of this "
-                         "many 80 x 80 shells (0: skip)")
     ap.add_argument("--arch", default="2,6,10,20,30,80",
-                    help="elements per span of the arch-bridge rows to time ('' = none)")
+                    help="elements per span of the arch-bridge rows to time")
     ap.add_argument("--copy-mib", type=int, default=0,
-                    help="before the workload, copy a float64 tensor of this many MiB 3 times "
-                         "(a plain copy kernel of known size for scaling HBM counters)")
-    return ap.parse_args()
-
-
-def _oracle_rate(mesh, objective, budget_s, threads):
-    import numpy as np
-    import oracle
-    from threadpoolctl import threadpool_limits
-    a = None
-    if objective == "linear":
-        a = np.zeros(mesh.n_dof)
-        a[6 * (mesh.n_nodes // 2) + 2] = 1.0
-    n, t0 = 0, time.perf_counter()
-    with threadpool_limits(limits=threads):
-        while True:
-            oracle.analyze(mesh, objective, a=a)
-            n += 1
-            log(f"cpu baseline ({threads} BLAS threads): oracle analysis {n} done")
-            el = time.perf_counter() - t0
-            if el >= budget_s or el * (n + 1) / n > 1.5 * budget_s:
-                break
-    return n, el
-
-
-def cpu_baseline(mesh, objective, budget_s):
-    """The oracle as it stands, one forward + adjoint at a time, for about budget_s seconds with
-    one BLAS thread (the reported value), then for about budget_s / 2 seconds with every host
-    core given to BLAS (the banded Cholesky is the threaded part), and one SciPy sparse direct
-    solve of the same system (SuperLU) for context."""
-    import numpy as np
-    import scipy.sparse.linalg as sla
-    from oracle import assembly, solve
-    n, el = _oracle_rate(mesh, objective, budget_s, 1)
-    rate = n / el
-    # the host cores this process may use (the thread limit of the environment when it sets one)
-    all_cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
-    n2, el2 = _oracle_rate(mesh, objective, budget_s / 2, all_cores)
-    K = assembly.assemble(mesh)
-    f = assembly.load_vector(mesh)
-    F = solve.free_dofs(mesh)
-    Kff = K.tocsc()[F][:, F]
-    t0 = time.perf_counter()
-    sla.spsolve(Kff, np.asarray(f)[F])
-    t_sp = time.perf_counter() - t0
-    log(f"cpu baseline: SciPy spsolve {t_sp:.2f} s")
-    return {"value": rate, "unit": "solves/s", "dof_per_s": rate * mesh.n_dof, "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n} forward+adjoint analyses (pattern, assembly, banded Cholesky, "
-                      f"complex-step adjoint) of the benchmark workload in {el:.1f} s, "
-                      f"BLAS threads 1, host cpus {all_cores}",
-            "all_cores": {"value": n2 / el2, "unit": "solves/s", "cores": all_cores,
-                          "sample": f"{n2} analyses in {el2:.1f} s"},
-            "scipy_spsolve_s": t_sp}
+                    help="before the workload, copy a float64 buffer of this many MiB 3 times "
+                         "with the library's copy kernel (a known size for scaling HBM counters)")
+    args = ap.parse_args()
+    stream = args.workload == "stream"
+    if args.steps is None:
+        args.steps = 2000 if stream else 20
+    if args.warmup is None:
+        args.warmup = 32 if stream else 3
+    if args.precision is None:
+        args.precision = "mixed" if stream else "fp64"
+    if args.rtol is None:
+        args.rtol = 1e-10 if args.workload == "shell300" else 1e-8
+    return args
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serve_bench(n, slots, precision, solver, inner_max_it=0, refine_steps=20):
-    """Mixed-size served stream: grid-shells (n x n nodes, n ~ U{8..60}) and shells (m x m quads,
-    m ~ U{10..120}) with per-request seeds, rtol 1e-8 on the FP64 true residual, all requests in
-    flight iterating in shared multi-problem launches; FP64 or mixed precision (FP32 inner
-    iterations).  A closed-loop pass measures the capacity; the timed pass uses Poisson arrivals
-    at 0.8 x capacity."""
+# ---- CPU baseline: the oracle on the host ---------------------------------------------------
+
+def _threads(n):
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(limits=n)
+
+
+def _oracle_analyses(meshes, objective, budget_s, threads):
+    """Forward + adjoint analyses of meshes[0], meshes[1], ... by the oracle until about
+    budget_s seconds have passed (at least one); returns (count, DOF, seconds)."""
+    import oracle
+    n, dof, t0 = 0, 0, time.perf_counter()
+    with _threads(threads):
+        for mesh in meshes:
+            a = None
+            if objective == "linear":
+                a = np.zeros(mesh.n_dof)
+                a[6 * (mesh.n_nodes // 2) + 2] = 1.0
+            oracle.analyze(mesh, objective, a=a)
+            n += 1
+            dof += mesh.n_dof
+            el = time.perf_counter() - t0
+            log(f"cpu baseline ({threads} BLAS threads): {n} analyses, {el:.1f} s")
+            if el >= budget_s or el * (n + 1) / n > 1.5 * budget_s:
+                break
+    return n, dof, time.perf_counter() - t0
+
+
+def cpu_baseline(meshes, objective, budget_s, what):
+    """The oracle as it stands on a bounded sample: forward + adjoint analyses of `meshes` in
+    order for about budget_s seconds with one BLAS thread (the reported value), then about
+    budget_s / 2 seconds with every host core given to BLAS (the banded Cholesky is the threaded
+    part)."""
+    all_cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
+    n, dof, el = _oracle_analyses(meshes, objective, budget_s, 1)
+    n2, dof2, el2 = _oracle_analyses(meshes, objective, budget_s / 2, all_cores)
+    return {"value": n / el, "unit": "solves/s", "dof_per_s": dof / el, "cores": 1,
+            "kind": "oracle",
+            "sample": f"the first {n} {what} ({dof} DOF in all), one forward + adjoint "
+                      f"analysis each (pattern, assembly, banded Cholesky with long-double "
+                      f"refinement, complex-step adjoint) in {el:.1f} s, 1 BLAS thread; host "
+                      f"cpus {all_cores}",
+            "all_cores": {"value": n2 / el2, "unit": "solves/s", "dof_per_s": dof2 / el2,
+                          "cores": all_cores, "sample": f"{n2} analyses in {el2:.1f} s"}}
+
+
+# ---- the served stream ----------------------------------------------------------------------
+
+PREC_NAMES = ("mixed", "fp64")
+
+
+def _stream_options(sso, precision, rtol, args):
+    return sso.Options(rtol=rtol, max_it=400000,
+                       precision=sso.PREC_MIXED if precision == "mixed" else sso.PREC_FP64,
+                       inner_max_it=args.inner_max_it if precision == "mixed" else 0,
+                       refine_steps=args.refine_steps)
+
+
+def _size_buckets(results, meshes):
+    """p50/p99 latency per DOF quartile of the stream (Poisson pass)."""
+    dof = np.array([meshes[r.rid].n_dof for r in results])
+    lat = np.array([r.latency for r in results]) * 1000.0
+    edges = np.percentile(dof, [0, 25, 50, 75, 100])
+    out = []
+    for k in range(4):
+        sel = (dof >= edges[k]) & ((dof <= edges[k + 1]) if k == 3 else (dof < edges[k + 1]))
+        if np.any(sel):
+            out.append({"dof_range": [int(edges[k]), int(edges[k + 1])], "n": int(sel.sum()),
+                        "p50_ms": float(np.percentile(lat[sel], 50)),
+                        "p99_ms": float(np.percentile(lat[sel], 99))})
+    return out
+
+
+def stream_headline(args):
+    """The served stream: closed-loop capacity, then Poisson arrivals, in both precisions."""
     import paper_2407_20026_amd as sso
-    from paper_2407_20026_amd.serve import BatchedServer, Request, poisson_arrivals
+    from paper_2407_20026_amd.serve import (BatchedServer, Request, errors_against,
+                                            poisson_arrivals)
+    n = args.steps
     meshes = [meshgen.served_request(i) for i in range(n)]
-    # multi-problem launches take the standard recurrences under AUTO; mixed precision may cap
-    # each FP32 inner solve
-    opts = sso.Options(rtol=1e-8, precision=sso.PREC_MIXED if precision == "mixed" else
-                       sso.PREC_FP64,
-                       solver=solver if precision == "fp64" else sso.SOLVER_AUTO,
-                       inner_max_it=inner_max_it if precision == "mixed" else 0,
-                       refine_steps=refine_steps)
-    srv = BatchedServer(slots=slots, options=opts)
-    n_cl = min(n, 64)
-    cl = srv.run([Request(i, meshes[i], 0.0) for i in range(n_cl)])
-    log(f"serving {precision} closed loop: {cl.solves_per_s:.1f} solves/s")
-    lam = 0.8 * cl.solves_per_s
-    t = poisson_arrivals(n, lam, seed=3)
-    st = srv.run([Request(i, meshes[i], float(t[i])) for i in range(n)])
-    log(f"serving {precision} Poisson stream: {st.solves_per_s:.1f} solves/s "
-        f"p99 {st.p99_ms:.1f} ms")
-    return {"requests": st.n, "slots": slots, "precision": precision, "rtol": 1e-8,
-            "closed_loop_solves_per_s": cl.solves_per_s, "arrival_rate_per_s": lam,
-            "solves_per_s": st.solves_per_s, "dof_per_s": st.dof_per_s,
-            "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_queue_ms": st.mean_queue_ms,
-            "peak_inflight": st.peak_inflight,
-            "not_converged": st.not_converged + cl.not_converged,
-            "max_rel_residual": max(st.max_rel_residual, cl.max_rel_residual),
-            "mean_dof": float(np.mean([m.n_dof for m in meshes])),
-            "closed_loop_phase_s": {k: round(v, 4) for k, v in cl.host_s.items()},
-            "phase_s": {k: round(v, 4) for k, v in st.host_s.items()}}
+    warm = [meshgen.served_request(i, base_seed=2 * 10**6) for i in range(args.warmup)]
+    log(f"stream: {n} requests, {sum(m.n_dof for m in meshes)} DOF in all")
+    closed, poisson, servers = {}, {}, {}
+    for prec in PREC_NAMES:
+        srv = BatchedServer(slots=args.slots, options=_stream_options(sso, prec, args.rtol, args),
+                            chunk=args.chunk)
+        servers[prec] = srv
+        if warm:
+            srv.run([Request(i, m, 0.0) for i, m in enumerate(warm)])
+        torch.cuda.synchronize()
+        st = srv.run([Request(i, m, 0.0) for i, m in enumerate(meshes)])
+        closed[prec] = st
+        log(f"stream {prec} closed loop: {st.solves_per_s:.1f} solves/s, "
+            f"{st.dof_per_s / 1e6:.2f} M DOF/s, {st.wall_s:.1f} s")
+    lam = 0.8 * min(closed[p].solves_per_s for p in PREC_NAMES)
+    t_arr = poisson_arrivals(n, lam, seed=3)
+    for prec in PREC_NAMES:
+        st = servers[prec].run([Request(i, m, float(t_arr[i])) for i, m in enumerate(meshes)])
+        poisson[prec] = st
+        log(f"stream {prec} Poisson at {lam:.1f}/s: {st.solves_per_s:.1f} solves/s, "
+            f"p50 {st.p50_ms:.1f} ms, p99 {st.p99_ms:.1f} ms")
+    errs = errors_against(closed["mixed"].results, closed["fp64"].results)
+
+    def summary(key):
+        v = np.array([e.get(key, 0.0) for e in errs])
+        return {"max": float(v.max()), "p99": float(np.percentile(v, 99)),
+                "p50": float(np.percentile(v, 50))}
+
+    def leg(prec):
+        c, q = closed[prec], poisson[prec]
+        return {"closed_loop": {"solves_per_s": c.solves_per_s, "dof_per_s": c.dof_per_s,
+                                "wall_s": c.wall_s, "peak_inflight": c.peak_inflight,
+                                "phase_s": {k: round(v, 3) for k, v in c.host_s.items()}},
+                "poisson": {"arrival_rate_per_s": lam, "solves_per_s": q.solves_per_s,
+                            "dof_per_s": q.dof_per_s, "p50_ms": q.p50_ms, "p99_ms": q.p99_ms,
+                            "mean_queue_ms": q.mean_queue_ms, "peak_inflight": q.peak_inflight,
+                            "by_size": _size_buckets(q.results, meshes)},
+                "not_converged": c.not_converged + q.not_converged,
+                "max_rel_residual": max(c.max_rel_residual, q.max_rel_residual),
+                "iters_median": int(np.median([r.iters for r in c.results]))}
+
+    head = args.precision
+    c, q = closed[head], poisson[head]
+    out = {
+        "value": c.solves_per_s,
+        "dof_per_s": c.dof_per_s,
+        "ms_per_step": 1000.0 * c.wall_s / n,
+        "p50_ms": q.p50_ms,
+        "p99_ms": q.p99_ms,
+        "dtype": "f32 inner PCG / f64 flexible CG" if head == "mixed" else "f64",
+        "config": {
+            "workload": (f"served stream: {n} forward+adjoint requests (grid-shells n~U{{8..60}}, "
+                         f"shells m~U{{10..120}}, per-request seeds 10^6+i), compliance, "
+                         f"rtol {args.rtol:g}, {head} precision; value = closed-loop solves/s, "
+                         f"p50/p99 from arrival under Poisson arrivals at {lam:.1f}/s"),
+            "requests": n, "mean_dof": float(np.mean([m.n_dof for m in meshes])),
+            "slots": args.slots, "chunk": args.chunk, "rtol": args.rtol, "precision": head,
+            "arrival_rate_per_s": lam,
+            "status": "converged" if c.not_converged + q.not_converged == 0 else
+                      f"{c.not_converged + q.not_converged} requests stopped above rtol",
+        },
+        "stream": {p: leg(p) for p in PREC_NAMES},
+        "mixed_vs_fp64": {"requests": len(errs), "g_rel": summary("g_rel"),
+                          "dg_dxyz_rel_inf": summary("dg_dxyz_rel_inf"),
+                          "dg_dt_rel_inf": summary("dg_dt_rel_inf")},
+    }
+    return out, meshes
+
+
+# ---- one problem, repeated ------------------------------------------------------------------
+
+def problem_run(mesh, opts, steps, warmup, objective="compliance", with_grad=True):
+    """Forward + objective + adjoint of one problem, `steps` times after `warmup`; returns the
+    timings, PCG statistics, live iteration timing and the last u and gradients."""
+    import paper_2407_20026_amd as sso
+    a = None
+    if objective == "linear":
+        a = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+        a[6 * (mesh.n_nodes // 2) + 2] = 1.0
+    rec = dict(it_us=[], it_n=[], iters=[], resid=[], adj=[], outer=[], status=[], lat=[])
+    with sso.Problem(mesh, opts) as prob:
+        u_out = torch.empty((mesh.n_nodes, 6), dtype=torch.float64, device="cuda")
+        last = {}
+
+        def step(keep):
+            _, st = prob.solve(u_out, check=False)
+            if prob.last_status not in (sso.SSO_OK, sso.SSO_ENOTCONV):
+                raise sso.SSOError(prob.last_status, "sso_solve")
+            prob.objective(objective, a)
+            g = prob.adjoint(objective, dg_du=a) if with_grad else None
+            if keep:
+                rec["iters"].append(st["iters"])
+                rec["outer"].append(st["refine_steps"])
+                rec["resid"].append(st["rel_residual"])
+                rec["status"].append(prob.last_status)
+                rec["adj"].append(g["stats"]["iters"] if g else 0)
+                if st["spmv_samples"]:
+                    rec["it_us"].append(st["spmv_us"] * st["spmv_samples"])
+                    rec["it_n"].append(st["spmv_samples"])
+            last.update(st=st, g=g)
+
+        for _ in range(warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            step(True)
+            rec["lat"].append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n_blocks = prob.n_blocks
+        u = u_out.clone()
+    st = last["st"]
+    it_us = sum(rec["it_us"]) / max(1, sum(rec["it_n"]))
+    return {"wall_s": el, "steps": steps, "solves_per_s": steps / el,
+            "dof_per_s": steps * mesh.n_dof / el, "ms_per_step": 1000.0 * el / steps,
+            "p50_ms": 1000.0 * float(np.percentile(rec["lat"], 50)),
+            "p99_ms": 1000.0 * float(np.percentile(rec["lat"], 99)),
+            "pcg_iters": int(np.median(rec["iters"])),
+            "adjoint_pcg_iters": int(np.median(rec["adj"])),
+            "outer_steps": int(np.median(rec["outer"])),
+            "rel_residual": float(np.max(rec["resid"])),
+            "status": "converged" if all(v == sso.SSO_OK for v in rec["status"]) else
+                      "stopped above rtol",
+            "solver": "fused single-reduction" if st["solver"] == sso.SOLVER_FUSED else
+                      "standard",
+            "n_blocks": n_blocks, "n_nodes": mesh.n_nodes,
+            "iteration": {"kernels": "k_cg1_iter1" if st["solver"] == sso.SOLVER_FUSED else
+                          "k_spmv_dir + k_update", "bytes": st["spmv_bytes"],
+                          "avg_us": it_us, "samples": int(sum(rec["it_n"]))},
+            "_u": u, "_g": last["g"]}
+
+
+def algorithmic_iteration_bytes(n_nodes, n_blocks, precision):
+    """Algorithmic HBM bytes of one standard PCG iteration by the scope table's accounting:
+    the BSR values, block columns and row pointers once; twelve vector passes (p read and Ap
+    written by the product; x, r, p, Ap read and x, r, z written by the update; z and p read
+    and p written for the direction); the 6 x 6 block-Jacobi inverse of every node (36 values).
+    The library moves fewer than that (the direction is formed inside the product, the inverse
+    is stored packed, 21 values), so this is an upper bound of what the kernels need."""
+    v = 4.0 if precision == "mixed" else 8.0
+    n_dof = 6.0 * n_nodes
+    return (36.0 * v + 4.0) * n_blocks + 4.0 * (n_nodes + 1) + 12.0 * v * n_dof + \
+        36.0 * v * n_nodes
+
+
+def roofline_of(run, workload, precision, ceilings=None):
+    it = run["iteration"]
+    if it["kernels"] == "k_spmv_dir + k_update":
+        it = dict(it, library_bytes=it["bytes"],
+                  bytes=algorithmic_iteration_bytes(run["n_nodes"], run["n_blocks"], precision))
+    achieved = it["bytes"] / (it["avg_us"] * 1e-6) / 1e9 if it["avg_us"] > 0 else 0.0
+    out = {"bound": "hbm", "kernel": it["kernels"], "workload": workload,
+           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS,
+           "traffic": MEASURED_TRAFFIC.get((workload, precision, it["kernels"])),
+           "bytes_per_launch": it["bytes"], "avg_launch_us": it["avg_us"],
+           "samples": it["samples"]}
+    if "library_bytes" in it:
+        out["library_bytes_per_launch"] = it["library_bytes"]
+    if ceilings:
+        out["measured_read_gbs"] = ceilings["read_gbs"]
+        out["measured_copy_gbs"] = ceilings["copy_gbs"]
+        out["frac_of_measured_read"] = achieved / ceilings["read_gbs"]
+    return out
+
+
+def _public(run):
+    return {k: v for k, v in run.items() if not k.startswith("_")}
+
+
+def large_leg(args):
+    """The 300 x 300 shell at rtol 1e-10: FP64 (whose iteration gives the roofline) and mixed
+    precision, with the mixed result's error against the FP64 one."""
+    import paper_2407_20026_amd as sso
+    mesh = meshgen.shell_300()
+    out = {}
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        opts = sso.Options(rtol=1e-10, max_it=400000, profile_every=args.profile_every,
+                           precision=sso.PREC_MIXED if prec == "mixed" else sso.PREC_FP64,
+                           refine_steps=20000, inner_max_it=20 if prec == "mixed" else 0)
+        runs[prec] = problem_run(mesh, opts, steps=2, warmup=1)
+        log(f"300x300 shell {prec}: {runs[prec]['ms_per_step']:.1f} ms per forward + adjoint, "
+            f"iteration {runs[prec]['iteration']['avg_us']:.2f} us")
+        out[prec] = _public(runs[prec])
+    u64, umx = runs["fp64"]["_u"], runs["mixed"]["_u"]
+    g64, gmx = runs["fp64"]["_g"], runs["mixed"]["_g"]
+
+    def rel_inf(x, y):
+        return float((x - y).abs().max() / y.abs().max())
+    out["mixed"]["vs_fp64"] = {"u_rel_2norm": float((umx - u64).norm() / u64.norm()),
+                               "dg_dxyz_rel_inf": rel_inf(gmx["dg_dxyz"], g64["dg_dxyz"]),
+                               "dg_dt_rel_inf": rel_inf(gmx["dg_dt"], g64["dg_dt"])}
+    out["workload"] = "300x300 continuous shell, 543,606 DOF, compliance, rtol 1e-10, seed 2"
+    out["mixed"]["inner_max_it"] = 20
+    return out, runs["fp64"]
+
+
+def shell60_leg(args):
+    import paper_2407_20026_amd as sso
+    mesh = meshgen.shell_60()
+    opts = sso.Options(rtol=1e-8, max_it=400000, profile_every=args.profile_every)
+    run = problem_run(mesh, opts, steps=20, warmup=3)
+    log(f"60x60 shell: {run['ms_per_step']:.2f} ms per forward + adjoint")
+    out = _public(run)
+    out["workload"] = "60x60 continuous shell, 22,326 DOF, FP64, compliance, rtol 1e-8, seed 1"
+    return out, run
+
+
+def general_leg(args):
+    """The 60 x 60 shell with a linear objective g = u_z at the centre node: its adjoint is a
+    second PCG solve (K lambda = a), unlike compliance where lambda = u."""
+    import paper_2407_20026_amd as sso
+    run = problem_run(meshgen.shell_60(), sso.Options(rtol=1e-8, max_it=400000), steps=5,
+                      warmup=1, objective="linear")
+    log(f"general objective: {run['ms_per_step']:.2f} ms per forward + adjoint")
+    return {"objective": "linear (u_z at the centre node)", "workload": "60x60 shell",
+            "solves_per_s": run["solves_per_s"], "ms_per_step": run["ms_per_step"],
+            "pcg_iters": run["pcg_iters"], "adjoint_pcg_iters": run["adjoint_pcg_iters"]}
 
 
 def batch_bench(gen_seed, n_problems, rtol, objective, solver):
@@ -225,33 +461,6 @@ def batch_bench(gen_seed, n_problems, rtol, objective, solver):
     return {"problems": n_problems, "solves_per_s": n_problems / el,
             "dof_per_s": sum(m.n_dof for m in meshes) / el, "wall_ms": 1000 * el,
             "note": "same generator, seeds 1..n; all problems in flight together"}
-
-
-def general_objective_bench(mesh, opts, steps):
-    """The same workload with a linear objective g = u_z at the centre node: its adjoint is a
-    second PCG solve (K lambda = a), unlike compliance where lambda = u."""
-    import torch
-    import paper_2407_20026_amd as sso
-    a = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
-    a[6 * (mesh.n_nodes // 2) + 2] = 1.0
-    adj = []
-    with sso.Problem(mesh, opts) as prob:
-        def step():
-            prob.solve(check=False)
-            if prob.last_status not in (sso.SSO_OK, sso.SSO_ENOTCONV):
-                raise sso.SSOError(prob.last_status, "sso_solve")
-            prob.objective("linear", a)
-            adj.append(prob.adjoint("linear", dg_du=a)["stats"]["iters"])
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-    log(f"general objective: {1000 * el / steps:.2f} ms/step")
-    return {"objective": "linear (u_z at the centre node)", "solves_per_s": steps / el,
-            "ms_per_step": 1000 * el / steps, "adjoint_pcg_iters": int(np.median(adj))}
 
 
 # FEA time of the paper's performance table (seconds, best column: SciPy sparse with GPU
@@ -337,35 +546,11 @@ def shellnet_bench(n_variants, solver, m=80):
 
 
 def copy_calibration(mib):
-    import torch
-    n = mib * (1 << 20) // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    log(f"copy calibration: 3 x {mib} MiB")
-
-
-def measured_copy_bandwidth(mib=1024, reps=10):
-    """HBM bandwidth a plain device copy reaches on this GPU (bytes read + written per second,
-    GB/s), the measured ceiling beside the datasheet peak."""
-    import torch
-    n = mib * (1 << 20) // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    torch.cuda.empty_cache()
-    log(f"measured copy bandwidth: {gbs:.0f} GB/s")
-    return gbs
+    """Three copies of a float64 buffer of `mib` MiB by the library's copy kernel: a plain copy
+    of known size for scaling the HBM counters of a profiled run."""
+    from paper_2407_20026_amd import ceiling
+    ceiling.measure(mib=mib, reps=3)
+    log(f"copy calibration: {mib} MiB")
 
 
 def main():
@@ -375,140 +560,74 @@ def main():
               "(independent problems shard whole across GPUs; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    global torch
     import torch
     import paper_2407_20026_amd as sso
 
-    desc, gen = WORKLOADS[args.workload]
-    mesh = gen()
     torch.cuda.set_device(0)
+    legs = {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib)
-    a = None
-    if args.objective == "linear":
-        a = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
-        a[6 * (mesh.n_nodes // 2) + 2] = 1.0
-    prec = sso.PREC_MIXED if args.precision == "mixed" else sso.PREC_FP64
-    solver = {"auto": sso.SOLVER_AUTO, "standard": sso.SOLVER_STANDARD,
-              "fused": sso.SOLVER_FUSED}[args.solver]
-    opts = sso.Options(precision=prec, rtol=args.rtol, max_it=400000,
-                       profile_every=args.profile_every, solver=solver,
-                       refine_steps=args.refine_steps, inner_max_it=args.inner_max_it)
-    prob = sso.Problem(mesh, opts)
-    u_out = torch.empty((mesh.n_nodes, 6), dtype=torch.float64, device="cuda")
+    ceilings = None
+    if "ceilings" in legs:
+        from paper_2407_20026_amd import ceiling
+        ceilings = ceiling.measure()
+        log(f"ceilings: read {ceilings['read_gbs']:.0f} GB/s, copy {ceilings['copy_gbs']:.0f} "
+            f"GB/s, FP64 FMA {ceilings['fp64_fma_tflops']:.1f} TFLOP/s")
 
-    spmv_us, spmv_n, iters, resid, adj_iters, outer = [], [], [], [], [], []
-    last_g = []
-
-    statuses = []
-
-    def step():
-        _, st = prob.solve(u_out, check=False)
-        if prob.last_status not in (sso.SSO_OK, sso.SSO_ENOTCONV):
-            raise sso.SSOError(prob.last_status, "sso_solve")
-        statuses.append(prob.last_status)
-        prob.objective(args.objective, a) if args.objective == "linear" else \
-            prob.objective(args.objective)
-        g = prob.adjoint(args.objective, dg_du=a)
-        last_g[:] = [g]
-        iters.append(st["iters"])
-        outer.append(st["refine_steps"])
-        resid.append(st["rel_residual"])
-        adj_iters.append(g["stats"]["iters"])
-        if st["spmv_samples"]:
-            spmv_us.append(st["spmv_us"] * st["spmv_samples"])
-            spmv_n.append(st["spmv_samples"])
-        return st
-
-    log(f"{desc}: problem created")
-    for _ in range(args.warmup):
-        step()
-    log("warmup done")
-    spmv_us.clear(); spmv_n.clear(); iters.clear(); resid.clear(); adj_iters.clear()
-    statuses.clear()
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        st = step()
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    log(f"timed {args.steps} steps: {1000 * el / args.steps:.2f} ms/step")
-    vs_fp64 = None
-    if args.precision == "mixed":
-        # the error of u and of the gradients against the FP64 path, same mesh and rtol
-        u_mx, g_mx = u_out.clone(), last_g[0]
-        with sso.Problem(mesh, sso.Options(rtol=args.rtol, max_it=400000,
-                                           solver=solver)) as ref:
-            u_ref, _ = ref.solve(check=False)
-            g_ref = ref.adjoint(args.objective, dg_du=a)
-
-        def rel_inf(x, y):
-            return float((x - y).abs().max() / y.abs().max())
-        vs_fp64 = {"u_rel_2norm": float((u_mx - u_ref).norm() / u_ref.norm()),
-                   "dg_dxyz_rel_inf": rel_inf(g_mx["dg_dxyz"], g_ref["dg_dxyz"]),
-                   "dg_dt_rel_inf": rel_inf(g_mx["dg_dt"], g_ref["dg_dt"])
-                   if g_ref["dg_dt"] is not None and g_ref["dg_dt"].numel() else None}
-        log(f"mixed vs FP64: {vs_fp64}")
-    ms = 1000.0 * el / args.steps
-    rate = args.steps / el
-    spmv_bytes = st["spmv_bytes"]
-    spmv_avg_us = sum(spmv_us) / max(1, sum(spmv_n))
-    achieved = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9 if spmv_avg_us > 0 else 0.0
-    kernel = "k_cg1_iter1" if st["solver"] == sso.SOLVER_FUSED else "k_spmv_dir"
-    solver_name = "fused single-reduction" if st["solver"] == sso.SOLVER_FUSED else "standard"
-
-    out = {
-        "metric": METRIC,
-        "value": rate,
-        "unit": "solves/s",
-        "dof_per_s": rate * mesh.n_dof,
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "p50_ms": 1000.0 * float(np.percentile(lat, 50)),
-        "p99_ms": 1000.0 * float(np.percentile(lat, 99)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 inner / f64 flexible CG",
-        "data": "synthetic (seeded generator)",
-        "config": {"workload": desc, "n_dof": mesh.n_dof, "objective": args.objective,
-                   "rtol": args.rtol, "precision": args.precision, "pcg": solver_name,
-                   **({"inner_max_it": args.inner_max_it, "outer_steps": int(np.median(outer)),
-                       "vs_fp64": vs_fp64} if args.precision == "mixed" else {}),
-                   "pcg_iters": int(np.median(iters)),
-                   "adjoint_pcg_iters": int(np.median(adj_iters)),
-                   "rel_residual": float(np.max(resid)), "n_blocks": prob.n_blocks,
-                   "status": "converged" if all(v == sso.SSO_OK for v in statuses) else
-                   "stopped above rtol (FP64 residual floor)"},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision, kernel)),
-                     "bytes_per_launch": spmv_bytes,
-                     "avg_launch_us": spmv_avg_us, "samples": int(sum(spmv_n))},
-    }
-    prob.close()
-    copy_gbs = measured_copy_bandwidth()
-    out["roofline"]["measured_copy_gbs"] = copy_gbs
-    out["roofline"]["frac_of_measured"] = achieved / copy_gbs
-    if args.objective != "linear" and args.general_steps > 0:
-        out["general_objective"] = general_objective_bench(mesh, opts, args.general_steps)
-    if args.batch > 0 and args.workload in SEEDED and args.objective != "linear":
-        out["batched"] = batch_bench(SEEDED[args.workload], args.batch, args.rtol,
-                                     args.objective, solver)
-    if args.shellnet > 0:
-        out["shellnet"] = shellnet_bench(args.shellnet, solver)
-    if args.serve_requests > 0:
-        out["serving"] = {prec: serve_bench(args.serve_requests, args.serve_slots, prec, solver,
-                                            args.inner_max_it, args.refine_steps)
-                          for prec in ("fp64", "mixed")}
-    if args.arch:
+    out = {"metric": METRIC, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic (seeded generators)"}
+    roof = None
+    if args.workload == "stream":
+        head, meshes = stream_headline(args)
+        out.update(head)
+        cpu_meshes, cpu_what = meshes, "requests of the stream"
+    else:
+        desc, gen = WORKLOADS[args.workload]
+        mesh = gen()
+        prec = sso.PREC_MIXED if args.precision == "mixed" else sso.PREC_FP64
+        solver = {"auto": sso.SOLVER_AUTO, "standard": sso.SOLVER_STANDARD,
+                  "fused": sso.SOLVER_FUSED}[args.solver]
+        opts = sso.Options(precision=prec, rtol=args.rtol, max_it=400000,
+                           profile_every=args.profile_every, solver=solver,
+                           refine_steps=args.refine_steps, inner_max_it=args.inner_max_it)
+        run = problem_run(mesh, opts, args.steps, args.warmup, args.objective)
+        out.update(value=run["solves_per_s"], dof_per_s=run["dof_per_s"],
+                   ms_per_step=run["ms_per_step"], p50_ms=run["p50_ms"], p99_ms=run["p99_ms"],
+                   dtype="f64" if args.precision == "fp64" else "f32 inner PCG / f64 flexible CG",
+                   config={"workload": desc, "n_dof": mesh.n_dof, "objective": args.objective,
+                           "rtol": args.rtol, "precision": args.precision,
+                           **{k: v for k, v in _public(run).items()
+                              if k in ("pcg_iters", "adjoint_pcg_iters", "outer_steps",
+                                       "rel_residual", "status", "solver", "n_blocks")}})
+        roof = roofline_of(run, args.workload, args.precision, ceilings)
+        cpu_meshes, cpu_what = [mesh] * 1000, f"analyses of the {desc}"
+    if "large" in legs:
+        out["large"], run300 = large_leg(args)
+        if roof is None:
+            roof = roofline_of(run300, "shell300", "fp64", ceilings)
+    if "shell60" in legs:
+        out["shell60"], run60 = shell60_leg(args)
+        out["shell60"]["roofline"] = roofline_of(run60, "shell60", "fp64", ceilings)
+        out["shell60"]["roofline"]["note"] = ("9.4 MB of K: resident in the 256 MB Infinity "
+                                              "Cache, not an HBM figure")
+    if "general" in legs:
+        out["general_objective"] = general_leg(args)
+    if "batch" in legs:
+        out["batched"] = batch_bench(SEEDED["shell60"], 16, 1e-8, "compliance",
+                                     sso.SOLVER_AUTO)
+    if "network" in legs and args.network_variants > 0:
+        out["network"] = shellnet_bench(args.network_variants, sso.SOLVER_AUTO)
+    if "arch" in legs and args.arch:
         out["arch_replay"] = arch_bench([int(v) for v in args.arch.split(",")])
+    if roof is not None:
+        out["roofline"] = roof
+    if ceilings:
+        out["ceilings"] = ceilings
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, args.objective, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cpu_meshes, args.objective, args.cpu_seconds,
+                                           cpu_what)
     print(json.dumps(out), flush=True)
 
 

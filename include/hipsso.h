@@ -103,8 +103,8 @@ typedef struct {
                                  the reported residual is recomputed)                       */
   int32_t max_it;             /* PCG iteration limit per solve                               */
   int32_t refine_steps;       /* mixed precision: maximum outer (FP64) steps                 */
-  int32_t profile_every;      /* 0 = off; n > 0: time every n-th SpMV launch of the PCG with
-                                 HIP events on the problem's stream (stats.spmv_us)          */
+  int32_t profile_every;      /* 0 = off; n > 0: time every n-th PCG iteration with HIP
+                                 events on the problem's stream (stats.spmv_us)              */
   double inner_rtol;          /* mixed precision: relative tolerance of each FP32 inner PCG
                                  solve (0 = 1e-5)                                           */
   int32_t solver;             /* SSO_SOLVER_*: PCG recurrences (also of the FP32 inner solves) */
@@ -121,12 +121,12 @@ typedef struct {
   double t_solve_us;          /* PCG                                                         */
   double t_adj_us;            /* adjoint solve + element contraction + gather (sso_adjoint)  */
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
-  double spmv_us;             /* mean duration per launch of the sampled iteration kernel
-                                 (profile_every): k_spmv_dir of the standard recurrences,
-                                 timed alone; k_cg1_iter1 of the single-reduction ones, timed
-                                 over 8 back-to-back launches (dispatch gaps included)      */
-  int32_t spmv_samples;       /* number of sampled SpMV launches                             */
-  double spmv_bytes;          /* algorithmic bytes of one such launch                        */
+  double spmv_us;             /* mean duration of one sampled PCG iteration (profile_every):
+                                 k_spmv_dir + k_update of the standard recurrences, timed as a
+                                 pair; k_cg1_iter1 of the single-reduction ones, timed over 8
+                                 back-to-back launches (dispatch gaps included)              */
+  int32_t spmv_samples;       /* number of sampled iterations                                */
+  double spmv_bytes;          /* algorithmic bytes of one iteration                          */
   int32_t refine_steps;       /* mixed precision: outer steps (FP32 inner solves) run        */
   int32_t solver;             /* SSO_SOLVER_STANDARD or _FUSED: recurrences that ran         */
 } sso_stats;

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhipsso.so")
 SOURCES = ["api.hip", "pattern.hip", "elements.hip", "assemble.hip", "pcg.hip", "extras.hip",
-           "ceiling.hip"]
+           "ceiling.hip", "validate.cpp"]
 ARCH = os.environ.get("HIPSSO_ARCH", "gfx950")
 
 CFLAGS = [

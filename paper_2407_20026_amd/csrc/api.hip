@@ -2,8 +2,11 @@
 // the problem's stream, error mapping and per-stage timing.
 #include <new>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "sso_internal.h"
 
@@ -135,6 +138,66 @@ void free_problem(sso_problem* p) {
   delete p;
 }
 
+// Debug mode (HIPSSO_DEBUG set, and not "0", when a problem is created): the block pattern, the
+// sort permutation and the padded rows built on the GPU are copied to the host and checked
+// invariant by invariant (check_pattern); a failure is reported on stderr and as SSO_EINVAL.
+bool debug_mode() {
+  const char* v = std::getenv("HIPSSO_DEBUG");
+  return v && *v && !(v[0] == '0' && v[1] == '\0');
+}
+
+int debug_check_pattern(sso_problem* p) {
+  const Mesh& m = p->m;
+  const Pattern& pat = p->pat;
+  hipStream_t s = p->s;
+  const int n = m.n_nodes;
+  const int64_t nb = pat.n_blocks, nc = pat.n_bcoo;
+  std::vector<int32_t> brow(n + 1), bcol(nb), bseg(nb + 1), bperm(nc), bslot(nc), bdiag(n),
+      bsrow(nb), est(n + 1), ell((int64_t)n * pat.ell_w), bn(2 * (int64_t)m.n_beams),
+      qn(4 * (int64_t)m.n_quads);
+  auto get = [&](std::vector<int32_t>& v, const int32_t* src) {
+    return v.empty() ? hipSuccess
+                     : hipMemcpyAsync(v.data(), src, sizeof(int32_t) * v.size(),
+                                      hipMemcpyDeviceToHost, s);
+  };
+  TRY_HIP(get(brow, pat.brow_ptr));
+  TRY_HIP(get(bcol, pat.bcol));
+  TRY_HIP(get(bseg, pat.bseg));
+  TRY_HIP(get(bperm, pat.bperm));
+  TRY_HIP(get(bslot, pat.bslot));
+  TRY_HIP(get(bdiag, pat.bdiag));
+  TRY_HIP(get(bsrow, pat.bsrow));
+  TRY_HIP(get(est, pat.estart));
+  TRY_HIP(get(ell, pat.bcol_ell));
+  TRY_HIP(get(bn, m.beam_nodes));
+  TRY_HIP(get(qn, m.quad_nodes));
+  TRY_HIP(hipStreamSynchronize(s));
+  HostPattern h;
+  h.n_nodes = n;
+  h.n_beams = m.n_beams;
+  h.n_quads = m.n_quads;
+  h.ell_w = pat.ell_w;
+  h.n_blocks = nb;
+  h.n_bcoo = nc;
+  h.brow_ptr = brow.data();
+  h.bcol = bcol.data();
+  h.bseg = bseg.data();
+  h.bperm = bperm.data();
+  h.bslot = bslot.data();
+  h.bdiag = bdiag.data();
+  h.bsrow = bsrow.data();
+  h.estart = est.data();
+  h.bcol_ell = ell.data();
+  h.beam_nodes = bn.data();
+  h.quad_nodes = qn.data();
+  char msg[256];
+  if (check_pattern(h, msg, sizeof msg) != 0) {
+    std::fprintf(stderr, "hipsso debug: %s\n", msg);
+    return SSO_EINVAL;
+  }
+  return SSO_OK;
+}
+
 int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
                 sso_problem* p) {
   p->s = stream;
@@ -194,11 +257,15 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
   *p->h_err = 0;
   TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
   if (*p->h_err) return SSO_EINVAL;
+  if (debug_mode()) {
+    const int st = debug_check_pattern(p);
+    if (st != SSO_OK) return st;
+  }
   p->n_coo = 144 * nb + 576 * nq;
   TRY_HIP(dev_alloc(&p->coo, p->n_coo, s));
   TRY_HIP(dev_alloc(&p->qarea, nq, s));
   TRY_HIP(dev_alloc(&p->K, 36 * p->pat.n_blocks, s));
-  TRY_HIP(dev_alloc(&p->Dinv, 36 * nn, s));
+  TRY_HIP(dev_alloc(&p->Dinv, dinv_packed_len(nn), s));
   TRY_HIP(dev_alloc(&p->f, 6 * nn, s));
   TRY_HIP(dev_alloc(&p->u, 6 * nn, s));
   TRY_HIP(dev_alloc(&p->lam, 6 * nn, s));
@@ -315,7 +382,7 @@ int prepare(sso_problem* p, bool batch) {
   const bool mx = mixed(p), fu = fused(p);
   const int64_t nk = 36 * p->pat.n_blocks;
   const int64_t nb = 36 * right_precondition_blocks(p->pat, p->m.n_nodes);
-  if (mx && !p->Dinv32) TRY_HIP(dev_alloc(&p->Dinv32, 36 * (int64_t)p->m.n_nodes, s));
+  if (mx && !p->Dinv32) TRY_HIP(dev_alloc(&p->Dinv32, dinv_packed_len(p->m.n_nodes), s));
   if (mx && !fu && !p->K32) TRY_HIP(dev_alloc(&p->K32, nk, s));
   if (fu && !mx && !p->B) TRY_HIP(dev_alloc(&p->B, nb, s));
   if (fu && mx && !p->B32) TRY_HIP(dev_alloc(&p->B32, nb, s));
@@ -451,7 +518,7 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->spmv_us = p->w.prof_n ? p->w.prof_us / p->w.prof_n : 0.0;
     stats->spmv_bytes = fused_used(p)
                             ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
-                            : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, mixed(p));
+                            : pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p));
     stats->solver = p->solver_used;
   }
   // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available
@@ -512,7 +579,7 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->bytes_moved = solve_bytes(p, iters, outer);
     stats->spmv_bytes =
         fused(p) ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
-                 : spmv_bytes_per_launch(p->m.n_nodes, p->pat.n_blocks, mixed(p));
+                 : pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p));
     stats->solver = p->solver_used;
   }
   p->in_batch = false;

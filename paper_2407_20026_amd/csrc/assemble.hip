@@ -103,7 +103,8 @@ __global__ void k_mask_vector(int64_t n, const uint8_t* fixed, const double* in,
   out[t] = fixed[t] ? 0.0 : in[t];
 }
 
-// Dinv_I = (K_II)^{-1} by Cholesky of the (masked, SPD) diagonal block; full 6x6 row-major.
+// Dinv_I = (K_II)^{-1} by Cholesky of the (masked, SPD) diagonal block, stored packed (upper
+// triangle, dinv_index); entries (i, j) and (j, i) of W^T W are the same sum in the same order.
 __global__ void k_block_jacobi(int n_nodes, const int32_t* bdiag, const double* K, double* Dinv,
                                float* Dinv32, unsigned* err) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,13 +141,13 @@ __global__ void k_block_jacobi(int n_nodes, const int32_t* bdiag, const double* 
       W[i][j] = v / L[i][i];
     }
   }
-  double* out = Dinv + 36 * (int64_t)I;
+  double* out = Dinv + DINV_PACKED * (int64_t)I;
   for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) {
+    for (int j = i; j < 6; ++j) {
       double v = 0.0;
-      for (int k = (i > j ? i : j); k < 6; ++k) v += W[k][i] * W[k][j];
-      out[6 * i + j] = v;
-      if (Dinv32) Dinv32[36 * (int64_t)I + 6 * i + j] = (float)v;
+      for (int k = j; k < 6; ++k) v += W[k][i] * W[k][j];
+      out[dinv_index(i, j)] = v;
+      if (Dinv32) Dinv32[DINV_PACKED * (int64_t)I + dinv_index(i, j)] = (float)v;
     }
 }
 

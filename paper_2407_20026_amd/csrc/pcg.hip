@@ -148,6 +148,7 @@ __device__ inline void write_partials(const A v[NV], double* partials) {
 // ---- vector kernels: 6 consecutive lanes per node, 64 nodes per workgroup pass -----------
 
 constexpr int VEC_NODES = MAX_TPB / 6;   // 64
+static_assert(VEC_NODES == DINV_GROUP, "a vector pass covers one group of packed inverses");
 
 struct RowMap {
   int lr, a, I;
@@ -163,17 +164,52 @@ __device__ inline RowMap row_map_at(int group, int n_nodes) {
   return m;
 }
 
-// z = Dinv r for the node of this lane, r values of the node staged in LDS.
+// The packed block-Jacobi inverses of a group of 64 nodes (21 x 64 values, contiguous) are
+// loaded by the whole workgroup in 16-byte pieces -- each thread at most two, no bound test
+// (the array is padded to whole groups) -- and staged in LDS, where the 6 lanes of each node read
+// their rows.  Against every lane loading its own row of a full 6 x 6 block this reads 21 of 36
+// values per node from HBM, in coalesced loads.
 template <class T>
-__device__ inline T apply_dinv(const T* Dinv, const T* rs, int I, int a, int lr) {
-  using V = typename Vec2<T>::type;
-  const V* dv = reinterpret_cast<const V*>(Dinv + 36 * (int64_t)I + 6 * a);
+struct DinvChunk {
+  static constexpr int PER = 16 / sizeof(T);                            // values per piece
+  static constexpr int PIECES = DINV_PACKED * DINV_GROUP / PER;         // pieces per group
+  static constexpr int PER_THREAD = (PIECES + MAX_TPB - 1) / MAX_TPB;
+  using V = int4;
+  V v[PER_THREAD];
+};
+
+template <class T>
+__device__ inline DinvChunk<T> dinv_load(const T* __restrict__ Dinv, int group) {
+  using C = DinvChunk<T>;
+  C c;
+  const typename C::V* src =
+      reinterpret_cast<const typename C::V*>(Dinv + (int64_t)DINV_PACKED * DINV_GROUP * group);
+  for (int k = 0; k < C::PER_THREAD; ++k) {
+    const int i = (int)threadIdx.x + k * MAX_TPB;
+    if (i < C::PIECES) c.v[k] = src[i];
+  }
+  return c;
+}
+
+template <class T>
+__device__ inline void dinv_stage(const DinvChunk<T>& c, T* dl) {
+  using C = DinvChunk<T>;
+  typename C::V* dst = reinterpret_cast<typename C::V*>(dl);
+  for (int k = 0; k < C::PER_THREAD; ++k) {
+    const int i = (int)threadIdx.x + k * MAX_TPB;
+    if (i < C::PIECES) dst[i] = c.v[k];
+  }
+}
+
+// z = Dinv r for the node of this lane: row a of the node's inverse (staged in LDS at dl) applied
+// to its r values (staged at rs), in the order of the row: (0, 1), (2, 3), (4, 5).
+template <class T>
+__device__ inline T apply_dinv(const T* dl, const T* rs, int a, int lr) {
+  const T* dn = dl + DINV_PACKED * lr;
   const T* rr = rs + 6 * lr;
   T z = 0;
-  for (int h = 0; h < 3; ++h) {
-    V d = dv[h];
-    z += d.x * rr[2 * h] + d.y * rr[2 * h + 1];
-  }
+  for (int h = 0; h < 3; ++h)
+    z += dn[dinv_index(a, 2 * h)] * rr[2 * h] + dn[dinv_index(a, 2 * h + 1)] * rr[2 * h + 1];
   return z;
 }
 
@@ -338,6 +374,7 @@ __global__ void __launch_bounds__(MAX_TPB)
 k_pcg_init(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob, double rtol,
            int max_it) {
   __shared__ T rs[MAX_TPB];
+  __shared__ __align__(16) T dl[DINV_PACKED * DINV_GROUP];
   const Wg<T> W = wg_of(D, wg_prob);
   const PcgDesc<T>& d = *W.d;
   const int n_nodes = d.n_nodes;
@@ -345,6 +382,7 @@ k_pcg_init(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   for (int gi = W.lb; gi * VEC_NODES < n_nodes; gi += W.ng) {
     RowMap m = row_map_at(gi, n_nodes);
     const int64_t q = 6 * (int64_t)m.I + m.a;
+    const DinvChunk<T> dc = dinv_load(d.Dinv, gi);
     T rv = 0;
     if (m.valid) {
       rv = d.b[q];
@@ -353,9 +391,10 @@ k_pcg_init(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
       if constexpr (!zp_pairs<T>()) d.p[0][q] = 0;
     }
     rs[threadIdx.x] = rv;
+    dinv_stage(dc, dl);
     __syncthreads();
     if (m.valid) {
-      const T zz = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
+      const T zz = apply_dinv(dl, rs, m.a, m.lr);
       if constexpr (zp_pairs<T>()) {
         d.p[0][2 * q] = zz;
         d.p[0][2 * q + 1] = 0;
@@ -522,6 +561,7 @@ template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   __shared__ T rs[MAX_TPB];
+  __shared__ __align__(16) T dl[DINV_PACKED * DINV_GROUP];
   const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
   // every field the kernel uses in one batch of scalar loads
   asm volatile("" ::"s"(d.x), "s"(d.r), "s"(d.z), "s"(d.p[0]), "s"(d.p[1]), "s"(d.Ap),
@@ -537,6 +577,9 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   const RowMap m0 = row_map_at(lb, n_nodes);
   const int64_t q0 = 6 * (int64_t)(m0.valid ? m0.I : 0) + m0.a;
   const T x0 = x[q0], a0 = Ap[q0], r0 = r[q0];
+  // the first pass's inverses, state-free; a workgroup with no node group of its own (the
+  // launch has one workgroup per 18 block rows, a group is 64 nodes) reads group 0 and drops it
+  const DinvChunk<T> dc0 = dinv_load(d.Dinv, lb * VEC_NODES < n_nodes ? lb : 0);
   const StdState S = std_state(st);
   asm volatile("" ::"v"(x0), "v"(a0), "v"(r0), "s"(S.rz0), "s"(S.rz1), "s"(S.jc));
   if (S.done) return;
@@ -577,9 +620,10 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
       r[q] = rn;
     }
     rs[threadIdx.x] = rn;
+    dinv_stage(gi == lb ? dc0 : dinv_load(d.Dinv, gi), dl);
     __syncthreads();
     if (m.valid) {
-      const T zz = apply_dinv(d.Dinv, rs, m.I, m.a, m.lr);
+      const T zz = apply_dinv(dl, rs, m.a, m.lr);
       if constexpr (zp_pairs<T>())
         p[2 * q] = zz;   // z_{j+1} beside p_j
       else
@@ -735,23 +779,22 @@ __device__ inline T row_product_b(const FusedDesc<T>& d, int I, const T* __restr
   }
 }
 
-// Row a of the node's 6x6 block-Jacobi inverse applied to the 6 values at v.
+// Row a of the node's 6x6 block-Jacobi inverse (packed storage) applied to the 6 values at v.
 template <class T>
 struct DinvRow {
-  typename Vec2<T>::type d[3];
+  T d[6];
   __device__ inline T apply(const T* v) const {
     T z = 0;
-    for (int h = 0; h < 3; ++h) z += d[h].x * v[2 * h] + d[h].y * v[2 * h + 1];
+    for (int h = 0; h < 3; ++h) z += d[2 * h] * v[2 * h] + d[2 * h + 1] * v[2 * h + 1];
     return z;
   }
 };
 
 template <class T>
 __device__ inline DinvRow<T> dinv_row(const T* Dinv, int I, int a) {
-  using V = typename Vec2<T>::type;
-  const V* dv = reinterpret_cast<const V*>(Dinv + 36 * (int64_t)I + 6 * a);
+  const T* dn = Dinv + DINV_PACKED * (int64_t)I;
   DinvRow<T> R;
-  for (int h = 0; h < 3; ++h) R.d[h] = dv[h];
+  for (int b = 0; b < 6; ++b) R.d[b] = dn[dinv_index(a, b)];
   return R;
 }
 
@@ -1117,9 +1160,9 @@ k_right_precondition(int n_nodes, int64_t n_blocks, int w, const int32_t* __rest
     s = rb + u;
   }
   const double* k = K + 36 * s + 6 * a;
-  const double* m = Dinv + 36 * (int64_t)bcol[s] + b;
+  const double* m = Dinv + DINV_PACKED * (int64_t)bcol[s];
   double acc = 0.0;
-  for (int c = 0; c < 6; ++c) acc += k[c] * m[6 * c];
+  for (int c = 0; c < 6; ++c) acc += k[c] * m[dinv_index(c, b)];
   B[e] = (T)acc;
 }
 
@@ -1565,7 +1608,8 @@ static hipError_t pcg_start(const Mesh& m, const Pattern& pat, const T* K, const
   return hipGetLastError();
 }
 
-// One standard PCG solve in precision T on (K, Dinv, b) -> x; the SpMV kernel is profiled.
+// One standard PCG solve in precision T on (K, Dinv, b) -> x; a profiled sample spans one
+// whole iteration (k_spmv_dir and k_update).
 template <class T>
 static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T* Dinv,
                           const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
@@ -1579,8 +1623,8 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
     hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-    if (e1) (void)hipEventRecord(*e1, s);
     hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    if (e1) (void)hipEventRecord(*e1, s);
   };
   return run_polled(w, s, max_it, profile_every, 1, launch, iters, status);
 }
@@ -2135,8 +2179,8 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
         if (e0) (void)hipEventRecord(*e0, s);
         hipLaunchKernelGGL(k_spmv_dir<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-        if (e1) (void)hipEventRecord(*e1, s);
         hipLaunchKernelGGL(k_update<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+        if (e1) (void)hipEventRecord(*e1, s);
       };
       e = run_polled(w, s, cap, profile_every, 1, launch, &it, &st);
     }
@@ -2181,9 +2225,9 @@ hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double*
 
 double fused_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) {
   const double n_dof = 6.0 * (double)n_nodes, v = mixed ? 4.0 : 8.0;
-  // B values + block columns + row pointers; r, w, s gathered; p, x read; Dinv (36 per node);
-  // p, x, s, r, w written
-  return (36.0 * v + 4.0) * n_blocks + 4.0 * (n_nodes + 1) + (3 + 2 + 6 + 5) * v * n_dof;
+  // B values + block columns + row pointers; r, w, s gathered; p, x read; Dinv (21 per node,
+  // 3.5 per DOF); p, x, s, r, w written
+  return (36.0 * v + 4.0) * n_blocks + 4.0 * (n_nodes + 1) + (3 + 2 + 3.5 + 5) * v * n_dof;
 }
 
 double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed) {
@@ -2196,8 +2240,8 @@ double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) {
   const double n_dof = 6.0 * (double)n_nodes;
   // spmv: K values + block columns + row pointers; z, p_old read; p_new, Ap written
   double spmv = spmv_bytes_per_launch(n_nodes, n_blocks, mixed);
-  // update: x, p, Ap, r read, Dinv (6 per DOF); x, r, z written
-  double upd = 4.0 * fb * n_dof + 6.0 * fb * n_dof + 3.0 * fb * n_dof;
+  // update: x, p, Ap, r read, Dinv (21 per node, 3.5 per DOF); x, r, z written
+  double upd = 4.0 * fb * n_dof + 3.5 * fb * n_dof + 3.0 * fb * n_dof;
   return spmv + upd;
 }
 

@@ -104,6 +104,19 @@ inline int ell_width(int max_blocks) {
   return max_blocks <= 6 ? 6 : max_blocks <= 9 ? 9 : max_blocks <= 12 ? 12 : 0;
 }
 
+// The block-Jacobi inverse of a node is symmetric (W^T W): stored packed, its upper triangle
+// row by row (21 values per node), entry (a, b) at dinv_index(a, b).  The array is padded to
+// whole groups of 64 nodes, so that the vector kernels can stage a group's 21 x 64 values with
+// 16-byte loads without a bound test.
+constexpr int DINV_PACKED = 21;
+constexpr int DINV_GROUP = 64;
+__host__ __device__ constexpr int dinv_index(int a, int b) {
+  return a <= b ? a * (11 - a) / 2 + b : b * (11 - b) / 2 + a;
+}
+inline int64_t dinv_packed_len(int64_t n_nodes) {
+  return DINV_PACKED * ((n_nodes + DINV_GROUP - 1) / DINV_GROUP) * DINV_GROUP;
+}
+
 struct Mesh {
   int32_t n_nodes = 0, n_beams = 0, n_quads = 0;
   double* xyz = nullptr;
@@ -158,6 +171,18 @@ inline hipError_t dev_alloc(T** p, int64_t n, hipStream_t s) {
 inline void dev_free(void* p, hipStream_t s) {
   if (p) (void)hipFreeAsync(p, s);
 }
+
+// Host copies of a block pattern and the element connectivity, for check_pattern.
+struct HostPattern {
+  int n_nodes = 0, n_beams = 0, n_quads = 0, ell_w = 0;
+  int64_t n_blocks = 0, n_bcoo = 0;
+  const int32_t *brow_ptr = nullptr, *bcol = nullptr, *bseg = nullptr, *bperm = nullptr,
+                *bslot = nullptr, *bdiag = nullptr, *bsrow = nullptr, *estart = nullptr,
+                *bcol_ell = nullptr, *beam_nodes = nullptr, *quad_nodes = nullptr;
+};
+// validate.cpp: 0 when every invariant of the pattern holds, else the number of the first
+// failed check (1-8) with a message in msg.
+int check_pattern(const HostPattern& h, char* msg, size_t len);
 
 // ---- launch helpers (each defined in its own translation unit) ----------------------------
 

@@ -208,7 +208,9 @@ def test_network_batch_at_configured_size_vs_oracle_adjoint():
     print("[gpu] shellnet batch 80x80 x 2 variants vs oracle adjoint", flush=True)
     ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "shellnet80_oracle.npz"))
     L = 20.0
-    batch = ShellBatch(m=80, n_variants=2, L=L, options=sso.Options(rtol=1e-11, max_it=400000),
+    # rtol 1e-9: the rho^3 contrast puts the smallest true residual an FP64 u of these systems
+    # reaches near 1.4e-10 (measured with the compensated residual)
+    batch = ShellBatch(m=80, n_variants=2, L=L, options=sso.Options(rtol=1e-9, max_it=400000),
                        batched=True)
     try:
         net = DesignMLP().to("cuda")
@@ -218,10 +220,12 @@ def test_network_batch_at_configured_size_vs_oracle_adjoint():
         loss.backward()
         grads = [p.grad.detach().cpu().numpy().copy() for p in net.parameters()]
         statuses = [p.last_status for p in batch.problems]
+        resid = [p.last_stats["rel_residual"] for p in batch.problems]
         base = batch.base
     finally:
         batch.close()
-    assert statuses == [0, 0]
+    print(f"  statuses {statuses}, residuals {resid}")
+    assert statuses == [0, 0] and max(resid) <= 1e-9
     c_ref = np.mean([float(ref[f"c_{v}"]) for v in (0, 1)])
     assert loss.item() == pytest.approx(c_ref, rel=1e-9)
     gx = np.mean([ref[f"grad_xyz_{v}"] for v in (0, 1)], axis=0)

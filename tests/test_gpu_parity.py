@@ -418,3 +418,20 @@ def test_unsupported_structure_reports_failure():
         _, st = p.solve(check=False)
         assert p.last_status in (sso.SSO_ENOTCONV, sso.SSO_EBREAKDOWN)
         assert st["iters"] <= 400
+
+
+def test_debug_mode_checks_every_pattern(monkeypatch):
+    """HIPSSO_DEBUG: the GPU-built pattern, permutation and padded rows of every parity structure
+    pass the host-side check, and the debug problem's solve is bitwise the plain one's."""
+    sso = _sso()
+    print("[gpu] debug-mode pattern checks", flush=True)
+    for name, make in CASES.items():
+        mesh = make()
+        monkeypatch.setenv("HIPSSO_DEBUG", "1")
+        with _problem(mesh, rtol=1e-10) as p:
+            u_dbg, _ = p.solve(check=False)
+            u_dbg = u_dbg.cpu()
+        monkeypatch.delenv("HIPSSO_DEBUG")
+        with _problem(mesh, rtol=1e-10) as q:
+            u, _ = q.solve(check=False)
+        assert torch.equal(u_dbg, u.cpu()), name
