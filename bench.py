@@ -78,8 +78,9 @@ def parse():
                     choices=["compliance", "strain_energy", "linear"])
     ap.add_argument("--rtol", type=float, default=None,
                     help="relative residual target (default 1e-8; 1e-10 for shell300)")
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
-                    help="headline precision (default: mixed for the stream, fp64 otherwise)")
+    ap.add_argument("--precision", default=None, choices=["auto", "fp64", "mixed"],
+                    help="headline precision (default: auto for the stream -- FP32 inner "
+                         "solves where the problem's K outgrows the caches -- fp64 otherwise)")
     ap.add_argument("--inner-max-it", type=int, default=0,
                     help="mixed precision: iteration cap of each FP32 inner solve (0 = none)")
     ap.add_argument("--refine-steps", type=int, default=20,
@@ -111,7 +112,7 @@ def parse():
     if args.warmup is None:
         args.warmup = 32 if stream else 3
     if args.precision is None:
-        args.precision = "mixed" if stream else "fp64"
+        args.precision = "auto" if stream else "fp64"
     if args.rtol is None:
         args.rtol = 1e-10 if args.workload == "shell300" else 1e-8
     return args
@@ -169,12 +170,11 @@ def cpu_baseline(meshes, objective, budget_s, what):
 
 # ---- the served stream ----------------------------------------------------------------------
 
-PREC_NAMES = ("mixed", "fp64")
+PRECISIONS = {"auto": "PREC_AUTO", "fp64": "PREC_FP64", "mixed": "PREC_MIXED"}
 
 
 def _stream_options(sso, precision, rtol, args):
-    return sso.Options(rtol=rtol, max_it=400000,
-                       precision=sso.PREC_MIXED if precision == "mixed" else sso.PREC_FP64,
+    return sso.Options(rtol=rtol, max_it=400000, precision=getattr(sso, PRECISIONS[precision]),
                        inner_max_it=args.inner_max_it if precision == "mixed" else 0,
                        refine_steps=args.refine_steps)
 
@@ -194,8 +194,20 @@ def _size_buckets(results, meshes):
     return out
 
 
+def _error_summary(errs):
+    def one(key):
+        v = np.array([e.get(key, 0.0) for e in errs])
+        return {"max": float(v.max()), "p99": float(np.percentile(v, 99)),
+                "p50": float(np.percentile(v, 50))}
+    return {"requests": len(errs), "g_rel": one("g_rel"),
+            "dg_dxyz_rel_inf": one("dg_dxyz_rel_inf"), "dg_dt_rel_inf": one("dg_dt_rel_inf")}
+
+
 def stream_headline(args):
-    """The served stream: closed-loop capacity, then Poisson arrivals, in both precisions."""
+    """The served stream in the headline precision (the AUTO policy by default) and plain FP64:
+    closed-loop capacity, then Poisson arrivals at 0.8 of the smaller capacity; FP32 inner
+    solves forced on every request (mixed precision regardless of size) in a closed loop
+    beside them."""
     import paper_2407_20026_amd as sso
     from paper_2407_20026_amd.serve import (BatchedServer, Request, errors_against,
                                             poisson_arrivals)
@@ -203,8 +215,10 @@ def stream_headline(args):
     meshes = [meshgen.served_request(i) for i in range(n)]
     warm = [meshgen.served_request(i, base_seed=2 * 10**6) for i in range(args.warmup)]
     log(f"stream: {n} requests, {sum(m.n_dof for m in meshes)} DOF in all")
+    head = args.precision
+    order = [head] + [p for p in ("fp64", "mixed") if p != head]
     closed, poisson, servers = {}, {}, {}
-    for prec in PREC_NAMES:
+    for prec in order:
         srv = BatchedServer(slots=args.slots, options=_stream_options(sso, prec, args.rtol, args),
                             chunk=args.chunk)
         servers[prec] = srv
@@ -215,57 +229,58 @@ def stream_headline(args):
         closed[prec] = st
         log(f"stream {prec} closed loop: {st.solves_per_s:.1f} solves/s, "
             f"{st.dof_per_s / 1e6:.2f} M DOF/s, {st.wall_s:.1f} s")
-    lam = 0.8 * min(closed[p].solves_per_s for p in PREC_NAMES)
+    timed = [p for p in (head, "fp64") if p in closed][:2]
+    lam = 0.8 * min(closed[p].solves_per_s for p in timed)
     t_arr = poisson_arrivals(n, lam, seed=3)
-    for prec in PREC_NAMES:
+    for prec in timed:
         st = servers[prec].run([Request(i, m, float(t_arr[i])) for i, m in enumerate(meshes)])
         poisson[prec] = st
         log(f"stream {prec} Poisson at {lam:.1f}/s: {st.solves_per_s:.1f} solves/s, "
             f"p50 {st.p50_ms:.1f} ms, p99 {st.p99_ms:.1f} ms")
-    errs = errors_against(closed["mixed"].results, closed["fp64"].results)
-
-    def summary(key):
-        v = np.array([e.get(key, 0.0) for e in errs])
-        return {"max": float(v.max()), "p99": float(np.percentile(v, 99)),
-                "p50": float(np.percentile(v, 50))}
 
     def leg(prec):
-        c, q = closed[prec], poisson[prec]
-        return {"closed_loop": {"solves_per_s": c.solves_per_s, "dof_per_s": c.dof_per_s,
-                                "wall_s": c.wall_s, "peak_inflight": c.peak_inflight,
-                                "phase_s": {k: round(v, 3) for k, v in c.host_s.items()}},
-                "poisson": {"arrival_rate_per_s": lam, "solves_per_s": q.solves_per_s,
-                            "dof_per_s": q.dof_per_s, "p50_ms": q.p50_ms, "p99_ms": q.p99_ms,
-                            "mean_queue_ms": q.mean_queue_ms, "peak_inflight": q.peak_inflight,
-                            "by_size": _size_buckets(q.results, meshes)},
-                "not_converged": c.not_converged + q.not_converged,
-                "max_rel_residual": max(c.max_rel_residual, q.max_rel_residual),
-                "iters_median": int(np.median([r.iters for r in c.results]))}
+        c = closed[prec]
+        out = {"closed_loop": {"solves_per_s": c.solves_per_s, "dof_per_s": c.dof_per_s,
+                               "wall_s": c.wall_s, "peak_inflight": c.peak_inflight,
+                               "phase_s": {k: round(v, 3) for k, v in c.host_s.items()}},
+               "not_converged": c.not_converged, "max_rel_residual": c.max_rel_residual,
+               "iters_median": int(np.median([r.iters for r in c.results])),
+               "mixed_requests": int(sum(1 for r in c.results if r.outer_steps > 0))}
+        if prec in poisson:
+            q = poisson[prec]
+            out["poisson"] = {"arrival_rate_per_s": lam, "solves_per_s": q.solves_per_s,
+                              "dof_per_s": q.dof_per_s, "p50_ms": q.p50_ms, "p99_ms": q.p99_ms,
+                              "mean_queue_ms": q.mean_queue_ms,
+                              "peak_inflight": q.peak_inflight,
+                              "by_size": _size_buckets(q.results, meshes)}
+            out["not_converged"] += q.not_converged
+            out["max_rel_residual"] = max(out["max_rel_residual"], q.max_rel_residual)
+        return out
 
-    head = args.precision
     c, q = closed[head], poisson[head]
+    nc = sum(leg(p)["not_converged"] for p in order)
     out = {
         "value": c.solves_per_s,
         "dof_per_s": c.dof_per_s,
         "ms_per_step": 1000.0 * c.wall_s / n,
         "p50_ms": q.p50_ms,
         "p99_ms": q.p99_ms,
-        "dtype": "f32 inner PCG / f64 flexible CG" if head == "mixed" else "f64",
+        "dtype": {"auto": "f64, f32 inner PCG above the size crossover", "fp64": "f64",
+                  "mixed": "f32 inner PCG / f64 flexible CG"}[head],
         "config": {
             "workload": (f"served stream: {n} forward+adjoint requests (grid-shells n~U{{8..60}}, "
                          f"shells m~U{{10..120}}, per-request seeds 10^6+i), compliance, "
-                         f"rtol {args.rtol:g}, {head} precision; value = closed-loop solves/s, "
+                         f"rtol {args.rtol:g}, precision {head}; value = closed-loop solves/s, "
                          f"p50/p99 from arrival under Poisson arrivals at {lam:.1f}/s"),
             "requests": n, "mean_dof": float(np.mean([m.n_dof for m in meshes])),
             "slots": args.slots, "chunk": args.chunk, "rtol": args.rtol, "precision": head,
             "arrival_rate_per_s": lam,
-            "status": "converged" if c.not_converged + q.not_converged == 0 else
-                      f"{c.not_converged + q.not_converged} requests stopped above rtol",
+            "status": "converged" if nc == 0 else f"{nc} requests stopped above rtol",
         },
-        "stream": {p: leg(p) for p in PREC_NAMES},
-        "mixed_vs_fp64": {"requests": len(errs), "g_rel": summary("g_rel"),
-                          "dg_dxyz_rel_inf": summary("dg_dxyz_rel_inf"),
-                          "dg_dt_rel_inf": summary("dg_dt_rel_inf")},
+        "stream": {p: leg(p) for p in order},
+        "errors_vs_fp64": {p: _error_summary(errors_against(closed[p].results,
+                                                            closed["fp64"].results))
+                           for p in order if p != "fp64"},
     }
     return out, meshes
 
@@ -586,7 +601,7 @@ def main():
     else:
         desc, gen = WORKLOADS[args.workload]
         mesh = gen()
-        prec = sso.PREC_MIXED if args.precision == "mixed" else sso.PREC_FP64
+        prec = getattr(sso, PRECISIONS[args.precision])
         solver = {"auto": sso.SOLVER_AUTO, "standard": sso.SOLVER_STANDARD,
                   "fused": sso.SOLVER_FUSED}[args.solver]
         opts = sso.Options(precision=prec, rtol=args.rtol, max_it=400000,
@@ -595,7 +610,8 @@ def main():
         run = problem_run(mesh, opts, args.steps, args.warmup, args.objective)
         out.update(value=run["solves_per_s"], dof_per_s=run["dof_per_s"],
                    ms_per_step=run["ms_per_step"], p50_ms=run["p50_ms"], p99_ms=run["p99_ms"],
-                   dtype="f64" if args.precision == "fp64" else "f32 inner PCG / f64 flexible CG",
+                   dtype={"fp64": "f64", "mixed": "f32 inner PCG / f64 flexible CG",
+                          "auto": "f64, f32 inner PCG above the size crossover"}[args.precision],
                    config={"workload": desc, "n_dof": mesh.n_dof, "objective": args.objective,
                            "rtol": args.rtol, "precision": args.precision,
                            **{k: v for k, v in _public(run).items()

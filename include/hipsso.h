@@ -63,14 +63,22 @@ enum {
   SSO_OBJ_USER = 3            /* caller supplies dg/du; dg/dp omits explicit dependence    */
 };
 
-enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1 };
+/* Precision.  AUTO picks, per problem, mixed precision when the FP64 K alone holds at least
+ * SSO_AUTO_MIXED_K_BYTES (128 MiB) -- from there K no longer stays in the 256 MB Infinity Cache
+ * between iterations and the FP32 inner iterations' halved bytes pay for the extra iterations
+ * of the restarted inner solves (measured on single shells: FP64 faster up to a 200 x 200 shell,
+ * K 104 MB; mixed 10 % faster on 250 x 250 and 300 x 300, K 162 and 234 MB) -- and FP64
+ * otherwise.  In AUTO's mixed precision an inner_max_it of 0 means 30 (the best of the measured
+ * caps) and the outer step limit is at least max_it / 30. */
+enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1, SSO_PREC_AUTO = 2 };
+#define SSO_AUTO_MIXED_K_BYTES (128.0 * 1024.0 * 1024.0)
 
 /* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
  * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one
  * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
- * of K's size).  AUTO: sso_solve takes FUSED up to 18,432 nodes (latency-bound sizes; one
- * pass of 1,024 workgroups of 18 block rows) and STANDARD above; sso_solve_begin
- * (multi-problem launches) takes STANDARD. */
+ * of K's size).  AUTO: sso_solve takes FUSED up to 8,192 nodes (latency-bound sizes; measured:
+ * 13.4 against 20.2 ms on a 60 x 60 shell, equal on 90 x 90, 88 against 63 ms on 120 x 120)
+ * and STANDARD above; sso_solve_begin (multi-problem launches) takes STANDARD. */
 enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */
@@ -94,7 +102,8 @@ typedef struct {
 } sso_mesh;
 
 typedef struct {
-  int32_t precision;          /* SSO_PREC_FP64, or SSO_PREC_MIXED: FP64 flexible CG (one
+  int32_t precision;          /* SSO_PREC_FP64, SSO_PREC_AUTO (above), or SSO_PREC_MIXED:
+                                 FP64 flexible CG (one
                                  stored direction) whose preconditioner is an FP32 PCG solve
                                  (FP32 K, vectors, SpMV and dot accumulation); element
                                  stiffness, the outer products with K, the step lengths and
@@ -121,10 +130,10 @@ typedef struct {
   double t_solve_us;          /* PCG                                                         */
   double t_adj_us;            /* adjoint solve + element contraction + gather (sso_adjoint)  */
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
-  double spmv_us;             /* mean duration of one sampled PCG iteration (profile_every):
-                                 k_spmv_dir + k_update of the standard recurrences, timed as a
-                                 pair; k_cg1_iter1 of the single-reduction ones, timed over 8
-                                 back-to-back launches (dispatch gaps included)              */
+  double spmv_us;             /* mean duration of one PCG iteration, from samples of 8
+                                 back-to-back iterations (profile_every; dispatch gaps
+                                 included): k_spmv_dir + k_update of the standard
+                                 recurrences, k_cg1_iter1 of the single-reduction ones       */
   int32_t spmv_samples;       /* number of sampled iterations                                */
   double spmv_bytes;          /* algorithmic bytes of one iteration                          */
   int32_t refine_steps;       /* mixed precision: outer steps (FP32 inner solves) run        */
@@ -143,6 +152,21 @@ typedef struct sso_problem sso_problem;
  * an element that repeats a node; SSO_ENOMEM; SSO_EHIP. */
 int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
                        sso_problem** out);
+
+/* The same as sso_problem_create for a structure of the same topology as `like` (an existing
+ * problem on the current device): same node, member and quad counts and the same connectivity
+ * (beam_nodes, quad_nodes); coordinates, supports, loads and properties may all differ.  The
+ * pattern of K, the sort permutation and the padded rows are not rebuilt but shared with `like`
+ * (reference-counted: they live until the last problem that uses them is destroyed, whichever
+ * order the problems are destroyed in), so creation skips the pattern build and its
+ * synchronisations; results are bitwise those of sso_problem_create.  For request loops that
+ * see the same structure sizes again and again.  Sharing problems may run on different streams;
+ * destroying two of them at the same time from two threads is safe.  Errors: SSO_EINVAL (counts
+ * differ, connectivity differs -- checked on the device before the call returns --, `like` on
+ * another device, and as sso_problem_create), SSO_ENOMEM, SSO_EHIP.  sso_problem_bytes of the
+ * new problem does not count the shared pattern. */
+int sso_problem_create_like(const sso_problem* like, const sso_mesh* mesh,
+                            const sso_options* opts, hipStream_t stream, sso_problem** out);
 
 /* Replace design inputs without changing the topology: the design parameters p of the
  * optimisation problem (Sec. 2.3.1, Eq. (4); updated between steps as in Eq. (7)) -- nodal
@@ -278,6 +302,13 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
  * system's right-hand side f [n_nodes][6] (device, may be NULL) of the last solve (0 on the
  * fixed DOFs; with prescribed displacements the lifted load on the free ones). */
 int sso_matrix(sso_problem* p, double* vals, double* f);
+
+/* Device memory the problem holds (*bytes, host): every buffer allocated on its behalf so far --
+ * mesh copies, pattern, element list, K, preconditioner, solver vectors, and what later calls
+ * added (mixed-precision copies, the size objective's scratch, the scalar CSR view) -- all kept
+ * until sso_problem_destroy; buffers freed within a call are not counted.  For admission by
+ * memory footprint in a request loop.  Errors: SSO_EINVAL (NULL argument). */
+int sso_problem_bytes(const sso_problem* p, int64_t* bytes);
 
 /* Sizes: n_dof, block count (6x6 blocks of K) and nnz = 36 * blocks (host outputs). */
 int sso_sizes(const sso_problem* p, int64_t* n_dof, int64_t* n_blocks, int64_t* nnz);

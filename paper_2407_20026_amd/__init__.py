@@ -24,7 +24,7 @@ SSO_OK, SSO_EINVAL, SSO_ENOMEM, SSO_EHIP, SSO_ENOTCONV, SSO_EBREAKDOWN = 0, -1, 
 SSO_ESIZE = -6
 NOALLOC_MAX_QUADS = 139673   # SSO_NOALLOC_MAX_QUADS
 OBJ_COMPLIANCE, OBJ_STRAIN_ENERGY, OBJ_LINEAR, OBJ_USER = 0, 1, 2, 3
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_AUTO = 0, 1, 2
 SOLVER_AUTO, SOLVER_STANDARD, SOLVER_FUSED = 0, 1, 2
 
 OBJECTIVES = {"compliance": OBJ_COMPLIANCE, "strain_energy": OBJ_STRAIN_ENERGY,
@@ -60,11 +60,12 @@ class sso_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ("sso_problem_create", "sso_problem_update", "sso_set_options", "sso_solve",
+EXPORTS = ("sso_problem_create", "sso_problem_create_like", "sso_problem_update", "sso_set_options", "sso_solve",
            "sso_solve_begin", "sso_solve_end", "sso_batch_create", "sso_batch_iterate",
            "sso_batch_destroy", "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix",
            "sso_sizes", "sso_strerror", "sso_problem_destroy", "sso_size_objective",
-           "sso_size_objective_noalloc", "sso_size_penalty_update", "sso_hat_filter")
+           "sso_size_objective_noalloc", "sso_size_penalty_update", "sso_hat_filter",
+           "sso_problem_bytes")
 
 _lib = None
 _hip = None
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     lib.sso_problem_create.argtypes = [P(sso_mesh), P(sso_options), _vp, P(_vp)]
+    lib.sso_problem_create_like.argtypes = [_vp, P(sso_mesh), P(sso_options), _vp, P(_vp)]
     lib.sso_problem_update.argtypes = [_vp, _vp, _vp, _vp]
     lib.sso_set_options.argtypes = [_vp, P(sso_options)]
     lib.sso_solve.argtypes = [_vp, _vp, P(sso_stats)]
@@ -89,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 P(ctypes.c_int64)]
     lib.sso_matrix.argtypes = [_vp, _vp, _vp]
     lib.sso_sizes.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.sso_problem_bytes.argtypes = [_vp, P(ctypes.c_int64)]
     lib.sso_solve_begin.argtypes = [_vp]
     lib.sso_solve_end.argtypes = [_vp, _vp, P(sso_stats)]
     lib.sso_batch_create.argtypes = [_vp, P(_vp)]
@@ -172,9 +175,11 @@ class Problem:
     """One structure on one GPU: owns the library handle and the device copies of the mesh.
 
     ``mesh`` is a :class:`meshgen.Mesh`-like object (numpy or torch arrays with the C-ABI
-    layout).  All work runs on ``stream`` (default: torch's current stream)."""
+    layout).  All work runs on ``stream`` (default: torch's current stream).  ``like``: a live
+    problem of the same topology whose pattern is shared (sso_problem_create_like)."""
 
-    def __init__(self, mesh, options: Options | None = None, device="cuda", stream=None):
+    def __init__(self, mesh, options: Options | None = None, device="cuda", stream=None,
+                 like: "Problem | None" = None):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("hipsso needs a GPU (torch.cuda.is_available() is False)")
@@ -202,9 +207,14 @@ class Problem:
         self.options = options or Options()
         opts = self.options.c()
         h = ctypes.c_void_p()
-        _check(lib.sso_problem_create(ctypes.byref(cm), ctypes.byref(opts),
-                                      _stream_handle(self.stream), ctypes.byref(h)),
-               "sso_problem_create")
+        if like is not None:
+            _check(lib.sso_problem_create_like(like.handle, ctypes.byref(cm), ctypes.byref(opts),
+                                               _stream_handle(self.stream), ctypes.byref(h)),
+                   "sso_problem_create_like")
+        else:
+            _check(lib.sso_problem_create(ctypes.byref(cm), ctypes.byref(opts),
+                                          _stream_handle(self.stream), ctypes.byref(h)),
+                   "sso_problem_create")
         self.handle = h
         self.n_dof = 6 * self.n_nodes
         nd, nb, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -369,6 +379,12 @@ class Problem:
                     raise RuntimeError("hipMemcpy failed")
             out[name] = t
         return out
+
+    def device_bytes(self) -> int:
+        """Device memory the problem holds (sso_problem_bytes)."""
+        b = ctypes.c_int64()
+        _check(load_library().sso_problem_bytes(self.handle, ctypes.byref(b)), "sso_problem_bytes")
+        return b.value
 
     def matrix(self):
         """(K values in scalar CSR order [nnz], masked load vector [n_nodes, 6])."""

@@ -1,6 +1,7 @@
 // C ABI and host runtime of libhipsso: problem lifecycle, device buffers, launch sequencing on
 // the problem's stream, error mapping and per-stage timing.
 #include <new>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -21,10 +22,18 @@ static_assert(SSO_NOALLOC_MAX_QUADS * 15 + 2 * 1024 <=
                   (int64_t)(SSO_NOALLOC_SCRATCH_BYTES / sizeof(double)),
               "the no-allocation scratch holds the partials and 15 values per quad");
 
+// A block pattern shared by the problems of one topology (sso_problem_create_like); the last
+// problem to be destroyed frees it.
+struct SharedPattern {
+  Pattern pat;
+  std::atomic<int> refs{1};
+};
+
 struct sso_problem {
   hipStream_t s = nullptr;
   Mesh m;
-  Pattern pat;
+  Pattern pat;                  // the pattern's arrays (owned through `shared`)
+  SharedPattern* shared = nullptr;
   sso_options opt;
   int64_t n_coo = 0;
   double* coo = nullptr;
@@ -62,6 +71,7 @@ struct sso_problem {
   MixedState ms;                // mixed precision begun with sso_solve_begin
   hipEvent_t ev[6] = {};
   int device = 0;               // the device current at creation (holds the problem's memory)
+  int64_t bytes = 0;            // device memory allocated for the problem (sso_problem_bytes)
 };
 
 struct sso_batch {
@@ -85,10 +95,17 @@ sso_options default_options() {
 }
 
 bool options_ok(const sso_options& o) {
-  return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED) && o.rtol >= 0.0 &&
+  return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED ||
+          o.precision == SSO_PREC_AUTO) && o.rtol >= 0.0 &&
          o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0 && o.inner_rtol >= 0.0 &&
          o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_FUSED &&
          o.inner_max_it >= 0;
+}
+
+// The precision a problem runs in: AUTO resolves by the size of its FP64 K.
+bool mixed_for(const sso_options& o, int64_t n_blocks) {
+  if (o.precision == SSO_PREC_AUTO) return 288.0 * (double)n_blocks >= SSO_AUTO_MIXED_K_BYTES;
+  return o.precision == SSO_PREC_MIXED;
 }
 
 __global__ void k_fill(int64_t n, double v, double* out) {
@@ -128,7 +145,14 @@ void free_problem(sso_problem* p) {
                   (void*)p->perm, (void*)p->seg, (void*)m.u_presc, (void*)p->fm,
                   (void*)p->gw, (void*)p->wv, (void*)p->xpart})
     dev_free(q, s);
-  free_pattern(p->pat, s);
+  if (p->shared) {
+    if (p->shared->refs.fetch_sub(1) == 1) {   // the last problem of this topology
+      free_pattern(p->shared->pat, s);
+      delete p->shared;
+    }
+  } else {
+    free_pattern(p->pat, s);
+  }
   pcg_free(p->w, s);
   delete[] p->h_scal;
   delete p->h_err;
@@ -198,8 +222,14 @@ int debug_check_pattern(sso_problem* p) {
   return SSO_OK;
 }
 
+// 1 in *err where two connectivity arrays of n entries differ.
+__global__ void k_same_topology(int64_t n, const int32_t* a, const int32_t* b, unsigned* err) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && a[i] != b[i]) atomicOr(err, ERR_TOPO);
+}
+
 int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t stream,
-                sso_problem* p) {
+                sso_problem* p, const sso_problem* like) {
   p->s = stream;
   TRY_HIP(hipGetDevice(&p->device));
   p->opt = opts ? *opts : default_options();
@@ -255,11 +285,30 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
   p->h_scal = new double[8]();
   TRY_HIP(hipMemsetAsync(p->d_err, 0, sizeof(unsigned), s));
   *p->h_err = 0;
-  TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
-  if (*p->h_err) return SSO_EINVAL;
-  if (debug_mode()) {
-    const int st = debug_check_pattern(p);
-    if (st != SSO_OK) return st;
+  if (like) {
+    // the pattern of `like`, once its connectivity is shown to be this mesh's (checked with the
+    // other errors at the end of creation)
+    p->pat = like->pat;
+    p->shared = like->shared;
+    p->shared->refs.fetch_add(1);
+    const int64_t nbn = 2 * (int64_t)nb, nqn = 4 * (int64_t)nq;
+    if (nbn)
+      hipLaunchKernelGGL(k_same_topology, dim3((unsigned)((nbn + 255) / 256)), dim3(256), 0, s,
+                         nbn, m.beam_nodes, like->m.beam_nodes, p->d_err);
+    if (nqn)
+      hipLaunchKernelGGL(k_same_topology, dim3((unsigned)((nqn + 255) / 256)), dim3(256), 0, s,
+                         nqn, m.quad_nodes, like->m.quad_nodes, p->d_err);
+    TRY_HIP(hipGetLastError());
+  } else {
+    TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
+    if (*p->h_err) return SSO_EINVAL;
+    p->shared = new (std::nothrow) SharedPattern();
+    if (!p->shared) return SSO_ENOMEM;
+    p->shared->pat = p->pat;
+    if (debug_mode()) {
+      const int st = debug_check_pattern(p);
+      if (st != SSO_OK) return st;
+    }
   }
   p->n_coo = 144 * nb + 576 * nq;
   TRY_HIP(dev_alloc(&p->coo, p->n_coo, s));
@@ -272,9 +321,11 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
   TRY_HIP(dev_alloc(&p->rhs, 6 * nn, s));
   TRY_HIP(dev_alloc(&p->gbeam, 6 * nb, s));
   TRY_HIP(dev_alloc(&p->gquad, 14 * nq, s));
-  TRY_HIP(pcg_alloc(p->w, nn, p->opt.precision == SSO_PREC_MIXED, s));
+  TRY_HIP(pcg_alloc(p->w, nn, mixed_for(p->opt, p->pat.n_blocks), s));
   for (auto& e : p->ev) TRY_HIP(hipEventCreate(&e));
+  if (like) TRY_HIP(hipMemcpyAsync(p->h_err, p->d_err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   TRY_HIP(hipStreamSynchronize(s));
+  if (like && *p->h_err) return SSO_EINVAL;
   return SSO_OK;
 }
 
@@ -301,7 +352,33 @@ int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_
   if (opts && !options_ok(*opts)) return SSO_EINVAL;
   sso_problem* p = new (std::nothrow) sso_problem();
   if (!p) return SSO_ENOMEM;
-  int st = create_impl(mesh, opts, stream, p);
+  AllocCounter ac(&p->bytes);
+  int st = create_impl(mesh, opts, stream, p, nullptr);
+  if (st != SSO_OK) {
+    free_problem(p);
+    return st;
+  }
+  *out = p;
+  return SSO_OK;
+}
+
+int sso_problem_create_like(const sso_problem* like, const sso_mesh* mesh,
+                            const sso_options* opts, hipStream_t stream, sso_problem** out) {
+  if (!like || !mesh || !out) return SSO_EINVAL;
+  *out = nullptr;
+  if (mesh->n_nodes != like->m.n_nodes || mesh->n_beams != like->m.n_beams ||
+      mesh->n_quads != like->m.n_quads)
+    return SSO_EINVAL;
+  if (!mesh->xyz || !mesh->fixed || !mesh->f_nodal) return SSO_EINVAL;
+  if (mesh->n_beams > 0 && (!mesh->beam_nodes || !mesh->beam_prop)) return SSO_EINVAL;
+  if (mesh->n_quads > 0 && (!mesh->quad_nodes || !mesh->quad_prop)) return SSO_EINVAL;
+  if (opts && !options_ok(*opts)) return SSO_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != like->device) return SSO_EINVAL;
+  sso_problem* p = new (std::nothrow) sso_problem();
+  if (!p) return SSO_ENOMEM;
+  AllocCounter ac(&p->bytes);
+  int st = create_impl(mesh, opts, stream, p, like);
   if (st != SSO_OK) {
     free_problem(p);
     return st;
@@ -339,7 +416,7 @@ int sso_set_options(sso_problem* p, const sso_options* opts) {
 
 namespace {
 
-bool mixed(const sso_problem* p) { return p->opt.precision == SSO_PREC_MIXED; }
+bool mixed(const sso_problem* p) { return mixed_for(p->opt, p->pat.n_blocks); }
 bool fused(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
 // iteration of a begun problem has stopped (mixed precision: the refinement loop has)
 bool stopped(const sso_problem* p) { return mixed(p) ? p->ms.done : p->w.h_st->done != 0; }
@@ -351,6 +428,12 @@ MixedParams mixed_params(const sso_problem* p) {
   mp.max_it = p->opt.max_it;
   mp.refine_steps = p->opt.refine_steps;
   mp.inner_max_it = p->opt.inner_max_it;
+  if (p->opt.precision == SSO_PREC_AUTO) {   // AUTO's mixed precision: capped inner solves
+    constexpr int AUTO_INNER_CAP = 30;
+    if (mp.inner_max_it == 0) mp.inner_max_it = AUTO_INNER_CAP;
+    const int outer = p->opt.max_it / mp.inner_max_it + 1;
+    if (mp.refine_steps < outer) mp.refine_steps = outer;
+  }
   return mp;
 }
 
@@ -489,6 +572,7 @@ extern "C" {
 
 int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   if (!p) return SSO_EINVAL;
+  AllocCounter ac(&p->bytes);
   hipStream_t s = p->s;
   p->solved = false;
   p->in_batch = false;
@@ -528,6 +612,7 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
 
 int sso_solve_begin(sso_problem* p) {
   if (!p) return SSO_EINVAL;
+  AllocCounter ac(&p->bytes);
   // multi-problem launches run FP64 iterations of either kind and FP32 single-reduction ones
   hipStream_t s = p->s;
   p->solved = false;
@@ -549,6 +634,7 @@ int sso_solve_begin(sso_problem* p) {
 
 int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
   if (!p || !p->in_batch) return SSO_EINVAL;
+  AllocCounter ac(&p->bytes);
   hipStream_t s = p->s;
   TRY_HIP(hipMemcpyAsync(p->w.h_st, p->w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
   TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
@@ -672,6 +758,7 @@ int sso_objective(sso_problem* p, int kind, const double* a, double* g_host) {
 int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, double* dg_dt,
                 double* dg_dscale, sso_stats* stats) {
   if (!p || !p->solved || !dg_dxyz) return SSO_EINVAL;
+  AllocCounter ac(&p->bytes);
   hipStream_t s = p->s;
   double c_lam = 1.0, c_u = 1.0;
   const double* lam = p->u;
@@ -713,6 +800,7 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
 int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
                        double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats) {
   if (!size_args_ok(p, eps1, u_max, t_min, out_host, dg_dxyz)) return SSO_EINVAL;
+  AllocCounter ac(&p->bytes);
   if (!p->xpart) {
     TRY_HIP(dev_alloc(&p->xpart, 2 * SIZE_XWG, p->s));
     TRY_HIP(dev_alloc(&p->gw, 14 * (int64_t)p->m.n_quads, p->s));
@@ -763,6 +851,7 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
   if (!p) return SSO_EINVAL;
   if (p->n_coo >= ((int64_t)1 << 31) || 36 * p->pat.n_blocks >= ((int64_t)1 << 31))
     return SSO_EINVAL;
+  AllocCounter ac(&p->bytes);
   const int64_t nz = 36 * p->pat.n_blocks;
   hipStream_t s = p->s;
   if (!p->row_ptr) {
@@ -789,6 +878,12 @@ int sso_matrix(sso_problem* p, double* vals, double* f) {
     TRY_HIP(hipMemcpyAsync(f, p->f, sizeof(double) * 6 * (size_t)p->m.n_nodes,
                            hipMemcpyDeviceToDevice, p->s));
   TRY_HIP(hipStreamSynchronize(p->s));
+  return SSO_OK;
+}
+
+int sso_problem_bytes(const sso_problem* p, int64_t* bytes) {
+  if (!p || !bytes) return SSO_EINVAL;
+  *bytes = p->bytes;
   return SSO_OK;
 }
 

@@ -286,11 +286,11 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   uint64_t* keys = nullptr;
   int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE + 2;
   int64_t nk = pat.n_bcoo > 0 ? pat.n_bcoo : 1;
-  SSO_TRY(dev_alloc(&cnt, (n + 1), s));
-  SSO_TRY(dev_alloc(&fill, (n + 1), s));
-  SSO_TRY(dev_alloc(&ucnt, (n + 1), s));
-  SSO_TRY(dev_alloc(&tmp, nt, s));
-  SSO_TRY(dev_alloc(&keys, nk, s));
+  SSO_TRY(dev_alloc_scratch(&cnt, (n + 1), s));
+  SSO_TRY(dev_alloc_scratch(&fill, (n + 1), s));
+  SSO_TRY(dev_alloc_scratch(&ucnt, (n + 1), s));
+  SSO_TRY(dev_alloc_scratch(&tmp, nt, s));
+  SSO_TRY(dev_alloc_scratch(&keys, nk, s));
   SSO_TRY(dev_alloc(&pat.estart, (n + 1), s));
   SSO_TRY(dev_alloc(&pat.brow_ptr, (n + 1), s));
   SSO_TRY(dev_alloc(&pat.bperm, nk, s));

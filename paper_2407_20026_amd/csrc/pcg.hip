@@ -213,6 +213,17 @@ __device__ inline T apply_dinv(const T* dl, const T* rs, int a, int lr) {
   return z;
 }
 
+// A store of a vector entry that the iteration writes: streaming (non-temporal) for problems
+// whose K alone outgrows the caches (nothing written is read again before it would have been
+// evicted), plain otherwise (small problems read it back from cache).
+template <class T>
+__device__ __forceinline__ void put(T* p, T v, int streaming) {
+  if (streaming)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 // ---- SpMV layout: 18 lanes per block row, 3 block rows per wavefront ----------------------
 // Lane l of a row group owns entries (a, b..b+1) of every 6x6 block, a = l / 3, b = 2 (l % 3),
 // so the 18 lanes read each 288-byte block with one contiguous 16-byte load each.
@@ -541,10 +552,10 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
       const T pn = zI + beta * pI;
       const T Apq = sz + beta * sp;
       if constexpr (zp_pairs<T>())
-        pnew[2 * q + 1] = pn;
+        put(&pnew[2 * q + 1], pn, d.stream_stores);
       else
-        pnew[q] = pn;
-      Ap[q] = Apq;
+        put(&pnew[q], pn, d.stream_stores);
+      put(&Ap[q], Apq, d.stream_stores);
       my += pn * Apq;
     }
   }
@@ -566,7 +577,7 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   // every field the kernel uses in one batch of scalar loads
   asm volatile("" ::"s"(d.x), "s"(d.r), "s"(d.z), "s"(d.p[0]), "s"(d.p[1]), "s"(d.Ap),
                "s"(d.Dinv), "s"(d.pa), "s"(d.pb), "s"(d.st), "s"(d.n_nodes), "s"(d.n_wg),
-               "s"(d.wg_base));
+               "s"(d.wg_base), "s"(d.stream_stores));
   const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
   PcgState* st = d.st;
   const int n_nodes = d.n_nodes;
@@ -615,9 +626,9 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
     }
     T rn = 0;
     if (m.valid) {
-      x[q] = xv + alpha * pv;
+      put(&x[q], xv + alpha * pv, d.stream_stores);
       rn = rv - alpha * av;
-      r[q] = rn;
+      put(&r[q], rn, d.stream_stores);
     }
     rs[threadIdx.x] = rn;
     dinv_stage(gi == lb ? dc0 : dinv_load(d.Dinv, gi), dl);
@@ -625,9 +636,9 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
     if (m.valid) {
       const T zz = apply_dinv(dl, rs, m.a, m.lr);
       if constexpr (zp_pairs<T>())
-        p[2 * q] = zz;   // z_{j+1} beside p_j
+        put(&p[2 * q], zz, d.stream_stores);   // z_{j+1} beside p_j
       else
-        z[q] = zz;
+        put(&z[q], zz, d.stream_stores);
       v[0] += rn * zz;
       v[1] += rn * rn;
     }
@@ -1387,6 +1398,16 @@ static int choose_wg(int64_t n_nodes, int cap) {
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// Passes over its rows that a workgroup of the standard recurrences makes at least (below the
+// cap of PCG_MAX_WG workgroups): more passes amortise each workgroup's fixed start (descriptor,
+// state, the previous kernel's partials) over more rows.  Measured (served stream closed loop
+// of 256 requests / single 120 x 120 / single 300 x 300 shell): 1 pass 80.1 solves/s / 62.9 ms /
+// 599.6 ms; 2 passes 93.1 / 62.6 / 606.3; 4 passes 94.1 / 85.1 / 590.8; 8 passes 89.9 / 137.9 /
+// 674.3.  (The 300 x 300 shell is at the cap in every case.)
+#ifndef SSO_STD_PASSES
+#define SSO_STD_PASSES 2
+#endif
+
 // Partial-sum buffers (units of the stride S = max(n_wg, n_wg_f, 1024) doubles):
 //   [0, S) pA | [S, 3S) pB | [3S, 5S) one-off reductions, then 8 scalars |
 //   [5S + 8, 8S + 8) single-reduction even | [8S + 8, 11S + 8) single-reduction odd
@@ -1404,7 +1425,7 @@ static double* part_fused(PcgWork& w, int k) {
 
 hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s) {
   w.n_dof = 6 * n_nodes;
-  w.n_wg = choose_wg(n_nodes, PCG_MAX_WG);
+  w.n_wg = choose_wg((n_nodes + SSO_STD_PASSES - 1) / SSO_STD_PASSES, PCG_MAX_WG);
   w.n_wg_f = choose_wg(n_nodes, PCG_MAX_WG);
   hipError_t e;
   if ((e = dev_alloc(&w.r, w.n_dof , s)) != hipSuccess) return e;
@@ -1468,8 +1489,14 @@ void pcg_free(PcgWork& w, hipStream_t s) {
   w = PcgWork();
 }
 
+// K bytes from which the standard recurrences write their vectors with streaming stores: a K
+// this large (the 300 x 300 shell's is 234 MB) streams through the caches every iteration, and
+// stores that bypass them leave more room for the gathered vectors.
+static constexpr double STREAM_STORE_K_BYTES = 128.0 * (1 << 20);
+
 static constexpr int PROF_CAP = 1024;
 static constexpr int FUSED_SPAN = 8;   // launches per timing sample of the fused iteration
+static constexpr int STD_SPAN = 8;     // iterations per timing sample of the standard pair
 
 // Launch iterations in chunks of growing size (8 .. 64), reading the state record back after
 // each chunk; launch(e0, e1) enqueues one iteration, recording e0 (when not null) before the
@@ -1599,6 +1626,7 @@ static hipError_t pcg_start(const Mesh& m, const Pattern& pat, const T* K, const
   hd.n_nodes = m.n_nodes;
   hd.n_wg = w.n_wg;
   hd.wg_base = 0;
+  hd.stream_stores = 36.0 * sizeof(T) * (double)pat.n_blocks >= STREAM_STORE_K_BYTES ? 1 : 0;
   if (out) *out = hd;
   PcgDesc<T>* dd = reinterpret_cast<PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
   hipError_t e = hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, s);
@@ -1626,7 +1654,9 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
     hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
     if (e1) (void)hipEventRecord(*e1, s);
   };
-  return run_polled(w, s, max_it, profile_every, 1, launch, iters, status);
+  // a sample spans 8 back-to-back iterations (events between every pair would add their own
+  // latency to the iteration they bracket)
+  return run_polled(w, s, max_it, profile_every, STD_SPAN, launch, iters, status);
 }
 
 // Vectors of one single-reduction solve.
@@ -1906,11 +1936,12 @@ void batch_free(BatchWork& bw, hipStream_t s) {
 }
 
 // Up to this many nodes the single launch per iteration of the single-reduction recurrences wins
-// (the 60 x 60 shell: 19.1 vs 21.0 ms per solve); on large problems the standard pair streams
-// closer to the bandwidth peak (the 300 x 300 shell: 80 vs 125 us per iteration).  The limit is
-// the one-pass grid (PCG_MAX_WG workgroups of 18 block rows): the multi-pass instance of the
-// 12-slot padded rows keeps more values live than the registers hold.
-static constexpr int64_t FUSED_MAX_NODES = (int64_t)PCG_MAX_WG * ROWS_PER_WG;
+// (the 60 x 60 shell: 13.4 vs 20.2 ms per solve); from about 8,000 nodes the standard pair is as
+// fast or faster (90 x 90: 46.2 vs 45.3 ms; 120 x 120: 88 vs 63 ms), and on large problems it
+// streams closer to the bandwidth peak (the 300 x 300 shell: 80 vs 125 us per iteration).
+static constexpr int64_t FUSED_MAX_NODES = 8192;
+static_assert(FUSED_MAX_NODES <= (int64_t)PCG_MAX_WG * ROWS_PER_WG,
+              "the single-reduction recurrences run in one pass of the grid");
 
 int pcg_pick_solver(int solver, int64_t n_nodes) {
   if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED) return solver;
@@ -2182,7 +2213,7 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
         hipLaunchKernelGGL(k_update<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
         if (e1) (void)hipEventRecord(*e1, s);
       };
-      e = run_polled(w, s, cap, profile_every, 1, launch, &it, &st);
+      e = run_polled(w, s, cap, profile_every, cap >= STD_SPAN ? STD_SPAN : 1, launch, &it, &st);
     }
     if (e == hipSuccess) e = mixed_inner_done(m, pat, K, K32, Dinv32, B32, b, x, mp, w, s, ms);
   }

@@ -18,6 +18,7 @@ enum : unsigned {
   ERR_BEAM = 1u << 2,        // zero-length member or non-positive section property
   ERR_QUAD = 1u << 3,        // det J <= 0, zero area, bad t/E/nu, kx/ky != 1
   ERR_DIAG = 1u << 4,        // diagonal 6x6 block not positive definite
+  ERR_TOPO = 1u << 5,        // connectivity differs from the problem whose pattern is shared
 };
 
 // PCG scalar state record in device memory (written by workgroup 0 of the PCG kernels, polled
@@ -53,7 +54,8 @@ struct PcgDesc {
   double* pa;
   double* pb;
   PcgState* st;
-  int n_nodes, n_wg, wg_base, pad;
+  int n_nodes, n_wg, wg_base;
+  int stream_stores;   // 1: the vectors an iteration writes go out as streaming stores
 };
 
 // One problem of a single-reduction PCG launch (one kernel and one reduction per iteration).
@@ -161,12 +163,31 @@ __host__ __device__ inline int64_t coo_index(const BlockRef& r, int ca, int cb, 
   return 144 * (int64_t)n_beams + 576 * (int64_t)r.e + 24 * (6 * r.la + ca) + 6 * r.lb + cb;
 }
 
+// Device memory held by a problem: while an entry point works on a problem, an AllocCounter
+// points this thread's counter at the problem's byte count, and every dev_alloc adds to it
+// (sso_problem_bytes).  Buffers freed again within the call use dev_alloc_scratch instead.
+inline thread_local int64_t* alloc_counter = nullptr;
+struct AllocCounter {
+  int64_t* prev;
+  explicit AllocCounter(int64_t* c) : prev(alloc_counter) { alloc_counter = c; }
+  ~AllocCounter() { alloc_counter = prev; }
+  AllocCounter(const AllocCounter&) = delete;
+  AllocCounter& operator=(const AllocCounter&) = delete;
+};
+
 // Stream-ordered device memory: no device-wide synchronisation, so problems that live on
 // different streams keep overlapping while others are created or destroyed.
 template <class T>
-inline hipError_t dev_alloc(T** p, int64_t n, hipStream_t s) {
+inline hipError_t dev_alloc_scratch(T** p, int64_t n, hipStream_t s) {
   if (n <= 0) n = 1;
   return hipMallocAsync(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n, s);
+}
+template <class T>
+inline hipError_t dev_alloc(T** p, int64_t n, hipStream_t s) {
+  if (n <= 0) n = 1;
+  const hipError_t e = dev_alloc_scratch(p, n, s);
+  if (e == hipSuccess && alloc_counter) *alloc_counter += (int64_t)sizeof(T) * n;
+  return e;
 }
 inline void dev_free(void* p, hipStream_t s) {
   if (p) (void)hipFreeAsync(p, s);

@@ -19,6 +19,7 @@ request's lifetime.
 from __future__ import annotations
 
 import collections
+import hashlib
 import threading
 import time
 from dataclasses import dataclass, field
@@ -29,24 +30,37 @@ import torch
 from . import Options, Problem
 
 
-def footprint_bytes(mesh, mixed: bool = False) -> int:
-    """Upper bound of the device memory one problem holds (mesh, pattern, element list, K,
-    preconditioner, B = K M of the single-reduction PCG, PCG vectors, gradients)."""
+# sso_solve's automatic choice of the single-reduction recurrences (which keep B = K M beside
+# K) stops at this many nodes (include/hipsso.h, SSO_SOLVER_AUTO)
+FUSED_MAX_NODES = 8192
+
+
+def footprint_bytes(mesh, mixed: bool | None = False) -> int:
+    """Upper bound of the device memory one problem holds after its forward and adjoint
+    (mesh copies, pattern, element list, K, packed preconditioner, B = K M of the
+    single-reduction PCG or the FP32 copies of mixed precision, solver vectors, gradients).
+    mixed=None: the precision is picked by the library (AUTO), either bound.  Checked against
+    the library's own count (sso_problem_bytes) in the serving tests."""
+    if mixed is None:
+        return max(footprint_bytes(mesh, False), footprint_bytes(mesh, True))
     nn, nb, nq = mesh.n_nodes, mesh.n_beams, mesh.n_quads
     blocks = nn + 2 * nb + 12 * nq                  # diagonal + off-diagonal blocks (bound)
+    padded = 12 * nn                                # padded block rows, 12 slots at most
     nbcoo = 4 * nb + 16 * nq
     ndof = 6 * nn
+    dinv = 21 * (nn + 63) // 64 * 64                # packed inverses, whole groups of 64
     b = 0
     b += nn * (3 * 8 + 6 + 6 * 8) + nb * (8 + 48) + nq * (16 + 40 + 8)        # mesh copies
-    b += 4 * (3 * nbcoo + 3 * blocks + 4 * nn)                                  # pattern
-    b += 8 * (144 * nb + 576 * nq)                                              # element list
-    b += 288 * blocks + 288 * nn                                                # K, Dinv
-    b += 8 * ndof * 12 + 8 * (6 * nb + 14 * nq)                                 # vectors, grads
+    b += 4 * (3 * nbcoo + 3 * blocks + 4 * nn + padded)                         # pattern
+    b += 8 * (144 * nb + 576 * nq) + 8 * nq                                     # elements
+    b += 288 * blocks + 8 * dinv                                                # K, Dinv
+    b += 8 * ndof * 14 + 8 * (6 * nb + 14 * nq)                                 # vectors, grads
+    b += 8 * 11 * 1024 + 4096                                                   # partials
     if mixed:
-        b += 144 * blocks + 144 * nn + 4 * ndof * 9       # B (or K) and Dinv in FP32, vectors
-    else:
-        b += 288 * blocks                                 # B in FP64
-    return int(b * 1.1) + (1 << 20)
+        b += 144 * max(blocks, padded) + 4 * dinv + 4 * ndof * 9 + 4 * ndof * 2
+    elif nn <= FUSED_MAX_NODES:
+        b += 288 * max(blocks, padded)  # B = K M in FP64 (single-reduction recurrences)
+    return int(b * 1.05) + (1 << 20)
 
 
 @dataclass
@@ -70,6 +84,7 @@ class Result:
     done: float
     status: int = 0              # SSO_OK, or SSO_ENOTCONV (stopped above rtol)
     rel_residual: float = 0.0    # true relative residual of the solve
+    outer_steps: int = 0         # FP64 outer steps (> 0: the request ran in mixed precision)
 
     @property
     def latency(self) -> float:
@@ -97,6 +112,16 @@ def _convergence(results) -> dict:
     """How many requests stopped above rtol, and the largest true residual."""
     return {"not_converged": sum(1 for r in results if r.status != 0),
             "max_rel_residual": max((r.rel_residual for r in results), default=0.0)}
+
+
+def topology_key(mesh):
+    """Requests with equal keys have the same node, member and quad counts and connectivity,
+    so one problem's pattern can be shared with the next (sso_problem_create_like)."""
+    h = hashlib.blake2b(digest_size=16)
+    for a in (mesh.beam_nodes, mesh.quad_nodes):
+        h.update(np.ascontiguousarray(a, dtype=np.int32).tobytes())
+    return (int(mesh.n_nodes), int(mesh.beam_nodes.shape[0]), int(mesh.quad_nodes.shape[0]),
+            h.hexdigest())
 
 
 def errors_against(results, reference) -> list[dict]:
@@ -134,7 +159,7 @@ def run_one(req: Request, options: Options, stream=None, device="cuda") -> Resul
         gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
     t1 = time.perf_counter()
     return Result(req.rid, req.mesh.n_dof, g, gx, gt, st["iters"], 0.0, t0, t1,
-                  p.last_status, st["rel_residual"])
+                  p.last_status, st["rel_residual"], st["refine_steps"])
 
 
 class Server:
@@ -147,7 +172,8 @@ class Server:
         self.budget = hbm_budget
         self.options = options or Options()
         self.device = torch.device(device)
-        self.mixed = self.options.precision == 1
+        # FP64, mixed, or AUTO (the library picks per problem: either footprint)
+        self.mixed = {0: False, 1: True}.get(self.options.precision)
 
     def run(self, requests: list[Request]) -> ServeStats:
         reqs = sorted(requests, key=lambda r: r.arrival)
@@ -241,7 +267,7 @@ def finish_one(p: Problem, req: Request):
     gr = p.adjoint(req.objective)
     gx = gr["dg_dxyz"].cpu().numpy()
     gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
-    return g, gx, gt, st["iters"], p.last_status, st["rel_residual"]
+    return g, gx, gt, st["iters"], p.last_status, st["rel_residual"], st["refine_steps"]
 
 
 class BatchedServer:
@@ -249,11 +275,14 @@ class BatchedServer:
     flight advance together in multi-problem launches on one stream."""
 
     def __init__(self, slots: int = 64, hbm_budget: int = 64 << 30,
-                 options: Options | None = None, device="cuda", chunk: int = 32):
+                 options: Options | None = None, device="cuda", chunk: int = 32,
+                 share_patterns: bool = True):
+        self.share_patterns = share_patterns
         self.slots = slots
         self.budget = hbm_budget
         self.options = options or Options()
-        self.mixed = self.options.precision == 1
+        # FP64, mixed, or AUTO (the library picks per problem: either footprint)
+        self.mixed = {0: False, 1: True}.get(self.options.precision)
         self.device = torch.device(device)
         self.chunk = chunk
 
@@ -267,6 +296,7 @@ class BatchedServer:
         batch = Batch(stream, self.device)
         waiting = collections.deque()
         active = []          # (problem, request, admitted time, footprint)
+        live = collections.defaultdict(set)   # topology -> problems in flight (shared patterns)
         results: list[Result] = []
         free = self.budget
         peak_inflight = peak_bytes = 0
@@ -289,7 +319,13 @@ class BatchedServer:
                     req = waiting.popleft()
                     need = footprint_bytes(req.mesh, self.mixed)
                     free -= need
-                    p = Problem(req.mesh, self.options, device=self.device, stream=stream)
+                    key = topology_key(req.mesh) if self.share_patterns else None
+                    like = next(iter(live[key]), None) if key in live else None
+                    p = Problem(req.mesh, self.options, device=self.device, stream=stream,
+                                like=like)
+                    p.topology = key
+                    if key is not None:
+                        live[key].add(p)
                     p.solve_begin()
                     active.append((p, req, clock(), need))
                 t1 = time.perf_counter()
@@ -309,11 +345,13 @@ class BatchedServer:
                     if not flag:
                         still.append((p, req, adm, need))
                         continue
-                    g, gx, gt, iters, status, rres = finish_one(p, req)
+                    g, gx, gt, iters, status, rres, outer = finish_one(p, req)
+                    if p.topology is not None:
+                        live[p.topology].discard(p)
                     p.close()
                     free += need
                     results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
-                                          req.arrival, adm, clock(), status, rres))
+                                          req.arrival, adm, clock(), status, rres, outer))
                 active = still
                 phase["finish"] += time.perf_counter() - t2
         finally:

@@ -91,6 +91,7 @@ static void abi_argument_paths() {
   CHECK(sso_pattern(nullptr, &a0, &a1, &a2, &a3, &i0, &i1) == SSO_EINVAL);
   CHECK(sso_matrix(nullptr, nullptr, nullptr) == SSO_EINVAL);
   CHECK(sso_sizes(nullptr, &i0, &i1, &i2) == SSO_EINVAL);
+  CHECK(sso_problem_bytes(nullptr, &i0) == SSO_EINVAL);
   for (int k = -10; k <= 5; ++k) CHECK(sso_strerror(k) && std::strlen(sso_strerror(k)) > 0);
   sso_problem_destroy(nullptr);
   sso_batch_destroy(nullptr);

@@ -222,3 +222,18 @@ def test_mixed_precision_flexible_cg_at_full_size(big, ref):
         eor = np.abs(gm - g_ref).max() / np.abs(g_ref).max()
         print(f"  {name}: against the FP64 path {e64:.3e}, against the oracle {eor:.3e}")
         assert e64 <= 1e-8 and eor <= 1e-8, name
+
+
+def test_auto_precision_picks_mixed_at_full_size(big, ref):
+    """SSO_PREC_AUTO on the 300x300 shell (K of 234 MB, above the 128 MiB crossover) runs the
+    FP32 inner solves (capped at 30 iterations by the policy) and meets the same bars as FP64."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] large shell 300x300: AUTO precision", flush=True)
+    with sso.Problem(big["mesh"], sso.Options(precision=sso.PREC_AUTO, rtol=1e-10,
+                                              max_it=400000)) as p:
+        u, st = p.solve(check=False)
+        status = p.last_status
+    u = u.cpu().numpy().ravel()
+    print(f"  status={status} outer={st['refine_steps']} inner iters={st['iters']}")
+    assert status == 0 and st["refine_steps"] > 0
+    assert _check_against_reference(ref, u, 1e-10, "auto") <= 1e-10

@@ -65,3 +65,18 @@ def test_mixed_and_fp64_agree_on_the_same_gpu():
     print(f"[gpu] fp64 vs mixed: |du|/|u|={d:.2e} iters {out[0][1]['iters']} / "
           f"{out[1][1]['iters']}")
     assert d <= 1e-6
+
+
+def test_auto_precision_runs_fp64_below_the_crossover():
+    """SSO_PREC_AUTO on a problem whose K stays in the caches runs plain FP64: no outer steps,
+    and u bitwise that of the FP64 precision."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] AUTO precision below the crossover", flush=True)
+    mesh = meshgen.shell(40, seed=17)
+    us = {}
+    for name, prec in (("auto", sso.PREC_AUTO), ("fp64", sso.PREC_FP64)):
+        with sso.Problem(mesh, sso.Options(rtol=1e-10, precision=prec)) as p:
+            u, st = p.solve()
+            us[name] = (u.cpu(), st["refine_steps"])
+    assert us["auto"][1] == 0
+    assert torch.equal(us["auto"][0], us["fp64"][0])

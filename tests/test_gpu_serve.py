@@ -252,3 +252,71 @@ def test_mixed_served_results_report_their_error_against_fp64(served_sample):
         assert e.get("dg_dt_rel_inf", 0.0) <= 1e-8
     print("  mixed vs FP64: max g", max(e["g_rel"] for e in errs), "max dc/dxyz",
           max(e["dg_dxyz_rel_inf"] for e in errs))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_footprint_bounds_what_the_library_allocates(precision):
+    """Admission's footprint estimate against the library's own count of the device memory a
+    problem holds after its forward and adjoint (sso_problem_bytes): an upper bound, and not a
+    gross one, on a sample of the stream's sizes (both element kinds, smallest to largest)."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import footprint_bytes
+    print(f"[gpu] footprint vs allocation, {precision}", flush=True)
+    mixed = precision == "mixed"
+    opts = sso.Options(rtol=1e-8, precision=sso.PREC_MIXED if mixed else sso.PREC_FP64)
+    for i in (0, 1, 3, 4, 6, 10, 11, 51):
+        mesh = meshgen.served_request(i)
+        with sso.Problem(mesh, opts) as p:
+            p.solve(check=False)
+            p.adjoint("compliance")
+            held = p.device_bytes()
+        est = footprint_bytes(mesh, mixed)
+        print(f"  {mesh.name}: held {held / 2**20:.2f} MiB, estimate {est / 2**20:.2f} MiB")
+        assert 0 < held <= est <= 1.6 * held + (2 << 20), mesh.name
+
+
+def test_problems_sharing_a_pattern_match_problems_with_their_own():
+    """sso_problem_create_like: a problem of the same topology shares the first one's pattern and
+    gives bitwise the same results as one created on its own, whichever of the two is destroyed
+    first; a different connectivity or size is rejected."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] shared patterns", flush=True)
+    a_mesh, b_mesh = meshgen.shell(14, seed=41), meshgen.shell(14, seed=42)
+    opts = sso.Options(rtol=1e-10)
+    with sso.Problem(b_mesh, opts) as own:
+        u_own, _ = own.solve()
+        g_own = own.adjoint("compliance")["dg_dxyz"].cpu()
+        u_own = u_own.cpu()
+    first = sso.Problem(a_mesh, opts)
+    second = sso.Problem(b_mesh, opts, like=first)
+    first.close()                       # the pattern outlives the problem that built it
+    u, _ = second.solve()
+    g = second.adjoint("compliance")["dg_dxyz"].cpu()
+    assert torch.equal(u.cpu(), u_own) and torch.equal(g, g_own)
+    third = sso.Problem(a_mesh, opts, like=second)
+    second.close()
+    third.solve()
+    third.close()
+    other = meshgen.shell(14, seed=43)
+    other.quad_nodes = other.quad_nodes[:, [1, 2, 3, 0]].copy()   # same counts, other connectivity
+    with sso.Problem(a_mesh, opts) as base:
+        with pytest.raises(sso.SSOError) as e:
+            sso.Problem(other, opts, like=base)
+        assert e.value.status == sso.SSO_EINVAL
+        with pytest.raises(sso.SSOError):
+            sso.Problem(meshgen.shell(13, seed=44), opts, like=base)
+
+
+def test_batched_server_with_shared_patterns_matches_solves_alone():
+    """The batched loop shares patterns between requests of one topology in flight: each result
+    is still bitwise that of the request solved alone with the same recurrences."""
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import BatchedServer, Request, run_one
+    print("[gpu] batched serve with shared patterns", flush=True)
+    opts = sso.Options(rtol=1e-10, solver=sso.SOLVER_STANDARD)
+    reqs = [Request(i, meshgen.shell(12, seed=60 + i) if i % 2 else meshgen.gridshell(10, seed=i),
+                    0.0) for i in range(10)]
+    stats = BatchedServer(slots=10, options=opts, chunk=16).run(reqs)
+    for r, req in zip(stats.results, reqs):
+        alone = run_one(req, opts)
+        assert r.g == alone.g and np.array_equal(r.grad_xyz, alone.grad_xyz)
