@@ -390,6 +390,17 @@ def test_invalid_inputs_are_rejected():
         with pytest.raises(sso.SSOError) as e:
             p.solve()
         assert e.value.status == sso.SSO_EINVAL
+    # a concave (dart-shaped) quad: its third corner pulled to a tenth of the way from the first,
+    # so det J < 0 at the Gauss point next to that re-entrant corner, though the diagonals still
+    # give a positive area
+    s = small_shell(3)
+    s.xyz = s.xyz.copy()
+    a, b, c, d = s.quad_nodes[4]
+    s.xyz[c, :2] = s.xyz[a, :2] + 0.1 * (s.xyz[c, :2] - s.xyz[a, :2])
+    with _problem(s) as p:
+        with pytest.raises(sso.SSOError) as e:
+            p.solve()
+        assert e.value.status == sso.SSO_EINVAL
 
 
 def test_every_dof_fixed_gives_zero_solution():
