@@ -216,7 +216,24 @@ int sso_batch_create(hipStream_t stream, sso_batch** out);
  * iteration has stopped (converged, limit or breakdown).  Errors: SSO_EINVAL (problem not
  * begun, on another stream, or listed twice), SSO_EHIP. */
 int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, int32_t* done);
+/* sso_batch_iterate in two halves, so that the host can work while the GPU iterates:
+ * sso_batch_launch enqueues the n_iter iterations and the copy of the problems' states to pinned
+ * host memory and returns at once; sso_batch_wait(b, ps, n, done) waits for them, then does what
+ * sso_batch_iterate does after its launches (mixed precision's outer steps, done flags).  The
+ * wait must list the same problems in the same order as the launch; between the two, the listed
+ * problems may not be iterated, ended, moved to another stream or destroyed, and a batch holds at
+ * most one pending launch.  Errors: SSO_EINVAL (as sso_batch_iterate; a launch while one is
+ * pending; a wait without a launch or with another list), SSO_EHIP. */
+int sso_batch_launch(sso_batch* b, sso_problem* const* ps, int n, int n_iter);
+int sso_batch_wait(sso_batch* b, sso_problem* const* ps, int n, int32_t* done);
 void sso_batch_destroy(sso_batch* b);
+
+/* Move a problem's work to another stream (e.g. between a stream that admits and finishes
+ * requests and the stream of a multi-problem launcher): the new stream is ordered after all work
+ * already enqueued for the problem on its old stream (an event), and every later call enqueues on
+ * the new one.  Errors: SSO_EINVAL (NULL problem, or listed in a pending sso_batch_launch),
+ * SSO_EHIP. */
+int sso_problem_set_stream(sso_problem* p, hipStream_t stream);
 
 /* Objective value g(u) of the last solve (the objective of Sec. 2.3.1, Eq. (4)) into *g_host
  * (host): compliance f^T u (the loss of the network example, Sec. 3.6), strain energy f^T u / 2
@@ -315,7 +332,19 @@ int sso_sizes(const sso_problem* p, int64_t* n_dof, int64_t* n_blocks, int64_t* 
 
 const char* sso_strerror(int status);
 
+/* Frees the problem's device memory (stream-ordered on its stream, then waits for that stream)
+ * and its host state. */
 void sso_problem_destroy(sso_problem* p);
+
+/* Device memory: every buffer the library allocates comes from a memory pool of its own on the
+ * problem's device, which keeps freed memory for the next allocation instead of returning it to
+ * the driver (a request loop creates and destroys problems of recurring sizes; mapping fresh
+ * memory each time cost about 1 ms per problem).  The pool therefore holds up to the peak of what
+ * problems held at once.  sso_pool_trim releases what the pool holds beyond keep_bytes of unused
+ * memory back to the driver; memory freed on a stream whose work has not completed is released
+ * by a later call.  device: HIP device ordinal.  Errors: SSO_EINVAL (bad ordinal), SSO_EHIP.
+ * A device whose pool was never used returns SSO_OK. */
+int sso_pool_trim(int device, uint64_t keep_bytes);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,8 @@ EXPORTS = ("sso_problem_create", "sso_problem_create_like", "sso_problem_update"
            "sso_batch_destroy", "sso_objective", "sso_adjoint", "sso_pattern", "sso_matrix",
            "sso_sizes", "sso_strerror", "sso_problem_destroy", "sso_size_objective",
            "sso_size_objective_noalloc", "sso_size_penalty_update", "sso_hat_filter",
-           "sso_problem_bytes")
+           "sso_problem_bytes", "sso_batch_launch", "sso_batch_wait", "sso_problem_set_stream",
+           "sso_pool_trim")
 
 _lib = None
 _hip = None
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 P(ctypes.c_int64)]
     lib.sso_matrix.argtypes = [_vp, _vp, _vp]
     lib.sso_sizes.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.sso_pool_trim.argtypes = [ctypes.c_int, ctypes.c_uint64]
     lib.sso_problem_bytes.argtypes = [_vp, P(ctypes.c_int64)]
     lib.sso_solve_begin.argtypes = [_vp]
     lib.sso_solve_end.argtypes = [_vp, _vp, P(sso_stats)]
@@ -103,6 +105,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sso_size_penalty_update.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             P(ctypes.c_double)]
     lib.sso_hat_filter.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_double, _vp]
+    lib.sso_batch_launch.argtypes = [_vp, P(_vp), ctypes.c_int, ctypes.c_int]
+    lib.sso_batch_wait.argtypes = [_vp, P(_vp), ctypes.c_int, P(ctypes.c_int32)]
+    lib.sso_problem_set_stream.argtypes = [_vp, _vp]
     lib.sso_batch_destroy.argtypes = [_vp]
     lib.sso_batch_destroy.restype = None
     lib.sso_strerror.argtypes = [ctypes.c_int]
@@ -130,6 +135,12 @@ class SSOError(RuntimeError):
         self.status = status
         msg = load_library().sso_strerror(status).decode()
         super().__init__(f"{where}: {msg} (status {status})")
+
+
+def pool_trim(device=0, keep_bytes: int = 0) -> None:
+    """Release the library's cached device memory beyond keep_bytes (sso_pool_trim)."""
+    dev = torch.device(device) if not isinstance(device, int) else torch.device("cuda", device)
+    _check(load_library().sso_pool_trim(dev.index or 0, keep_bytes), "sso_pool_trim")
 
 
 def _check(status: int, where: str) -> int:
@@ -277,6 +288,13 @@ class Problem:
             _check(status, "sso_solve")
         return u_out, self.last_stats
 
+    def set_stream(self, stream):
+        """Move the problem's work to `stream` (sso_problem_set_stream): ordered after the work
+        already enqueued on its old stream."""
+        _check(load_library().sso_problem_set_stream(self.handle, _stream_handle(stream)),
+               "sso_problem_set_stream")
+        self.stream = stream
+
     def solve_begin(self):
         """Everything up to the first PCG iteration; then iterate with :class:`Batch`."""
         self.generation += 1
@@ -411,6 +429,20 @@ class Batch:
         done = (ctypes.c_int32 * max(n, 1))()
         _check(load_library().sso_batch_iterate(self.handle, arr, n, n_iter, done),
                "sso_batch_iterate")
+        return [bool(done[i]) for i in range(n)]
+
+    def launch(self, problems, n_iter: int):
+        """Enqueue n_iter iterations of every begun, unfinished problem and return at once
+        (sso_batch_launch); wait(problems) with the same list collects the done flags."""
+        n = len(problems)
+        arr = (ctypes.c_void_p * max(n, 1))(*[p.handle for p in problems])
+        _check(load_library().sso_batch_launch(self.handle, arr, n, n_iter), "sso_batch_launch")
+
+    def wait(self, problems):
+        n = len(problems)
+        arr = (ctypes.c_void_p * max(n, 1))(*[p.handle for p in problems])
+        done = (ctypes.c_int32 * max(n, 1))()
+        _check(load_library().sso_batch_wait(self.handle, arr, n, done), "sso_batch_wait")
         return [bool(done[i]) for i in range(n)]
 
     def close(self):

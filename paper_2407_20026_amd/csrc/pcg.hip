@@ -1878,9 +1878,10 @@ static hipError_t fused_upload(std::map<int, LaunchTable<FusedDesc<T>>>& tables,
   return hipSuccess;
 }
 
-hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hipStream_t s) {
+hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipStream_t s) {
   const int nt = (int)(L.standard.size() + L.fused.size() + L.standard32.size() +
                        L.fused32.size());
+  bw.pending_nt = nt;
   if (nt <= 0) return hipSuccess;
   hipError_t e;
   if ((e = table_upload(bw.standard, L.standard.data(), (int)L.standard.size(), s)) !=
@@ -1918,14 +1919,48 @@ hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hip
   hipLaunchKernelGGL(k_gather_states, dim3((nt + 63) / 64), dim3(64), 0, s, bw.d_stp, nt,
                      bw.d_states);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bw.h_states.resize(nt);
-  if ((e = hipMemcpyAsync(bw.h_states.data(), bw.d_states, sizeof(PcgState) * nt,
-                          hipMemcpyDeviceToHost, s)) != hipSuccess)
+  if (nt > bw.cap_pin) {   // no copy into the old buffer is pending: the last launch was waited for
+    if (bw.h_pin) (void)hipHostFree(bw.h_pin);
+    bw.h_pin = nullptr;
+    bw.cap_pin = 0;
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&bw.h_pin), sizeof(PcgState) * 2 * nt,
+                           hipHostMallocDefault)) != hipSuccess)
+      return e;
+    bw.cap_pin = 2 * nt;
+  }
+  if (!bw.ev && (e = hipEventCreateWithFlags(&bw.ev, hipEventDisableTiming)) != hipSuccess)
     return e;
-  return hipStreamSynchronize(s);
+  if ((e = hipMemcpyAsync(bw.h_pin, bw.d_states, sizeof(PcgState) * nt, hipMemcpyDeviceToHost,
+                          s)) != hipSuccess)
+    return e;
+  return hipEventRecord(bw.ev, s);
+}
+
+hipError_t pcg_batch_wait(BatchWork& bw) {
+  const int nt = bw.pending_nt;
+  bw.pending_nt = -1;
+  if (nt <= 0) {
+    bw.h_states.clear();
+    return hipSuccess;
+  }
+  hipError_t e = hipEventSynchronize(bw.ev);
+  if (e != hipSuccess) return e;
+  bw.h_states.assign(bw.h_pin, bw.h_pin + nt);
+  return hipSuccess;
+}
+
+hipError_t pcg_batch_iterate(const BatchLists& L, int n_iter, BatchWork& bw, hipStream_t s) {
+  hipError_t e = pcg_batch_launch(L, n_iter, bw, s);
+  if (e != hipSuccess) return e;
+  return pcg_batch_wait(bw);
 }
 
 void batch_free(BatchWork& bw, hipStream_t s) {
+  if (bw.ev) {
+    (void)hipEventSynchronize(bw.ev);
+    (void)hipEventDestroy(bw.ev);
+  }
+  if (bw.h_pin) (void)hipHostFree(bw.h_pin);
   table_free(bw.standard, s);
   for (auto& kv : bw.fused) table_free(kv.second, s);
   table_free(bw.standard32, s);

@@ -175,12 +175,14 @@ struct AllocCounter {
   AllocCounter& operator=(const AllocCounter&) = delete;
 };
 
-// Stream-ordered device memory: no device-wide synchronisation, so problems that live on
-// different streams keep overlapping while others are created or destroyed.
+// Stream-ordered device memory from the library's pool on the stream's device (api.hip): no
+// device-wide synchronisation, so problems that live on different streams keep overlapping
+// while others are created or destroyed, and freed memory is reused without remapping.
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 template <class T>
 inline hipError_t dev_alloc_scratch(T** p, int64_t n, hipStream_t s) {
   if (n <= 0) n = 1;
-  return hipMallocAsync(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n, s);
+  return pool_alloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n, s);
 }
 template <class T>
 inline hipError_t dev_alloc(T** p, int64_t n, hipStream_t s) {
@@ -363,6 +365,12 @@ struct BatchWork {
   std::vector<PcgState*> h_stp;
   std::vector<PcgState> h_states;
   int64_t launched = 0;
+  // asynchronous form: the states of the launched problems land in pinned memory, and an event
+  // marks when they are there
+  PcgState* h_pin = nullptr;
+  int cap_pin = 0;
+  hipEvent_t ev = nullptr;
+  int pending_nt = -1;    // problems of the launch not yet waited for (-1: none pending)
 };
 hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,
@@ -377,6 +385,10 @@ struct BatchLists {
   std::vector<PcgDesc<float>> standard32;   // FP32 inner solves of mixed precision
   std::vector<FusedDesc<float>> fused32;
 };
+// The same in two halves: pcg_batch_launch enqueues the iterations and the copy of the states to
+// pinned host memory and returns; pcg_batch_wait waits for them and fills bw.h_states.
+hipError_t pcg_batch_launch(const BatchLists& lists, int n_iter, BatchWork& bw, hipStream_t s);
+hipError_t pcg_batch_wait(BatchWork& bw);
 // Launch n_iter iterations for every listed problem, one launch per kernel and kind, then copy
 // their state records into bw.h_states in list order (standard, fused, standard32, fused32;
 // synchronises the stream).

@@ -6,10 +6,12 @@ frees its slot and its memory at once and the next waiting request is admitted. 
 the loops record arrival, admission and completion times, so p50/p99 latency (arrival to
 result) and throughput (solves/s, DOF/s) are reported side by side.
 
-* :class:`BatchedServer` -- one host thread and one stream: every admitted request's PCG
-  iterations run in shared launches (``sso_batch_iterate``: one launch per kernel for all
-  requests in flight, each request on its own range of workgroups); requests join and leave at
-  the chunk boundaries.  FP64 or mixed precision (FP32 inner iterations, FP64 refinement).
+* :class:`BatchedServer` -- one host thread: every admitted request's PCG iterations run in
+  shared launches on one stream (``sso_batch_launch`` / ``sso_batch_wait``: one launch per
+  kernel for all requests in flight, each request on its own range of workgroups); requests are
+  admitted and finished on a second stream while the next chunk runs, and join and leave the
+  iterations at the chunk boundaries.  FP64, mixed precision (FP32 inner iterations, FP64
+  refinement) or AUTO.
 * :class:`Server` -- one host thread and one HIP stream per slot, each slot solving its request
   with ``sso_solve``.
 
@@ -272,12 +274,21 @@ def finish_one(p: Problem, req: Request):
 
 class BatchedServer:
     """Admission by slot count and device-memory budget; the iterations of all requests in
-    flight advance together in multi-problem launches on one stream."""
+    flight advance together in multi-problem launches on one stream.
+
+    overlap=True (default): requests are admitted (creation, elements, assembly, PCG start) and
+    finished (true residual, objective, adjoint, copies) on a second stream while the next chunk
+    of iterations runs: the loop launches a chunk (sso_batch_launch), does the host and admission
+    work of the requests that stopped at the previous poll or arrived since, then waits for the
+    chunk (sso_batch_wait).  A request moves to the launcher's stream when it joins the
+    iterations and back when it stops (sso_problem_set_stream).  The kernels and their
+    decomposition are the same either way, so every result is bitwise the same."""
 
     def __init__(self, slots: int = 64, hbm_budget: int = 64 << 30,
                  options: Options | None = None, device="cuda", chunk: int = 32,
-                 share_patterns: bool = True):
+                 share_patterns: bool = True, overlap: bool = True):
         self.share_patterns = share_patterns
+        self.overlap = overlap
         self.slots = slots
         self.budget = hbm_budget
         self.options = options or Options()
@@ -292,10 +303,13 @@ class BatchedServer:
         for r in reqs:
             if footprint_bytes(r.mesh, self.mixed) > self.budget:
                 raise ValueError(f"request {r.rid} can never be admitted: footprint above budget")
-        stream = torch.cuda.Stream(device=self.device)
-        batch = Batch(stream, self.device)
+        it_stream = torch.cuda.Stream(device=self.device)
+        aux = torch.cuda.Stream(device=self.device) if self.overlap else it_stream
+        batch = Batch(it_stream, self.device)
         waiting = collections.deque()
-        active = []          # (problem, request, admitted time, footprint)
+        active = []          # iterating: (problem, request, admitted time, footprint)
+        joining = []         # begun on the admission stream, join at the next launch
+        finishing = []       # stopped at the last poll, finished on the admission stream
         live = collections.defaultdict(set)   # topology -> problems in flight (shared patterns)
         results: list[Result] = []
         free = self.budget
@@ -307,55 +321,73 @@ class BatchedServer:
         def clock():
             return time.perf_counter() - t_start
 
+        def admit():
+            nonlocal free
+            while waiting and len(active) + len(joining) < self.slots and \
+                    footprint_bytes(waiting[0].mesh, self.mixed) <= free:
+                req = waiting.popleft()
+                need = footprint_bytes(req.mesh, self.mixed)
+                free -= need
+                key = topology_key(req.mesh) if self.share_patterns else None
+                like = next(iter(live[key]), None) if key in live else None
+                p = Problem(req.mesh, self.options, device=self.device, stream=aux, like=like)
+                p.topology = key
+                if key is not None:
+                    live[key].add(p)
+                p.solve_begin()
+                joining.append((p, req, clock(), need))
+
+        def finish():
+            nonlocal free
+            for p, req, adm, need in finishing:
+                g, gx, gt, iters, status, rres, outer = finish_one(p, req)
+                if p.topology is not None:
+                    live[p.topology].discard(p)
+                p.close()
+                free += need
+                results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
+                                      req.arrival, adm, clock(), status, rres, outer))
+            finishing.clear()
+
         try:
             while len(results) < len(reqs):
                 now = clock()
                 while nxt < len(reqs) and reqs[nxt].arrival <= now:
                     waiting.append(reqs[nxt])
                     nxt += 1
-                t0 = time.perf_counter()
-                while waiting and len(active) < self.slots and \
-                        footprint_bytes(waiting[0].mesh, self.mixed) <= free:
-                    req = waiting.popleft()
-                    need = footprint_bytes(req.mesh, self.mixed)
-                    free -= need
-                    key = topology_key(req.mesh) if self.share_patterns else None
-                    like = next(iter(live[key]), None) if key in live else None
-                    p = Problem(req.mesh, self.options, device=self.device, stream=stream,
-                                like=like)
-                    p.topology = key
-                    if key is not None:
-                        live[key].add(p)
-                    p.solve_begin()
-                    active.append((p, req, clock(), need))
-                t1 = time.perf_counter()
-                phase["admit"] += t1 - t0
+                for item in joining:
+                    item[0].set_stream(it_stream)
+                    active.append(item)
+                joining.clear()
                 peak_inflight = max(peak_inflight, len(active))
                 peak_bytes = max(peak_bytes, self.budget - free)
-                if not active:
-                    if nxt < len(reqs):
-                        time.sleep(max(0.0, reqs[nxt].arrival - clock()))
-                    phase["idle"] += time.perf_counter() - t1
-                    continue
-                done = batch.iterate([a[0] for a in active], self.chunk)
+                t0 = time.perf_counter()
+                if active:
+                    batch.launch([a[0] for a in active], self.chunk)
+                # while the chunk runs: finish what stopped at the last poll, admit arrivals
+                t1 = time.perf_counter()
+                finish()
                 t2 = time.perf_counter()
-                phase["iterate"] += t2 - t1
-                still = []
-                for flag, (p, req, adm, need) in zip(done, active):
-                    if not flag:
-                        still.append((p, req, adm, need))
-                        continue
-                    g, gx, gt, iters, status, rres, outer = finish_one(p, req)
-                    if p.topology is not None:
-                        live[p.topology].discard(p)
-                    p.close()
-                    free += need
-                    results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
-                                          req.arrival, adm, clock(), status, rres, outer))
-                active = still
-                phase["finish"] += time.perf_counter() - t2
+                admit()
+                t3 = time.perf_counter()
+                phase["finish"] += t2 - t1
+                phase["admit"] += t3 - t2
+                if active:
+                    done = batch.wait([a[0] for a in active])
+                    still = []
+                    for flag, item in zip(done, active):
+                        if flag:
+                            item[0].set_stream(aux)
+                            finishing.append(item)
+                        else:
+                            still.append(item)
+                    active = still
+                    phase["iterate"] += (t1 - t0) + (time.perf_counter() - t3)
+                elif not joining and not finishing and nxt < len(reqs):
+                    time.sleep(max(0.0, reqs[nxt].arrival - clock()))
+                    phase["idle"] += time.perf_counter() - t3
         finally:
-            for p, *_ in active:
+            for p, *_ in active + joining + finishing:
                 p.close()
             batch.close()
         wall = clock()

@@ -92,6 +92,12 @@ static void abi_argument_paths() {
   CHECK(sso_matrix(nullptr, nullptr, nullptr) == SSO_EINVAL);
   CHECK(sso_sizes(nullptr, &i0, &i1, &i2) == SSO_EINVAL);
   CHECK(sso_problem_bytes(nullptr, &i0) == SSO_EINVAL);
+  CHECK(sso_batch_launch(nullptr, nullptr, 0, 1) == SSO_EINVAL);
+  CHECK(sso_batch_wait(nullptr, nullptr, 0, nullptr) == SSO_EINVAL);
+  CHECK(sso_problem_set_stream(nullptr, nullptr) == SSO_EINVAL);
+  CHECK(sso_pool_trim(-1, 0) == SSO_EINVAL);
+  CHECK(sso_pool_trim(1 << 20, 0) == SSO_EINVAL);
+  CHECK(sso_pool_trim(0, 0) == SSO_OK);   // no pool was ever created: nothing to release
   for (int k = -10; k <= 5; ++k) CHECK(sso_strerror(k) && std::strlen(sso_strerror(k)) > 0);
   sso_problem_destroy(nullptr);
   sso_batch_destroy(nullptr);

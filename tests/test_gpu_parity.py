@@ -390,13 +390,14 @@ def test_invalid_inputs_are_rejected():
         with pytest.raises(sso.SSOError) as e:
             p.solve()
         assert e.value.status == sso.SSO_EINVAL
-    # a concave (dart-shaped) quad: its third corner pulled to a tenth of the way from the first,
-    # so det J < 0 at the Gauss point next to that re-entrant corner, though the diagonals still
-    # give a positive area
+    # a concave (dart-shaped) quad: its third corner pulled (in all three coordinates, so that
+    # the dart survives the projection onto the element's mean plane of this curved shell) to a
+    # tenth of the way from the first; det J at the four Gauss points of the element's frame is
+    # then 1.23, 0.19, 0.19, -0.85, though the diagonals still give a positive area (0.76)
     s = small_shell(3)
     s.xyz = s.xyz.copy()
     a, b, c, d = s.quad_nodes[4]
-    s.xyz[c, :2] = s.xyz[a, :2] + 0.1 * (s.xyz[c, :2] - s.xyz[a, :2])
+    s.xyz[c] = s.xyz[a] + 0.1 * (s.xyz[c] - s.xyz[a])
     with _problem(s) as p:
         with pytest.raises(sso.SSOError) as e:
             p.solve()
@@ -446,3 +447,20 @@ def test_debug_mode_checks_every_pattern(monkeypatch):
         with _problem(mesh, rtol=1e-10) as q:
             u, _ = q.solve(check=False)
         assert torch.equal(u_dbg, u.cpu()), name
+
+
+def test_pool_trim_between_solves_changes_nothing():
+    """Destroyed problems' memory stays in the library's pool; trimming it back to the driver
+    and solving again gives bitwise the same displacements."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] pool trim", flush=True)
+    mesh = meshgen.shell(12, seed=5)
+    us = []
+    for trim in (False, True, False):
+        with sso.Problem(mesh, sso.Options(rtol=1e-10)) as p:
+            u, _ = p.solve()
+            us.append(u.cpu())
+        torch.cuda.synchronize()
+        if trim:
+            sso.pool_trim(0, 0)
+    assert torch.equal(us[0], us[1]) and torch.equal(us[0], us[2])

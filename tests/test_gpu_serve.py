@@ -320,3 +320,56 @@ def test_batched_server_with_shared_patterns_matches_solves_alone():
     for r, req in zip(stats.results, reqs):
         alone = run_one(req, opts)
         assert r.g == alone.g and np.array_equal(r.grad_xyz, alone.grad_xyz)
+
+
+def test_asynchronous_launch_protocol():
+    """sso_batch_launch / sso_batch_wait: the wait must name the launched list, one launch is
+    pending at a time, a pending problem may not move streams or end, and a launch + wait gives
+    bitwise what sso_batch_iterate gives."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] batch launch/wait protocol", flush=True)
+    meshes = [meshgen.shell(10, seed=71), meshgen.gridshell(9, seed=72)]
+    stream = torch.cuda.Stream()
+    other = torch.cuda.Stream()
+    opts = sso.Options(rtol=1e-10, solver=sso.SOLVER_STANDARD)
+    outs = []
+    for mode in ("iterate", "launch"):
+        batch = sso.Batch(stream)
+        probs = [sso.Problem(m, opts, stream=stream) for m in meshes]
+        try:
+            for p in probs:
+                p.solve_begin()
+            done = [False] * len(probs)
+            while not all(done):
+                if mode == "iterate":
+                    done = batch.iterate(probs, 8)
+                    continue
+                batch.launch(probs, 8)
+                with pytest.raises(sso.SSOError):
+                    batch.launch(probs, 8)                 # one pending launch at a time
+                with pytest.raises(sso.SSOError):
+                    batch.wait(probs[::-1])                # not the launched list
+                with pytest.raises(sso.SSOError):
+                    probs[0].set_stream(other)             # pending: may not move
+                with pytest.raises(sso.SSOError):
+                    probs[0].solve_end()                   # pending: may not end
+                done = batch.wait(probs)
+            outs.append([p.solve_end()[0].cpu() for p in probs])
+        finally:
+            for p in probs:
+                p.close()
+            batch.close()
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_overlapped_and_plain_loops_give_the_same_results():
+    import paper_2407_20026_amd as sso
+    from paper_2407_20026_amd.serve import BatchedServer
+    print("[gpu] overlapped vs plain batched loop", flush=True)
+    reqs = _requests(12, seed=8, rate=5000.0)
+    opts = sso.Options(rtol=1e-10, solver=sso.SOLVER_STANDARD)
+    a = BatchedServer(slots=6, options=opts, chunk=16, overlap=True).run(reqs)
+    b = BatchedServer(slots=6, options=opts, chunk=16, overlap=False).run(reqs)
+    for ra, rb in zip(a.results, b.results):
+        assert ra.rid == rb.rid and ra.g == rb.g and np.array_equal(ra.grad_xyz, rb.grad_xyz)

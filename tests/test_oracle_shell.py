@@ -227,3 +227,20 @@ def test_area_of_planar_quad_is_exact():
     x, y = X[0, :, 0], X[0, :, 1]
     shoelace = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
     assert elements.shell_area(X)[0] == pytest.approx(shoelace, rel=1e-15)
+
+
+def test_dart_quad_of_a_curved_shell_has_a_negative_gauss_jacobian():
+    """The inverted-element input of the GPU error tests: on the curved 3x3 shell, the centre
+    quad's third corner pulled in all three coordinates to a tenth of the way from the first
+    gives det J < 0 at a Gauss point of the mean-plane frame with a positive area; pulled in x
+    and y only, the corner keeps its height and the projected quad stays convex."""
+    import meshgen
+    base = meshgen.shell(3, L=8.0, seed=3)
+    a, b, c, d = base.quad_nodes[4]
+    for full, negative in ((True, True), (False, False)):
+        xyz = base.xyz.copy()
+        k = slice(None) if full else slice(0, 2)
+        xyz[c, k] = xyz[a, k] + 0.1 * (xyz[c, k] - xyz[a, k])
+        _, x, y, _, area = elements.shell_frame(xyz[[a, b, c, d]][None])
+        assert area[0] > 0.0
+        assert (elements.min_gauss_detJ(x, y)[0] < 0.0) == negative
