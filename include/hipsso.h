@@ -320,10 +320,12 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
  * fixed DOFs; with prescribed displacements the lifted load on the free ones). */
 int sso_matrix(sso_problem* p, double* vals, double* f);
 
-/* Device memory the problem holds (*bytes, host): every buffer allocated on its behalf so far --
- * mesh copies, pattern, element list, K, preconditioner, solver vectors, and what later calls
- * added (mixed-precision copies, the size objective's scratch, the scalar CSR view) -- all kept
- * until sso_problem_destroy; buffers freed within a call are not counted.  For admission by
+/* Device memory the problem holds (*bytes, host): the memory taken for every buffer allocated on
+ * its behalf so far -- mesh copies, pattern, element list, K, preconditioner, solver vectors, and
+ * what later calls added (mixed-precision copies, the size objective's scratch, the scalar CSR
+ * view) -- all kept until sso_problem_destroy; buffers freed within a call are not counted.
+ * Buffers above 512 KiB are taken one by one; smaller ones are carved from 2 MiB chunks, counted
+ * whole (a chunk is left for a new one only with less than 512 KiB free).  For admission by
  * memory footprint in a request loop.  Errors: SSO_EINVAL (NULL argument). */
 int sso_problem_bytes(const sso_problem* p, int64_t* bytes);
 

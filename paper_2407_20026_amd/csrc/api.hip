@@ -34,6 +34,7 @@ struct sso_problem {
   Mesh m;
   Pattern pat;                  // the pattern's arrays (owned through `shared`)
   SharedPattern* shared = nullptr;
+  Arena mem;                    // chunks holding the problem's own device buffers
   sso_options opt;
   int64_t n_coo = 0;
   double* coo = nullptr;
@@ -149,7 +150,7 @@ void free_problem(sso_problem* p) {
                   (void*)p->d_scal, (void*)p->d_err, (void*)p->row_ptr, (void*)p->col,
                   (void*)p->perm, (void*)p->seg, (void*)m.u_presc, (void*)p->fm,
                   (void*)p->gw, (void*)p->wv, (void*)p->xpart})
-    dev_free(q, s);
+    dev_release(q, &p->mem, s);
   if (p->shared) {
     if (p->shared->refs.fetch_sub(1) == 1) {   // the last problem of this topology
       free_pattern(p->shared->pat, s);
@@ -158,7 +159,8 @@ void free_problem(sso_problem* p) {
   } else {
     free_pattern(p->pat, s);
   }
-  pcg_free(p->w, s);
+  pcg_free(p->w, &p->mem, s);
+  arena_free(p->mem, s);
   delete[] p->h_scal;
   delete p->h_err;
   for (auto& e : p->ev)
@@ -306,7 +308,10 @@ int create_impl(const sso_mesh* mesh, const sso_options* opts, hipStream_t strea
                          nqn, m.quad_nodes, like->m.quad_nodes, p->d_err);
     TRY_HIP(hipGetLastError());
   } else {
-    TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
+    {
+      AllocScope ps(&p->bytes, &p->pat.mem);   // the pattern outlives this problem if shared
+      TRY_HIP(build_pattern(m, p->pat, p->d_err, s, p->h_err));
+    }
     if (*p->h_err) return SSO_EINVAL;
     p->shared = new (std::nothrow) SharedPattern();
     if (!p->shared) return SSO_ENOMEM;
@@ -358,7 +363,7 @@ int sso_problem_create(const sso_mesh* mesh, const sso_options* opts, hipStream_
   if (opts && !options_ok(*opts)) return SSO_EINVAL;
   sso_problem* p = new (std::nothrow) sso_problem();
   if (!p) return SSO_ENOMEM;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   int st = create_impl(mesh, opts, stream, p, nullptr);
   if (st != SSO_OK) {
     free_problem(p);
@@ -383,7 +388,7 @@ int sso_problem_create_like(const sso_problem* like, const sso_mesh* mesh,
   if (hipGetDevice(&dev) != hipSuccess || dev != like->device) return SSO_EINVAL;
   sso_problem* p = new (std::nothrow) sso_problem();
   if (!p) return SSO_ENOMEM;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   int st = create_impl(mesh, opts, stream, p, like);
   if (st != SSO_OK) {
     free_problem(p);
@@ -619,13 +624,52 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
   return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
 
+hipError_t arena_alloc(Arena& a, size_t bytes, hipStream_t s, void** out, int64_t* held) {
+  bytes = (bytes + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+  *held = 0;
+  if (bytes > ARENA_CHUNK / 4) {   // a chunk of its own
+    void* q = nullptr;
+    const hipError_t e = pool_alloc(&q, bytes, s);
+    if (e != hipSuccess) return e;
+    a.chunks.emplace_back(static_cast<char*>(q), bytes);
+    *held = (int64_t)bytes;
+    *out = q;
+    return hipSuccess;
+  }
+  if (bytes > a.left) {
+    void* q = nullptr;
+    const hipError_t e = pool_alloc(&q, ARENA_CHUNK, s);
+    if (e != hipSuccess) return e;
+    a.chunks.emplace_back(static_cast<char*>(q), ARENA_CHUNK);
+    a.cur = static_cast<char*>(q);
+    a.left = ARENA_CHUNK;
+    *held = (int64_t)ARENA_CHUNK;
+  }
+  *out = a.cur;
+  a.cur += bytes;
+  a.left -= bytes;
+  return hipSuccess;
+}
+
+bool arena_owns(const Arena& a, const void* p) {
+  const char* c = static_cast<const char*>(p);
+  for (const auto& k : a.chunks)
+    if (c >= k.first && c < k.first + k.second) return true;
+  return false;
+}
+
+void arena_free(Arena& a, hipStream_t s) {
+  for (const auto& k : a.chunks) (void)hipFreeAsync(k.first, s);
+  a = Arena();
+}
+
 }  // namespace sso
 
 extern "C" {
 
 int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
   if (!p) return SSO_EINVAL;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   hipStream_t s = p->s;
   p->solved = false;
   p->in_batch = false;
@@ -665,7 +709,7 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
 
 int sso_solve_begin(sso_problem* p) {
   if (!p) return SSO_EINVAL;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   // multi-problem launches run FP64 iterations of either kind and FP32 single-reduction ones
   hipStream_t s = p->s;
   p->solved = false;
@@ -687,7 +731,7 @@ int sso_solve_begin(sso_problem* p) {
 
 int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
   if (!p || !p->in_batch || p->batch_pending) return SSO_EINVAL;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   hipStream_t s = p->s;
   TRY_HIP(hipMemcpyAsync(p->w.h_st, p->w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
   TRY_HIP(launch_true_residual(p->m, p->pat, p->K, p->u, p->f, nullptr, p->w, p->d_scal, s));
@@ -842,7 +886,7 @@ int sso_objective(sso_problem* p, int kind, const double* a, double* g_host) {
 int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, double* dg_dt,
                 double* dg_dscale, sso_stats* stats) {
   if (!p || !p->solved || !dg_dxyz) return SSO_EINVAL;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   hipStream_t s = p->s;
   double c_lam = 1.0, c_u = 1.0;
   const double* lam = p->u;
@@ -884,7 +928,7 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
 int sso_size_objective(sso_problem* p, double eps1, double u_max, double t_min,
                        double* out_host, double* dg_dxyz, double* dg_dt, sso_stats* stats) {
   if (!size_args_ok(p, eps1, u_max, t_min, out_host, dg_dxyz)) return SSO_EINVAL;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   if (!p->xpart) {
     TRY_HIP(dev_alloc(&p->xpart, 2 * SIZE_XWG, p->s));
     TRY_HIP(dev_alloc(&p->gw, 14 * (int64_t)p->m.n_quads, p->s));
@@ -935,7 +979,7 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
   if (!p) return SSO_EINVAL;
   if (p->n_coo >= ((int64_t)1 << 31) || 36 * p->pat.n_blocks >= ((int64_t)1 << 31))
     return SSO_EINVAL;
-  AllocCounter ac(&p->bytes);
+  AllocScope ac(&p->bytes, &p->mem);
   const int64_t nz = 36 * p->pat.n_blocks;
   hipStream_t s = p->s;
   if (!p->row_ptr) {

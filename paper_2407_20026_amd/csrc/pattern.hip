@@ -286,11 +286,21 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   uint64_t* keys = nullptr;
   int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE + 2;
   int64_t nk = pat.n_bcoo > 0 ? pat.n_bcoo : 1;
-  SSO_TRY(dev_alloc_scratch(&cnt, (n + 1), s));
-  SSO_TRY(dev_alloc_scratch(&fill, (n + 1), s));
-  SSO_TRY(dev_alloc_scratch(&ucnt, (n + 1), s));
-  SSO_TRY(dev_alloc_scratch(&tmp, nt, s));
-  SSO_TRY(dev_alloc_scratch(&keys, nk, s));
+  // the build's own scratch: one arena, freed on every way out of this function
+  Arena scratch;
+  struct Release {
+    Arena& a;
+    hipStream_t s;
+    ~Release() { arena_free(a, s); }
+  } release{scratch, s};
+  {
+    AllocScope sc(nullptr, &scratch);
+    SSO_TRY(dev_alloc(&cnt, (n + 1), s));
+    SSO_TRY(dev_alloc(&fill, (n + 1), s));
+    SSO_TRY(dev_alloc(&ucnt, (n + 1), s));
+    SSO_TRY(dev_alloc(&tmp, nt, s));
+    SSO_TRY(dev_alloc(&keys, nk, s));
+  }
   SSO_TRY(dev_alloc(&pat.estart, (n + 1), s));
   SSO_TRY(dev_alloc(&pat.brow_ptr, (n + 1), s));
   SSO_TRY(dev_alloc(&pat.bperm, nk, s));
@@ -304,10 +314,7 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   SSO_TRY(hipGetLastError());
   SSO_TRY(hipMemcpyAsync(h_err, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   SSO_TRY(hipStreamSynchronize(s));
-  if (*h_err) {
-    dev_free(cnt, s); dev_free(fill, s); dev_free(ucnt, s); dev_free(tmp, s); dev_free(keys, s);
-    return hipSuccess;   // caller reports SSO_EINVAL
-  }
+  if (*h_err) return hipSuccess;   // caller reports SSO_EINVAL
   SSO_TRY(exclusive_scan(cnt, n, pat.estart, tmp, s));
   if (pat.n_bcoo)
     hipLaunchKernelGGL(k_block_place, dim3(blocks_for(pat.n_bcoo)), dim3(TPB), 0, s, m,
@@ -341,7 +348,6 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
                        pat.brow_ptr, pat.bcol, pat.bcol_ell);
     SSO_TRY(hipGetLastError());
   }
-  dev_free(cnt, s); dev_free(fill, s); dev_free(ucnt, s); dev_free(tmp, s); dev_free(keys, s);
   return hipSuccess;
 }
 
@@ -358,9 +364,11 @@ hipError_t build_scalar_view(const Mesh& m, const Pattern& pat, int32_t* row_ptr
 }
 
 void free_pattern(Pattern& pat, hipStream_t s) {
-  dev_free(pat.brow_ptr, s); dev_free(pat.bcol, s); dev_free(pat.bseg, s);
-  dev_free(pat.bperm, s); dev_free(pat.bslot, s); dev_free(pat.bdiag, s);
-  dev_free(pat.estart, s); dev_free(pat.bsrow, s); dev_free(pat.bcol_ell, s);
+  for (void* q : {(void*)pat.brow_ptr, (void*)pat.bcol, (void*)pat.bseg, (void*)pat.bperm,
+                  (void*)pat.bslot, (void*)pat.bdiag, (void*)pat.estart, (void*)pat.bsrow,
+                  (void*)pat.bcol_ell})
+    dev_release(q, &pat.mem, s);
+  arena_free(pat.mem, s);
   pat = Pattern();
 }
 

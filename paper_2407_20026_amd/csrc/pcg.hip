@@ -1466,13 +1466,13 @@ hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s) {
   return hipSuccess;
 }
 
-void pcg_free(PcgWork& w, hipStream_t s) {
-  dev_free(w.r, s); dev_free(w.z, s); dev_free(w.p[0], s); dev_free(w.p[1], s);
-  dev_free(w.Ap, s); dev_free(w.partials, s); dev_free(w.st, s);
-  dev_free(w.xc, s); dev_free(w.rc, s);
-  dev_free(w.fw[0], s); dev_free(w.fw[1], s); dev_free(w.fw32[0], s); dev_free(w.fw32[1], s);
-  dev_free(w.jw, s); dev_free(w.fdesc64, s); dev_free(w.fdesc32, s);
-  dev_free(w.desc64, s); dev_free(w.desc32, s);
+void pcg_free(PcgWork& w, const Arena* owner, hipStream_t s) {
+  dev_release(w.r, owner, s); dev_release(w.z, owner, s); dev_release(w.p[0], owner, s); dev_release(w.p[1], owner, s);
+  dev_release(w.Ap, owner, s); dev_release(w.partials, owner, s); dev_release(w.st, owner, s);
+  dev_release(w.xc, owner, s); dev_release(w.rc, owner, s);
+  dev_release(w.fw[0], owner, s); dev_release(w.fw[1], owner, s); dev_release(w.fw32[0], owner, s); dev_release(w.fw32[1], owner, s);
+  dev_release(w.jw, owner, s); dev_release(w.fdesc64, owner, s); dev_release(w.fdesc32, owner, s);
+  dev_release(w.desc64, owner, s); dev_release(w.desc32, owner, s);
   delete w.h_st;
   if (w.h_ring) {
     (void)hipStreamSynchronize(s);   // the last polled chunk's read-back may still be queued
@@ -1480,8 +1480,8 @@ void pcg_free(PcgWork& w, hipStream_t s) {
   }
   for (auto& ev : w.poll_ev)
     if (ev) (void)hipEventDestroy(ev);
-  dev_free(w.r32, s); dev_free(w.z32, s); dev_free(w.p32[0], s); dev_free(w.p32[1], s);
-  dev_free(w.Ap32, s); dev_free(w.x32, s); dev_free(w.b32, s);
+  dev_release(w.r32, owner, s); dev_release(w.z32, owner, s); dev_release(w.p32[0], owner, s); dev_release(w.p32[1], owner, s);
+  dev_release(w.Ap32, owner, s); dev_release(w.x32, owner, s); dev_release(w.b32, owner, s);
   if (w.prof_ev) {
     for (int i = 0; i < 2 * w.prof_cap; ++i) (void)hipEventDestroy(w.prof_ev[i]);
     delete[] w.prof_ev;
@@ -1813,14 +1813,14 @@ static hipError_t table_upload(LaunchTable<Desc>& t, const Desc* descs, int n, h
     dev_free(t.d_desc, s);
     t.d_desc = nullptr;
     t.cap_desc = 2 * n;
-    if ((e = dev_alloc(reinterpret_cast<Desc**>(&t.d_desc), t.cap_desc, s)) != hipSuccess)
-      return e;
+    e = dev_alloc_scratch(reinterpret_cast<Desc**>(&t.d_desc), t.cap_desc, s);
+    if (e != hipSuccess) return e;
   }
   if (t.total > t.cap_wg) {
     dev_free(t.d_wg, s);
     t.d_wg = nullptr;
     t.cap_wg = 2 * t.total;
-    if ((e = dev_alloc(&t.d_wg, t.cap_wg, s)) != hipSuccess) return e;
+    if ((e = dev_alloc_scratch(&t.d_wg, t.cap_wg, s)) != hipSuccess) return e;
   }
   if ((e = hipMemcpyAsync(t.d_desc, t.h_desc.data(), sizeof(Desc) * n, hipMemcpyHostToDevice,
                           s)) != hipSuccess)
@@ -1910,8 +1910,8 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
     bw.d_states = nullptr;
     bw.d_stp = nullptr;
     bw.cap_states = bw.cap_stp = 2 * nt;
-    if ((e = dev_alloc(&bw.d_states, bw.cap_states, s)) != hipSuccess) return e;
-    if ((e = dev_alloc(&bw.d_stp, bw.cap_stp, s)) != hipSuccess) return e;
+    if ((e = dev_alloc_scratch(&bw.d_states, bw.cap_states, s)) != hipSuccess) return e;
+    if ((e = dev_alloc_scratch(&bw.d_stp, bw.cap_stp, s)) != hipSuccess) return e;
   }
   if ((e = hipMemcpyAsync(bw.d_stp, bw.h_stp.data(), sizeof(PcgState*) * nt,
                           hipMemcpyHostToDevice, s)) != hipSuccess)

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <utility>
 #include <vector>
 
 #include "hipsso.h"
@@ -80,6 +81,19 @@ struct FusedDesc {
   int max_it;       //   (set when it starts; read by the single-problem iteration)
 };
 
+// Memory that lives as long as its owner (a problem, a block pattern) is carved from a few
+// chunks of the pool and freed with them when the owner ends: a stream-ordered free costs about
+// 20 us of host time, and a problem has some 45 buffers.  A buffer above ARENA_CHUNK / 4 gets a
+// chunk of its own; smaller ones share chunks of ARENA_CHUNK bytes, and a chunk is left only when
+// less than ARENA_CHUNK / 4 of it is free, so every chunk but the last is at least 3/4 used.
+struct Arena {
+  std::vector<std::pair<char*, size_t>> chunks;   // base, size
+  char* cur = nullptr;
+  size_t left = 0;
+};
+constexpr size_t ARENA_CHUNK = (size_t)2 << 20;
+constexpr size_t ARENA_ALIGN = 256;
+
 // Block-level pattern (6x6 blocks, one block row per node).
 struct Pattern {
   int64_t n_bcoo = 0;       // block contributions: 4 per beam, 16 per quad
@@ -97,6 +111,7 @@ struct Pattern {
   // row's block count, I itself (with a zero block) beyond.
   int ell_w = 0;
   int32_t* bcol_ell = nullptr;  // [n_nodes * ell_w]
+  Arena mem;                    // chunks holding the arrays above
 };
 
 // Slots per row of the padded block-row layout for a largest row of `max_blocks` blocks; wider
@@ -163,22 +178,39 @@ __host__ __device__ inline int64_t coo_index(const BlockRef& r, int ca, int cb, 
   return 144 * (int64_t)n_beams + 576 * (int64_t)r.e + 24 * (6 * r.la + ca) + 6 * r.lb + cb;
 }
 
-// Device memory held by a problem: while an entry point works on a problem, an AllocCounter
-// points this thread's counter at the problem's byte count, and every dev_alloc adds to it
-// (sso_problem_bytes).  Buffers freed again within the call use dev_alloc_scratch instead.
-inline thread_local int64_t* alloc_counter = nullptr;
-struct AllocCounter {
-  int64_t* prev;
-  explicit AllocCounter(int64_t* c) : prev(alloc_counter) { alloc_counter = c; }
-  ~AllocCounter() { alloc_counter = prev; }
-  AllocCounter(const AllocCounter&) = delete;
-  AllocCounter& operator=(const AllocCounter&) = delete;
-};
-
 // Stream-ordered device memory from the library's pool on the stream's device (api.hip): no
 // device-wide synchronisation, so problems that live on different streams keep overlapping
 // while others are created or destroyed, and freed memory is reused without remapping.
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
+
+// Carves `bytes` (rounded up to ARENA_ALIGN) on stream s; *held = bytes newly taken from the pool.
+hipError_t arena_alloc(Arena& a, size_t bytes, hipStream_t s, void** out, int64_t* held);
+bool arena_owns(const Arena& a, const void* p);
+void arena_free(Arena& a, hipStream_t s);   // every chunk, stream-ordered on s
+
+// While an entry point works on a problem, an AllocScope points this thread's allocations at
+// the problem's arena and its byte count (sso_problem_bytes: the chunks held); the pattern build
+// points them at the pattern's arena.  Outside a scope dev_alloc takes a buffer of its own from
+// the pool (the multi-problem launch tables, which grow and shrink with the batch).
+inline thread_local int64_t* alloc_counter = nullptr;
+inline thread_local Arena* alloc_arena = nullptr;
+struct AllocScope {
+  int64_t* prev;
+  Arena* prev_arena;
+  AllocScope(int64_t* c, Arena* a) : prev(alloc_counter), prev_arena(alloc_arena) {
+    alloc_counter = c;
+    alloc_arena = a;
+  }
+  ~AllocScope() {
+    alloc_counter = prev;
+    alloc_arena = prev_arena;
+  }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
+// A buffer of its own from the pool, never counted and never in an arena: for buffers freed
+// with dev_free (the multi-problem launch tables and state arrays, owned by a batch).
 template <class T>
 inline hipError_t dev_alloc_scratch(T** p, int64_t n, hipStream_t s) {
   if (n <= 0) n = 1;
@@ -187,9 +219,20 @@ inline hipError_t dev_alloc_scratch(T** p, int64_t n, hipStream_t s) {
 template <class T>
 inline hipError_t dev_alloc(T** p, int64_t n, hipStream_t s) {
   if (n <= 0) n = 1;
+  const size_t bytes = sizeof(T) * (size_t)n;
+  if (alloc_arena) {
+    int64_t held = 0;
+    const hipError_t e = arena_alloc(*alloc_arena, bytes, s, reinterpret_cast<void**>(p), &held);
+    if (e == hipSuccess && alloc_counter) *alloc_counter += held;
+    return e;
+  }
   const hipError_t e = dev_alloc_scratch(p, n, s);
-  if (e == hipSuccess && alloc_counter) *alloc_counter += (int64_t)sizeof(T) * n;
+  if (e == hipSuccess && alloc_counter) *alloc_counter += (int64_t)bytes;
   return e;
+}
+// Frees a buffer unless `owner` holds it in one of its chunks (freed with the owner).
+inline void dev_release(void* p, const Arena* owner, hipStream_t s) {
+  if (p && !(owner && arena_owns(*owner, p))) (void)hipFreeAsync(p, s);
 }
 inline void dev_free(void* p, hipStream_t s) {
   if (p) (void)hipFreeAsync(p, s);
@@ -291,7 +334,7 @@ struct PcgWork {
 
 hipError_t pcg_alloc(PcgWork& w, int64_t n_nodes, bool mixed, hipStream_t s);
 hipError_t pcg_alloc_mixed(PcgWork& w, hipStream_t s);
-void pcg_free(PcgWork& w, hipStream_t s);
+void pcg_free(PcgWork& w, const Arena* owner, hipStream_t s);  // owner: the problem's arena
 // Solve K x = b (b already masked); x overwritten.  Returns SSO status via *status.
 // profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
 // B = K Dinv (launch_right_precondition) selects the single-reduction recurrences, B = nullptr

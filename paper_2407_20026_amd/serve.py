@@ -37,12 +37,26 @@ from . import Options, Problem
 FUSED_MAX_NODES = 8192
 
 
+ARENA_CHUNK = 2 << 20      # the library's chunk size for the buffers of one owner
+
+
+def _arena_bound(bufs) -> int:
+    """Device memory an owner holds for buffers of the given byte sizes: a buffer above a
+    quarter chunk has a chunk of its own, smaller ones share chunks that are left only when
+    less than a quarter chunk is free (so each but the last is at least 3/4 used)."""
+    big = sum(-(-b // 256) * 256 for b in bufs if b > ARENA_CHUNK // 4)
+    small = sum(-(-b // 256) * 256 for b in bufs if b <= ARENA_CHUNK // 4)
+    chunks = 0 if small == 0 else int(small * 4 / 3 // ARENA_CHUNK) + 1
+    return big + chunks * ARENA_CHUNK
+
+
 def footprint_bytes(mesh, mixed: bool | None = False) -> int:
     """Upper bound of the device memory one problem holds after its forward and adjoint
     (mesh copies, pattern, element list, K, packed preconditioner, B = K M of the
-    single-reduction PCG or the FP32 copies of mixed precision, solver vectors, gradients).
-    mixed=None: the precision is picked by the library (AUTO), either bound.  Checked against
-    the library's own count (sso_problem_bytes) in the serving tests."""
+    single-reduction PCG or the FP32 copies of mixed precision, solver vectors, gradients),
+    in the chunks the library carves them from.  mixed=None: the precision is picked by the
+    library (AUTO), either bound.  Checked against the library's own count (sso_problem_bytes)
+    in the serving tests."""
     if mixed is None:
         return max(footprint_bytes(mesh, False), footprint_bytes(mesh, True))
     nn, nb, nq = mesh.n_nodes, mesh.n_beams, mesh.n_quads
@@ -51,18 +65,17 @@ def footprint_bytes(mesh, mixed: bool | None = False) -> int:
     nbcoo = 4 * nb + 16 * nq
     ndof = 6 * nn
     dinv = 21 * (nn + 63) // 64 * 64                # packed inverses, whole groups of 64
-    b = 0
-    b += nn * (3 * 8 + 6 + 6 * 8) + nb * (8 + 48) + nq * (16 + 40 + 8)        # mesh copies
-    b += 4 * (3 * nbcoo + 3 * blocks + 4 * nn + padded)                         # pattern
-    b += 8 * (144 * nb + 576 * nq) + 8 * nq                                     # elements
-    b += 288 * blocks + 8 * dinv                                                # K, Dinv
-    b += 8 * ndof * 14 + 8 * (6 * nb + 14 * nq)                                 # vectors, grads
-    b += 8 * 11 * 1024 + 4096                                                   # partials
+    pattern = [4 * nbcoo] * 3 + [4 * blocks] * 3 + [4 * (nn + 1)] * 4 + [4 * padded]
+    bufs = [24 * nn, 6 * nn, 48 * nn, 8 * nb, 48 * nb, 16 * nq, 40 * nq, 8 * nq]   # mesh copies
+    bufs += [8 * (144 * nb + 576 * nq), 8 * nq]                                    # elements
+    bufs += [288 * blocks, 8 * dinv]                                               # K, Dinv
+    bufs += [8 * ndof] * 14 + [8 * 6 * nb, 8 * 14 * nq]                            # vectors, grads
+    bufs += [8 * 11 * 1024, 4096, 64]                                              # partials
     if mixed:
-        b += 144 * max(blocks, padded) + 4 * dinv + 4 * ndof * 9 + 4 * ndof * 2
+        bufs += [144 * max(blocks, padded), 4 * dinv] + [4 * ndof] * 11
     elif nn <= FUSED_MAX_NODES:
-        b += 288 * max(blocks, padded)  # B = K M in FP64 (single-reduction recurrences)
-    return int(b * 1.05) + (1 << 20)
+        bufs += [288 * max(blocks, padded)]  # B = K M in FP64 (single-reduction recurrences)
+    return int(1.05 * (_arena_bound(pattern) + _arena_bound(bufs))) + (1 << 20)
 
 
 @dataclass
