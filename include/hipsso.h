@@ -78,8 +78,15 @@ enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1, SSO_PREC_AUTO = 2 };
  * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
  * of K's size).  AUTO: sso_solve takes FUSED up to 8,192 nodes (latency-bound sizes; measured:
  * 13.4 against 20.2 ms on a 60 x 60 shell, equal on 90 x 90, 88 against 63 ms on 120 x 120)
- * and STANDARD above; sso_solve_begin (multi-problem launches) takes STANDARD. */
-enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2 };
+ * and STANDARD above; sso_solve_begin (multi-problem launches) takes STANDARD.
+ * WG: the standard recurrences with one workgroup per problem, every iteration inside one launch
+ * (workgroup barriers between the phases, no grid-wide synchronisation; a single solve is one
+ * launch up to 16,384 iterations, a multi-problem launch gives such a problem 16 times the
+ * iterations asked for, in a kernel of its own beside the other kinds).  For problems too small
+ * to fill more than one compute unit.  FP64 only (with SSO_PREC_MIXED: SSO_EINVAL; AUTO precision
+ * resolves to FP64).  Its rounding differs from STANDARD's in the order of the three
+ * reductions only. */
+enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2, SSO_SOLVER_WG = 3 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */
 typedef struct {
@@ -137,7 +144,7 @@ typedef struct {
   int32_t spmv_samples;       /* number of sampled iterations                                */
   double spmv_bytes;          /* algorithmic bytes of one iteration                          */
   int32_t refine_steps;       /* mixed precision: outer steps (FP32 inner solves) run        */
-  int32_t solver;             /* SSO_SOLVER_STANDARD or _FUSED: recurrences that ran         */
+  int32_t solver;             /* SSO_SOLVER_STANDARD, _FUSED or _WG: recurrences that ran    */
 } sso_stats;
 
 typedef struct sso_problem sso_problem;

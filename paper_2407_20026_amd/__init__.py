@@ -25,7 +25,7 @@ SSO_ESIZE = -6
 NOALLOC_MAX_QUADS = 139673   # SSO_NOALLOC_MAX_QUADS
 OBJ_COMPLIANCE, OBJ_STRAIN_ENERGY, OBJ_LINEAR, OBJ_USER = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED, PREC_AUTO = 0, 1, 2
-SOLVER_AUTO, SOLVER_STANDARD, SOLVER_FUSED = 0, 1, 2
+SOLVER_AUTO, SOLVER_STANDARD, SOLVER_FUSED, SOLVER_WG = 0, 1, 2, 3
 
 OBJECTIVES = {"compliance": OBJ_COMPLIANCE, "strain_energy": OBJ_STRAIN_ENERGY,
               "linear": OBJ_LINEAR, "user": OBJ_USER}

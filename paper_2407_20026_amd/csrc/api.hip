@@ -82,7 +82,7 @@ struct sso_batch {
   BatchWork bw;
   bool pending = false;                  // a launch not yet waited for
   std::vector<sso_problem*> listed;      // its problem list, in the caller's order
-  std::vector<int> idx[4];               // positions in that list by launch kind
+  std::vector<int> idx[5];               // positions in that list by launch kind
 };
 
 namespace {
@@ -104,12 +104,13 @@ bool options_ok(const sso_options& o) {
   return (o.precision == SSO_PREC_FP64 || o.precision == SSO_PREC_MIXED ||
           o.precision == SSO_PREC_AUTO) && o.rtol >= 0.0 &&
          o.max_it > 0 && o.refine_steps >= 0 && o.profile_every >= 0 && o.inner_rtol >= 0.0 &&
-         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_FUSED &&
-         o.inner_max_it >= 0;
+         o.inner_rtol < 1.0 && o.solver >= SSO_SOLVER_AUTO && o.solver <= SSO_SOLVER_WG &&
+         o.inner_max_it >= 0 && !(o.solver == SSO_SOLVER_WG && o.precision == SSO_PREC_MIXED);
 }
 
 // The precision a problem runs in: AUTO resolves by the size of its FP64 K.
 bool mixed_for(const sso_options& o, int64_t n_blocks) {
+  if (o.solver == SSO_SOLVER_WG) return false;   // the one-workgroup solver runs in FP64
   if (o.precision == SSO_PREC_AUTO) return 288.0 * (double)n_blocks >= SSO_AUTO_MIXED_K_BYTES;
   return o.precision == SSO_PREC_MIXED;
 }
@@ -429,6 +430,7 @@ namespace {
 
 bool mixed(const sso_problem* p) { return mixed_for(p->opt, p->pat.n_blocks); }
 bool fused(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
+bool one_wg(const sso_problem* p) { return p->solver_used == SSO_SOLVER_WG; }
 // iteration of a begun problem has stopped (mixed precision: the refinement loop has)
 bool stopped(const sso_problem* p) { return mixed(p) ? p->ms.done : p->w.h_st->done != 0; }
 
@@ -452,7 +454,10 @@ MixedParams mixed_params(const sso_problem* p) {
 int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* outer) {
   int status = SSO_OK;
   *outer = 0;
-  if (!mixed(p)) {
+  if (one_wg(p)) {
+    TRY_HIP(pcg_solve_wg(p->m, p->pat, p->K, p->Dinv, b, x, p->opt.rtol, p->opt.max_it, p->w,
+                         p->s, iters, &status, p->opt.profile_every));
+  } else if (!mixed(p)) {
     TRY_HIP(pcg_solve(p->m, p->pat, p->K, p->Dinv, fused(p) ? p->B : nullptr, b, x, p->opt.rtol,
                       p->opt.max_it, p->w, p->s, iters, &status, p->opt.profile_every));
   } else {
@@ -801,6 +806,11 @@ int sso_batch_launch(sso_batch* b, sso_problem* const* ps, int n, int n_iter) {
     } else if (fused(p)) {
       lists.fused.push_back(p->fdesc);
       b->idx[1].push_back(i);
+    } else if (one_wg(p)) {
+      PcgDesc<double> d = p->desc;
+      d.n_wg = 1;
+      lists.wg.push_back(d);
+      b->idx[4].push_back(i);
     } else {
       lists.standard.push_back(p->desc);
       b->idx[0].push_back(i);

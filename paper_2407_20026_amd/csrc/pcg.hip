@@ -224,6 +224,25 @@ __device__ __forceinline__ void put(T* p, T v, int streaming) {
     *p = v;
 }
 
+// Row a of a node's packed block-Jacobi inverse, applied to the node's six values.
+template <class T>
+struct DinvRow {
+  T d[6];
+  __device__ inline T apply(const T* v) const {
+    T z = 0;
+    for (int h = 0; h < 3; ++h) z += d[2 * h] * v[2 * h] + d[2 * h + 1] * v[2 * h + 1];
+    return z;
+  }
+};
+
+template <class T>
+__device__ inline DinvRow<T> dinv_row(const T* Dinv, int I, int a) {
+  const T* dn = Dinv + DINV_PACKED * (int64_t)I;
+  DinvRow<T> R;
+  for (int b = 0; b < 6; ++b) R.d[b] = dn[dinv_index(a, b)];
+  return R;
+}
+
 // ---- SpMV layout: 18 lanes per block row, 3 block rows per wavefront ----------------------
 // Lane l of a row group owns entries (a, b..b+1) of every 6x6 block, a = l / 3, b = 2 (l % 3),
 // so the 18 lanes read each 288-byte block with one contiguous 16-byte load each.
@@ -649,6 +668,155 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   if (lb == 0 && threadIdx.x == 0) st->jn = j + 1;
 }
 
+// ---- one workgroup per problem: every iteration inside one launch ----------------------------
+// For the smallest problems an iteration of the kernel pair is a few microseconds of launch and
+// round-trip latency around almost no data.  Here one workgroup of 16 waves holds a whole
+// problem and runs the standard recurrences with workgroup barriers between the phases (no grid
+// synchronisation); several problems share a launch, one workgroup each.  The block-row products
+// are the pair's (row_product2), so only the order of the three reductions differs.  Between
+// launches the state record carries rz_j, rz_{j-1} and rr_j, so a launch resumes where the last
+// one stopped.
+constexpr int WG1_TPB = 1024;
+constexpr int WG1_WAVES = WG1_TPB / 64;
+constexpr int WG1_ROWS = ROWS_PER_WAVE * WG1_WAVES;   // 48 block rows per product pass
+constexpr int WG1_NODE_LANES = 60;                    // 10 nodes a wave in the vector pass
+constexpr int WG1_NODES = (WG1_NODE_LANES / 6) * WG1_WAVES;   // 160 nodes per vector pass
+
+// Fixed-order sum of NV values over the 16 waves, returned to every thread; ends with a barrier
+// (the LDS array is reused by the next call, and the phase that follows reads what other waves
+// wrote before the call).
+template <int NV>
+__device__ inline void wg1_sum(double v[NV]) {
+  __shared__ double lds[NV][WG1_WAVES];
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+    for (int k = 0; k < NV; ++k) lds[k][wave] = v[k];
+  __syncthreads();
+  for (int k = 0; k < NV; ++k) {
+    double t = lds[k][0];
+    for (int w = 1; w < WG1_WAVES; ++w) t += lds[k][w];
+    v[k] = t;
+  }
+  __syncthreads();
+}
+
+// Up to n_iter iterations of problem blockIdx.x (descriptor D[blockIdx.x]; its n_wg, wg_base,
+// pa and pb are not used).  At j = 0 (x = 0, r = b, z = Dinv b, p_{-1} = 0 from the
+// initialisation kernel) the kernel forms r^T z and r^T r itself.  The stopping test is the
+// standard pair's, on r_j^T r_j against rtol^2 |b|^2.
+__global__ void __launch_bounds__(WG1_TPB)
+k_pcg_wg(const PcgDesc<double>* __restrict__ D, int n_iter) {
+  const PcgDesc<double> d = D[blockIdx.x];
+  PcgState* st = d.st;
+  const int n = d.n_nodes;
+  const StdState S = std_state(st);
+  if (S.done) return;
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n_dof = 6 * (int64_t)n;
+  int j = S.jn;
+  double rz, rzp = 1.0, rr, ff = S.ff;
+  if (j == 0) {
+    double v[2] = {0.0, 0.0};
+    for (int64_t q = threadIdx.x; q < n_dof; q += WG1_TPB) {
+      const double rq = d.r[q];
+      v[0] += rq * d.z[q];
+      v[1] += rq * rq;
+    }
+    wg1_sum<2>(v);
+    rz = v[0];
+    rr = v[1];
+    ff = rr;
+  } else {
+    rz = (j & 1) ? S.rz1 : S.rz0;
+    rzp = (j & 1) ? S.rz0 : S.rz1;
+    rr = uniform(st->rr);
+  }
+  const int j_end = j + n_iter;
+  int stop = 0, status = SSO_OK;
+  for (;; ++j) {
+    if (!std::isfinite(rr) || !std::isfinite(rz)) {
+      stop = 1;
+      status = SSO_EBREAKDOWN;
+    } else if (rr <= S.rtol2 * ff) {
+      stop = 1;
+    } else if (j >= S.max_it) {
+      stop = 1;
+      status = SSO_ENOTCONV;
+    }
+    if (stop || j >= j_end) break;
+    const double beta = (j == 0) ? 0.0 : rz / rzp;
+    const double* __restrict__ pold = (j & 1) ? d.p[1] : d.p[0];
+    double* __restrict__ pnew = (j & 1) ? d.p[0] : d.p[1];
+    // Ap_j = K z_j + beta K p_{j-1}, p_j = z_j + beta p_{j-1}; partial p_j^T Ap_j
+    double my = 0.0;
+    for (int I0 = 0; I0 < n; I0 += WG1_ROWS) {
+      const int I = I0 + wave * ROWS_PER_WAVE + L.g;
+      const bool ok = L.ok && I < n;
+      int rb = 0, re = 0;
+      if (ok) {
+        rb = d.brow_ptr[I];
+        re = d.brow_ptr[I + 1];
+      }
+      double az, ap;
+      row_product2<double>(rb, re, d.bcol, d.K, d.z, pold, L.a, L.b, az, ap);
+      const double sz = sum3(az), sp = sum3(ap);
+      if (ok && L.b == 0) {
+        const int64_t q = 6 * (int64_t)I + L.a;
+        const double pn = d.z[q] + beta * pold[q];
+        const double Apq = sz + beta * sp;
+        pnew[q] = pn;
+        d.Ap[q] = Apq;
+        my += pn * Apq;
+      }
+    }
+    double pap[1] = {my};
+    wg1_sum<1>(pap);
+    const double alpha = rz / pap[0];
+    // x += alpha p_j, r -= alpha Ap_j, z = Dinv r (a node's six r values by wave shuffles);
+    // partials of r^T z and r^T r
+    double v[2] = {0.0, 0.0};
+    const int k = lane / 6, a = lane - 6 * k;
+    for (int I0 = 0; I0 < n; I0 += WG1_NODES) {
+      const int I = I0 + wave * (WG1_NODE_LANES / 6) + k;
+      const bool ok = lane < WG1_NODE_LANES && I < n;
+      const int64_t q = 6 * (int64_t)I + a;
+      double rv = 0.0;
+      if (ok) {
+        d.x[q] += alpha * pnew[q];
+        rv = d.r[q] - alpha * d.Ap[q];
+        d.r[q] = rv;
+      }
+      double rn[6];
+      for (int c = 0; c < 6; ++c) rn[c] = __shfl(rv, 6 * k + c, 64);
+      if (ok) {
+        const double zq = dinv_row(d.Dinv, I, a).apply(rn);
+        d.z[q] = zq;
+        v[0] += rv * zq;
+        v[1] += rv * rv;
+      }
+    }
+    wg1_sum<2>(v);
+    rzp = rz;
+    rz = v[0];
+    rr = v[1];
+  }
+  if (threadIdx.x == 0) {
+    st->rzs[j & 1] = rz;
+    st->rzs[(j + 1) & 1] = rzp;
+    st->rr = rr;
+    st->ff = ff;
+    st->it = j;
+    st->jc = j;
+    st->jn = j;
+    if (stop) {
+      st->status = status;
+      st->done = 1;
+    }
+  }
+}
+
 // ---- single-reduction PCG (Chronopoulos & Gear): one kernel and one reduction per iteration --
 //
 // The recurrences carry s = K p beside p, and w = K M r (M the block-Jacobi inverse) comes from
@@ -791,24 +959,6 @@ __device__ inline T row_product_b(const FusedDesc<T>& d, int I, const T* __restr
 }
 
 // Row a of the node's 6x6 block-Jacobi inverse (packed storage) applied to the 6 values at v.
-template <class T>
-struct DinvRow {
-  T d[6];
-  __device__ inline T apply(const T* v) const {
-    T z = 0;
-    for (int h = 0; h < 3; ++h) z += d[2 * h] * v[2 * h] + d[2 * h + 1] * v[2 * h + 1];
-    return z;
-  }
-};
-
-template <class T>
-__device__ inline DinvRow<T> dinv_row(const T* Dinv, int I, int a) {
-  const T* dn = Dinv + DINV_PACKED * (int64_t)I;
-  DinvRow<T> R;
-  for (int b = 0; b < 6; ++b) R.d[b] = dn[dinv_index(a, b)];
-  return R;
-}
-
 // The 6 values v of this lane's node (SpMV layout: lane 18 g + 3 c of row group g holds
 // component c), gathered by wave shuffles.
 template <class T>
@@ -1878,9 +2028,43 @@ static hipError_t fused_upload(std::map<int, LaunchTable<FusedDesc<T>>>& tables,
   return hipSuccess;
 }
 
+// A multi-problem launch gives each one-workgroup problem this many times the iterations of the
+// other kinds (an iteration of a small problem on one workgroup takes a few microseconds, the
+// launch pairs of the others a hundred or so when many problems are in flight).
+constexpr int WG1_BATCH_FACTOR = 16;
+
+// The one-workgroup problems' launch runs on a second stream of the batch, beside the launches
+// of the other kinds: it waits for what the batch stream enqueued before it (the problems' own
+// earlier work and the table upload), and the batch stream waits for it before the states are
+// gathered.
+static hipError_t launch_wg(BatchWork& bw, int n_iter, hipStream_t s) {
+  const int np = bw.wg.total;
+  if (np == 0) return hipSuccess;
+  hipError_t e;
+  if (!bw.s_wg) {
+    int dev = 0, cur = 0;
+    if ((e = hipStreamGetDevice(s, &dev)) != hipSuccess) return e;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&bw.s_wg, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bw.ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bw.ev_wg, hipEventDisableTiming);
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+  }
+  if ((e = hipEventRecord(bw.ev_in, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(bw.s_wg, bw.ev_in, 0)) != hipSuccess) return e;
+  const int64_t budget = (int64_t)n_iter * WG1_BATCH_FACTOR;
+  const int it = budget > (1 << 30) ? (1 << 30) : (int)budget;
+  hipLaunchKernelGGL(k_pcg_wg, dim3(np), dim3(WG1_TPB), 0, bw.s_wg,
+                     reinterpret_cast<const PcgDesc<double>*>(bw.wg.d_desc), it);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipEventRecord(bw.ev_wg, bw.s_wg);
+}
+
 hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipStream_t s) {
   const int nt = (int)(L.standard.size() + L.fused.size() + L.standard32.size() +
-                       L.fused32.size());
+                       L.fused32.size() + L.wg.size());
   bw.pending_nt = nt;
   if (nt <= 0) return hipSuccess;
   hipError_t e;
@@ -1892,6 +2076,8 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
       hipSuccess)
     return e;
   if ((e = fused_upload(bw.fused32, L.fused32, s)) != hipSuccess) return e;
+  if ((e = table_upload(bw.wg, L.wg.data(), (int)L.wg.size(), s)) != hipSuccess) return e;
+  if (n_iter > 0 && (e = launch_wg(bw, n_iter, s)) != hipSuccess) return e;
   for (int i = 0; i < n_iter; ++i) {
     launch_standard(bw.standard, s);
     launch_fused(bw.fused, s);
@@ -1904,6 +2090,9 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
   for (const auto& d : L.fused) bw.h_stp.push_back(d.st);
   for (const auto& d : L.standard32) bw.h_stp.push_back(d.st);
   for (const auto& d : L.fused32) bw.h_stp.push_back(d.st);
+  for (const auto& d : L.wg) bw.h_stp.push_back(d.st);
+  if (n_iter > 0 && bw.wg.total > 0 && (e = hipStreamWaitEvent(s, bw.ev_wg, 0)) != hipSuccess)
+    return e;
   if (nt > bw.cap_states) {
     dev_free(bw.d_states, s);
     dev_free(bw.d_stp, s);
@@ -1965,6 +2154,13 @@ void batch_free(BatchWork& bw, hipStream_t s) {
   for (auto& kv : bw.fused) table_free(kv.second, s);
   table_free(bw.standard32, s);
   for (auto& kv : bw.fused32) table_free(kv.second, s);
+  table_free(bw.wg, s);
+  if (bw.s_wg) {
+    (void)hipStreamSynchronize(bw.s_wg);
+    (void)hipStreamDestroy(bw.s_wg);
+  }
+  if (bw.ev_in) (void)hipEventDestroy(bw.ev_in);
+  if (bw.ev_wg) (void)hipEventDestroy(bw.ev_wg);
   dev_free(bw.d_stp, s);
   dev_free(bw.d_states, s);
   bw = BatchWork();
@@ -1979,7 +2175,8 @@ static_assert(FUSED_MAX_NODES <= (int64_t)PCG_MAX_WG * ROWS_PER_WG,
               "the single-reduction recurrences run in one pass of the grid");
 
 int pcg_pick_solver(int solver, int64_t n_nodes) {
-  if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED) return solver;
+  if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED || solver == SSO_SOLVER_WG)
+    return solver;
   return n_nodes <= FUSED_MAX_NODES ? SSO_SOLVER_FUSED : SSO_SOLVER_STANDARD;
 }
 
@@ -1998,6 +2195,51 @@ hipError_t launch_right_precondition(const Mesh& m, const Pattern& pat, const do
                        m.n_nodes, pat.n_blocks, pat.ell_w, pat.brow_ptr, pat.bcol, K, Dinv,
                        B32);
   return hipGetLastError();
+}
+
+// Iterations per launch of a single solve on one workgroup (k_pcg_wg): a solve of up to this
+// many iterations is one launch.
+constexpr int WG1_SOLO_ITERS = 1 << 14;
+
+hipError_t pcg_solve_wg(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                        const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                        hipStream_t s, int* iters, int* status, int profile_every) {
+  w.prof_us = 0.0;
+  w.prof_n = 0;
+  hipError_t e = pcg_start<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w,
+                                   s, nullptr);
+  if (e != hipSuccess) return e;
+  if (profile_every > 0 && !w.prof_ev) {
+    w.prof_ev = new hipEvent_t[2 * PROF_CAP];
+    for (int i = 0; i < 2 * PROF_CAP; ++i)
+      if ((e = hipEventCreate(&w.prof_ev[i])) != hipSuccess) return e;
+    w.prof_cap = PROF_CAP;
+  }
+  const PcgDesc<double>* dd = reinterpret_cast<const PcgDesc<double>*>(w.desc64);
+  // the kernel stops itself at iteration max_it, so the launches end
+  for (int64_t launched = 0;; launched += WG1_SOLO_ITERS) {
+    const bool prof = profile_every > 0 && launched == 0;
+    if (prof && (e = hipEventRecord(w.prof_ev[0], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pcg_wg, dim3(1), dim3(WG1_TPB), 0, s, dd, WG1_SOLO_ITERS);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (prof && (e = hipEventRecord(w.prof_ev[1], s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (prof && w.h_st->it > 0) {   // mean duration of an iteration of the first launch
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, w.prof_ev[0], w.prof_ev[1]) == hipSuccess) {
+        w.prof_us = 1000.0 * ms / w.h_st->it;
+        w.prof_n = 1;
+      }
+    }
+    if (w.h_st->done) break;
+  }
+  *iters = w.h_st->it;
+  *status = w.h_st->status;
+  if (*status != SSO_OK) return hipSuccess;
+  return pcg_correct(m, pat, K, Dinv, b, x, rtol, max_it, w, s, iters, status);
 }
 
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,

@@ -339,6 +339,11 @@ void pcg_free(PcgWork& w, const Arena* owner, hipStream_t s);  // owner: the pro
 // profile_every > 0 times every n-th SpMV launch with HIP events (w.prof_us, w.prof_n).
 // B = K Dinv (launch_right_precondition) selects the single-reduction recurrences, B = nullptr
 // the standard ones.
+// The standard recurrences on one workgroup (k_pcg_wg), all iterations in one launch (up to
+// 16,384), then the same FP64 correction as pcg_solve.
+hipError_t pcg_solve_wg(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
+                        const double* b, double* x, double rtol, int max_it, PcgWork& w,
+                        hipStream_t s, int* iters, int* status, int profile_every);
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* B, const double* b, double* x, double rtol, int max_it,
                      PcgWork& w, hipStream_t s, int* iters, int* status, int profile_every = 0);
@@ -401,6 +406,9 @@ struct BatchWork {
   std::map<int, LaunchTable<FusedDesc<double>>> fused;   // by padded width
   LaunchTable<PcgDesc<float>> standard32;   // FP32 inner solves of mixed-precision problems
   std::map<int, LaunchTable<FusedDesc<float>>> fused32;
+  LaunchTable<PcgDesc<double>> wg;   // one-workgroup problems, launched on s_wg
+  hipStream_t s_wg = nullptr;
+  hipEvent_t ev_in = nullptr, ev_wg = nullptr;
   PcgState** d_stp = nullptr;
   int cap_stp = 0;
   PcgState* d_states = nullptr;
@@ -427,6 +435,7 @@ struct BatchLists {
   std::vector<FusedDesc<double>> fused;
   std::vector<PcgDesc<float>> standard32;   // FP32 inner solves of mixed precision
   std::vector<FusedDesc<float>> fused32;
+  std::vector<PcgDesc<double>> wg;          // one workgroup per problem (k_pcg_wg), n_wg = 1
 };
 // The same in two halves: pcg_batch_launch enqueues the iterations and the copy of the states to
 // pinned host memory and returns; pcg_batch_wait waits for them and fills bw.h_states.

@@ -24,12 +24,12 @@ import collections
 import hashlib
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 import torch
 
-from . import Options, Problem
+from . import PREC_MIXED, SOLVER_AUTO, SOLVER_WG, Options, Problem
 
 
 # sso_solve's automatic choice of the single-reduction recurrences (which keep B = K M beside
@@ -100,6 +100,7 @@ class Result:
     status: int = 0              # SSO_OK, or SSO_ENOTCONV (stopped above rtol)
     rel_residual: float = 0.0    # true relative residual of the solve
     outer_steps: int = 0         # FP64 outer steps (> 0: the request ran in mixed precision)
+    iter_bytes: float = 0.0      # algorithmic bytes of its PCG iterations (iters x per iteration)
 
     @property
     def latency(self) -> float:
@@ -121,6 +122,7 @@ class ServeStats:
     host_s: dict = field(default_factory=dict)   # BatchedServer: wall time per phase
     not_converged: int = 0         # requests that stopped above rtol (status SSO_ENOTCONV)
     max_rel_residual: float = 0.0  # largest true relative residual over the requests
+    iteration_bytes_per_s: float = 0.0   # the requests' algorithmic PCG iteration bytes / wall
 
 
 def _convergence(results) -> dict:
@@ -282,7 +284,8 @@ def finish_one(p: Problem, req: Request):
     gr = p.adjoint(req.objective)
     gx = gr["dg_dxyz"].cpu().numpy()
     gt = gr["dg_dt"].cpu().numpy() if gr["dg_dt"] is not None else None
-    return g, gx, gt, st["iters"], p.last_status, st["rel_residual"], st["refine_steps"]
+    return (g, gx, gt, st["iters"], p.last_status, st["rel_residual"], st["refine_steps"],
+            st["iters"] * st["spmv_bytes"])
 
 
 class BatchedServer:
@@ -299,7 +302,7 @@ class BatchedServer:
 
     def __init__(self, slots: int = 64, hbm_budget: int = 64 << 30,
                  options: Options | None = None, device="cuda", chunk: int = 32,
-                 share_patterns: bool = True, overlap: bool = True):
+                 share_patterns: bool = True, overlap: bool = True, wg_max_nodes: int = 0):
         self.share_patterns = share_patterns
         self.overlap = overlap
         self.slots = slots
@@ -309,6 +312,18 @@ class BatchedServer:
         self.mixed = {0: False, 1: True}.get(self.options.precision)
         self.device = torch.device(device)
         self.chunk = chunk
+        # requests of at most wg_max_nodes nodes run on one workgroup each (SSO_SOLVER_WG), in a
+        # kernel of their own beside the multi-problem launches (AUTO recurrences, not mixed)
+        self.wg_max_nodes = wg_max_nodes
+        self.options_wg = None
+        if wg_max_nodes > 0 and self.options.solver == SOLVER_AUTO and \
+                self.options.precision != PREC_MIXED:
+            self.options_wg = replace(self.options, solver=SOLVER_WG)
+
+    def options_for(self, mesh) -> Options:
+        if self.options_wg is not None and mesh.n_nodes <= self.wg_max_nodes:
+            return self.options_wg
+        return self.options
 
     def run(self, requests: list[Request]) -> ServeStats:
         from . import Batch
@@ -343,7 +358,8 @@ class BatchedServer:
                 free -= need
                 key = topology_key(req.mesh) if self.share_patterns else None
                 like = next(iter(live[key]), None) if key in live else None
-                p = Problem(req.mesh, self.options, device=self.device, stream=aux, like=like)
+                p = Problem(req.mesh, self.options_for(req.mesh), device=self.device, stream=aux,
+                            like=like)
                 p.topology = key
                 if key is not None:
                     live[key].add(p)
@@ -353,13 +369,13 @@ class BatchedServer:
         def finish():
             nonlocal free
             for p, req, adm, need in finishing:
-                g, gx, gt, iters, status, rres, outer = finish_one(p, req)
+                g, gx, gt, iters, status, rres, outer, ib = finish_one(p, req)
                 if p.topology is not None:
                     live[p.topology].discard(p)
                 p.close()
                 free += need
                 results.append(Result(req.rid, req.mesh.n_dof, g, gx, gt, iters,
-                                      req.arrival, adm, clock(), status, rres, outer))
+                                      req.arrival, adm, clock(), status, rres, outer, ib))
             finishing.clear()
 
         try:
@@ -412,7 +428,8 @@ class BatchedServer:
             mean_queue_ms=1000 * float(np.mean([r.admitted - r.arrival for r in results])),
             peak_inflight=peak_inflight, peak_bytes=peak_bytes,
             results=sorted(results, key=lambda r: r.rid),
-            host_s=phase, **_convergence(results))
+            host_s=phase, iteration_bytes_per_s=sum(r.iter_bytes for r in results) / wall,
+            **_convergence(results))
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = 3) -> np.ndarray:

@@ -52,7 +52,7 @@ static void abi_argument_paths() {
   m.n_quads = 1 << 28;                                                 // 16 n_quads >= 2^31
   CHECK(sso_problem_create(&m, nullptr, nullptr, &p) == SSO_EINVAL);
   m.n_quads = 1;
-  sso_options bad[6];
+  sso_options bad[7];
   for (auto& o : bad) {
     o.precision = SSO_PREC_FP64;
     o.rtol = 1e-8;
@@ -69,6 +69,8 @@ static void abi_argument_paths() {
   bad[3].inner_rtol = 1.0;
   bad[4].solver = 9;
   bad[5].inner_max_it = -3;
+  bad[6].solver = SSO_SOLVER_WG;      // the one-workgroup solver runs in FP64 only
+  bad[6].precision = SSO_PREC_MIXED;
   for (auto& o : bad) CHECK(sso_problem_create(&m, &o, nullptr, &p) == SSO_EINVAL && !p);
   CHECK(sso_problem_update(nullptr, nullptr, nullptr, nullptr) == SSO_EINVAL);
   CHECK(sso_set_options(nullptr, &bad[0]) == SSO_EINVAL);

@@ -306,14 +306,16 @@ def test_bitwise_determinism(refs, name):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("solver", ["standard", "fused"])
+@pytest.mark.parametrize("solver", ["standard", "fused", "wg"])
 @pytest.mark.parametrize("name", ["grid11", "hub", "mixed", "shell60"])
 def test_both_recurrences(refs, name, solver):
-    """Standard and single-reduction (fused) PCG recurrences, each chosen explicitly: u and the
-    gradients at the parity bars, the recurrence reported back, and two runs bitwise equal."""
+    """Standard, single-reduction (fused) and one-workgroup PCG, each chosen explicitly: u and
+    the gradients at the parity bars, the recurrence reported back, and two runs bitwise
+    equal."""
     sso = _sso()
     mesh, _, r = refs(name)
-    code = {"standard": sso.SOLVER_STANDARD, "fused": sso.SOLVER_FUSED}[solver]
+    code = {"standard": sso.SOLVER_STANDARD, "fused": sso.SOLVER_FUSED,
+            "wg": sso.SOLVER_WG}[solver]
     print(f"[gpu] recurrences {name} {solver}", flush=True)
     outs = []
     for _ in range(2):

@@ -373,3 +373,52 @@ def test_overlapped_and_plain_loops_give_the_same_results():
     b = BatchedServer(slots=6, options=opts, chunk=16, overlap=False).run(reqs)
     for ra, rb in zip(a.results, b.results):
         assert ra.rid == rb.rid and ra.g == rb.g and np.array_equal(ra.grad_xyz, rb.grad_xyz)
+
+
+def test_one_workgroup_problems_in_a_batch_match_solves_alone():
+    """The one-workgroup solver (SSO_SOLVER_WG) in multi-problem launches beside standard
+    problems: its kernel resumes from the state record at every launch (8 x 16 iterations
+    here), against one launch for the whole solve alone; u, the iteration count and the
+    gradient must be bitwise the same."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] one-workgroup problems in a batch", flush=True)
+    meshes = [meshgen.gridshell(8, seed=81), meshgen.shell(10, seed=82),
+              meshgen.gridshell(13, seed=83), meshgen.shell(14, seed=84)]
+    kinds = [sso.SOLVER_WG, sso.SOLVER_WG, sso.SOLVER_STANDARD, sso.SOLVER_WG]
+    alone = []
+    for m, k in zip(meshes, kinds):
+        with sso.Problem(m, sso.Options(rtol=1e-10, solver=k)) as p:
+            u, st = p.solve()
+            g = p.adjoint("compliance")
+            assert st["solver"] == k
+            alone.append((u.cpu(), st["iters"], g["dg_dxyz"].cpu()))
+    stream = torch.cuda.Stream()
+    batch = sso.Batch(stream)
+    probs = [sso.Problem(m, sso.Options(rtol=1e-10, solver=k), stream=stream)
+             for m, k in zip(meshes, kinds)]
+    try:
+        for p in probs:
+            p.solve_begin()
+        done = [False] * len(probs)
+        launches = 0
+        while not all(done):
+            done = batch.iterate(probs, 8)
+            launches += 1
+        assert launches > 2
+        for p, (u0, it0, g0) in zip(probs, alone):
+            u, st = p.solve_end()
+            g = p.adjoint("compliance")
+            assert st["iters"] == it0
+            assert torch.equal(u.cpu(), u0)
+            assert torch.equal(g["dg_dxyz"].cpu(), g0)
+    finally:
+        for p in probs:
+            p.close()
+        batch.close()
+
+
+def test_one_workgroup_solver_rejects_mixed_precision():
+    import paper_2407_20026_amd as sso
+    with pytest.raises(sso.SSOError):
+        sso.Problem(meshgen.gridshell(6), sso.Options(solver=sso.SOLVER_WG,
+                                                      precision=sso.PREC_MIXED))
