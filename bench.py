@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--refine-steps", type=int, default=20,
                     help="mixed precision: outer (FP64 flexible CG) step limit")
     ap.add_argument("--solver", default="auto", choices=["auto", "standard", "fused"])
+    ap.add_argument("--stream-beside", default="fp64,mixed",
+                    help="stream: precisions timed beside the headline (comma-separated; '' = "
+                         "the headline alone, and no error-against-FP64 summary)")
     ap.add_argument("--slots", type=int, default=32, help="stream: requests in flight at most")
     ap.add_argument("--chunk", type=int, default=32,
                     help="stream: iterations per multi-problem launch sequence between polls")
@@ -218,7 +221,8 @@ def stream_headline(args):
     warm = [meshgen.served_request(i, base_seed=2 * 10**6) for i in range(args.warmup)]
     log(f"stream: {n} requests, {sum(m.n_dof for m in meshes)} DOF in all")
     head = args.precision
-    order = [head] + [p for p in ("fp64", "mixed") if p != head]
+    beside = [p for p in args.stream_beside.split(",") if p]
+    order = [head] + [p for p in ("fp64", "mixed") if p != head and p in beside]
     closed, poisson, servers = {}, {}, {}
     for prec in order:
         srv = BatchedServer(slots=args.slots, options=_stream_options(sso, prec, args.rtol, args),
@@ -244,6 +248,7 @@ def stream_headline(args):
         c = closed[prec]
         out = {"closed_loop": {"solves_per_s": c.solves_per_s, "dof_per_s": c.dof_per_s,
                                "wall_s": c.wall_s, "peak_inflight": c.peak_inflight,
+                               "iteration_gbs": c.iteration_bytes_per_s / 1e9,
                                "phase_s": {k: round(v, 3) for k, v in c.host_s.items()}},
                "not_converged": c.not_converged, "max_rel_residual": c.max_rel_residual,
                "iters_median": int(np.median([r.iters for r in c.results])),
@@ -282,7 +287,7 @@ def stream_headline(args):
         "stream": {p: leg(p) for p in order},
         "errors_vs_fp64": {p: _error_summary(errors_against(closed[p].results,
                                                             closed["fp64"].results))
-                           for p in order if p != "fp64"},
+                           for p in order if p != "fp64" and "fp64" in closed},
     }
     return out, meshes
 
@@ -586,16 +591,11 @@ def main():
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib)
     ceilings = None
-    if "ceilings" in legs:
-        from paper_2407_20026_amd import ceiling
-        ceilings = ceiling.measure()
-        log(f"ceilings: read {ceilings['read_gbs']:.0f} GB/s, copy {ceilings['copy_gbs']:.0f} "
-            f"GB/s, FP64 FMA {ceilings['fp64_fma_tflops']:.1f} TFLOP/s")
 
     out = {"metric": METRIC, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic (seeded generators)"}
-    roof = None
+    roof_of = None   # (run, workload, precision) of the roofline, taken once the ceilings are in
     if args.workload == "stream":
         head, meshes = stream_headline(args)
         out.update(head)
@@ -619,17 +619,15 @@ def main():
                            **{k: v for k, v in _public(run).items()
                               if k in ("pcg_iters", "adjoint_pcg_iters", "outer_steps",
                                        "rel_residual", "status", "solver", "n_blocks")}})
-        roof = roofline_of(run, args.workload, args.precision, ceilings)
+        roof_of = (run, args.workload, args.precision)
         cpu_meshes, cpu_what = [mesh] * 1000, f"analyses of the {desc}"
     if "large" in legs:
         out["large"], run300 = large_leg(args)
-        if roof is None:
-            roof = roofline_of(run300, "shell300", "fp64", ceilings)
+        if roof_of is None:
+            roof_of = (run300, "shell300", "fp64")
+    run60 = None
     if "shell60" in legs:
         out["shell60"], run60 = shell60_leg(args)
-        out["shell60"]["roofline"] = roofline_of(run60, "shell60", "fp64", ceilings)
-        out["shell60"]["roofline"]["note"] = ("9.4 MB of K: resident in the 256 MB Infinity "
-                                              "Cache, not an HBM figure")
     if "general" in legs:
         out["general_objective"] = general_leg(args)
     if "batch" in legs:
@@ -639,8 +637,20 @@ def main():
         out["network"] = shellnet_bench(args.network_variants, sso.SOLVER_AUTO)
     if "arch" in legs and args.arch:
         out["arch_replay"] = arch_bench([int(v) for v in args.arch.split(",")])
-    if roof is not None:
-        out["roofline"] = roof
+    # last of the GPU work: the ceilings' 4 GiB of torch buffers and the cache release after
+    # them were measured to slow the host calls of a stream that follows (about 2.7 ms per
+    # request)
+    if "ceilings" in legs:
+        from paper_2407_20026_amd import ceiling
+        ceilings = ceiling.measure()
+        log(f"ceilings: read {ceilings['read_gbs']:.0f} GB/s, copy {ceilings['copy_gbs']:.0f} "
+            f"GB/s, FP64 FMA {ceilings['fp64_fma_tflops']:.1f} TFLOP/s")
+    if run60 is not None:
+        out["shell60"]["roofline"] = roofline_of(run60, "shell60", "fp64", ceilings)
+        out["shell60"]["roofline"]["note"] = ("9.4 MB of K: resident in the 256 MB Infinity "
+                                              "Cache, not an HBM figure")
+    if roof_of is not None:
+        out["roofline"] = roofline_of(*roof_of, ceilings)
     if ceilings:
         out["ceilings"] = ceilings
     if not args.no_cpu_baseline:
