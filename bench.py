@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--stream-beside", default="fp64,mixed",
                     help="stream: precisions timed beside the headline (comma-separated; '' = "
                          "the headline alone, and no error-against-FP64 summary)")
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="stream: closed loop only (p50/p99 then from the closed loop, all "
+                         "requests arriving at once; for profiling one pass)")
     ap.add_argument("--slots", type=int, default=32, help="stream: requests in flight at most")
     ap.add_argument("--chunk", type=int, default=32,
                     help="stream: iterations per multi-problem launch sequence between polls")
@@ -236,7 +239,9 @@ def stream_headline(args):
         log(f"stream {prec} closed loop: {st.solves_per_s:.1f} solves/s, "
             f"{st.dof_per_s / 1e6:.2f} M DOF/s, {st.wall_s:.1f} s")
     timed = [p for p in (head, "fp64") if p in closed][:2]
-    lam = 0.8 * min(closed[p].solves_per_s for p in timed)
+    if args.no_poisson:
+        timed = []
+    lam = 0.8 * min(closed[p].solves_per_s for p in closed)
     t_arr = poisson_arrivals(n, lam, seed=3)
     for prec in timed:
         st = servers[prec].run([Request(i, m, float(t_arr[i])) for i, m in enumerate(meshes)])
@@ -264,7 +269,8 @@ def stream_headline(args):
             out["max_rel_residual"] = max(out["max_rel_residual"], q.max_rel_residual)
         return out
 
-    c, q = closed[head], poisson[head]
+    c = closed[head]
+    q = poisson.get(head, c)
     nc = sum(leg(p)["not_converged"] for p in order)
     out = {
         "value": c.solves_per_s,
@@ -278,7 +284,9 @@ def stream_headline(args):
             "workload": (f"served stream: {n} forward+adjoint requests (grid-shells n~U{{8..60}}, "
                          f"shells m~U{{10..120}}, per-request seeds 10^6+i), compliance, "
                          f"rtol {args.rtol:g}, precision {head}; value = closed-loop solves/s, "
-                         f"p50/p99 from arrival under Poisson arrivals at {lam:.1f}/s"),
+                         + ("p50/p99 of the closed loop (all requests at t = 0)"
+                            if args.no_poisson else
+                            f"p50/p99 from arrival under Poisson arrivals at {lam:.1f}/s")),
             "requests": n, "mean_dof": float(np.mean([m.n_dof for m in meshes])),
             "slots": args.slots, "chunk": args.chunk, "rtol": args.rtol, "precision": head,
             "arrival_rate_per_s": lam,
