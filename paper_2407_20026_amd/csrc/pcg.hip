@@ -323,36 +323,84 @@ __device__ inline T sum3(T acc) {
   return acc + t1 + t2;
 }
 
-// sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
-// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Two blocks per step:
-// 72 VGPRs and 7 waves per SIMD; measured on the 300 x 300 shell 58.7 us per launch against
-// 67.8 (three per step, 88 VGPRs, 5 waves) and 77 (six per step).
+// Pointers into global memory: the kernels take their operands from descriptors read from
+// memory, so the compiler sees generic pointers and emits flat loads, whose completion it can
+// only wait for together with every other memory and LDS operation in flight.  Through these
+// it emits global loads and waits for exactly the loads a value needs.
 template <class T>
-__device__ inline void row_product2(int rb, int re, const int32_t* __restrict__ bcol,
-                                    const T* __restrict__ K, const T* __restrict__ z,
-                                    const T* __restrict__ p, int a, int b, T& az, T& ap) {
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)p;
+}
+template <class T>
+struct Native2 {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+template <class V, class T>
+__device__ __forceinline__ V load2(gptr<T> p) {
+  typedef typename Native2<T>::type N;
+  const N v = *(const __attribute__((address_space(1))) N*)p;
+  V r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+// sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
+// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Two blocks per step.
+// A step issues its K values and gathers together with the block columns of the next step, so
+// a step costs one round trip to memory instead of two (the columns, then the gathers that
+// need them); the products and their order are those of one block after another.
+template <class T>
+__device__ inline void row_product2(int rb, int re, const int32_t* __restrict__ bcol_,
+                                    const T* __restrict__ K_, const T* __restrict__ z_,
+                                    const T* __restrict__ p_, int a, int b, T& az, T& ap) {
   using V = typename Vec2<T>::type;
+  const gptr<int32_t> bcol = as_global(bcol_);
+  const gptr<T> K = as_global(K_);
+  const gptr<T> z = as_global(z_);
+  const gptr<T> p = as_global(p_);
   const int off = 6 * a + b;
   T sz = 0, sp = 0;
   int s = rb;
-  for (; s + 2 <= re; s += 2) {
-    const int64_t J0 = bcol[s], J1 = bcol[s + 1];
-    const V k0 = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
-    const V k1 = *reinterpret_cast<const V*>(K + 36 * (int64_t)(s + 1) + off);
-    const V z0 = *reinterpret_cast<const V*>(z + 6 * J0 + b);
-    const V z1 = *reinterpret_cast<const V*>(z + 6 * J1 + b);
-    const V p0 = *reinterpret_cast<const V*>(p + 6 * J0 + b);
-    const V p1 = *reinterpret_cast<const V*>(p + 6 * J1 + b);
-    sz += k0.x * z0.x + k0.y * z0.y;
-    sp += k0.x * p0.x + k0.y * p0.y;
-    sz += k1.x * z1.x + k1.y * z1.y;
-    sp += k1.x * p1.x + k1.y * p1.y;
-  }
-  for (; s < re; ++s) {
-    const int64_t J = bcol[s];
-    const V kv = *reinterpret_cast<const V*>(K + 36 * (int64_t)s + off);
-    const V zv = *reinterpret_cast<const V*>(z + 6 * J + b);
-    const V pv = *reinterpret_cast<const V*>(p + 6 * J + b);
+  if (re - rb >= 2) {
+    int J0 = bcol[s], J1 = bcol[s + 1];
+    for (;;) {
+      const V k0 = load2<V>(K + 36 * (int64_t)s + off);
+      const V k1 = load2<V>(K + 36 * (int64_t)(s + 1) + off);
+      const V z0 = load2<V>(z + 6 * (int64_t)J0 + b);
+      const V z1 = load2<V>(z + 6 * (int64_t)J1 + b);
+      const V p0 = load2<V>(p + 6 * (int64_t)J0 + b);
+      const V p1 = load2<V>(p + 6 * (int64_t)J1 + b);
+      // the next step's columns; past the last pair, the row's last two (the odd block's
+      // column is then the second)
+      const int sn = s + 2;
+      const int sc = sn + 2 <= re ? sn : re - 2;
+      const int J0n = bcol[sc], J1n = bcol[sc + 1];
+      sz += k0.x * z0.x + k0.y * z0.y;
+      sp += k0.x * p0.x + k0.y * p0.y;
+      sz += k1.x * z1.x + k1.y * z1.y;
+      sp += k1.x * p1.x + k1.y * p1.y;
+      s = sn;
+      if (s + 2 > re) {
+        if (s < re) {   // one block left: column bcol[re - 1] = J1n
+          const V kv = load2<V>(K + 36 * (int64_t)s + off);
+          const V zv = load2<V>(z + 6 * (int64_t)J1n + b);
+          const V pv = load2<V>(p + 6 * (int64_t)J1n + b);
+          sz += kv.x * zv.x + kv.y * zv.y;
+          sp += kv.x * pv.x + kv.y * pv.y;
+        }
+        break;
+      }
+      J0 = J0n;
+      J1 = J1n;
+    }
+  } else if (s < re) {
+    const int J = bcol[s];
+    const V kv = load2<V>(K + 36 * (int64_t)s + off);
+    const V zv = load2<V>(z + 6 * (int64_t)J + b);
+    const V pv = load2<V>(p + 6 * (int64_t)J + b);
     sz += kv.x * zv.x + kv.y * zv.y;
     sp += kv.x * pv.x + kv.y * pv.y;
   }
