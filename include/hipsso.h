@@ -28,7 +28,12 @@
  *   - Outputs go to caller-allocated device buffers.
  *   - Work is enqueued on the stream given at creation.  sso_problem_create, sso_solve,
  *     sso_objective and sso_adjoint synchronise that stream before returning (they report
- *     convergence, errors and host scalars); sso_problem_update only enqueues.
+ *     convergence, errors and host scalars); sso_problem_update only enqueues.  A solve
+ *     cannot return at enqueue and still report its outcome, because its stopping test reads
+ *     the iteration state back between chunks of iterations.  The asynchronous form is
+ *     sso_solve_begin, then sso_batch_launch (returns at once) and sso_batch_wait (waits for
+ *     the states only), then sso_solve_end; sso_problem_set_stream moves a problem between
+ *     streams.
  *   - A problem is not thread-safe: use one problem per host thread.
  *   - Every function returns SSO_OK (0) or a negative status; sso_strerror gives the text.
  *     On error, outputs are left unspecified and the problem stays usable (except after
