@@ -348,6 +348,60 @@ __device__ __forceinline__ V load2(gptr<T> p) {
 }
 
 // sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
+// not wait for beta): the direction's product is K p_new = Kz + beta Kp.  NB blocks per step; a
+// step issues its K values and gathers together with the block columns of the next step, so a
+// step costs one round trip to memory instead of two (the columns, then the gathers that need
+// them).  Indices past the row's end are clamped to its last block and their products not
+// added, so every NB gives the products of one block after another, in that order (bitwise the
+// same sums as row_product2 below, the two-block form without the clamping, which measured
+// faster where bandwidth bounds the pair).
+template <class T, int NB>
+__device__ inline void row_product_nb(int rb, int re, const int32_t* __restrict__ bcol_,
+                                      const T* __restrict__ K_, const T* __restrict__ z_,
+                                      const T* __restrict__ p_, int a, int b, T& az, T& ap) {
+  using V = typename Vec2<T>::type;
+  const gptr<int32_t> bcol = as_global(bcol_);
+  const gptr<T> K = as_global(K_);
+  const gptr<T> z = as_global(z_);
+  const gptr<T> p = as_global(p_);
+  const int off = 6 * a + b;
+  const int last = re - 1;
+  T sz = 0, sp = 0;
+  int s = rb;
+  if (s < re) {
+    int J[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) J[u] = bcol[s + u < re ? s + u : last];
+    for (;;) {
+      V kv[NB], zv[NB], pv[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int su = s + u < re ? s + u : last;
+        kv[u] = load2<V>(K + 36 * (int64_t)su + off);
+        zv[u] = load2<V>(z + 6 * (int64_t)J[u] + b);
+        pv[u] = load2<V>(p + 6 * (int64_t)J[u] + b);
+      }
+      const int sn = s + NB;
+      int Jn[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) Jn[u] = bcol[sn + u < re ? sn + u : last];
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (s + u < re) {
+          sz += kv[u].x * zv[u].x + kv[u].y * zv[u].y;
+          sp += kv[u].x * pv[u].x + kv[u].y * pv[u].y;
+        }
+      s = sn;
+      if (s >= re) break;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) J[u] = Jn[u];
+    }
+  }
+  az = sz;
+  ap = sp;
+}
+
+// sum over the block row of K[s][a][b..b+1] . z and . p (two accumulators, so the products do
 // not wait for beta): the direction's product is K p_new = Kz + beta Kp.  Two blocks per step.
 // A step issues its K values and gathers together with the block columns of the next step, so
 // a step costs one round trip to memory instead of two (the columns, then the gathers that
@@ -535,7 +589,7 @@ __device__ __forceinline__ StdState std_state(const PcgState* __restrict__ st) {
 // test, beta_j), so the reduction overlaps the loads.  The descriptor is copied whole and the
 // first pass's row pointers are loaded with the state (neither needs the other), so a
 // workgroup's first products start two round trips after its descriptor.
-template <class T>
+template <class T, int NB = 2>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
   const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
@@ -577,7 +631,10 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
         pI = pold[2 * (6 * (int64_t)I + L.a) + 1];
       }
     } else {
-      row_product2<T>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
+      if constexpr (NB == 2)
+        row_product2<T>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
+      else
+        row_product_nb<T, NB>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
       if (ok && L.b == 0) {
         zI = z[6 * (int64_t)I + L.a];
         pI = pold[6 * (int64_t)I + L.a];
@@ -1606,6 +1663,15 @@ static int choose_wg(int64_t n_nodes, int cap) {
 #define SSO_STD_PASSES 2
 #endif
 
+// Workgroups of k_update that own nodes: it covers 64 nodes a pass where k_spmv_dir covers 36
+// rows (two passes of 18), so of the n_wg workgroups that share the partial sums only the first
+// ceil(n / 64) have work.  The others would write zero partials, which the initialisation kernel
+// (all n_wg workgroups) has already left in their slots, so the update launches only these.
+static inline int update_wg(int n_wg, int64_t n_nodes) {
+  const int64_t g = (n_nodes + VEC_NODES - 1) / VEC_NODES;
+  return (int)(g < n_wg ? (g < 1 ? 1 : g) : n_wg);
+}
+
 // Partial-sum buffers (units of the stride S = max(n_wg, n_wg_f, 1024) doubles):
 //   [0, S) pA | [S, 3S) pB | [3S, 5S) one-off reductions, then 8 scalars |
 //   [5S + 8, 8S + 8) single-reduction even | [8S + 8, 11S + 8) single-reduction odd
@@ -1844,12 +1910,13 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   hipError_t e = pcg_start<T>(m, pat, K, Dinv, b, x, r, z, p, Ap, rtol, max_it, w, s, nullptr);
   if (e != hipSuccess) return e;
   const int nwg = w.n_wg;
+  const int nwg_upd = update_wg(nwg, m.n_nodes);
   const PcgDesc<T>* dd =
       reinterpret_cast<const PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
     hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-    hipLaunchKernelGGL(k_update<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    hipLaunchKernelGGL(k_update<T>, dim3(nwg_upd), dim3(MAX_TPB), 0, s, dd, nullptr);
     if (e1) (void)hipEventRecord(*e1, s);
   };
   // a sample spans 8 back-to-back iterations (events between every pair would add their own
@@ -1996,13 +2063,19 @@ hipError_t fused_begin(const Mesh& m, const Pattern& pat, const double* B, const
   return hipSuccess;
 }
 
+// Lays the problems' workgroups out one problem after another (wg_base: the first of each) and
+// uploads the descriptors and the workgroup -> problem map.  update: the k_update launch, which
+// takes only the workgroups that own nodes (update_wg); n_wg stays the partial sums' count.
 template <class Desc>
-static hipError_t table_upload(LaunchTable<Desc>& t, const Desc* descs, int n, hipStream_t s) {
+static hipError_t table_upload(LaunchTable<Desc>& t, const Desc* descs, int n, hipStream_t s,
+                               bool update = false) {
   t.h_desc.assign(descs, descs + n);
   t.h_wg.clear();
   for (int i = 0; i < n; ++i) {
     t.h_desc[i].wg_base = (int)t.h_wg.size();
-    for (int k = 0; k < t.h_desc[i].n_wg; ++k) t.h_wg.push_back(i);
+    const int nw =
+        update ? update_wg(t.h_desc[i].n_wg, t.h_desc[i].n_nodes) : t.h_desc[i].n_wg;
+    for (int k = 0; k < nw; ++k) t.h_wg.push_back(i);
   }
   t.total = (int)t.h_wg.size();
   if (n == 0) return hipSuccess;
@@ -2033,12 +2106,27 @@ static void table_free(LaunchTable<Desc>& t, hipStream_t s) {
   dev_free(t.d_wg, s);
 }
 
+// Multi-problem launches of more workgroups than stay resident at once run the product kernel
+// with three blocks per step (74 VGPRs, 6 waves per SIMD): every workgroup there makes only a
+// few passes, and more loads in flight per wave beat occupancy.  Measured on one box, 32 and
+// 48 60 x 60 shells per launch: 3.32-3.35 against 3.41 and 3.30 against 3.38 us per problem-
+// iteration; the served stream 114.7-114.8 against 112.3 solves/s.  Four per step (91 VGPRs,
+// 5 waves) lost (3.8-3.9 us); single problems keep two (the 300 x 300 shell: bandwidth-bound).
+constexpr int BATCH_NB = 3;
+constexpr int BATCH_NB_MIN_WG = 1024;
+
 template <class T>
-static void launch_standard(const LaunchTable<PcgDesc<T>>& t, hipStream_t s) {
+static void launch_standard(const LaunchTable<PcgDesc<T>>& t, const LaunchTable<PcgDesc<T>>& u,
+                            hipStream_t s) {
   if (t.total == 0) return;
   const PcgDesc<T>* d = reinterpret_cast<const PcgDesc<T>*>(t.d_desc);
-  hipLaunchKernelGGL(k_spmv_dir<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
-  hipLaunchKernelGGL(k_update<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+  if (t.total > BATCH_NB_MIN_WG)
+    hipLaunchKernelGGL((k_spmv_dir<T, BATCH_NB>), dim3(t.total), dim3(MAX_TPB), 0, s, d,
+                       t.d_wg);
+  else
+    hipLaunchKernelGGL(k_spmv_dir<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+  hipLaunchKernelGGL(k_update<T>, dim3(u.total), dim3(MAX_TPB), 0, s,
+                     reinterpret_cast<const PcgDesc<T>*>(u.d_desc), u.d_wg);
 }
 
 template <class T, int W>
@@ -2119,17 +2207,23 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
   if ((e = table_upload(bw.standard, L.standard.data(), (int)L.standard.size(), s)) !=
       hipSuccess)
     return e;
+  if ((e = table_upload(bw.standard_upd, L.standard.data(), (int)L.standard.size(), s, true)) !=
+      hipSuccess)
+    return e;
   if ((e = fused_upload(bw.fused, L.fused, s)) != hipSuccess) return e;
   if ((e = table_upload(bw.standard32, L.standard32.data(), (int)L.standard32.size(), s)) !=
       hipSuccess)
+    return e;
+  if ((e = table_upload(bw.standard32_upd, L.standard32.data(), (int)L.standard32.size(), s,
+                        true)) != hipSuccess)
     return e;
   if ((e = fused_upload(bw.fused32, L.fused32, s)) != hipSuccess) return e;
   if ((e = table_upload(bw.wg, L.wg.data(), (int)L.wg.size(), s)) != hipSuccess) return e;
   if (n_iter > 0 && (e = launch_wg(bw, n_iter, s)) != hipSuccess) return e;
   for (int i = 0; i < n_iter; ++i) {
-    launch_standard(bw.standard, s);
+    launch_standard(bw.standard, bw.standard_upd, s);
     launch_fused(bw.fused, s);
-    launch_standard(bw.standard32, s);
+    launch_standard(bw.standard32, bw.standard32_upd, s);
     launch_fused(bw.fused32, s);
     ++bw.launched;
   }
@@ -2203,6 +2297,8 @@ void batch_free(BatchWork& bw, hipStream_t s) {
   table_free(bw.standard32, s);
   for (auto& kv : bw.fused32) table_free(kv.second, s);
   table_free(bw.wg, s);
+  table_free(bw.standard_upd, s);
+  table_free(bw.standard32_upd, s);
   if (bw.s_wg) {
     (void)hipStreamSynchronize(bw.s_wg);
     (void)hipStreamDestroy(bw.s_wg);
@@ -2535,7 +2631,8 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
         if (e0) (void)hipEventRecord(*e0, s);
         hipLaunchKernelGGL(k_spmv_dir<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-        hipLaunchKernelGGL(k_update<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+        hipLaunchKernelGGL(k_update<float>, dim3(update_wg(nwg, m.n_nodes)), dim3(MAX_TPB), 0, s,
+                           dd, nullptr);
         if (e1) (void)hipEventRecord(*e1, s);
       };
       e = run_polled(w, s, cap, profile_every, cap >= STD_SPAN ? STD_SPAN : 1, launch, &it, &st);

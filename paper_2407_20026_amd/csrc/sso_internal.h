@@ -405,6 +405,8 @@ struct BatchWork {
   LaunchTable<PcgDesc<double>> standard;
   std::map<int, LaunchTable<FusedDesc<double>>> fused;   // by padded width
   LaunchTable<PcgDesc<float>> standard32;   // FP32 inner solves of mixed-precision problems
+  LaunchTable<PcgDesc<double>> standard_upd;   // the k_update launches of the two above
+  LaunchTable<PcgDesc<float>> standard32_upd;
   std::map<int, LaunchTable<FusedDesc<float>>> fused32;
   LaunchTable<PcgDesc<double>> wg;   // one-workgroup problems, launched on s_wg
   hipStream_t s_wg = nullptr;
