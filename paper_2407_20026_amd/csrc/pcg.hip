@@ -1658,7 +1658,10 @@ static int choose_wg(int64_t n_nodes, int cap) {
 // state, the previous kernel's partials) over more rows.  Measured (served stream closed loop
 // of 256 requests / single 120 x 120 / single 300 x 300 shell): 1 pass 80.1 solves/s / 62.9 ms /
 // 599.6 ms; 2 passes 93.1 / 62.6 / 606.3; 4 passes 94.1 / 85.1 / 590.8; 8 passes 89.9 / 137.9 /
-// 674.3.  (The 300 x 300 shell is at the cap in every case.)
+// 674.3.  (The 300 x 300 shell is at the cap in every case.)  With three blocks per step in
+// large multi-problem launches, 3 or 4 passes for problems of at most 8,192 nodes only (whose
+// single solves take the fused kernel) gave 116.5 and 113.3 against 117.5-117.9 solves/s on
+// 1,000 requests of the stream.
 #ifndef SSO_STD_PASSES
 #define SSO_STD_PASSES 2
 #endif
