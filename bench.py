@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     ("shell60", "fp64", "k_cg1_iter1"): (6570.6 * 2.000 + 954.4 * 1.000) * 1024,
     ("shell300", "fp64", "k_spmv_dir + k_update"):
-        (130708.6 * 2.000 + 8492.5 * 1.000 + 15952.6 * 2.000 + 12705.9 * 1.000) * 1024,
+        (128416.2 * 2.000 + 8706.5 * 1.000 + 15948.1 * 2.000 + 12705.9 * 1.000) * 1024,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
