@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 # read for a plain copy of known size (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel
 # code they were taken on: an entry is removed when one of its kernels changes.
 MEASURED_TRAFFIC = {
-    ("shell60", "fp64", "k_cg1_iter1"): (6570.6 * 2.000 + 954.4 * 1.000) * 1024,
+    ("shell60", "fp64", "k_cg1_iter1"): (6334.7 * 2.000 + 947.0 * 1.000) * 1024,
     ("shell300", "fp64", "k_spmv_dir + k_update"):
         (128416.2 * 2.000 + 8706.5 * 1.000 + 15948.1 * 2.000 + 12705.9 * 1.000) * 1024,
 }
