@@ -239,9 +239,9 @@ def stream_headline(args):
         log(f"stream {prec} closed loop: {st.solves_per_s:.1f} solves/s, "
             f"{st.dof_per_s / 1e6:.2f} M DOF/s, {st.wall_s:.1f} s")
     timed = [p for p in (head, "fp64") if p in closed][:2]
+    lam = 0.8 * min(closed[p].solves_per_s for p in timed)
     if args.no_poisson:
         timed = []
-    lam = 0.8 * min(closed[p].solves_per_s for p in closed)
     t_arr = poisson_arrivals(n, lam, seed=3)
     for prec in timed:
         st = servers[prec].run([Request(i, m, float(t_arr[i])) for i, m in enumerate(meshes)])
