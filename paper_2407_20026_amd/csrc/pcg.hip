@@ -470,29 +470,51 @@ constexpr bool zp_pairs() {
   return sizeof(T) == 4;
 }
 
-// row_product2 on interleaved (z, p) pairs: the same products in the same order.
-__device__ inline void row_product2_zp(int rb, int re, const int32_t* __restrict__ bcol,
-                                       const float* __restrict__ K,
-                                       const float* __restrict__ zp, int a, int b, float& az,
+// row_product2 on interleaved (z, p) pairs: the same products in the same order, with the same
+// global-address loads and the next step's block columns issued with the current step's loads.
+__device__ inline void row_product2_zp(int rb, int re, const int32_t* __restrict__ bcol_,
+                                       const float* __restrict__ K_,
+                                       const float* __restrict__ zp_, int a, int b, float& az,
                                        float& ap) {
+  typedef float N4 __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) N4* G4;
+  const gptr<int32_t> bcol = as_global(bcol_);
+  const gptr<float> K = as_global(K_);
+  const gptr<float> zp = as_global(zp_);
   const int off = 6 * a + b;
   float sz = 0, sp = 0;
   int s = rb;
-  for (; s + 2 <= re; s += 2) {
-    const int64_t J0 = bcol[s], J1 = bcol[s + 1];
-    const float2 k0 = *reinterpret_cast<const float2*>(K + 36 * (int64_t)s + off);
-    const float2 k1 = *reinterpret_cast<const float2*>(K + 36 * (int64_t)(s + 1) + off);
-    const float4 v0 = *reinterpret_cast<const float4*>(zp + 2 * (6 * J0 + b));
-    const float4 v1 = *reinterpret_cast<const float4*>(zp + 2 * (6 * J1 + b));
-    sz += k0.x * v0.x + k0.y * v0.z;
-    sp += k0.x * v0.y + k0.y * v0.w;
-    sz += k1.x * v1.x + k1.y * v1.z;
-    sp += k1.x * v1.y + k1.y * v1.w;
-  }
-  for (; s < re; ++s) {
-    const int64_t J = bcol[s];
-    const float2 kv = *reinterpret_cast<const float2*>(K + 36 * (int64_t)s + off);
-    const float4 v = *reinterpret_cast<const float4*>(zp + 2 * (6 * J + b));
+  if (re - rb >= 2) {
+    int J0 = bcol[s], J1 = bcol[s + 1];
+    for (;;) {
+      const float2 k0 = load2<float2>(K + 36 * (int64_t)s + off);
+      const float2 k1 = load2<float2>(K + 36 * (int64_t)(s + 1) + off);
+      const N4 v0 = *(G4)(zp + 2 * (6 * (int64_t)J0 + b));
+      const N4 v1 = *(G4)(zp + 2 * (6 * (int64_t)J1 + b));
+      const int sn = s + 2;
+      const int sc = sn + 2 <= re ? sn : re - 2;
+      const int J0n = bcol[sc], J1n = bcol[sc + 1];
+      sz += k0.x * v0.x + k0.y * v0.z;
+      sp += k0.x * v0.y + k0.y * v0.w;
+      sz += k1.x * v1.x + k1.y * v1.z;
+      sp += k1.x * v1.y + k1.y * v1.w;
+      s = sn;
+      if (s + 2 > re) {
+        if (s < re) {   // one block left: column bcol[re - 1] = J1n
+          const float2 kv = load2<float2>(K + 36 * (int64_t)s + off);
+          const N4 v = *(G4)(zp + 2 * (6 * (int64_t)J1n + b));
+          sz += kv.x * v.x + kv.y * v.z;
+          sp += kv.x * v.y + kv.y * v.w;
+        }
+        break;
+      }
+      J0 = J0n;
+      J1 = J1n;
+    }
+  } else if (s < re) {
+    const int J = bcol[s];
+    const float2 kv = load2<float2>(K + 36 * (int64_t)s + off);
+    const N4 v = *(G4)(zp + 2 * (6 * (int64_t)J + b));
     sz += kv.x * v.x + kv.y * v.z;
     sp += kv.x * v.y + kv.y * v.w;
   }
