@@ -81,16 +81,19 @@ enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1, SSO_PREC_AUTO = 2 };
 /* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
  * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one
  * reduction per iteration; keeps B = K M, M the block-Jacobi inverse, beside K: one more array
- * of K's size).  AUTO: sso_solve takes FUSED up to 8,192 nodes (latency-bound sizes; measured:
- * 13.4 against 20.2 ms on a 60 x 60 shell, equal on 90 x 90, 88 against 63 ms on 120 x 120)
- * and STANDARD above; sso_solve_begin (multi-problem launches) takes STANDARD.
+ * of K's size).  AUTO: sso_solve takes WG for FP64 problems resident in one workgroup's LDS
+ * (at most 144 nodes; measured 3.07 against 4.39 ms on the 121-node grid-shell), FUSED up to
+ * 8,192 nodes (latency-bound sizes; 13.4 against 20.2 ms on a 60 x 60 shell, equal on 90 x 90,
+ * 88 against 63 ms on 120 x 120) and STANDARD above; sso_solve_begin (multi-problem launches)
+ * takes WG for the same LDS-resident problems and STANDARD for the others.
  * WG: the standard recurrences with one workgroup per problem, every iteration inside one launch
  * (workgroup barriers between the phases, no grid-wide synchronisation; a single solve is one
  * launch up to 16,384 iterations, a multi-problem launch gives such a problem 16 times the
- * iterations asked for, in a kernel of its own beside the other kinds).  For problems too small
- * to fill more than one compute unit.  FP64 only (with SSO_PREC_MIXED: SSO_EINVAL; AUTO precision
- * resolves to FP64).  Its rounding differs from STANDARD's in the order of the three
- * reductions only. */
+ * iterations asked for, in a kernel of its own beside the other kinds).  A problem of at most
+ * 144 nodes whose vectors, pattern and packed inverses fit 60 KiB runs resident in LDS (only K
+ * read from memory each iteration); larger ones read everything from memory and are slower than
+ * the other recurrences.  FP64 only (with SSO_PREC_MIXED: SSO_EINVAL; AUTO precision resolves to
+ * FP64).  Its rounding differs from STANDARD's in the order of the reductions only. */
 enum { SSO_SOLVER_AUTO = 0, SSO_SOLVER_STANDARD = 1, SSO_SOLVER_FUSED = 2, SSO_SOLVER_WG = 3 };
 
 /* Structure description.  Sec. 2.2.1 model-building API. */

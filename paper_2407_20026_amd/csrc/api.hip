@@ -473,11 +473,15 @@ int run_solver(sso_problem* p, const double* b, double* x, int* iters, int* oute
 // bracket the stages.
 int prepare(sso_problem* p, bool batch) {
   hipStream_t s = p->s;
-  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes);
+  p->solver_used = pcg_pick_solver(p->opt.solver, p->m.n_nodes, p->pat.n_blocks,
+                                   mixed_for(p->opt, p->pat.n_blocks));
   // multi-problem launches: many problems in flight make the iteration bandwidth-bound, where
   // the standard pair streams faster than the fused kernel (16 60 x 60 shells: 123 vs 93
-  // solves/s; 256 80 x 80 shells: 13.2 vs 19.2 s)
-  if (batch && p->opt.solver == SSO_SOLVER_AUTO) p->solver_used = SSO_SOLVER_STANDARD;
+  // solves/s; 256 80 x 80 shells: 13.2 vs 19.2 s).  A problem resident in one workgroup's LDS
+  // keeps that solver in its kernel beside the launches (served stream: the small requests'
+  // median latency 14.5 -> 5.1 ms at the same capacity).
+  if (batch && p->opt.solver == SSO_SOLVER_AUTO && p->solver_used != SSO_SOLVER_WG)
+    p->solver_used = SSO_SOLVER_STANDARD;
   const bool mx = mixed(p), fu = fused(p);
   const int64_t nk = 36 * p->pat.n_blocks;
   const int64_t nb = 36 * right_precondition_blocks(p->pat, p->m.n_nodes);

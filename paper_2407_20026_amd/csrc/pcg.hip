@@ -828,13 +828,11 @@ __device__ inline void wg1_sum(double v[NV]) {
   __syncthreads();
 }
 
-// Up to n_iter iterations of problem blockIdx.x (descriptor D[blockIdx.x]; its n_wg, wg_base,
-// pa and pb are not used).  At j = 0 (x = 0, r = b, z = Dinv b, p_{-1} = 0 from the
-// initialisation kernel) the kernel forms r^T z and r^T r itself.  The stopping test is the
-// standard pair's, on r_j^T r_j against rtol^2 |b|^2.
-__global__ void __launch_bounds__(WG1_TPB)
-k_pcg_wg(const PcgDesc<double>* __restrict__ D, int n_iter) {
-  const PcgDesc<double> d = D[blockIdx.x];
+// Up to n_iter iterations of one problem, its vectors in global memory (descriptor d; its n_wg,
+// wg_base, pa and pb are not used).  At j = 0 (x = 0, r = b, z = Dinv b, p_{-1} = 0 from the
+// initialisation kernel) it forms r^T z and r^T r itself.  The stopping test is the standard
+// pair's, on r_j^T r_j against rtol^2 |b|^2.
+__device__ inline void wg_global(const PcgDesc<double>& d, int n_iter) {
   PcgState* st = d.st;
   const int n = d.n_nodes;
   const StdState S = std_state(st);
@@ -942,6 +940,245 @@ k_pcg_wg(const PcgDesc<double>* __restrict__ D, int n_iter) {
       st->done = 1;
     }
   }
+}
+
+// The same iterations with the problem resident in the workgroup's LDS, for problems of at most
+// WGL_MAX_NODES nodes whose gathered vectors and pattern fit it (wgl_bytes): z, p_{j-1} and p_j,
+// the block columns and the row pointers are staged once per launch.  Each lane that owns a DOF
+// (the first of its 3-lane set, as in the products) keeps the DOF's x and r in registers for the
+// whole launch and uses the same mapping in both phases; Ap and p_j pass between the phases
+// through LDS, a node's six r values come by wave shuffles, and the packed inverses are staged
+// in LDS too.  Only K is read from memory each iteration.  The products, and their order, are those of the global path; the
+// reduction trees differ (lanes, not 60-lane node groups, in the second phase).
+constexpr int WGL_PASSES = 3;
+constexpr int WGL_MAX_NODES = WG1_ROWS * WGL_PASSES;   // 144
+constexpr int WGL_LDS_BYTES = 60 * 1024;
+__host__ __device__ inline int64_t wgl_bytes(int64_t n_nodes, int64_t n_blocks) {
+  return (4 * 6 + DINV_PACKED) * 8 * n_nodes + 4 * (n_nodes + 1 + n_blocks);
+}
+
+// row_product2 with the block columns and the gathered vectors in LDS (K from memory), three
+// blocks a step so that a step's K loads are in flight together.
+__device__ inline void row_product_lds(int rb, int re, const int32_t* bcl,
+                                       const double* __restrict__ K_, const double* zl,
+                                       const double* pl, int a, int b, double& az,
+                                       double& ap) {
+  const gptr<double> K = as_global(K_);
+  const int off = 6 * a + b;
+  double sz = 0, sp = 0;
+  int s = rb;
+  for (; s + 3 <= re; s += 3) {
+    const int J0 = bcl[s], J1 = bcl[s + 1], J2 = bcl[s + 2];
+    const double2 k0 = load2<double2>(K + 36 * (int64_t)s + off);
+    const double2 k1 = load2<double2>(K + 36 * (int64_t)(s + 1) + off);
+    const double2 k2 = load2<double2>(K + 36 * (int64_t)(s + 2) + off);
+    const double2 z0 = *reinterpret_cast<const double2*>(zl + 6 * J0 + b);
+    const double2 z1 = *reinterpret_cast<const double2*>(zl + 6 * J1 + b);
+    const double2 z2 = *reinterpret_cast<const double2*>(zl + 6 * J2 + b);
+    const double2 p0 = *reinterpret_cast<const double2*>(pl + 6 * J0 + b);
+    const double2 p1 = *reinterpret_cast<const double2*>(pl + 6 * J1 + b);
+    const double2 p2 = *reinterpret_cast<const double2*>(pl + 6 * J2 + b);
+    sz += k0.x * z0.x + k0.y * z0.y;
+    sp += k0.x * p0.x + k0.y * p0.y;
+    sz += k1.x * z1.x + k1.y * z1.y;
+    sp += k1.x * p1.x + k1.y * p1.y;
+    sz += k2.x * z2.x + k2.y * z2.y;
+    sp += k2.x * p2.x + k2.y * p2.y;
+  }
+  for (; s < re; ++s) {
+    const int J = bcl[s];
+    const double2 kv = load2<double2>(K + 36 * (int64_t)s + off);
+    const double2 zv = *reinterpret_cast<const double2*>(zl + 6 * J + b);
+    const double2 pv = *reinterpret_cast<const double2*>(pl + 6 * J + b);
+    sz += kv.x * zv.x + kv.y * zv.y;
+    sp += kv.x * pv.x + kv.y * pv.y;
+  }
+  az = sz;
+  ap = sp;
+}
+
+__device__ inline void wg_lds(const PcgDesc<double>& d, int n_iter, unsigned char* smem) {
+  PcgState* st = d.st;
+  const int n = d.n_nodes;
+  const int n6 = 6 * n;
+  const StdState S = std_state(st);
+  if (S.done) return;
+  const SpLane L = sp_lane();
+  const int wave = threadIdx.x >> 6;
+  double* zl = reinterpret_cast<double*>(smem);
+  double* pl0 = zl + n6;
+  double* pl1 = pl0 + n6;
+  double* apl = pl1 + n6;
+  double* dl = apl + n6;   // packed inverses, DINV_PACKED per node
+  int32_t* rpl = reinterpret_cast<int32_t*>(dl + DINV_PACKED * n);
+  int32_t* bcl = rpl + (n + 1);
+  const gptr<int32_t> brow = as_global(d.brow_ptr);
+  int j = S.jn;
+  {
+    const int nbk = brow[n];
+    const gptr<int32_t> bc = as_global(d.bcol);
+    for (int i = threadIdx.x; i <= n; i += WG1_TPB) rpl[i] = brow[i];
+    for (int i = threadIdx.x; i < nbk; i += WG1_TPB) bcl[i] = bc[i];
+    const gptr<double> zg = as_global(d.z);
+    const gptr<double> pg = as_global((j & 1) ? d.p[1] : d.p[0]);   // p_{j-1}
+    double* po = (j & 1) ? pl1 : pl0;
+    for (int q = threadIdx.x; q < n6; q += WG1_TPB) {
+      zl[q] = zg[q];
+      po[q] = pg[q];
+    }
+    const gptr<double> dg = as_global(d.Dinv);
+    for (int i = threadIdx.x; i < DINV_PACKED * n; i += WG1_TPB) dl[i] = dg[i];
+  }
+  const bool owner = L.ok && L.b == 0;
+  double xk[WGL_PASSES], rk[WGL_PASSES];
+#pragma unroll
+  for (int k = 0; k < WGL_PASSES; ++k) {
+    const int I = k * WG1_ROWS + wave * ROWS_PER_WAVE + L.g;
+    xk[k] = 0.0;
+    rk[k] = 0.0;
+    if (owner && I < n) {
+      const int64_t q = 6 * (int64_t)I + L.a;
+      xk[k] = as_global(d.x)[q];
+      rk[k] = as_global(d.r)[q];
+    }
+  }
+  __syncthreads();
+  double rz, rzp = 1.0, rr, ff = S.ff;
+  if (j == 0) {
+    double v[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < WGL_PASSES; ++k) {
+      const int I = k * WG1_ROWS + wave * ROWS_PER_WAVE + L.g;
+      if (owner && I < n) {
+        v[0] += rk[k] * zl[6 * I + L.a];
+        v[1] += rk[k] * rk[k];
+      }
+    }
+    wg1_sum<2>(v);
+    rz = v[0];
+    rr = v[1];
+    ff = rr;
+  } else {
+    rz = (j & 1) ? S.rz1 : S.rz0;
+    rzp = (j & 1) ? S.rz0 : S.rz1;
+    rr = uniform(st->rr);
+  }
+  const int j_end = j + n_iter;
+  int stop = 0, status = SSO_OK;
+  for (;; ++j) {
+    if (!std::isfinite(rr) || !std::isfinite(rz)) {
+      stop = 1;
+      status = SSO_EBREAKDOWN;
+    } else if (rr <= S.rtol2 * ff) {
+      stop = 1;
+    } else if (j >= S.max_it) {
+      stop = 1;
+      status = SSO_ENOTCONV;
+    }
+    if (stop || j >= j_end) break;
+    const double beta = (j == 0) ? 0.0 : rz / rzp;
+    const double* po = (j & 1) ? pl1 : pl0;   // p_{j-1}
+    double* pnl = (j & 1) ? pl0 : pl1;        // p_j
+    double my = 0.0;
+#pragma unroll 1
+    for (int k = 0; k * WG1_ROWS < n; ++k) {
+      const int I = k * WG1_ROWS + wave * ROWS_PER_WAVE + L.g;
+      const bool ok = L.ok && I < n;
+      int rb = 0, re = 0;
+      if (ok) {
+        rb = rpl[I];
+        re = rpl[I + 1];
+      }
+      double az, ap;
+      row_product_lds(rb, re, bcl, d.K, zl, po, L.a, L.b, az, ap);
+      const double sz = sum3(az), sp = sum3(ap);
+      if (ok && L.b == 0) {
+        const int q = 6 * I + L.a;
+        const double pn = zl[q] + beta * po[q];
+        const double Apq = sz + beta * sp;
+        pnl[q] = pn;
+        apl[q] = Apq;
+        my += pn * Apq;
+      }
+    }
+    double pap[1] = {my};
+    wg1_sum<1>(pap);
+    const double alpha = rz / pap[0];
+    double v[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < WGL_PASSES; ++k) {
+      if (k * WG1_ROWS >= n) continue;
+      const int I = k * WG1_ROWS + wave * ROWS_PER_WAVE + L.g;
+      const bool ok = owner && I < n;
+      if (ok) {
+        const int q = 6 * I + L.a;   // written by this lane in the product phase
+        xk[k] += alpha * pnl[q];
+        rk[k] -= alpha * apl[q];
+      }
+      double rn[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) rn[c] = __shfl(rk[k], ROW_LANES * L.g + 3 * c, 64);
+      if (ok) {
+        const double* dn = dl + DINV_PACKED * I;
+        double zq = 0;
+#pragma unroll
+        for (int h = 0; h < 3; ++h)
+          zq += dn[dinv_index(L.a, 2 * h)] * rn[2 * h] +
+                dn[dinv_index(L.a, 2 * h + 1)] * rn[2 * h + 1];
+        zl[6 * I + L.a] = zq;
+        v[0] += rk[k] * zq;
+        v[1] += rk[k] * rk[k];
+      }
+    }
+    wg1_sum<2>(v);
+    rzp = rz;
+    rz = v[0];
+    rr = v[1];
+  }
+  // back to memory: x and r of the owned DOFs, z and p_{j-1} of the next launch
+#pragma unroll
+  for (int k = 0; k < WGL_PASSES; ++k) {
+    const int I = k * WG1_ROWS + wave * ROWS_PER_WAVE + L.g;
+    if (owner && I < n) {
+      const int64_t q = 6 * (int64_t)I + L.a;
+      d.x[q] = xk[k];
+      d.r[q] = rk[k];
+    }
+  }
+  {
+    double* pg = (j & 1) ? d.p[1] : d.p[0];
+    const double* po = (j & 1) ? pl1 : pl0;
+    for (int q = threadIdx.x; q < n6; q += WG1_TPB) {
+      d.z[q] = zl[q];
+      pg[q] = po[q];
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->rzs[j & 1] = rz;
+    st->rzs[(j + 1) & 1] = rzp;
+    st->rr = rr;
+    st->ff = ff;
+    st->it = j;
+    st->jc = j;
+    st->jn = j;
+    if (stop) {
+      st->status = status;
+      st->done = 1;
+    }
+  }
+}
+
+// One problem per workgroup (descriptor D[blockIdx.x]): resident in LDS when it fits the
+// lds_bytes of dynamic LDS the launch provides, else from global memory.
+__global__ void __launch_bounds__(WG1_TPB)
+k_pcg_wg(const PcgDesc<double>* __restrict__ D, int n_iter, int lds_bytes) {
+  extern __shared__ __align__(16) unsigned char wg_smem[];
+  const PcgDesc<double> d = D[blockIdx.x];
+  const int n = d.n_nodes;
+  if (n <= WGL_MAX_NODES && wgl_bytes(n, as_global(d.brow_ptr)[n]) <= (int64_t)lds_bytes)
+    wg_lds(d, n_iter, wg_smem);
+  else
+    wg_global(d, n_iter);
 }
 
 // ---- single-reduction PCG (Chronopoulos & Gear): one kernel and one reduction per iteration --
@@ -2217,8 +2454,8 @@ static hipError_t launch_wg(BatchWork& bw, int n_iter, hipStream_t s) {
   if ((e = hipStreamWaitEvent(bw.s_wg, bw.ev_in, 0)) != hipSuccess) return e;
   const int64_t budget = (int64_t)n_iter * WG1_BATCH_FACTOR;
   const int it = budget > (1 << 30) ? (1 << 30) : (int)budget;
-  hipLaunchKernelGGL(k_pcg_wg, dim3(np), dim3(WG1_TPB), 0, bw.s_wg,
-                     reinterpret_cast<const PcgDesc<double>*>(bw.wg.d_desc), it);
+  hipLaunchKernelGGL(k_pcg_wg, dim3(np), dim3(WG1_TPB), WGL_LDS_BYTES, bw.s_wg,
+                     reinterpret_cast<const PcgDesc<double>*>(bw.wg.d_desc), it, WGL_LDS_BYTES);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipEventRecord(bw.ev_wg, bw.s_wg);
 }
@@ -2343,9 +2580,15 @@ static constexpr int64_t FUSED_MAX_NODES = 8192;
 static_assert(FUSED_MAX_NODES <= (int64_t)PCG_MAX_WG * ROWS_PER_WG,
               "the single-reduction recurrences run in one pass of the grid");
 
-int pcg_pick_solver(int solver, int64_t n_nodes) {
+// AUTO: one workgroup per problem (FP64) when the problem is resident in its LDS (at most 144 nodes;
+// single solves measured 1.50 against 2.87 ms at 64 nodes, 3.07 against 4.39 ms at 121 and
+// 2.67 against 3.26 ms at 144), the single-reduction recurrences up to FUSED_MAX_NODES, the
+// standard ones above.
+int pcg_pick_solver(int solver, int64_t n_nodes, int64_t n_blocks, bool mixed) {
   if (solver == SSO_SOLVER_STANDARD || solver == SSO_SOLVER_FUSED || solver == SSO_SOLVER_WG)
     return solver;
+  if (!mixed && n_nodes <= WGL_MAX_NODES && wgl_bytes(n_nodes, n_blocks) <= WGL_LDS_BYTES)
+    return SSO_SOLVER_WG;
   return n_nodes <= FUSED_MAX_NODES ? SSO_SOLVER_FUSED : SSO_SOLVER_STANDARD;
 }
 
@@ -2385,11 +2628,14 @@ hipError_t pcg_solve_wg(const Mesh& m, const Pattern& pat, const double* K, cons
     w.prof_cap = PROF_CAP;
   }
   const PcgDesc<double>* dd = reinterpret_cast<const PcgDesc<double>*>(w.desc64);
+  // resident in LDS when the problem fits
+  const int64_t lb = wgl_bytes(m.n_nodes, pat.n_blocks);
+  const int lds = (m.n_nodes <= WGL_MAX_NODES && lb <= WGL_LDS_BYTES) ? (int)lb : 0;
   // the kernel stops itself at iteration max_it, so the launches end
   for (int64_t launched = 0;; launched += WG1_SOLO_ITERS) {
     const bool prof = profile_every > 0 && launched == 0;
     if (prof && (e = hipEventRecord(w.prof_ev[0], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pcg_wg, dim3(1), dim3(WG1_TPB), 0, s, dd, WG1_SOLO_ITERS);
+    hipLaunchKernelGGL(k_pcg_wg, dim3(1), dim3(WG1_TPB), lds, s, dd, WG1_SOLO_ITERS, lds);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (prof && (e = hipEventRecord(w.prof_ev[1], s)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(w.h_st, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s)) !=

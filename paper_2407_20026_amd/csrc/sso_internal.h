@@ -347,8 +347,9 @@ hipError_t pcg_solve_wg(const Mesh& m, const Pattern& pat, const double* K, cons
 hipError_t pcg_solve(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* B, const double* b, double* x, double rtol, int max_it,
                      PcgWork& w, hipStream_t s, int* iters, int* status, int profile_every = 0);
-// SSO_SOLVER_STANDARD or SSO_SOLVER_FUSED for an sso_options.solver value.
-int pcg_pick_solver(int solver, int64_t n_nodes);
+// The recurrences that run for an sso_options.solver value (AUTO resolved by size; the
+// one-workgroup solver only in FP64).
+int pcg_pick_solver(int solver, int64_t n_nodes, int64_t n_blocks, bool mixed);
 // B = K Dinv block by block (B32: the same rounded to FP32; either may be null), in the padded
 // block-row layout when the pattern has one; B holds right_precondition_blocks() 6x6 blocks.
 int64_t right_precondition_blocks(const Pattern& pat, int64_t n_nodes);

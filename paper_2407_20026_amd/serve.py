@@ -335,8 +335,9 @@ class BatchedServer:
         self.mixed = {0: False, 1: True}.get(self.options.precision)
         self.device = torch.device(device)
         self.chunk = chunk
-        # requests of at most wg_max_nodes nodes run on one workgroup each (SSO_SOLVER_WG), in a
-        # kernel of their own beside the multi-problem launches (AUTO recurrences, not mixed)
+        # wg_max_nodes > 0: requests of at most that many nodes run on one workgroup each
+        # (SSO_SOLVER_WG) whatever their size in LDS; 0: the library's AUTO choice, which puts the
+        # LDS-resident ones (at most 144 nodes) there
         self.wg_max_nodes = wg_max_nodes
         self.options_wg = None
         if wg_max_nodes > 0 and self.options.solver == SOLVER_AUTO and \
