@@ -1458,7 +1458,7 @@ __host__ __device__ inline Cg1Args<T> cg1_args(const FusedDesc<T>& d, int i) {
 // values, gathered vectors).  Otherwise (multi-problem launches) the index is the workgroup's
 // own counter and the partials are loaded where they are summed, which keeps the register
 // count, and the occupancy that many problems in flight need, lower.
-template <class T, bool SINGLE, int W, bool ONE_PASS = false>
+template <class T, bool SINGLE, int W, bool ONE_PASS = false, bool JW = !SINGLE>
 __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int ng) {
   PcgState* st = d.st;
   const PcgState* stv = SINGLE ? lane_view(st) : st;
@@ -1629,7 +1629,7 @@ __device__ __forceinline__ void cg1_iteration(const Cg1Args<T>& d, int lb, int n
   }
   block_sum<3, T, 2, true>(v);   // the kernel ends after it
   write_partials<3, T>(v, d.pp_out, lb, ng);
-  if (!SINGLE && threadIdx.x == 0) d.jw[lb] = i + 1;
+  if (JW && threadIdx.x == 0) d.jw[lb] = i + 1;
 }
 
 // Multi-problem form: descriptor table + workgroup map, iteration index per workgroup.
@@ -1639,6 +1639,177 @@ k_cg1_iter(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
   const WgOf<FusedDesc<T>> G = wg_of(D, wg_prob);
   if (G.d->st->done) return;
   cg1_iteration<T, false, W>(cg1_args(*G.d, G.d->jw[G.lb]), G.lb, G.ng);
+}
+
+// Multi-problem form for padded rows (W = 6, 9 or 12) with a register budget for many
+// workgroups in flight: the iteration above, in the same arithmetic order, but with three slots a
+// step (the next step's columns and values loaded with this step's gathers) instead of a whole
+// row's loads at once, which holds the single-problem kernel to two waves per SIMD.  The
+// descriptor is copied whole; the workgroup's iteration counter, the state, the first step's
+// slots, the own-row operands and the previous partials (at most two per thread: n_wg <= 768)
+// are issued together.  One pass: every row has a workgroup (n_wg x 18 >= n_nodes).
+constexpr int CG1_LEAN_MAX_WG = 2 * MAX_TPB;
+
+template <class T, int W>
+__global__ void __launch_bounds__(MAX_TPB)
+k_cg1_lean(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  static_assert(W % 3 == 0 && W > 0, "three padded slots a step");
+  using V = typename Vec2<T>::type;
+  const FusedDesc<T> d = D[wg_prob[blockIdx.x]];
+  const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
+  const SpLane L = sp_lane();
+  const int slot = (threadIdx.x >> 6) * ROWS_PER_WAVE + L.g;
+  const int I = lb * ROWS_PER_WG + slot;
+  const bool ok = L.ok && I < d.n_nodes;
+  const bool own = ok && L.b == 0;
+  const int Ic = ok ? I : 0;
+  const int64_t q = 6 * (int64_t)I + L.a;
+  const int64_t qc = 6 * (int64_t)Ic + L.a;
+  // first group: iteration counter and state (vector loads, see lane_view), the first step's
+  // slots, the own-row operands that do not depend on the iteration's parity, the inverse row,
+  // the previous partials of both parities' buffers being unknown yet: read after the counter
+  int zo;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zo));
+  const int i = __builtin_amdgcn_readfirstlane(
+      *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(d.jw + lb) + zo));
+  const PcgState* stv = lane_view(d.st);
+  const int done = stv->done;
+  const double ff_prev = stv->ff, rz0 = stv->rzs[0], rz1 = stv->rzs[1];
+  const double al0 = stv->alphas[0], al1 = stv->alphas[1];
+  const gptr<int32_t> bce = as_global(d.bcol_ell);
+  const gptr<T> B = as_global(d.B);
+  const int64_t base = (int64_t)Ic * W;
+  const int off = 6 * L.a + L.b;
+  int J[3];
+  V kb[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    J[u] = bce[base + u];
+    kb[u] = load2<V>(B + 36 * (base + u) + off);
+  }
+  const T pq = as_global(d.p)[qc], xq = as_global(d.x)[qc];
+  if (__builtin_amdgcn_readfirstlane(done)) return;
+  const int par = i & 1;
+  // parity by selects: an array member indexed at run time would put the descriptor in scratch
+  const gptr<T> ri = as_global(par ? d.r[1] : d.r[0]);
+  const gptr<T> wi = as_global(par ? d.w[1] : d.w[0]);
+  const gptr<T> so = as_global(par ? d.s[1] : d.s[0]);
+  const gptr<double> pp = as_global(par ? d.pp[1] : d.pp[0]);
+  const T rq = ri[qc], wq = wi[qc], sq = so[qc];
+  double pv[3][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int k = (int)threadIdx.x + u * MAX_TPB;
+    const int kc = k < ng ? k : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pv[c][u] = pp[c * ng + kc];
+  }
+  T br = 0, bw = 0, bs = 0;
+#pragma unroll 1
+  for (int u0 = 0; u0 < W; u0 += 3) {
+    V rv[3], wv[3], tv[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int64_t j = 6 * (int64_t)J[u] + L.b;
+      rv[u] = load2<V>(ri + j);
+      wv[u] = load2<V>(wi + j);
+      tv[u] = load2<V>(so + j);
+    }
+    const int un = u0 + 3 < W ? u0 + 3 : u0;   // past the row: this step's slots again, unused
+    int Jn[3];
+    V kn[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      Jn[u] = bce[base + un + u];
+      kn[u] = load2<V>(B + 36 * (base + un + u) + off);
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      br += kb[u].x * rv[u].x + kb[u].y * rv[u].y;
+      bw += kb[u].x * wv[u].x + kb[u].y * wv[u].y;
+      bs += kb[u].x * tv[u].x + kb[u].y * tv[u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      J[u] = Jn[u];
+      kb[u] = kn[u];
+    }
+  }
+  const DinvRow<T> M = dinv_row(d.Dinv, Ic, L.a);   // in flight across the reduction
+  // the previous partials in the order of the single-problem iteration (a third per thread that
+  // n_wg <= 768 never has), then the step lengths and the stopping test
+  double tot[3];
+  {
+    const int k0 = (int)threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      tot[c] = ((0.0 + (k0 < ng ? pv[c][0] : 0.0)) + (k0 + MAX_TPB < ng ? pv[c][1] : 0.0)) + 0.0;
+  }
+  block_sum<3, double, 1, true>(tot);
+  const double gam = tot[0], del = tot[1], rho = tot[2];
+  const double ff = (i == 0) ? rho : ff_prev;
+  const double gam_prev = ((i - 1) & 1) ? rz1 : rz0, alpha_prev = ((i - 1) & 1) ? al1 : al0;
+  double beta_d = 0.0, alpha_d;
+  if (i == 0) {
+    alpha_d = gam / del;
+  } else {
+    beta_d = gam / gam_prev;
+    alpha_d = gam / (del - beta_d * gam / alpha_prev);
+  }
+  int stop = 0, status = SSO_OK;
+  if (!std::isfinite(rho) || !std::isfinite(gam)) {
+    stop = 1;
+    status = SSO_EBREAKDOWN;
+  } else if (rho <= d.rtol2 * ff) {
+    stop = 1;
+  } else if (i >= d.max_it) {
+    stop = 1;
+    status = SSO_ENOTCONV;
+  } else if (!(alpha_d > 0.0) || !std::isfinite(alpha_d)) {
+    stop = 1;
+    status = SSO_EBREAKDOWN;
+  }
+  PcgState* st = d.st;
+  if (lb == 0 && threadIdx.x == 0) {
+    st->rzs[i & 1] = gam;
+    st->alphas[i & 1] = alpha_d;
+    st->rr = rho;
+    st->it = i;
+    if (i == 0) st->ff = rho;
+    if (stop) {
+      st->status = status;
+      st->done = 1;
+    }
+  }
+  if (stop) return;
+  const T alpha = (T)alpha_d, beta = (T)beta_d, ab = alpha * beta;
+  const T wv = sum3(br - alpha * bw - ab * bs);
+  T r6[6];
+  node_values(rq, L, r6);
+  const T pvv = M.apply(r6) + beta * pq;
+  const T sv = wq + beta * sq;
+  const T rv = rq - alpha * sv;
+  T v[3] = {0, 0, 0};
+  T* const s_out = par ? d.s[0] : d.s[1];
+  T* const r_out = par ? d.r[0] : d.r[1];
+  T* const w_out = par ? d.w[0] : d.w[1];
+  if (own) {
+    __builtin_nontemporal_store(pvv, &d.p[q]);
+    __builtin_nontemporal_store(sv, &s_out[q]);
+    __builtin_nontemporal_store(xq + alpha * pvv, &d.x[q]);
+    __builtin_nontemporal_store(rv, &r_out[q]);
+    __builtin_nontemporal_store(wv, &w_out[q]);
+  }
+  node_values(rv, L, r6);
+  if (own) {
+    const T uv = M.apply(r6);
+    v[0] += rv * uv;
+    v[1] += wv * uv;
+    v[2] += rv * rv;
+  }
+  block_sum<3, T, 2, true>(v);
+  write_partials<3, T>(v, par ? d.pp[0] : d.pp[1], lb, ng);
+  if (threadIdx.x == 0) d.jw[lb] = i + 1;
 }
 
 // One problem: the descriptor by value, launch k performs iteration k (unless done).
@@ -2394,6 +2565,12 @@ static void launch_standard(const LaunchTable<PcgDesc<T>>& t, const LaunchTable<
 template <class T, int W>
 static void launch_fused_w(const LaunchTable<FusedDesc<T>>& t, hipStream_t s) {
   const FusedDesc<T>* d = reinterpret_cast<const FusedDesc<T>*>(t.d_desc);
+  if constexpr (W > 0) {
+    if (t.lean) {
+      hipLaunchKernelGGL((k_cg1_lean<T, W>), dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_cg1_iter<T, W>), dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
 }
 
@@ -2422,6 +2599,10 @@ static hipError_t fused_upload(std::map<int, LaunchTable<FusedDesc<T>>>& tables,
       return hipErrorInvalidValue;
     hipError_t e = table_upload(tables[kv.first], kv.second.data(), (int)kv.second.size(), s);
     if (e != hipSuccess) return e;
+    bool lean = true;   // every problem one pass, at most CG1_LEAN_MAX_WG workgroups
+    for (const auto& d : kv.second)
+      lean = lean && d.n_wg <= CG1_LEAN_MAX_WG && (int64_t)d.n_wg * ROWS_PER_WG >= d.n_nodes;
+    tables[kv.first].lean = lean;
   }
   return hipSuccess;
 }

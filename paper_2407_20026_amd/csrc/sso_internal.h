@@ -401,6 +401,7 @@ struct LaunchTable {
   std::vector<Desc> h_desc;
   std::vector<int32_t> h_wg;
   int total = 0;          // workgroups of one launch
+  bool lean = false;      // fused tables: every problem fits the lean multi-problem kernel
 };
 struct BatchWork {
   LaunchTable<PcgDesc<double>> standard;
