@@ -49,6 +49,8 @@ MEASURED_TRAFFIC = {
     ("shell60", "fp64", "k_cg1_iter1"): (6334.7 * 2.000 + 947.0 * 1.000) * 1024,
     ("shell300", "fp64", "k_spmv_dir + k_update"):
         (128416.2 * 2.000 + 8706.5 * 1.000 + 15948.1 * 2.000 + 12705.9 * 1.000) * 1024,
+    ("shell300", "fp64", "k_spmv_dir_sym + k_update"):
+        (83808.9 * 2.000 + 8705.5 * 1.000 + 15985.7 * 2.000 + 12775.4 * 1.000) * 1024,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
@@ -360,27 +362,40 @@ def problem_run(mesh, opts, steps, warmup, objective="compliance", with_grad=Tru
                       "standard",
             "n_blocks": n_blocks, "n_nodes": mesh.n_nodes,
             "iteration": {"kernels": "k_cg1_iter1" if st["solver"] == sso.SOLVER_FUSED else
+                          "k_spmv_dir_sym + k_update" if st["sym_products"] else
                           "k_spmv_dir + k_update", "bytes": st["spmv_bytes"],
                           "avg_us": it_us, "samples": int(sum(rec["it_n"]))},
             "_u": u, "_g": last["g"]}
 
 
-def algorithmic_iteration_bytes(n_nodes, n_blocks, precision):
+def algorithmic_iteration_bytes(n_nodes, n_blocks, precision, symmetric=False):
     """Algorithmic HBM bytes of one standard PCG iteration by the scope table's accounting:
     the BSR values, block columns and row pointers once; twelve vector passes (p read and Ap
     written by the product; x, r, p, Ap read and x, r, z written by the update; z and p read
     and p written for the direction); the 6 x 6 block-Jacobi inverse of every node (36 values).
     The library moves fewer than that (the direction is formed inside the product, the inverse
-    is stored packed, 21 values), so this is an upper bound of what the kernels need."""
+    is stored packed, 21 values), so this is an upper bound of what the kernels need.
+    symmetric: what a product that reads only K's upper triangle must fetch (the diagonal blocks
+    and half the others, with an 8-byte (column, value slot) pair per block in place of the
+    4-byte column): the bytes-read figure reported beside the scope table's one."""
     v = 4.0 if precision == "mixed" else 8.0
     n_dof = 6.0 * n_nodes
-    return (36.0 * v + 4.0) * n_blocks + 4.0 * (n_nodes + 1) + 12.0 * v * n_dof + \
-        36.0 * v * n_nodes
+    if symmetric:
+        k_bytes = 36.0 * v * 0.5 * (n_blocks + n_nodes) + 8.0 * n_blocks
+    else:
+        k_bytes = (36.0 * v + 4.0) * n_blocks
+    return k_bytes + 4.0 * (n_nodes + 1) + 12.0 * v * n_dof + 36.0 * v * n_nodes
 
 
 def roofline_of(run, workload, precision, ceilings=None):
     it = run["iteration"]
-    if it["kernels"] == "k_spmv_dir + k_update":
+    sym_read = None
+    if it["kernels"] in ("k_spmv_dir + k_update", "k_spmv_dir_sym + k_update"):
+        # the unit of work is one PCG iteration on this K, counted by the scope table (all of K
+        # read); the upper-triangle product fetches less, which is reported beside it
+        if "_sym" in it["kernels"]:
+            sym_read = algorithmic_iteration_bytes(run["n_nodes"], run["n_blocks"], precision,
+                                                   symmetric=True)
         it = dict(it, library_bytes=it["bytes"],
                   bytes=algorithmic_iteration_bytes(run["n_nodes"], run["n_blocks"], precision))
     achieved = it["bytes"] / (it["avg_us"] * 1e-6) / 1e9 if it["avg_us"] > 0 else 0.0
@@ -392,6 +407,9 @@ def roofline_of(run, workload, precision, ceilings=None):
            "samples": it["samples"]}
     if "library_bytes" in it:
         out["library_bytes_per_launch"] = it["library_bytes"]
+    if sym_read is not None and it["avg_us"] > 0:
+        out["bytes_read_per_launch"] = sym_read
+        out["frac_on_bytes_read"] = sym_read / (it["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
     if ceilings:
         out["measured_read_gbs"] = ceilings["read_gbs"]
         out["measured_copy_gbs"] = ceilings["copy_gbs"]

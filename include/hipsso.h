@@ -153,6 +153,11 @@ typedef struct {
   double spmv_bytes;          /* algorithmic bytes of one iteration                          */
   int32_t refine_steps;       /* mixed precision: outer steps (FP32 inner solves) run        */
   int32_t solver;             /* SSO_SOLVER_STANDARD, _FUSED or _WG: recurrences that ran    */
+  int32_t sym_products;       /* 1: the standard recurrences' products read only K's upper
+                                 triangle, each block below the diagonal as the transpose of
+                                 its mirror (single FP64 solves of a K of 128 MiB or more; the
+                                 same sums, bitwise, as reading all of K); spmv_bytes counts
+                                 that triangle                                               */
 } sso_stats;
 
 typedef struct sso_problem sso_problem;
@@ -332,7 +337,9 @@ int sso_pattern(sso_problem* p, const int32_t** row_ptr, const int32_t** col,
 
 /* Read back the assembled, masked K in scalar CSR order into vals [nnz] (device), the masked
  * system's right-hand side f [n_nodes][6] (device, may be NULL) of the last solve (0 on the
- * fixed DOFs; with prescribed displacements the lifted load on the free ones). */
+ * fixed DOFs; with prescribed displacements the lifted load on the free ones).  K is bitwise
+ * symmetric: an entry below the diagonal holds the sum of its transposed entry's element
+ * contributions, in that entry's order (the element matrices are symmetric up to rounding). */
 int sso_matrix(sso_problem* p, double* vals, double* f);
 
 /* Device memory the problem holds (*bytes, host): the memory taken for every buffer allocated on

@@ -54,7 +54,8 @@ class sso_stats(ctypes.Structure):
                 ("t_solve_us", ctypes.c_double), ("t_adj_us", ctypes.c_double),
                 ("bytes_moved", ctypes.c_double), ("spmv_us", ctypes.c_double),
                 ("spmv_samples", ctypes.c_int32), ("spmv_bytes", ctypes.c_double),
-                ("refine_steps", ctypes.c_int32), ("solver", ctypes.c_int32)]
+                ("refine_steps", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("sym_products", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -186,7 +186,7 @@ int debug_check_pattern(sso_problem* p) {
   const int n = m.n_nodes;
   const int64_t nb = pat.n_blocks, nc = pat.n_bcoo;
   std::vector<int32_t> brow(n + 1), bcol(nb), bseg(nb + 1), bperm(nc), bslot(nc), bdiag(n),
-      bsrow(nb), est(n + 1), ell((int64_t)n * pat.ell_w), bn(2 * (int64_t)m.n_beams),
+      bsrow(nb), bsym(2 * nb), est(n + 1), ell((int64_t)n * pat.ell_w), bn(2 * (int64_t)m.n_beams),
       qn(4 * (int64_t)m.n_quads);
   auto get = [&](std::vector<int32_t>& v, const int32_t* src) {
     return v.empty() ? hipSuccess
@@ -200,6 +200,7 @@ int debug_check_pattern(sso_problem* p) {
   TRY_HIP(get(bslot, pat.bslot));
   TRY_HIP(get(bdiag, pat.bdiag));
   TRY_HIP(get(bsrow, pat.bsrow));
+  TRY_HIP(get(bsym, pat.bsym));
   TRY_HIP(get(est, pat.estart));
   TRY_HIP(get(ell, pat.bcol_ell));
   TRY_HIP(get(bn, m.beam_nodes));
@@ -219,6 +220,7 @@ int debug_check_pattern(sso_problem* p) {
   h.bslot = bslot.data();
   h.bdiag = bdiag.data();
   h.bsrow = bsrow.data();
+  h.bsym = bsym.data();
   h.estart = est.data();
   h.bcol_ell = ell.data();
   h.beam_nodes = bn.data();
@@ -512,13 +514,19 @@ int prepare(sso_problem* p, bool batch) {
 
 bool fused_used(const sso_problem* p) { return p->solver_used == SSO_SOLVER_FUSED; }
 
-double solve_bytes(const sso_problem* p, int iters, int outer) {
+// single: a solve of its own (sso_solve, the adjoint), whose standard FP64 products read only
+// K's upper triangle above the size pcg_sym_products names; multi-problem launches read all of K
+bool sym_used(const sso_problem* p, bool single) {
+  return single && p->solver_used == SSO_SOLVER_STANDARD && pcg_sym_products(p->pat.n_blocks, mixed(p));
+}
+
+double solve_bytes(const sso_problem* p, int iters, int outer, bool single) {
   const int64_t nn = p->m.n_nodes, nb = p->pat.n_blocks;
   if (fused_used(p) && !mixed(p)) return iters * fused_bytes_per_iteration(nn, nb, false);
-  if (!mixed(p)) return iters * pcg_bytes_per_iteration(nn, nb, false);
+  if (!mixed(p)) return iters * pcg_bytes_per_iteration(nn, nb, false, sym_used(p, single));
   // inner FP32 iterations + one FP64 residual SpMV (K, x, b read; r written) per outer step
   double resid = 292.0 * nb + 4.0 * (nn + 1) + 3.0 * 8.0 * 6.0 * nn;
-  return iters * pcg_bytes_per_iteration(nn, nb, true) + (outer + 1) * resid;
+  return iters * pcg_bytes_per_iteration(nn, nb, true, false) + (outer + 1) * resid;
 }
 
 // ---- penalised volume objective (Sec. 3.3): shared by the allocating and static-scratch forms
@@ -703,13 +711,15 @@ int sso_solve(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->t_elem_us = elapsed_us(p->ev[0], p->ev[1]);
     stats->t_asm_us = elapsed_us(p->ev[1], p->ev[2]);
     stats->t_solve_us = elapsed_us(p->ev[2], p->ev[3]);
-    stats->bytes_moved = solve_bytes(p, iters, outer);
+    stats->bytes_moved = solve_bytes(p, iters, outer, true);
     stats->spmv_samples = p->w.prof_n;
     stats->spmv_us = p->w.prof_n ? p->w.prof_us / p->w.prof_n : 0.0;
-    stats->spmv_bytes = fused_used(p)
-                            ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
-                            : pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p));
+    stats->spmv_bytes =
+        fused_used(p) ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
+                      : pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p),
+                                                sym_used(p, true));
     stats->solver = p->solver_used;
+    stats->sym_products = sym_used(p, true) ? 1 : 0;
   }
   // after SSO_ENOTCONV u holds the last iterate; objective and adjoint stay available
   p->solved = (status == SSO_OK || status == SSO_ENOTCONV);
@@ -768,10 +778,10 @@ int sso_solve_end(sso_problem* p, double* u_out, sso_stats* stats) {
     stats->iters = iters;
     stats->rel_residual = p->h_scal[1] > 0 ? sqrt(p->h_scal[0] / p->h_scal[1]) : 0.0;
     stats->refine_steps = outer;
-    stats->bytes_moved = solve_bytes(p, iters, outer);
+    stats->bytes_moved = solve_bytes(p, iters, outer, false);
     stats->spmv_bytes =
         fused(p) ? fused_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p))
-                 : pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p));
+                 : pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, mixed(p), false);
     stats->solver = p->solver_used;
   }
   p->in_batch = false;
@@ -934,7 +944,7 @@ int sso_adjoint(sso_problem* p, int kind, const double* dg_du, double* dg_dxyz, 
     std::memset(stats, 0, sizeof(*stats));
     stats->iters = iters;
     stats->t_adj_us = elapsed_us(p->ev[4], p->ev[5]);
-    stats->bytes_moved = solve_bytes(p, iters, 0);
+    stats->bytes_moved = solve_bytes(p, iters, 0, true);
   }
   return status;
 }

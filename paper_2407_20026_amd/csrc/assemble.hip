@@ -8,7 +8,11 @@
 //
 // Assembly is gather-based and deterministic: one thread per entry (slot, a, b) of a 6x6 block
 // sums the slot's element contributions in ascending contribution id (= ascending element, then
-// ascending scalar index), with no atomics, so K is bitwise reproducible.
+// ascending scalar index), with no atomics, so K is bitwise reproducible.  An entry below the
+// diagonal (block (I, J) with J < I, or a > b in a diagonal block) sums the contributions of its
+// transposed entry, (b, a) of block (J, I), in the same order: the element matrices are
+// symmetric only up to rounding, and this makes K bitwise symmetric, which lets the PCG
+// products read a lower block as the transpose of its mirror.
 #include "sso_internal.h"
 
 namespace sso {
@@ -19,8 +23,8 @@ inline unsigned nblk(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb
 
 // K block values, row-major inside each 6x6 block, blocks in slot order.
 __global__ void k_assemble(Mesh m, int64_t n_blocks, const int32_t* bsrow, const int32_t* bcol,
-                           const int32_t* bseg, const int32_t* bperm, const double* coo,
-                           double* K) {
+                           const int32_t* bseg, const int32_t* bperm, const int32_t* bsym,
+                           const double* coo, double* K) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= 36 * n_blocks) return;
   int64_t s = t / 36;
@@ -30,10 +34,15 @@ __global__ void k_assemble(Mesh m, int64_t n_blocks, const int32_t* bsrow, const
   if (m.fixed[6 * (int64_t)I + a] || m.fixed[6 * (int64_t)J + b]) {
     v = (I == J && a == b) ? 1.0 : 0.0;
   } else {
+    // the upper triangle's entry whose value this one takes: itself, or its transpose (in the
+    // value slot: block (J, I) for J < I, the slot itself otherwise)
+    const bool low = J < I || (J == I && a > b);
+    const int64_t su = bsym[2 * s + 1];
+    const int ra = low ? b : a, rb = low ? a : b;
     v = 0.0;
-    for (int p = bseg[s]; p < bseg[s + 1]; ++p) {
+    for (int p = bseg[su]; p < bseg[su + 1]; ++p) {
       BlockRef r = decode_block(bperm[p], m.n_beams);
-      v += coo[coo_index(r, a, b, m.n_beams)];
+      v += coo[coo_index(r, ra, rb, m.n_beams)];
     }
   }
   K[t] = v;
@@ -168,7 +177,8 @@ __global__ void k_scalar_values(int n_nodes, const int32_t* brow_ptr, const doub
 hipError_t launch_assemble(const Mesh& m, const Pattern& pat, const double* coo, double* K,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_assemble, dim3(nblk(36 * pat.n_blocks, 256)), dim3(256), 0, s, m,
-                     pat.n_blocks, pat.bsrow, pat.bcol, pat.bseg, pat.bperm, coo, K);
+                     pat.n_blocks, pat.bsrow, pat.bcol, pat.bseg, pat.bperm, pat.bsym, coo,
+                     K);
   return hipGetLastError();
 }
 

@@ -115,6 +115,30 @@ __global__ void k_emit(int n_nodes, const int32_t* estart, const uint64_t* keys,
   }
 }
 
+// (column, value slot) of each slot: a block (I, J) with J < I takes the values of block (J, I)
+// (an element couples its nodes both ways, so that block exists; found by bisection in row J's
+// sorted columns), any other block its own.
+__global__ void k_sym_slots(int64_t n_blocks, const int32_t* brow_ptr, const int32_t* bcol,
+                            const int32_t* bsrow, int32_t* bsym) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n_blocks) return;
+  const int I = bsrow[s], J = bcol[s];
+  int m = (int)s;
+  if (J < I) {
+    int lo = brow_ptr[J], hi = brow_ptr[J + 1];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (bcol[mid] < I)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    m = lo;
+  }
+  bsym[2 * s] = J;
+  bsym[2 * s + 1] = m;
+}
+
 // ---- exclusive scan of int32 counts (n entries) into out[0..n], out[n] = total -------------
 
 constexpr int SCAN_TPB = 256;
@@ -335,6 +359,10 @@ hipError_t build_pattern(const Mesh& m, Pattern& pat, unsigned* d_err, hipStream
   SSO_TRY(hipGetLastError());
   int32_t last = (int32_t)pat.n_bcoo;
   SSO_TRY(hipMemcpyAsync(pat.bseg + nblk, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SSO_TRY(dev_alloc(&pat.bsym, 2 * (int64_t)nblk, s));
+  hipLaunchKernelGGL(k_sym_slots, dim3(blocks_for(nblk)), dim3(TPB), 0, s, (int64_t)nblk,
+                     pat.brow_ptr, pat.bcol, pat.bsrow, pat.bsym);
+  SSO_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_max_row, dim3(1), dim3(256), 0, s, n, pat.brow_ptr, tmp);
   SSO_TRY(hipGetLastError());
   int32_t max_row = 0;
@@ -366,7 +394,7 @@ hipError_t build_scalar_view(const Mesh& m, const Pattern& pat, int32_t* row_ptr
 void free_pattern(Pattern& pat, hipStream_t s) {
   for (void* q : {(void*)pat.brow_ptr, (void*)pat.bcol, (void*)pat.bseg, (void*)pat.bperm,
                   (void*)pat.bslot, (void*)pat.bdiag, (void*)pat.estart, (void*)pat.bsrow,
-                  (void*)pat.bcol_ell})
+                  (void*)pat.bcol_ell, (void*)pat.bsym})
     dev_release(q, &pat.mem, s);
   arena_free(pat.mem, s);
   pat = Pattern();

@@ -462,6 +462,110 @@ __device__ inline void row_product2(int rb, int re, const int32_t* __restrict__ 
   ap = sp;
 }
 
+// row_product2 reading only K's upper triangle (K is assembled bitwise symmetric): block s of
+// row I with column J < I equals the transpose of block (J, I), so its entries (a, b) and
+// (a, b + 1) are that block's (b, a) and (b + 1, a).  Each slot's (column, value slot) pair
+// comes in one 8-byte load; the value slot is below s exactly for these blocks.  The values,
+// the products and their order are row_product2's, so the sums are bitwise the same.  The
+// mirrors are upper blocks of rows up to a grid line earlier, which the same XCD reads for
+// those rows' own products at about the same time (xcd_tile): on the 300 x 300 shell the L2s
+// fetch 182 MB per launch against 249 MB for the full K.  An upper block is one 16-byte load
+// per lane, a mirror two 8-byte loads (stride 6); the choice is a branch per block, uniform
+// within a wave away from the mesh's edges.  Measured per iteration on the 300 x 300 shell
+// against 65.8 us for the full K: 57.1 us; two 8-byte loads for every block without the branch
+// 62.0; a 16- and an 8-byte load 61.0-61.9; a scheduling barrier between a step's loads and its
+// products 61.1; a register budget of 6 waves per SIMD 68.7.
+template <class T>
+__device__ inline void row_product2_sym(int rb, int re, const int32_t* __restrict__ bsym_,
+                                        const T* __restrict__ K_, const T* __restrict__ z_,
+                                        const T* __restrict__ p_, int a, int b, T& az, T& ap) {
+  using V = typename Vec2<T>::type;
+  const gptr<int32_t> bsym = as_global(bsym_);
+  const gptr<T> K = as_global(K_);
+  const gptr<T> z = as_global(z_);
+  const gptr<T> p = as_global(p_);
+  const int off_u = 6 * a + b, off_l = 6 * b + a;
+  auto slot = [&](int s) { return load2<int2>(bsym + 2 * (int64_t)s); };   // (J, value slot)
+  auto kval = [&](int s, int m) {
+    V v;
+    if (m < s) {
+      const gptr<T> q = K + 36 * (int64_t)m + off_l;
+      v.x = q[0];
+      v.y = q[6];
+    } else {
+      v = load2<V>(K + 36 * (int64_t)m + off_u);
+    }
+    return v;
+  };
+  T sz = 0, sp = 0;
+  int s = rb;
+  if (re - rb >= 2) {
+    int2 c0 = slot(s), c1 = slot(s + 1);
+    for (;;) {
+      // the next step's pairs (past the last pair, the row's last two), then this step's values
+      // and gathers
+      const int sn = s + 2;
+      const int sc = sn + 2 <= re ? sn : re - 2;
+      const int2 c0n = slot(sc), c1n = slot(sc + 1);
+      const V k0 = kval(s, c0.y);
+      const V k1 = kval(s + 1, c1.y);
+      const V z0 = load2<V>(z + 6 * (int64_t)c0.x + b);
+      const V z1 = load2<V>(z + 6 * (int64_t)c1.x + b);
+      const V p0 = load2<V>(p + 6 * (int64_t)c0.x + b);
+      const V p1 = load2<V>(p + 6 * (int64_t)c1.x + b);
+      sz += k0.x * z0.x + k0.y * z0.y;
+      sp += k0.x * p0.x + k0.y * p0.y;
+      sz += k1.x * z1.x + k1.y * z1.y;
+      sp += k1.x * p1.x + k1.y * p1.y;
+      s = sn;
+      if (s + 2 > re) {
+        if (s < re) {   // one block left, slot re - 1: its pair is c1n
+          const V kv = kval(s, c1n.y);
+          const V zv = load2<V>(z + 6 * (int64_t)c1n.x + b);
+          const V pv = load2<V>(p + 6 * (int64_t)c1n.x + b);
+          sz += kv.x * zv.x + kv.y * zv.y;
+          sp += kv.x * pv.x + kv.y * pv.y;
+        }
+        break;
+      }
+      c0 = c0n;
+      c1 = c1n;
+    }
+  } else if (s < re) {
+    const int2 c = slot(s);
+    const V kv = kval(s, c.y);
+    const V zv = load2<V>(z + 6 * (int64_t)c.x + b);
+    const V pv = load2<V>(p + 6 * (int64_t)c.x + b);
+    sz += kv.x * zv.x + kv.y * zv.y;
+    sp += kv.x * pv.x + kv.y * pv.y;
+  }
+  az = sz;
+  ap = sp;
+}
+
+// The tile (group of ROWS_PER_WG block rows) that workgroup lb of ng covers in each pass, as an
+// offset into the pass's ng tiles.  Workgroups are dealt to the 8 XCDs in turn (lb mod 8), so
+// this gives each XCD a contiguous range of the pass's tiles: the rows whose upper blocks a
+// row's lower blocks mirror (a grid line back) are then mostly read by the same XCD.  A
+// bijection of [0, ng); the per-workgroup partial sums follow the tiles a workgroup covers, so
+// every launch of a problem (alone or in a multi-problem table) sums in the same order.
+__device__ __forceinline__ int xcd_tile(int lb, int ng) {
+  const int x = lb & 7, q = ng >> 3, r = ng & 7;
+  return x * q + (x < r ? x : r) + (lb >> 3);
+}
+
+// Single FP64 solves whose K takes at least this many bytes read only its upper triangle
+// (k_spmv_dir_sym).  Measured per iteration, full K against upper triangle: 300 x 300 shell
+// (234 MB) 65.8 against 57.1 us; 120 x 120 shell (38 MB, resident in the 256 MB Infinity
+// Cache, where the bytes saved cost nothing) 18.7 against 19.8 us.
+constexpr double SYM_PRODUCT_MIN_K_BYTES = 128.0 * 1024 * 1024;
+
+template <class T>
+static bool sym_products(const Pattern& pat) {
+  return pcg_sym_products(pat.n_blocks, sizeof(T) != 8);
+}
+
+
 // FP32 standard recurrences keep z and p interleaved: buffer k holds (z, p) pairs, (z_j,
 // p_{j-1}) in buffer j & 1, so that one 16-byte gather per lane brings both vectors' entries of
 // a block (two entries each), where separate arrays need two 8-byte gathers.
@@ -521,6 +625,7 @@ __device__ inline void row_product2_zp(int rb, int re, const int32_t* __restrict
   az = sz;
   ap = sp;
 }
+
 
 // x = 0, r = b, z = Dinv b, p_{-1} = 0; partials of r^T z, r^T r; reset the state record.
 template <class T>
@@ -610,17 +715,20 @@ __device__ __forceinline__ StdState std_state(const PcgState* __restrict__ st) {
 // are issued before the previous kernel's partials are finished (rz_j, rr_j -> convergence
 // test, beta_j), so the reduction overlaps the loads.  The descriptor is copied whole and the
 // first pass's row pointers are loaded with the state (neither needs the other), so a
-// workgroup's first products start two round trips after its descriptor.
-template <class T, int NB = 2>
-__global__ void __launch_bounds__(MAX_TPB)
-k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+// workgroup's first products start two round trips after its descriptor.  SYM: the products
+// read K's upper triangle only (row_product2_sym; bitwise the same sums).
+template <class T, int NB, bool SYM>
+__device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
+                                         const int32_t* __restrict__ wg_prob) {
+  static_assert(!SYM || (NB == 2 && !zp_pairs<T>()), "symmetric products: FP64, two blocks a step");
   const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
   const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
   PcgState* st = d.st;
   const int n_nodes = d.n_nodes;
   const SpLane L = sp_lane();
   const int wave = threadIdx.x >> 6;
-  const int I0 = lb * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
+  const int t0 = xcd_tile(lb, ng);
+  const int I0 = t0 * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
   const int I0c = (L.ok && I0 < n_nodes) ? I0 : 0;
   const int rb0 = d.brow_ptr[I0c], re0 = d.brow_ptr[I0c + 1];
   const StdState S = std_state(st);
@@ -636,12 +744,12 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   T* __restrict__ pnew = (j & 1) ? d.p[0] : d.p[1];
   T* __restrict__ Ap = d.Ap;
   T beta = 0, my = 0;
-  for (int gi = lb; gi * ROWS_PER_WG < n_nodes; gi += ng) {
+  for (int gi = t0; gi * ROWS_PER_WG < n_nodes; gi += ng) {
     const int I = gi * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
     const bool ok = L.ok && I < n_nodes;
     T az = 0, ap = 0, zI = 0, pI = 0;
     int rb = rb0, re = re0;
-    if (gi != lb && ok) {
+    if (gi != t0 && ok) {
       rb = d.brow_ptr[I];
       re = d.brow_ptr[I + 1];
     }
@@ -653,7 +761,9 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
         pI = pold[2 * (6 * (int64_t)I + L.a) + 1];
       }
     } else {
-      if constexpr (NB == 2)
+      if constexpr (SYM)
+        row_product2_sym<T>(rb, re, d.bsym, K, z, pold, L.a, L.b, az, ap);
+      else if constexpr (NB == 2)
         row_product2<T>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
       else
         row_product_nb<T, NB>(rb, re, d.bcol, K, z, pold, L.a, L.b, az, ap);
@@ -662,7 +772,7 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
         pI = pold[6 * (int64_t)I + L.a];
       }
     }
-    if (gi == lb) {
+    if (gi == t0) {
       double tot[2];
       finish_partials<2>(d.pb, ng, tot);
       const double rz = tot[0], rr = tot[1];
@@ -708,6 +818,19 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   T v[1] = {my};
   block_sum<1, T>(v);
   write_partials<1, T>(v, d.pa, lb, ng);
+}
+
+template <class T, int NB = 2>
+__global__ void __launch_bounds__(MAX_TPB)
+k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  spmv_dir<T, NB, false>(D, wg_prob);
+}
+
+// The upper-triangle form (66 VGPRs, 7 waves per SIMD).
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_spmv_dir_sym(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  spmv_dir<T, 2, true>(D, wg_prob);
 }
 
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
@@ -2308,6 +2431,7 @@ static hipError_t pcg_start(const Mesh& m, const Pattern& pat, const T* K, const
   PcgDesc<T> hd{};
   hd.brow_ptr = pat.brow_ptr;
   hd.bcol = pat.bcol;
+  hd.bsym = pat.bsym;
   hd.K = K;
   hd.Dinv = Dinv;
   hd.b = b;
@@ -2323,6 +2447,7 @@ static hipError_t pcg_start(const Mesh& m, const Pattern& pat, const T* K, const
   hd.n_nodes = m.n_nodes;
   hd.n_wg = w.n_wg;
   hd.wg_base = 0;
+  hd.n_blocks = pat.n_blocks;
   hd.stream_stores = 36.0 * sizeof(T) * (double)pat.n_blocks >= STREAM_STORE_K_BYTES ? 1 : 0;
   if (out) *out = hd;
   PcgDesc<T>* dd = reinterpret_cast<PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
@@ -2344,11 +2469,19 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
   if (e != hipSuccess) return e;
   const int nwg = w.n_wg;
   const int nwg_upd = update_wg(nwg, m.n_nodes);
+  const bool sym = sym_products<T>(pat);
   const PcgDesc<T>* dd =
       reinterpret_cast<const PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
-    hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    if constexpr (sizeof(T) == 8) {
+      if (sym)
+        hipLaunchKernelGGL(k_spmv_dir_sym<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+      else
+        hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    } else {
+      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+    }
     hipLaunchKernelGGL(k_update<T>, dim3(nwg_upd), dim3(MAX_TPB), 0, s, dd, nullptr);
     if (e1) (void)hipEventRecord(*e1, s);
   };
@@ -2553,6 +2686,14 @@ static void launch_standard(const LaunchTable<PcgDesc<T>>& t, const LaunchTable<
                             hipStream_t s) {
   if (t.total == 0) return;
   const PcgDesc<T>* d = reinterpret_cast<const PcgDesc<T>*>(t.d_desc);
+  if constexpr (sizeof(T) == 8) {
+    if (t.sym) {
+      hipLaunchKernelGGL(k_spmv_dir_sym<T>, dim3(t.total), dim3(MAX_TPB), 0, s, d, t.d_wg);
+      hipLaunchKernelGGL(k_update<T>, dim3(u.total), dim3(MAX_TPB), 0, s,
+                         reinterpret_cast<const PcgDesc<T>*>(u.d_desc), u.d_wg);
+      return;
+    }
+  }
   if (t.total > BATCH_NB_MIN_WG)
     hipLaunchKernelGGL((k_spmv_dir<T, BATCH_NB>), dim3(t.total), dim3(MAX_TPB), 0, s, d,
                        t.d_wg);
@@ -2650,6 +2791,14 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
   if ((e = table_upload(bw.standard, L.standard.data(), (int)L.standard.size(), s)) !=
       hipSuccess)
     return e;
+#ifndef SSO_BATCH_SYM
+#define SSO_BATCH_SYM 0
+#endif
+  {
+    double kb = 0.0;
+    for (const auto& d : L.standard) kb += 36.0 * 8.0 * (double)d.n_blocks;
+    bw.standard.sym = SSO_BATCH_SYM && kb >= SYM_PRODUCT_MIN_K_BYTES;
+  }
   if ((e = table_upload(bw.standard_upd, L.standard.data(), (int)L.standard.size(), s, true)) !=
       hipSuccess)
     return e;
@@ -3135,16 +3284,24 @@ double fused_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) 
   return (36.0 * v + 4.0) * n_blocks + 4.0 * (n_nodes + 1) + (3 + 2 + 3.5 + 5) * v * n_dof;
 }
 
-double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed) {
-  const double fb = mixed ? 4.0 : 8.0;
-  return 36.0 * fb * n_blocks + 4.0 * n_blocks + 4.0 * (n_nodes + 1) + 4.0 * fb * 6.0 * n_nodes;
+bool pcg_sym_products(int64_t n_blocks, bool mixed) {
+  return !mixed && 36.0 * 8.0 * (double)n_blocks >= SYM_PRODUCT_MIN_K_BYTES;
 }
 
-double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed) {
+double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed, bool sym) {
+  const double fb = mixed ? 4.0 : 8.0;
+  const double tail = 4.0 * (n_nodes + 1) + 4.0 * fb * 6.0 * n_nodes;
+  // upper triangle: the diagonal and half the off-diagonal blocks, (column, value slot) pairs
+  if (sym) return 36.0 * fb * 0.5 * (double)(n_blocks + n_nodes) + 8.0 * n_blocks + tail;
+  return 36.0 * fb * n_blocks + 4.0 * n_blocks + tail;
+}
+
+double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed, bool sym) {
   const double fb = mixed ? 4.0 : 8.0;
   const double n_dof = 6.0 * (double)n_nodes;
-  // spmv: K values + block columns + row pointers; z, p_old read; p_new, Ap written
-  double spmv = spmv_bytes_per_launch(n_nodes, n_blocks, mixed);
+  // spmv: K values (the upper triangle: sym) + block columns + row pointers; z, p_old read;
+  // p_new, Ap written
+  double spmv = spmv_bytes_per_launch(n_nodes, n_blocks, mixed, sym);
   // update: x, p, Ap, r read, Dinv (21 per node, 3.5 per DOF); x, r, z written
   double upd = 4.0 * fb * n_dof + 3.5 * fb * n_dof + 3.0 * fb * n_dof;
   return spmv + upd;

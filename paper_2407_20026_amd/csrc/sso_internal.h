@@ -44,6 +44,7 @@ template <class T>
 struct PcgDesc {
   const int32_t* brow_ptr;
   const int32_t* bcol;
+  const int32_t* bsym;      // (column, value slot) of each block slot
   const T* K;
   const T* Dinv;
   const T* b;
@@ -57,6 +58,7 @@ struct PcgDesc {
   PcgState* st;
   int n_nodes, n_wg, wg_base;
   int stream_stores;   // 1: the vectors an iteration writes go out as streaming stores
+  int64_t n_blocks;    // blocks of K
 };
 
 // One problem of a single-reduction PCG launch (one kernel and one reduction per iteration).
@@ -106,6 +108,9 @@ struct Pattern {
   int32_t* bdiag = nullptr;     // [n_nodes] slot of the diagonal block of each row
   int32_t* bsrow = nullptr;     // [n_blocks] block row of each slot
   int32_t* estart = nullptr;    // [n_nodes + 1] first sorted position of each block row
+  // [2 n_blocks] per slot s of block (I, J): J, then the slot whose values the block takes
+  // in the symmetric products (s itself for J >= I; the slot of (J, I) for J < I)
+  int32_t* bsym = nullptr;
   // Padded layout of the block rows (every row ell_w slots; 0 = not built: a row has more
   // than 12 blocks): bcol_ell[I * ell_w + u] = column of block u of row I for u below the
   // row's block count, I itself (with a zero block) beyond.
@@ -244,10 +249,11 @@ struct HostPattern {
   int64_t n_blocks = 0, n_bcoo = 0;
   const int32_t *brow_ptr = nullptr, *bcol = nullptr, *bseg = nullptr, *bperm = nullptr,
                 *bslot = nullptr, *bdiag = nullptr, *bsrow = nullptr, *estart = nullptr,
-                *bcol_ell = nullptr, *beam_nodes = nullptr, *quad_nodes = nullptr;
+                *bcol_ell = nullptr, *beam_nodes = nullptr, *quad_nodes = nullptr,
+                *bsym = nullptr;
 };
 // validate.cpp: 0 when every invariant of the pattern holds, else the number of the first
-// failed check (1-8) with a message in msg.
+// failed check (1-9) with a message in msg.
 int check_pattern(const HostPattern& h, char* msg, size_t len);
 
 // ---- launch helpers (each defined in its own translation unit) ----------------------------
@@ -402,6 +408,7 @@ struct LaunchTable {
   std::vector<int32_t> h_wg;
   int total = 0;          // workgroups of one launch
   bool lean = false;      // fused tables: every problem fits the lean multi-problem kernel
+  bool sym = false;       // standard FP64 tables: the products read K's upper triangle
 };
 struct BatchWork {
   LaunchTable<PcgDesc<double>> standard;
@@ -458,8 +465,10 @@ hipError_t launch_dot(const double* a, const double* b, int64_t n, PcgWork& w, d
 hipError_t launch_true_residual(const Mesh& m, const Pattern& pat, const double* K,
                                 const double* x, const double* b, double* r, PcgWork& w,
                                 double* d_out, hipStream_t s);
-double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed);
-double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed);
+// Single standard FP64 solves of a K of at least 128 MiB read only its upper triangle.
+bool pcg_sym_products(int64_t n_blocks, bool mixed);
+double pcg_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed, bool sym);
+double spmv_bytes_per_launch(int64_t n_nodes, int64_t n_blocks, bool mixed, bool sym);
 double fused_bytes_per_iteration(int64_t n_nodes, int64_t n_blocks, bool mixed);
 
 }  // namespace sso

@@ -13,7 +13,10 @@
 //   6 every contribution sits in the slot of its own (row node, column node), ids ascending
 //     within a slot (the stable order of the element-major contribution list);
 //   7 estart: each row's first sorted position;
-//   8 padded rows (ell_w > 0): each row's columns in order, then the row's own node.
+//   8 padded rows (ell_w > 0): each row's columns in order, then the row's own node;
+//   9 bsym: each slot's column, then its value slot: the slot of (J, I) for a block (I, J) with
+//     J < I (the pattern is structurally symmetric: an element couples its nodes both ways),
+//     the slot itself for J >= I.
 #include <cstdio>
 #include <vector>
 
@@ -86,6 +89,13 @@ int check_pattern(const HostPattern& h, char* msg, size_t len) {
           return fail(msg, len, 8, "padded row", (int64_t)I * h.ell_w + u);
       }
     }
+  }
+  for (int64_t s = 0; s < nb; ++s) {
+    const int32_t J = h.bsym[2 * s], m = h.bsym[2 * s + 1];
+    const bool ok = J == h.bcol[s] &&
+                    (J >= h.bsrow[s] ? m == s
+                                     : m >= 0 && m < nb && h.bsrow[m] == J && h.bcol[m] == h.bsrow[s]);
+    if (!ok) return fail(msg, len, 9, "bsym", s);
   }
   return 0;
 }

@@ -117,7 +117,8 @@ static void abi_argument_paths() {
 // checker's own tests): slot (I, J) holds the ids of its block contributions in ascending order.
 struct Built {
   int n_nodes, n_beams, n_quads;
-  std::vector<int32_t> beams, quads, brow, bcol, bseg, bperm, bslot, bdiag, bsrow, est, ell;
+  std::vector<int32_t> beams, quads, brow, bcol, bseg, bperm, bslot, bdiag, bsrow, est, ell,
+      sym;
   int ell_w = 0;
   sso::HostPattern view() const {
     sso::HostPattern h;
@@ -138,6 +139,7 @@ struct Built {
     h.bcol_ell = ell.data();
     h.beam_nodes = beams.data();
     h.quad_nodes = quads.data();
+    h.bsym = sym.data();
     return h;
   }
 };
@@ -184,6 +186,12 @@ static Built build(int n_nodes, const std::vector<int32_t>& beams,
     if (cnt > max_row) max_row = cnt;
   }
   for (int I = 0; I <= n_nodes; ++I) b.est[I] = I < n_nodes ? b.bseg[b.brow[I]] : id;
+  std::map<std::pair<int, int>, int32_t> slot_of;
+  for (size_t s = 0; s < b.bcol.size(); ++s) slot_of[{b.bsrow[s], b.bcol[s]}] = (int32_t)s;
+  for (size_t s = 0; s < b.bcol.size(); ++s) {
+    b.sym.push_back(b.bcol[s]);
+    b.sym.push_back(b.bcol[s] < b.bsrow[s] ? slot_of.at({b.bcol[s], b.bsrow[s]}) : (int32_t)s);
+  }
   b.ell_w = sso::ell_width(max_row);
   b.ell.assign((size_t)n_nodes * (b.ell_w > 0 ? b.ell_w : 0), 0);
   for (int I = 0; I < n_nodes && b.ell_w > 0; ++I)
@@ -258,6 +266,28 @@ static void pattern_checks() {
     Built c = b;
     c.ell[(size_t)16 * c.ell_w + c.ell_w - 1] = 3;             // padding of the isolated node
     CHECK(check(c) == 8);
+  }
+  {
+    Built c = b;
+    const int32_t s = c.brow[5];                               // (5, 0): left of the diagonal
+    c.sym[2 * s + 1] = c.sym[2 * s + 3];
+    CHECK(check(c) == 9);
+  }
+  {
+    Built c = b;
+    const int32_t s = c.brow[5] + 5;                           // right of the diagonal: itself
+    c.sym[2 * s + 1] = c.sym[2 * c.brow[5] + 1];
+    CHECK(check(c) == 9);
+  }
+  {
+    Built c = b;
+    c.sym[2 * c.bdiag[16] + 1] = c.bdiag[15];                 // a diagonal names another row's
+    CHECK(check(c) == 9);
+  }
+  {
+    Built c = b;
+    c.sym[2 * c.brow[9]] = c.bcol[c.brow[9] + 1];              // a wrong column
+    CHECK(check(c) == 9);
   }
 }
 
