@@ -157,7 +157,9 @@ typedef struct {
                                  triangle, each block below the diagonal as the transpose of
                                  its mirror (single FP64 solves of a K of 128 MiB or more; the
                                  same sums, bitwise, as reading all of K); spmv_bytes counts
-                                 that triangle                                               */
+                                 that triangle.  Multi-problem launches do the same when their
+                                 problems' K take 128 MiB together; sso_solve_end reports 0
+                                 and counts all of K for them                                */
 } sso_stats;
 
 typedef struct sso_problem sso_problem;

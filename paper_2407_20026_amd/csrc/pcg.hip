@@ -554,10 +554,13 @@ __device__ __forceinline__ int xcd_tile(int lb, int ng) {
   return x * q + (x < r ? x : r) + (lb >> 3);
 }
 
-// Single FP64 solves whose K takes at least this many bytes read only its upper triangle
-// (k_spmv_dir_sym).  Measured per iteration, full K against upper triangle: 300 x 300 shell
-// (234 MB) 65.8 against 57.1 us; 120 x 120 shell (38 MB, resident in the 256 MB Infinity
-// Cache, where the bytes saved cost nothing) 18.7 against 19.8 us.
+// FP64 products read only K's upper triangle (k_spmv_dir_sym) for a single solve whose K takes at
+// least this many bytes, and in a multi-problem launch whose problems' K take that many together
+// (the same sums either way).  Measured per iteration, full K against upper triangle: 300 x 300
+// shell (234 MB) 65.8 against 57.1 us; 120 x 120 shell (38 MB, resident in the 256 MB Infinity
+// Cache, where the bytes saved buy nothing) 18.7 against 19.8 us.  Launches of 24 / 32 / 48
+// 60 x 60 shells: 2.80 / 2.99 / 3.20 against 2.97 / 3.29 / 3.24 us per problem-iteration (the
+// full-K side with three blocks a step), the served stream 120.0 against 117.3 solves/s.
 constexpr double SYM_PRODUCT_MIN_K_BYTES = 128.0 * 1024 * 1024;
 
 template <class T>
@@ -2791,13 +2794,11 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
   if ((e = table_upload(bw.standard, L.standard.data(), (int)L.standard.size(), s)) !=
       hipSuccess)
     return e;
-#ifndef SSO_BATCH_SYM
-#define SSO_BATCH_SYM 0
-#endif
   {
+    // the upper-triangle products once the problems' K together outgrow the Infinity Cache
     double kb = 0.0;
     for (const auto& d : L.standard) kb += 36.0 * 8.0 * (double)d.n_blocks;
-    bw.standard.sym = SSO_BATCH_SYM && kb >= SYM_PRODUCT_MIN_K_BYTES;
+    bw.standard.sym = kb >= SYM_PRODUCT_MIN_K_BYTES;
   }
   if ((e = table_upload(bw.standard_upd, L.standard.data(), (int)L.standard.size(), s, true)) !=
       hipSuccess)
