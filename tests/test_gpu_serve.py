@@ -142,6 +142,39 @@ def test_batch_mixing_both_recurrences_matches_solves_alone():
         assert np.array_equal(u, ua.cpu().numpy())
 
 
+def test_batch_reading_the_upper_triangle_matches_full_products_alone():
+    """Four 120 x 120 shells (37.5 MB of K each) iterate in one multi-problem launch, whose K
+    (150 MB together) is past the 128 MiB at which the products read only K's upper triangle;
+    alone, each reads all of K.  K is assembled bitwise symmetric and the products sum the same
+    values in the same order, so each u is bitwise its solve alone."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] batch of upper-triangle products against full products alone", flush=True)
+    meshes = [meshgen.shell(120, seed=s) for s in (41, 42, 43, 44)]
+    opts = sso.Options(rtol=1e-8, solver=sso.SOLVER_STANDARD)
+    stream = torch.cuda.Stream()
+    batch = sso.Batch(stream)
+    probs = [sso.Problem(m, opts, stream=stream) for m in meshes]
+    try:
+        for p in probs:
+            p.solve_begin()
+        done = [False] * len(probs)
+        for _ in range(1000):
+            done = batch.iterate(probs, 64)
+            if all(done):
+                break
+        assert all(done)
+        got = [p.solve_end()[0].cpu().numpy() for p in probs]
+    finally:
+        for p in probs:
+            p.close()
+        batch.close()
+    for m, u in zip(meshes, got):
+        with sso.Problem(m, opts) as q:
+            ua, st = q.solve()
+        assert st["sym_products"] == 0   # alone: 37.5 MB of K, the full product
+        assert np.array_equal(u, ua.cpu().numpy())
+
+
 @pytest.mark.parametrize("solver", ["standard", "fused"])
 def test_batched_mixed_precision_matches_solves_alone(solver):
     """Mixed precision in multi-problem launches (FP32 inner iterations, FP64 refinement between
