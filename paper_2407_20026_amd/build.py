@@ -18,9 +18,14 @@ SOURCES = ["api.hip", "pattern.hip", "elements.hip", "assemble.hip", "pcg.hip", 
            "ceiling.hip", "validate.cpp"]
 ARCH = os.environ.get("HIPSSO_ARCH", "gfx950")
 
+# Kernel arguments preloaded into SGPRs (gfx950), up to 16 dwords: a kernel's first loads need
+# no round trip for its descriptor pointers.  Measured A/B (two alternating runs each): the
+# 120 x 120 shell's iteration 18.1 against 18.65 us, the 300 x 300 shell's 56.6 against 57.0 us,
+# the served stream 122.1-122.4 against 121.0-121.3 solves/s; the 60 x 60 shell unchanged.
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-function",
 ]
