@@ -734,6 +734,21 @@ __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
   const int I0 = t0 * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
   const int I0c = (L.ok && I0 < n_nodes) ? I0 : 0;
   const int rb0 = d.brow_ptr[I0c], re0 = d.brow_ptr[I0c + 1];
+#ifndef SSO_DIR_EARLY
+#define SSO_DIR_EARLY 0
+#endif
+#if SSO_DIR_EARLY
+  // the update kernel's partials of r^T z and r^T r, issued with the state (at most three per
+  // thread and sum), summed after the first pass's products in finish_partials' order
+  double pb6[2][3];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int k = (int)threadIdx.x + u * MAX_TPB;
+      pb6[c][u] = d.pb[c * ng + (k < ng ? k : 0)];
+    }
+#endif
   const StdState S = std_state(st);
   // the first group in registers before the done test (an empty asm that takes them), so that
   // the compiler cannot sink these loads below it, one round trip after another
@@ -777,7 +792,18 @@ __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
     }
     if (gi == t0) {
       double tot[2];
+#if SSO_DIR_EARLY
+      {
+        const int k0 = (int)threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          tot[c] = ((0.0 + (k0 < ng ? pb6[c][0] : 0.0)) + (k0 + MAX_TPB < ng ? pb6[c][1] : 0.0)) +
+                   (k0 + 2 * MAX_TPB < ng ? pb6[c][2] : 0.0);
+        block_sum<2, double>(tot);
+      }
+#else
       finish_partials<2>(d.pb, ng, tot);
+#endif
       const double rz = tot[0], rr = tot[1];
       const double ff = (j == 0) ? rr : S.ff;
       const double beta_d = (j == 0) ? 0.0 : rz / ((j & 1) ? S.rz0 : S.rz1);
@@ -838,8 +864,8 @@ k_spmv_dir_sym(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_
 
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
 // partials of (rz_{j+1}, rr_{j+1}); the state's next iteration index becomes j + 1.  The first
-// pass's operands are loaded before the reduction, those that need no state (x, Ap, r) with the
-// state itself.
+// pass's operands (x, Ap, r, p of both parities, the inverses) and the product kernel's partials
+// are loaded with the state itself, so the reduction and the updates wait for one round trip.
 template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
@@ -863,6 +889,20 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   // the first pass's inverses, state-free; a workgroup with no node group of its own (the
   // launch has one workgroup per 18 block rows, a group is 64 nodes) reads group 0 and drops it
   const DinvChunk<T> dc0 = dinv_load(d.Dinv, lb * VEC_NODES < n_nodes ? lb : 0);
+  // Issued with the state, which neither needs: the product kernel's partials of p^T A p (at
+  // most three per thread: ng <= PCG_MAX_WG <= 3 MAX_TPB), summed below in finish_partials'
+  // order, and the first pass's p from both parity buffers (the state names which is p_j).
+  // Waiting for the state first and then for these cost a second round trip: on the 300 x 300
+  // shell 55.8 against 56.6 us per iteration (two alternating runs each).
+  static_assert(3 * MAX_TPB >= PCG_MAX_WG, "three partials per thread");
+  double pa3[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int k = (int)threadIdx.x + u * MAX_TPB;
+    pa3[u] = d.pa[k < ng ? k : 0];
+  }
+  const int64_t qp0 = zp_pairs<T>() ? 2 * q0 + 1 : q0;
+  const T p0e = d.p[0][qp0], p1e = d.p[1][qp0];
   const StdState S = std_state(st);
   asm volatile("" ::"v"(x0), "v"(a0), "v"(r0), "s"(S.rz0), "s"(S.rz1), "s"(S.jc));
   if (S.done) return;
@@ -879,12 +919,19 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
         xv = x[q];
         av = Ap[q];
         rv = r[q];
+        pv = zp_pairs<T>() ? p[2 * q + 1] : p[q];
+      } else {
+        pv = (j & 1) ? p0e : p1e;
       }
-      pv = zp_pairs<T>() ? p[2 * q + 1] : p[q];
     }
     if (gi == lb) {
       double tot[1];
-      finish_partials<1>(d.pa, ng, tot);
+      {
+        const int k0 = (int)threadIdx.x;
+        tot[0] = ((0.0 + (k0 < ng ? pa3[0] : 0.0)) + (k0 + MAX_TPB < ng ? pa3[1] : 0.0)) +
+                 (k0 + 2 * MAX_TPB < ng ? pa3[2] : 0.0);
+        block_sum<1, double>(tot);
+      }
       const double pAp = tot[0];
       const double alpha_d = ((j & 1) ? S.rz1 : S.rz0) / pAp;
       if (!(pAp > 0.0) || !std::isfinite(alpha_d)) {
