@@ -719,8 +719,13 @@ __device__ __forceinline__ StdState std_state(const PcgState* __restrict__ st) {
 // test, beta_j), so the reduction overlaps the loads.  The descriptor is copied whole and the
 // first pass's row pointers are loaded with the state (neither needs the other), so a
 // workgroup's first products start two round trips after its descriptor.  SYM: the products
-// read K's upper triangle only (row_product2_sym; bitwise the same sums).
-template <class T, int NB, bool SYM>
+// read K's upper triangle only (row_product2_sym; bitwise the same sums).  EARLY: the update
+// kernel's partials are issued with the state instead of after the first pass's products, so
+// that finishing them costs no round trip of its own; the sums are the same.  Measured on the
+// 300 x 300 shell (upper triangle, single solve): 54.3 against 55.4 us per iteration; in
+// multi-problem launches, whose workgroups make one or two passes and lose a wave per SIMD to
+// the registers on the two-block form, 2 % slower (the stream 0.8 %).
+template <class T, int NB, bool SYM, bool EARLY>
 __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
                                          const int32_t* __restrict__ wg_prob) {
   static_assert(!SYM || (NB == 2 && !zp_pairs<T>()), "symmetric products: FP64, two blocks a step");
@@ -734,21 +739,18 @@ __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
   const int I0 = t0 * ROWS_PER_WG + wave * ROWS_PER_WAVE + L.g;
   const int I0c = (L.ok && I0 < n_nodes) ? I0 : 0;
   const int rb0 = d.brow_ptr[I0c], re0 = d.brow_ptr[I0c + 1];
-#ifndef SSO_DIR_EARLY
-#define SSO_DIR_EARLY 0
-#endif
-#if SSO_DIR_EARLY
-  // the update kernel's partials of r^T z and r^T r, issued with the state (at most three per
-  // thread and sum), summed after the first pass's products in finish_partials' order
-  double pb6[2][3];
+  // EARLY: the update kernel's partials of r^T z and r^T r, issued with the state (at most
+  // three per thread and sum), summed after the first pass's products in finish_partials' order
+  double pb6[2][3] = {};
+  if constexpr (EARLY) {
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int k = (int)threadIdx.x + u * MAX_TPB;
-      pb6[c][u] = d.pb[c * ng + (k < ng ? k : 0)];
-    }
-#endif
+      for (int u = 0; u < 3; ++u) {
+        const int k = (int)threadIdx.x + u * MAX_TPB;
+        pb6[c][u] = d.pb[c * ng + (k < ng ? k : 0)];
+      }
+  }
   const StdState S = std_state(st);
   // the first group in registers before the done test (an empty asm that takes them), so that
   // the compiler cannot sink these loads below it, one round trip after another
@@ -792,18 +794,16 @@ __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
     }
     if (gi == t0) {
       double tot[2];
-#if SSO_DIR_EARLY
-      {
+      if constexpr (EARLY) {
         const int k0 = (int)threadIdx.x;
 #pragma unroll
         for (int c = 0; c < 2; ++c)
           tot[c] = ((0.0 + (k0 < ng ? pb6[c][0] : 0.0)) + (k0 + MAX_TPB < ng ? pb6[c][1] : 0.0)) +
                    (k0 + 2 * MAX_TPB < ng ? pb6[c][2] : 0.0);
         block_sum<2, double>(tot);
+      } else {
+        finish_partials<2>(d.pb, ng, tot);
       }
-#else
-      finish_partials<2>(d.pb, ng, tot);
-#endif
       const double rz = tot[0], rr = tot[1];
       const double ff = (j == 0) ? rr : S.ff;
       const double beta_d = (j == 0) ? 0.0 : rz / ((j & 1) ? S.rz0 : S.rz1);
@@ -852,14 +852,14 @@ __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
 template <class T, int NB = 2>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  spmv_dir<T, NB, false>(D, wg_prob);
+  spmv_dir<T, NB, false, false>(D, wg_prob);
 }
 
-// The upper-triangle form (66 VGPRs, 7 waves per SIMD).
-template <class T>
+// The upper-triangle form (66 VGPRs, 7 waves per SIMD; 70 with EARLY, for single solves).
+template <class T, bool EARLY = false>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir_sym(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  spmv_dir<T, 2, true>(D, wg_prob);
+  spmv_dir<T, 2, true, EARLY>(D, wg_prob);
 }
 
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
@@ -2526,7 +2526,8 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
     if (e0) (void)hipEventRecord(*e0, s);
     if constexpr (sizeof(T) == 8) {
       if (sym)
-        hipLaunchKernelGGL(k_spmv_dir_sym<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
+        hipLaunchKernelGGL((k_spmv_dir_sym<T, true>), dim3(nwg), dim3(MAX_TPB), 0, s, dd,
+                           nullptr);
       else
         hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
     } else {
