@@ -469,7 +469,7 @@ __device__ inline void row_product2(int rb, int re, const int32_t* __restrict__ 
 // the products and their order are row_product2's, so the sums are bitwise the same.  The
 // mirrors are upper blocks of rows up to a grid line earlier, which the same XCD reads for
 // those rows' own products at about the same time (xcd_tile): on the 300 x 300 shell the L2s
-// fetch 182 MB per launch against 249 MB for the full K.  An upper block is one 16-byte load
+// fetch 172 MB per launch against 249 MB for the full K.  An upper block is one 16-byte load
 // per lane, a mirror two 8-byte loads (stride 6); the choice is a branch per block, uniform
 // within a wave away from the mesh's edges.  Measured per iteration on the 300 x 300 shell
 // against 65.8 us for the full K: 57.1 us; two 8-byte loads for every block without the branch
@@ -567,7 +567,6 @@ template <class T>
 static bool sym_products(const Pattern& pat) {
   return pcg_sym_products(pat.n_blocks, sizeof(T) != 8);
 }
-
 
 // FP32 standard recurrences keep z and p interleaved: buffer k holds (z, p) pairs, (z_j,
 // p_{j-1}) in buffer j & 1, so that one 16-byte gather per lane brings both vectors' entries of
