@@ -854,7 +854,10 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   spmv_dir<T, NB, false, false>(D, wg_prob);
 }
 
-// The upper-triangle form (66 VGPRs, 7 waves per SIMD; 70 with EARLY, for single solves).
+// The upper-triangle form (66 VGPRs, 7 waves per SIMD; 70 with EARLY, for single solves).  A
+// three-blocks-per-step form for multi-problem launches of more than 1,024 workgroups (80 VGPRs,
+// 6 waves) measured 3.0-3.4 against 2.78-3.13 us per problem-iteration on 24-48 60 x 60 shells
+// and the served stream 114.6-115.0 against 122.9-123.2 solves/s, and was not kept.
 template <class T, bool EARLY = false>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir_sym(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
