@@ -143,13 +143,16 @@ def test_batch_mixing_both_recurrences_matches_solves_alone():
 
 
 def test_batch_reading_the_upper_triangle_matches_full_products_alone():
-    """Four 120 x 120 shells (37.5 MB of K each) iterate in one multi-problem launch, whose K
-    (150 MB together) is past the 128 MiB at which the products read only K's upper triangle;
-    alone, each reads all of K.  K is assembled bitwise symmetric and the products sum the same
-    values in the same order, so each u is bitwise its solve alone."""
+    """Three 120 x 120 shells (37.5 MB of K each) and a 100 x 100 one (26.1 MB) iterate in one
+    multi-problem launch, whose K (138.6 MB together) is past the 128 MiB at which the products
+    read only K's upper triangle; alone, each reads all of K.  Only the problems still running
+    are launched, and any three of them hold less than 128 MiB, so once the first converges
+    (the smaller shell, hundreds of iterations earlier) the launches read all of K again: the
+    others change product form mid-solve.  K is assembled bitwise symmetric and both forms sum
+    the same values in the same order, so each u is bitwise its solve alone."""
     import paper_2407_20026_amd as sso
     print("[gpu] batch of upper-triangle products against full products alone", flush=True)
-    meshes = [meshgen.shell(120, seed=s) for s in (41, 42, 43, 44)]
+    meshes = [meshgen.shell(120, seed=s) for s in (41, 42, 43)] + [meshgen.shell(100, seed=44)]
     opts = sso.Options(rtol=1e-8, solver=sso.SOLVER_STANDARD)
     stream = torch.cuda.Stream()
     batch = sso.Batch(stream)
@@ -157,12 +160,15 @@ def test_batch_reading_the_upper_triangle_matches_full_products_alone():
     try:
         for p in probs:
             p.solve_begin()
-        done = [False] * len(probs)
+        running, sizes = list(probs), []
         for _ in range(1000):
-            done = batch.iterate(probs, 64)
-            if all(done):
+            sizes.append(len(running))
+            flags = batch.iterate(running, 16)
+            running = [p for p, f in zip(running, flags) if not f]
+            if not running:
                 break
-        assert all(done)
+        assert not running
+        assert sizes[0] == 4 and min(sizes) < 4   # both product forms ran
         got = [p.solve_end()[0].cpu().numpy() for p in probs]
     finally:
         for p in probs:
