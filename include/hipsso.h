@@ -71,12 +71,18 @@ enum {
 /* Precision.  AUTO picks, per problem, mixed precision when the FP64 K alone holds at least
  * SSO_AUTO_MIXED_K_BYTES (128 MiB) -- from there K no longer stays in the 256 MB Infinity Cache
  * between iterations and the FP32 inner iterations' halved bytes pay for the extra iterations
- * of the restarted inner solves (measured on single shells: FP64 faster up to a 200 x 200 shell,
- * K 104 MB; mixed 10 % faster on 250 x 250 and 300 x 300, K 162 and 234 MB) -- and FP64
- * otherwise.  In AUTO's mixed precision an inner_max_it of 0 means 30 (the best of the measured
- * caps) and the outer step limit is at least max_it / 30. */
+ * of the restarted inner solves -- and, for a tolerance of SSO_AUTO_TIGHT_RTOL (1e-9) or tighter,
+ * at least SSO_AUTO_MIXED_TIGHT_K_BYTES (256 MiB): there the restarts cost more outer steps.
+ * FP64 otherwise.  Measured on single shells, forward solve, FP64 against mixed with inner
+ * solves capped at 30: rtol 1e-8, 250 x 250 (K 162 MB) 297 against 264 ms, 300 x 300 (234 MB)
+ * 515 against 493, 400 x 400 (417 MB) 1,368 against 1,067; rtol 1e-10, 250 x 250 342 against
+ * 349, 300 x 300 529-560 against 576-597, 400 x 400 1,517 against 1,243.  In AUTO's mixed
+ * precision an inner_max_it of 0 means 30 (the best of the measured caps) and the outer step
+ * limit is at least max_it / 30. */
 enum { SSO_PREC_FP64 = 0, SSO_PREC_MIXED = 1, SSO_PREC_AUTO = 2 };
 #define SSO_AUTO_MIXED_K_BYTES (128.0 * 1024.0 * 1024.0)
+#define SSO_AUTO_MIXED_TIGHT_K_BYTES (256.0 * 1024.0 * 1024.0)
+#define SSO_AUTO_TIGHT_RTOL 1e-9
 
 /* PCG recurrences.  STANDARD: Hestenes-Stiefel CG, two kernels and two reductions per
  * iteration.  FUSED: the single-reduction form of Chronopoulos & Gear (one kernel and one

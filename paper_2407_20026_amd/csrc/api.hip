@@ -111,7 +111,11 @@ bool options_ok(const sso_options& o) {
 // The precision a problem runs in: AUTO resolves by the size of its FP64 K.
 bool mixed_for(const sso_options& o, int64_t n_blocks) {
   if (o.solver == SSO_SOLVER_WG) return false;   // the one-workgroup solver runs in FP64
-  if (o.precision == SSO_PREC_AUTO) return 288.0 * (double)n_blocks >= SSO_AUTO_MIXED_K_BYTES;
+  if (o.precision == SSO_PREC_AUTO) {
+    const double k_bytes = 288.0 * (double)n_blocks;
+    return k_bytes >= (o.rtol <= SSO_AUTO_TIGHT_RTOL ? SSO_AUTO_MIXED_TIGHT_K_BYTES
+                                                    : SSO_AUTO_MIXED_K_BYTES);
+  }
   return o.precision == SSO_PREC_MIXED;
 }
 

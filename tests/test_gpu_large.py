@@ -224,16 +224,22 @@ def test_mixed_precision_flexible_cg_at_full_size(big, ref):
         assert e64 <= 1e-8 and eor <= 1e-8, name
 
 
-def test_auto_precision_picks_mixed_at_full_size(big, ref):
-    """SSO_PREC_AUTO on the 300x300 shell (K of 234 MB, above the 128 MiB crossover) runs the
-    FP32 inner solves (capped at 30 iterations by the policy) and meets the same bars as FP64."""
+def test_auto_precision_at_full_size(big, ref):
+    """SSO_PREC_AUTO on the 300x300 shell (K of 234 MB): at rtol 1e-10 (below the 256 MiB that
+    tight tolerances need) it runs FP64 and meets the FP64 bars; at 1e-8 (above 128 MiB) it runs
+    the FP32 inner solves, capped at 30 iterations, and converges."""
     import paper_2407_20026_amd as sso
     print("[gpu] large shell 300x300: AUTO precision", flush=True)
     with sso.Problem(big["mesh"], sso.Options(precision=sso.PREC_AUTO, rtol=1e-10,
                                               max_it=400000)) as p:
         u, st = p.solve(check=False)
         status = p.last_status
-    u = u.cpu().numpy().ravel()
-    print(f"  status={status} outer={st['refine_steps']} inner iters={st['iters']}")
-    assert status == 0 and st["refine_steps"] > 0
-    assert _check_against_reference(ref, u, 1e-10, "auto") <= 1e-10
+        u = u.cpu().numpy().ravel()
+        print(f"  1e-10: status={status} outer={st['refine_steps']} iters={st['iters']}")
+        assert status == 0 and st["refine_steps"] == 0
+        assert _check_against_reference(ref, u, 1e-10, "auto") <= 1e-10
+        p.set_options(sso.Options(precision=sso.PREC_AUTO, rtol=1e-8, max_it=400000))
+        _, st = p.solve(check=False)
+        status = p.last_status
+    print(f"  1e-8: status={status} outer={st['refine_steps']} inner iters={st['iters']}")
+    assert status == 0 and st["refine_steps"] > 0 and st["rel_residual"] <= 1e-8
