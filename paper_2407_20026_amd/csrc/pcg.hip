@@ -1992,7 +1992,22 @@ k_cg1_lean(const FusedDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_pr
 // One problem: the descriptor by value, launch k performs iteration k (unless done).
 template <class T, int W, bool ONE_PASS>
 __global__ void __launch_bounds__(MAX_TPB)
-k_cg1_iter1(const Cg1Args<T> a) {
+k_cg1_iter1(PcgState* st, const int32_t* bcol_ell, const T* B, const double* pp_in,
+            const T* r_in, int n_nodes, int i, int n_wg, int max_it, Cg1Args<T> a) {
+  // The leading scalar arguments arrive preloaded in SGPRs (14 dwords here; an aggregate
+  // argument is not preloaded): what the first group of loads needs before the gathers, so they
+  // go out without waiting for the argument segment.  The struct carries the rest.  Measured
+  // against the struct alone: 60 x 60 / 80 x 80 / 40 x 40 shells 12.42 / 32.44 / 9.38 against
+  // 12.73 / 32.96 / 9.69 ms per forward solve.
+  a.st = st;
+  a.bcol_ell = bcol_ell;
+  a.B = B;
+  a.pp_in = pp_in;
+  a.r_in = r_in;
+  a.n_nodes = n_nodes;
+  a.i = i;
+  a.max_it = max_it;
+  a.n_wg = n_wg;
   // the grid is a.n_wg workgroups; taking the count from the arguments keeps it in the one
   // batch of argument loads
   cg1_iteration<T, true, W, ONE_PASS>(a, blockIdx.x, a.n_wg);
@@ -2563,16 +2578,20 @@ static void launch_iter1_w(const FusedDesc<T>& hd, int nwg, int k, hipStream_t s
   a.n_wg = nwg;   // the grid launched below
   switch (hd.ell_w) {
     case 6:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 6, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
+      hipLaunchKernelGGL((k_cg1_iter1<T, 6, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a.st,
+                         a.bcol_ell, a.B, a.pp_in, a.r_in, a.n_nodes, a.i, a.n_wg, a.max_it, a);
       break;
     case 9:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 9, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
+      hipLaunchKernelGGL((k_cg1_iter1<T, 9, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a.st,
+                         a.bcol_ell, a.B, a.pp_in, a.r_in, a.n_nodes, a.i, a.n_wg, a.max_it, a);
       break;
     case 12:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 12, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
+      hipLaunchKernelGGL((k_cg1_iter1<T, 12, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a.st,
+                         a.bcol_ell, a.B, a.pp_in, a.r_in, a.n_nodes, a.i, a.n_wg, a.max_it, a);
       break;
     default:
-      hipLaunchKernelGGL((k_cg1_iter1<T, 0, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a);
+      hipLaunchKernelGGL((k_cg1_iter1<T, 0, P1>), dim3(nwg), dim3(MAX_TPB), 0, s, a.st,
+                         a.bcol_ell, a.B, a.pp_in, a.r_in, a.n_nodes, a.i, a.n_wg, a.max_it, a);
   }
 }
 
