@@ -17,7 +17,7 @@ Inputs are resident in HBM before each request's timed work starts: a request's 
 when it is admitted, which is part of serving it.
 
 Legs: the 300 x 300 shell (543,606 DOF) at rtol 1e-10 in FP64 and mixed precision, whose PCG
-iteration (k_spmv_dir + k_update, timed live with HIP events on the problem's stream) gives the
+iteration (k_spmv_dir_single + k_update_single, timed live with HIP events on the problem's stream) gives the
 roofline; the 60 x 60 shell; a linear objective (second PCG for the adjoint); the network batch
 (256 variants of the 80 x 80 shell through the MLP); the paper's arch-bridge rows; the measured
 HBM and FP64 ceilings; the oracle timed on the host on a sample of the stream's requests.
@@ -46,11 +46,8 @@ HBM_PEAK_GBS = 8000.0
 # read for a plain copy of known size (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel
 # code they were taken on: an entry is removed when one of its kernels changes.
 MEASURED_TRAFFIC = {
-    ("shell60", "fp64", "k_cg1_iter1"): (6334.7 * 2.000 + 947.0 * 1.000) * 1024,
-    ("shell300", "fp64", "k_spmv_dir + k_update"):
-        (128416.2 * 2.000 + 8706.5 * 1.000 + 15948.1 * 2.000 + 12705.9 * 1.000) * 1024,
-    ("shell300", "fp64", "k_spmv_dir_sym + k_update"):
-        (83891.6 * 2.000 + 8677.5 * 1.000 + 17524.5 * 2.000 + 12775.4 * 1.000) * 1024,
+    ("shell60", "fp64", "k_cg1_iter1"): None,
+    ("shell300", "fp64", "k_spmv_dir_single<sym> + k_update_single"): None,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
@@ -362,8 +359,8 @@ def problem_run(mesh, opts, steps, warmup, objective="compliance", with_grad=Tru
                       "standard",
             "n_blocks": n_blocks, "n_nodes": mesh.n_nodes,
             "iteration": {"kernels": "k_cg1_iter1" if st["solver"] == sso.SOLVER_FUSED else
-                          "k_spmv_dir_sym + k_update" if st["sym_products"] else
-                          "k_spmv_dir + k_update", "bytes": st["spmv_bytes"],
+                          "k_spmv_dir_single<sym> + k_update_single" if st["sym_products"] else
+                          "k_spmv_dir_single + k_update_single", "bytes": st["spmv_bytes"],
                           "avg_us": it_us, "samples": int(sum(rec["it_n"]))},
             "_u": u, "_g": last["g"]}
 
@@ -390,10 +387,10 @@ def algorithmic_iteration_bytes(n_nodes, n_blocks, precision, symmetric=False):
 def roofline_of(run, workload, precision, ceilings=None):
     it = run["iteration"]
     sym_read = None
-    if it["kernels"] in ("k_spmv_dir + k_update", "k_spmv_dir_sym + k_update"):
+    if it["kernels"].startswith("k_spmv_dir"):
         # the unit of work is one PCG iteration on this K, counted by the scope table (all of K
         # read); the upper-triangle product fetches less, which is reported beside it
-        if "_sym" in it["kernels"]:
+        if "<sym>" in it["kernels"]:
             sym_read = algorithmic_iteration_bytes(run["n_nodes"], run["n_blocks"], precision,
                                                    symmetric=True)
         it = dict(it, library_bytes=it["bytes"],

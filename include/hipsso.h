@@ -153,9 +153,9 @@ typedef struct {
   double bytes_moved;         /* algorithmic HBM bytes of the PCG iterations                 */
   double spmv_us;             /* mean duration of one PCG iteration, from samples of 8
                                  back-to-back iterations (profile_every; dispatch gaps
-                                 included): k_spmv_dir (or k_spmv_dir_sym, see sym_products)
-                                 + k_update of the standard recurrences, k_cg1_iter1 of the
-                                 single-reduction ones                                       */
+                                 included): k_spmv_dir_single (reading K's upper triangle
+                                 when sym_products) + k_update_single of the standard
+                                 recurrences, k_cg1_iter1 of the single-reduction ones       */
   int32_t spmv_samples;       /* number of sampled iterations                                */
   double spmv_bytes;          /* algorithmic bytes of one iteration                          */
   int32_t refine_steps;       /* mixed precision: outer steps (FP32 inner solves) run        */

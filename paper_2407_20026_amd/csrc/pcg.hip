@@ -563,6 +563,12 @@ __device__ __forceinline__ int xcd_tile(int lb, int ng) {
 // full-K side with three blocks a step), the served stream 120.0 against 117.3 solves/s.
 constexpr double SYM_PRODUCT_MIN_K_BYTES = 128.0 * 1024 * 1024;
 
+// the upper-triangle product exists for FP64 only
+template <class T>
+constexpr bool spmv_sym_ok() {
+  return sizeof(T) == 8;
+}
+
 template <class T>
 static bool sym_products(const Pattern& pat) {
   return pcg_sym_products(pat.n_blocks, sizeof(T) != 8);
@@ -724,11 +730,22 @@ __device__ __forceinline__ StdState std_state(const PcgState* __restrict__ st) {
 // 300 x 300 shell (upper triangle, single solve): 54.3 against 55.4 us per iteration; in
 // multi-problem launches, whose workgroups make one or two passes and lose a wave per SIMD to
 // the registers on the two-block form, 2 % slower (the stream 0.8 %).
-template <class T, int NB, bool SYM, bool EARLY>
+template <class T, int NB, bool SYM, bool EARLY, bool LEAD = false>
 __device__ __forceinline__ void spmv_dir(const PcgDesc<T>* __restrict__ D,
-                                         const int32_t* __restrict__ wg_prob) {
+                                         const int32_t* __restrict__ wg_prob,
+                                         const int32_t* brow_ptr_l = nullptr,
+                                         PcgState* st_l = nullptr, const double* pb_l = nullptr,
+                                         int n_nodes_l = 0, int n_wg_l = 0) {
   static_assert(!SYM || (NB == 2 && !zp_pairs<T>()), "symmetric products: FP64, two blocks a step");
-  const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
+  PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
+  if constexpr (LEAD) {   // single problem: the first group's fields from preloaded arguments
+    d.brow_ptr = brow_ptr_l;
+    d.st = st_l;
+    d.pb = const_cast<double*>(pb_l);
+    d.n_nodes = n_nodes_l;
+    d.n_wg = n_wg_l;
+    d.wg_base = 0;
+  }
   const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
   PcgState* st = d.st;
   const int n_nodes = d.n_nodes;
@@ -856,7 +873,8 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
   spmv_dir<T, NB, false, false>(D, wg_prob);
 }
 
-// The upper-triangle form (66 VGPRs, 7 waves per SIMD; 70 with EARLY, for single solves).  A
+// The upper-triangle form for multi-problem launches (66 VGPRs, 7 waves per SIMD; single solves
+// take k_spmv_dir_single, 70 with its early partials).  A
 // three-blocks-per-step form for multi-problem launches of more than 1,024 workgroups (80 VGPRs,
 // 6 waves) measured 3.0-3.4 against 2.78-3.13 us per problem-iteration on 24-48 60 x 60 shells
 // and the served stream 114.6-115.0 against 122.9-123.2 solves/s, and was not kept.
@@ -866,20 +884,49 @@ k_spmv_dir_sym(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_
   spmv_dir<T, 2, true, EARLY>(D, wg_prob);
 }
 
+// Single problems: the fields of the first group of loads (row pointers, state, the update
+// kernel's partials, sizes) as leading scalar arguments, which arrive preloaded in SGPRs, so
+// those loads do not wait for the descriptor; the descriptor brings the rest meanwhile.  SYM:
+// the upper-triangle products, with the partials issued with the state (EARLY).
+template <class T, bool SYM>
+__global__ void __launch_bounds__(MAX_TPB)
+k_spmv_dir_single(const int32_t* brow_ptr, PcgState* st, const double* pb, int n_nodes, int n_wg,
+                  const PcgDesc<T>* __restrict__ D) {
+  spmv_dir<T, 2, SYM, SYM, true>(D, nullptr, brow_ptr, st, pb, n_nodes, n_wg);
+}
+
 // Iteration j, second half: finish pAp_j, alpha_j; x += alpha p, r -= alpha Ap, z = Dinv r,
 // partials of (rz_{j+1}, rr_{j+1}); the state's next iteration index becomes j + 1.  The first
 // pass's operands (x, Ap, r, p of both parities, the inverses) and the product kernel's partials
 // are loaded with the state itself, so the reduction and the updates wait for one round trip.
-template <class T>
-__global__ void __launch_bounds__(MAX_TPB)
-k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+// LEAD (single problems): the sizes, Ap, r, both p buffers, the product kernel's partials and
+// the state come as preloaded arguments (14 dwords, as many as are preloaded), so the first
+// group of loads goes out at once; x and the inverses, not needed before alpha, come with the
+// descriptor, their loads issued after the others'.
+template <class T, bool LEAD>
+__device__ __forceinline__ void update_body(const PcgDesc<T>* __restrict__ D,
+                                            const int32_t* __restrict__ wg_prob, int n_nodes_l,
+                                            int n_wg_l, const T* Ap_l, T* r_l, T* p0_l,
+                                            T* p1_l, const double* pa_l, PcgState* st_l) {
   __shared__ T rs[MAX_TPB];
   __shared__ __align__(16) T dl[DINV_PACKED * DINV_GROUP];
-  const PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
-  // every field the kernel uses in one batch of scalar loads
-  asm volatile("" ::"s"(d.x), "s"(d.r), "s"(d.z), "s"(d.p[0]), "s"(d.p[1]), "s"(d.Ap),
-               "s"(d.Dinv), "s"(d.pa), "s"(d.pb), "s"(d.st), "s"(d.n_nodes), "s"(d.n_wg),
-               "s"(d.wg_base), "s"(d.stream_stores));
+  PcgDesc<T> d = D[wg_prob ? wg_prob[blockIdx.x] : 0];
+  if constexpr (LEAD) {
+    d.Ap = const_cast<T*>(Ap_l);
+    d.r = r_l;
+    d.p[0] = p0_l;
+    d.p[1] = p1_l;
+    d.pa = const_cast<double*>(pa_l);
+    d.st = st_l;
+    d.n_nodes = n_nodes_l;
+    d.n_wg = n_wg_l;
+    d.wg_base = 0;
+  } else {
+    // every field the kernel uses in one batch of scalar loads
+    asm volatile("" ::"s"(d.x), "s"(d.r), "s"(d.z), "s"(d.p[0]), "s"(d.p[1]), "s"(d.Ap),
+                 "s"(d.Dinv), "s"(d.pa), "s"(d.pb), "s"(d.st), "s"(d.n_nodes), "s"(d.n_wg),
+                 "s"(d.wg_base), "s"(d.stream_stores));
+  }
   const int lb = (int)blockIdx.x - d.wg_base, ng = d.n_wg;
   PcgState* st = d.st;
   const int n_nodes = d.n_nodes;
@@ -889,10 +936,14 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   const T* __restrict__ Ap = d.Ap;
   const RowMap m0 = row_map_at(lb, n_nodes);
   const int64_t q0 = 6 * (int64_t)(m0.valid ? m0.I : 0) + m0.a;
-  const T x0 = x[q0], a0 = Ap[q0], r0 = r[q0];
+  T x0 = 0;
+  if constexpr (!LEAD) x0 = x[q0];
+  const T a0 = Ap[q0], r0 = r[q0];
   // the first pass's inverses, state-free; a workgroup with no node group of its own (the
   // launch has one workgroup per 18 block rows, a group is 64 nodes) reads group 0 and drops it
-  const DinvChunk<T> dc0 = dinv_load(d.Dinv, lb * VEC_NODES < n_nodes ? lb : 0);
+  // (LEAD: issued after the preloaded group, below)
+  DinvChunk<T> dc0{};
+  if constexpr (!LEAD) dc0 = dinv_load(d.Dinv, lb * VEC_NODES < n_nodes ? lb : 0);
   // Issued with the state, which neither needs: the product kernel's partials of p^T A p (at
   // most three per thread: ng <= PCG_MAX_WG <= 3 MAX_TPB), summed below in finish_partials'
   // order, and the first pass's p from both parity buffers (the state names which is p_j).
@@ -908,6 +959,10 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   const int64_t qp0 = zp_pairs<T>() ? 2 * q0 + 1 : q0;
   const T p0e = d.p[0][qp0], p1e = d.p[1][qp0];
   const StdState S = std_state(st);
+  if constexpr (LEAD) {
+    x0 = x[q0];
+    dc0 = dinv_load(d.Dinv, lb * VEC_NODES < n_nodes ? lb : 0);
+  }
   asm volatile("" ::"v"(x0), "v"(a0), "v"(r0), "s"(S.rz0), "s"(S.rz1), "s"(S.jc));
   if (S.done) return;
   const int j = S.jc;
@@ -970,6 +1025,19 @@ k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) 
   block_sum<2, T>(v);
   write_partials<2, T>(v, d.pb, lb, ng);
   if (lb == 0 && threadIdx.x == 0) st->jn = j + 1;
+}
+
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_update(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
+  update_body<T, false>(D, wg_prob, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+template <class T>
+__global__ void __launch_bounds__(MAX_TPB)
+k_update_single(int n_nodes, int n_wg, const T* Ap, T* r, T* p0, T* p1, const double* pa,
+                PcgState* st, const PcgDesc<T>* __restrict__ D) {
+  update_body<T, true>(D, nullptr, n_nodes, n_wg, Ap, r, p0, p1, pa, st);
 }
 
 // ---- one workgroup per problem: every iteration inside one launch ----------------------------
@@ -2534,25 +2602,28 @@ static hipError_t pcg_run(const Mesh& m, const Pattern& pat, const T* K, const T
                           const T* b, T* x, T* r, T* z, T* const p[2], T* Ap, double rtol,
                           int max_it, PcgWork& w, hipStream_t s, int* iters, int* status,
                           int profile_every) {
-  hipError_t e = pcg_start<T>(m, pat, K, Dinv, b, x, r, z, p, Ap, rtol, max_it, w, s, nullptr);
+  PcgDesc<T> hd{};
+  hipError_t e = pcg_start<T>(m, pat, K, Dinv, b, x, r, z, p, Ap, rtol, max_it, w, s, &hd);
   if (e != hipSuccess) return e;
   const int nwg = w.n_wg;
   const int nwg_upd = update_wg(nwg, m.n_nodes);
   const bool sym = sym_products<T>(pat);
   const PcgDesc<T>* dd =
       reinterpret_cast<const PcgDesc<T>*>(sizeof(T) == 8 ? w.desc64 : w.desc32);
+  // the single-problem kernels, whose first group's fields arrive as preloaded arguments:
+  // against the descriptor alone, 54.3 against 54.7 us per iteration on the 300 x 300 shell,
+  // 17.9 against 18.25 us on the 120 x 120 one (two alternating runs each)
   auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
     if (e0) (void)hipEventRecord(*e0, s);
-    if constexpr (sizeof(T) == 8) {
-      if (sym)
-        hipLaunchKernelGGL((k_spmv_dir_sym<T, true>), dim3(nwg), dim3(MAX_TPB), 0, s, dd,
-                           nullptr);
-      else
-        hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-    } else {
-      hipLaunchKernelGGL(k_spmv_dir<T>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-    }
-    hipLaunchKernelGGL(k_update<T>, dim3(nwg_upd), dim3(MAX_TPB), 0, s, dd, nullptr);
+    if (sym)
+      hipLaunchKernelGGL((k_spmv_dir_single<T, spmv_sym_ok<T>()>), dim3(nwg), dim3(MAX_TPB), 0,
+                         s, hd.brow_ptr, hd.st, (const double*)hd.pb, hd.n_nodes, hd.n_wg, dd);
+    else
+      hipLaunchKernelGGL((k_spmv_dir_single<T, false>), dim3(nwg), dim3(MAX_TPB), 0, s,
+                         hd.brow_ptr, hd.st, (const double*)hd.pb, hd.n_nodes, hd.n_wg, dd);
+    hipLaunchKernelGGL(k_update_single<T>, dim3(nwg_upd), dim3(MAX_TPB), 0, s, hd.n_nodes,
+                       hd.n_wg, (const T*)hd.Ap, hd.r, hd.p[0], hd.p[1], (const double*)hd.pa,
+                       hd.st, dd);
     if (e1) (void)hipEventRecord(*e1, s);
   };
   // a sample spans 8 back-to-back iterations (events between every pair would add their own
