@@ -46,8 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # read for a plain copy of known size (FETCH x 2.000, WRITE x 1.000).  Valid only for the kernel
 # code they were taken on: an entry is removed when one of its kernels changes.
 MEASURED_TRAFFIC = {
-    ("shell60", "fp64", "k_cg1_iter1"): None,
-    ("shell300", "fp64", "k_spmv_dir_single<sym> + k_update_single"): None,
+    ("shell60", "fp64", "k_cg1_iter1"): (6340.9 * 2.000 + 939.9 * 1.000) * 1024,
+    ("shell300", "fp64", "k_spmv_dir_single<sym> + k_update_single"):
+        (83791.4 * 2.000 + 8692.7 * 1.000 + 17524.3 * 2.000 + 12775.4 * 1.000) * 1024,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
