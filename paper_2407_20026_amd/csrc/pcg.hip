@@ -3372,11 +3372,17 @@ hipError_t pcg_solve_mixed(const Mesh& m, const Pattern& pat, const double* K, c
       e = run_polled(w, s, cap, profile_every, FUSED_SPAN, launch, &it, &st);
     } else {
       const PcgDesc<float>* dd = reinterpret_cast<const PcgDesc<float>*>(w.desc32);
+      // the single-problem kernels with their first group's fields preloaded (forced mixed
+      // precision: 300 x 300 shell at 1e-10 575.4-575.5 against 576.6-578.0 ms, 250 x 250 at
+      // 1e-8 259.0-260.7 against 262.5-263.4 ms)
       auto launch = [&](hipEvent_t* e0, hipEvent_t* e1) {
         if (e0) (void)hipEventRecord(*e0, s);
-        hipLaunchKernelGGL(k_spmv_dir<float>, dim3(nwg), dim3(MAX_TPB), 0, s, dd, nullptr);
-        hipLaunchKernelGGL(k_update<float>, dim3(update_wg(nwg, m.n_nodes)), dim3(MAX_TPB), 0, s,
-                           dd, nullptr);
+        const PcgDesc<float>& hd = ms.sdesc;
+        hipLaunchKernelGGL((k_spmv_dir_single<float, false>), dim3(nwg), dim3(MAX_TPB), 0, s,
+                           hd.brow_ptr, hd.st, (const double*)hd.pb, hd.n_nodes, hd.n_wg, dd);
+        hipLaunchKernelGGL(k_update_single<float>, dim3(update_wg(nwg, m.n_nodes)),
+                           dim3(MAX_TPB), 0, s, hd.n_nodes, hd.n_wg, (const float*)hd.Ap, hd.r,
+                           hd.p[0], hd.p[1], (const double*)hd.pa, hd.st, dd);
         if (e1) (void)hipEventRecord(*e1, s);
       };
       e = run_polled(w, s, cap, profile_every, cap >= STD_SPAN ? STD_SPAN : 1, launch, &it, &st);
