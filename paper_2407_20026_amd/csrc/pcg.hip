@@ -878,10 +878,10 @@ k_spmv_dir(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob
 // three-blocks-per-step form for multi-problem launches of more than 1,024 workgroups (80 VGPRs,
 // 6 waves) measured 3.0-3.4 against 2.78-3.13 us per problem-iteration on 24-48 60 x 60 shells
 // and the served stream 114.6-115.0 against 122.9-123.2 solves/s, and was not kept.
-template <class T, bool EARLY = false>
+template <class T>
 __global__ void __launch_bounds__(MAX_TPB)
 k_spmv_dir_sym(const PcgDesc<T>* __restrict__ D, const int32_t* __restrict__ wg_prob) {
-  spmv_dir<T, 2, true, EARLY>(D, wg_prob);
+  spmv_dir<T, 2, true, false>(D, wg_prob);
 }
 
 // Single problems: the fields of the first group of loads (row pointers, state, the update
