@@ -255,6 +255,24 @@ int sso_batch_iterate(sso_batch* b, sso_problem* const* ps, int n, int n_iter, i
  * pending; a wait without a launch or with another list), SSO_EHIP. */
 int sso_batch_launch(sso_batch* b, sso_problem* const* ps, int n, int n_iter);
 int sso_batch_wait(sso_batch* b, sso_problem* const* ps, int n, int32_t* done);
+/* Timing samples of the multi-problem FP64 standard iterations (the product kernel over all of
+ * K or its upper triangle, then k_update; Sec. 2.2.1 Eq. (1) solved by PCG, the same kernels as
+ * without sampling), for measurement.  every > 0: of the launches (sso_batch_launch or
+ * sso_batch_iterate) whose problems all run FP64 standard recurrences -- one-workgroup problems
+ * may run beside them on the batch's second stream -- every every-th brackets its first
+ * min(span, n_iter) iterations with HIP events on the batch stream; every = 0 stops sampling.
+ * Resets the sums.  Errors: SSO_EINVAL (NULL batch, every or span negative, span 0 with every
+ * > 0, a launch pending), SSO_EHIP (event creation). */
+int sso_batch_profile(sso_batch* b, int every, int span);
+/* The sums since sso_batch_profile: us = the sampled spans' event time in microseconds,
+ * iters = iterations in those spans (each one launch of each kernel over all listed problems),
+ * bytes = algorithmic bytes of the problem-iterations done inside the spans with all of K
+ * counted (a problem's iterations there from its next-iteration index before and after the
+ * launch, at most the span), bytes_read = the same with K counted as the launch's product read
+ * it (its upper triangle when the problems' K take 128 MiB together).  Outputs are host
+ * pointers, each may be NULL.  Errors: SSO_EINVAL (NULL batch). */
+int sso_batch_timing(const sso_batch* b, double* us, int64_t* iters, double* bytes,
+                     double* bytes_read);
 void sso_batch_destroy(sso_batch* b);
 
 /* Move a problem's work to another stream (e.g. between a stream that admits and finishes

@@ -67,7 +67,7 @@ EXPORTS = ("sso_problem_create", "sso_problem_create_like", "sso_problem_update"
            "sso_sizes", "sso_strerror", "sso_problem_destroy", "sso_size_objective",
            "sso_size_objective_noalloc", "sso_size_penalty_update", "sso_hat_filter",
            "sso_problem_bytes", "sso_batch_launch", "sso_batch_wait", "sso_problem_set_stream",
-           "sso_pool_trim")
+           "sso_pool_trim", "sso_batch_profile", "sso_batch_timing")
 
 _lib = None
 _hip = None
@@ -109,6 +109,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sso_batch_launch.argtypes = [_vp, P(_vp), ctypes.c_int, ctypes.c_int]
     lib.sso_batch_wait.argtypes = [_vp, P(_vp), ctypes.c_int, P(ctypes.c_int32)]
     lib.sso_problem_set_stream.argtypes = [_vp, _vp]
+    lib.sso_batch_profile.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+    lib.sso_batch_timing.argtypes = [_vp, P(ctypes.c_double), P(ctypes.c_int64),
+                                     P(ctypes.c_double), P(ctypes.c_double)]
     lib.sso_batch_destroy.argtypes = [_vp]
     lib.sso_batch_destroy.restype = None
     lib.sso_strerror.argtypes = [ctypes.c_int]
@@ -445,6 +448,22 @@ class Batch:
         done = (ctypes.c_int32 * max(n, 1))()
         _check(load_library().sso_batch_wait(self.handle, arr, n, done), "sso_batch_wait")
         return [bool(done[i]) for i in range(n)]
+
+    def profile(self, every: int, span: int = 8):
+        """Time the first span iterations of every every-th launch of FP64 standard problems
+        with HIP events (sso_batch_profile; every = 0 stops); resets the sums."""
+        _check(load_library().sso_batch_profile(self.handle, int(every), int(span)),
+               "sso_batch_profile")
+
+    def timing(self) -> dict:
+        """Sums of the timed spans (sso_batch_timing): event time, iterations, the problem-
+        iterations' algorithmic bytes with all of K counted and as the products read K."""
+        us, bt, br = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        it = ctypes.c_int64()
+        _check(load_library().sso_batch_timing(self.handle, ctypes.byref(us), ctypes.byref(it),
+                                               ctypes.byref(bt), ctypes.byref(br)),
+               "sso_batch_timing")
+        return {"us": us.value, "iters": it.value, "bytes": bt.value, "bytes_read": br.value}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -83,6 +83,13 @@ struct sso_batch {
   bool pending = false;                  // a launch not yet waited for
   std::vector<sso_problem*> listed;      // its problem list, in the caller's order
   std::vector<int> idx[5];               // positions in that list by launch kind
+  // sso_batch_profile: timing samples of the FP64 standard iterations
+  int prof_every = 0, prof_span = 0;
+  int64_t prof_calls = 0;                // launches that could be sampled so far
+  int armed = 0;                         // iterations timed in the pending launch (0: none)
+  std::vector<int> jn0;                  // its FP64 standard problems' next iteration index
+  double prof_us = 0.0, prof_bytes = 0.0, prof_bytes_read = 0.0;
+  int64_t prof_iters = 0;
 };
 
 namespace {
@@ -834,6 +841,17 @@ int sso_batch_launch(sso_batch* b, sso_problem* const* ps, int n, int n_iter) {
       b->idx[0].push_back(i);
     }
   }
+  // a timing sample: every prof_every-th launch that holds FP64 standard problems and no other
+  // kind on the batch stream (one-workgroup problems run on their own stream beside them)
+  b->armed = 0;
+  if (b->prof_every > 0 && n_iter > 0 && !lists.standard.empty() && lists.fused.empty() &&
+      lists.standard32.empty() && lists.fused32.empty() &&
+      b->prof_calls++ % b->prof_every == 0) {
+    b->armed = b->prof_span < n_iter ? b->prof_span : n_iter;
+    b->jn0.clear();
+    for (int i : b->idx[0]) b->jn0.push_back(ps[i]->w.h_st->jn);
+  }
+  b->bw.time_span = b->armed;
   TRY_HIP(pcg_batch_launch(lists, n_iter, b->bw, b->s));
   b->listed.assign(ps, ps + n);
   for (int i = 0; i < n; ++i) ps[i]->batch_pending = true;
@@ -851,6 +869,25 @@ int sso_batch_wait(sso_batch* b, sso_problem* const* ps, int n, int32_t* done) {
   size_t k0 = 0;
   for (const auto& v : b->idx)
     for (int i : v) *ps[i]->w.h_st = b->bw.h_states[k0++];
+  if (b->armed > 0) {
+    // each problem's iterations inside the timed span: how far its next iteration index moved
+    // (an iteration that finds the problem stopped does no work and does not move it), at most
+    // the span; bytes per iteration with all of K counted, and as the launch's product read K
+    const int span = b->armed;
+    b->armed = 0;
+    float ms = 0.0f;
+    TRY_HIP(hipEventElapsedTime(&ms, b->bw.ev_t0, b->bw.ev_t1));
+    b->prof_us += 1000.0 * (double)ms;
+    b->prof_iters += span;
+    const bool sym = b->bw.standard.sym;
+    for (size_t k = 0; k < b->idx[0].size(); ++k) {
+      const sso_problem* p = ps[b->idx[0][k]];
+      int d = p->w.h_st->jn - b->jn0[k];
+      d = d < 0 ? 0 : (d > span ? span : d);
+      b->prof_bytes += d * pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false, false);
+      b->prof_bytes_read += d * pcg_bytes_per_iteration(p->m.n_nodes, p->pat.n_blocks, false, sym);
+    }
+  }
   // mixed precision: a stopped inner solve is refined in FP64 and the next one started
   for (const std::vector<int>* v : {&b->idx[2], &b->idx[3]})
     for (int i : *v) {
@@ -876,6 +913,36 @@ int sso_problem_set_stream(sso_problem* p, hipStream_t stream) {
   TRY_HIP(hipEventRecord(p->ev_move, p->s));
   TRY_HIP(hipStreamWaitEvent(stream, p->ev_move, 0));
   p->s = stream;
+  return SSO_OK;
+}
+
+int sso_batch_profile(sso_batch* b, int every, int span) {
+  if (!b || every < 0 || span < 0 || (every > 0 && span == 0) || b->pending) return SSO_EINVAL;
+  if (every > 0 && !b->bw.ev_t0) {
+    int dev = 0, cur = 0;
+    TRY_HIP(hipStreamGetDevice(b->s, &dev));
+    TRY_HIP(hipGetDevice(&cur));
+    if (cur != dev) TRY_HIP(hipSetDevice(dev));
+    hipError_t e = hipEventCreate(&b->bw.ev_t0);
+    if (e == hipSuccess) e = hipEventCreate(&b->bw.ev_t1);
+    if (cur != dev) (void)hipSetDevice(cur);
+    TRY_HIP(e);
+  }
+  b->prof_every = every;
+  b->prof_span = span;
+  b->prof_calls = 0;
+  b->prof_us = b->prof_bytes = b->prof_bytes_read = 0.0;
+  b->prof_iters = 0;
+  return SSO_OK;
+}
+
+int sso_batch_timing(const sso_batch* b, double* us, int64_t* iters, double* bytes,
+                     double* bytes_read) {
+  if (!b) return SSO_EINVAL;
+  if (us) *us = b->prof_us;
+  if (iters) *iters = b->prof_iters;
+  if (bytes) *bytes = b->prof_bytes;
+  if (bytes_read) *bytes_read = b->prof_bytes_read;
   return SSO_OK;
 }
 

@@ -2758,6 +2758,7 @@ hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const d
   hipError_t e = pcg_start<double>(m, pat, K, Dinv, b, x, w.r, w.z, w.p, w.Ap, rtol, max_it, w,
                                    s, desc);
   w.h_st->done = 0;
+  w.h_st->jn = 0;   // as k_pcg_init leaves the device state
   return e;
 }
 
@@ -2955,12 +2956,15 @@ hipError_t pcg_batch_launch(const BatchLists& L, int n_iter, BatchWork& bw, hipS
   if ((e = fused_upload(bw.fused32, L.fused32, s)) != hipSuccess) return e;
   if ((e = table_upload(bw.wg, L.wg.data(), (int)L.wg.size(), s)) != hipSuccess) return e;
   if (n_iter > 0 && (e = launch_wg(bw, n_iter, s)) != hipSuccess) return e;
+  const int span = bw.time_span < n_iter ? bw.time_span : n_iter;
   for (int i = 0; i < n_iter; ++i) {
+    if (span > 0 && i == 0 && (e = hipEventRecord(bw.ev_t0, s)) != hipSuccess) return e;
     launch_standard(bw.standard, bw.standard_upd, s);
     launch_fused(bw.fused, s);
     launch_standard(bw.standard32, bw.standard32_upd, s);
     launch_fused(bw.fused32, s);
     ++bw.launched;
+    if (span > 0 && i + 1 == span && (e = hipEventRecord(bw.ev_t1, s)) != hipSuccess) return e;
   }
   bw.h_stp.clear();
   for (const auto& d : L.standard) bw.h_stp.push_back(d.st);
@@ -3040,6 +3044,8 @@ void batch_free(BatchWork& bw, hipStream_t s) {
   }
   if (bw.ev_in) (void)hipEventDestroy(bw.ev_in);
   if (bw.ev_wg) (void)hipEventDestroy(bw.ev_wg);
+  if (bw.ev_t0) (void)hipEventDestroy(bw.ev_t0);
+  if (bw.ev_t1) (void)hipEventDestroy(bw.ev_t1);
   dev_free(bw.d_stp, s);
   dev_free(bw.d_states, s);
   bw = BatchWork();

@@ -433,6 +433,10 @@ struct BatchWork {
   int cap_pin = 0;
   hipEvent_t ev = nullptr;
   int pending_nt = -1;    // problems of the launch not yet waited for (-1: none pending)
+  // timing samples (sso_batch_profile): time_span > 0 brackets the first time_span iterations of
+  // the next launch with ev_t0 / ev_t1 on the launch stream
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+  int time_span = 0;
 };
 hipError_t pcg_begin(const Mesh& m, const Pattern& pat, const double* K, const double* Dinv,
                      const double* b, double* x, double rtol, int max_it, PcgWork& w,

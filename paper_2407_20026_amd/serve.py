@@ -124,6 +124,9 @@ class ServeStats:
     max_rel_residual: float = 0.0  # largest true relative residual over the requests
     iteration_bytes_per_s: float = 0.0   # the requests' algorithmic PCG iteration bytes / wall
     streams_overlap: bool | None = None  # BatchedServer: its two streams ran concurrently
+    # BatchedServer(profile_every > 0): sums of the timed FP64 standard iteration spans
+    # (Batch.timing: event us, iterations, algorithmic bytes all-K and as read)
+    iteration_timing: dict | None = None
 
 
 def _convergence(results) -> dict:
@@ -325,7 +328,12 @@ class BatchedServer:
 
     def __init__(self, slots: int = 64, hbm_budget: int = 64 << 30,
                  options: Options | None = None, device="cuda", chunk: int = 32,
-                 share_patterns: bool = True, overlap: bool = True, wg_max_nodes: int = 0):
+                 share_patterns: bool = True, overlap: bool = True, wg_max_nodes: int = 0,
+                 profile_every: int = 0, profile_span: int = 8):
+        # profile_every > 0: time the first profile_span iterations of every profile_every-th
+        # chunk of FP64 standard problems with HIP events (Batch.profile); kernels unchanged
+        self.profile_every = profile_every
+        self.profile_span = profile_span
         self.share_patterns = share_patterns
         self.overlap = overlap
         self.slots = slots
@@ -368,6 +376,9 @@ class BatchedServer:
                 if overlapping is not False:
                     break
         batch = Batch(it_stream, self.device)
+        if self.profile_every > 0:
+            batch.profile(self.profile_every, self.profile_span)
+        timing = None
         waiting = collections.deque()
         active = []          # iterating: (problem, request, admitted time, footprint)
         joining = []         # begun on the admission stream, join at the next launch
@@ -449,6 +460,8 @@ class BatchedServer:
                 elif not joining and not finishing and nxt < len(reqs):
                     time.sleep(max(0.0, reqs[nxt].arrival - clock()))
                     phase["idle"] += time.perf_counter() - t3
+            if self.profile_every > 0:
+                timing = batch.timing()
         finally:
             for p, *_ in active + joining + finishing:
                 p.close()
@@ -463,7 +476,7 @@ class BatchedServer:
             peak_inflight=peak_inflight, peak_bytes=peak_bytes,
             results=sorted(results, key=lambda r: r.rid),
             host_s=phase, iteration_bytes_per_s=sum(r.iter_bytes for r in results) / wall,
-            streams_overlap=overlapping,
+            streams_overlap=overlapping, iteration_timing=timing,
             **_convergence(results))
 
 

@@ -461,3 +461,64 @@ def test_one_workgroup_solver_rejects_mixed_precision():
     with pytest.raises(sso.SSOError):
         sso.Problem(meshgen.gridshell(6), sso.Options(solver=sso.SOLVER_WG,
                                                       precision=sso.PREC_MIXED))
+
+
+def _timed_batch(sso, meshes, opts, stream, every, span, chunk=8):
+    batch = sso.Batch(stream)
+    probs = [sso.Problem(m, opts, stream=stream) for m in meshes]
+    try:
+        if every:
+            batch.profile(every, span)
+        for p in probs:
+            p.solve_begin()
+        calls = 0
+        done = [False] * len(probs)
+        while not all(done):
+            done = batch.iterate(probs, chunk)
+            calls += 1
+        timing = batch.timing()
+        us = [p.solve_end()[0].cpu() for p in probs]
+        per_it = [(36 * 8 + 4) * p.n_blocks + 4 * (p.n_nodes + 1) + 4 * 8 * 6 * p.n_nodes +
+                  (4 + 3.5 + 3) * 8 * 6 * p.n_nodes for p in probs]
+    finally:
+        for p in probs:
+            p.close()
+        batch.close()
+    return timing, calls, us, per_it
+
+
+def test_batch_timing_samples_count_the_iterations_they_time():
+    """sso_batch_profile / sso_batch_timing.  Each problem alone with whole chunks timed gives
+    its batch iteration count as bytes / (bytes per iteration, all of K); three together with
+    the first 4 of every 8 iterations timed then give 4 timed iterations per launch and, per
+    problem, min(4, iterations left) of each chunk's iterations in the bytes; results are bitwise
+    those of an unsampled batch."""
+    import paper_2407_20026_amd as sso
+    print("[gpu] batch timing samples", flush=True)
+    meshes = [meshgen.shell(12, seed=91), meshgen.gridshell(10, seed=92),
+              meshgen.shell(16, seed=93)]
+    opts = sso.Options(rtol=1e-10, solver=sso.SOLVER_STANDARD)
+    stream = torch.cuda.Stream()
+    counts = []
+    for m in meshes:
+        t, calls, _, (per_it,) = _timed_batch(sso, [m], opts, stream, 1, 8)
+        n = t["bytes"] / per_it
+        assert n == round(n) and 8 * (calls - 1) <= n <= 8 * calls
+        assert t["iters"] == 8 * calls
+        counts.append(int(round(n)))
+    t0, _, u0, _ = _timed_batch(sso, meshes, opts, stream, 0, 0)
+    assert t0 == {"us": 0.0, "iters": 0, "bytes": 0.0, "bytes_read": 0.0}
+    t1, calls, u1, per_it = _timed_batch(sso, meshes, opts, stream, 1, 4)
+    assert t1["iters"] == 4 * calls and t1["us"] > 0
+    want = sum(w * sum(min(4, max(0, n - 8 * c)) for c in range(calls))
+               for n, w in zip(counts, per_it))
+    assert t1["bytes"] == pytest.approx(want, rel=1e-12)
+    assert t1["bytes_read"] == pytest.approx(want, rel=1e-12)   # small K: all of it read
+    for a, b in zip(u0, u1):
+        assert torch.equal(a, b)
+    batch = sso.Batch(stream)
+    try:
+        with pytest.raises(sso.SSOError):
+            batch.profile(1, 0)
+    finally:
+        batch.close()
