@@ -49,6 +49,8 @@ MEASURED_TRAFFIC = {
     ("shell60", "fp64", "k_cg1_iter1"): (6340.9 * 2.000 + 939.9 * 1.000) * 1024,
     ("shell300", "fp64", "k_spmv_dir_single<sym> + k_update_single"):
         (83791.4 * 2.000 + 8692.7 * 1.000 + 17524.3 * 2.000 + 12775.4 * 1.000) * 1024,
+    ("shell500", "fp64", "k_spmv_dir_single<sym> + k_update_single"):
+        (243043.5 * 2.000 + 25219.8 * 1.000 + 45718.6 * 2.000 + 35349.3 * 1.000) * 1024,
 }
 METRIC = "forward+adjoint solves/s & DOF/s at 1e-8 residual; p50/p99 latency, mixed sizes"
 
@@ -100,9 +102,10 @@ def parse():
     ap.add_argument("--profile-every", type=int, default=64,
                     help="time every n-th PCG iteration with HIP events "
                          "(16: ~5 %% overhead, 64: ~1.5 %%, 0: off)")
-    ap.add_argument("--legs", default="large,shell60,general,network,arch,ceilings",
+    ap.add_argument("--legs", default="large,large500,shell60,general,network,arch,ceilings",
                     help="comma-separated extra measurements ('' = none): large (300x300 shell, "
-                         "FP64 + mixed, rtol 1e-10, the roofline), shell60, general (linear "
+                         "FP64 + mixed, rtol 1e-10, the roofline), large500 (the 500x500 "
+                         "shell's iteration, out of the Infinity Cache), shell60, general (linear "
                          "objective), batch (16 60x60 shells in one launch), network (the MLP "
                          "batch), arch (the paper's arch-bridge rows), ceilings")
     ap.add_argument("--network-variants", type=int, default=256)
@@ -479,6 +482,29 @@ def large_leg(args):
     return out, runs["fp64"]
 
 
+def out_of_cache_leg(args):
+    """The upper-triangle iteration of the single-solve FP64 kernels on a 500 x 500 shell
+    (1,506,006 DOF; K 650 MB, the upper triangle 596 MB per iteration: no part of the working set
+    stays in the 256 MB Infinity Cache between iterations).  Only the iteration is measured:
+    3,000 iterations timed live with HIP events (every 16th, samples of 8 back-to-back
+    iterations), the solve stopping at that limit."""
+    import paper_2407_20026_amd as sso
+    mesh = meshgen.shell(500, seed=5)
+    opts = sso.Options(precision=sso.PREC_FP64, rtol=1e-10, max_it=3000, profile_every=16)
+    with sso.Problem(mesh, opts) as prob:
+        for _ in range(2):   # the first solve pays the pattern, the second is the one kept
+            prob.solve(check=False)
+        st = prob.last_stats
+        n_blocks = prob.n_blocks
+    run = {"n_nodes": mesh.n_nodes, "n_blocks": n_blocks,
+           "iteration": {"kernels": "k_spmv_dir_single<sym> + k_update_single"
+                         if st["sym_products"] else "k_spmv_dir_single + k_update_single",
+                         "bytes": st["spmv_bytes"], "avg_us": st["spmv_us"],
+                         "samples": st["spmv_samples"]}}
+    log(f"500x500 shell: iteration {st['spmv_us']:.2f} us over {st['spmv_samples']} samples")
+    return run
+
+
 def shell60_leg(args):
     import paper_2407_20026_amd as sso
     mesh = meshgen.shell_60()
@@ -683,6 +709,9 @@ def main():
         out["large"], run300 = large_leg(args)
         if roof_of is None:
             roof_of = (run300, "shell300", "fp64")
+    run500 = None
+    if "large500" in legs:
+        run500 = out_of_cache_leg(args)
     run60 = None
     if "shell60" in legs:
         out["shell60"], run60 = shell60_leg(args)
@@ -709,6 +738,11 @@ def main():
                                               "Cache, not an HBM figure")
     if roof_of is not None:
         out["roofline"] = roofline_of(*roof_of, ceilings)
+    if run500 is not None:
+        out["shell500_roofline"] = roofline_of(run500, "shell500", "fp64", ceilings)
+        out["shell500_roofline"]["note"] = (
+            "500x500 shell, 1,506,006 DOF, seed 5: the same kernels with no working set in the "
+            "Infinity Cache; iteration only (3,000 iterations, the solve stops at that limit)")
     if args.workload == "stream":
         sr = stream_roofline(stream_timing, ceilings)
         if sr is not None:
