@@ -161,54 +161,14 @@ def _oracle_analyses(meshes, objective, budget_s, threads):
     return n, dof, time.perf_counter() - t0
 
 
-_POOL_LIMITS = None
-
-
-def _pool_init():
-    """Worker of the oracle's process pool: one BLAS thread, the oracle imported once."""
-    global _POOL_LIMITS
-    _POOL_LIMITS = _threads(1)
-    import oracle  # noqa: F401
-
-
-def _pool_analysis(mesh, objective):
-    import oracle
-    a = None
-    if objective == "linear":
-        a = np.zeros(mesh.n_dof)
-        a[6 * (mesh.n_nodes // 2) + 2] = 1.0
-    oracle.analyze(mesh, objective, a=a)
-    return mesh.n_dof
-
-
-def _oracle_pool(meshes, objective, budget_s, workers, per_analysis_s):
-    """The oracle on every host core the other way: independent problems, one per worker
-    process with one BLAS thread each.  The first k meshes, k sized from the one-thread rate to
-    take about budget_s seconds (at least one per worker); workers are started and warmed
-    before the clock starts.  Spawned children: they import numpy and the oracle only."""
-    import multiprocessing as mp
-    k = max(workers, int(workers * budget_s / max(per_analysis_s, 1e-3)))
-    k = min(k, len(meshes))
-    with mp.get_context("spawn").Pool(workers, initializer=_pool_init) as pool:
-        small = min(meshes[:k], key=lambda m: m.n_dof)
-        pool.starmap(_pool_analysis, [(small, objective)] * workers, chunksize=1)   # warm up
-        t0 = time.perf_counter()
-        dofs = pool.starmap(_pool_analysis, [(m, objective) for m in meshes[:k]], chunksize=1)
-        el = time.perf_counter() - t0
-    log(f"cpu baseline (process pool of {workers}): {k} analyses, {el:.1f} s")
-    return k, int(sum(dofs)), el
-
-
 def cpu_baseline(meshes, objective, budget_s, what):
     """The oracle as it stands on a bounded sample: forward + adjoint analyses of `meshes` in
     order for about budget_s seconds with one BLAS thread (the reported value), then about
     budget_s / 2 seconds with every host core given to BLAS (the banded Cholesky is the threaded
-    part), then about budget_s / 2 seconds with independent problems in a process pool, one
-    worker per host core."""
+    part)."""
     all_cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
     n, dof, el = _oracle_analyses(meshes, objective, budget_s, 1)
     n2, dof2, el2 = _oracle_analyses(meshes, objective, budget_s / 2, all_cores)
-    n3, dof3, el3 = _oracle_pool(meshes, objective, budget_s / 2, all_cores, el / n)
     return {"value": n / el, "unit": "solves/s", "dof_per_s": dof / el, "cores": 1,
             "kind": "oracle",
             "sample": f"the first {n} {what} ({dof} DOF in all), one forward + adjoint "
@@ -216,12 +176,7 @@ def cpu_baseline(meshes, objective, budget_s, what):
                       f"refinement, complex-step adjoint) in {el:.1f} s, 1 BLAS thread; host "
                       f"cpus {all_cores}",
             "all_cores": {"value": n2 / el2, "unit": "solves/s", "dof_per_s": dof2 / el2,
-                          "cores": all_cores, "sample": f"{n2} analyses in {el2:.1f} s"},
-            "process_pool": {"value": n3 / el3, "unit": "solves/s", "dof_per_s": dof3 / el3,
-                             "cores": all_cores,
-                             "sample": f"the first {n3} {what}, one analysis per worker process "
-                                       f"({all_cores} processes, 1 BLAS thread each) in "
-                                       f"{el3:.1f} s"}}
+                          "cores": all_cores, "sample": f"{n2} analyses in {el2:.1f} s"}}
 
 
 # ---- the served stream ----------------------------------------------------------------------
