@@ -56,6 +56,8 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.sso_problem_create(ctypes.byref(m), None, None, ctypes.byref(h)) == sso.SSO_EINVAL
     assert lib.sso_solve(None, None, None) == sso.SSO_EINVAL
     assert lib.sso_adjoint(None, 0, None, None, None, None, None) == sso.SSO_EINVAL
+    assert lib.sso_batch_profile(None, 1, 8) == sso.SSO_EINVAL
+    assert lib.sso_batch_timing(None, None, None, None, None) == sso.SSO_EINVAL
 
 
 def test_struct_layouts_match_the_header(tmp_path):
